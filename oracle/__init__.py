@@ -1,0 +1,271 @@
+"""Python access to the FP64 C oracle (oracle/oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests, by the smoke check and by the benchmark's
+CPU-baseline leg.  The GPU library never imports or links it, and it never imports the
+GPU library.  All arrays are float64, C-contiguous, row-major.
+
+Function names follow the paper's notation: X the data tensor, A_n (= F^(n)) the Tucker
+factors, G the core, B_n the CP factors of the core, C_n = A_n B_n the lifted factors.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_dpp = ctypes.POINTER(_dp)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH) or \
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = ctypes.CDLL(build())
+        L.orc_nmode.argtypes = [ctypes.c_int, _i64p, _dp, ctypes.c_int, _dp, ctypes.c_int64, _dp]
+        L.orc_ttm_t.argtypes = [ctypes.c_int, _i64p, _dp, ctypes.c_int, _dp, ctypes.c_int64, _dp]
+        L.orc_contract_except.argtypes = [ctypes.c_int, _i64p, _dp, _i64p, _dp, ctypes.c_int, _dp]
+        L.orc_gram.argtypes = [_dp, ctypes.c_int64, ctypes.c_int64, _dp]
+        L.orc_tucker_full.argtypes = [ctypes.c_int, _i64p, _i64p, _dp, _dpp, _dp]
+        L.orc_cp_full.argtypes = [ctypes.c_int, _i64p, ctypes.c_int64, _dpp, _dp]
+        L.orc_sumsq.argtypes = [_dp, ctypes.c_int64]
+        L.orc_sumsq.restype = ctypes.c_double
+        L.orc_tucker_sq_residual.argtypes = [ctypes.c_int, _i64p, _dp, _i64p, _dp, _dpp]
+        L.orc_tucker_sq_residual.restype = ctypes.c_double
+        L.orc_cp_sq_residual.argtypes = [ctypes.c_int, _i64p, _dp, ctypes.c_int64, _dpp]
+        L.orc_cp_sq_residual.restype = ctypes.c_double
+        L.orc_nntucker.argtypes = [ctypes.c_int, _i64p, _dp, _i64p, ctypes.c_int, ctypes.c_double,
+                                   _dp, _dpp, _dp]
+        L.orc_nntucker.restype = ctypes.c_longlong
+        L.orc_mttkrp.argtypes = [ctypes.c_int, _i64p, _dp, ctypes.c_int, ctypes.c_int64, _dpp, _dp]
+        L.orc_nncp.argtypes = [ctypes.c_int, _i64p, _dp, ctypes.c_int64, ctypes.c_int,
+                               ctypes.c_double, _dpp, _dp]
+        L.orc_nncp.restype = ctypes.c_longlong
+        L.orc_lift.argtypes = [ctypes.c_int, _i64p, _i64p, ctypes.c_int64, _dpp, _dpp, _dpp]
+        L.orc_tucker_grad.argtypes = [ctypes.c_int, _i64p, _dp, _i64p, _dp, _dpp, _dp, _dpp]
+        L.orc_tucker_grad.restype = ctypes.c_double
+        L.orc_tucker_numden.argtypes = [ctypes.c_int, _i64p, _dp, _i64p, _dp, _dpp, _dpp, _dpp,
+                                        _dp, _dp]
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_get_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+def _dims(shape):
+    arr = (ctypes.c_int64 * len(shape))(*[int(s) for s in shape])
+    return arr
+
+
+def _ptrs(mats):
+    arr = (_dp * len(mats))(*[_p(m) for m in mats])
+    return arr
+
+
+def set_threads(n: int) -> None:
+    lib().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().orc_get_threads())
+
+
+def nmode(X, n: int, M) -> np.ndarray:
+    """X x_n M (Appendix A): out[.., i, ..] = sum_l X[.., l, ..] M[i, l]."""
+    X, M = _f64(X), _f64(M)
+    assert M.ndim == 2 and M.shape[1] == X.shape[n]
+    shape = list(X.shape)
+    shape[n] = M.shape[0]
+    out = np.empty(shape, dtype=np.float64)
+    lib().orc_nmode(X.ndim, _dims(X.shape), _p(X), n, _p(M), M.shape[0], _p(out))
+    return out
+
+
+def ttm_t(X, n: int, A) -> np.ndarray:
+    """X x_n A^T for a factor A of shape (dims[n], R)."""
+    X, A = _f64(X), _f64(A)
+    assert A.ndim == 2 and A.shape[0] == X.shape[n]
+    shape = list(X.shape)
+    shape[n] = A.shape[1]
+    out = np.empty(shape, dtype=np.float64)
+    lib().orc_ttm_t(X.ndim, _dims(X.shape), _p(X), n, _p(A), A.shape[1], _p(out))
+    return out
+
+
+def contract_except(U, V, n: int) -> np.ndarray:
+    """out[i, j] = sum over every index but mode n of U[.., i, ..] V[.., j, ..]."""
+    U, V = _f64(U), _f64(V)
+    out = np.empty((U.shape[n], V.shape[n]), dtype=np.float64)
+    lib().orc_contract_except(U.ndim, _dims(U.shape), _p(U), _dims(V.shape), _p(V), n, _p(out))
+    return out
+
+
+def gram(A) -> np.ndarray:
+    A = _f64(A)
+    S = np.empty((A.shape[1], A.shape[1]), dtype=np.float64)
+    lib().orc_gram(_p(A), A.shape[0], A.shape[1], _p(S))
+    return S
+
+
+def tucker_full(G, A) -> np.ndarray:
+    """G x_1 A_1 x_2 ... x_d A_d."""
+    G = _f64(G)
+    A = [_f64(a) for a in A]
+    dims = [a.shape[0] for a in A]
+    out = np.empty(dims, dtype=np.float64)
+    lib().orc_tucker_full(G.ndim, _dims(dims), _dims(G.shape), _p(G), _ptrs(A), _p(out))
+    return out
+
+
+def cp_full(C) -> np.ndarray:
+    """sum_rho outer(C_1[:, rho], ..., C_d[:, rho])."""
+    C = [_f64(c) for c in C]
+    dims = [c.shape[0] for c in C]
+    out = np.empty(dims, dtype=np.float64)
+    lib().orc_cp_full(len(C), _dims(dims), C[0].shape[1], _ptrs(C), _p(out))
+    return out
+
+
+def sumsq(X) -> float:
+    X = _f64(X)
+    return float(lib().orc_sumsq(_p(X), X.size))
+
+
+def tucker_rel_residual(X, G, A) -> float:
+    """||X - G x {A}||_F / ||X||_F (Section 4.1 relative error)."""
+    X, G = _f64(X), _f64(G)
+    A = [_f64(a) for a in A]
+    s = lib().orc_tucker_sq_residual(X.ndim, _dims(X.shape), _p(X), _dims(G.shape), _p(G), _ptrs(A))
+    return float(np.sqrt(s / sumsq(X)))
+
+
+def cp_rel_residual(X, C) -> float:
+    X = _f64(X)
+    C = [_f64(c) for c in C]
+    s = lib().orc_cp_sq_residual(X.ndim, _dims(X.shape), _p(X), C[0].shape[1], _ptrs(C))
+    return float(np.sqrt(s / sumsq(X)))
+
+
+def nntucker(X, G0, A0, iters: int, eps: float = 1e-12, history: bool = False):
+    """nnTucker by multiplicative updates; returns (G, [A_n], clips, f_hist or None)."""
+    X = _f64(X)
+    G = _f64(G0).copy()
+    A = [_f64(a).copy() for a in A0]
+    d = X.ndim
+    R = [a.shape[1] for a in A]
+    assert tuple(G.shape) == tuple(R)
+    hist = np.zeros(max(iters, 1), dtype=np.float64) if history else None
+    clips = lib().orc_nntucker(d, _dims(X.shape), _p(X), _dims(R), int(iters), float(eps), _p(G),
+                               _ptrs(A), _p(hist) if history else None)
+    return G, A, int(clips), (hist[:iters] if history else None)
+
+
+def mttkrp(T, n: int, B) -> np.ndarray:
+    T = _f64(T)
+    B = [_f64(b) for b in B]
+    r = B[0].shape[1]
+    out = np.empty((T.shape[n], r), dtype=np.float64)
+    lib().orc_mttkrp(T.ndim, _dims(T.shape), _p(T), n, r, _ptrs(B), _p(out))
+    return out
+
+
+def nncp(T, B0, iters: int, eps: float = 1e-12, history: bool = False):
+    """nnCP of T by multiplicative updates; returns ([B_n], clips, f_hist or None)."""
+    T = _f64(T)
+    B = [_f64(b).copy() for b in B0]
+    r = B[0].shape[1]
+    hist = np.zeros(max(iters, 1), dtype=np.float64) if history else None
+    clips = lib().orc_nncp(T.ndim, _dims(T.shape), _p(T), r, int(iters), float(eps), _ptrs(B),
+                           _p(hist) if history else None)
+    return B, int(clips), (hist[:iters] if history else None)
+
+
+def lift(A, B):
+    """C_n = A_n B_n (substitution of the core's CP into the Tucker model)."""
+    A = [_f64(a) for a in A]
+    B = [_f64(b) for b in B]
+    r = B[0].shape[1]
+    dims = [a.shape[0] for a in A]
+    ranks = [a.shape[1] for a in A]
+    C = [np.empty((dims[k], r), dtype=np.float64) for k in range(len(A))]
+    lib().orc_lift(len(A), _dims(dims), _dims(ranks), r, _ptrs(A), _ptrs(B), _ptrs(C))
+    return C
+
+
+def tucker_grad(X, G, A):
+    """(L, dL/dG, [dL/dA_n]) for L = 0.5 ||X - G x {A}||^2, from the explicit residual."""
+    X, G = _f64(X), _f64(G)
+    A = [_f64(a) for a in A]
+    gG = np.empty_like(G)
+    gA = [np.empty_like(a) for a in A]
+    L = lib().orc_tucker_grad(X.ndim, _dims(X.shape), _p(X), _dims(G.shape), _p(G), _ptrs(A),
+                              _p(gG), _ptrs(gA))
+    return float(L), gG, gA
+
+
+def tucker_numden(X, G, A):
+    """Block numerators/denominators at a fixed point: ([num_n], [den_n], num_G, den_G)."""
+    X, G = _f64(X), _f64(G)
+    A = [_f64(a) for a in A]
+    num = [np.empty_like(a) for a in A]
+    den = [np.empty_like(a) for a in A]
+    numG, denG = np.empty_like(G), np.empty_like(G)
+    lib().orc_tucker_numden(X.ndim, _dims(X.shape), _p(X), _dims(G.shape), _p(G), _ptrs(A),
+                            _ptrs(num), _ptrs(den), _p(numG), _p(denG))
+    return num, den, numG, denG
+
+
+def mean_congruence(P, Q) -> float:
+    """Mean congruence of two rank-r CP models after the best matching of components
+    (Section 4.1 scoring): the congruence of two rank-one tensors is the product over
+    modes of the cosines between their factor vectors.  Brute force over permutations."""
+    import itertools
+    P = [_f64(p) for p in P]
+    Q = [_f64(q) for q in Q]
+    r = P[0].shape[1]
+    assert r <= 8 and all(q.shape[1] == r for q in Q)
+    cos = np.ones((r, r))
+    for p, q in zip(P, Q):
+        pn = p / np.linalg.norm(p, axis=0, keepdims=True)
+        qn = q / np.linalg.norm(q, axis=0, keepdims=True)
+        cos *= pn.T @ qn
+    best = max(np.mean([cos[i, perm[i]] for i in range(r)])
+               for perm in itertools.permutations(range(r)))
+    return float(best)
+
+
+def nncandelinc(X, G0, A0, B0, tucker_iters: int, cp_iters: int, eps: float = 1e-12):
+    """Algorithm 1 end to end: nnTucker, nnCP of the core, lift, residuals."""
+    G, A, c1, _ = nntucker(X, G0, A0, tucker_iters, eps)
+    B, c2, _ = nncp(G, B0, cp_iters, eps)
+    C = lift(A, B)
+    return dict(G=G, A=A, B=B, C=C, clips=c1 + c2,
+                tucker_rel=tucker_rel_residual(X, G, A), cp_rel=cp_rel_residual(X, C))

@@ -1,0 +1,182 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the benchmark.
+
+This module holds no arithmetic of the decomposition method itself: it only draws
+numbers and assembles the planted test tensors (sums of outer products, the
+construction of a rank-R tensor in the paper's Section 2 definition of the tensor
+product) that both sides then receive as identical inputs.
+
+Random numbers come from a counter-based form of SplitMix64 (Steele, Lea & Flood,
+"Fast splittable pseudorandom number generators", OOPSLA 2014): the 64-bit value for
+element ``i`` of stream ``s`` under seed ``seed`` is
+
+    key   = mix64(mix64(seed + GAMMA) ^ (s * GOLDEN2))
+    u64   = mix64(key + (i + 1) * GAMMA)          (all arithmetic mod 2**64)
+
+with SplitMix64's finaliser ``mix64`` and ``GAMMA = 0x9E3779B97F4A7C15``.  A uniform
+double in [0, 1) is ``(u64 >> 11) * 2**-53``.  Values are independent of the order of
+generation, so any slice of a stream can be produced on its own.
+
+Stream ids (one per role):  planted factor n -> n;  zero mask of planted factor n ->
+16 + n;  additive noise -> 32;  initial core G0 -> 48;  initial Tucker factor n ->
+64 + n;  nnCP restart j, factor n -> 1024 + 16 j + n.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+GAMMA = 0x9E3779B97F4A7C15
+GOLDEN2 = 0xD1B54A32D192ED03
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+_MASK = (1 << 64) - 1
+
+STREAM_PLANTED = 0
+STREAM_MASK = 16
+STREAM_NOISE = 32
+STREAM_CORE0 = 48
+STREAM_FACTOR0 = 64
+STREAM_CP_RESTART = 1024
+
+
+def _mix64_int(z: int) -> int:
+    z &= _MASK
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK
+    return z ^ (z >> 31)
+
+
+def _mix64(z: np.ndarray) -> np.ndarray:
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def stream_key(seed: int, stream: int) -> int:
+    return _mix64_int(_mix64_int(seed + GAMMA) ^ ((stream * GOLDEN2) & _MASK))
+
+
+def raw_u64(seed: int, stream: int, n: int, offset: int = 0) -> np.ndarray:
+    """``n`` raw 64-bit draws of ``stream`` starting at element ``offset``."""
+    key = np.uint64(stream_key(seed, stream))
+    idx = np.arange(offset + 1, offset + n + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = key + idx * np.uint64(GAMMA)
+    return _mix64(z)
+
+
+def uniform(seed: int, stream: int, n: int, offset: int = 0) -> np.ndarray:
+    """``n`` doubles in [0, 1) (53-bit resolution)."""
+    u = raw_u64(seed, stream, n, offset) >> np.uint64(11)
+    return u.astype(np.float64) * (2.0 ** -53)
+
+
+def round_bf16(x: np.ndarray) -> np.ndarray:
+    """Round float64 values to the nearest bfloat16 (ties to even); returns float64.
+
+    bfloat16 keeps 8 significant bits.  Only finite normal-range values are expected.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros_like(x)
+    nz = x != 0
+    _, e = np.frexp(x[nz])          # x = m * 2**e with 0.5 <= |m| < 1
+    q = np.ldexp(1.0, e - 8)        # spacing of 8-significant-bit values in that binade
+    # np.round is round-half-to-even
+    out[nz] = np.round(x[nz] / q) * q
+    return out
+
+
+def to_bf16_bits(x64: np.ndarray) -> np.ndarray:
+    """bfloat16 bit patterns (uint16) of float64 values that are already bf16-exact."""
+    f32 = np.asarray(x64, dtype=np.float32)
+    return (f32.view(np.uint32) >> np.uint32(16)).astype(np.uint16)
+
+
+def bf16_bits_to_f64(bits: np.ndarray) -> np.ndarray:
+    u32 = bits.astype(np.uint32) << np.uint32(16)
+    return u32.view(np.float32).astype(np.float64)
+
+
+def uniform_matrix(seed: int, stream: int, rows: int, cols: int) -> np.ndarray:
+    return uniform(seed, stream, rows * cols).reshape(rows, cols)
+
+
+def init_factors(seed: int, dims, ranks, dtype=np.float32):
+    """Initial Tucker factors A0_n ~ U[0,1), each dims[n] x ranks[n], rounded to ``dtype``."""
+    return [uniform_matrix(seed, STREAM_FACTOR0 + n, int(dims[n]), int(ranks[n])).astype(dtype)
+            for n in range(len(dims))]
+
+
+def init_core(seed: int, ranks, dtype=np.float32):
+    """Initial core G0 ~ U[0,1) of shape ranks, rounded to ``dtype``."""
+    size = int(np.prod(ranks))
+    return uniform(seed, STREAM_CORE0, size).reshape(tuple(int(r) for r in ranks)).astype(dtype)
+
+
+def init_cp_factors(seed: int, core_dims, rank: int, restart: int = 0, dtype=np.float32):
+    """Initial nnCP factors B0_n ~ U[0,1), each core_dims[n] x rank."""
+    return [uniform_matrix(seed, STREAM_CP_RESTART + 16 * restart + n, int(core_dims[n]), rank)
+            .astype(dtype) for n in range(len(core_dims))]
+
+
+def planted_factors(seed: int, dims, R: int, zero_prob: float = 0.0):
+    """Planted nonnegative CP factors a_n (dims[n] x R), entries U[0,1).
+
+    With ``zero_prob`` > 0 each entry is zeroed when its own mask draw is below
+    ``zero_prob``; a column left entirely zero keeps the entry with the largest mask draw.
+    """
+    facs = []
+    for n, N in enumerate(dims):
+        a = uniform_matrix(seed, STREAM_PLANTED + n, int(N), R)
+        if zero_prob > 0.0:
+            u = uniform_matrix(seed, STREAM_MASK + n, int(N), R)
+            keep = u >= zero_prob
+            for c in range(R):
+                if not keep[:, c].any():
+                    keep[int(np.argmax(u[:, c])), c] = True
+            a = np.where(keep, a, 0.0)
+        facs.append(a)
+    return facs
+
+
+def planted_tensor(seed: int, dims, R: int, zero_prob: float = 0.0, noise: float = 1e-3,
+                   dtype: str = "f32", chunk_elems: int = 1 << 24):
+    """Dense planted tensor X = sum_rho outer(a_1[:,rho], ..., a_d[:,rho]) + E, E ~ U[0, noise).
+
+    X is formed in float64 and rounded once to ``dtype``:
+      "f64" -> float64 array, "f32" -> float32 array (RNE),
+      "bf16" -> uint16 array of bfloat16 bit patterns (RNE of the float64 value).
+    Returns (X, planted_factors).  Built in chunks of leading-mode rows to bound memory.
+    """
+    dims = [int(n) for n in dims]
+    d = len(dims)
+    facs = planted_factors(seed, dims, R, zero_prob)
+    total = int(np.prod(dims))
+    last = dims[-1]
+    lead = total // last
+    out_dt = {"f64": np.float64, "f32": np.float32, "bf16": np.uint16}[dtype]
+    X = np.empty(total, dtype=out_dt)
+    rows_per_chunk = max(1, chunk_elems // last)
+    lead_dims = dims[:-1]
+    for r0 in range(0, lead, rows_per_chunk):
+        r1 = min(lead, r0 + rows_per_chunk)
+        m = np.arange(r0, r1, dtype=np.int64)
+        # Khatri-Rao rows of the leading factors for flattened leading indices m.
+        kr = np.ones((r1 - r0, R), dtype=np.float64)
+        rem = m.copy()
+        for k in range(d - 2, -1, -1):
+            ik = rem % lead_dims[k]
+            rem //= lead_dims[k]
+            kr *= facs[k][ik, :]
+        blk = kr @ facs[-1].T
+        flat0, flat1 = r0 * last, r1 * last
+        if noise > 0.0:
+            blk = blk + noise * uniform(seed, STREAM_NOISE, flat1 - flat0, flat0).reshape(blk.shape)
+        if dtype == "f64":
+            X[flat0:flat1] = blk.ravel()
+        elif dtype == "f32":
+            X[flat0:flat1] = blk.ravel().astype(np.float32)
+        else:
+            X[flat0:flat1] = to_bf16_bits(round_bf16(blk.ravel()))
+    return X.reshape(dims), facs
