@@ -1,0 +1,213 @@
+/*
+ * nncandelinc.h -- C ABI of the MI355X (gfx950) library for nonnegative CANDELINC
+ * computed as in Algorithm 1 of Alexandrov, DeSantis, Manzini, Skau, "Nonnegative
+ * Canonical Tensor Decomposition with Linear Constraints: nnCANDELINC" (arXiv 1909.07570):
+ * a nonnegative Tucker compression X ~ G x_1 F1 x_2 F2 ... x_d Fd, a nonnegative CP of the
+ * core G ~ I x_1 B1 ... x_d Bd, and the lift C_n = F_n B_n, which together solve the
+ * constrained least-squares problem of Section 4 (eq. nnCANDELINC).
+ *
+ * Conventions shared by every entry point
+ *   - Tensors are dense and row-major (last index fastest): element (i_1, ..., i_d) of a
+ *     tensor with dims N_1..N_d lives at offset ((i_1 N_2 + i_2) N_3 + ...) + i_d.
+ *     Factor matrices are row-major: F_n is dims[n] x R_n, B_n is R_n x r, C_n is dims[n] x r.
+ *     In the text below F_n is written A_n.
+ *   - Pointers are DEVICE pointers unless marked "host".  The caller owns every buffer.
+ *     The library never allocates device memory.  Entry points that need scratch space take
+ *     a caller-provided device workspace whose minimum size a *_workspace_bytes query
+ *     returns; workspace contents need not be initialised and are clobbered.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Work is
+ *     enqueued on it in order.  An entry point returns without synchronising unless it
+ *     must hand a value back to host memory (marked "syncs").
+ *   - Every argument is validated before any HIP call, so invalid calls fail the same way
+ *     with or without a GPU.  Status codes are returned; nothing is thrown across the ABI.
+ *     nnc_last_error() describes the most recent non-OK status of the calling thread.
+ *   - ndim is 2..8.  Multiranks may exceed the dimensions they compress (Section 4.2 fits
+ *     multirank [5,5,5] to a 4x4x4 tensor).
+ *   - Multiplicative updates (MU): the paper delegates the solvers to library routines run
+ *     for a fixed iteration count with random initialisation and no early stop (Section 4.1).
+ *     This library applies Lee-Seung Frobenius multiplicative updates block by block:
+ *       factor n (n = 1..d in order, Gauss-Seidel):
+ *         A_n <- A_n * num_n / max(den_n, eps)
+ *         num_n = unfold_n(X x_{k!=n} A_k^T) unfold_n(G)^T
+ *         den_n = A_n unfold_n(G x_{k!=n} A_k^T A_k) unfold_n(G)^T
+ *       core:  G <- G * (X x_1 A_1^T ... x_d A_d^T) / max(G x_1 A_1^T A_1 ... x_d A_d^T A_d, eps)
+ *       nnCP of the core, factor n:  B_n <- B_n * M_n / max(B_n H_n, eps),
+ *         M_n = MTTKRP of the core with the other factors, H_n = Hadamard product of their Grams.
+ *     (x * num) / max(den, eps) is evaluated in double precision and rounded to float.
+ *     Initial values are inputs (the caller draws them), and the results are written back
+ *     in place into the same buffers, so a fit can be resumed by calling again.
+ */
+#ifndef NNCANDELINC_H
+#define NNCANDELINC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NNC_OK = 0,
+  NNC_EINVAL = -1,       /* invalid argument (null pointer, bad size, bad enum)            */
+  NNC_EUNSUPPORTED = -2, /* valid request this build does not implement                    */
+  NNC_EWORKSPACE = -3,   /* workspace missing or smaller than the query says               */
+  NNC_EHIP = -4,         /* a HIP runtime call failed (message in nnc_last_error)          */
+  NNC_ENUMERIC = -5      /* non-finite value in the result (e.g. NaN or Inf in X)          */
+} nnc_status;
+
+typedef enum { NNC_F32 = 0, NNC_BF16 = 1 } nnc_dtype;
+
+/* Options of nntucker_fit.  Zero-initialised options are valid defaults (eps 1e-12). */
+typedef struct {
+  int fp32_final_sweeps;   /* with X in NNC_BF16: the last k sweeps read x_fp32 and run the
+                              X-streaming contractions in FP32 (refinement)                   */
+  const float *x_fp32;     /* optional FP32 copy of X (device).  Required when
+                              fp32_final_sweeps > 0.  When given, residuals are measured
+                              against it                                                        */
+  double eps;              /* MU denominator floor; 0 selects 1e-12                            */
+  int objective_every;     /* 0: residual only at the end (if a report is requested);
+                              k > 0: also after every k-th sweep into report history          */
+  int use_graph;           /* 1: capture one sweep in a HIP graph and replay it              */
+  void *workspace;         /* device scratch of at least nntucker_workspace_bytes()          */
+  size_t workspace_bytes;
+} nnc_options;
+
+/* Report of a fit (host struct).  Passing a report makes the call synchronise. */
+typedef struct {
+  int sweeps_done;
+  double rel_residual;        /* ||X - G x {A}||_F / ||X||_F after the last sweep            */
+  long long eps_clips;        /* number of MU entries whose denominator was below eps        */
+  double *objective_history;  /* host, optional: relative residual after every
+                                 objective_every-th sweep (length >= iters / objective_every) */
+  int history_len;            /* entries written                                             */
+  double seconds;             /* wall time of the call                                       */
+  double ttm_pass_ms;         /* summed GPU time of the two X-streaming TTM passes (when
+                                 timing is requested through nnc_set_timing)                  */
+  long long ttm_pass_launches;
+} nnc_report;
+
+/* Thread-local description of the last non-OK status (never NULL). */
+const char *nnc_last_error(void);
+
+/* 1 if the library was built for and can see a gfx950 device, else 0 (no error raised). */
+int nnc_device_ok(void);
+
+/* Turn per-launch timing of the X-streaming TTM passes on (1) or off (0).  When on, the
+ * library records HIP events around each pass launch on the caller's stream and nntucker_fit
+ * reports their summed duration. */
+void nnc_set_timing(int on);
+
+/*
+ * n-mode product with a transposed factor, out = X x_n A^T (Appendix A, definition of
+ * n-mode multiplication, with the matrix A^T):
+ *   out[i_1..r..i_d] = sum_l X[i_1..l..i_d] * A[l, r],   l < dims[n], r < R.
+ * X: dims (xdt = NNC_F32 or NNC_BF16).  A: dims[n] x R float.  out: float, the shape of X
+ * with dims[n] replaced by R.  n is 0-based.  Runs the same MFMA pass kernels as the fit
+ * when their shape conditions hold, else a general kernel.
+ */
+nnc_status nnc_ttm(const void *X, nnc_dtype xdt, int ndim, const int64_t *dims, int n,
+                   const float *A, int64_t R, float *out, void *stream);
+
+/* Round FP32 to bfloat16 (round to nearest, ties to even; NaN stays NaN).  out holds
+ * count uint16 bit patterns. */
+nnc_status nnc_convert_f32_bf16(const float *in, uint16_t *out, int64_t count, void *stream);
+
+/*
+ * Nonnegative Tucker decomposition by multiplicative updates (the nnTD step of
+ * Algorithm 1), exactly `iters` sweeps, no early stop (Section 4.1).  The arithmetic of the
+ * two X-streaming contractions of every sweep follows xdt: NNC_F32 runs FP32 MFMA;
+ * NNC_BF16 runs bf16 MFMA with FP32 accumulation (the factor is applied as a hi + lo pair
+ * of bf16 values, so the rounding of X to bf16 is the only reduction of precision).
+ * Everything else (partial contractions, Grams, updates) is FP32 with FP64 divisions.
+ *   X          dims[0..ndim-1], dtype xdt.
+ *   multirank  host, R_n = multirank[n] >= 1.
+ *   core       in: initial G (prod R_n floats, entries >= 0); out: fitted G.
+ *   factors    host array of ndim device pointers; factor n is dims[n] x R_n;
+ *              in: initial A_n >= 0; out: fitted A_n.
+ *   opt        nullable (defaults); workspace is required.
+ *   rep        nullable; non-NULL makes the call synchronise and fill it.
+ * iters = 0 leaves the inputs unchanged (and reports their residual).
+ */
+size_t nntucker_workspace_bytes(int ndim, const int64_t *dims, const int64_t *multirank);
+nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *dims,
+                        const int64_t *multirank, int iters, float *core, float *const *factors,
+                        const nnc_options *opt, nnc_report *rep, void *stream);
+
+/*
+ * Nonnegative CP of a (small) tensor, here the Tucker core (the nnCPD step of Algorithm 1),
+ * exactly `iters` MU sweeps in one persistent launch.
+ *   core        core_dims[0..ndim-1] floats.
+ *   cp_factors  host array of ndim device pointers; factor n is core_dims[n] x rank;
+ *               in: initial B_n >= 0; out: fitted B_n.
+ *   rel_residual  host, nullable: ||core - cp(B)|| / ||core||; non-NULL syncs.
+ *   workspace     at least nncp_workspace_bytes().
+ */
+size_t nncp_workspace_bytes(int ndim, const int64_t *core_dims, int rank);
+nnc_status nncp_fit(const float *core, int ndim, const int64_t *core_dims, int rank, int iters,
+                    float *const *cp_factors, double eps, double *rel_residual, void *workspace,
+                    size_t workspace_bytes, void *stream);
+
+/*
+ * Many independent nnCP fits of one core (random restarts, possibly different ranks) in a
+ * single persistent launch: restart j has rank ranks[j] (host array) and factors
+ * cp_factors[j*ndim + n] (core_dims[n] x ranks[j]).  rel_residuals: host, nbatch entries
+ * (syncs).  Every rank must be <= 32.  threads_per_fit: 0 lets the library's tuner choose.
+ */
+size_t nncp_batched_workspace_bytes(int ndim, const int64_t *core_dims, int nbatch, const int *ranks);
+nnc_status nncp_fit_batched(const float *core, int ndim, const int64_t *core_dims, int nbatch,
+                            const int *ranks, int iters, float *const *cp_factors, double eps,
+                            double *rel_residuals, int threads_per_fit, void *workspace,
+                            size_t workspace_bytes, void *stream);
+
+/*
+ * Lift: C_n = A_n B_n for every mode (substituting the core's CP into the Tucker model,
+ * Section 2.1 lemma proof and Section 2.2).  tucker_factors[n]: dims[n] x multirank[n];
+ * cp_factors[n]: multirank[n] x rank; out_factors[n]: dims[n] x rank.  Host arrays of
+ * device pointers.
+ */
+nnc_status nncandelinc_lift(int ndim, const int64_t *dims, const int64_t *multirank, int rank,
+                            const float *const *tucker_factors, const float *const *cp_factors,
+                            float *const *out_factors, void *stream);
+
+/*
+ * Relative reconstruction error ||X - Xhat||_F / ||X||_F (Section 4.1 scoring), with
+ * squared differences accumulated in double precision.  Syncs.
+ *   core != NULL: Tucker model Xhat = core x_1 A_1 ... x_d A_d, model_dims = multirank.
+ *   core == NULL: CP model Xhat = sum_rho outer(A_1[:,rho], ..., A_d[:,rho]);
+ *                 model_dims[0] = rank (other entries ignored).
+ * factors: host array of ndim device pointers, factor n is dims[n] x model_dims[n] (Tucker)
+ * or dims[n] x rank (CP).
+ */
+size_t reconstruct_workspace_bytes(int ndim, const int64_t *dims, const int64_t *model_dims,
+                                   int is_cp);
+nnc_status reconstruct_residual(const void *X, nnc_dtype xdt, int ndim, const int64_t *dims,
+                                const float *core, const int64_t *model_dims,
+                                const float *const *factors, double *rel_residual,
+                                void *workspace, size_t workspace_bytes, void *stream);
+
+/* The two sums behind reconstruct_residual: sq_error = ||X - Xhat||_F^2 and
+ * sq_norm = ||X||_F^2 (host doubles; syncs).  Same arguments and workspace otherwise. */
+nnc_status reconstruct_sq_sums(const void *X, nnc_dtype xdt, int ndim, const int64_t *dims,
+                               const float *core, const int64_t *model_dims,
+                               const float *const *factors, double *sq_error, double *sq_norm,
+                               void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Adjoint of L = 0.5 ||X - G x {A}||_F^2 at one point (every block held fixed):
+ *   dL/dA_n = den_n - num_n,   dL/dG = den_G - num_G,
+ * the same numerators and denominators the multiplicative updates use, recomputed from X
+ * (two X passes; nothing is kept from a forward call).  grad_core: prod R floats;
+ * grad_factors: host array of device pointers (dims[n] x R_n).  loss: host, nullable
+ * (non-NULL adds one more X pass and syncs).  Workspace: nntucker_workspace_bytes().
+ */
+nnc_status nntucker_grad(const void *X, nnc_dtype xdt, int ndim, const int64_t *dims,
+                         const int64_t *multirank, const float *core, const float *const *factors,
+                         float *grad_core, float *const *grad_factors, double *loss,
+                         void *workspace, size_t workspace_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NNCANDELINC_H */

@@ -1,0 +1,380 @@
+"""Python binding of libnncandelinc (include/nncandelinc.h): nonnegative CANDELINC on
+AMD Instinct MI355X (gfx950), computed as Algorithm 1 of arXiv 1909.07570 -- a nonnegative
+Tucker compression by multiplicative updates, a nonnegative CP of the core, and the lift
+of the CP factors through the Tucker factors (Section 4.1).
+
+The binding only marshals arguments: torch tensors provide device memory and the current
+stream; every step runs in the library's HIP kernels.  There is no CPU fallback: if the
+shared library is missing or no gfx950 device is visible, calls raise.
+
+Names follow the paper: X the data tensor, A_n (= F^(n)) the Tucker factors, G the core,
+B_n the CP factors of the core, C_n = A_n B_n the lifted (constrained) CP factors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnncandelinc.so")
+
+NNC_OK, NNC_EINVAL, NNC_EUNSUPPORTED, NNC_EWORKSPACE, NNC_EHIP, NNC_ENUMERIC = 0, -1, -2, -3, -4, -5
+NNC_F32, NNC_BF16 = 0, 1
+STATUS_NAMES = {0: "NNC_OK", -1: "NNC_EINVAL", -2: "NNC_EUNSUPPORTED", -3: "NNC_EWORKSPACE",
+                -4: "NNC_EHIP", -5: "NNC_ENUMERIC"}
+
+_i64 = ctypes.c_int64
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_vp = ctypes.c_void_p
+_vpp = ctypes.POINTER(ctypes.c_void_p)
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class NncError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, str(status)), msg))
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("fp32_final_sweeps", ctypes.c_int), ("x_fp32", _vp), ("eps", ctypes.c_double),
+                ("objective_every", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("workspace", _vp), ("workspace_bytes", ctypes.c_size_t)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("sweeps_done", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("eps_clips", ctypes.c_longlong), ("objective_history", _dp),
+                ("history_len", ctypes.c_int), ("seconds", ctypes.c_double),
+                ("ttm_pass_ms", ctypes.c_double), ("ttm_pass_launches", ctypes.c_longlong)]
+
+
+EXPORTED = ["nnc_last_error", "nnc_device_ok", "nnc_set_timing", "nnc_ttm", "nnc_convert_f32_bf16",
+            "nntucker_workspace_bytes", "nntucker_fit", "nncp_workspace_bytes", "nncp_fit",
+            "nncp_batched_workspace_bytes", "nncp_fit_batched", "nncandelinc_lift",
+            "reconstruct_workspace_bytes", "reconstruct_residual", "reconstruct_sq_sums",
+            "nntucker_grad"]
+
+_lib = None
+
+
+def lib():
+    """Load the shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libnncandelinc.so is not built; run `python -m paper_1909_07570_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.nnc_last_error.restype = ctypes.c_char_p
+        L.nnc_device_ok.restype = ctypes.c_int
+        L.nnc_set_timing.argtypes = [ctypes.c_int]
+        L.nnc_ttm.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _i64p, ctypes.c_int, _vp, _i64, _vp, _vp]
+        L.nnc_convert_f32_bf16.argtypes = [_vp, _vp, _i64, _vp]
+        L.nntucker_workspace_bytes.argtypes = [ctypes.c_int, _i64p, _i64p]
+        L.nntucker_workspace_bytes.restype = ctypes.c_size_t
+        L.nntucker_fit.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _i64p, _i64p, ctypes.c_int, _vp,
+                                   _vpp, ctypes.POINTER(Options), ctypes.POINTER(Report), _vp]
+        L.nncp_workspace_bytes.argtypes = [ctypes.c_int, _i64p, ctypes.c_int]
+        L.nncp_workspace_bytes.restype = ctypes.c_size_t
+        L.nncp_fit.argtypes = [_vp, ctypes.c_int, _i64p, ctypes.c_int, ctypes.c_int, _vpp,
+                               ctypes.c_double, _dp, _vp, ctypes.c_size_t, _vp]
+        L.nncp_batched_workspace_bytes.argtypes = [ctypes.c_int, _i64p, ctypes.c_int,
+                                                   ctypes.POINTER(ctypes.c_int)]
+        L.nncp_batched_workspace_bytes.restype = ctypes.c_size_t
+        L.nncp_fit_batched.argtypes = [_vp, ctypes.c_int, _i64p, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_int), ctypes.c_int, _vpp,
+                                       ctypes.c_double, _dp, ctypes.c_int, _vp, ctypes.c_size_t, _vp]
+        L.nncandelinc_lift.argtypes = [ctypes.c_int, _i64p, _i64p, ctypes.c_int, _vpp, _vpp, _vpp, _vp]
+        L.reconstruct_workspace_bytes.argtypes = [ctypes.c_int, _i64p, _i64p, ctypes.c_int]
+        L.reconstruct_workspace_bytes.restype = ctypes.c_size_t
+        L.reconstruct_residual.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _i64p, _vp, _i64p, _vpp,
+                                           _dp, _vp, ctypes.c_size_t, _vp]
+        L.reconstruct_sq_sums.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _i64p, _vp, _i64p, _vpp,
+                                          _dp, _dp, _vp, ctypes.c_size_t, _vp]
+        L.nntucker_grad.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _i64p, _i64p, _vp, _vpp, _vp,
+                                    _vpp, _dp, _vp, ctypes.c_size_t, _vp]
+        for name in EXPORTED:
+            if name not in ("nnc_last_error", "nnc_device_ok", "nnc_set_timing") and \
+                    not name.endswith("_bytes"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().nnc_last_error().decode()
+
+
+def _check(status: int) -> None:
+    if status != NNC_OK:
+        raise NncError(status, last_error())
+
+
+def _dims(seq):
+    seq = [int(x) for x in seq]
+    return (ctypes.c_int64 * len(seq))(*seq)
+
+
+def _ptrs(tensors):
+    return (ctypes.c_void_p * len(tensors))(*[t.data_ptr() if t is not None else None for t in tensors])
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str, dtypes=(torch.float32,)) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype not in dtypes:
+        raise ValueError("%s has dtype %s, expected %s" % (name, t.dtype, dtypes))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t
+
+
+def _xdt(X: torch.Tensor) -> int:
+    if X.dtype == torch.float32:
+        return NNC_F32
+    if X.dtype == torch.bfloat16:
+        return NNC_BF16
+    raise ValueError("X must be float32 or bfloat16")
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def set_timing(on: bool) -> None:
+    lib().nnc_set_timing(1 if on else 0)
+
+
+def device_ok() -> bool:
+    return bool(lib().nnc_device_ok())
+
+
+# ------------------------------------------------------------------------------- primitives
+def nnc_ttm(X: torch.Tensor, n: int, A: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """X x_n A^T (Appendix A n-mode product with the transposed factor A, dims[n] x R)."""
+    _dev(X, "X", (torch.float32, torch.bfloat16))
+    _dev(A, "A")
+    shape = list(X.shape)
+    shape[n] = A.shape[1]
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=X.device)
+    _dev(out, "out")
+    _check(lib().nnc_ttm(X.data_ptr(), _xdt(X), X.dim(), _dims(X.shape), n, A.data_ptr(), A.shape[1],
+                         out.data_ptr(), _stream()))
+    return out
+
+
+def nnc_convert_f32_bf16(x: torch.Tensor) -> torch.Tensor:
+    """Round-to-nearest-even FP32 -> bfloat16 on the GPU."""
+    _dev(x, "x")
+    out = torch.empty(x.shape, dtype=torch.bfloat16, device=x.device)
+    _check(lib().nnc_convert_f32_bf16(x.data_ptr(), out.data_ptr(), x.numel(), _stream()))
+    return out
+
+
+# ------------------------------------------------------------------------------- nnTucker
+@dataclass
+class FitReport:
+    sweeps_done: int
+    rel_residual: float
+    eps_clips: int
+    seconds: float
+    history: List[float] = field(default_factory=list)
+    ttm_pass_ms: float = 0.0
+    ttm_pass_launches: int = 0
+
+
+def nntucker_workspace_bytes(dims: Sequence[int], multirank: Sequence[int]) -> int:
+    return int(lib().nntucker_workspace_bytes(len(dims), _dims(dims), _dims(multirank)))
+
+
+def nntucker_fit(X: torch.Tensor, multirank: Sequence[int], iters: int, core: torch.Tensor,
+                 factors: Sequence[torch.Tensor], *, x_fp32: Optional[torch.Tensor] = None,
+                 fp32_final_sweeps: int = 0, eps: float = 1e-12, objective_every: int = 0,
+                 use_graph: bool = True, report: bool = True,
+                 workspace: Optional[torch.Tensor] = None) -> Optional[FitReport]:
+    """nnTucker by multiplicative updates, `iters` sweeps, in place on core and factors."""
+    _dev(X, "X", (torch.float32, torch.bfloat16))
+    _dev(core, "core")
+    for k, f in enumerate(factors):
+        _dev(f, "factors[%d]" % k)
+    d = X.dim()
+    need = nntucker_workspace_bytes(X.shape, multirank)
+    if workspace is None:
+        workspace = _workspace(need, X.device)
+    opt = Options()
+    opt.fp32_final_sweeps = int(fp32_final_sweeps)
+    opt.x_fp32 = _dev(x_fp32, "x_fp32").data_ptr() if x_fp32 is not None else None
+    opt.eps = float(eps)
+    opt.objective_every = int(objective_every)
+    opt.use_graph = 1 if use_graph else 0
+    opt.workspace = workspace.data_ptr()
+    opt.workspace_bytes = workspace.numel()
+    rep = Report()
+    hist = None
+    if objective_every > 0:
+        hist = (ctypes.c_double * max(1, iters // objective_every + 1))()
+        rep.objective_history = ctypes.cast(hist, _dp)
+    st = lib().nntucker_fit(X.data_ptr(), _xdt(X), d, _dims(X.shape), _dims(multirank), int(iters),
+                            core.data_ptr(), _ptrs(factors), ctypes.byref(opt),
+                            ctypes.byref(rep) if (report or objective_every) else None, _stream())
+    _check(st)
+    if not (report or objective_every):
+        return None
+    return FitReport(rep.sweeps_done, rep.rel_residual, rep.eps_clips, rep.seconds,
+                     [hist[i] for i in range(rep.history_len)] if hist is not None else [],
+                     rep.ttm_pass_ms, rep.ttm_pass_launches)
+
+
+# ------------------------------------------------------------------------------- nnCP
+def nncp_fit(core: torch.Tensor, rank: int, iters: int, cp_factors: Sequence[torch.Tensor], *,
+             eps: float = 1e-12, residual: bool = True) -> Optional[float]:
+    """nnCP of the core by multiplicative updates in one persistent launch, in place."""
+    _dev(core, "core")
+    for k, f in enumerate(cp_factors):
+        _dev(f, "cp_factors[%d]" % k)
+    d = core.dim()
+    ws = _workspace(lib().nncp_workspace_bytes(d, _dims(core.shape), int(rank)), core.device)
+    res = ctypes.c_double(0.0)
+    _check(lib().nncp_fit(core.data_ptr(), d, _dims(core.shape), int(rank), int(iters),
+                          _ptrs(cp_factors), float(eps), ctypes.byref(res) if residual else None,
+                          ws.data_ptr(), ws.numel(), _stream()))
+    return res.value if residual else None
+
+
+def nncp_fit_batched(core: torch.Tensor, ranks: Sequence[int], iters: int,
+                     cp_factors: Sequence[Sequence[torch.Tensor]], *, eps: float = 1e-12,
+                     threads_per_fit: int = 0) -> List[float]:
+    """Independent nnCP fits of one core (restart j: rank ranks[j], factors cp_factors[j])
+    in a single persistent launch.  Returns each fit's relative residual."""
+    _dev(core, "core")
+    d = core.dim()
+    nb = len(ranks)
+    flat = []
+    for j, fs in enumerate(cp_factors):
+        assert len(fs) == d
+        for k, f in enumerate(fs):
+            flat.append(_dev(f, "cp_factors[%d][%d]" % (j, k)))
+    rk = (ctypes.c_int * nb)(*[int(r) for r in ranks])
+    ws = _workspace(lib().nncp_batched_workspace_bytes(d, _dims(core.shape), nb, rk), core.device)
+    res = (ctypes.c_double * nb)()
+    _check(lib().nncp_fit_batched(core.data_ptr(), d, _dims(core.shape), nb, rk, int(iters),
+                                  _ptrs(flat), float(eps), res, int(threads_per_fit), ws.data_ptr(),
+                                  ws.numel(), _stream()))
+    return [res[j] for j in range(nb)]
+
+
+# ------------------------------------------------------------------------------- lift, residual
+def nncandelinc_lift(tucker_factors: Sequence[torch.Tensor], cp_factors: Sequence[torch.Tensor],
+                     out: Optional[Sequence[torch.Tensor]] = None) -> List[torch.Tensor]:
+    """C_n = A_n B_n for every mode."""
+    d = len(tucker_factors)
+    rank = cp_factors[0].shape[1]
+    dims = [a.shape[0] for a in tucker_factors]
+    mr = [a.shape[1] for a in tucker_factors]
+    for k in range(d):
+        _dev(tucker_factors[k], "tucker_factors[%d]" % k)
+        _dev(cp_factors[k], "cp_factors[%d]" % k)
+    if out is None:
+        out = [torch.empty(dims[k], rank, dtype=torch.float32, device=tucker_factors[0].device)
+               for k in range(d)]
+    _check(lib().nncandelinc_lift(d, _dims(dims), _dims(mr), int(rank), _ptrs(tucker_factors),
+                                  _ptrs(cp_factors), _ptrs(out), _stream()))
+    return list(out)
+
+
+def reconstruct_residual(X: torch.Tensor, factors: Sequence[torch.Tensor],
+                         core: Optional[torch.Tensor] = None) -> float:
+    """||X - Xhat||_F / ||X||_F for a Tucker model (core given) or a CP model (core None)."""
+    _dev(X, "X", (torch.float32, torch.bfloat16))
+    d = X.dim()
+    if core is not None:
+        _dev(core, "core")
+        model = list(core.shape)
+        is_cp = 0
+    else:
+        model = [factors[0].shape[1]] + [0] * (d - 1)
+        is_cp = 1
+    for k, f in enumerate(factors):
+        _dev(f, "factors[%d]" % k)
+    ws = _workspace(lib().reconstruct_workspace_bytes(d, _dims(X.shape), _dims(model), is_cp), X.device)
+    res = ctypes.c_double(0.0)
+    _check(lib().reconstruct_residual(X.data_ptr(), _xdt(X), d, _dims(X.shape),
+                                      core.data_ptr() if core is not None else None, _dims(model),
+                                      _ptrs(factors), ctypes.byref(res), ws.data_ptr(), ws.numel(),
+                                      _stream()))
+    return res.value
+
+
+# ------------------------------------------------------------------------------- adjoint
+def nntucker_grad(X: torch.Tensor, core: torch.Tensor, factors: Sequence[torch.Tensor],
+                  want_loss: bool = True):
+    """(loss, dL/dG, [dL/dA_n]) for L = 0.5 ||X - G x {A}||^2 from the library's adjoint."""
+    _dev(X, "X", (torch.float32, torch.bfloat16))
+    _dev(core, "core")
+    d = X.dim()
+    mr = list(core.shape)
+    ws = _workspace(nntucker_workspace_bytes(X.shape, mr), X.device)
+    gG = torch.empty_like(core)
+    gA = [torch.empty_like(_dev(f, "factors[%d]" % k)) for k, f in enumerate(factors)]
+    loss = ctypes.c_double(0.0)
+    _check(lib().nntucker_grad(X.data_ptr(), _xdt(X), d, _dims(X.shape), _dims(mr), core.data_ptr(),
+                               _ptrs(factors), gG.data_ptr(), _ptrs(gA),
+                               ctypes.byref(loss) if want_loss else None, ws.data_ptr(), ws.numel(),
+                               _stream()))
+    return (loss.value if want_loss else None), gG, gA
+
+
+def reconstruct_sq_sums(X: torch.Tensor, factors: Sequence[torch.Tensor],
+                        core: Optional[torch.Tensor] = None):
+    """(||X - Xhat||_F^2, ||X||_F^2) in double precision (Tucker if core given, else CP)."""
+    _dev(X, "X", (torch.float32, torch.bfloat16))
+    d = X.dim()
+    if core is not None:
+        _dev(core, "core")
+        model, is_cp = list(core.shape), 0
+    else:
+        model, is_cp = [factors[0].shape[1]] + [0] * (d - 1), 1
+    for k, f in enumerate(factors):
+        _dev(f, "factors[%d]" % k)
+    ws = _workspace(lib().reconstruct_workspace_bytes(d, _dims(X.shape), _dims(model), is_cp), X.device)
+    e, n = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(lib().reconstruct_sq_sums(X.data_ptr(), _xdt(X), d, _dims(X.shape),
+                                     core.data_ptr() if core is not None else None, _dims(model),
+                                     _ptrs(factors), ctypes.byref(e), ctypes.byref(n), ws.data_ptr(),
+                                     ws.numel(), _stream()))
+    return e.value, n.value
+
+
+class NNTuckerLoss(torch.autograd.Function):
+    """L = 0.5 ||X - G x_1 A_1 ... x_d A_d||_F^2 with the hand-written adjoint as backward.
+
+    forward(X, G, A_1, ..., A_d) -> 0-dim float64 tensor (fused residual pass, FP64 sum).
+    backward recomputes the contraction chain from X (nothing but the inputs is saved) and
+    returns dL/dG = den_G - num_G and dL/dA_n = den_n - num_n; X gets no gradient.
+    """
+
+    @staticmethod
+    def forward(ctx, X, G, *A):
+        ctx.save_for_backward(X, G, *A)
+        sq, _ = reconstruct_sq_sums(X, [a.contiguous() for a in A], G.contiguous())
+        return torch.tensor(0.5 * sq, dtype=torch.float64, device=X.device)
+
+    @staticmethod
+    def backward(ctx, gout):
+        X, G, *A = ctx.saved_tensors
+        _, gG, gA = nntucker_grad(X, G.contiguous(), [a.contiguous() for a in A], want_loss=False)
+        s = gout.to(torch.float32)
+        return (None, gG * s, *[g * s for g in gA])
+
+
+def nntucker_loss(X: torch.Tensor, G: torch.Tensor, factors: Sequence[torch.Tensor]) -> torch.Tensor:
+    return NNTuckerLoss.apply(X, G, *factors)

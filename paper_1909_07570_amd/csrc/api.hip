@@ -1,0 +1,825 @@
+// C ABI of the library: argument validation (before any HIP call), workspace planning,
+// the sweep schedule of the nonnegative Tucker multiplicative updates, the nnCP / lift /
+// residual / adjoint entry points.
+//
+// Sweep schedule (d modes, factors 0..d-1 updated in order, then the core):
+//   pass 1: P = X x_{d-1} A_{d-1}^T                     (streams X; contraction index contiguous)
+//   for n < d-1:  Y_n = P x_{k<n} A_k^T(new) x_{n<k<d-1} A_k^T(old); update A_n
+//           (A_{d-1} has not changed yet, so P serves every one of these modes; the prefix
+//            P x_0 A_0^T ... x_{n-1} A_{n-1}^T is kept and extended mode by mode)
+//   pass 2: T = X x_0 A_0^T(new)                          (streams X; contraction index strided)
+//           Y_{d-1} = T x_1 A_1^T ... x_{d-2} A_{d-2}^T;  update A_{d-1}
+//   core:   num_G = Y_{d-1} x_{d-1} A_{d-1}^T(new),  den_G = G x_k A_k^T A_k;  update G
+// By the commutativity of mode products (Appendix A) every Y_n equals X x_{k!=n} A_k^T with
+// the Gauss-Seidel factors, so two passes over X per sweep suffice for any d.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <chrono>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "nnc_internal.h"
+
+namespace nnc {
+
+static thread_local std::string g_err = "no error";
+static int g_timing = 0;
+
+nnc_status fail(nnc_status st, const char *fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+static int64_t prod(const int64_t *a, int lo, int hi) {
+  int64_t p = 1;
+  for (int k = lo; k < hi; ++k) p *= a[k];
+  return p;
+}
+
+static nnc_status check_dims(int ndim, const int64_t *dims, const char *what) {
+  if (ndim < 2 || ndim > kMaxDim) return fail(NNC_EINVAL, "ndim %d outside [2, %d]", ndim, kMaxDim);
+  if (!dims) return fail(NNC_EINVAL, "%s is NULL", what);
+  double p = 1.0;
+  for (int k = 0; k < ndim; ++k) {
+    if (dims[k] < 1) return fail(NNC_EINVAL, "%s[%d] = %lld < 1", what, k, (long long)dims[k]);
+    p *= (double)dims[k];
+  }
+  if (p > 4.0e18) return fail(NNC_EINVAL, "%s: element count overflows", what);
+  return NNC_OK;
+}
+
+static nnc_status check_ptrs(const void *const *ptrs, int n, const char *what) {
+  if (!ptrs) return fail(NNC_EINVAL, "%s is NULL", what);
+  for (int k = 0; k < n; ++k)
+    if (!ptrs[k]) return fail(NNC_EINVAL, "%s[%d] is NULL", what, k);
+  return NNC_OK;
+}
+
+// ------------------------------------------------------------------ workspace layout
+struct Layout {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return o;
+  }
+};
+
+struct TuckerPlan {
+  int d = 0;
+  int64_t N[kMaxDim], R[kMaxDim];
+  int64_t size = 0, gsize = 0;
+  int64_t nP = 0, nT = 0, nU = 0, nC = 0, nY = 0, nNum = 0, nS = 0, nM = 0;
+  size_t oP, oT, oU0, oU1, oC0, oC1, oY, oNum, oDen, oS, oM, oG0, oG1, oG2, oG3, oClip, oFlag,
+      oRed, oPart, total;
+};
+
+static void grow(int64_t &v, int64_t x) {
+  if (x > v) v = x;
+}
+
+// Sizes of every intermediate of the schedule above (and of the residual's expansion
+// G x_0 A_0 ... x_{d-2} A_{d-2}), so that the same code paths fit in the buffers.
+static TuckerPlan plan_tucker(int d, const int64_t *dims, const int64_t *rk) {
+  TuckerPlan p;
+  p.d = d;
+  for (int k = 0; k < d; ++k) {
+    p.N[k] = dims[k];
+    p.R[k] = rk[k];
+  }
+  p.size = prod(p.N, 0, d);
+  p.gsize = prod(p.R, 0, d);
+  p.nP = p.size / p.N[d - 1] * p.R[d - 1];
+  p.nT = p.size / p.N[0] * p.R[0];
+  int64_t cur[kMaxDim];
+  for (int n = 0; n < d - 1; ++n) {
+    // U_n = P x_{k<n} A_k^T : dims R_0..R_{n-1}, N_n..N_{d-2}, R_{d-1}
+    for (int k = 0; k < d; ++k) cur[k] = (k < n || k == d - 1) ? p.R[k] : p.N[k];
+    if (n >= 1) grow(p.nU, prod(cur, 0, d));
+    for (int k = n + 1; k < d - 1; ++k) {
+      cur[k] = p.R[k];
+      if (k < d - 2) grow(p.nC, prod(cur, 0, d));
+    }
+  }
+  for (int k = 0; k < d; ++k) cur[k] = (k == 0) ? p.R[0] : p.N[k];
+  for (int k = 1; k < d - 1; ++k) {
+    cur[k] = p.R[k];
+    if (k < d - 2) grow(p.nC, prod(cur, 0, d));
+  }
+  for (int k = 0; k < d; ++k) cur[k] = p.R[k];
+  for (int k = 0; k < d - 1; ++k) {
+    cur[k] = p.N[k];
+    if (k < d - 2) grow(p.nC, prod(cur, 0, d));
+  }
+  for (int n = 0; n < d; ++n) {
+    grow(p.nY, p.gsize / p.R[n] * p.N[n]);
+    grow(p.nNum, p.N[n] * p.R[n]);
+    grow(p.nM, p.R[n] * p.R[n]);
+    p.nS += p.R[n] * p.R[n];
+  }
+  Layout L;
+  p.oP = L.take(sizeof(float) * p.nP);
+  p.oT = L.take(sizeof(float) * p.nT);
+  p.oU0 = L.take(sizeof(float) * p.nU);
+  p.oU1 = L.take(sizeof(float) * p.nU);
+  p.oC0 = L.take(sizeof(float) * p.nC);
+  p.oC1 = L.take(sizeof(float) * p.nC);
+  p.oY = L.take(sizeof(float) * p.nY);
+  p.oNum = L.take(sizeof(float) * p.nNum);
+  p.oDen = L.take(sizeof(float) * p.nNum);
+  p.oS = L.take(sizeof(float) * p.nS);
+  p.oM = L.take(sizeof(float) * p.nM);
+  p.oG0 = L.take(sizeof(float) * p.gsize);
+  p.oG1 = L.take(sizeof(float) * p.gsize);
+  p.oG2 = L.take(sizeof(float) * p.gsize);
+  p.oG3 = L.take(sizeof(float) * p.gsize);
+  p.oClip = L.take(sizeof(unsigned long long));
+  p.oFlag = L.take(sizeof(unsigned int));
+  p.oRed = L.take(2 * sizeof(double));
+  p.oPart = L.take(2 * sizeof(double) * resid_stream_max_blocks());
+  p.total = L.off;
+  return p;
+}
+
+struct TuckerBufs {
+  char *base;
+  const TuckerPlan *p;
+  float *f(size_t off) const { return reinterpret_cast<float *>(base + off); }
+  float *P() const { return f(p->oP); }
+  float *T() const { return f(p->oT); }
+  float *U(int i) const { return f(i ? p->oU1 : p->oU0); }
+  float *C(int i) const { return f(i ? p->oC1 : p->oC0); }
+  float *Y() const { return f(p->oY); }
+  float *num() const { return f(p->oNum); }
+  float *den() const { return f(p->oDen); }
+  float *S(int k) const {
+    size_t o = p->oS;
+    for (int j = 0; j < k; ++j) o += sizeof(float) * p->R[j] * p->R[j];
+    return f(o);
+  }
+  float *M() const { return f(p->oM); }
+  float *G(int i) const {
+    const size_t o[4] = {p->oG0, p->oG1, p->oG2, p->oG3};
+    return f(o[i]);
+  }
+  unsigned long long *clips() const { return reinterpret_cast<unsigned long long *>(base + p->oClip); }
+  unsigned int *flag() const { return reinterpret_cast<unsigned int *>(base + p->oFlag); }
+  double *red() const { return reinterpret_cast<double *>(base + p->oRed); }
+  double *part() const { return reinterpret_cast<double *>(base + p->oPart); }
+};
+
+// ------------------------------------------------------------------ TTM helpers
+// out = in x_k A^T where `in` has dims cur (float) and A is cur[k] x R (row-major).
+static nnc_status ttm_mode(const void *in, nnc_dtype dt, int d, const int64_t *cur, int k,
+                           const float *A, int64_t R, float *out, hipStream_t s,
+                           bool mfma = true) {
+  return launch_ttm(in, dt, prod(cur, 0, k), cur[k], prod(cur, k + 1, d), A, R, 1, R, out, s, mfma);
+}
+
+// out = in x_k A where A is N x cur[k] stored as a factor (N rows of cur[k]): the expansion
+// of mode k from a rank index back to a data index.
+static nnc_status expand_mode(const float *in, int d, const int64_t *cur, int k, const float *A,
+                              int64_t N, float *out, hipStream_t s) {
+  return launch_ttm(in, NNC_F32, prod(cur, 0, k), cur[k], prod(cur, k + 1, d), A, 1, cur[k], N, out,
+                    s, false);
+}
+
+// Chain of contractions of the modes in `modes` (in order) of `src` (dims cur, updated in
+// place), factors A[k] (cur[k] x R[k]).  Intermediates ping-pong in C0/C1, the result goes
+// to `dst`.  With no modes, returns src.
+static nnc_status chain(const float *src, int d, int64_t *cur, const int *modes, int nm,
+                        float *const *A, const int64_t *R, float *c0, float *c1, float *dst,
+                        const float **result, hipStream_t s) {
+  const float *in = src;
+  for (int i = 0; i < nm; ++i) {
+    const int k = modes[i];
+    float *out = (i == nm - 1) ? dst : ((i % 2) ? c1 : c0);
+    NNC_TRY(ttm_mode(in, NNC_F32, d, cur, k, A[k], R[k], out, s));
+    cur[k] = R[k];
+    in = out;
+  }
+  *result = in;
+  return NNC_OK;
+}
+
+// H = G x_{k != skip} S_k (core space), skip = -1: every mode.  Ping-pongs in G buffers 0/1,
+// result pointer returned.
+static nnc_status core_chain(const TuckerBufs &b, const float *G, int skip, float *dst,
+                             const float **result, hipStream_t s) {
+  const TuckerPlan &p = *b.p;
+  int64_t cur[kMaxDim];
+  for (int k = 0; k < p.d; ++k) cur[k] = p.R[k];
+  const float *in = G;
+  int cnt = 0, total = 0;
+  for (int k = 0; k < p.d; ++k)
+    if (k != skip) ++total;
+  for (int k = 0; k < p.d; ++k) {
+    if (k == skip) continue;
+    float *out = (cnt == total - 1 && dst) ? dst : b.G(cnt % 2);
+    NNC_TRY(ttm_mode(in, NNC_F32, p.d, cur, k, b.S(k), p.R[k], out, s, false));
+    in = out;
+    ++cnt;
+  }
+  *result = in;
+  return NNC_OK;
+}
+
+// num_n, M_n and, when `grad` is null, the MU update of A_n and its new Gram; when `grad`
+// is given, grad = A_n M_n - num_n instead (no update).
+static nnc_status factor_block(const TuckerBufs &b, int n, const float *Y, const float *G,
+                               float *A, double eps, float *grad, hipStream_t s) {
+  const TuckerPlan &p = *b.p;
+  const int64_t pre = prod(p.R, 0, n), post = prod(p.R, n + 1, p.d);
+  NNC_TRY(launch_contract_except(Y, G, pre, p.N[n], p.R[n], post, b.num(), s));
+  const float *H = nullptr;
+  NNC_TRY(core_chain(b, G, n, nullptr, &H, s));
+  NNC_TRY(launch_contract_except(H, G, pre, p.R[n], p.R[n], post, b.M(), s));
+  if (grad) {
+    NNC_TRY(launch_matmul_small(A, b.M(), p.N[n], p.R[n], p.R[n], b.den(), s));
+    NNC_TRY(launch_sub(b.den(), b.num(), grad, p.N[n] * p.R[n], s));
+    return NNC_OK;
+  }
+  NNC_TRY(launch_mu_factor(A, b.num(), b.M(), p.N[n], p.R[n], eps, b.clips(), s));
+  NNC_TRY(launch_gram(A, p.N[n], p.R[n], b.S(n), s));
+  return NNC_OK;
+}
+
+// ------------------------------------------------------------------ pass timing
+struct PassTimer {
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  nnc_status start(hipStream_t s) {
+    if (used + 2 > ev.size()) {
+      for (int i = 0; i < 64; ++i) {
+        hipEvent_t e;
+        NNC_HIP(hipEventCreate(&e));
+        ev.push_back(e);
+      }
+    }
+    NNC_HIP(hipEventRecord(ev[used], s));
+    return NNC_OK;
+  }
+  nnc_status stop(hipStream_t s) {
+    NNC_HIP(hipEventRecord(ev[used + 1], s));
+    used += 2;
+    return NNC_OK;
+  }
+  nnc_status total_ms(double *ms) {
+    double t = 0;
+    for (size_t i = 0; i + 1 < used; i += 2) {
+      NNC_HIP(hipEventSynchronize(ev[i + 1]));
+      float x = 0.f;
+      NNC_HIP(hipEventElapsedTime(&x, ev[i], ev[i + 1]));
+      t += x;
+    }
+    *ms = t;
+    return NNC_OK;
+  }
+  ~PassTimer() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+// ------------------------------------------------------------------ one sweep
+static nnc_status tucker_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, float *G,
+                               float *const *A, double eps, hipStream_t s, PassTimer *tm) {
+  const TuckerPlan &p = *b.p;
+  const int d = p.d;
+  // pass 1
+  if (tm) NNC_TRY(tm->start(s));
+  NNC_TRY(launch_ttm(X, dt, p.size / p.N[d - 1], p.N[d - 1], 1, A[d - 1], p.R[d - 1], 1, p.R[d - 1],
+                     b.P(), s, true));
+  if (tm) NNC_TRY(tm->stop(s));
+  const float *U = b.P();
+  for (int n = 0; n < d - 1; ++n) {
+    int64_t cur[kMaxDim];
+    for (int k = 0; k < d; ++k) cur[k] = (k < n || k == d - 1) ? p.R[k] : p.N[k];
+    int modes[kMaxDim], nm = 0;
+    for (int k = n + 1; k < d - 1; ++k) modes[nm++] = k;
+    const float *Y = nullptr;
+    int64_t ycur[kMaxDim];
+    memcpy(ycur, cur, sizeof ycur);
+    NNC_TRY(chain(U, d, ycur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
+    NNC_TRY(factor_block(b, n, Y, G, A[n], eps, nullptr, s));
+    if (n < d - 2) {
+      float *Un = b.U(n % 2);
+      NNC_TRY(ttm_mode(U, NNC_F32, d, cur, n, A[n], p.R[n], Un, s));
+      U = Un;
+    }
+  }
+  // pass 2
+  if (tm) NNC_TRY(tm->start(s));
+  NNC_TRY(launch_ttm(X, dt, 1, p.N[0], p.size / p.N[0], A[0], p.R[0], 1, p.R[0], b.T(), s, true));
+  if (tm) NNC_TRY(tm->stop(s));
+  {
+    int64_t cur[kMaxDim];
+    for (int k = 0; k < d; ++k) cur[k] = (k == 0) ? p.R[0] : p.N[k];
+    int modes[kMaxDim], nm = 0;
+    for (int k = 1; k < d - 1; ++k) modes[nm++] = k;
+    const float *Y = nullptr;
+    NNC_TRY(chain(b.T(), d, cur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
+    NNC_TRY(factor_block(b, d - 1, Y, G, A[d - 1], eps, nullptr, s));
+    // core: num_G = Y x_{d-1} A_{d-1}^T (cur[d-1] is N_{d-1} here)
+    NNC_TRY(ttm_mode(Y, NNC_F32, d, cur, d - 1, A[d - 1], p.R[d - 1], b.G(2), s, false));
+  }
+  const float *den = nullptr;
+  NNC_TRY(core_chain(b, G, -1, b.G(3), &den, s));
+  NNC_TRY(launch_mu_elem(G, b.G(2), den, p.gsize, eps, b.clips(), s));
+  return NNC_OK;
+}
+
+// ||X - G x {A}||^2 and ||X||^2 into b.red() (device), Tucker model.
+static nnc_status tucker_resid(const TuckerBufs &b, const void *X, nnc_dtype dt, const float *G,
+                               const float *const *A, hipStream_t s) {
+  const TuckerPlan &p = *b.p;
+  const int d = p.d;
+  int64_t cur[kMaxDim];
+  for (int k = 0; k < d; ++k) cur[k] = p.R[k];
+  const float *in = G;
+  for (int k = 0; k < d - 1; ++k) {
+    float *out = (k == d - 2) ? b.P() : b.C(k % 2);
+    NNC_TRY(expand_mode(in, d, cur, k, A[k], p.N[k], out, s));
+    cur[k] = p.N[k];
+    in = out;
+  }
+  int nb = 0;
+  NNC_TRY(launch_resid_stream(X, dt, p.size / p.N[d - 1], p.N[d - 1], in, A[d - 1], p.R[d - 1],
+                              b.part(), &nb, s));
+  NNC_TRY(launch_reduce_pairs(b.part(), nb, b.red(), s));
+  return NNC_OK;
+}
+
+static nnc_status read_red(const TuckerBufs &b, double out[2], hipStream_t s) {
+  NNC_HIP(hipMemcpyAsync(out, b.red(), 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  NNC_HIP(hipStreamSynchronize(s));
+  return NNC_OK;
+}
+
+static double rel_of(const double red[2]) { return red[1] > 0 ? sqrt(red[0] / red[1]) : 0.0; }
+
+// A library-owned stream for graph capture when the caller passes the default stream
+// (which cannot be captured).  Default priority.
+static hipStream_t capture_stream() {
+  static std::mutex mu;
+  static hipStream_t st = nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!st) {
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
+  }
+  return st;
+}
+
+}  // namespace nnc
+
+using namespace nnc;
+
+extern "C" {
+
+const char *nnc_last_error(void) { return g_err.c_str(); }
+
+void nnc_set_timing(int on) { g_timing = on ? 1 : 0; }
+
+int nnc_device_ok(void) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return 0;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+  return strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
+}
+
+nnc_status nnc_ttm(const void *X, nnc_dtype xdt, int ndim, const int64_t *dims, int n,
+                   const float *A, int64_t R, float *out, void *stream) {
+  NNC_TRY(check_dims(ndim, dims, "dims"));
+  if (!X || !A || !out) return fail(NNC_EINVAL, "X, A and out must be non-NULL");
+  if (xdt != NNC_F32 && xdt != NNC_BF16) return fail(NNC_EINVAL, "unknown dtype %d", (int)xdt);
+  if (n < 0 || n >= ndim) return fail(NNC_EINVAL, "mode %d outside [0, %d)", n, ndim);
+  if (R < 1) return fail(NNC_EINVAL, "R = %lld < 1", (long long)R);
+  return launch_ttm(X, xdt, prod(dims, 0, n), dims[n], prod(dims, n + 1, ndim), A, R, 1, R, out,
+                    (hipStream_t)stream, true);
+}
+
+nnc_status nnc_convert_f32_bf16(const float *in, uint16_t *out, int64_t count, void *stream) {
+  if (!in || !out) return fail(NNC_EINVAL, "in and out must be non-NULL");
+  if (count < 0) return fail(NNC_EINVAL, "count < 0");
+  if (count == 0) return NNC_OK;
+  return launch_convert_bf16(in, out, count, (hipStream_t)stream);
+}
+
+size_t nntucker_workspace_bytes(int ndim, const int64_t *dims, const int64_t *multirank) {
+  if (check_dims(ndim, dims, "dims") != NNC_OK) return 0;
+  if (check_dims(ndim, multirank, "multirank") != NNC_OK) return 0;
+  return plan_tucker(ndim, dims, multirank).total;
+}
+
+nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *dims,
+                        const int64_t *multirank, int iters, float *core, float *const *factors,
+                        const nnc_options *opt, nnc_report *rep, void *stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  NNC_TRY(check_dims(ndim, dims, "dims"));
+  NNC_TRY(check_dims(ndim, multirank, "multirank"));
+  if (!X) return fail(NNC_EINVAL, "X is NULL");
+  if (!core) return fail(NNC_EINVAL, "core is NULL");
+  NNC_TRY(check_ptrs((const void *const *)factors, ndim, "factors"));
+  if (xdt != NNC_F32 && xdt != NNC_BF16) return fail(NNC_EINVAL, "unknown dtype %d", (int)xdt);
+  if (iters < 0) return fail(NNC_EINVAL, "iters = %d < 0", iters);
+  for (int k = 0; k < ndim; ++k)
+    if (multirank[k] > 256)
+      return fail(NNC_EUNSUPPORTED, "multirank[%d] = %lld above 256", k, (long long)multirank[k]);
+  nnc_options o;
+  memset(&o, 0, sizeof o);
+  if (opt) o = *opt;
+  if (o.eps < 0) return fail(NNC_EINVAL, "eps < 0");
+  const double eps = o.eps > 0 ? o.eps : 1e-12;
+  if (o.fp32_final_sweeps < 0) return fail(NNC_EINVAL, "fp32_final_sweeps < 0");
+  if (o.fp32_final_sweeps > 0 && xdt != NNC_BF16)
+    return fail(NNC_EINVAL, "fp32_final_sweeps needs X in NNC_BF16");
+  if (o.fp32_final_sweeps > 0 && !o.x_fp32)
+    return fail(NNC_EINVAL, "fp32_final_sweeps > 0 needs x_fp32");
+  if (o.objective_every < 0) return fail(NNC_EINVAL, "objective_every < 0");
+  if (o.objective_every > 0 && (!rep || !rep->objective_history))
+    return fail(NNC_EINVAL, "objective_every > 0 needs rep->objective_history");
+  const TuckerPlan p = plan_tucker(ndim, dims, multirank);
+  if (!o.workspace) return fail(NNC_EWORKSPACE, "workspace is NULL (need %zu bytes)", p.total);
+  if (o.workspace_bytes < p.total)
+    return fail(NNC_EWORKSPACE, "workspace has %zu bytes, need %zu", o.workspace_bytes, p.total);
+
+  hipStream_t s = (hipStream_t)stream;
+  TuckerBufs b{(char *)o.workspace, &p};
+  NNC_HIP(hipMemsetAsync(b.clips(), 0, sizeof(unsigned long long), s));
+  NNC_HIP(hipMemsetAsync(b.flag(), 0, sizeof(unsigned int), s));
+  for (int k = 0; k < ndim; ++k) NNC_TRY(launch_gram(factors[k], p.N[k], p.R[k], b.S(k), s));
+
+  PassTimer timer;
+  PassTimer *tm = g_timing ? &timer : nullptr;
+  const bool graphs = o.use_graph && !g_timing;
+  const int split = (xdt == NNC_BF16 && o.fp32_final_sweeps > 0)
+                        ? (iters > o.fp32_final_sweeps ? iters - o.fp32_final_sweeps : 0)
+                        : iters;
+  const float *xres = o.x_fp32 ? o.x_fp32 : (const float *)X;
+  const nnc_dtype dres = o.x_fp32 ? NNC_F32 : xdt;
+  int hist = 0;
+
+  // run sweeps [t0, t1) on (Xs, dts)
+  auto run_range = [&](int ta, int tb, const void *Xs, nnc_dtype dts) -> nnc_status {
+    if (ta >= tb) return NNC_OK;
+    const bool every = o.objective_every > 0;
+    if (!graphs) {
+      for (int t = ta; t < tb; ++t) {
+        NNC_TRY(tucker_sweep(b, Xs, dts, core, factors, eps, s, tm));
+        if (every && (t + 1) % o.objective_every == 0) {
+          NNC_TRY(tucker_resid(b, xres, dres, core, factors, s));
+          double red[2];
+          NNC_TRY(read_red(b, red, s));
+          rep->objective_history[hist++] = rel_of(red);
+        }
+      }
+      return NNC_OK;
+    }
+    hipStream_t cs = s;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    if (!s) {
+      cs = capture_stream();
+      if (!cs) return fail(NNC_EHIP, "could not create a capture stream");
+      NNC_HIP(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
+      NNC_HIP(hipEventCreateWithFlags(&ev_out, hipEventDisableTiming));
+      NNC_HIP(hipEventRecord(ev_in, s));
+      NNC_HIP(hipStreamWaitEvent(cs, ev_in, 0));
+    }
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    NNC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    nnc_status st = tucker_sweep(b, Xs, dts, core, factors, eps, cs, nullptr);
+    hipError_t ec = hipStreamEndCapture(cs, &g);
+    if (st != NNC_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (ec != hipSuccess) return fail(NNC_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
+    NNC_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+    for (int t = ta; t < tb; ++t) {
+      NNC_HIP(hipGraphLaunch(ge, cs));
+      if (every && (t + 1) % o.objective_every == 0) {
+        NNC_TRY(tucker_resid(b, xres, dres, core, factors, cs));
+        double red[2];
+        NNC_TRY(read_red(b, red, cs));
+        rep->objective_history[hist++] = rel_of(red);
+      }
+    }
+    NNC_HIP(hipGraphExecDestroy(ge));
+    NNC_HIP(hipGraphDestroy(g));
+    if (!s) {
+      NNC_HIP(hipEventRecord(ev_out, cs));
+      NNC_HIP(hipStreamWaitEvent(s, ev_out, 0));
+      NNC_HIP(hipEventDestroy(ev_in));
+      NNC_HIP(hipEventDestroy(ev_out));
+    }
+    return NNC_OK;
+  };
+  NNC_TRY(run_range(0, split, X, xdt));
+  NNC_TRY(run_range(split, iters, o.x_fp32, NNC_F32));
+
+  if (rep) {
+    NNC_TRY(tucker_resid(b, xres, dres, core, factors, s));
+    NNC_TRY(launch_check_finite(core, p.gsize, b.flag(), s));
+    for (int k = 0; k < ndim; ++k) NNC_TRY(launch_check_finite(factors[k], p.N[k] * p.R[k], b.flag(), s));
+    double red[2];
+    unsigned long long clips = 0;
+    unsigned int flag = 0;
+    NNC_HIP(hipMemcpyAsync(red, b.red(), sizeof red, hipMemcpyDeviceToHost, s));
+    NNC_HIP(hipMemcpyAsync(&clips, b.clips(), sizeof clips, hipMemcpyDeviceToHost, s));
+    NNC_HIP(hipMemcpyAsync(&flag, b.flag(), sizeof flag, hipMemcpyDeviceToHost, s));
+    NNC_HIP(hipStreamSynchronize(s));
+    rep->sweeps_done = iters;
+    rep->rel_residual = rel_of(red);
+    rep->eps_clips = (long long)clips;
+    rep->history_len = hist;
+    rep->ttm_pass_ms = 0;
+    rep->ttm_pass_launches = (long long)(timer.used / 2);
+    if (tm) NNC_TRY(timer.total_ms(&rep->ttm_pass_ms));
+    rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (flag || !std::isfinite(rep->rel_residual))
+      return fail(NNC_ENUMERIC, "non-finite values in the fitted model (NaN or Inf in X?)");
+  }
+  return NNC_OK;
+}
+
+size_t reconstruct_workspace_bytes(int ndim, const int64_t *dims, const int64_t *model_dims,
+                                   int is_cp) {
+  if (check_dims(ndim, dims, "dims") != NNC_OK || !model_dims) return 0;
+  if (is_cp) {
+    if (model_dims[0] < 1) return 0;
+    Layout L;
+    L.take(sizeof(float) * (size_t)(prod(dims, 0, ndim - 1) * model_dims[0]));
+    L.take(2 * sizeof(double));
+    L.take(2 * sizeof(double) * resid_stream_max_blocks());
+    return L.off;
+  }
+  if (check_dims(ndim, model_dims, "model_dims") != NNC_OK) return 0;
+  return plan_tucker(ndim, dims, model_dims).total;
+}
+
+static nnc_status resid_impl(const void *X, nnc_dtype xdt, int ndim, const int64_t *dims,
+                             const float *core, const int64_t *model_dims,
+                             const float *const *factors, double red[2], void *workspace,
+                             size_t workspace_bytes, void *stream) {
+  NNC_TRY(check_dims(ndim, dims, "dims"));
+  if (!X || !model_dims) return fail(NNC_EINVAL, "X and model_dims must be non-NULL");
+  if (xdt != NNC_F32 && xdt != NNC_BF16) return fail(NNC_EINVAL, "unknown dtype %d", (int)xdt);
+  NNC_TRY(check_ptrs((const void *const *)factors, ndim, "factors"));
+  const bool cp = core == nullptr;
+  if (cp && model_dims[0] < 1) return fail(NNC_EINVAL, "rank %lld < 1", (long long)model_dims[0]);
+  if (!cp) NNC_TRY(check_dims(ndim, model_dims, "model_dims"));
+  const size_t need = reconstruct_workspace_bytes(ndim, dims, model_dims, cp ? 1 : 0);
+  if (!workspace || workspace_bytes < need)
+    return fail(NNC_EWORKSPACE, "workspace has %zu bytes, need %zu", workspace ? workspace_bytes : 0, need);
+  hipStream_t s = (hipStream_t)stream;
+  if (cp) {
+    const int64_t r = model_dims[0];
+    Layout L;
+    const size_t oW = L.take(sizeof(float) * (size_t)(prod(dims, 0, ndim - 1) * r));
+    const size_t oRed = L.take(2 * sizeof(double));
+    const size_t oPart = L.take(2 * sizeof(double) * resid_stream_max_blocks());
+    char *base = (char *)workspace;
+    float *W = (float *)(base + oW);
+    NNC_TRY(launch_kr_rows(ndim, dims, r, factors, W, s));
+    int nb = 0;
+    NNC_TRY(launch_resid_stream(X, xdt, prod(dims, 0, ndim - 1), dims[ndim - 1], W, factors[ndim - 1],
+                                r, (double *)(base + oPart), &nb, s));
+    NNC_TRY(launch_reduce_pairs((double *)(base + oPart), nb, (double *)(base + oRed), s));
+    NNC_HIP(hipMemcpyAsync(red, base + oRed, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    NNC_HIP(hipStreamSynchronize(s));
+  } else {
+    const TuckerPlan p = plan_tucker(ndim, dims, model_dims);
+    TuckerBufs b{(char *)workspace, &p};
+    NNC_TRY(tucker_resid(b, X, xdt, core, factors, s));
+    NNC_TRY(read_red(b, red, s));
+  }
+  if (!std::isfinite(red[0]) || !std::isfinite(red[1]))
+    return fail(NNC_ENUMERIC, "non-finite residual (NaN or Inf in X or the model)");
+  return NNC_OK;
+}
+
+nnc_status reconstruct_residual(const void *X, nnc_dtype xdt, int ndim, const int64_t *dims,
+                                const float *core, const int64_t *model_dims,
+                                const float *const *factors, double *rel_residual,
+                                void *workspace, size_t workspace_bytes, void *stream) {
+  if (!rel_residual) return fail(NNC_EINVAL, "rel_residual is NULL");
+  double red[2];
+  NNC_TRY(resid_impl(X, xdt, ndim, dims, core, model_dims, factors, red, workspace, workspace_bytes,
+                     stream));
+  *rel_residual = rel_of(red);
+  return NNC_OK;
+}
+
+nnc_status reconstruct_sq_sums(const void *X, nnc_dtype xdt, int ndim, const int64_t *dims,
+                               const float *core, const int64_t *model_dims,
+                               const float *const *factors, double *sq_error, double *sq_norm,
+                               void *workspace, size_t workspace_bytes, void *stream) {
+  if (!sq_error || !sq_norm) return fail(NNC_EINVAL, "sq_error and sq_norm must be non-NULL");
+  double red[2];
+  NNC_TRY(resid_impl(X, xdt, ndim, dims, core, model_dims, factors, red, workspace, workspace_bytes,
+                     stream));
+  *sq_error = red[0];
+  *sq_norm = red[1];
+  return NNC_OK;
+}
+
+nnc_status nntucker_grad(const void *X, nnc_dtype xdt, int ndim, const int64_t *dims,
+                         const int64_t *multirank, const float *core, const float *const *factors,
+                         float *grad_core, float *const *grad_factors, double *loss,
+                         void *workspace, size_t workspace_bytes, void *stream) {
+  NNC_TRY(check_dims(ndim, dims, "dims"));
+  NNC_TRY(check_dims(ndim, multirank, "multirank"));
+  if (!X || !core || !grad_core) return fail(NNC_EINVAL, "X, core and grad_core must be non-NULL");
+  if (xdt != NNC_F32 && xdt != NNC_BF16) return fail(NNC_EINVAL, "unknown dtype %d", (int)xdt);
+  NNC_TRY(check_ptrs((const void *const *)factors, ndim, "factors"));
+  NNC_TRY(check_ptrs((const void *const *)grad_factors, ndim, "grad_factors"));
+  for (int k = 0; k < ndim; ++k)
+    if (multirank[k] > 256)
+      return fail(NNC_EUNSUPPORTED, "multirank[%d] = %lld above 256", k, (long long)multirank[k]);
+  const TuckerPlan p = plan_tucker(ndim, dims, multirank);
+  if (!workspace || workspace_bytes < p.total)
+    return fail(NNC_EWORKSPACE, "workspace has %zu bytes, need %zu", workspace ? workspace_bytes : 0, p.total);
+  hipStream_t s = (hipStream_t)stream;
+  TuckerBufs b{(char *)workspace, &p};
+  const int d = ndim;
+  float *const *A = const_cast<float *const *>(factors);
+  for (int k = 0; k < d; ++k) NNC_TRY(launch_gram(A[k], p.N[k], p.R[k], b.S(k), s));
+  // factors 0..d-2 from P = X x_{d-1} A_{d-1}^T (all factors held fixed)
+  NNC_TRY(launch_ttm(X, xdt, p.size / p.N[d - 1], p.N[d - 1], 1, A[d - 1], p.R[d - 1], 1, p.R[d - 1],
+                     b.P(), s, true));
+  for (int n = 0; n < d - 1; ++n) {
+    int64_t cur[kMaxDim];
+    for (int k = 0; k < d; ++k) cur[k] = (k == d - 1) ? p.R[k] : p.N[k];
+    int modes[kMaxDim], nm = 0;
+    for (int k = 0; k < d - 1; ++k)
+      if (k != n) modes[nm++] = k;
+    const float *Y = nullptr;
+    NNC_TRY(chain(b.P(), d, cur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
+    NNC_TRY(factor_block(b, n, Y, core, A[n], 0.0, grad_factors[n], s));
+  }
+  // factor d-1 and the core from T = X x_0 A_0^T
+  NNC_TRY(launch_ttm(X, xdt, 1, p.N[0], p.size / p.N[0], A[0], p.R[0], 1, p.R[0], b.T(), s, true));
+  int64_t cur[kMaxDim];
+  for (int k = 0; k < d; ++k) cur[k] = (k == 0) ? p.R[0] : p.N[k];
+  int modes[kMaxDim], nm = 0;
+  for (int k = 1; k < d - 1; ++k) modes[nm++] = k;
+  const float *Y = nullptr;
+  NNC_TRY(chain(b.T(), d, cur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
+  NNC_TRY(factor_block(b, d - 1, Y, core, A[d - 1], 0.0, grad_factors[d - 1], s));
+  NNC_TRY(ttm_mode(Y, NNC_F32, d, cur, d - 1, A[d - 1], p.R[d - 1], b.G(2), s, false));
+  const float *den = nullptr;
+  NNC_TRY(core_chain(b, core, -1, b.G(3), &den, s));
+  NNC_TRY(launch_sub(den, b.G(2), grad_core, p.gsize, s));
+  if (loss) {
+    NNC_TRY(tucker_resid(b, X, xdt, core, factors, s));
+    double red[2];
+    NNC_TRY(read_red(b, red, s));
+    *loss = 0.5 * red[0];
+    if (!std::isfinite(*loss)) return fail(NNC_ENUMERIC, "non-finite loss");
+  }
+  return NNC_OK;
+}
+
+// ------------------------------------------------------------------ nnCP of the core
+static nnc_status check_cp(const float *core, int ndim, const int64_t *core_dims, int rank,
+                           int iters) {
+  NNC_TRY(check_dims(ndim, core_dims, "core_dims"));
+  if (!core) return fail(NNC_EINVAL, "core is NULL");
+  if (rank < 1) return fail(NNC_EINVAL, "rank %d < 1", rank);
+  if (iters < 0) return fail(NNC_EINVAL, "iters = %d < 0", iters);
+  return NNC_OK;
+}
+
+static size_t cp_ws(int nbatch, int ndim) {
+  Layout L;
+  L.take(sizeof(int) * nbatch);
+  L.take(sizeof(float *) * (size_t)nbatch * ndim);
+  L.take(sizeof(double) * nbatch);
+  L.take(sizeof(unsigned long long));
+  return L.off;
+}
+
+size_t nncp_workspace_bytes(int ndim, const int64_t *core_dims, int rank) {
+  if (check_cp((const float *)1, ndim, core_dims, rank, 0) != NNC_OK) return 0;
+  return cp_ws(1, ndim);
+}
+
+size_t nncp_batched_workspace_bytes(int ndim, const int64_t *core_dims, int nbatch, const int *ranks) {
+  if (nbatch < 1 || !ranks) return 0;
+  if (check_dims(ndim, core_dims, "core_dims") != NNC_OK) return 0;
+  return cp_ws(nbatch, ndim);
+}
+
+static CpProblem cp_problem(int ndim, const int64_t *core_dims) {
+  CpProblem pb;
+  pb.d = ndim;
+  pb.size = 1;
+  for (int k = 0; k < ndim; ++k) {
+    pb.dims[k] = core_dims[k];
+    pb.size *= core_dims[k];
+  }
+  return pb;
+}
+
+nnc_status nncp_fit(const float *core, int ndim, const int64_t *core_dims, int rank, int iters,
+                    float *const *cp_factors, double eps, double *rel_residual, void *workspace,
+                    size_t workspace_bytes, void *stream) {
+  NNC_TRY(check_cp(core, ndim, core_dims, rank, iters));
+  NNC_TRY(check_ptrs((const void *const *)cp_factors, ndim, "cp_factors"));
+  if (eps < 0) return fail(NNC_EINVAL, "eps < 0");
+  if (rank > 64) return fail(NNC_EUNSUPPORTED, "rank %d above 64", rank);
+  const size_t need = cp_ws(1, ndim);
+  if (!workspace || workspace_bytes < need)
+    return fail(NNC_EWORKSPACE, "workspace has %zu bytes, need %zu", workspace ? workspace_bytes : 0, need);
+  const CpProblem pb = cp_problem(ndim, core_dims);
+  hipStream_t s = (hipStream_t)stream;
+  Layout L;
+  L.take(sizeof(int));
+  L.take(sizeof(float *) * ndim);
+  const size_t oRes = L.take(sizeof(double));
+  const size_t oClip = L.take(sizeof(unsigned long long));
+  char *base = (char *)workspace;
+  NNC_HIP(hipMemsetAsync(base + oClip, 0, sizeof(unsigned long long), s));
+  NNC_TRY(launch_nncp(core, pb, 1, nullptr, rank, nullptr, cp_factors, iters, eps > 0 ? eps : 1e-12,
+                      rel_residual ? (double *)(base + oRes) : nullptr,
+                      (unsigned long long *)(base + oClip), 0, s));
+  if (rel_residual) {
+    NNC_HIP(hipMemcpyAsync(rel_residual, base + oRes, sizeof(double), hipMemcpyDeviceToHost, s));
+    NNC_HIP(hipStreamSynchronize(s));
+    if (!std::isfinite(*rel_residual)) return fail(NNC_ENUMERIC, "non-finite nnCP residual");
+  }
+  return NNC_OK;
+}
+
+nnc_status nncp_fit_batched(const float *core, int ndim, const int64_t *core_dims, int nbatch,
+                            const int *ranks, int iters, float *const *cp_factors, double eps,
+                            double *rel_residuals, int threads_per_fit, void *workspace,
+                            size_t workspace_bytes, void *stream) {
+  NNC_TRY(check_cp(core, ndim, core_dims, 1, iters));
+  if (nbatch < 1) return fail(NNC_EINVAL, "nbatch %d < 1", nbatch);
+  if (!ranks || !rel_residuals) return fail(NNC_EINVAL, "ranks and rel_residuals must be non-NULL");
+  NNC_TRY(check_ptrs((const void *const *)cp_factors, nbatch * ndim, "cp_factors"));
+  if (eps < 0) return fail(NNC_EINVAL, "eps < 0");
+  int maxr = 0;
+  for (int j = 0; j < nbatch; ++j) {
+    if (ranks[j] < 1) return fail(NNC_EINVAL, "ranks[%d] = %d < 1", j, ranks[j]);
+    if (ranks[j] > 32) return fail(NNC_EUNSUPPORTED, "ranks[%d] = %d above 32", j, ranks[j]);
+    if (ranks[j] > maxr) maxr = ranks[j];
+  }
+  if (threads_per_fit != 0 && (threads_per_fit < 64 || threads_per_fit > 1024 || threads_per_fit % 64))
+    return fail(NNC_EINVAL, "threads_per_fit must be 0 or a multiple of 64 in [64, 1024]");
+  const size_t need = cp_ws(nbatch, ndim);
+  if (!workspace || workspace_bytes < need)
+    return fail(NNC_EWORKSPACE, "workspace has %zu bytes, need %zu", workspace ? workspace_bytes : 0, need);
+  const CpProblem pb = cp_problem(ndim, core_dims);
+  hipStream_t s = (hipStream_t)stream;
+  Layout L;
+  const size_t oRank = L.take(sizeof(int) * nbatch);
+  const size_t oPtr = L.take(sizeof(float *) * (size_t)nbatch * ndim);
+  const size_t oRes = L.take(sizeof(double) * nbatch);
+  const size_t oClip = L.take(sizeof(unsigned long long));
+  char *base = (char *)workspace;
+  // The tables are copied before the launch; the call synchronises below, so the host
+  // arrays only need to live for the duration of the call.
+  NNC_HIP(hipMemcpyAsync(base + oRank, ranks, sizeof(int) * nbatch, hipMemcpyHostToDevice, s));
+  NNC_HIP(hipMemcpyAsync(base + oPtr, cp_factors, sizeof(float *) * (size_t)nbatch * ndim,
+                         hipMemcpyHostToDevice, s));
+  NNC_HIP(hipMemsetAsync(base + oClip, 0, sizeof(unsigned long long), s));
+  NNC_TRY(launch_nncp(core, pb, nbatch, (const int *)(base + oRank), maxr,
+                      (float *const *)(base + oPtr), nullptr, iters, eps > 0 ? eps : 1e-12,
+                      (double *)(base + oRes), (unsigned long long *)(base + oClip),
+                      threads_per_fit, s));
+  NNC_HIP(hipMemcpyAsync(rel_residuals, base + oRes, sizeof(double) * nbatch, hipMemcpyDeviceToHost, s));
+  NNC_HIP(hipStreamSynchronize(s));
+  for (int j = 0; j < nbatch; ++j)
+    if (!std::isfinite(rel_residuals[j])) return fail(NNC_ENUMERIC, "non-finite residual of fit %d", j);
+  return NNC_OK;
+}
+
+nnc_status nncandelinc_lift(int ndim, const int64_t *dims, const int64_t *multirank, int rank,
+                            const float *const *tucker_factors, const float *const *cp_factors,
+                            float *const *out_factors, void *stream) {
+  NNC_TRY(check_dims(ndim, dims, "dims"));
+  NNC_TRY(check_dims(ndim, multirank, "multirank"));
+  if (rank < 1) return fail(NNC_EINVAL, "rank %d < 1", rank);
+  NNC_TRY(check_ptrs((const void *const *)tucker_factors, ndim, "tucker_factors"));
+  NNC_TRY(check_ptrs((const void *const *)cp_factors, ndim, "cp_factors"));
+  NNC_TRY(check_ptrs((const void *const *)out_factors, ndim, "out_factors"));
+  hipStream_t s = (hipStream_t)stream;
+  for (int k = 0; k < ndim; ++k)
+    NNC_TRY(launch_lift(tucker_factors[k], cp_factors[k], dims[k], multirank[k], rank, out_factors[k], s));
+  return NNC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,759 @@
+// HIP kernels for gfx950 (CDNA4): tensor-times-matrix contractions on MFMA, multiplicative
+// update steps, residual reductions and conversions.
+//
+// Contraction forms (n-mode product with a transposed factor, Appendix A):
+//   X viewed as [P][N][Q] (N = the contracted mode, Q = product of the later modes):
+//     out[p][r][q] = sum_n F(n, r) * X[p][n][q].
+//   Q == 1 (last mode, contraction index contiguous)  -> ttm_last_*  (X is an M x K matrix)
+//   Q  > 1 (earlier mode, contraction index strided)  -> ttm_mid_*   (coalesced along q)
+// The MFMA kernels keep the factor (<= 32 columns, zero-padded to 16-column tiles) in LDS
+// and stream X once in its natural layout.
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <mutex>
+#include <set>
+
+#include "nnc_internal.h"
+
+namespace nnc {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+
+static __device__ inline uint16_t f2bf_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+static __device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+static __device__ inline float load_x(const float *p) { return *p; }
+static __device__ inline float load_x(const uint16_t *p) { return bf2f(*p); }
+
+static __device__ inline bf8 as_bf8(u4 v) { return __builtin_bit_cast(bf8, v); }
+
+static __device__ inline f4 mfma_bf16(u4 a, u4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(a), as_bf8(b), c, 0, 0, 0);
+}
+
+// =====================================================================================
+// Last-mode contraction, FP32 MFMA (v_mfma_f32_16x16x4_f32).
+// out[m][r] = sum_k X[m][k] F(k, r);  X is M x K row-major, K % 4 == 0.
+// A wave owns 16-row tiles.  Lane (li = lane%16, lg = lane/16) loads the float4
+// X[row li][k0 + 4 lg .. +3]; component c feeds the MFMA whose k-slot lg stands for
+// k = k0 + 4 lg + c, paired with the factor row k from LDS.
+// =====================================================================================
+constexpr int kTtmThreads = 512;
+
+template <int RT>
+__global__ __launch_bounds__(kTtmThreads) void ttm_last_f32_k(const float *__restrict__ X, int64_t M,
+                                                              int K, const float *__restrict__ F,
+                                                              int64_t ldl, int64_t ldr, int R,
+                                                              float *__restrict__ out) {
+  extern __shared__ __attribute__((aligned(16))) float lds[];
+  constexpr int RP = 16 * RT;
+  constexpr int RS = RP + 4;  // row stride: the four lane groups hit distinct bank ranges
+  const int Kp = (K + 15) & ~15;
+  for (int e = threadIdx.x; e < Kp * RP; e += blockDim.x) {
+    const int k = e / RP, r = e - k * RP;
+    lds[k * RS + r] = (k < K && r < R) ? F[k * ldl + r * ldr] : 0.f;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int nw = blockDim.x >> 6;
+  const int64_t ntile = (M + 15) >> 4;
+  for (int64_t t = (int64_t)blockIdx.x * nw + wave; t < ntile; t += (int64_t)gridDim.x * nw) {
+    const int64_t row = t * 16 + li;
+    const bool rv = row < M;
+    const float *xr = X + (rv ? row : 0) * (int64_t)K;
+    f4 acc[RT];
+#pragma unroll
+    for (int nt = 0; nt < RT; ++nt) acc[nt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+    for (int k0 = 0; k0 < Kp; k0 += 16) {
+      const int kk = k0 + 4 * lg;
+      f4 xv = f4{0.f, 0.f, 0.f, 0.f};
+      if (rv && kk < K) xv = *reinterpret_cast<const f4 *>(xr + kk);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float *brow = lds + (kk + c) * RS + li;
+#pragma unroll
+        for (int nt = 0; nt < RT; ++nt)
+          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[c], brow[nt * 16], acc[nt], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int nt = 0; nt < RT; ++nt) {
+      const int r = nt * 16 + li;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t m = t * 16 + 4 * lg + j;
+        if (m < M && r < R) out[m * R + r] = acc[nt][j];
+      }
+    }
+  }
+}
+
+// =====================================================================================
+// Last-mode contraction, BF16 MFMA (v_mfma_f32_16x16x32_bf16), FP32 accumulation.
+// X is bfloat16 M x K, K % 8 == 0.  Lane (li, lg) loads 8 bf16 X[row li][k0 + 8 lg .. +7]
+// (16 bytes) as its A operand.  The factor is staged transposed in LDS as bf16 rows of k
+// so that each lane reads its 8-k B operand with one 16-byte load.  With SPLIT the factor
+// is carried as hi + lo bf16 parts (hi = bf16(f), lo = bf16(f - hi)) and both are applied,
+// so only the rounding of X remains.
+// =====================================================================================
+template <int RT, bool SPLIT>
+__global__ __launch_bounds__(kTtmThreads) void ttm_last_bf16_k(const uint16_t *__restrict__ X,
+                                                               int64_t M, int K,
+                                                               const float *__restrict__ F,
+                                                               int64_t ldl, int64_t ldr, int R,
+                                                               float *__restrict__ out) {
+  extern __shared__ __attribute__((aligned(16))) uint16_t ldsb[];
+  constexpr int RP = 16 * RT;
+  const int Kp = (K + 31) & ~31;
+  const int KS = Kp + 8;  // 16-byte pad per row
+  uint16_t *hi = ldsb;
+  uint16_t *lo = ldsb + RP * KS;
+  for (int e = threadIdx.x; e < RP * Kp; e += blockDim.x) {
+    const int r = e / Kp, k = e - r * Kp;
+    const float a = (k < K && r < R) ? F[k * ldl + r * ldr] : 0.f;
+    const uint16_t h = f2bf_rne(a);
+    hi[r * KS + k] = h;
+    if (SPLIT) lo[r * KS + k] = f2bf_rne(a - bf2f(h));
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int nw = blockDim.x >> 6;
+  const int64_t ntile = (M + 15) >> 4;
+  for (int64_t t = (int64_t)blockIdx.x * nw + wave; t < ntile; t += (int64_t)gridDim.x * nw) {
+    const int64_t row = t * 16 + li;
+    const bool rv = row < M;
+    const uint16_t *xr = X + (rv ? row : 0) * (int64_t)K;
+    f4 acc[RT];
+#pragma unroll
+    for (int nt = 0; nt < RT; ++nt) acc[nt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+    for (int k0 = 0; k0 < Kp; k0 += 32) {
+      const int kk = k0 + 8 * lg;
+      u4 xv = u4{0u, 0u, 0u, 0u};
+      if (rv && kk < K) xv = *reinterpret_cast<const u4 *>(xr + kk);
+#pragma unroll
+      for (int nt = 0; nt < RT; ++nt) {
+        const int off = (nt * 16 + li) * KS + kk;
+        acc[nt] = mfma_bf16(xv, *reinterpret_cast<const u4 *>(hi + off), acc[nt]);
+        if (SPLIT) acc[nt] = mfma_bf16(xv, *reinterpret_cast<const u4 *>(lo + off), acc[nt]);
+      }
+    }
+#pragma unroll
+    for (int nt = 0; nt < RT; ++nt) {
+      const int r = nt * 16 + li;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t m = t * 16 + 4 * lg + j;
+        if (m < M && r < R) out[m * R + r] = acc[nt][j];
+      }
+    }
+  }
+}
+
+// =====================================================================================
+// Earlier-mode contraction, FP32 MFMA.  X is [P][N][Q], Q % 4 == 0.
+// A wave owns 64 consecutive q of one p.  Lane (li, lg) loads the float4
+// X[p][n0 + lg][q0 + 4 li .. +3] (16 lanes read 256 contiguous bytes of one row n);
+// component c feeds MFMA c, whose output row i stands for q = q0 + 4 i + c.
+// Output rows of lane group lg are then q0 + 16 lg + [0, 16): stored as float4s.
+// =====================================================================================
+template <int RT>
+__global__ __launch_bounds__(kTtmThreads) void ttm_mid_f32_k(const float *__restrict__ X, int64_t P,
+                                                             int N, int64_t Q,
+                                                             const float *__restrict__ F,
+                                                             int64_t ldl, int64_t ldr, int R,
+                                                             float *__restrict__ out) {
+  extern __shared__ __attribute__((aligned(16))) float lds[];
+  constexpr int RP = 16 * RT;
+  constexpr int RS = RP + 4;  // row pad: the four lane groups read rows 4 banks apart
+  const int Np = (N + 3) & ~3;
+  for (int e = threadIdx.x; e < Np * RP; e += blockDim.x) {
+    const int n = e / RP, r = e - n * RP;
+    lds[n * RS + r] = (n < N && r < R) ? F[n * ldl + r * ldr] : 0.f;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int nw = blockDim.x >> 6;
+  const int64_t qt = (Q + 63) >> 6;
+  const int64_t ntile = P * qt;
+  for (int64_t t = (int64_t)blockIdx.x * nw + wave; t < ntile; t += (int64_t)gridDim.x * nw) {
+    const int64_t p = t / qt;
+    const int64_t q0 = (t - p * qt) * 64;
+    const int64_t qa = q0 + 4 * li;
+    const bool qv = qa < Q;
+    const float *xp = X + p * (int64_t)N * Q + (qv ? qa : 0);
+    f4 acc[4][RT];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int nt = 0; nt < RT; ++nt) acc[c][nt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+    for (int n0 = 0; n0 < Np; n0 += 4) {
+      const int n = n0 + lg;
+      f4 xv = f4{0.f, 0.f, 0.f, 0.f};
+      if (qv && n < N) xv = *reinterpret_cast<const f4 *>(xp + (int64_t)n * Q);
+      const float *brow = lds + n * RS + li;
+#pragma unroll
+      for (int nt = 0; nt < RT; ++nt) {
+        const float b = brow[nt * 16];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          acc[c][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[c], b, acc[c][nt], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int nt = 0; nt < RT; ++nt) {
+      const int r = nt * 16 + li;
+      if (r >= R) continue;
+      float *orow = out + (p * R + r) * Q;
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int64_t q = q0 + 16 * lg + 4 * jj;
+        if (q < Q)
+          *reinterpret_cast<f4 *>(orow + q) =
+              f4{acc[0][nt][jj], acc[1][nt][jj], acc[2][nt][jj], acc[3][nt][jj]};
+      }
+    }
+  }
+}
+
+// =====================================================================================
+// Earlier-mode contraction, BF16 MFMA.  X is bf16 [P][N][Q], Q % 8 == 0.
+// A wave owns 128 consecutive q of one p.  Lane (li, lg) loads eight 16-byte rows
+// X[p][n0 + 8 lg + j][q0 + 8 li .. +7], j = 0..7, i.e. an 8 (n) x 8 (q) block, and
+// transposes it in registers into eight A operands (one per q offset c, each holding the
+// 8 n values of that q).  MFMA c's output row i stands for q = q0 + 8 i + c, so lane group
+// lg ends up owning q0 + 32 lg + [0, 32).
+// =====================================================================================
+template <int RT, bool SPLIT>
+__global__ __launch_bounds__(kTtmThreads) void ttm_mid_bf16_k(const uint16_t *__restrict__ X,
+                                                              int64_t P, int N, int64_t Q,
+                                                              const float *__restrict__ F,
+                                                              int64_t ldl, int64_t ldr, int R,
+                                                              float *__restrict__ out) {
+  extern __shared__ __attribute__((aligned(16))) uint16_t ldsb[];
+  constexpr int RP = 16 * RT;
+  const int Np = (N + 31) & ~31;
+  const int NS = Np + 8;
+  uint16_t *hi = ldsb;
+  uint16_t *lo = ldsb + RP * NS;
+  for (int e = threadIdx.x; e < RP * Np; e += blockDim.x) {
+    const int r = e / Np, n = e - r * Np;
+    const float a = (n < N && r < R) ? F[n * ldl + r * ldr] : 0.f;
+    const uint16_t h = f2bf_rne(a);
+    hi[r * NS + n] = h;
+    if (SPLIT) lo[r * NS + n] = f2bf_rne(a - bf2f(h));
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int nw = blockDim.x >> 6;
+  const int64_t qt = (Q + 127) >> 7;
+  const int64_t ntile = P * qt;
+  for (int64_t t = (int64_t)blockIdx.x * nw + wave; t < ntile; t += (int64_t)gridDim.x * nw) {
+    const int64_t p = t / qt;
+    const int64_t q0 = (t - p * qt) * 128;
+    const int64_t qa = q0 + 8 * li;
+    const bool qv = qa < Q;
+    const uint16_t *xp = X + p * (int64_t)N * Q + (qv ? qa : 0);
+    f4 acc[8][RT];
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+      for (int nt = 0; nt < RT; ++nt) acc[c][nt] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int n0 = 0; n0 < Np; n0 += 32) {
+      u4 v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int n = n0 + 8 * lg + j;
+        v[j] = (qv && n < N) ? *reinterpret_cast<const u4 *>(xp + (int64_t)n * Q)
+                             : u4{0u, 0u, 0u, 0u};
+      }
+      u4 bh[RT], bl[RT];
+#pragma unroll
+      for (int nt = 0; nt < RT; ++nt) {
+        const int off = (nt * 16 + li) * NS + n0 + 8 * lg;
+        bh[nt] = *reinterpret_cast<const u4 *>(hi + off);
+        if (SPLIT) bl[nt] = *reinterpret_cast<const u4 *>(lo + off);
+      }
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        u4 op;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const uint32_t a = v[2 * w][c >> 1], b = v[2 * w + 1][c >> 1];
+          op[w] = (c & 1) ? ((a >> 16) | (b & 0xffff0000u)) : ((a & 0xffffu) | (b << 16));
+        }
+#pragma unroll
+        for (int nt = 0; nt < RT; ++nt) {
+          acc[c][nt] = mfma_bf16(op, bh[nt], acc[c][nt]);
+          if (SPLIT) acc[c][nt] = mfma_bf16(op, bl[nt], acc[c][nt]);
+        }
+      }
+    }
+#pragma unroll
+    for (int nt = 0; nt < RT; ++nt) {
+      const int r = nt * 16 + li;
+      if (r >= R) continue;
+      float *orow = out + (p * R + r) * Q;
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int64_t q = q0 + 32 * lg + 8 * jj;
+        if (q < Q) {
+          *reinterpret_cast<f4 *>(orow + q) =
+              f4{acc[0][nt][jj], acc[1][nt][jj], acc[2][nt][jj], acc[3][nt][jj]};
+          *reinterpret_cast<f4 *>(orow + q + 4) =
+              f4{acc[4][nt][jj], acc[5][nt][jj], acc[6][nt][jj], acc[7][nt][jj]};
+        }
+      }
+    }
+  }
+}
+
+// =====================================================================================
+// General contraction (any shape, any R): one thread per (p, 4 columns r, q), sequential
+// sum over the contracted index.
+// =====================================================================================
+template <typename XT>
+__global__ __launch_bounds__(256) void ttm_generic_k(const XT *__restrict__ X, int64_t P, int64_t N,
+                                                     int64_t Q, const float *__restrict__ F,
+                                                     int64_t ldl, int64_t ldr, int64_t R,
+                                                     float *__restrict__ out) {
+  const int64_t RC = (R + 3) >> 2;
+  const int64_t total = P * RC * Q;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = idx % Q;
+    const int64_t t = idx / Q;
+    const int64_t rc = t % RC;
+    const int64_t p = t / RC;
+    const int64_t r0 = rc * 4;
+    const int nr = (int)((R - r0) < 4 ? (R - r0) : 4);
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    const XT *x = X + p * N * Q + q;
+    for (int64_t l = 0; l < N; ++l) {
+      const float xv = load_x(x + l * Q);
+      const float *f = F + l * ldl + r0 * ldr;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (j < nr) acc[j] = fmaf(f[j * ldr], xv, acc[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (j < nr) out[(p * R + r0 + j) * Q + q] = acc[j];
+  }
+}
+
+static int grid_for(int64_t work, int threads, int cap) {
+  int64_t g = (work + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// Blocks for the streaming MFMA kernels: enough to fill 256 CUs several times while each
+// block still amortises its LDS staging of the factor over many tiles.
+constexpr int kStreamBlocks = 1024;
+
+// Dynamic LDS above 64 KiB must be allowed per kernel once.
+static nnc_status allow_big_lds(const void *kern) {
+  static std::mutex mu;
+  static std::set<const void *> done;
+  std::lock_guard<std::mutex> lk(mu);
+  if (done.count(kern)) return NNC_OK;
+  NNC_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  done.insert(kern);
+  return NNC_OK;
+}
+
+template <typename... KArgs, typename... Args>
+static nnc_status launch_stream(void (*kern)(KArgs...), size_t lds, int64_t tiles, hipStream_t s,
+                                Args... args) {
+  NNC_TRY(allow_big_lds(reinterpret_cast<const void *>(kern)));
+  const int waves = kTtmThreads / 64;
+  const int grid = grid_for(tiles, waves, kStreamBlocks);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kTtmThreads), lds, s, static_cast<KArgs>(args)...);
+  return NNC_OK;
+}
+
+nnc_status launch_ttm(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64_t Q, const float *F,
+                      int64_t ldl, int64_t ldr, int64_t R, float *out, hipStream_t s,
+                      bool allow_mfma, const char **kernel_name) {
+  const char *name = "ttm_generic";
+  const int64_t total_rows = P * N * Q;
+  if (total_rows == 0 || R == 0) return NNC_OK;
+  const bool small_r = R <= 32;
+  const int RT = R <= 16 ? 1 : 2;
+  bool done = false;
+  if (allow_mfma && small_r && aligned16(X) && aligned16(out) && N <= 2048 && N < (1 << 20)) {
+    if (Q == 1) {
+      // last-mode contraction: X is (P) x (N) with contiguous rows
+      const int64_t M = P;
+      const int K = (int)N;
+      const int64_t tiles = (M + 15) / 16;
+      if (xdt == NNC_F32 && K % 4 == 0) {
+        const int Kp = (K + 15) & ~15;
+        const size_t lds = (size_t)Kp * (16 * RT + 4) * sizeof(float);
+        if (lds <= 96 * 1024) {
+          if (RT == 1)
+            NNC_TRY(launch_stream(ttm_last_f32_k<1>, lds, tiles, s, X, M, K, F, ldl, ldr, (int)R, out));
+          else
+            NNC_TRY(launch_stream(ttm_last_f32_k<2>, lds, tiles, s, X, M, K, F, ldl, ldr, (int)R, out));
+          name = "ttm_last_f32";
+          done = true;
+        }
+      } else if (xdt == NNC_BF16 && K % 8 == 0) {
+        const int Kp = (K + 31) & ~31;
+        const size_t lds = (size_t)2 * (16 * RT) * (Kp + 8) * sizeof(uint16_t);
+        if (lds <= 96 * 1024) {
+          if (RT == 1)
+            NNC_TRY(launch_stream(ttm_last_bf16_k<1, true>, lds, tiles, s, X, M, K, F, ldl, ldr, (int)R, out));
+          else
+            NNC_TRY(launch_stream(ttm_last_bf16_k<2, true>, lds, tiles, s, X, M, K, F, ldl, ldr, (int)R, out));
+          name = "ttm_last_bf16";
+          done = true;
+        }
+      }
+    } else {
+      if (xdt == NNC_F32 && Q % 4 == 0) {
+        const int Np = ((int)N + 3) & ~3;
+        const size_t lds = (size_t)Np * (16 * RT + 4) * sizeof(float);
+        const int64_t tiles = P * ((Q + 63) / 64);
+        if (lds <= 96 * 1024) {
+          if (RT == 1)
+            NNC_TRY(launch_stream(ttm_mid_f32_k<1>, lds, tiles, s, X, P, N, Q, F, ldl, ldr, (int)R, out));
+          else
+            NNC_TRY(launch_stream(ttm_mid_f32_k<2>, lds, tiles, s, X, P, N, Q, F, ldl, ldr, (int)R, out));
+          name = "ttm_mid_f32";
+          done = true;
+        }
+      } else if (xdt == NNC_BF16 && Q % 8 == 0) {
+        const int Np = ((int)N + 31) & ~31;
+        const size_t lds = (size_t)2 * (16 * RT) * (Np + 8) * sizeof(uint16_t);
+        const int64_t tiles = P * ((Q + 127) / 128);
+        if (lds <= 96 * 1024) {
+          if (RT == 1)
+            NNC_TRY(launch_stream(ttm_mid_bf16_k<1, true>, lds, tiles, s, X, P, N, Q, F, ldl, ldr, (int)R, out));
+          else
+            NNC_TRY(launch_stream(ttm_mid_bf16_k<2, true>, lds, tiles, s, X, P, N, Q, F, ldl, ldr, (int)R, out));
+          name = "ttm_mid_bf16";
+          done = true;
+        }
+      }
+    }
+  }
+  if (!done) {
+    const int64_t work = P * ((R + 3) / 4) * Q;
+    const int grid = grid_for(work, 256, 65536);
+    if (xdt == NNC_F32)
+      hipLaunchKernelGGL(ttm_generic_k<float>, dim3(grid), dim3(256), 0, s, (const float *)X, P, N,
+                         Q, F, ldl, ldr, R, out);
+    else
+      hipLaunchKernelGGL(ttm_generic_k<uint16_t>, dim3(grid), dim3(256), 0, s, (const uint16_t *)X,
+                         P, N, Q, F, ldl, ldr, R, out);
+  }
+  if (kernel_name) *kernel_name = name;
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+// =====================================================================================
+// Small dense steps of the multiplicative updates.
+// =====================================================================================
+__global__ void contract_except_k(const float *__restrict__ U, const float *__restrict__ V,
+                                  int64_t pre, int64_t I, int64_t J, int64_t post,
+                                  float *__restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= I * J) return;
+  const int64_t i = idx / J, j = idx - (idx / J) * J;
+  float acc = 0.f;
+  for (int64_t p = 0; p < pre; ++p) {
+    const float *u = U + (p * I + i) * post;
+    const float *v = V + (p * J + j) * post;
+    for (int64_t q = 0; q < post; ++q) acc = fmaf(u[q], v[q], acc);
+  }
+  out[idx] = acc;
+}
+
+nnc_status launch_contract_except(const float *U, const float *V, int64_t pre, int64_t I, int64_t J,
+                                  int64_t post, float *out, hipStream_t s) {
+  const int64_t n = I * J;
+  hipLaunchKernelGGL(contract_except_k, dim3(grid_for(n, 128, 1 << 30)), dim3(128), 0, s, U, V, pre,
+                     I, J, post, out);
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+__global__ void gram_k(const float *__restrict__ A, int64_t N, int64_t R, float *__restrict__ S) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= R * R) return;
+  const int64_t r = idx / R, c = idx - (idx / R) * R;
+  float acc = 0.f;
+  for (int64_t i = 0; i < N; ++i) acc = fmaf(A[i * R + r], A[i * R + c], acc);
+  S[idx] = acc;
+}
+
+nnc_status launch_gram(const float *A, int64_t N, int64_t R, float *S, hipStream_t s) {
+  hipLaunchKernelGGL(gram_k, dim3(grid_for(R * R, 64, 1 << 30)), dim3(64), 0, s, A, N, R, S);
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+static __device__ inline float mu_step(float x, float num, float den, double eps,
+                                       unsigned long long *clips) {
+  double dd = (double)den;
+  if (dd < eps) {
+    dd = eps;
+    atomicAdd(clips, 1ull);
+  }
+  return (float)(((double)x * (double)num) / dd);
+}
+
+// Rows are owned by one block; every thread reads its row of A before the barrier and
+// writes its entry after it.
+__global__ void mu_factor_k(float *__restrict__ A, const float *__restrict__ num,
+                            const float *__restrict__ M, int64_t N, int64_t R, double eps,
+                            unsigned long long *clips) {
+  const int64_t rpb = blockDim.x / R;
+  const int64_t i = (int64_t)blockIdx.x * rpb + threadIdx.x / R;
+  const int64_t r = threadIdx.x % R;
+  const bool act = threadIdx.x < rpb * R && i < N;
+  float nv = 0.f;
+  if (act) {
+    float den = 0.f;
+    for (int64_t s = 0; s < R; ++s) den = fmaf(A[i * R + s], M[s * R + r], den);
+    nv = mu_step(A[i * R + r], num[i * R + r], den, eps, clips);
+  }
+  __syncthreads();
+  if (act) A[i * R + r] = nv;
+}
+
+nnc_status launch_mu_factor(float *A, const float *num, const float *M, int64_t N, int64_t R,
+                            double eps, unsigned long long *clips, hipStream_t s) {
+  const int threads = 256;
+  if (R > threads) return fail(NNC_EUNSUPPORTED, "rank %lld above %d", (long long)R, threads);
+  const int64_t rpb = threads / R;
+  hipLaunchKernelGGL(mu_factor_k, dim3((unsigned)((N + rpb - 1) / rpb)), dim3(threads), 0, s, A, num,
+                     M, N, R, eps, clips);
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+__global__ void mu_elem_k(float *__restrict__ x, const float *__restrict__ num,
+                          const float *__restrict__ den, int64_t n, double eps,
+                          unsigned long long *clips) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = mu_step(x[i], num[i], den[i], eps, clips);
+}
+
+nnc_status launch_mu_elem(float *x, const float *num, const float *den, int64_t n, double eps,
+                          unsigned long long *clips, hipStream_t s) {
+  hipLaunchKernelGGL(mu_elem_k, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, x, num, den, n, eps,
+                     clips);
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+__global__ void sub_k(const float *__restrict__ a, const float *__restrict__ b, float *__restrict__ o,
+                      int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    o[i] = a[i] - b[i];
+}
+
+nnc_status launch_sub(const float *den, const float *num, float *out, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(sub_k, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, den, num, out, n);
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+__global__ void matmul_small_k(const float *__restrict__ A, const float *__restrict__ M, int64_t N,
+                               int64_t R, int64_t C, float *__restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N * C) return;
+  const int64_t i = idx / C, c = idx - (idx / C) * C;
+  float acc = 0.f;
+  for (int64_t s = 0; s < R; ++s) acc = fmaf(A[i * R + s], M[s * C + c], acc);
+  out[idx] = acc;
+}
+
+nnc_status launch_matmul_small(const float *A, const float *M, int64_t N, int64_t R, int64_t C,
+                               float *out, hipStream_t s) {
+  hipLaunchKernelGGL(matmul_small_k, dim3(grid_for(N * C, 256, 1 << 30)), dim3(256), 0, s, A, M, N,
+                     R, C, out);
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+nnc_status launch_lift(const float *A, const float *B, int64_t N, int64_t Rm, int64_t r, float *C,
+                       hipStream_t s) {
+  return launch_matmul_small(A, B, N, Rm, r, C, s);
+}
+
+struct KrArgs {
+  int d;
+  int64_t dims[kMaxDim];
+  const float *C[kMaxDim];
+};
+
+// W[m][rho] = prod_{k < d-1} C_k[i_k][rho] for the flattened leading index m.
+__global__ void kr_rows_k(KrArgs a, int64_t lead, int64_t r, float *__restrict__ W) {
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < lead * r;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t rho = idx % r;
+    int64_t m = idx / r;
+    float p = 1.f;
+    for (int k = a.d - 2; k >= 0; --k) {
+      const int64_t ik = m % a.dims[k];
+      m /= a.dims[k];
+      p *= a.C[k][ik * r + rho];
+    }
+    W[idx] = p;
+  }
+}
+
+nnc_status launch_kr_rows(int d, const int64_t *dims, int64_t r, const float *const *C, float *W,
+                          hipStream_t s) {
+  KrArgs a;
+  a.d = d;
+  int64_t lead = 1;
+  for (int k = 0; k < d; ++k) {
+    a.dims[k] = dims[k];
+    a.C[k] = C[k];
+    if (k < d - 1) lead *= dims[k];
+  }
+  hipLaunchKernelGGL(kr_rows_k, dim3(grid_for(lead * r, 256, 65536)), dim3(256), 0, s, a, lead, r, W);
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+// =====================================================================================
+// Residual: sum over X (M x K) of (x - W[m,:] . Ad[k,:])^2 and of x^2, accumulated per
+// thread in double, then a fixed-shape tree per block.  The grid size depends only on
+// the problem size, so the summation order (and the result) is reproducible.
+// =====================================================================================
+constexpr int kResidThreads = 256;
+constexpr int kResidMaxBlocks = 2048;
+
+int resid_stream_max_blocks() { return kResidMaxBlocks; }
+
+template <typename XT>
+__global__ __launch_bounds__(kResidThreads) void resid_stream_k(const XT *__restrict__ X, int64_t M,
+                                                                int64_t K, const float *__restrict__ W,
+                                                                const float *__restrict__ Ad,
+                                                                int64_t R, double *__restrict__ part) {
+  __shared__ double s0[kResidThreads], s1[kResidThreads];
+  double sr = 0.0, sx = 0.0;
+  const int64_t total = M * K;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t m = e / K, k = e - (e / K) * K;
+    const float *w = W + m * R;
+    const float *a = Ad + k * R;
+    float xh = 0.f;
+    for (int64_t r = 0; r < R; ++r) xh = fmaf(w[r], a[r], xh);
+    const float x = load_x(X + e);
+    const double df = (double)x - (double)xh;
+    sr += df * df;
+    sx += (double)x * (double)x;
+  }
+  s0[threadIdx.x] = sr;
+  s1[threadIdx.x] = sx;
+  __syncthreads();
+  for (int w = kResidThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      s0[threadIdx.x] += s0[threadIdx.x + w];
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s0[0];
+    part[2 * blockIdx.x + 1] = s1[0];
+  }
+}
+
+nnc_status launch_resid_stream(const void *X, nnc_dtype xdt, int64_t M, int64_t K, const float *W,
+                               const float *Ad, int64_t R, double *part, int *nblocks_out,
+                               hipStream_t s) {
+  const int grid = grid_for(M * K, kResidThreads, kResidMaxBlocks);
+  if (xdt == NNC_F32)
+    hipLaunchKernelGGL(resid_stream_k<float>, dim3(grid), dim3(kResidThreads), 0, s,
+                       (const float *)X, M, K, W, Ad, R, part);
+  else
+    hipLaunchKernelGGL(resid_stream_k<uint16_t>, dim3(grid), dim3(kResidThreads), 0, s,
+                       (const uint16_t *)X, M, K, W, Ad, R, part);
+  *nblocks_out = grid;
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+__global__ void reduce_pairs_k(const double *__restrict__ part, int n, double *__restrict__ out) {
+  __shared__ double s0[256], s1[256];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
+  }
+  s0[threadIdx.x] = a;
+  s1[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      s0[threadIdx.x] += s0[threadIdx.x + w];
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = s0[0];
+    out[1] = s1[0];
+  }
+}
+
+nnc_status launch_reduce_pairs(const double *part, int n, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_pairs_k, dim3(1), dim3(256), 0, s, part, n, out);
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+__global__ void convert_bf16_k(const float *__restrict__ in, uint16_t *__restrict__ out, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = f2bf_rne(in[i]);
+}
+
+nnc_status launch_convert_bf16(const float *in, uint16_t *out, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(convert_bf16_k, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, in, out, n);
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+__global__ void check_finite_k(const float *__restrict__ x, int64_t n, unsigned int *flag) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if (!isfinite(x[i])) atomicOr(flag, 1u);
+}
+
+nnc_status launch_check_finite(const float *x, int64_t n, unsigned int *flag, hipStream_t s) {
+  hipLaunchKernelGGL(check_finite_k, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, x, n, flag);
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+}  // namespace nnc

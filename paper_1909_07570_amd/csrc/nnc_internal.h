@@ -1,0 +1,103 @@
+// Internal declarations shared by the library's translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "nncandelinc.h"
+
+namespace nnc {
+
+constexpr int kMaxDim = 8;
+
+// Sets the thread-local error message and returns `st`.
+nnc_status fail(nnc_status st, const char *fmt, ...);
+
+// Checks the result of a HIP call; on failure records the message.
+#define NNC_HIP(call)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return ::nnc::fail(NNC_EHIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                         __FILE__, __LINE__);                                            \
+  } while (0)
+
+#define NNC_TRY(expr)                 \
+  do {                                \
+    nnc_status s_ = (expr);           \
+    if (s_ != NNC_OK) return s_;      \
+  } while (0)
+
+// ------------------------------------------------------------------ launchers (kernels.hip)
+
+// out[p][r][q] = sum_l F(l, r) * X[p][l][q], F(l, r) = F[l*ldl + r*ldr];
+// X is [P][N][Q] of dtype xdt; out is [P][R][Q] float.  Chooses an MFMA kernel when the
+// shape allows (allow_mfma) and a general kernel otherwise.
+nnc_status launch_ttm(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64_t Q, const float *F,
+                      int64_t ldl, int64_t ldr, int64_t R, float *out, hipStream_t s,
+                      bool allow_mfma, const char **kernel_name = nullptr);
+
+// out[i][j] = sum_{p<pre, q<post} U[(p*I+i)*post+q] * V[(p*J+j)*post+q]
+nnc_status launch_contract_except(const float *U, const float *V, int64_t pre, int64_t I, int64_t J,
+                                  int64_t post, float *out, hipStream_t s);
+
+// S = A^T A for A (N x R)
+nnc_status launch_gram(const float *A, int64_t N, int64_t R, float *S, hipStream_t s);
+
+// A <- A * num / max(A M, eps) row-wise (A: N x R, M: R x R); counts clips.
+nnc_status launch_mu_factor(float *A, const float *num, const float *M, int64_t N, int64_t R,
+                            double eps, unsigned long long *clips, hipStream_t s);
+
+// x <- x * num / max(den, eps) elementwise.
+nnc_status launch_mu_elem(float *x, const float *num, const float *den, int64_t n, double eps,
+                          unsigned long long *clips, hipStream_t s);
+
+// out = den - num elementwise (gradients).
+nnc_status launch_sub(const float *den, const float *num, float *out, int64_t n, hipStream_t s);
+
+// out = A M (A: N x R, M: R x C)
+nnc_status launch_matmul_small(const float *A, const float *M, int64_t N, int64_t R, int64_t C,
+                               float *out, hipStream_t s);
+
+// Khatri-Rao rows W[m][rho] = prod_{k<d-1} C_k[i_k][rho] over the leading d-1 modes.
+nnc_status launch_kr_rows(int d, const int64_t *dims, int64_t r, const float *const *C, float *W,
+                          hipStream_t s);
+
+// Squared-residual partial sums of X (M x K) against W (M x R) * Ad (K x R)^T; writes
+// part[0..nblocks) pairs (sum (x-xhat)^2, sum x^2) and returns nblocks via *nblocks_out.
+nnc_status launch_resid_stream(const void *X, nnc_dtype xdt, int64_t M, int64_t K, const float *W,
+                               const float *Ad, int64_t R, double *part, int *nblocks_out,
+                               hipStream_t s);
+// out[0] = sum part[2i], out[1] = sum part[2i+1] in a fixed order.
+nnc_status launch_reduce_pairs(const double *part, int n, double *out, hipStream_t s);
+int resid_stream_max_blocks();
+
+nnc_status launch_convert_bf16(const float *in, uint16_t *out, int64_t n, hipStream_t s);
+
+// flag |= 1 if any of x[0..n) is not finite.
+nnc_status launch_check_finite(const float *x, int64_t n, unsigned int *flag, hipStream_t s);
+
+// ------------------------------------------------------------------ nnCP (cp_kernels.hip)
+struct CpProblem {
+  int d;
+  int64_t dims[kMaxDim];
+  int64_t size;  // prod dims
+};
+
+// One workgroup per fit.  Batched: fit b has rank d_ranks[b] <= max_rank and factor
+// pointers d_factor_ptrs[b*d + n] (device tables).  Single fit: d_ranks == nullptr,
+// nbatch == 1, rank max_rank and host array single_ptrs (passed by value).
+// d_resid (nullable) receives each fit's relative residual.
+nnc_status launch_nncp(const float *T, const CpProblem &pb, int nbatch, const int *d_ranks,
+                       int max_rank, float *const *d_factor_ptrs, float *const *single_ptrs,
+                       int iters, double eps, double *d_resid, unsigned long long *clips,
+                       int threads, hipStream_t s);
+int64_t nncp_lds_bytes(const CpProblem &pb, int max_rank, int threads);
+int nncp_default_threads(const CpProblem &pb, int max_rank);
+
+nnc_status launch_lift(const float *A, const float *B, int64_t N, int64_t Rm, int64_t r, float *C,
+                       hipStream_t s);
+
+}  // namespace nnc

@@ -78,7 +78,7 @@ def round_bf16(x: np.ndarray) -> np.ndarray:
     bfloat16 keeps 8 significant bits.  Only finite normal-range values are expected.
     """
     x = np.asarray(x, dtype=np.float64)
-    out = np.zeros_like(x)
+    out = x.copy()                  # zeros (of either sign) are already exact
     nz = x != 0
     _, e = np.frexp(x[nz])          # x = m * 2**e with 0.5 <= |m| < 1
     q = np.ldexp(1.0, e - 8)        # spacing of 8-significant-bit values in that binade

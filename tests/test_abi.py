@@ -1,0 +1,109 @@
+"""The C ABI on the CPU: every declared symbol is exported, and argument validation runs
+before any HIP call, so invalid calls return the documented status without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1909_07570_amd as nnc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "nncandelinc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\*?\s*([a-z_0-9]+)\s*\(", src, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared()
+    assert len(names) >= 15, names
+    L = nnc.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(nnc.EXPORTED)
+
+
+def D(*xs):
+    return (ctypes.c_int64 * len(xs))(*xs)
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+
+def _ptrs(n, null_at=None):
+    return (ctypes.c_void_p * n)(*[None if i == null_at else 0x1000 for i in range(n)])
+
+
+def test_workspace_queries():
+    L = nnc.lib()
+    b = L.nntucker_workspace_bytes(3, D(512, 512, 512), D(20, 20, 20))
+    assert b >= 4 * (512 * 512 * 20 * 2)
+    assert L.nntucker_workspace_bytes(1, D(5), D(5)) == 0
+    assert L.nntucker_workspace_bytes(3, D(5, 0, 5), D(2, 2, 2)) == 0
+    assert L.reconstruct_workspace_bytes(3, D(8, 8, 8), D(3, 0, 0), 1) > 0
+    assert L.nncp_workspace_bytes(3, D(5, 5, 5), 3) > 0
+
+
+def test_nntucker_fit_validation():
+    L = nnc.lib()
+    opt = nnc.Options()
+    opt.workspace = 0x1000
+    opt.workspace_bytes = 1 << 40
+    f = L.nntucker_fit
+    assert f(FAKE, 0, 1, D(4), D(2), 1, FAKE, _ptrs(1), ctypes.byref(opt), None, None) == nnc.NNC_EINVAL
+    assert f(FAKE, 0, 9, D(*[2] * 9), D(*[2] * 9), 1, FAKE, _ptrs(9), ctypes.byref(opt), None, None) == nnc.NNC_EINVAL
+    assert f(None, 0, 3, D(4, 4, 4), D(2, 2, 2), 1, FAKE, _ptrs(3), ctypes.byref(opt), None, None) == nnc.NNC_EINVAL
+    assert f(FAKE, 0, 3, D(4, 4, 4), D(2, 2, 2), 1, FAKE, _ptrs(3, 1), ctypes.byref(opt), None, None) == nnc.NNC_EINVAL
+    assert "factors[1]" in nnc.last_error()
+    assert f(FAKE, 0, 3, D(4, 4, 4), D(2, 0, 2), 1, FAKE, _ptrs(3), ctypes.byref(opt), None, None) == nnc.NNC_EINVAL
+    assert f(FAKE, 0, 3, D(4, 4, 4), D(2, 2, 2), -1, FAKE, _ptrs(3), ctypes.byref(opt), None, None) == nnc.NNC_EINVAL
+    assert f(FAKE, 7, 3, D(4, 4, 4), D(2, 2, 2), 1, FAKE, _ptrs(3), ctypes.byref(opt), None, None) == nnc.NNC_EINVAL
+    # refinement sweeps need bf16 X and an fp32 copy
+    o2 = nnc.Options()
+    o2.workspace, o2.workspace_bytes, o2.fp32_final_sweeps = 0x1000, 1 << 40, 5
+    assert f(FAKE, 0, 3, D(4, 4, 4), D(2, 2, 2), 10, FAKE, _ptrs(3), ctypes.byref(o2), None, None) == nnc.NNC_EINVAL
+    assert f(FAKE, 1, 3, D(4, 4, 4), D(2, 2, 2), 10, FAKE, _ptrs(3), ctypes.byref(o2), None, None) == nnc.NNC_EINVAL
+    # workspace
+    o3 = nnc.Options()
+    assert f(FAKE, 0, 3, D(4, 4, 4), D(2, 2, 2), 1, FAKE, _ptrs(3), ctypes.byref(o3), None, None) == nnc.NNC_EWORKSPACE
+    o3.workspace, o3.workspace_bytes = 0x1000, 16
+    assert f(FAKE, 0, 3, D(4, 4, 4), D(2, 2, 2), 1, FAKE, _ptrs(3), ctypes.byref(o3), None, None) == nnc.NNC_EWORKSPACE
+    # unsupported multirank
+    assert f(FAKE, 0, 3, D(400, 4, 4), D(300, 2, 2), 1, FAKE, _ptrs(3), ctypes.byref(opt), None, None) == nnc.NNC_EUNSUPPORTED
+
+
+def test_other_entry_points_validate():
+    L = nnc.lib()
+    assert L.nnc_ttm(FAKE, 0, 3, D(4, 4, 4), 3, FAKE, 2, FAKE, None) == nnc.NNC_EINVAL
+    assert L.nnc_ttm(FAKE, 0, 3, D(4, 4, 4), 0, FAKE, 0, FAKE, None) == nnc.NNC_EINVAL
+    assert L.nnc_ttm(FAKE, 2, 3, D(4, 4, 4), 0, FAKE, 2, FAKE, None) == nnc.NNC_EINVAL
+    assert L.nnc_convert_f32_bf16(None, FAKE, 4, None) == nnc.NNC_EINVAL
+    assert L.nnc_convert_f32_bf16(FAKE, FAKE, -1, None) == nnc.NNC_EINVAL
+    assert L.nncp_fit(FAKE, 3, D(5, 5, 5), 0, 10, _ptrs(3), 0.0, None, FAKE, 1 << 20, None) == nnc.NNC_EINVAL
+    assert L.nncp_fit(FAKE, 3, D(5, 5, 5), 3, 10, _ptrs(3, 2), 0.0, None, FAKE, 1 << 20, None) == nnc.NNC_EINVAL
+    assert L.nncp_fit(FAKE, 3, D(5, 5, 5), 3, 10, _ptrs(3), 0.0, None, None, 0, None) == nnc.NNC_EWORKSPACE
+    assert L.nncp_fit(FAKE, 3, D(5, 5, 5), 65, 10, _ptrs(3), 0.0, None, FAKE, 1 << 20, None) == nnc.NNC_EUNSUPPORTED
+    rk = (ctypes.c_int * 2)(3, 40)
+    res = (ctypes.c_double * 2)()
+    assert L.nncp_fit_batched(FAKE, 3, D(5, 5, 5), 2, rk, 10, _ptrs(6), 0.0, res, 0, FAKE, 1 << 20, None) == nnc.NNC_EUNSUPPORTED
+    rk0 = (ctypes.c_int * 2)(3, 0)
+    assert L.nncp_fit_batched(FAKE, 3, D(5, 5, 5), 2, rk0, 10, _ptrs(6), 0.0, res, 0, FAKE, 1 << 20, None) == nnc.NNC_EINVAL
+    rk1 = (ctypes.c_int * 2)(3, 4)
+    assert L.nncp_fit_batched(FAKE, 3, D(5, 5, 5), 2, rk1, 10, _ptrs(6), 0.0, res, 100, FAKE, 1 << 20, None) == nnc.NNC_EINVAL
+    assert L.nncandelinc_lift(3, D(4, 4, 4), D(2, 2, 2), 0, _ptrs(3), _ptrs(3), _ptrs(3), None) == nnc.NNC_EINVAL
+    assert L.nncandelinc_lift(3, D(4, 4, 4), D(2, 2, 2), 2, _ptrs(3), _ptrs(3, 0), _ptrs(3), None) == nnc.NNC_EINVAL
+    r = ctypes.c_double()
+    assert L.reconstruct_residual(FAKE, 0, 3, D(4, 4, 4), None, D(0, 0, 0), _ptrs(3), ctypes.byref(r), FAKE, 1 << 30, None) == nnc.NNC_EINVAL
+    assert L.reconstruct_residual(FAKE, 0, 3, D(4, 4, 4), FAKE, D(2, 2, 2), _ptrs(3), None, FAKE, 1 << 30, None) == nnc.NNC_EINVAL
+    assert L.reconstruct_residual(FAKE, 0, 3, D(4, 4, 4), FAKE, D(2, 2, 2), _ptrs(3), ctypes.byref(r), FAKE, 8, None) == nnc.NNC_EWORKSPACE
+    assert L.nntucker_grad(FAKE, 0, 3, D(4, 4, 4), D(2, 2, 2), FAKE, _ptrs(3), None, _ptrs(3), None, FAKE, 1 << 30, None) == nnc.NNC_EINVAL
+    assert L.nntucker_grad(FAKE, 0, 3, D(4, 4, 4), D(2, 2, 2), FAKE, _ptrs(3), FAKE, _ptrs(3), None, FAKE, 8, None) == nnc.NNC_EWORKSPACE
+
+
+def test_binding_rejects_cpu_tensors():
+    import torch
+    with pytest.raises(ValueError):
+        nnc.nnc_ttm(torch.zeros(4, 4, 4), 0, torch.zeros(4, 2))
