@@ -1,0 +1,203 @@
+"""Benchmark: nnTucker MU sweeps/s and TTM TFLOP/s on 512^3 (BF16-MFMA form vs FP32 form at
+equal final residual), whole Algorithm 1 per step (nnTucker -> nnCP of the core -> lift ->
+residual), on one GPU.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--sweeps 500] [--no-cpu]
+
+Prints ONE JSON line.  `value` is the BF16 form's nnTucker sweeps per second over the whole
+timed step (nnCP, lift and the final residual included).  The FP32 form is timed the same
+way and reported under "fp32_form"; both start from identical initial values and run the
+same number of sweeps, and their final relative residuals (both measured against the FP32
+X) are reported with their difference.
+
+The roofline object describes the dominant kernel (the X-streaming contraction of the BF16
+form, timed per launch with HIP events on the stream it runs on).  The cpu_baseline object
+times the FP64 oracle on a bounded sample (a few sweeps of the same 512^3 problem).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "nnTucker MU iters/s + TTM TFLOP/s, 512³: BF16-MFMA vs FP32 at equal residual"
+HBM_PEAK_GBS = 8000.0
+SEED = 2
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--sweeps", type=int, default=500)
+    ap.add_argument("--fp32-final", type=int, default=20)
+    ap.add_argument("--cp-sweeps", type=int, default=300)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sweeps", type=int, default=1)
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1909_07570_amd as nnc
+    import synth
+
+    if not torch.cuda.is_available() or not nnc.device_ok():
+        raise SystemExit("bench.py needs an MI355X (gfx950) GPU and the built library")
+    dev = torch.device("cuda:0")
+    N, R, rank = args.n, 20, 10
+    dims, ranks = (N, N, N), (R, R, R)
+
+    t0 = time.time()
+    X32h, _ = synth.planted_tensor(SEED, dims, 10, zero_prob=0.5, noise=1e-3, dtype="f32")
+    log("generated X %s in %.1fs" % (dims, time.time() - t0))
+    X32 = torch.from_numpy(X32h).to(dev)
+    G0 = torch.from_numpy(synth.init_core(SEED, ranks)).to(dev)
+    A0 = [torch.from_numpy(a).to(dev) for a in synth.init_factors(SEED, dims, ranks)]
+    B0 = [torch.from_numpy(b).to(dev) for b in synth.init_cp_factors(SEED, ranks, rank)]
+    torch.cuda.synchronize()
+    tc = time.time()
+    Xb = nnc.nnc_convert_f32_bf16(X32)
+    torch.cuda.synchronize()
+    convert_ms = (time.time() - tc) * 1e3
+
+    ws = torch.empty(nnc.nntucker_workspace_bytes(dims, ranks), dtype=torch.uint8, device=dev)
+    G = torch.empty_like(G0)
+    A = [torch.empty_like(a) for a in A0]
+    B = [torch.empty_like(b) for b in B0]
+
+    def step(bf16: bool):
+        G.copy_(G0)
+        for a, a0 in zip(A, A0):
+            a.copy_(a0)
+        for b, b0 in zip(B, B0):
+            b.copy_(b0)
+        if bf16:
+            nnc.nntucker_fit(Xb, ranks, args.sweeps, G, A, x_fp32=X32,
+                             fp32_final_sweeps=args.fp32_final, report=False, workspace=ws)
+        else:
+            nnc.nntucker_fit(X32, ranks, args.sweeps, G, A, report=False, workspace=ws)
+        nnc.nncp_fit(G, rank, args.cp_sweeps, B, residual=False)
+        C = nnc.nncandelinc_lift(A, B)
+        cp_rel = nnc.reconstruct_residual(X32, C)
+        tucker_rel = nnc.reconstruct_residual(X32, A, G)
+        return tucker_rel, cp_rel
+
+    results = {}
+    for form, bf16 in (("bf16", True), ("fp32", False)):
+        for _ in range(args.warmup):
+            step(bf16)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            tucker_rel, cp_rel = step(bf16)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        results[form] = dict(seconds=el, ms_per_step=el / args.steps * 1e3,
+                             sweeps_per_s=args.sweeps * args.steps / el,
+                             tucker_rel=tucker_rel, cp_rel=cp_rel)
+        log("%s: %.1f ms/step, %.0f sweeps/s, tucker rel %.6g, lifted rel %.6g"
+            % (form, results[form]["ms_per_step"], results[form]["sweeps_per_s"], tucker_rel, cp_rel))
+
+    # ---- per-launch timing of the two X-streaming contractions (same kernels, same launch
+    # configuration as inside the fit), HIP events on the stream they are launched on.
+    size = N ** 3
+    def time_kernel(Xt, mode, A_):
+        out = torch.empty([N, N, R] if mode == 2 else [R, N, N], dtype=torch.float32, device=dev)
+        for _ in range(3):
+            nnc.nnc_ttm(Xt, mode, A_, out)
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(args.kernel_reps):
+            nnc.nnc_ttm(Xt, mode, A_, out)
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.kernel_reps
+    kern = {}
+    for name, Xt, esz in (("bf16", Xb, 2), ("fp32", X32, 4)):
+        for mode, kname in ((2, "ttm_last"), (0, "ttm_mid")):
+            ms = time_kernel(Xt, mode, A0[mode])
+            bytes_ = size * esz + size // N * R * 4
+            kern["%s_%s" % (kname, name)] = dict(
+                avg_us=ms * 1e3, gbs=bytes_ / (ms * 1e-3) / 1e9,
+                tflops=2.0 * size * R / (ms * 1e-3) / 1e12, alg_bytes=bytes_)
+            log("%s_%s: %.1f us, %.0f GB/s, %.1f TFLOP/s" % (kname, name, ms * 1e3,
+                kern["%s_%s" % (kname, name)]["gbs"], kern["%s_%s" % (kname, name)]["tflops"]))
+    # in-fit cross-check: event-timed passes of an eager BF16 fit
+    nnc.set_timing(True)
+    G.copy_(G0)
+    for a, a0 in zip(A, A0):
+        a.copy_(a0)
+    rep = nnc.nntucker_fit(Xb, ranks, 20, G, A, workspace=ws)
+    nnc.set_timing(False)
+    infit_pass_us = rep.ttm_pass_ms / max(1, rep.ttm_pass_launches) * 1e3
+
+    dom = max(("ttm_last_bf16", "ttm_mid_bf16"), key=lambda k: kern[k]["avg_us"])
+    dk = kern[dom]
+    roofline = {"bound": "hbm", "achieved": round(dk["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(dk["gbs"] / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "avg_us": round(dk["avg_us"], 2), "alg_bytes_per_launch": dk["alg_bytes"]}
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        X64 = X32h.astype(np.float64)
+        g0 = synth.init_core(SEED, ranks).astype(np.float64)
+        a0 = [a.astype(np.float64) for a in synth.init_factors(SEED, dims, ranks)]
+        t = time.perf_counter()
+        oracle.nntucker(X64, g0, a0, args.cpu_sweeps)
+        el = time.perf_counter() - t
+        cpu = {"value": round(args.cpu_sweeps / el, 5), "unit": "MU sweeps/s", "cores": oracle.get_threads(),
+               "kind": "oracle",
+               "sample": "%d nnTucker sweep(s) of the same 512^3 problem (multirank 20^3) in FP64, %.1f s"
+                         % (args.cpu_sweeps, el)}
+        del X64
+
+    bf, fp = results["bf16"], results["fp32"]
+    sweep_flops = 2.0 * size * (R + R)  # the two X-streaming contractions of one sweep
+    line = {
+        "metric": METRIC, "value": round(bf["sweeps_per_s"], 2), "unit": "MU sweeps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(bf["ms_per_step"], 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "512^3 FP32 planted rank-10 tensor (U[0,1) factors zeroed w.p. 0.5, "
+                               "U[0,1e-3) noise); nnTucker multirank (20,20,20), %d MU sweeps "
+                               "(BF16-MFMA, last %d on FP32 X); nnCP rank %d, %d sweeps; lift; "
+                               "residuals" % (args.sweeps, args.fp32_final, rank, args.cp_sweeps),
+                   "dims": list(dims), "multirank": list(ranks), "cp_rank": rank,
+                   "sweeps": args.sweeps, "fp32_final_sweeps": args.fp32_final},
+        "ttm_tflops": round(sweep_flops * args.sweeps / (bf["seconds"] / args.steps) / 1e12, 2),
+        "ttm_kernel_tflops": {k: round(v["tflops"], 2) for k, v in kern.items()},
+        "kernels": {k: {"avg_us": round(v["avg_us"], 2), "GB/s": round(v["gbs"], 1)} for k, v in kern.items()},
+        "infit_pass_avg_us_bf16": round(infit_pass_us, 2),
+        "residuals": {"bf16_tucker": bf["tucker_rel"], "fp32_tucker": fp["tucker_rel"],
+                      "bf16_lifted_cp": bf["cp_rel"], "fp32_lifted_cp": fp["cp_rel"],
+                      "abs_diff_tucker": abs(bf["tucker_rel"] - fp["tucker_rel"])},
+        "fp32_form": {"value": round(fp["sweeps_per_s"], 2), "unit": "MU sweeps/s",
+                      "ms_per_step": round(fp["ms_per_step"], 3)},
+        "bf16_speedup_vs_fp32": round(bf["sweeps_per_s"] / fp["sweeps_per_s"], 3),
+        "x_to_bf16_ms": round(convert_ms, 3),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -136,7 +136,7 @@ nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *d
 
 /*
  * Nonnegative CP of a (small) tensor, here the Tucker core (the nnCPD step of Algorithm 1),
- * exactly `iters` MU sweeps in one persistent launch.
+ * exactly `iters` MU sweeps in one persistent launch.  rank <= 32.
  *   core        core_dims[0..ndim-1] floats.
  *   cp_factors  host array of ndim device pointers; factor n is core_dims[n] x rank;
  *               in: initial B_n >= 0; out: fitted B_n.

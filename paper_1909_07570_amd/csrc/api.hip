@@ -16,7 +16,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -77,9 +79,10 @@ struct TuckerPlan {
   int d = 0;
   int64_t N[kMaxDim], R[kMaxDim];
   int64_t size = 0, gsize = 0;
-  int64_t nP = 0, nT = 0, nU = 0, nC = 0, nY = 0, nNum = 0, nS = 0, nM = 0;
-  size_t oP, oT, oU0, oU1, oC0, oC1, oY, oNum, oDen, oS, oM, oG0, oG1, oG2, oG3, oClip, oFlag,
-      oRed, oPart, total;
+  int64_t nP = 0, nT = 0, nU = 0, nC = 0, nY = 0, nNum = 0, nS = 0, nM = 0, nGp = 0, nGr = 0;
+  bool fast = false;  // every multirank <= 32: fused small-step kernels
+  size_t oP, oT, oU0, oU1, oC0, oC1, oY, oNum, oDen, oS, oM, oG0, oG1, oG2, oG3, oGp, oGr, oClip,
+      oFlag, oRed, oPart, total;
 };
 
 static void grow(int64_t &v, int64_t x) {
@@ -125,6 +128,12 @@ static TuckerPlan plan_tucker(int d, const int64_t *dims, const int64_t *rk) {
     grow(p.nM, p.R[n] * p.R[n]);
     p.nS += p.R[n] * p.R[n];
   }
+  p.fast = true;
+  for (int n = 0; n < d; ++n)
+    if (p.R[n] > 32) p.fast = false;
+  p.nGp = mu_rows_blocks(p.N[d - 1]) * p.gsize;
+  for (int n = 0; n < d; ++n) grow(p.nGr, mu_rows_blocks(p.N[n]) * p.R[n] * p.R[n]);
+  p.nGr *= d;  // the prologue keeps the partials of every factor
   Layout L;
   p.oP = L.take(sizeof(float) * p.nP);
   p.oT = L.take(sizeof(float) * p.nT);
@@ -141,6 +150,8 @@ static TuckerPlan plan_tucker(int d, const int64_t *dims, const int64_t *rk) {
   p.oG1 = L.take(sizeof(float) * p.gsize);
   p.oG2 = L.take(sizeof(float) * p.gsize);
   p.oG3 = L.take(sizeof(float) * p.gsize);
+  p.oGp = L.take(sizeof(float) * p.nGp);
+  p.oGr = L.take(sizeof(float) * p.nGr);
   p.oClip = L.take(sizeof(unsigned long long));
   p.oFlag = L.take(sizeof(unsigned int));
   p.oRed = L.take(2 * sizeof(double));
@@ -170,6 +181,8 @@ struct TuckerBufs {
     const size_t o[4] = {p->oG0, p->oG1, p->oG2, p->oG3};
     return f(o[i]);
   }
+  float *gpart() const { return f(p->oGp); }
+  float *gram() const { return f(p->oGr); }
   unsigned long long *clips() const { return reinterpret_cast<unsigned long long *>(base + p->oClip); }
   unsigned int *flag() const { return reinterpret_cast<unsigned int *>(base + p->oFlag); }
   double *red() const { return reinterpret_cast<double *>(base + p->oRed); }
@@ -287,6 +300,129 @@ struct PassTimer {
     for (auto e : ev) (void)hipEventDestroy(e);
   }
 };
+
+// ------------------------------------------------------------------ fused sweep (R <= 32)
+static CoreArgsHost core_args(const TuckerBufs &b, float *G, float *const *A, double eps) {
+  const TuckerPlan &p = *b.p;
+  CoreArgsHost h;
+  memset(&h, 0, sizeof h);
+  h.d = p.d;
+  for (int k = 0; k < p.d; ++k) {
+    h.R[k] = p.R[k];
+    h.N[k] = p.N[k];
+    h.A[k] = A[k];
+    h.S[k] = b.S(k);
+  }
+  h.G = G;
+  h.M = b.M();
+  h.t0 = b.G(0);
+  h.t1 = b.G(1);
+  h.numG = b.G(2);
+  h.gpart = b.gpart();
+  h.eps = eps;
+  h.clips = b.clips();
+  h.next = -1;
+  return h;
+}
+
+// Every Gram and the R x R matrix of mode 0: the state a fused sweep starts from.
+static nnc_status fused_prologue(const TuckerBufs &b, float *G, float *const *A, double eps,
+                                 hipStream_t s) {
+  const TuckerPlan &p = *b.p;
+  int64_t stride = 0;
+  for (int k = 0; k < p.d; ++k) stride = std::max(stride, mu_rows_blocks(p.N[k]) * p.R[k] * p.R[k]);
+  // one core step per factor: the partials of factors with different sizes differ in count
+  for (int k = 0; k < p.d; ++k) {
+    NNC_TRY(launch_gram_parts(A[k], p.N[k], p.R[k], b.gram(), s));
+    CoreArgsHost h = core_args(b, G, A, eps);
+    h.gram_from = k;
+    h.gram_to = k + 1;
+    h.gram = b.gram();
+    h.gram_parts = (int)mu_rows_blocks(p.N[k]);
+    h.gram_stride = stride;
+    h.next = (k == p.d - 1) ? 0 : -1;
+    NNC_TRY(launch_core_step(h, s));
+  }
+  return NNC_OK;
+}
+
+static nnc_status ttm_f32(const float *in, int d, const int64_t *cur, int k, const float *A,
+                          int64_t R, float *out, hipStream_t s) {
+  return launch_ttm_small(in, prod(cur, 0, k), cur[k], prod(cur, k + 1, d), A, R, 1, R, out, s);
+}
+
+// Contract modes `modes` of `src` (dims cur, updated) with ttm_small; result pointer out.
+static nnc_status chain_small(const float *src, int d, int64_t *cur, const int *modes, int nm,
+                              float *const *A, const int64_t *R, float *c0, float *c1, float *dst,
+                              const float **result, hipStream_t s) {
+  const float *in = src;
+  for (int i = 0; i < nm; ++i) {
+    const int k = modes[i];
+    float *out = (i == nm - 1) ? dst : ((i % 2) ? c1 : c0);
+    NNC_TRY(ttm_f32(in, d, cur, k, A[k], R[k], out, s));
+    cur[k] = R[k];
+    in = out;
+  }
+  *result = in;
+  return NNC_OK;
+}
+
+static nnc_status fused_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, float *G,
+                              float *const *A, double eps, hipStream_t s, PassTimer *tm) {
+  const TuckerPlan &p = *b.p;
+  const int d = p.d;
+  if (tm) NNC_TRY(tm->start(s));
+  NNC_TRY(launch_ttm(X, dt, p.size / p.N[d - 1], p.N[d - 1], 1, A[d - 1], p.R[d - 1], 1, p.R[d - 1],
+                     b.P(), s, true));
+  if (tm) NNC_TRY(tm->stop(s));
+  const float *U = b.P();
+  for (int n = 0; n < d - 1; ++n) {
+    int64_t cur[kMaxDim];
+    for (int k = 0; k < d; ++k) cur[k] = (k < n || k == d - 1) ? p.R[k] : p.N[k];
+    int modes[kMaxDim], nm = 0;
+    for (int k = n + 1; k < d - 1; ++k) modes[nm++] = k;
+    int64_t ycur[kMaxDim];
+    memcpy(ycur, cur, sizeof ycur);
+    const float *Y = nullptr;
+    NNC_TRY(chain_small(U, d, ycur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
+    NNC_TRY(launch_mu_rows(Y, G, A[n], b.M(), prod(p.R, 0, n), p.N[n], prod(p.R, n + 1, d), p.R[n],
+                           eps, b.clips(), b.gram(), nullptr, nullptr, s));
+    CoreArgsHost h = core_args(b, G, A, eps);
+    h.gram_from = n;
+    h.gram_to = n + 1;
+    h.gram = b.gram();
+    h.gram_parts = (int)mu_rows_blocks(p.N[n]);
+    h.next = n + 1;
+    NNC_TRY(launch_core_step(h, s));
+    if (n < d - 2) {
+      float *Un = b.U(n % 2);
+      NNC_TRY(ttm_f32(U, d, cur, n, A[n], p.R[n], Un, s));
+      U = Un;
+    }
+  }
+  if (tm) NNC_TRY(tm->start(s));
+  NNC_TRY(launch_ttm(X, dt, 1, p.N[0], p.size / p.N[0], A[0], p.R[0], 1, p.R[0], b.T(), s, true));
+  if (tm) NNC_TRY(tm->stop(s));
+  int64_t cur[kMaxDim];
+  for (int k = 0; k < d; ++k) cur[k] = (k == 0) ? p.R[0] : p.N[k];
+  int modes[kMaxDim], nm = 0;
+  for (int k = 1; k < d - 1; ++k) modes[nm++] = k;
+  const float *Y = nullptr;
+  NNC_TRY(chain_small(b.T(), d, cur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
+  NNC_TRY(launch_mu_rows(Y, G, A[d - 1], b.M(), prod(p.R, 0, d - 1), p.N[d - 1], 1, p.R[d - 1], eps,
+                         b.clips(), b.gram(), b.gpart(), nullptr, s));
+  NNC_TRY(launch_sum_parts(b.gpart(), (int)mu_rows_blocks(p.N[d - 1]), p.gsize, b.G(2), s));
+  CoreArgsHost h = core_args(b, G, A, eps);
+  h.gram_from = d - 1;
+  h.gram_to = d;
+  h.gram = b.gram();
+  h.gram_parts = (int)mu_rows_blocks(p.N[d - 1]);
+  h.do_core = 1;
+  h.nparts = (int)mu_rows_blocks(p.N[d - 1]);
+  h.next = 0;
+  NNC_TRY(launch_core_step(h, s));
+  return NNC_OK;
+}
 
 // ------------------------------------------------------------------ one sweep
 static nnc_status tucker_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, float *G,
@@ -457,7 +593,10 @@ nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *d
   TuckerBufs b{(char *)o.workspace, &p};
   NNC_HIP(hipMemsetAsync(b.clips(), 0, sizeof(unsigned long long), s));
   NNC_HIP(hipMemsetAsync(b.flag(), 0, sizeof(unsigned int), s));
-  for (int k = 0; k < ndim; ++k) NNC_TRY(launch_gram(factors[k], p.N[k], p.R[k], b.S(k), s));
+  if (p.fast)
+    NNC_TRY(fused_prologue(b, core, factors, eps, s));
+  else
+    for (int k = 0; k < ndim; ++k) NNC_TRY(launch_gram(factors[k], p.N[k], p.R[k], b.S(k), s));
 
   PassTimer timer;
   PassTimer *tm = g_timing ? &timer : nullptr;
@@ -475,7 +614,8 @@ nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *d
     const bool every = o.objective_every > 0;
     if (!graphs) {
       for (int t = ta; t < tb; ++t) {
-        NNC_TRY(tucker_sweep(b, Xs, dts, core, factors, eps, s, tm));
+        NNC_TRY(p.fast ? fused_sweep(b, Xs, dts, core, factors, eps, s, tm)
+                       : tucker_sweep(b, Xs, dts, core, factors, eps, s, tm));
         if (every && (t + 1) % o.objective_every == 0) {
           NNC_TRY(tucker_resid(b, xres, dres, core, factors, s));
           double red[2];
@@ -498,7 +638,8 @@ nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *d
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
     NNC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    nnc_status st = tucker_sweep(b, Xs, dts, core, factors, eps, cs, nullptr);
+    nnc_status st = p.fast ? fused_sweep(b, Xs, dts, core, factors, eps, cs, nullptr)
+                           : tucker_sweep(b, Xs, dts, core, factors, eps, cs, nullptr);
     hipError_t ec = hipStreamEndCapture(cs, &g);
     if (st != NNC_OK) {
       if (g) (void)hipGraphDestroy(g);
@@ -701,26 +842,6 @@ static nnc_status check_cp(const float *core, int ndim, const int64_t *core_dims
   return NNC_OK;
 }
 
-static size_t cp_ws(int nbatch, int ndim) {
-  Layout L;
-  L.take(sizeof(int) * nbatch);
-  L.take(sizeof(float *) * (size_t)nbatch * ndim);
-  L.take(sizeof(double) * nbatch);
-  L.take(sizeof(unsigned long long));
-  return L.off;
-}
-
-size_t nncp_workspace_bytes(int ndim, const int64_t *core_dims, int rank) {
-  if (check_cp((const float *)1, ndim, core_dims, rank, 0) != NNC_OK) return 0;
-  return cp_ws(1, ndim);
-}
-
-size_t nncp_batched_workspace_bytes(int ndim, const int64_t *core_dims, int nbatch, const int *ranks) {
-  if (nbatch < 1 || !ranks) return 0;
-  if (check_dims(ndim, core_dims, "core_dims") != NNC_OK) return 0;
-  return cp_ws(nbatch, ndim);
-}
-
 static CpProblem cp_problem(int ndim, const int64_t *core_dims) {
   CpProblem pb;
   pb.d = ndim;
@@ -732,33 +853,136 @@ static CpProblem cp_problem(int ndim, const int64_t *core_dims) {
   return pb;
 }
 
+// Workspace of nnCP fits: rank table, factor-pointer table, residuals, clip counter, the
+// contraction scratch (used when it does not fit in LDS) and, for the batched entry point,
+// the tuner's scratch factors and their pointer table.
+struct CpWs {
+  size_t oRank, oPtr, oRes, oClip, oZ, oTune, oTunePtr, total;
+};
+
+static CpWs cp_ws(const CpProblem &pb, int nbatch, const int *ranks, bool tune) {
+  int maxr = 1;
+  int64_t facs = 0;
+  for (int j = 0; j < nbatch; ++j) {
+    maxr = std::max(maxr, ranks[j]);
+    for (int k = 0; k < pb.d; ++k) facs += pb.dims[k] * ranks[j];
+  }
+  Layout L;
+  CpWs w;
+  w.oRank = L.take(sizeof(int) * nbatch);
+  w.oPtr = L.take(sizeof(float *) * (size_t)nbatch * pb.d);
+  w.oRes = L.take(sizeof(double) * nbatch);
+  w.oClip = L.take(sizeof(unsigned long long));
+  w.oZ = L.take(sizeof(float) * (size_t)(nbatch * nncp_zscratch_floats(pb, maxr)));
+  w.oTune = L.take(tune ? sizeof(float) * (size_t)facs : 0);
+  w.oTunePtr = L.take(tune ? sizeof(float *) * (size_t)nbatch * pb.d : 0);
+  w.total = L.off;
+  return w;
+}
+
+size_t nncp_workspace_bytes(int ndim, const int64_t *core_dims, int rank) {
+  if (check_cp((const float *)1, ndim, core_dims, rank, 0) != NNC_OK) return 0;
+  const CpProblem pb = cp_problem(ndim, core_dims);
+  return cp_ws(pb, 1, &rank, false).total;
+}
+
+size_t nncp_batched_workspace_bytes(int ndim, const int64_t *core_dims, int nbatch, const int *ranks) {
+  if (nbatch < 1 || !ranks) return 0;
+  if (check_dims(ndim, core_dims, "core_dims") != NNC_OK) return 0;
+  for (int j = 0; j < nbatch; ++j)
+    if (ranks[j] < 1) return 0;
+  return cp_ws(cp_problem(ndim, core_dims), nbatch, ranks, true).total;
+}
+
 nnc_status nncp_fit(const float *core, int ndim, const int64_t *core_dims, int rank, int iters,
                     float *const *cp_factors, double eps, double *rel_residual, void *workspace,
                     size_t workspace_bytes, void *stream) {
   NNC_TRY(check_cp(core, ndim, core_dims, rank, iters));
   NNC_TRY(check_ptrs((const void *const *)cp_factors, ndim, "cp_factors"));
   if (eps < 0) return fail(NNC_EINVAL, "eps < 0");
-  if (rank > 64) return fail(NNC_EUNSUPPORTED, "rank %d above 64", rank);
-  const size_t need = cp_ws(1, ndim);
-  if (!workspace || workspace_bytes < need)
-    return fail(NNC_EWORKSPACE, "workspace has %zu bytes, need %zu", workspace ? workspace_bytes : 0, need);
+  if (rank > 32) return fail(NNC_EUNSUPPORTED, "rank %d above 32", rank);
   const CpProblem pb = cp_problem(ndim, core_dims);
+  const CpWs w = cp_ws(pb, 1, &rank, false);
+  if (!workspace || workspace_bytes < w.total)
+    return fail(NNC_EWORKSPACE, "workspace has %zu bytes, need %zu", workspace ? workspace_bytes : 0,
+                w.total);
   hipStream_t s = (hipStream_t)stream;
-  Layout L;
-  L.take(sizeof(int));
-  L.take(sizeof(float *) * ndim);
-  const size_t oRes = L.take(sizeof(double));
-  const size_t oClip = L.take(sizeof(unsigned long long));
   char *base = (char *)workspace;
-  NNC_HIP(hipMemsetAsync(base + oClip, 0, sizeof(unsigned long long), s));
+  NNC_TRY(launch_fill_u64((unsigned long long *)(base + w.oClip), 1, 0ull, s));
   NNC_TRY(launch_nncp(core, pb, 1, nullptr, rank, nullptr, cp_factors, iters, eps > 0 ? eps : 1e-12,
-                      rel_residual ? (double *)(base + oRes) : nullptr,
-                      (unsigned long long *)(base + oClip), 0, s));
+                      rel_residual ? (double *)(base + w.oRes) : nullptr,
+                      (unsigned long long *)(base + w.oClip), (float *)(base + w.oZ), 0, s));
   if (rel_residual) {
-    NNC_HIP(hipMemcpyAsync(rel_residual, base + oRes, sizeof(double), hipMemcpyDeviceToHost, s));
+    NNC_HIP(hipMemcpyAsync(rel_residual, base + w.oRes, sizeof(double), hipMemcpyDeviceToHost, s));
     NNC_HIP(hipStreamSynchronize(s));
     if (!std::isfinite(*rel_residual)) return fail(NNC_ENUMERIC, "non-finite nnCP residual");
   }
+  return NNC_OK;
+}
+
+// ---- tuner for the batched launch: threads per fit, timed on scratch factors, cached per
+// (core shape, rank multiset) for the life of the process.
+static std::mutex g_tune_mu;
+static std::map<std::string, int> g_tune_cache;
+
+static std::string tune_key(const CpProblem &pb, int nbatch, const int *ranks) {
+  std::string k = std::to_string(pb.d);
+  for (int i = 0; i < pb.d; ++i) k += "x" + std::to_string(pb.dims[i]);
+  std::vector<int> rs(ranks, ranks + nbatch);
+  std::sort(rs.begin(), rs.end());
+  for (int r : rs) k += "," + std::to_string(r);
+  return k;
+}
+
+static nnc_status tune_threads(const float *core, const CpProblem &pb, int nbatch, const int *ranks,
+                               int maxr, const CpWs &w, char *base, int iters, hipStream_t s,
+                               int *best) {
+  const std::string key = tune_key(pb, nbatch, ranks);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      *best = it->second;
+      return NNC_OK;
+    }
+  }
+  // scratch factors (constant 0.5) and their pointer table
+  std::vector<float *> ptrs((size_t)nbatch * pb.d);
+  float *fbase = (float *)(base + w.oTune);
+  int64_t off = 0;
+  for (int j = 0; j < nbatch; ++j)
+    for (int k = 0; k < pb.d; ++k) {
+      ptrs[(size_t)j * pb.d + k] = fbase + off;
+      off += pb.dims[k] * ranks[j];
+    }
+  NNC_HIP(hipMemcpy(base + w.oTunePtr, ptrs.data(), sizeof(float *) * ptrs.size(), hipMemcpyHostToDevice));
+  hipEvent_t e0, e1;
+  NNC_HIP(hipEventCreate(&e0));
+  NNC_HIP(hipEventCreate(&e1));
+  const int titers = std::max(1, std::min(iters, 10));
+  float best_ms = 1e30f;
+  int best_t = nncp_default_threads(pb, maxr);
+  for (int t : {256, 512, 1024}) {
+    if (nncp_lds_bytes(pb, maxr, t) > 150 * 1024) continue;
+    NNC_TRY(launch_fill_f32(fbase, off, 0.5f, s));
+    NNC_HIP(hipEventRecord(e0, s));
+    NNC_TRY(launch_nncp(core, pb, nbatch, (const int *)(base + w.oRank), maxr,
+                        (float *const *)(base + w.oTunePtr), nullptr, titers, 1e-12, nullptr,
+                        (unsigned long long *)(base + w.oClip), (float *)(base + w.oZ), t, s));
+    NNC_HIP(hipEventRecord(e1, s));
+    NNC_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    NNC_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best_t = t;
+    }
+  }
+  NNC_HIP(hipEventDestroy(e0));
+  NNC_HIP(hipEventDestroy(e1));
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[key] = best_t;
+  *best = best_t;
   return NNC_OK;
 }
 
@@ -779,29 +1003,47 @@ nnc_status nncp_fit_batched(const float *core, int ndim, const int64_t *core_dim
   }
   if (threads_per_fit != 0 && (threads_per_fit < 64 || threads_per_fit > 1024 || threads_per_fit % 64))
     return fail(NNC_EINVAL, "threads_per_fit must be 0 or a multiple of 64 in [64, 1024]");
-  const size_t need = cp_ws(nbatch, ndim);
-  if (!workspace || workspace_bytes < need)
-    return fail(NNC_EWORKSPACE, "workspace has %zu bytes, need %zu", workspace ? workspace_bytes : 0, need);
   const CpProblem pb = cp_problem(ndim, core_dims);
+  const CpWs w = cp_ws(pb, nbatch, ranks, true);
+  if (!workspace || workspace_bytes < w.total)
+    return fail(NNC_EWORKSPACE, "workspace has %zu bytes, need %zu", workspace ? workspace_bytes : 0,
+                w.total);
   hipStream_t s = (hipStream_t)stream;
-  Layout L;
-  const size_t oRank = L.take(sizeof(int) * nbatch);
-  const size_t oPtr = L.take(sizeof(float *) * (size_t)nbatch * ndim);
-  const size_t oRes = L.take(sizeof(double) * nbatch);
-  const size_t oClip = L.take(sizeof(unsigned long long));
   char *base = (char *)workspace;
-  // The tables are copied before the launch; the call synchronises below, so the host
-  // arrays only need to live for the duration of the call.
-  NNC_HIP(hipMemcpyAsync(base + oRank, ranks, sizeof(int) * nbatch, hipMemcpyHostToDevice, s));
-  NNC_HIP(hipMemcpyAsync(base + oPtr, cp_factors, sizeof(float *) * (size_t)nbatch * ndim,
-                         hipMemcpyHostToDevice, s));
-  NNC_HIP(hipMemsetAsync(base + oClip, 0, sizeof(unsigned long long), s));
-  NNC_TRY(launch_nncp(core, pb, nbatch, (const int *)(base + oRank), maxr,
-                      (float *const *)(base + oPtr), nullptr, iters, eps > 0 ? eps : 1e-12,
-                      (double *)(base + oRes), (unsigned long long *)(base + oClip),
-                      threads_per_fit, s));
-  NNC_HIP(hipMemcpyAsync(rel_residuals, base + oRes, sizeof(double) * nbatch, hipMemcpyDeviceToHost, s));
+  // The tables are copied synchronously: the host arrays need only live for the call.
   NNC_HIP(hipStreamSynchronize(s));
+  NNC_HIP(hipMemcpy(base + w.oRank, ranks, sizeof(int) * nbatch, hipMemcpyHostToDevice));
+  NNC_HIP(hipMemcpy(base + w.oPtr, cp_factors, sizeof(float *) * (size_t)nbatch * ndim,
+                    hipMemcpyHostToDevice));
+  int threads = threads_per_fit;
+  if (threads == 0) NNC_TRY(tune_threads(core, pb, nbatch, ranks, maxr, w, base, iters, s, &threads));
+  // One graph: clear the clip counter, then the single persistent launch of every fit.
+  hipStream_t cs = s;
+  if (!s) {
+    cs = capture_stream();
+    if (!cs) return fail(NNC_EHIP, "could not create a capture stream");
+    NNC_HIP(hipStreamSynchronize(nullptr));
+  }
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  NNC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  nnc_status st = launch_fill_u64((unsigned long long *)(base + w.oClip), 1, 0ull, cs);
+  if (st == NNC_OK)
+    st = launch_nncp(core, pb, nbatch, (const int *)(base + w.oRank), maxr, (float *const *)(base + w.oPtr),
+                     nullptr, iters, eps > 0 ? eps : 1e-12, (double *)(base + w.oRes),
+                     (unsigned long long *)(base + w.oClip), (float *)(base + w.oZ), threads, cs);
+  hipError_t ec = hipStreamEndCapture(cs, &g);
+  if (st != NNC_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (ec != hipSuccess) return fail(NNC_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
+  NNC_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+  NNC_HIP(hipGraphLaunch(ge, cs));
+  NNC_HIP(hipMemcpyAsync(rel_residuals, base + w.oRes, sizeof(double) * nbatch, hipMemcpyDeviceToHost, cs));
+  NNC_HIP(hipStreamSynchronize(cs));
+  NNC_HIP(hipGraphExecDestroy(ge));
+  NNC_HIP(hipGraphDestroy(g));
   for (int j = 0; j < nbatch; ++j)
     if (!std::isfinite(rel_residuals[j])) return fail(NNC_ENUMERIC, "non-finite residual of fit %d", j);
   return NNC_OK;

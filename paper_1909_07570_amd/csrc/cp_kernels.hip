@@ -1,14 +1,22 @@
 // Nonnegative CP of a small tensor (the Tucker core) by multiplicative updates, entirely
-// inside one workgroup: the CP factors, their Grams and the update temporaries live in LDS;
-// the tensor is read through the cache.  One workgroup per fit, so a launch can run many
+// inside one workgroup: the CP factors, their Grams and the update temporaries live in LDS,
+// and so does the tensor when it fits.  One workgroup per fit, so a launch can run many
 // independent fits (random restarts, uneven ranks) at once, and every sweep of every fit
 // happens inside that single launch.
 //
 // Sweep (factors 1..d in order):  M_n = MTTKRP(T, {B_k}_{k!=n}),  H_n = Hadamard_{k!=n} B_k^T B_k,
 //   B_n <- B_n * M_n / max(B_n H_n, eps),  then B_n^T B_n is refreshed.
-// MTTKRP by its definition: M_n[i, rho] = sum over entries with i_n = i of
-// T[idx] * prod_{k!=n} B_k[i_k, rho].  Each (i, rho) pair is split over several threads that
-// sum fixed index ranges; the partial sums are then added in a fixed order.
+// MTTKRP M_n[i, rho] = sum over entries with i_n = i of T[idx] prod_{k!=n} B_k[i_k, rho] is
+// evaluated in two stages: first the last mode L != n is contracted for every rho at once,
+//   Z[o][rho] = sum_l T[.., l (mode L), ..] B_L[l, rho]        (o = the other indices of T),
+// then Z is summed over the remaining modes != n with their factor entries.  Partial sums
+// are added in a fixed order, so results are reproducible.
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+
 #include "nnc_internal.h"
 
 namespace nnc {
@@ -19,106 +27,209 @@ struct CpPtrs {
 
 struct CpArgs {
   int d;
-  int64_t dims[kMaxDim];
-  int64_t size;
+  int dims[kMaxDim];
+  int size;
   int maxdim;
+  int t_lds;  // 1: T staged in LDS
+  int z_lds;  // 1: Z in LDS, else in global scratch
+  int zmax;   // rows of Z (max over modes of size / dims[L])
 };
 
-static __device__ inline float mu_cp(float x, float num, float den, double eps,
-                                     unsigned long long *clips) {
+static __device__ inline float mu_cp(float x, float num, float den, double eps, unsigned int *nclip) {
   double dd = (double)den;
   if (dd < eps) {
     dd = eps;
-    atomicAdd(clips, 1ull);
+    atomicAdd(nclip, 1u);
   }
   return (float)(((double)x * (double)num) / dd);
 }
 
-// LDS layout (floats): B_k (dims[k] x r) for every k | Gram_k (r x r) for every k | H (r x r)
-//                      | M (maxdim x r) | part (blockDim)
-__host__ __device__ inline int64_t cp_lds_floats(const CpArgs &a, int r, int threads) {
-  int64_t s = 0;
-  for (int k = 0; k < a.d; ++k) s += a.dims[k] * r;
-  s += (int64_t)a.d * r * r + (int64_t)r * r + (int64_t)a.maxdim * r + threads;
+// LDS floats of one fit of rank r with `threads` threads:
+//   [T if t_lds] B_k (dims[k] x r) | Gram_k (r x r) | H (r x r) | M (maxdim x r)
+//   | part (max(threads, maxdim * r)) | red (2 * threads doubles) | [Z (zmax x r) if z_lds]
+static int64_t cp_lds_floats(const CpArgs &a, int r, int threads, bool t_lds, bool z_lds) {
+  int64_t s = t_lds ? a.size : 0;
+  for (int k = 0; k < a.d; ++k) s += (int64_t)a.dims[k] * r;
+  s += (int64_t)(a.d + 1) * r * r + (int64_t)a.maxdim * r;
+  s += std::max<int64_t>(threads, (int64_t)a.maxdim * r);
+  s += (s & 1);               // keep the doubles 8-byte aligned
+  s += 4 * (int64_t)threads;  // 2 * threads doubles
+  if (z_lds) s += (int64_t)a.zmax * r;
   return s;
 }
 
-// A single fit passes its rank and factor pointers by value (ranks == nullptr); a batch
-// passes device tables.
-__global__ void nncp_k(const float *__restrict__ T, CpArgs a, int rank0, CpPtrs ptr0,
-                       const int *__restrict__ ranks, float *const *__restrict__ fptrs, int iters,
-                       double eps, double *__restrict__ resid, unsigned long long *clips) {
-  extern __shared__ float sm[];
+// Every per-mode array below is indexed only by loop counters of fully unrolled loops over
+// kMaxDim, so it lives in registers (no scratch memory); factor blocks are addressed by
+// offsets kept in LDS.
+template <int RM>
+__global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpArgs a, int rank0,
+                                               CpPtrs ptr0, const int *__restrict__ ranks,
+                                               float *const *__restrict__ fptrs, int iters,
+                                               double eps, double *__restrict__ resid,
+                                               unsigned long long *clips, float *__restrict__ zg) {
+  extern __shared__ __attribute__((aligned(16))) float sm[];
+  __shared__ unsigned int nclip;
+  __shared__ int boff[kMaxDim + 1];
   const int b = blockIdx.x;
   const int r = ranks ? ranks[b] : rank0;
-  float *const *Bg = ranks ? fptrs + (int64_t)b * a.d : ptr0.p;
   const int tid = threadIdx.x, nt = blockDim.x;
-  float *Bs[kMaxDim];
-  float *Wg[kMaxDim];
+  const int d = a.d;
   float *p = sm;
-  for (int k = 0; k < a.d; ++k) {
-    Bs[k] = p;
-    p += a.dims[k] * r;
+  const float *T = Tg;
+  if (a.t_lds) {
+    for (int e = tid; e < a.size; e += nt) p[e] = Tg[e];
+    T = p;
+    p += a.size;
   }
-  for (int k = 0; k < a.d; ++k) {
-    Wg[k] = p;
-    p += r * r;
-  }
+  float *sB = p;  // B_k at sB + boff[k]
+  int nb = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxDim; ++k)
+    if (k < d) nb += a.dims[k] * r;
+  p += nb;
+  float *sW = p;  // Gram_k at sW + k*r*r
+  p += d * r * r;
   float *H = p;
   p += r * r;
   float *Mm = p;
   p += a.maxdim * r;
   float *part = p;
-
-  for (int k = 0; k < a.d; ++k)
-    for (int64_t e = tid; e < a.dims[k] * r; e += nt) Bs[k][e] = Bg[k][e];
+  p += (nt > a.maxdim * r ? nt : a.maxdim * r);
+  p += ((p - sm) & 1);
+  double *red = reinterpret_cast<double *>(p);
+  p += 4 * nt;
+  float *Z = a.z_lds ? p : zg + (int64_t)b * a.zmax * RM;
+  if (tid == 0) {
+    nclip = 0;
+    int o = 0;
+    for (int k = 0; k < d; ++k) {
+      boff[k] = o;
+      o += a.dims[k] * r;
+    }
+    boff[d] = o;
+  }
   __syncthreads();
-  for (int k = 0; k < a.d; ++k)
+#pragma unroll
+  for (int k = 0; k < kMaxDim; ++k) {
+    if (k >= d) break;
+    const float *src = ranks ? fptrs[(int64_t)b * d + k] : ptr0.p[k];
+    for (int e = tid; e < a.dims[k] * r; e += nt) sB[boff[k] + e] = src[e];
+  }
+  __syncthreads();
+  for (int k = 0; k < d; ++k) {
+    const float *Bk = sB + boff[k];
     for (int e = tid; e < r * r; e += nt) {
       const int x = e / r, y = e - (e / r) * r;
       float acc = 0.f;
-      for (int64_t i = 0; i < a.dims[k]; ++i) acc = fmaf(Bs[k][i * r + x], Bs[k][i * r + y], acc);
-      Wg[k][e] = acc;
+      for (int i = 0; i < a.dims[k]; ++i) acc = fmaf(Bk[i * r + x], Bk[i * r + y], acc);
+      sW[k * r * r + e] = acc;
     }
+  }
   __syncthreads();
 
   for (int it = 0; it < iters; ++it) {
-    for (int n = 0; n < a.d; ++n) {
-      const int64_t In = a.dims[n];
-      const int64_t npairs = In * r;
-      int64_t post = 1;
-      for (int k = n + 1; k < a.d; ++k) post *= a.dims[k];
-      const int64_t other = a.size / In;
-      const int S = npairs >= nt ? 1 : (int)(nt / npairs);
-      // ---- MTTKRP, split into S fixed index ranges per (i, rho)
-      for (int64_t w = tid; w < npairs * S; w += nt) {
-        const int64_t pr = w % npairs;
-        const int s = (int)(w / npairs);
-        const int64_t i = pr / r;
-        const int rho = (int)(pr - i * r);
-        const int64_t o0 = other * s / S, o1 = other * (s + 1) / S;
-        // decode o0 into the other indices (odometer, modes != n, last fastest)
-        int64_t idx[kMaxDim];
-        int64_t rem = o0;
-        for (int k = a.d - 1; k >= 0; --k) {
-          if (k == n) {
-            idx[k] = i;
-            continue;
+    for (int n = 0; n < d; ++n) {
+      const int L = (n == d - 1) ? d - 2 : d - 1;
+      const int mL = a.dims[L];
+      int postL = 1;
+      for (int k = L + 1; k < d; ++k) postL *= a.dims[k];
+      const int zrows = a.size / mL;
+      const float *BL = sB + boff[L];
+      // ---- stage 1: Z[o][rho] = sum_l T[(pre*mL + l)*postL + q] B_L[l][rho], o = pre*postL + q
+      for (int o = tid; o < zrows; o += nt) {
+        const int pre = o / postL, q = o - (o / postL) * postL;
+        const float *t = T + pre * mL * postL + q;
+        float acc[RM];
+#pragma unroll
+        for (int rho = 0; rho < RM; ++rho) acc[rho] = 0.f;
+        for (int l = 0; l < mL; ++l) {
+          const float x = t[l * postL];
+          const float *bl = BL + l * r;
+#pragma unroll
+          for (int rho = 0; rho < RM; ++rho)
+            if (rho < r) acc[rho] = fmaf(x, bl[rho], acc[rho]);
+        }
+        float *zo = Z + o * r;
+#pragma unroll
+        for (int rho = 0; rho < RM; ++rho)
+          if (rho < r) zo[rho] = acc[rho];
+      }
+      if (!a.z_lds) __threadfence_block();
+      __syncthreads();
+      // ---- stage 2: M[i][rho] = sum over Z rows with i_n = i of Z[o][rho] prod_{k!=n,L} B_k[i_k][rho]
+      // Z's modes are T's modes without L (row-major).  zdims/zstride/zb/idx are indexed by
+      // unrolled loop counters only.
+      int zdims[kMaxDim], zstride[kMaxDim], zb[kMaxDim], idx[kMaxDim];
+      int nz = 0, npos = 0;
+#pragma unroll
+      for (int j = 0; j < kMaxDim; ++j) {
+        zdims[j] = 1;
+        zstride[j] = 0;
+        zb[j] = 0;
+        idx[j] = 0;
+      }
+#pragma unroll
+      for (int k = 0; k < kMaxDim; ++k) {
+        if (k < d && k != L) {
+          if (k == n) npos = nz;
+#pragma unroll
+          for (int j = 0; j < kMaxDim; ++j)
+            if (j == nz) {
+              zdims[j] = a.dims[k];
+              zb[j] = boff[k];
+            }
+          ++nz;
+        }
+      }
+      {
+        int st = 1;
+#pragma unroll
+        for (int j = kMaxDim - 1; j >= 0; --j)
+          if (j < nz) {
+            zstride[j] = st;
+            st *= zdims[j];
           }
-          idx[k] = rem % a.dims[k];
-          rem /= a.dims[k];
+      }
+      int nstride = 0;
+#pragma unroll
+      for (int j = 0; j < kMaxDim; ++j)
+        if (j == npos) nstride = zstride[j];
+      const int In = a.dims[n];
+      const int npairs = In * r;
+      const int other = zrows / In;
+      const int S = npairs >= nt ? 1 : nt / npairs;
+      for (int w = tid; w < npairs * S; w += nt) {
+        const int pr = w % npairs, s = w / npairs;
+        const int i = pr / r, rho = pr - (pr / r) * r;
+        const int o0 = (int)((int64_t)other * s / S), o1 = (int)((int64_t)other * (s + 1) / S);
+        int rem = o0, zoff = i * nstride;
+#pragma unroll
+        for (int j = kMaxDim - 1; j >= 0; --j) {
+          if (j < nz && j != npos) {
+            idx[j] = rem % zdims[j];
+            rem /= zdims[j];
+            zoff += idx[j] * zstride[j];
+          }
         }
         float acc = 0.f;
-        for (int64_t o = o0; o < o1; ++o) {
-          const int64_t pre = o / post, q = o - (o / post) * post;
-          float prod = T[(pre * In + i) * post + q];
-          for (int k = 0; k < a.d; ++k)
-            if (k != n) prod *= Bs[k][idx[k] * r + rho];
+        for (int o = o0; o < o1; ++o) {
+          float prod = Z[zoff * r + rho];
+#pragma unroll
+          for (int j = 0; j < kMaxDim; ++j)
+            if (j < nz && j != npos) prod *= sB[zb[j] + idx[j] * r + rho];
           acc += prod;
-          for (int k = a.d - 1; k >= 0; --k) {  // advance the odometer
-            if (k == n) continue;
-            if (++idx[k] < a.dims[k]) break;
-            idx[k] = 0;
+          bool carry = true;  // odometer over the modes != n of Z, last fastest
+#pragma unroll
+          for (int j = kMaxDim - 1; j >= 0; --j) {
+            if (carry && j < nz && j != npos) {
+              zoff += zstride[j];
+              if (++idx[j] == zdims[j]) {
+                zoff -= zdims[j] * zstride[j];
+                idx[j] = 0;
+              } else {
+                carry = false;
+              }
+            }
           }
         }
         if (S == 1)
@@ -127,68 +238,66 @@ __global__ void nncp_k(const float *__restrict__ T, CpArgs a, int rank0, CpPtrs 
           part[w] = acc;
       }
       __syncthreads();
-      if (S > 1) {
-        for (int64_t pr = tid; pr < npairs; pr += nt) {
+      if (S > 1)
+        for (int pr = tid; pr < npairs; pr += nt) {
           float acc = 0.f;
           for (int s = 0; s < S; ++s) acc += part[s * npairs + pr];
           Mm[pr] = acc;
         }
-      }
-      // ---- H = Hadamard product of the other Grams
       for (int e = tid; e < r * r; e += nt) {
         float h = 1.f;
-        for (int k = 0; k < a.d; ++k)
-          if (k != n) h *= Wg[k][e];
+        for (int k = 0; k < d; ++k)
+          if (k != n) h *= sW[k * r * r + e];
         H[e] = h;
       }
       __syncthreads();
-      // ---- B_n <- B_n * M / max(B_n H, eps)   (read phase, barrier, write phase)
-      float nv[4];
-      int cnt = 0;
-      for (int64_t e = tid; e < npairs; e += nt) {
-        const int64_t i = e / r;
-        const int c = (int)(e - i * r);
+      // ---- B_n <- B_n * M / max(B_n H, eps): new values go to `part` first
+      float *Bn = sB + boff[n];
+      for (int e = tid; e < npairs; e += nt) {
+        const int i = e / r, c = e - (e / r) * r;
         float den = 0.f;
-        for (int s = 0; s < r; ++s) den = fmaf(Bs[n][i * r + s], H[s * r + c], den);
-        const float v = mu_cp(Bs[n][e], Mm[e], den, eps, clips);
-        if (cnt < 4) nv[cnt] = v;
-        else part[e] = v;
-        ++cnt;
+        for (int s2 = 0; s2 < r; ++s2) den = fmaf(Bn[i * r + s2], H[s2 * r + c], den);
+        part[e] = mu_cp(Bn[e], Mm[e], den, eps, &nclip);
       }
       __syncthreads();
-      cnt = 0;
-      for (int64_t e = tid; e < npairs; e += nt) {
-        Bs[n][e] = cnt < 4 ? nv[cnt] : part[e];
-        ++cnt;
-      }
+      for (int e = tid; e < npairs; e += nt) Bn[e] = part[e];
       __syncthreads();
-      // ---- Gram of the new B_n
       for (int e = tid; e < r * r; e += nt) {
         const int x = e / r, y = e - (e / r) * r;
         float acc = 0.f;
-        for (int64_t i = 0; i < In; ++i) acc = fmaf(Bs[n][i * r + x], Bs[n][i * r + y], acc);
-        Wg[n][e] = acc;
+        for (int i = 0; i < In; ++i) acc = fmaf(Bn[i * r + x], Bn[i * r + y], acc);
+        sW[n * r * r + e] = acc;
       }
       __syncthreads();
     }
   }
-  for (int k = 0; k < a.d; ++k)
-    for (int64_t e = tid; e < a.dims[k] * r; e += nt) Bg[k][e] = Bs[k][e];
+#pragma unroll
+  for (int k = 0; k < kMaxDim; ++k) {
+    if (k >= d) break;
+    float *dst = ranks ? fptrs[(int64_t)b * d + k] : ptr0.p[k];
+    for (int e = tid; e < a.dims[k] * r; e += nt) dst[e] = sB[boff[k] + e];
+  }
+  if (tid == 0 && nclip) atomicAdd(clips, (unsigned long long)nclip);
 
-  // relative residual ||T - cp(B)|| / ||T||, double accumulation, fixed tree
-  if (resid) {
+  if (resid) {  // ||T - cp(B)|| / ||T||, double accumulation, fixed tree
     double sr = 0.0, sx = 0.0;
-    for (int64_t e = tid; e < a.size; e += nt) {
-      int64_t rem = e;
-      int64_t idx[kMaxDim];
-      for (int k = a.d - 1; k >= 0; --k) {
-        idx[k] = rem % a.dims[k];
-        rem /= a.dims[k];
+    for (int e = tid; e < a.size; e += nt) {
+      int ix[kMaxDim];
+      int rem = e;
+#pragma unroll
+      for (int k = kMaxDim - 1; k >= 0; --k) {
+        ix[k] = 0;
+        if (k < d) {
+          ix[k] = rem % a.dims[k];
+          rem /= a.dims[k];
+        }
       }
       float xh = 0.f;
       for (int rho = 0; rho < r; ++rho) {
         float pp = 1.f;
-        for (int k = 0; k < a.d; ++k) pp *= Bs[k][idx[k] * r + rho];
+#pragma unroll
+        for (int k = 0; k < kMaxDim; ++k)
+          if (k < d) pp *= sB[boff[k] + ix[k] * r + rho];
         xh += pp;
       }
       const double x = T[e];
@@ -196,74 +305,120 @@ __global__ void nncp_k(const float *__restrict__ T, CpArgs a, int rank0, CpPtrs 
       sr += df * df;
       sx += x * x;
     }
-    __shared__ double red[1024];
     red[tid] = sr;
+    red[nt + tid] = sx;
     __syncthreads();
     for (int w = 512; w > 0; w >>= 1) {
-      if (tid < w && tid + w < nt) red[tid] += red[tid + w];
+      if (tid < w && tid + w < nt) {
+        red[tid] += red[tid + w];
+        red[nt + tid] += red[nt + tid + w];
+      }
       __syncthreads();
     }
-    const double tr = red[0];
-    __syncthreads();
-    red[tid] = sx;
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-      if (tid < w && tid + w < nt) red[tid] += red[tid + w];
-      __syncthreads();
-    }
-    if (tid == 0) resid[b] = red[0] > 0.0 ? sqrt(tr / red[0]) : 0.0;
+    if (tid == 0) resid[b] = red[nt] > 0.0 ? sqrt(red[0] / red[nt]) : 0.0;
   }
-}
-
-int nncp_default_threads(const CpProblem &pb, int max_rank) {
-  int64_t maxpairs = 0;
-  for (int k = 0; k < pb.d; ++k) maxpairs = pb.dims[k] * max_rank > maxpairs ? pb.dims[k] * max_rank : maxpairs;
-  // enough threads to give every (i, rho) pair a few slices of the index range
-  if (pb.size * max_rank >= 1 << 16) return 1024;
-  if (maxpairs * 4 >= 512) return 512;
-  return 256;
 }
 
 static CpArgs make_args(const CpProblem &pb) {
   CpArgs a;
+  memset(&a, 0, sizeof a);
   a.d = pb.d;
-  a.size = pb.size;
+  a.size = (int)pb.size;
   a.maxdim = 0;
   for (int k = 0; k < pb.d; ++k) {
-    a.dims[k] = pb.dims[k];
-    if (pb.dims[k] > a.maxdim) a.maxdim = (int)pb.dims[k];
+    a.dims[k] = (int)pb.dims[k];
+    if (a.dims[k] > a.maxdim) a.maxdim = a.dims[k];
   }
+  const int mlast = a.dims[pb.d - 1], mprev = a.dims[pb.d - 2];
+  a.zmax = a.size / (mlast < mprev ? mlast : mprev);
   return a;
 }
 
-// LDS of one fit: the layout above, with `part` holding max(threads, maxdim * r) floats
-// (MTTKRP partial sums need at most `threads`; the update may park up to maxdim * r values).
-int64_t nncp_lds_bytes(const CpProblem &pb, int max_rank, int threads) {
-  const CpArgs a = make_args(pb);
-  int64_t part = threads;
-  if ((int64_t)a.maxdim * max_rank > part) part = (int64_t)a.maxdim * max_rank;
-  return (cp_lds_floats(a, max_rank, 0) + part) * (int64_t)sizeof(float);
+// Dynamic LDS a single fit may use (one workgroup per CU; gfx950 has 160 KiB per CU).
+constexpr int64_t kCpLdsBudget = 150 * 1024;
+
+struct CpLayout {
+  CpArgs a;
+  int64_t lds_bytes;
+};
+
+// Keep T in LDS when possible (it is read every stage), then Z.
+static CpLayout cp_layout(const CpProblem &pb, int max_rank, int threads) {
+  CpLayout L;
+  L.a = make_args(pb);
+  const bool opts[4][2] = {{true, true}, {true, false}, {false, true}, {false, false}};
+  for (const auto &o : opts) {
+    const int64_t bytes = cp_lds_floats(L.a, max_rank, threads, o[0], o[1]) * 4;
+    if (bytes <= kCpLdsBudget || (!o[0] && !o[1])) {
+      L.a.t_lds = o[0];
+      L.a.z_lds = o[1];
+      L.lds_bytes = bytes;
+      return L;
+    }
+  }
+  return L;
 }
 
-// Dynamic LDS per fit the nnCP kernel may request (the static reduction array adds 8 KiB).
-constexpr int64_t kCpLdsBudget = 56 * 1024;
+int64_t nncp_lds_bytes(const CpProblem &pb, int max_rank, int threads) {
+  return cp_layout(pb, max_rank, threads).lds_bytes;
+}
+
+int64_t nncp_zscratch_floats(const CpProblem &pb, int max_rank) {
+  const CpArgs a = make_args(pb);
+  const int RM = max_rank <= 8 ? 8 : (max_rank <= 16 ? 16 : 32);
+  return (int64_t)a.zmax * RM;
+}
+
+int nncp_default_threads(const CpProblem &pb, int max_rank) {
+  const int64_t work = pb.size * (int64_t)max_rank;
+  if (work >= (1 << 16)) return 1024;
+  if (work >= (1 << 13)) return 512;
+  return 256;
+}
+
+// Raise a kernel's dynamic-LDS limit to `bytes` (once per larger size).
+static nnc_status allow_lds(const void *kern, int64_t bytes) {
+  static std::mutex mu;
+  static std::map<const void *, int64_t> done;
+  if (bytes <= 64 * 1024) return NNC_OK;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = done.find(kern);
+  if (it != done.end() && it->second >= bytes) return NNC_OK;
+  NNC_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  done[kern] = bytes;
+  return NNC_OK;
+}
 
 nnc_status launch_nncp(const float *T, const CpProblem &pb, int nbatch, const int *d_ranks,
                        int max_rank, float *const *d_factor_ptrs, float *const *single_ptrs,
                        int iters, double eps, double *d_resid, unsigned long long *clips,
-                       int threads, hipStream_t s) {
-  const CpArgs a = make_args(pb);
+                       float *zscratch, int threads, hipStream_t s) {
+  if (pb.size > (1 << 26)) return fail(NNC_EUNSUPPORTED, "nnCP tensor too large for one workgroup");
+  if (max_rank > 32) return fail(NNC_EUNSUPPORTED, "nnCP rank above 32");
   if (threads <= 0) threads = nncp_default_threads(pb, max_rank);
   if (threads > 1024 || threads % 64)
     return fail(NNC_EINVAL, "threads_per_fit must be a multiple of 64 <= 1024");
-  const int64_t lds = nncp_lds_bytes(pb, max_rank, threads);
-  if (lds > kCpLdsBudget)
+  const CpLayout L = cp_layout(pb, max_rank, threads);
+  if (L.lds_bytes > kCpLdsBudget)
     return fail(NNC_EUNSUPPORTED, "nnCP working set %lld bytes exceeds the LDS budget",
-                (long long)lds);
+                (long long)L.lds_bytes);
+  if (!L.a.z_lds && !zscratch) return fail(NNC_EWORKSPACE, "nnCP needs Z scratch in the workspace");
   CpPtrs p0;
   for (int k = 0; k < kMaxDim; ++k) p0.p[k] = (single_ptrs && k < pb.d) ? single_ptrs[k] : nullptr;
-  hipLaunchKernelGGL(nncp_k, dim3(nbatch), dim3(threads), (size_t)lds, s, T, a, max_rank, p0, d_ranks,
-                     d_factor_ptrs, iters, eps, d_resid, clips);
+  const size_t lds = (size_t)L.lds_bytes;
+#define NNC_CP_LAUNCH(RM)                                                                      \
+  do {                                                                                         \
+    NNC_TRY(allow_lds(reinterpret_cast<const void *>(nncp_k<RM>), L.lds_bytes));                            \
+    hipLaunchKernelGGL(nncp_k<RM>, dim3(nbatch), dim3(threads), lds, s, T, L.a, max_rank, p0,  \
+                       d_ranks, d_factor_ptrs, iters, eps, d_resid, clips, zscratch);          \
+  } while (0)
+  if (max_rank <= 8)
+    NNC_CP_LAUNCH(8);
+  else if (max_rank <= 16)
+    NNC_CP_LAUNCH(16);
+  else
+    NNC_CP_LAUNCH(32);
+#undef NNC_CP_LAUNCH
   NNC_HIP(hipGetLastError());
   return NNC_OK;
 }

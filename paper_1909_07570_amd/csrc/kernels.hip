@@ -12,7 +12,7 @@
 #include <stdio.h>
 
 #include <mutex>
-#include <set>
+#include <map>
 
 #include "nnc_internal.h"
 
@@ -369,21 +369,23 @@ static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 
 // block still amortises its LDS staging of the factor over many tiles.
 constexpr int kStreamBlocks = 1024;
 
-// Dynamic LDS above 64 KiB must be allowed per kernel once.
-static nnc_status allow_big_lds(const void *kern) {
+// Dynamic LDS above 64 KiB must be allowed per kernel (once per larger size).
+static nnc_status allow_big_lds(const void *kern, size_t bytes) {
   static std::mutex mu;
-  static std::set<const void *> done;
+  static std::map<const void *, size_t> done;
+  if (bytes <= 64 * 1024) return NNC_OK;
   std::lock_guard<std::mutex> lk(mu);
-  if (done.count(kern)) return NNC_OK;
-  NNC_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-  done.insert(kern);
+  auto it = done.find(kern);
+  if (it != done.end() && it->second >= bytes) return NNC_OK;
+  NNC_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  done[kern] = bytes;
   return NNC_OK;
 }
 
 template <typename... KArgs, typename... Args>
 static nnc_status launch_stream(void (*kern)(KArgs...), size_t lds, int64_t tiles, hipStream_t s,
                                 Args... args) {
-  NNC_TRY(allow_big_lds(reinterpret_cast<const void *>(kern)));
+  NNC_TRY(allow_big_lds(reinterpret_cast<const void *>(kern), lds));
   const int waves = kTtmThreads / 64;
   const int grid = grid_for(tiles, waves, kStreamBlocks);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kTtmThreads), lds, s, static_cast<KArgs>(args)...);
@@ -752,6 +754,30 @@ __global__ void check_finite_k(const float *__restrict__ x, int64_t n, unsigned 
 
 nnc_status launch_check_finite(const float *x, int64_t n, unsigned int *flag, hipStream_t s) {
   hipLaunchKernelGGL(check_finite_k, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, x, n, flag);
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+__global__ void fill_u64_k(unsigned long long *x, int64_t n, unsigned long long v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+__global__ void fill_f32_k(float *x, int64_t n, float v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+nnc_status launch_fill_u64(unsigned long long *x, int64_t n, unsigned long long v, hipStream_t s) {
+  hipLaunchKernelGGL(fill_u64_k, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, x, n, v);
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+nnc_status launch_fill_f32(float *x, int64_t n, float v, hipStream_t s) {
+  hipLaunchKernelGGL(fill_f32_k, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, x, n, v);
   NNC_HIP(hipGetLastError());
   return NNC_OK;
 }

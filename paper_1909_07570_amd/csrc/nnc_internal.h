@@ -79,6 +79,10 @@ nnc_status launch_convert_bf16(const float *in, uint16_t *out, int64_t n, hipStr
 // flag |= 1 if any of x[0..n) is not finite.
 nnc_status launch_check_finite(const float *x, int64_t n, unsigned int *flag, hipStream_t s);
 
+// x[0..n) = v (a kernel, so that it can sit inside a captured graph).
+nnc_status launch_fill_u64(unsigned long long *x, int64_t n, unsigned long long v, hipStream_t s);
+nnc_status launch_fill_f32(float *x, int64_t n, float v, hipStream_t s);
+
 // ------------------------------------------------------------------ nnCP (cp_kernels.hip)
 struct CpProblem {
   int d;
@@ -89,15 +93,52 @@ struct CpProblem {
 // One workgroup per fit.  Batched: fit b has rank d_ranks[b] <= max_rank and factor
 // pointers d_factor_ptrs[b*d + n] (device tables).  Single fit: d_ranks == nullptr,
 // nbatch == 1, rank max_rank and host array single_ptrs (passed by value).
-// d_resid (nullable) receives each fit's relative residual.
+// d_resid (nullable) receives each fit's relative residual.  zscratch: nbatch *
+// nncp_zscratch_floats() floats, used when the contraction temporaries do not fit in LDS.
 nnc_status launch_nncp(const float *T, const CpProblem &pb, int nbatch, const int *d_ranks,
                        int max_rank, float *const *d_factor_ptrs, float *const *single_ptrs,
                        int iters, double eps, double *d_resid, unsigned long long *clips,
-                       int threads, hipStream_t s);
+                       float *zscratch, int threads, hipStream_t s);
 int64_t nncp_lds_bytes(const CpProblem &pb, int max_rank, int threads);
+int64_t nncp_zscratch_floats(const CpProblem &pb, int max_rank);
 int nncp_default_threads(const CpProblem &pb, int max_rank);
 
 nnc_status launch_lift(const float *A, const float *B, int64_t N, int64_t Rm, int64_t r, float *C,
                        hipStream_t s);
+
+// ------------------------------------------------------------------ sweep_kernels.hip
+// out[p][r][q] = sum_n F[n*ldl + r*ldr] * in[p][n][q] for FP32 partials, R <= 32.
+nnc_status launch_ttm_small(const float *in, int64_t P, int64_t N, int64_t Q, const float *F,
+                            int64_t ldl, int64_t ldr, int64_t R, float *out, hipStream_t s);
+
+// Fused num/den/update of factor rows (R <= 32); see sweep_kernels.hip.
+nnc_status launch_mu_rows(const float *Y, const float *G, float *A, const float *M, int64_t pre,
+                          int64_t Nn, int64_t post, int64_t R, double eps, unsigned long long *clips,
+                          float *gram, float *gpart, float *grad, hipStream_t s);
+int64_t mu_rows_blocks(int64_t Nn);
+// Per-block Gram partials of a factor, as mu_rows_k leaves them.
+nnc_status launch_gram_parts(const float *A, int64_t Nn, int64_t R, float *gram, hipStream_t s);
+
+struct CoreArgsHost {
+  int d;
+  int64_t R[kMaxDim];
+  int64_t N[kMaxDim];
+  const float *A[kMaxDim];
+  float *S[kMaxDim];
+  float *G;
+  float *M;
+  const float *gpart;
+  int nparts;
+  const float *gram;      // per-block Gram partials of factors gram_from.. (gram_stride apart)
+  int gram_parts;
+  int64_t gram_stride;
+  float *t0, *t1, *numG;
+  double eps;
+  unsigned long long *clips;
+  int gram_from, gram_to, do_core, next;
+};
+nnc_status launch_core_step(const CoreArgsHost &h, hipStream_t s);
+// out[e] = sum_{b < nparts} part[b][e] (fixed order)
+nnc_status launch_sum_parts(const float *part, int nparts, int64_t n, float *out, hipStream_t s);
 
 }  // namespace nnc

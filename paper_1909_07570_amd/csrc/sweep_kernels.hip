@@ -1,0 +1,633 @@
+// Kernels for the small (non-X-streaming) steps of a multiplicative-update sweep:
+//   ttm_small_k : contraction of an FP32 partial tensor (P x_k A^T), split over waves
+//   mu_rows_k   : fused numerator, denominator and update of a block of factor rows
+//   core_step_k : one workgroup doing the core-space work between mode updates
+//                 (Gram of the new factor, the core update, the next mode's R x R matrix)
+#include <string.h>
+
+#include <algorithm>
+
+#include "nnc_internal.h"
+
+namespace nnc {
+
+// =====================================================================================
+// out[p][r][q] = sum_n F[n*ldl + r*ldr] * in[p][n][q]   (R <= 32, FP32)
+// A block owns 64 consecutive (p, q) pairs, one per lane.  The factor is staged in LDS in
+// chunks of kSmallChunk rows, zero-padded to RM columns (so the inner loop has no
+// branches and reads float4 broadcasts); the block's 8 waves take contiguous slices of
+// every chunk, load their X values 16 at a time, and their partial sums are added in a
+// fixed order at the end.
+// =====================================================================================
+constexpr int kSmallWaves = 8;
+constexpr int kSmallRows = 64;  // rows of one chunk per wave, all loaded before use
+
+template <int RM>
+__global__ __launch_bounds__(64 * kSmallWaves) void ttm_small_k(const float *__restrict__ in, int64_t P,
+                                                               int64_t N, int64_t Q,
+                                                               const float *__restrict__ F,
+                                                               int64_t ldl, int64_t ldr, int R,
+                                                               float *__restrict__ out) {
+  constexpr int kChunkRows = (RM <= 24 ? 512 : 256);  // factor rows staged per chunk
+  constexpr int RH = RM < 16 ? RM : (RM % 16 ? 8 : 16);  // LDS reduction slice width
+  __shared__ __attribute__((aligned(16))) float Fs[kChunkRows][RM];
+  __shared__ float red[kSmallWaves][RH][64];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t PQ = P * Q;
+  const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+  const bool valid = e < PQ;
+  const int64_t p = valid ? e / Q : 0, q = valid ? e - (e / Q) * Q : 0;
+  const float *src = in + p * N * Q + q;  // in bounds for every lane (invalid lanes read p=q=0)
+  float acc[RM];
+#pragma unroll
+  for (int r = 0; r < RM; ++r) acc[r] = 0.f;
+  for (int64_t c0 = 0; c0 < N; c0 += kChunkRows) {
+    const int cn = (int)((N - c0) < kChunkRows ? (N - c0) : kChunkRows);
+    const int s0 = cn * w / kSmallWaves, s1 = cn * (w + 1) / kSmallWaves;  // <= 64 rows
+    // this wave's X values of the chunk, all loads in flight together
+    float x[kSmallRows];
+#pragma unroll
+    for (int u = 0; u < kSmallRows; ++u) x[u] = (s0 + u < s1) ? src[(c0 + s0 + u) * Q] : 0.f;
+    // factor rows of the chunk, zero-padded to RM columns
+    constexpr int kStage = (RM * kChunkRows + 64 * kSmallWaves - 1) / (64 * kSmallWaves);
+    float v[kStage];
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      const int idx = tid + u * 64 * kSmallWaves;
+      const int n = idx / RM, r = idx - (idx / RM) * RM;
+      v[u] = (n < cn && r < R) ? F[(c0 + n) * ldl + r * ldr] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      const int idx = tid + u * 64 * kSmallWaves;
+      if (idx < kChunkRows * RM) Fs[idx / RM][idx % RM] = v[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kSmallRows; ++u) {
+      if (s0 + u >= s1) break;
+      const float4 *f4 = reinterpret_cast<const float4 *>(&Fs[s0 + u][0]);
+#pragma unroll
+      for (int r4 = 0; r4 < RM / 4; ++r4) {
+        const float4 f = f4[r4];
+        acc[4 * r4 + 0] = fmaf(f.x, x[u], acc[4 * r4 + 0]);
+        acc[4 * r4 + 1] = fmaf(f.y, x[u], acc[4 * r4 + 1]);
+        acc[4 * r4 + 2] = fmaf(f.z, x[u], acc[4 * r4 + 2]);
+        acc[4 * r4 + 3] = fmaf(f.w, x[u], acc[4 * r4 + 3]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int h = 0; h < RM; h += RH) {
+#pragma unroll
+    for (int r = 0; r < RH; ++r) red[w][r][lane] = acc[h + r];
+    __syncthreads();
+    for (int idx = tid; idx < RH * 64; idx += 64 * kSmallWaves) {
+      const int r = h + (idx >> 6), l = idx & 63;
+      const int64_t e2 = (int64_t)blockIdx.x * 64 + l;
+      if (r >= R || e2 >= PQ) continue;
+      float s2 = red[0][r - h][l];
+#pragma unroll
+      for (int ww = 1; ww < kSmallWaves; ++ww) s2 += red[ww][r - h][l];
+      const int64_t p2 = e2 / Q, q2 = e2 - (e2 / Q) * Q;
+      out[(p2 * R + r) * Q + q2] = s2;
+    }
+    __syncthreads();
+  }
+}
+
+nnc_status launch_ttm_small(const float *in, int64_t P, int64_t N, int64_t Q, const float *F,
+                            int64_t ldl, int64_t ldr, int64_t R, float *out, hipStream_t s) {
+  if (R > 32) return fail(NNC_EUNSUPPORTED, "ttm_small: R %lld above 32", (long long)R);
+  const int64_t blocks = (P * Q + 63) / 64;
+  if (blocks > 0x7fffffff) return fail(NNC_EUNSUPPORTED, "ttm_small: too many blocks");
+  const dim3 g((unsigned)blocks), b(64 * kSmallWaves);
+  if (R <= 8)
+    hipLaunchKernelGGL(ttm_small_k<8>, g, b, 0, s, in, P, N, Q, F, ldl, ldr, (int)R, out);
+  else if (R <= 16)
+    hipLaunchKernelGGL(ttm_small_k<16>, g, b, 0, s, in, P, N, Q, F, ldl, ldr, (int)R, out);
+  else if (R <= 24)
+    hipLaunchKernelGGL(ttm_small_k<24>, g, b, 0, s, in, P, N, Q, F, ldl, ldr, (int)R, out);
+  else
+    hipLaunchKernelGGL(ttm_small_k<32>, g, b, 0, s, in, P, N, Q, F, ldl, ldr, (int)R, out);
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+// =====================================================================================
+// Fused multiplicative update of rows [i0, i0 + kRB) of factor A_n (N_n x R, R <= 32):
+//   num[i][r] = sum_{c=(p,q)} Y[p][i][q] * G[p][r][q]        (unfold_n(Y) unfold_n(G)^T)
+//   den[i][r] = sum_s A[i][s] * M[s][r]
+//   A[i][r]  <- A[i][r] * num / max(den, eps)        (or grad[i][r] = den - num)
+// Each block also leaves the Gram of its new rows in gram[block][R][R] (summed later in a
+// fixed order) and, with gpart (last mode, q range 1), its share of the core numerator
+// gpart[block][p][r] = sum_{i in block} Y[p][i] * Anew[i][r].
+// =====================================================================================
+constexpr int kRB = 8;
+constexpr int kRowThreads = 512;
+constexpr int kRowBatch = 16;           // loads in flight per thread while staging
+constexpr int kRowLdsFloats = 14 * 1024;  // dynamic LDS budget of one block (floats)
+
+// Copy n values src[map(i)] -> dst[i] for i < n with every thread issuing kRowBatch loads
+// before storing them.
+template <typename Load, typename Store>
+static __device__ inline void staged_copy(int n, Load ld, Store st) {
+  for (int base = 0; base < n; base += kRowBatch * kRowThreads) {
+    float v[kRowBatch];
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) {
+      const int i = base + threadIdx.x + u * kRowThreads;
+      v[u] = i < n ? ld(i) : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) {
+      const int i = base + threadIdx.x + u * kRowThreads;
+      if (i < n) st(i, v[u]);
+    }
+  }
+}
+
+// LDS: Gs[CH][R+1] | Ys[kRB][CH+1]  (dynamic), As, Ms (static)
+__global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict__ Y,
+                                                         const float *__restrict__ G,
+                                                         float *__restrict__ A,
+                                                         const float *__restrict__ M, int pre,
+                                                         int Nn, int post, int R, int CH,
+                                                         double eps, unsigned long long *clips,
+                                                         float *__restrict__ gram,
+                                                         float *__restrict__ gpart,
+                                                         float *__restrict__ grad) {
+  extern __shared__ __attribute__((aligned(16))) float dynr[];
+  __shared__ float As[kRB][33];
+  __shared__ float Ms[32][33];
+  __shared__ unsigned int nclip;
+  const int GS = R + 1, YS = CH + 1;
+  float *Gs = dynr;
+  float *Ys = dynr + CH * GS;
+  const int tid = threadIdx.x;
+  const int i0 = blockIdx.x * kRB;
+  const int nr = (Nn - i0) < kRB ? (Nn - i0) : kRB;
+  const int C = pre * post;
+  const int ii = tid / R, r = tid - (tid / R) * R;
+  const bool act = tid < nr * R;
+  if (tid == 0) nclip = 0;
+  float acc = 0.f;
+  for (int c0 = 0; c0 < C; c0 += CH) {
+    const int cn = (C - c0) < CH ? (C - c0) : CH;
+    staged_copy(
+        cn * R,
+        [&](int idx) {
+          const int cc = idx / R, rr = idx - (idx / R) * R;
+          const int c = c0 + cc, pp = c / post, q = c - (c / post) * post;
+          return G[((int64_t)pp * R + rr) * post + q];
+        },
+        [&](int idx, float v) { Gs[(idx / R) * GS + idx % R] = v; });
+    staged_copy(
+        nr * cn,
+        [&](int idx) {
+          const int i = idx / cn, cc = idx - (idx / cn) * cn;
+          const int c = c0 + cc, pp = c / post, q = c - (c / post) * post;
+          return Y[((int64_t)pp * Nn + i0 + i) * post + q];
+        },
+        [&](int idx, float v) { Ys[(idx / cn) * YS + idx % cn] = v; });
+    __syncthreads();
+    if (act) {
+      const float *yrow = Ys + ii * YS;
+      const float *gcol = Gs + r;
+      for (int cc = 0; cc < cn; ++cc) acc = fmaf(yrow[cc], gcol[cc * GS], acc);
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < nr * R; idx += kRowThreads) {
+    const int i = idx / R, rr = idx - (idx / R) * R;
+    As[i][rr] = A[(int64_t)(i0 + i) * R + rr];
+  }
+  for (int idx = tid; idx < R * R; idx += kRowThreads) Ms[idx / R][idx % R] = M[idx];
+  __syncthreads();
+  float nv = 0.f;
+  if (act) {
+    float den = 0.f;
+    for (int s2 = 0; s2 < R; ++s2) den = fmaf(As[ii][s2], Ms[s2][r], den);
+    if (grad) {
+      nv = den - acc;
+    } else {
+      double dd = (double)den;
+      if (dd < eps) {
+        dd = eps;
+        atomicAdd(&nclip, 1u);
+      }
+      nv = (float)(((double)As[ii][r] * (double)acc) / dd);
+    }
+  }
+  __syncthreads();
+  if (act) {
+    if (grad) {
+      grad[(int64_t)(i0 + ii) * R + r] = nv;
+    } else {
+      A[(int64_t)(i0 + ii) * R + r] = nv;
+      As[ii][r] = nv;
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && nclip) atomicAdd(clips, (unsigned long long)nclip);
+  if (grad) return;
+  if (gram) {  // Gram of this block's new rows
+    float *gb = gram + (int64_t)blockIdx.x * R * R;
+    for (int idx = tid; idx < R * R; idx += kRowThreads) {
+      const int x = idx / R, y = idx - (idx / R) * R;
+      float s2 = 0.f;
+      for (int i = 0; i < nr; ++i) s2 = fmaf(As[i][x], As[i][y], s2);
+      gb[idx] = s2;
+    }
+  }
+  if (gpart) {
+    // last mode: Y is [pre][Nn] (post == 1); stage Y[p][i0..i0+nr) for chunks of p
+    float *gp = gpart + (int64_t)blockIdx.x * pre * R;
+    const int PC = (CH * GS + kRB * YS) / kRB;  // rows of p per chunk that fit
+    for (int p0 = 0; p0 < pre; p0 += PC) {
+      const int pn = (pre - p0) < PC ? (pre - p0) : PC;
+      __syncthreads();
+      staged_copy(
+          pn * nr,
+          [&](int idx) {
+            const int pp = idx / nr, i = idx - (idx / nr) * nr;
+            return Y[(int64_t)(p0 + pp) * Nn + i0 + i];
+          },
+          [&](int idx, float v) { dynr[idx] = v; });
+      __syncthreads();
+      for (int idx = tid; idx < pn * R; idx += kRowThreads) {
+        const int pp = idx / R, rr = idx - (idx / R) * R;
+        float s2 = 0.f;
+        for (int i = 0; i < nr; ++i) s2 = fmaf(dynr[pp * nr + i], As[i][rr], s2);
+        gp[(int64_t)(p0 + pp) * R + rr] = s2;
+      }
+    }
+  }
+}
+
+// Gram partials of a factor from its rows: gram[b][x][y] = sum_{i in [8b, 8b+8)} A[i][x] A[i][y],
+// the same arithmetic as the epilogue of mu_rows_k.
+__global__ __launch_bounds__(256) void gram_parts_k(const float *__restrict__ A, int Nn, int R,
+                                                    float *__restrict__ gram) {
+  const int i0 = blockIdx.x * kRB;
+  const int nr = (Nn - i0) < kRB ? (Nn - i0) : kRB;
+  for (int idx = threadIdx.x; idx < R * R; idx += blockDim.x) {
+    const int x = idx / R, y = idx - (idx / R) * R;
+    float s2 = 0.f;
+    for (int i = 0; i < nr; ++i) s2 = fmaf(A[(int64_t)(i0 + i) * R + x], A[(int64_t)(i0 + i) * R + y], s2);
+    gram[(int64_t)blockIdx.x * R * R + idx] = s2;
+  }
+}
+
+nnc_status launch_gram_parts(const float *A, int64_t Nn, int64_t R, float *gram, hipStream_t s) {
+  hipLaunchKernelGGL(gram_parts_k, dim3((unsigned)((Nn + kRB - 1) / kRB)), dim3(256), 0, s, A, (int)Nn,
+                     (int)R, gram);
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+nnc_status launch_mu_rows(const float *Y, const float *G, float *A, const float *M, int64_t pre,
+                          int64_t Nn, int64_t post, int64_t R, double eps, unsigned long long *clips,
+                          float *gram, float *gpart, float *grad, hipStream_t s) {
+  if (R > 32) return fail(NNC_EUNSUPPORTED, "mu_rows: R %lld above 32", (long long)R);
+  if (pre * post > (int64_t)1 << 30 || Nn > (int64_t)1 << 30)
+    return fail(NNC_EUNSUPPORTED, "mu_rows: sizes above 2^30");
+  const int64_t C = pre * post;
+  int64_t CH = (kRowLdsFloats - kRB) / (R + 1 + kRB);
+  if (CH > C) CH = C;
+  const size_t lds = (size_t)(CH * (R + 1) + kRB * (CH + 1)) * sizeof(float);
+  const int64_t blocks = (Nn + kRB - 1) / kRB;
+  hipLaunchKernelGGL(mu_rows_k, dim3((unsigned)blocks), dim3(kRowThreads), lds, s, Y, G, A, M, (int)pre,
+                     (int)Nn, (int)post, (int)R, (int)CH, eps, clips, gram, gpart, grad);
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+int64_t mu_rows_blocks(int64_t Nn) { return (Nn + kRB - 1) / kRB; }
+
+// out[e] = sum_{b < nparts} part[b][e], blocks added in order (loads issued 8 at a time).
+__global__ __launch_bounds__(256) void sum_parts_k(const float *__restrict__ part, int nparts,
+                                                   int64_t n, float *__restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  float s2 = 0.f;
+  for (int b0 = 0; b0 < nparts; b0 += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = (b0 + u < nparts) ? part[(int64_t)(b0 + u) * n + e] : 0.f;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (b0 + u < nparts) s2 += v[u];
+  }
+  out[e] = s2;
+}
+
+nnc_status launch_sum_parts(const float *part, int nparts, int64_t n, float *out, hipStream_t s) {
+  hipLaunchKernelGGL(sum_parts_k, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, nparts, n, out);
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+// =====================================================================================
+// Core-space step, one workgroup.  The core and its temporaries live in LDS when they fit
+// (lds != 0), else in global scratch; every phase ends with a barrier (and a device-scope
+// fence when global scratch carries data between phases).
+//   1. Gram S_k = A_k^T A_k for k in [gram_from, gram_to), the factor staged in LDS
+//   2. if do_core: num_G = sum of the row-block partials, den_G = G x_0 S_0 ... x_{d-1} S_{d-1},
+//      G <- G * num_G / max(den_G, eps)
+//   3. M = unfold_next(G x_{k != next} S_k) unfold_next(G)^T       (R_next x R_next)
+// =====================================================================================
+struct CoreArgs {
+  int d;
+  int R[kMaxDim];
+  int N[kMaxDim];
+  const float *A[kMaxDim];
+  float *S[kMaxDim];
+  float *G;
+  float *M;
+  const float *gpart;
+  int nparts;
+  const float *gram;
+  int gram_parts;
+  int64_t gram_stride;
+  float *t0, *t1, *numG;
+  double eps;
+  unsigned long long *clips;
+  int gram_from, gram_to, do_core, next;
+  int lds;
+  int gsize;
+};
+
+constexpr int kCoreThreads = 1024;
+constexpr int kCoreLdsMax = 8192;  // cores up to this many entries are kept in LDS
+
+static __device__ inline void phase_sync(bool global) {
+  if (global) __threadfence();
+  __syncthreads();
+}
+
+// out = in x_k S (S symmetric R_k x R_k, stored with row stride RM and zero padding),
+// core-shaped; one thread per (p, q, group of 4 output columns).
+template <int RM>
+static __device__ void core_ttm(const CoreArgs &a, const float *in, int k, const float *S,
+                                float *out) {
+  int pre = 1, post = 1;
+#pragma unroll
+  for (int j = 0; j < kMaxDim; ++j) {
+    if (j < k) pre *= a.R[j];
+    if (j > k && j < a.d) post *= a.R[j];
+  }
+  const int Rk = a.R[k];
+  const int ng = (Rk + 3) / 4;
+  const int tasks = pre * post * ng;
+  for (int t = threadIdx.x; t < tasks; t += blockDim.x) {
+    const int g = t % ng, pq = t / ng;
+    const int p = pq / post, q = pq - (pq / post) * post;
+    const float *src = in + p * Rk * post + q;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int l = 0; l < Rk; ++l) {
+      const float x = src[l * post];
+      const float4 sv = reinterpret_cast<const float4 *>(S + l * RM)[g];
+      acc.x = fmaf(sv.x, x, acc.x);
+      acc.y = fmaf(sv.y, x, acc.y);
+      acc.z = fmaf(sv.z, x, acc.z);
+      acc.w = fmaf(sv.w, x, acc.w);
+    }
+    float *dst = out + p * Rk * post + q;
+    const int r0 = 4 * g;
+    dst[r0 * post] = acc.x;
+    if (r0 + 1 < Rk) dst[(r0 + 1) * post] = acc.y;
+    if (r0 + 2 < Rk) dst[(r0 + 2) * post] = acc.z;
+    if (r0 + 3 < Rk) dst[(r0 + 3) * post] = acc.w;
+  }
+}
+
+template <int RM>
+__global__ __launch_bounds__(kCoreThreads) void core_step_k(CoreArgs a) {
+  extern __shared__ __attribute__((aligned(16))) float dyn[];
+  __shared__ float part[kCoreThreads];
+  const int tid = threadIdx.x;
+  const int d = a.d;
+  const bool glb = !a.lds;
+  // working copies: G and its temporaries (LDS when they fit, else global scratch) and the
+  // Grams padded to RM columns in LDS (Sp), which every core contraction reads
+  __shared__ __attribute__((aligned(16))) float Sp[kMaxDim][32 * RM];
+  float *G = a.G, *t0 = a.t0, *t1 = a.t1;
+  if (a.lds) {
+    G = dyn;
+    t0 = dyn + a.gsize;
+    t1 = dyn + 2 * a.gsize;
+    for (int e0 = 0; e0 < a.gsize; e0 += 8 * kCoreThreads) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + tid + u * kCoreThreads;
+        v[u] = e < a.gsize ? a.G[e] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + tid + u * kCoreThreads;
+        if (e < a.gsize) G[e] = v[u];
+      }
+    }
+  }
+  for (int k = 0; k < d; ++k) {
+    const int Rk = a.R[k];
+    for (int e = tid; e < 32 * RM; e += kCoreThreads) {
+      const int l = e / RM, r = e - (e / RM) * RM;
+      Sp[k][e] = (l < Rk && r < Rk) ? a.S[k][l * Rk + r] : 0.f;
+    }
+  }
+  __syncthreads();
+  // ---- 1. Gram S_k = A_k^T A_k (k = gram_from .. gram_to-1) from per-block partials
+  // gram[b][R][R] (Gram of factor rows [8b, 8b+8), see mu_rows_k / gram_parts_k).  Thread
+  // (entry, chunk) sums a contiguous range of blocks; the chunks are then added in order.
+  // The partials and this order are the same at the start of a fit and within it, so a
+  // fit resumed from its outputs continues bit for bit.
+  for (int k = a.gram_from; k < a.gram_to; ++k) {
+    const int Rk = a.R[k];
+    const int RR = Rk * Rk;
+    const int nch = kCoreThreads / RR;
+    const int e = tid % RR, ch = tid / RR;
+    const float *gk = a.gram + (int64_t)(k - a.gram_from) * a.gram_stride;
+    float acc = 0.f;
+    if (ch < nch) {
+      const int b0 = (int)((int64_t)a.gram_parts * ch / nch);
+      const int b1 = (int)((int64_t)a.gram_parts * (ch + 1) / nch);
+      for (int bb = b0; bb < b1; bb += 16) {
+        float v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = (bb + u < b1) ? gk[(int64_t)(bb + u) * RR + e] : 0.f;
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (bb + u < b1) acc += v[u];
+      }
+    }
+    part[tid] = (ch < nch) ? acc : 0.f;
+    __syncthreads();
+    if (tid < RR) {
+      float s2 = 0.f;
+      for (int c = 0; c < nch; ++c) s2 += part[c * RR + tid];
+      Sp[k][(tid / Rk) * RM + tid % Rk] = s2;
+      a.S[k][tid] = s2;
+    }
+    phase_sync(glb);
+  }
+  // ---- 2. core update
+  if (a.do_core) {
+    const float *numG = a.numG;  // summed from the row-block partials by sum_parts_k
+    const float *in = G;
+    for (int k = 0; k < d; ++k) {
+      float *o = (k % 2) ? t1 : t0;
+      core_ttm<RM>(a, in, k, Sp[k], o);
+      phase_sync(glb);
+      in = o;
+    }
+    unsigned int nclip = 0;
+    for (int e = tid; e < a.gsize; e += kCoreThreads) {
+      double dd = (double)in[e];
+      if (dd < a.eps) {
+        dd = a.eps;
+        ++nclip;
+      }
+      const float g = (float)(((double)G[e] * (double)numG[e]) / dd);
+      G[e] = g;
+      if (a.lds) a.G[e] = g;
+    }
+    if (nclip) atomicAdd(a.clips, (unsigned long long)nclip);
+    phase_sync(glb);
+  }
+  // ---- 3. M for the next mode
+  if (a.next >= 0) {
+    const int n = a.next;
+    const float *in = G;
+    int cnt = 0;
+    for (int k = 0; k < d; ++k) {
+      if (k == n) continue;
+      float *o = (cnt % 2) ? t1 : t0;
+      core_ttm<RM>(a, in, k, Sp[k], o);
+      phase_sync(glb);
+      in = o;
+      ++cnt;
+    }
+    const float *H = in;
+    int pre = 1, post = 1;
+    for (int j = 0; j < n; ++j) pre *= a.R[j];
+    for (int j = n + 1; j < d; ++j) post *= a.R[j];
+    const int Rn = a.R[n];
+    const int nb2 = (Rn + 1) / 2;           // 2x2 blocks of M per row/column
+    const int blocks2 = nb2 * nb2;
+    const int split = kCoreThreads / blocks2;
+    const int bi = tid % blocks2, sp = tid / blocks2;
+    const int x0 = 2 * (bi / nb2), y0 = 2 * (bi % nb2);
+    const int x1 = x0 + 1 < Rn ? x0 + 1 : x0, y1 = y0 + 1 < Rn ? y0 + 1 : y0;
+    float m00 = 0.f, m01 = 0.f, m10 = 0.f, m11 = 0.f;
+    if (sp < split) {
+      const int C = pre * post;
+      const int c0 = (int)((int64_t)C * sp / split), c1 = (int)((int64_t)C * (sp + 1) / split);
+      int pp = c0 / post, q = c0 - (c0 / post) * post;
+      for (int c = c0; c < c1; ++c) {
+        const int base = pp * Rn * post + q;
+        const float h0 = H[base + x0 * post], h1 = H[base + x1 * post];
+        const float g0 = G[base + y0 * post], g1 = G[base + y1 * post];
+        m00 = fmaf(h0, g0, m00);
+        m01 = fmaf(h0, g1, m01);
+        m10 = fmaf(h1, g0, m10);
+        m11 = fmaf(h1, g1, m11);
+        if (++q == post) {
+          q = 0;
+          ++pp;
+        }
+      }
+    }
+    // partial sums of the split ranges, added in order; 4 values per thread.  Scratch of
+    // kCoreThreads * 4 floats: LDS after G/t0/t1, or (global mode) numG, which is free here
+    // and has more than 8192 entries.
+    float *pm = a.lds ? dyn + 3 * a.gsize : a.numG;
+    __syncthreads();
+    if (sp < split) {
+      pm[(sp * blocks2 + bi) * 4 + 0] = m00;
+      pm[(sp * blocks2 + bi) * 4 + 1] = m01;
+      pm[(sp * blocks2 + bi) * 4 + 2] = m10;
+      pm[(sp * blocks2 + bi) * 4 + 3] = m11;
+    }
+    phase_sync(glb);
+    for (int e = tid; e < Rn * Rn; e += kCoreThreads) {
+      const int x = e / Rn, y = e % Rn;
+      const int b2 = (x / 2) * nb2 + (y / 2), j = (x % 2) * 2 + (y % 2);
+      float s2 = 0.f;
+      for (int c = 0; c < split; ++c) s2 += pm[(c * blocks2 + b2) * 4 + j];
+      a.M[e] = s2;
+    }
+  }
+}
+
+nnc_status launch_core_step(const CoreArgsHost &h, hipStream_t s) {
+  CoreArgs a;
+  memset(&a, 0, sizeof a);
+  a.d = h.d;
+  int64_t gsize = 1, ssum = 0;
+  for (int k = 0; k < kMaxDim; ++k) {
+    a.R[k] = k < h.d ? (int)h.R[k] : 1;
+    a.N[k] = k < h.d ? (int)h.N[k] : 1;
+    a.A[k] = k < h.d ? h.A[k] : nullptr;
+    a.S[k] = k < h.d ? h.S[k] : nullptr;
+  }
+  for (int k = 0; k < h.d; ++k) {
+    if (h.R[k] > 32) return fail(NNC_EUNSUPPORTED, "core_step: rank above 32");
+    gsize *= h.R[k];
+    ssum += h.R[k] * h.R[k];
+  }
+  if (gsize > (int64_t)1 << 28) return fail(NNC_EUNSUPPORTED, "core_step: core too large");
+  a.gsize = (int)gsize;
+  a.G = h.G;
+  a.M = h.M;
+  a.gpart = h.gpart;
+  a.nparts = h.nparts;
+  a.gram = h.gram;
+  a.gram_parts = h.gram_parts;
+  a.gram_stride = h.gram_stride;
+  a.t0 = h.t0;
+  a.t1 = h.t1;
+  a.numG = h.numG;
+  a.eps = h.eps;
+  a.clips = h.clips;
+  a.gram_from = h.gram_from;
+  a.gram_to = h.gram_to;
+  a.do_core = h.do_core;
+  a.next = h.next;
+  int maxr = 1;
+  for (int k = 0; k < h.d; ++k) maxr = std::max(maxr, (int)h.R[k]);
+  size_t lds = 0;
+  if (gsize <= kCoreLdsMax) {
+    a.lds = 1;
+    lds = (size_t)(3 * gsize + 4 * kCoreThreads) * sizeof(float);
+  }
+#define NNC_CORE_LAUNCH(RM)                                                                     \
+  do {                                                                                          \
+    static bool attr = false;                                                                   \
+    if (!attr) {                                                                                \
+      NNC_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(core_step_k<RM>),              \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,                   \
+                                  (int)((3 * kCoreLdsMax + 4 * kCoreThreads) * sizeof(float))));                     \
+      attr = true;                                                                              \
+    }                                                                                           \
+    hipLaunchKernelGGL(core_step_k<RM>, dim3(1), dim3(kCoreThreads), lds, s, a);                \
+  } while (0)
+  if (maxr <= 8)
+    NNC_CORE_LAUNCH(8);
+  else if (maxr <= 16)
+    NNC_CORE_LAUNCH(16);
+  else if (maxr <= 24)
+    NNC_CORE_LAUNCH(24);
+  else
+    NNC_CORE_LAUNCH(32);
+#undef NNC_CORE_LAUNCH
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+}  // namespace nnc
