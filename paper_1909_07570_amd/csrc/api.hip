@@ -367,10 +367,35 @@ static nnc_status chain_small(const float *src, int d, int64_t *cur, const int *
   return NNC_OK;
 }
 
+// A second stream (default priority) and fork/join events: the core-space step of mode n
+// runs beside the next mode's contraction (or pass 2), which does not depend on it.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork[kMaxDim] = {}, join[kMaxDim] = {};
+  bool ok = false;
+};
+
+static SideStream *side_stream() {
+  static std::mutex mu;
+  static SideStream ss;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ss.ok) {
+    if (hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    for (int k = 0; k < kMaxDim; ++k) {
+      if (hipEventCreateWithFlags(&ss.fork[k], hipEventDisableTiming) != hipSuccess) return nullptr;
+      if (hipEventCreateWithFlags(&ss.join[k], hipEventDisableTiming) != hipSuccess) return nullptr;
+    }
+    ss.ok = true;
+  }
+  return &ss;
+}
+
 static nnc_status fused_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, float *G,
                               float *const *A, double eps, hipStream_t s, PassTimer *tm) {
   const TuckerPlan &p = *b.p;
   const int d = p.d;
+  SideStream *ss = side_stream();
+  if (!ss) return fail(NNC_EHIP, "could not create the side stream");
   if (tm) NNC_TRY(tm->start(s));
   NNC_TRY(launch_ttm(X, dt, p.size / p.N[d - 1], p.N[d - 1], 1, A[d - 1], p.R[d - 1], 1, p.R[d - 1],
                      b.P(), s, true));
@@ -385,15 +410,20 @@ static nnc_status fused_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, 
     memcpy(ycur, cur, sizeof ycur);
     const float *Y = nullptr;
     NNC_TRY(chain_small(U, d, ycur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
+    if (n > 0) NNC_HIP(hipStreamWaitEvent(s, ss->join[n - 1], 0));  // M_n from core step n-1
     NNC_TRY(launch_mu_rows(Y, G, A[n], b.M(), prod(p.R, 0, n), p.N[n], prod(p.R, n + 1, d), p.R[n],
                            eps, b.clips(), b.gram(), nullptr, nullptr, s));
+    // core step n on the side stream: Gram of the new A_n and M_{n+1}
+    NNC_HIP(hipEventRecord(ss->fork[n], s));
+    NNC_HIP(hipStreamWaitEvent(ss->s, ss->fork[n], 0));
     CoreArgsHost h = core_args(b, G, A, eps);
     h.gram_from = n;
     h.gram_to = n + 1;
     h.gram = b.gram();
     h.gram_parts = (int)mu_rows_blocks(p.N[n]);
     h.next = n + 1;
-    NNC_TRY(launch_core_step(h, s));
+    NNC_TRY(launch_core_step(h, ss->s));
+    NNC_HIP(hipEventRecord(ss->join[n], ss->s));
     if (n < d - 2) {
       float *Un = b.U(n % 2);
       NNC_TRY(ttm_f32(U, d, cur, n, A[n], p.R[n], Un, s));
@@ -409,6 +439,7 @@ static nnc_status fused_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, 
   for (int k = 1; k < d - 1; ++k) modes[nm++] = k;
   const float *Y = nullptr;
   NNC_TRY(chain_small(b.T(), d, cur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
+  NNC_HIP(hipStreamWaitEvent(s, ss->join[d - 2], 0));  // M_{d-1}; joins the side stream
   NNC_TRY(launch_mu_rows(Y, G, A[d - 1], b.M(), prod(p.R, 0, d - 1), p.N[d - 1], 1, p.R[d - 1], eps,
                          b.clips(), b.gram(), b.gpart(), nullptr, s));
   NNC_TRY(launch_sum_parts(b.gpart(), (int)mu_rows_blocks(p.N[d - 1]), p.gsize, b.G(2), s));

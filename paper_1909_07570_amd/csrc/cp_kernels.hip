@@ -49,12 +49,15 @@ static __device__ inline float mu_cp(float x, float num, float den, double eps, 
 //   | part (max(threads, maxdim * r)) | red (2 * threads doubles) | [Z (zmax x r) if z_lds]
 static int64_t cp_lds_floats(const CpArgs &a, int r, int threads, bool t_lds, bool z_lds) {
   int64_t s = t_lds ? a.size : 0;
-  for (int k = 0; k < a.d; ++k) s += (int64_t)a.dims[k] * r;
+  s = (s + 3) & ~(int64_t)3;  // factor rows are read as float4
+  const int RM = r <= 8 ? 8 : (r <= 16 ? 16 : 32);  // factor rows and Z rows are padded to RM
+  for (int k = 0; k < a.d; ++k) s += (int64_t)a.dims[k] * RM;
   s += (int64_t)(a.d + 1) * r * r + (int64_t)a.maxdim * r;
   s += std::max<int64_t>(threads, (int64_t)a.maxdim * r);
   s += (s & 1);               // keep the doubles 8-byte aligned
   s += 4 * (int64_t)threads;  // 2 * threads doubles
-  if (z_lds) s += (int64_t)a.zmax * r;
+  s = (s + 3) & ~(int64_t)3;  // Z rows are written as float4
+  if (z_lds) s += (int64_t)a.zmax * RM;
   return s;
 }
 
@@ -81,11 +84,12 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
     T = p;
     p += a.size;
   }
-  float *sB = p;  // B_k at sB + boff[k]
+  p += (4 - ((p - sm) & 3)) & 3;
+  float *sB = p;  // B_k at sB + boff[k], rows padded to RM columns (zeros past r)
   int nb = 0;
 #pragma unroll
   for (int k = 0; k < kMaxDim; ++k)
-    if (k < d) nb += a.dims[k] * r;
+    if (k < d) nb += a.dims[k] * RM;
   p += nb;
   float *sW = p;  // Gram_k at sW + k*r*r
   p += d * r * r;
@@ -98,13 +102,14 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
   p += ((p - sm) & 1);
   double *red = reinterpret_cast<double *>(p);
   p += 4 * nt;
+  p += (4 - ((p - sm) & 3)) & 3;
   float *Z = a.z_lds ? p : zg + (int64_t)b * a.zmax * RM;
   if (tid == 0) {
     nclip = 0;
     int o = 0;
     for (int k = 0; k < d; ++k) {
       boff[k] = o;
-      o += a.dims[k] * r;
+      o += a.dims[k] * RM;
     }
     boff[d] = o;
   }
@@ -113,7 +118,10 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
   for (int k = 0; k < kMaxDim; ++k) {
     if (k >= d) break;
     const float *src = ranks ? fptrs[(int64_t)b * d + k] : ptr0.p[k];
-    for (int e = tid; e < a.dims[k] * r; e += nt) sB[boff[k] + e] = src[e];
+    for (int e = tid; e < a.dims[k] * RM; e += nt) {
+      const int i = e / RM, c = e - (e / RM) * RM;
+      sB[boff[k] + e] = c < r ? src[i * r + c] : 0.f;
+    }
   }
   __syncthreads();
   for (int k = 0; k < d; ++k) {
@@ -121,7 +129,7 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
     for (int e = tid; e < r * r; e += nt) {
       const int x = e / r, y = e - (e / r) * r;
       float acc = 0.f;
-      for (int i = 0; i < a.dims[k]; ++i) acc = fmaf(Bk[i * r + x], Bk[i * r + y], acc);
+      for (int i = 0; i < a.dims[k]; ++i) acc = fmaf(Bk[i * RM + x], Bk[i * RM + y], acc);
       sW[k * r * r + e] = acc;
     }
   }
@@ -144,15 +152,20 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
         for (int rho = 0; rho < RM; ++rho) acc[rho] = 0.f;
         for (int l = 0; l < mL; ++l) {
           const float x = t[l * postL];
-          const float *bl = BL + l * r;
+          const float4 *bl = reinterpret_cast<const float4 *>(BL + l * RM);
 #pragma unroll
-          for (int rho = 0; rho < RM; ++rho)
-            if (rho < r) acc[rho] = fmaf(x, bl[rho], acc[rho]);
+          for (int r4 = 0; r4 < RM / 4; ++r4) {
+            const float4 bv = bl[r4];
+            acc[4 * r4 + 0] = fmaf(x, bv.x, acc[4 * r4 + 0]);
+            acc[4 * r4 + 1] = fmaf(x, bv.y, acc[4 * r4 + 1]);
+            acc[4 * r4 + 2] = fmaf(x, bv.z, acc[4 * r4 + 2]);
+            acc[4 * r4 + 3] = fmaf(x, bv.w, acc[4 * r4 + 3]);
+          }
         }
-        float *zo = Z + o * r;
+        float4 *zo = reinterpret_cast<float4 *>(Z + o * RM);
 #pragma unroll
-        for (int rho = 0; rho < RM; ++rho)
-          if (rho < r) zo[rho] = acc[rho];
+        for (int r4 = 0; r4 < RM / 4; ++r4)
+          zo[r4] = make_float4(acc[4 * r4], acc[4 * r4 + 1], acc[4 * r4 + 2], acc[4 * r4 + 3]);
       }
       if (!a.z_lds) __threadfence_block();
       __syncthreads();
@@ -213,10 +226,10 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
         }
         float acc = 0.f;
         for (int o = o0; o < o1; ++o) {
-          float prod = Z[zoff * r + rho];
+          float prod = Z[zoff * RM + rho];
 #pragma unroll
           for (int j = 0; j < kMaxDim; ++j)
-            if (j < nz && j != npos) prod *= sB[zb[j] + idx[j] * r + rho];
+            if (j < nz && j != npos) prod *= sB[zb[j] + idx[j] * RM + rho];
           acc += prod;
           bool carry = true;  // odometer over the modes != n of Z, last fastest
 #pragma unroll
@@ -256,16 +269,16 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
       for (int e = tid; e < npairs; e += nt) {
         const int i = e / r, c = e - (e / r) * r;
         float den = 0.f;
-        for (int s2 = 0; s2 < r; ++s2) den = fmaf(Bn[i * r + s2], H[s2 * r + c], den);
-        part[e] = mu_cp(Bn[e], Mm[e], den, eps, &nclip);
+        for (int s2 = 0; s2 < r; ++s2) den = fmaf(Bn[i * RM + s2], H[s2 * r + c], den);
+        part[e] = mu_cp(Bn[i * RM + c], Mm[e], den, eps, &nclip);
       }
       __syncthreads();
-      for (int e = tid; e < npairs; e += nt) Bn[e] = part[e];
+      for (int e = tid; e < npairs; e += nt) Bn[(e / r) * RM + e % r] = part[e];
       __syncthreads();
       for (int e = tid; e < r * r; e += nt) {
         const int x = e / r, y = e - (e / r) * r;
         float acc = 0.f;
-        for (int i = 0; i < In; ++i) acc = fmaf(Bn[i * r + x], Bn[i * r + y], acc);
+        for (int i = 0; i < In; ++i) acc = fmaf(Bn[i * RM + x], Bn[i * RM + y], acc);
         sW[n * r * r + e] = acc;
       }
       __syncthreads();
@@ -275,7 +288,7 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
   for (int k = 0; k < kMaxDim; ++k) {
     if (k >= d) break;
     float *dst = ranks ? fptrs[(int64_t)b * d + k] : ptr0.p[k];
-    for (int e = tid; e < a.dims[k] * r; e += nt) dst[e] = sB[boff[k] + e];
+    for (int e = tid; e < a.dims[k] * r; e += nt) dst[e] = sB[boff[k] + (e / r) * RM + e % r];
   }
   if (tid == 0 && nclip) atomicAdd(clips, (unsigned long long)nclip);
 
@@ -297,7 +310,7 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
         float pp = 1.f;
 #pragma unroll
         for (int k = 0; k < kMaxDim; ++k)
-          if (k < d) pp *= sB[boff[k] + ix[k] * r + rho];
+          if (k < d) pp *= sB[boff[k] + ix[k] * RM + rho];
         xh += pp;
       }
       const double x = T[e];

@@ -392,12 +392,20 @@ static nnc_status launch_stream(void (*kern)(KArgs...), size_t lds, int64_t tile
   return NNC_OK;
 }
 
+// 1: X-streaming contractions use the software-pipelined kernels when the shape allows.
+static int g_use_pipe = 1;
+void set_use_pipe(int on) { g_use_pipe = on; }
+
 nnc_status launch_ttm(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64_t Q, const float *F,
                       int64_t ldl, int64_t ldr, int64_t R, float *out, hipStream_t s,
                       bool allow_mfma, const char **kernel_name) {
   const char *name = "ttm_generic";
   const int64_t total_rows = P * N * Q;
   if (total_rows == 0 || R == 0) return NNC_OK;
+  if (allow_mfma && g_use_pipe) {
+    const nnc_status st = launch_pass(X, xdt, P, N, Q, F, ldl, ldr, R, out, s, kernel_name);
+    if (st != NNC_EUNSUPPORTED) return st;
+  }
   const bool small_r = R <= 32;
   const int RT = R <= 16 ? 1 : 2;
   bool done = false;

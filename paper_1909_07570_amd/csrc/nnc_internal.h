@@ -39,6 +39,12 @@ nnc_status launch_ttm(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64_
                       int64_t ldl, int64_t ldr, int64_t R, float *out, hipStream_t s,
                       bool allow_mfma, const char **kernel_name = nullptr);
 
+// Software-pipelined X-streaming contractions (pass_kernels.hip).  Returns NNC_EUNSUPPORTED
+// without recording an error when the shape does not suit them.
+nnc_status launch_pass(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64_t Q, const float *F,
+                       int64_t ldl, int64_t ldr, int64_t R, float *out, hipStream_t s,
+                       const char **kernel_name);
+
 // out[i][j] = sum_{p<pre, q<post} U[(p*I+i)*post+q] * V[(p*J+j)*post+q]
 nnc_status launch_contract_except(const float *U, const float *V, int64_t pre, int64_t I, int64_t J,
                                   int64_t post, float *out, hipStream_t s);

@@ -1,0 +1,401 @@
+// The X-streaming contractions of a sweep (the two passes over X), software-pipelined:
+// every wave keeps the loads of its next work unit in flight while the MFMAs consume the
+// current one, so each CU holds tens of KiB of X requests at any time.
+//
+//   ttm_last_pipe_k : out[m][r] = sum_k X[m][k] F(k, r)        (contraction index contiguous)
+//   ttm_mid_pipe_k  : out[p][r][q] = sum_n F(n, r) X[p][n][q]  (contraction index strided)
+// X is FP32 (v_mfma_f32_16x16x4_f32) or bfloat16 (v_mfma_f32_16x16x32_bf16, FP32
+// accumulation, factor applied as bf16 hi + lo parts).  The factor (R <= 32 columns,
+// zero-padded to 16-column tiles) lives in LDS.
+#include <map>
+#include <mutex>
+
+#include "nnc_internal.h"
+
+namespace nnc {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+
+static __device__ inline uint16_t p_f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+static __device__ inline float p_bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+static __device__ inline f4 p_mfma_bf16(u4 a, u4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b),
+                                                c, 0, 0, 0);
+}
+static __device__ inline f4 p_mfma_f32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+constexpr int kPassThreads = 256;
+constexpr int kUnitChunks = 16;  // 16-byte loads per lane per work unit
+
+// =====================================================================================
+// Last-mode contraction.  A work unit is 16 rows x KU k-values: lane (li = lane%16,
+// lg = lane/16) loads, for each of 16 chunks c, the 16 bytes X[row li][kb*KU + c*KPC + EPC*lg ..]
+// (EPC elements; KPC = 4*EPC k-values per chunk across the four lane groups).
+//   bf16: the 8 elements are the lane's MFMA A operand (k-slots 8 lg .. 8 lg + 7), paired
+//         with 8 consecutive k of the factor's transposed bf16 rows in LDS.
+//   f32 : element e of the chunk feeds the MFMA whose k-slot lg stands for k = .. + 4 lg + e.
+// Output tile: lane holds rows 4 lg + j, column li of each 16-column tile.
+// =====================================================================================
+template <bool BF, int RT>
+__global__ __launch_bounds__(kPassThreads) void ttm_last_pipe_k(const void *__restrict__ Xv, int64_t M,
+                                                                int K, const float *__restrict__ F,
+                                                                int64_t ldl, int64_t ldr, int R,
+                                                                float *__restrict__ out) {
+  extern __shared__ __attribute__((aligned(16))) uint16_t lds_u16[];
+  constexpr int EPC = BF ? 8 : 4;
+  constexpr int KPC = 4 * EPC;
+  constexpr int KU = kUnitChunks * KPC;
+  constexpr int RP = 16 * RT;
+  const int Kp = (K + KPC - 1) / KPC * KPC;
+  // ---- factor staging
+  const int KS = Kp + 8;    // bf16: [RP][KS] hi then lo
+  const int RS = RP + 4;    // f32: [Kp][RS]
+  uint16_t *hi = lds_u16;
+  uint16_t *lo = lds_u16 + RP * KS;
+  float *fl = reinterpret_cast<float *>(lds_u16);
+  if (BF) {
+    for (int e = threadIdx.x; e < RP * Kp; e += blockDim.x) {
+      const int r = e / Kp, k = e - r * Kp;
+      const float a = (k < K && r < R) ? F[k * ldl + r * ldr] : 0.f;
+      const uint16_t h = p_f2bf(a);
+      hi[r * KS + k] = h;
+      lo[r * KS + k] = p_f2bf(a - p_bf2f(h));
+    }
+  } else {
+    for (int e = threadIdx.x; e < Kp * RP; e += blockDim.x) {
+      const int k = e / RP, r = e - k * RP;
+      fl[k * RS + r] = (k < K && r < R) ? F[k * ldl + r * ldr] : 0.f;
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int nw = blockDim.x >> 6;
+  const int64_t ntile = (M + 15) >> 4;
+  const int upt = (Kp + KU - 1) / KU;  // units per tile
+  const int64_t tstride = (int64_t)gridDim.x * nw;
+
+  auto load_unit = [&](u4 (&buf)[kUnitChunks], int64_t t, int kb) {
+    const int64_t row = t * 16 + li;
+    const bool rv = row < M;
+    const char *xr = reinterpret_cast<const char *>(Xv) + (rv ? row : 0) * (int64_t)K * (BF ? 2 : 4);
+#pragma unroll
+    for (int c = 0; c < kUnitChunks; ++c) {
+      const int k = kb * KU + c * KPC + EPC * lg;
+      buf[c] = (rv && k < K) ? *reinterpret_cast<const u4 *>(xr + (int64_t)k * (BF ? 2 : 4))
+                             : u4{0u, 0u, 0u, 0u};
+    }
+  };
+  f4 acc[RT];
+  auto compute_unit = [&](const u4 (&buf)[kUnitChunks], int64_t t, int kb) {
+    if (kb == 0) {
+#pragma unroll
+      for (int nt = 0; nt < RT; ++nt) acc[nt] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int c = 0; c < kUnitChunks; ++c) {
+      const int kc = kb * KU + c * KPC;
+      if (kc >= Kp) break;  // uniform
+      if (BF) {
+        const int kk = kc + 8 * lg;
+#pragma unroll
+        for (int nt = 0; nt < RT; ++nt) {
+          const int off = (nt * 16 + li) * KS + kk;
+          acc[nt] = p_mfma_bf16(buf[c], *reinterpret_cast<const u4 *>(hi + off), acc[nt]);
+          acc[nt] = p_mfma_bf16(buf[c], *reinterpret_cast<const u4 *>(lo + off), acc[nt]);
+        }
+      } else {
+        const int kk = kc + 4 * lg;
+        const f4 xv = __builtin_bit_cast(f4, buf[c]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float *brow = fl + (kk + e) * RS + li;
+#pragma unroll
+          for (int nt = 0; nt < RT; ++nt) acc[nt] = p_mfma_f32(xv[e], brow[nt * 16], acc[nt]);
+        }
+      }
+    }
+    if (kb == upt - 1) {
+#pragma unroll
+      for (int nt = 0; nt < RT; ++nt) {
+        const int r = nt * 16 + li;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int64_t m = t * 16 + 4 * lg + j;
+          if (m < M && r < R) out[m * R + r] = acc[nt][j];
+        }
+      }
+    }
+  };
+  auto advance = [&](int64_t &t, int &kb) {
+    if (++kb == upt) {
+      kb = 0;
+      t += tstride;
+    }
+  };
+
+  u4 b0[kUnitChunks], b1[kUnitChunks];
+  int64_t t = (int64_t)blockIdx.x * nw + wave;
+  int kb = 0;
+  if (t < ntile) load_unit(b0, t, kb);
+  while (t < ntile) {
+    int64_t tn = t;
+    int kbn = kb;
+    advance(tn, kbn);
+    if (tn < ntile) load_unit(b1, tn, kbn);
+    compute_unit(b0, t, kb);
+    t = tn;
+    kb = kbn;
+    if (t >= ntile) break;
+    tn = t;
+    kbn = kb;
+    advance(tn, kbn);
+    if (tn < ntile) load_unit(b0, tn, kbn);
+    compute_unit(b1, t, kb);
+    t = tn;
+    kb = kbn;
+  }
+}
+
+// =====================================================================================
+// Earlier-mode contraction.  A wave owns Q-tile (p, q0 .. q0 + QT) and walks the contracted
+// index n in steps; the loads of step s+1 are in flight during the MFMAs of step s.
+//   bf16 (QT = 128): a step is 32 rows n0 + 8 lg + j (j < 8); lane (li, lg) loads the 16 bytes
+//        X[p][n][q0 + 8 li ..] of each, transposes the 8 x 8 block in registers into eight
+//        A operands (one per q offset c: the 8 n values of that q), so MFMA c's output row i
+//        stands for q = q0 + 8 i + c and lane group lg owns q0 + 32 lg + [0, 32).
+//   f32  (QT = 64): a step is 32 rows n0 + lg + 4 s (s < 8); lane loads X[p][n][q0 + 4 li ..],
+//        component c feeds MFMA c whose output row i stands for q = q0 + 4 i + c; lane group
+//        lg owns q0 + 16 lg + [0, 16).
+// =====================================================================================
+template <bool BF, int RT>
+__global__ __launch_bounds__(kPassThreads) void ttm_mid_pipe_k(const void *__restrict__ Xv, int64_t P,
+                                                               int N, int64_t Q,
+                                                               const float *__restrict__ F,
+                                                               int64_t ldl, int64_t ldr, int R,
+                                                               float *__restrict__ out) {
+  extern __shared__ __attribute__((aligned(16))) uint16_t lds_u16[];
+  constexpr int RP = 16 * RT;
+  constexpr int QT = BF ? 128 : 64;
+  constexpr int NSTEP = 32;
+  const int Np = (N + NSTEP - 1) / NSTEP * NSTEP;
+  const int NS = Np + 8;   // bf16: [RP][NS] hi then lo (transposed factor)
+  const int RS = RP + 4;   // f32: [Np][RS]
+  uint16_t *hi = lds_u16;
+  uint16_t *lo = lds_u16 + RP * NS;
+  float *fl = reinterpret_cast<float *>(lds_u16);
+  if (BF) {
+    for (int e = threadIdx.x; e < RP * Np; e += blockDim.x) {
+      const int r = e / Np, n = e - r * Np;
+      const float a = (n < N && r < R) ? F[n * ldl + r * ldr] : 0.f;
+      const uint16_t h = p_f2bf(a);
+      hi[r * NS + n] = h;
+      lo[r * NS + n] = p_f2bf(a - p_bf2f(h));
+    }
+  } else {
+    for (int e = threadIdx.x; e < Np * RP; e += blockDim.x) {
+      const int n = e / RP, r = e - n * RP;
+      fl[n * RS + r] = (n < N && r < R) ? F[n * ldl + r * ldr] : 0.f;
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int nw = blockDim.x >> 6;
+  const int64_t qt = (Q + QT - 1) / QT;
+  const int64_t ntile = P * qt;
+  const int nsteps = Np / NSTEP;
+  constexpr int NC = BF ? 8 : 4;  // accumulator sets (q offsets) per 16-column tile
+  for (int64_t t = (int64_t)blockIdx.x * nw + wave; t < ntile; t += (int64_t)gridDim.x * nw) {
+    const int64_t p = t / qt;
+    const int64_t q0 = (t - p * qt) * QT;
+    const int64_t qa = q0 + (BF ? 8 : 4) * li;
+    const bool qv = qa < Q;
+    const char *xp = reinterpret_cast<const char *>(Xv) + (p * (int64_t)N * Q + (qv ? qa : 0)) * (BF ? 2 : 4);
+    const int64_t rowbytes = Q * (BF ? 2 : 4);
+    f4 acc[NC][RT];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int nt = 0; nt < RT; ++nt) acc[c][nt] = f4{0.f, 0.f, 0.f, 0.f};
+    // row of slot j in step s: bf16 n0 + 8 lg + j, f32 n0 + lg + 4 j
+    auto load_step = [&](u4 (&v)[8], int s) {
+      const int n0 = s * NSTEP;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int n = BF ? (n0 + 8 * lg + j) : (n0 + lg + 4 * j);
+        v[j] = (qv && n < N) ? *reinterpret_cast<const u4 *>(xp + (int64_t)n * rowbytes)
+                             : u4{0u, 0u, 0u, 0u};
+      }
+    };
+    auto compute_step = [&](const u4 (&v)[8], int s) {
+      const int n0 = s * NSTEP;
+      if (BF) {
+        u4 bh[RT], bl[RT];
+#pragma unroll
+        for (int nt = 0; nt < RT; ++nt) {
+          const int off = (nt * 16 + li) * NS + n0 + 8 * lg;
+          bh[nt] = *reinterpret_cast<const u4 *>(hi + off);
+          bl[nt] = *reinterpret_cast<const u4 *>(lo + off);
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          u4 op;
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            const uint32_t a = v[2 * w][c >> 1], b = v[2 * w + 1][c >> 1];
+            op[w] = (c & 1) ? ((a >> 16) | (b & 0xffff0000u)) : ((a & 0xffffu) | (b << 16));
+          }
+#pragma unroll
+          for (int nt = 0; nt < RT; ++nt) {
+            acc[c][nt] = p_mfma_bf16(op, bh[nt], acc[c][nt]);
+            acc[c][nt] = p_mfma_bf16(op, bl[nt], acc[c][nt]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int n = n0 + lg + 4 * j;
+          const f4 xv = __builtin_bit_cast(f4, v[j]);
+          const float *brow = fl + n * RS + li;
+#pragma unroll
+          for (int nt = 0; nt < RT; ++nt) {
+            const float b = brow[nt * 16];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c][nt] = p_mfma_f32(xv[c], b, acc[c][nt]);
+          }
+        }
+      }
+    };
+    u4 v0[8], v1[8];
+    load_step(v0, 0);
+    for (int s = 0; s < nsteps; s += 2) {
+      if (s + 1 < nsteps) load_step(v1, s + 1);
+      compute_step(v0, s);
+      if (s + 1 >= nsteps) break;
+      if (s + 2 < nsteps) load_step(v0, s + 2);
+      compute_step(v1, s + 1);
+    }
+#pragma unroll
+    for (int nt = 0; nt < RT; ++nt) {
+      const int r = nt * 16 + li;
+      if (r >= R) continue;
+      float *orow = out + (p * R + r) * Q;
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        if (BF) {
+          const int64_t q = q0 + 32 * lg + 8 * jj;
+          if (q < Q) {
+            *reinterpret_cast<f4 *>(orow + q) =
+                f4{acc[0][nt][jj], acc[1][nt][jj], acc[2][nt][jj], acc[3][nt][jj]};
+            *reinterpret_cast<f4 *>(orow + q + 4) =
+                f4{acc[4 % NC][nt][jj], acc[5 % NC][nt][jj], acc[6 % NC][nt][jj], acc[7 % NC][nt][jj]};
+          }
+        } else {
+          const int64_t q = q0 + 16 * lg + 4 * jj;
+          if (q < Q)
+            *reinterpret_cast<f4 *>(orow + q) =
+                f4{acc[0][nt][jj], acc[1][nt][jj], acc[2][nt][jj], acc[3][nt][jj]};
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+static nnc_status allow_lds_bytes(const void *kern, size_t bytes) {
+  static std::mutex mu;
+  static std::map<const void *, size_t> done;
+  if (bytes <= 64 * 1024) return NNC_OK;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = done.find(kern);
+  if (it != done.end() && it->second >= bytes) return NNC_OK;
+  NNC_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  done[kern] = bytes;
+  return NNC_OK;
+}
+
+constexpr size_t kPassLdsMax = 96 * 1024;
+static int g_pipe_mid = 0;
+constexpr int kPassBlocks = 512;  // persistent: two blocks per CU
+
+size_t pass_last_lds(bool bf, int RT, int64_t K) {
+  if (bf) {
+    const int64_t Kp = (K + 31) / 32 * 32;
+    return (size_t)(2 * 16 * RT * (Kp + 8) * 2);
+  }
+  const int64_t Kp = (K + 15) / 16 * 16;
+  return (size_t)(Kp * (16 * RT + 4) * 4);
+}
+
+size_t pass_mid_lds(bool bf, int RT, int64_t N) {
+  const int64_t Np = (N + 31) / 32 * 32;
+  if (bf) return (size_t)(2 * 16 * RT * (Np + 8) * 2);
+  return (size_t)(Np * (16 * RT + 4) * 4);
+}
+
+// Returns NNC_EUNSUPPORTED (without recording an error) when the shape does not suit the
+// pipelined kernels, so the caller can fall back.
+nnc_status launch_pass(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64_t Q, const float *F,
+                       int64_t ldl, int64_t ldr, int64_t R, float *out, hipStream_t s,
+                       const char **kernel_name) {
+  if (R > 32 || R < 1) return NNC_EUNSUPPORTED;
+  if ((reinterpret_cast<uintptr_t>(X) & 15u) || (reinterpret_cast<uintptr_t>(out) & 15u))
+    return NNC_EUNSUPPORTED;
+  const bool bf = xdt == NNC_BF16;
+  const int RT = R <= 16 ? 1 : 2;
+  const int waves = kPassThreads / 64;
+  if (Q == 1) {
+    if (N % (bf ? 8 : 4)) return NNC_EUNSUPPORTED;
+    const size_t lds = pass_last_lds(bf, RT, N);
+    if (lds > kPassLdsMax || N > (1 << 20)) return NNC_EUNSUPPORTED;
+    const int64_t tiles = (P + 15) / 16;
+    const int grid = (int)std::min<int64_t>(std::max<int64_t>((tiles + waves - 1) / waves, 1), kPassBlocks);
+#define NNC_LAST(BFV, RTV)                                                                        \
+  do {                                                                                            \
+    NNC_TRY(allow_lds_bytes(reinterpret_cast<const void *>(ttm_last_pipe_k<BFV, RTV>), lds));     \
+    hipLaunchKernelGGL((ttm_last_pipe_k<BFV, RTV>), dim3(grid), dim3(kPassThreads), lds, s, X, P, \
+                       (int)N, F, ldl, ldr, (int)R, out);                                         \
+  } while (0)
+    if (bf && RT == 1) NNC_LAST(true, 1);
+    else if (bf) NNC_LAST(true, 2);
+    else if (RT == 1) NNC_LAST(false, 1);
+    else NNC_LAST(false, 2);
+#undef NNC_LAST
+    if (kernel_name) *kernel_name = bf ? "ttm_last_pipe_bf16" : "ttm_last_pipe_f32";
+  } else {
+    // the earlier-mode contraction keeps its single-buffered kernel (ttm_mid_*_k), which
+    // runs at two waves per SIMD; this pipelined form needs more registers than that
+    if (!g_pipe_mid) return NNC_EUNSUPPORTED;
+    if (Q % (bf ? 8 : 4)) return NNC_EUNSUPPORTED;
+    const size_t lds = pass_mid_lds(bf, RT, N);
+    if (lds > kPassLdsMax || N > (1 << 20)) return NNC_EUNSUPPORTED;
+    const int64_t tiles = P * ((Q + (bf ? 127 : 63)) / (bf ? 128 : 64));
+    const int grid = (int)std::min<int64_t>(std::max<int64_t>((tiles + waves - 1) / waves, 1), kPassBlocks);
+#define NNC_MID(BFV, RTV)                                                                         \
+  do {                                                                                            \
+    NNC_TRY(allow_lds_bytes(reinterpret_cast<const void *>(ttm_mid_pipe_k<BFV, RTV>), lds));      \
+    hipLaunchKernelGGL((ttm_mid_pipe_k<BFV, RTV>), dim3(grid), dim3(kPassThreads), lds, s, X, P,  \
+                       (int)N, Q, F, ldl, ldr, (int)R, out);                                      \
+  } while (0)
+    if (bf && RT == 1) NNC_MID(true, 1);
+    else if (bf) NNC_MID(true, 2);
+    else if (RT == 1) NNC_MID(false, 1);
+    else NNC_MID(false, 2);
+#undef NNC_MID
+    if (kernel_name) *kernel_name = bf ? "ttm_mid_pipe_bf16" : "ttm_mid_pipe_f32";
+  }
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+}  // namespace nnc

@@ -1,0 +1,153 @@
+"""GPU parity at the workloads' full sizes, in the launch configuration bench.py times.
+
+- The two X-streaming contractions of the 512^3 workload (FP32 and BF16 forms) on sampled
+  output entries, each recomputed by the oracle from its slice of X.
+- One whole sweep at 512^3 (and at 128^4, stored BF16) against one oracle sweep from the
+  same initial values.
+- 500 sweeps at 512^3 (FP32 form and BF16 form with FP32 refinement), nnCP and lift:
+  final relative residuals within 1e-3 of the oracle's, stored in tests/golden/c2_reference.json
+  by tests/golden/make_c2_reference.py (oracle only).
+- The adjoint at 256^3 with a 32^3 core against the oracle gradient.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import bf16_dev, dev, host, need_gpu, rel_fro
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_reference.json")
+SEED, N, R = 2, 512, 20
+
+
+@pytest.fixture(scope="module")
+def c2():
+    X32, _ = synth.planted_tensor(SEED, (N, N, N), 10, zero_prob=0.5, noise=1e-3, dtype="f32")
+    G0 = synth.init_core(SEED, (R, R, R))
+    A0 = synth.init_factors(SEED, (N, N, N), (R, R, R))
+    return X32, G0, A0
+
+
+def _sampled_pass_check(nnc, Xd, Xhost64, A0, tol):
+    rng = np.random.default_rng(0)
+    # pass 1: P[i, j, r] = sum_k X[i, j, k] A_3[k, r]
+    P = host(nnc.nnc_ttm(Xd, 2, dev(A0[2])))
+    # pass 2: T[r, j, k] = sum_i A_1[i, r] X[i, j, k]
+    T = host(nnc.nnc_ttm(Xd, 0, dev(A0[0])))
+    errs = []
+    for _ in range(64):
+        i, j, k = rng.integers(0, N, 3)
+        ref_p = oracle.ttm_t(Xhost64(i, j, None)[None, None, :], 2, A0[2].astype(np.float64))[0, 0]
+        ref_t = oracle.ttm_t(Xhost64(None, j, k)[:, None, None], 0, A0[0].astype(np.float64))[:, 0, 0]
+        errs.append(rel_fro(P[i, j], ref_p))
+        errs.append(rel_fro(T[:, j, k], ref_t))
+    assert max(errs) <= tol, max(errs)
+
+
+def test_c2_passes_sampled_fp32(c2):
+    nnc = need_gpu()
+    X32, G0, A0 = c2
+
+    def xs(i, j, k):
+        return (X32[i, j, :] if k is None else X32[:, j, k]).astype(np.float64)
+    _sampled_pass_check(nnc, dev(X32), xs, A0, 1e-5)
+
+
+def test_c2_passes_sampled_bf16(c2):
+    nnc = need_gpu()
+    X32, G0, A0 = c2
+    Xb = nnc.nnc_convert_f32_bf16(dev(X32))
+    Xb_host = synth.bf16_bits_to_f64(Xb.view(__import__("torch").int16).cpu().numpy().view(np.uint16))
+    assert np.array_equal(Xb_host, synth.round_bf16(X32.astype(np.float64)))
+
+    def xs(i, j, k):
+        return Xb_host[i, j, :] if k is None else Xb_host[:, j, k]
+    _sampled_pass_check(nnc, Xb, xs, A0, 1e-4)
+
+
+def test_c2_one_sweep_matches_oracle(c2):
+    nnc = need_gpu()
+    X32, G0, A0 = c2
+    X64 = X32.astype(np.float64)
+    Go, Ao, _, _ = oracle.nntucker(X64, G0, A0, 1)
+    for bf in (False, True):
+        Xd = dev(X32)
+        G = dev(G0)
+        A = [dev(a) for a in A0]
+        if bf:
+            Xb = nnc.nnc_convert_f32_bf16(Xd)
+            nnc.nntucker_fit(Xb, (R, R, R), 1, G, A)
+            tol = 2e-3  # X rounded to bf16 (relative 2^-9 per entry)
+        else:
+            nnc.nntucker_fit(Xd, (R, R, R), 1, G, A)
+            tol = 1e-4
+        assert rel_fro(host(G), Go) <= tol
+        for a, ao in zip(A, Ao):
+            assert rel_fro(host(a), ao) <= tol
+
+
+def test_c2_final_residuals_match_stored_oracle(c2):
+    """500 sweeps (both forms), nnCP rank 10 x 300 sweeps, lift (the bench's step)."""
+    if not os.path.exists(GOLDEN):
+        pytest.skip("tests/golden/c2_reference.json not generated")
+    ref = json.load(open(GOLDEN))
+    nnc = need_gpu()
+    X32, G0, A0 = c2
+    Xd = dev(X32)
+    Xb = nnc.nnc_convert_f32_bf16(Xd)
+    B0 = synth.init_cp_factors(SEED, (R, R, R), 10)
+    for form in ("fp32", "bf16"):
+        G = dev(G0)
+        A = [dev(a) for a in A0]
+        if form == "fp32":
+            rep = nnc.nntucker_fit(Xd, (R, R, R), 500, G, A)
+        else:
+            rep = nnc.nntucker_fit(Xb, (R, R, R), 500, G, A, x_fp32=Xd, fp32_final_sweeps=20)
+        assert abs(rep.rel_residual - ref["tucker_rel"]) <= 1e-3, (form, rep.rel_residual, ref["tucker_rel"])
+        assert rep.eps_clips == 0
+        B = [dev(b) for b in B0]
+        nnc.nncp_fit(G, 10, 300, B)
+        C = nnc.nncandelinc_lift(A, B)
+        cp_rel = nnc.reconstruct_residual(Xd, C)
+        assert abs(cp_rel - ref["cp_rel"]) <= 1e-3, (form, cp_rel, ref["cp_rel"])
+
+
+def test_c3_one_sweep_bf16_4way():
+    """128^4 stored bf16, multirank 16^4: one sweep against the oracle on the bf16 values."""
+    nnc = need_gpu()
+    dims, ranks = (128,) * 4, (16,) * 4
+    Xbits, _ = synth.planted_tensor(3, dims, 8, noise=1e-3, dtype="bf16")
+    import torch
+    Xd = torch.from_numpy(Xbits.view(np.int16)).to("cuda").view(torch.bfloat16)
+    X64 = synth.bf16_bits_to_f64(Xbits)
+    del Xbits
+    G0 = synth.init_core(3, ranks)
+    A0 = synth.init_factors(3, dims, ranks)
+    G = dev(G0)
+    A = [dev(a) for a in A0]
+    rep = nnc.nntucker_fit(Xd, ranks, 1, G, A)
+    Go, Ao, _, _ = oracle.nntucker(X64, G0, A0, 1)
+    assert rel_fro(host(G), Go) <= 1e-4
+    for a, ao in zip(A, Ao):
+        assert rel_fro(host(a), ao) <= 1e-4
+    assert abs(rep.rel_residual - oracle.tucker_rel_residual(X64, Go, Ao)) <= 1e-5
+
+
+def test_c4_adjoint_full_size():
+    """256^3, core 32^3, factors 256 x 32: dL/dG and dL/dA_n against the oracle gradient."""
+    nnc = need_gpu()
+    dims, ranks = (256,) * 3, (32,) * 3
+    X32, _ = synth.planted_tensor(4, dims, 12, zero_prob=0.3, noise=0.0, dtype="f32")
+    G0 = synth.init_core(4, ranks)
+    A0 = synth.init_factors(4, dims, ranks)
+    L, gG, gA = nnc.nntucker_grad(dev(X32), dev(G0), [dev(a) for a in A0])
+    Lo, gGo, gAo = oracle.tucker_grad(X32.astype(np.float64), G0, A0)
+    assert abs(L - Lo) <= 1e-6 * Lo
+    assert rel_fro(host(gG), gGo) <= 1e-4
+    for g, go in zip(gA, gAo):
+        assert rel_fro(host(g), go) <= 1e-4

@@ -359,3 +359,26 @@ def test_planted_recovery_through_tucker_core():
     rel, C = best
     assert rel <= tucker_rel + 1e-3
     assert oracle.mean_congruence(C, planted) >= 0.999
+
+
+def test_gradient_finite_differences_16cubed_core_4cubed():
+    """The adjoint workload's FD instance: 16^3 planted data, core 4^3, FP64 central differences."""
+    X, _ = synth.planted_tensor(4, (16, 16, 16), 12, zero_prob=0.3, noise=0.0, dtype="f64")
+    G = synth.init_core(4, (4, 4, 4), dtype=np.float64)
+    A = synth.init_factors(4, (16, 16, 16), (4, 4, 4), dtype=np.float64)
+    _, gG, gA = oracle.tucker_grad(X, G, A)
+    rng = _rng(40)
+    for _ in range(6):
+        blk = int(rng.integers(0, 4))
+        theta = G if blk == 3 else A[blk]
+        idx = tuple(int(rng.integers(0, s)) for s in theta.shape)
+        g = gG[idx] if blk == 3 else gA[blk][idx]
+        h = 1e-6 * max(1.0, abs(theta[idx]))
+        old = theta[idx]
+        theta[idx] = old + h
+        lp = _loss(X, G, A)
+        theta[idx] = old - h
+        lm = _loss(X, G, A)
+        theta[idx] = old
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - g) <= 1e-6 * max(1.0, abs(g)), (blk, idx, fd, g)
