@@ -34,6 +34,139 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+PASS_SOURCES = ["paper_1909_07570_amd/csrc/pass_kernels.hip", "paper_1909_07570_amd/csrc/kernels.hip"]
+COUNTERS = os.path.join(ROOT, "profiles", "pass_counters_512cubed.json")
+N_COPY = 128 << 20
+
+
+def sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in PASS_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def kernel_only(args):
+    """Launch each X-streaming pass kernel (512^3, R = 20, both forms) and a plain 512 MiB
+    device copy a few times: the workload of the rocprofv3 counter runs."""
+    import torch
+
+    import paper_1909_07570_amd as nnc
+    import synth
+    dev = torch.device("cuda:0")
+    N, R = args.n, 20
+    X32 = torch.from_numpy(synth.planted_tensor(SEED, (N, N, N), 10, zero_prob=0.5, noise=1e-3,
+                                                dtype="f32")[0]).to(dev)
+    Xb = nnc.nnc_convert_f32_bf16(X32)
+    A = [torch.from_numpy(a).to(dev) for a in synth.init_factors(SEED, (N, N, N), (R, R, R))]
+    src = torch.ones(N_COPY, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)  # calibration: reads and writes N_COPY floats
+        for Xt in (Xb, X32):
+            nnc.nnc_ttm(Xt, 2, A[2])
+            nnc.nnc_ttm(Xt, 0, A[0])
+    torch.cuda.synchronize()
+    print("kernel-only done", flush=True)
+
+
+def _find(d, suffix):
+    import glob
+    hits = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not hits:
+        raise SystemExit("no *%s under %s" % (suffix, d))
+    return hits[0]
+
+
+def summarize(args):
+    """Write the profiles/ summaries from three rocprofv3 CSV output folders (kernel trace
+    with --stats; --pmc FETCH_SIZE; --pmc WRITE_SIZE).  Needs no GPU."""
+    import csv
+    prof_dir, fetch_dir, write_dir = args.summarize
+    lines = ["# Kernel time of one 512^3 bench step, both forms (rocprofv3 --kernel-trace --stats)", "",
+             "Command (repo root):", "",
+             "    rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof -o run -- "
+             "python -u bench.py --steps 1 --warmup 0 --no-cpu", "",
+             "The step runs 500 nnTucker sweeps per form (BF16 form: 480 on BF16 X + 20 on FP32 X),",
+             "nnCP rank 10 x 300 sweeps, lift and residuals; bench.py then times each X-streaming",
+             "pass kernel over 23 launches and runs a 20-sweep eager fit.", "",
+             "| kernel | calls | total ms | avg us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
+    with open(_find(prof_dir, "kernel_stats.csv")) as f:
+        rows = list(csv.DictReader(f))
+    for r in rows[:18]:
+        lines.append("| %s | %s | %.2f | %.2f | %.2f | %.2f | %.2f |" % (
+            r["Name"].split("(")[0], r["Calls"], float(r["TotalDurationNs"]) / 1e6,
+            float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
+            float(r["Percentage"])))
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", "kernel_stats_512cubed.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+    def counter(d, name):
+        per = {}
+        with open(_find(d, "counter_collection.csv")) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != name:
+                    continue
+                key = (r["Kernel_Name"], r["Dispatch_Id"])
+                per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+        out = {}
+        for (kn, _), v in per.items():
+            out.setdefault(kn, []).append(v)
+        return out
+    fetch = counter(fetch_dir, "FETCH_SIZE")
+    write = counter(write_dir, "WRITE_SIZE")
+
+    def pick(d, key):
+        ks = [k for k in d if key in k]
+        if not ks:
+            return None
+        v = sorted(d[ks[0]])
+        return v[len(v) // 2]  # median dispatch, KiB
+    copy_bytes = 2 * N_COPY * 4  # the calibration kernel reads and writes N_COPY floats each
+    copy_f, copy_w = pick(fetch, "MulFunctor"), pick(write, "MulFunctor")
+    f_scale = (copy_bytes / 2) / (copy_f * 1024.0)
+    w_scale = (copy_bytes / 2) / (copy_w * 1024.0)
+    res = {"source_sha": sources_sha(), "copy_fetch_kib": copy_f, "copy_write_kib": copy_w,
+           "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
+    alg = {}
+    for key, esz in (("ttm_last_pipe_k<true", 2), ("ttm_mid_bf16_k", 2),
+                     ("ttm_last_pipe_k<false", 4), ("ttm_mid_f32_k", 4)):
+        fk, wk = pick(fetch, key), pick(write, key)
+        if fk is None or wk is None:
+            continue
+        alg[key] = 512 ** 3 * esz + 512 * 512 * 20 * 4
+        res["kernels"][key] = {"fetch_kib": fk, "write_kib": wk,
+                               "traffic_bytes": fk * 1024 * f_scale + wk * 1024 * w_scale,
+                               "alg_bytes": alg[key]}
+    with open(COUNTERS, "w") as f:
+        json.dump(res, f, indent=1)
+    md = ["# HBM traffic of the X-streaming pass kernels, 512^3, R = 20 (rocprofv3 --pmc)", "",
+          "Commands (repo root), one counter per run:", "",
+          "    rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o run -- "
+          "python -u bench.py --kernel-only",
+          "    rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o run -- "
+          "python -u bench.py --kernel-only",
+          "    python bench.py --summarize gpurun_out/prof gpurun_out/pmc_fetch gpurun_out/pmc_write", "",
+          "Calibration: a plain elementwise copy of %d MiB (FP32 multiply by 1) reads FETCH_SIZE = %.0f KiB "
+          "and writes WRITE_SIZE = %.0f KiB per dispatch (the torch fill that creates its source is not used); "
+          "counter KiB are scaled by %.4f (fetch) and "
+          "%.4f (write) to HBM bytes." % (copy_bytes // 2 >> 20, copy_f, copy_w, f_scale, w_scale), "",
+          "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled HBM bytes | algorithmic bytes | ratio |",
+          "|---|---|---|---|---|---|"]
+    for k, v in res["kernels"].items():
+        md.append("| %s | %.0f | %.0f | %.0f | %d | %.3f |" % (
+            k, v["fetch_kib"], v["write_kib"], v["traffic_bytes"], alg[k], v["traffic_bytes"] / alg[k]))
+    md += ["", "Algorithmic bytes: X once (2 B or 4 B per entry) + the FP32 output (512 x 512 x 20).",
+           "Source hash of the pass kernels when measured: %s" % res["source_sha"]]
+    with open(os.path.join(ROOT, "profiles", "pass_traffic_512cubed.md"), "w") as f:
+        f.write("\n".join(md) + "\n")
+    print(json.dumps(res, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -44,9 +177,20 @@ def main():
     ap.add_argument("--cp-sweeps", type=int, default=300)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sweeps", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="the oracle baseline runs whole sweeps until this much time has passed")
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only launch the pass kernels and a calibration copy (counter runs)")
+    ap.add_argument("--summarize", nargs=3, metavar=("PROF_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/ summaries from rocprofv3 CSV outputs (no GPU needed)")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args)
+        return
+    if args.kernel_only:
+        kernel_only(args)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -150,8 +294,14 @@ def main():
 
     dom = max(("ttm_last_bf16", "ttm_mid_bf16"), key=lambda k: kern[k]["avg_us"])
     dk = kern[dom]
+    traffic = None
+    if os.path.exists(COUNTERS):
+        cnt = json.load(open(COUNTERS))
+        key = {"ttm_last_bf16": "ttm_last_pipe_k<true", "ttm_mid_bf16": "ttm_mid_bf16_k"}[dom]
+        if cnt.get("source_sha") == sources_sha() and key in cnt.get("kernels", {}):
+            traffic = round(cnt["kernels"][key]["traffic_bytes"])
     roofline = {"bound": "hbm", "achieved": round(dk["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(dk["gbs"] / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "frac": round(dk["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "avg_us": round(dk["avg_us"], 2), "alg_bytes_per_launch": dk["alg_bytes"]}
 
     cpu = None
@@ -161,12 +311,17 @@ def main():
         g0 = synth.init_core(SEED, ranks).astype(np.float64)
         a0 = [a.astype(np.float64) for a in synth.init_factors(SEED, dims, ranks)]
         t = time.perf_counter()
-        oracle.nntucker(X64, g0, a0, args.cpu_sweeps)
-        el = time.perf_counter() - t
-        cpu = {"value": round(args.cpu_sweeps / el, 5), "unit": "MU sweeps/s", "cores": oracle.get_threads(),
+        done = 0
+        while True:
+            g0, a0, _, _ = oracle.nntucker(X64, g0, a0, 1)
+            done += 1
+            el = time.perf_counter() - t
+            if el >= args.cpu_seconds:
+                break
+        cpu = {"value": round(done / el, 5), "unit": "MU sweeps/s", "cores": oracle.get_threads(),
                "kind": "oracle",
-               "sample": "%d nnTucker sweep(s) of the same 512^3 problem (multirank 20^3) in FP64, %.1f s"
-                         % (args.cpu_sweeps, el)}
+               "sample": "%d FP64 nnTucker sweeps of the same 512^3 problem (multirank 20^3) from the "
+                         "same initial values, %.1f s" % (done, el)}
         del X64
 
     bf, fp = results["bf16"], results["fp32"]
