@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kTtmThreads) void ttm_mid_f32_k(const float *__rest
     for (int n0 = 0; n0 < Np; n0 += 4) {
       const int n = n0 + lg;
       f4 xv = f4{0.f, 0.f, 0.f, 0.f};
-      if (qv && n < N) xv = *reinterpret_cast<const f4 *>(xp + (int64_t)n * Q);
+      if (qv && n < N) xv = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(xp + (int64_t)n * Q));
       const float *brow = lds + n * RS + li;
 #pragma unroll
       for (int nt = 0; nt < RT; ++nt) {
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(kTtmThreads) void ttm_mid_bf16_k(const uint16_t *__
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int n = n0 + 8 * lg + j;
-        v[j] = (qv && n < N) ? *reinterpret_cast<const u4 *>(xp + (int64_t)n * Q)
+        v[j] = (qv && n < N) ? __builtin_nontemporal_load(reinterpret_cast<const u4 *>(xp + (int64_t)n * Q))
                              : u4{0u, 0u, 0u, 0u};
       }
       u4 bh[RT], bl[RT];

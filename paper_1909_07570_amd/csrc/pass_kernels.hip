@@ -311,6 +311,213 @@ __global__ __launch_bounds__(kPassThreads) void ttm_mid_pipe_k(const void *__res
   }
 }
 
+// =====================================================================================
+// Last-mode contraction with row-contiguous loads.  Fed straight from memory, the MFMA
+// operand layout makes every load instruction touch 16 rows (64 bytes of each), which
+// splits each 128-byte line over two requests and keeps the stream well short of HBM speed.
+// Here each load instruction covers whole row segments instead: a piece is 16 rows x CPR
+// 16-byte chunks, and lane l of load j reads chunk l % CPR of row j * (64 / CPR) + l / CPR,
+// so one instruction reads 64 / CPR segments of CPR * 16 contiguous bytes, non-temporally.
+// The wave writes the piece to its own padded LDS region and reads it back in the MFMA
+// layout (lane (li, lg) takes row li, chunk 4 s + lg at k-step s).  Three register buffers
+// keep three pieces in flight while one is consumed from LDS; every load is issued on every
+// path, so the wait before each store leaves the two younger pieces outstanding.
+//   bf16: chunk = 8 k, k-step = 32 k; A = the chunk, B = the factor's bf16 hi and lo rows.
+//   f32 : chunk = 4 k, k-step = 16 k; element e of the chunk feeds MFMA e, whose k-slot lg
+//         stands for k = 16 s + 4 lg + e; B = the matching 4 floats of the factor.
+// The factor is stored transposed, [16 RT][Kp + pad], so both operand reads are 16-byte
+// LDS loads free of bank conflicts.  One 512-thread block per CU.
+// =====================================================================================
+constexpr int kLdsThreads = 512;
+constexpr int kLdsWaves = kLdsThreads / 64;
+
+template <bool BF, int RT, int CPR>
+__global__ __launch_bounds__(kLdsThreads) void ttm_last_lds_k(const void *__restrict__ Xv, int64_t M,
+                                                              int K, const float *__restrict__ F,
+                                                              int64_t ldl, int64_t ldr, int R,
+                                                              float *__restrict__ out) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_b[];
+  constexpr int EPC = BF ? 8 : 4;    // elements per 16-byte chunk
+  constexpr int ESZ = BF ? 2 : 4;    // bytes per element
+  constexpr int KC = CPR * EPC;      // k-values per piece
+  constexpr int LPI = CPR / 4;       // loads per lane per piece
+  constexpr int RPI = 64 / CPR;      // rows per load instruction
+  constexpr int SS = CPR * 16 + 16;  // staging row stride in bytes (16 bytes of padding)
+  constexpr int KSTEP = BF ? 32 : 16;
+  constexpr int RP = 16 * RT;
+  constexpr int kFB = 32;            // factor loads in flight per thread while staging
+  const int Kp = (K + KC - 1) / KC * KC;
+  const int KS = Kp + (BF ? 8 : 4);  // factor row stride (elements)
+  uint16_t *hi = reinterpret_cast<uint16_t *>(lds_b);
+  uint16_t *lo = hi + RP * KS;
+  float *fl = reinterpret_cast<float *>(lds_b);
+  const int fbytes = BF ? 2 * RP * KS * 2 : RP * KS * 4;  // a multiple of 16
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const int li = lane & 15, lg = lane >> 4;
+  unsigned char *stg = lds_b + fbytes + wave * 16 * SS;
+  const int64_t ntile = (M + 15) >> 4;
+  const int kpt = Kp / KC;  // pieces per tile
+  const int64_t gw = (int64_t)blockIdx.x * kLdsWaves + wave;
+  const int64_t tstride = (int64_t)gridDim.x * kLdsWaves;
+
+  const int crow = lane / CPR, cch = lane % CPR;
+  // Lanes outside X load from inside it instead: rows past the end read the last row
+  // (their output rows are never stored) and chunks past K read the row's first chunk (the
+  // factor is zero there, so they add 0 for finite X; a row holding Inf or NaN has a
+  // non-finite result either way).  So every lane issues every load and the loaded values
+  // go to LDS untouched, which keeps the waits exact.
+  auto load_piece = [&](u4 (&b)[LPI], int64_t t, int h) {
+    const int k = h * KC + cch * EPC;
+    const int kc = k < K ? k : 0;
+#pragma unroll
+    for (int j = 0; j < LPI; ++j) {
+      int64_t row = t * 16 + j * RPI + crow;
+      row = row < M ? row : M - 1;
+      b[j] = __builtin_nontemporal_load(reinterpret_cast<const u4 *>(
+          reinterpret_cast<const char *>(Xv) + (row * (int64_t)K + kc) * ESZ));
+    }
+  };
+  auto store_piece = [&](const u4 (&b)[LPI]) {
+#pragma unroll
+    for (int j = 0; j < LPI; ++j)
+      *reinterpret_cast<u4 *>(stg + (j * RPI + crow) * SS + cch * 16) = b[j];
+  };
+  f4 acc[RT];
+  auto compute_piece = [&](int64_t t, int h) {
+    if (h == 0) {
+#pragma unroll
+      for (int nt = 0; nt < RT; ++nt) acc[nt] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+    const unsigned char *srow = stg + li * SS + lg * 16;
+#pragma unroll
+    for (int st = 0; st < CPR / 4; ++st) {
+      const u4 a = *reinterpret_cast<const u4 *>(srow + st * 64);
+      const int kk = h * KC + st * KSTEP;
+      if (BF) {
+#pragma unroll
+        for (int nt = 0; nt < RT; ++nt) {
+          const int off = (nt * 16 + li) * KS + kk + 8 * lg;
+          acc[nt] = p_mfma_bf16(a, *reinterpret_cast<const u4 *>(hi + off), acc[nt]);
+          acc[nt] = p_mfma_bf16(a, *reinterpret_cast<const u4 *>(lo + off), acc[nt]);
+        }
+      } else {
+        const f4 xv = __builtin_bit_cast(f4, a);
+#pragma unroll
+        for (int nt = 0; nt < RT; ++nt) {
+          const f4 bv = *reinterpret_cast<const f4 *>(fl + (nt * 16 + li) * KS + kk + 4 * lg);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[nt] = p_mfma_f32(xv[e], bv[e], acc[nt]);
+        }
+      }
+    }
+    if (h == kpt - 1) {
+      // The tile's output rows t*16 .. t*16+15 are one contiguous block of out: the wave
+      // puts its accumulators into its staging region (free once the reads above are done;
+      // LDS operations of a wave complete in order) and writes the block in 16-byte pieces.
+      float *ot = reinterpret_cast<float *>(stg);
+#pragma unroll
+      for (int nt = 0; nt < RT; ++nt) {
+        const int r = nt * 16 + li;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (r < R) ot[(4 * lg + j) * R + r] = acc[nt][j];
+      }
+      const int64_t rows = (M - t * 16) < 16 ? (M - t * 16) : 16;
+      const int nfl = (int)rows * R;
+      float *dst = out + t * 16 * (int64_t)R;
+#pragma unroll
+      for (int e0 = 0; e0 < 16 * RP; e0 += 256) {
+        const int e = e0 + 4 * lane;
+        if (e + 4 <= nfl) {
+          *reinterpret_cast<f4 *>(dst + e) = *reinterpret_cast<const f4 *>(ot + e);
+        } else if (e < nfl) {
+          for (int q = e; q < nfl; ++q) dst[q] = ot[q];
+        }
+      }
+    }
+  };
+  auto adv = [&](int64_t &t, int &h) {
+    if (++h == kpt) {
+      h = 0;
+      t += tstride;
+    }
+  };
+  // piece i lives in buffer i % 3: it is stored to LDS once it has arrived, the buffer is
+  // refilled at once with piece i + 3, and the MFMAs then consume piece i from LDS, so
+  // three pieces are in flight during every compute step
+  u4 b0[LPI], b1[LPI], b2[LPI];
+  int64_t lt = gw, ct = gw;  // load and compute cursors (tile, piece)
+  int lh = 0, ch = 0;
+  // Prologue, in this order: the first batch of factor loads, the first three pieces of X,
+  // then the factor's conversion into LDS.  The conversion waits only for the factor loads
+  // (the older ones), so the X requests stay in flight through it and the barrier.  The
+  // scheduling barriers keep this order, which the waits count on.  A wave without tiles
+  // loads clamped rows and leaves after the barrier.
+  // thread -> column r = tid % RP of the factor and rows k = tid / RP + u * KSTR
+  constexpr int KSTR = kLdsThreads / RP;
+  const int fr = threadIdx.x % RP, fk = threadIdx.x / RP;
+  const int frc = fr < R ? fr : R - 1;
+  auto fac_load = [&](int k) { return F[(int64_t)(k < K ? k : K - 1) * ldl + (int64_t)frc * ldr]; };
+  // Rows k >= Kp go to the padding column Kp, which no MFMA reads: the store is then
+  // unconditional, so every factor load is consumed on every path.
+  auto fac_store = [&](int k, float x) {
+    const float a = (k < K && fr < R) ? x : 0.f;
+    const int kk = k < Kp ? k : Kp;
+    if (BF) {
+      const uint16_t h = p_f2bf(a);
+      hi[fr * KS + kk] = h;
+      lo[fr * KS + kk] = p_f2bf(a - p_bf2f(h));
+    } else {
+      fl[fr * KS + kk] = a;
+    }
+  };
+  float fv[kFB];
+#pragma unroll
+  for (int u = 0; u < kFB; ++u) fv[u] = fac_load(fk + u * KSTR);
+  __builtin_amdgcn_sched_barrier(0);
+  load_piece(b0, lt, lh);
+  adv(lt, lh);
+  __builtin_amdgcn_sched_barrier(0);
+  load_piece(b1, lt, lh);
+  adv(lt, lh);
+  __builtin_amdgcn_sched_barrier(0);
+  load_piece(b2, lt, lh);
+  adv(lt, lh);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int u = 0; u < kFB; ++u) fac_store(fk + u * KSTR, fv[u]);
+  // longer factors: further batches (these waits also cover the X requests above)
+  for (int k0 = kFB * KSTR; k0 < Kp; k0 += kFB * KSTR) {
+#pragma unroll
+    for (int u = 0; u < kFB; ++u) fv[u] = fac_load(k0 + fk + u * KSTR);
+#pragma unroll
+    for (int u = 0; u < kFB; ++u) fac_store(k0 + fk + u * KSTR, fv[u]);
+  }
+  __syncthreads();
+  if (gw >= ntile) return;  // no barrier follows
+  const int64_t np = ((ntile - 1 - gw) / tstride + 1) * kpt;  // pieces of this wave
+  auto step = [&](u4 (&b)[LPI]) {
+    store_piece(b);
+    load_piece(b, lt, lh);
+    adv(lt, lh);
+    __builtin_amdgcn_sched_barrier(0);
+    compute_piece(ct, ch);
+    adv(ct, ch);
+  };
+  // whole rounds of three steps (a single back edge, so the waits stay exact), then the
+  // remaining one or two pieces; the loads issued for pieces past the end read the last
+  // row of X again and are never used
+  int64_t i = 0;
+  for (; i + 3 <= np; i += 3) {
+    step(b0);
+    step(b1);
+    step(b2);
+  }
+  if (i < np) step(b0);
+  if (i + 1 < np) step(b1);
+}
+
 // ------------------------------------------------------------------ launchers
 static nnc_status allow_lds_bytes(const void *kern, size_t bytes) {
   static std::mutex mu;
@@ -343,6 +550,74 @@ size_t pass_mid_lds(bool bf, int RT, int64_t N) {
   return (size_t)(Np * (16 * RT + 4) * 4);
 }
 
+// Row-contiguous last-mode kernel: chunks per piece row (CPR) is the largest of 32, 16, 8
+// whose piece width does not exceed K; the whole LDS (factor + staging) must fit a CU.
+static int g_last_lds = 1;
+void set_last_lds(int on) { g_last_lds = on; }
+constexpr size_t kCuLdsBytes = 160 * 1024;
+
+static int cu_count() {
+  static int n = 0;
+  if (!n) {
+    int dev = 0, c = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && c > 0)
+      n = c;
+    else
+      n = 256;
+  }
+  return n;
+}
+
+size_t last_lds_bytes(bool bf, int RT, int CPR, int64_t K) {
+  const int64_t EPC = bf ? 8 : 4, KC = CPR * EPC;
+  const int64_t Kp = (K + KC - 1) / KC * KC;
+  const int64_t KS = Kp + (bf ? 8 : 4);
+  const int64_t fbytes = bf ? 2 * 16 * RT * KS * 2 : 16 * RT * KS * 4;
+  return (size_t)(fbytes + (int64_t)kLdsWaves * 16 * (CPR * 16 + 16));
+}
+
+static nnc_status launch_last_lds(const void *X, bool bf, int64_t M, int64_t K, const float *F,
+                                  int64_t ldl, int64_t ldr, int64_t R, float *out, hipStream_t s,
+                                  const char **kernel_name) {
+  const int EPC = bf ? 8 : 4;
+  if (K % EPC || K > (1 << 20) || K < 8 * EPC) return NNC_EUNSUPPORTED;
+  const int CPR = K >= 32 * EPC ? 32 : (K >= 16 * EPC ? 16 : 8);
+  const int RT = R <= 16 ? 1 : 2;
+  const size_t lds = last_lds_bytes(bf, RT, CPR, K);
+  if (lds > kCuLdsBytes) return NNC_EUNSUPPORTED;
+  const int64_t tiles = (M + 15) / 16;
+  const int grid = (int)std::min<int64_t>((tiles + kLdsWaves - 1) / kLdsWaves, cu_count());
+#define NNC_LL(BFV, RTV, CPRV)                                                                    \
+  do {                                                                                            \
+    NNC_TRY(allow_lds_bytes(reinterpret_cast<const void *>(ttm_last_lds_k<BFV, RTV, CPRV>), lds)); \
+    hipLaunchKernelGGL((ttm_last_lds_k<BFV, RTV, CPRV>), dim3(grid), dim3(kLdsThreads), lds, s, X, \
+                       M, (int)K, F, ldl, ldr, (int)R, out);                                      \
+  } while (0)
+#define NNC_LL_CPR(BFV, RTV)           \
+  do {                                 \
+    if (CPR == 32)                     \
+      NNC_LL(BFV, RTV, 32);            \
+    else if (CPR == 16)                \
+      NNC_LL(BFV, RTV, 16);            \
+    else                               \
+      NNC_LL(BFV, RTV, 8);             \
+  } while (0)
+  if (bf && RT == 1)
+    NNC_LL_CPR(true, 1);
+  else if (bf)
+    NNC_LL_CPR(true, 2);
+  else if (RT == 1)
+    NNC_LL_CPR(false, 1);
+  else
+    NNC_LL_CPR(false, 2);
+#undef NNC_LL_CPR
+#undef NNC_LL
+  if (kernel_name) *kernel_name = bf ? "ttm_last_lds_bf16" : "ttm_last_lds_f32";
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
 // Returns NNC_EUNSUPPORTED (without recording an error) when the shape does not suit the
 // pipelined kernels, so the caller can fall back.
 nnc_status launch_pass(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64_t Q, const float *F,
@@ -354,6 +629,10 @@ nnc_status launch_pass(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64
   const bool bf = xdt == NNC_BF16;
   const int RT = R <= 16 ? 1 : 2;
   const int waves = kPassThreads / 64;
+  if (Q == 1 && g_last_lds) {
+    const nnc_status st = launch_last_lds(X, bf, P, N, F, ldl, ldr, R, out, s, kernel_name);
+    if (st != NNC_EUNSUPPORTED) return st;
+  }
   if (Q == 1) {
     if (N % (bf ? 8 : 4)) return NNC_EUNSUPPORTED;
     const size_t lds = pass_last_lds(bf, RT, N);

@@ -57,6 +57,36 @@ def test_ttm_bf16_every_mode(shape, R):
         assert err <= 1e-4, (shape, R, n, err)
 
 
+# Last-mode (contraction index contiguous) shapes chosen for the row-contiguous pass kernel:
+# every piece width (64/128/256 k for bf16, 32/64/128 for f32), partial last pieces, fewer
+# rows than one tile, ragged row counts, and enough tiles that waves get 1..3 pieces each.
+LAST_SHAPES = [(5, 64), (77, 520), (45, 136), (1000, 256), (70001, 128), (3000, 512), (33, 40)]
+
+
+@pytest.mark.parametrize("shape", LAST_SHAPES)
+@pytest.mark.parametrize("R", [3, 16, 20, 32])
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+def test_ttm_last_mode_row_contiguous(shape, R, dt):
+    nnc = need_gpu()
+    rng = np.random.default_rng(hash((shape, R, dt)) % 2**32)
+    M, K = shape
+    A = rng.random((K, R)).astype(np.float32)
+    if dt == "bf16":
+        X64 = synth.round_bf16(rng.random(shape))
+        Xd, tol = bf16_dev(X64), 1e-4
+    else:
+        X32 = rng.random(shape).astype(np.float32)
+        X64, Xd, tol = X32.astype(np.float64), dev(X32), 1e-5
+    out = host(nnc.nnc_ttm(Xd, 1, dev(A)))
+    ref = X64 @ A.astype(np.float64)
+    assert out.shape == (M, R)
+    err = rel_fro(out, ref)
+    assert err <= tol, (shape, R, dt, err)
+    # every row individually (a wrong tile or piece shows up even when the total is close)
+    rows = np.linalg.norm(out - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-30)
+    assert rows.max() <= 10 * tol, (shape, R, dt, int(rows.argmax()), rows.max())
+
+
 @pytest.mark.parametrize("dt", ["f32", "bf16"])
 def test_identity_factor_returns_x_bit_exact(dt):
     nnc = need_gpu()
