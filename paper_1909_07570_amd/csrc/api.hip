@@ -14,6 +14,7 @@
 // the Gauss-Seidel factors, so two passes over X per sweep suffice for any d.
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -372,6 +373,7 @@ static nnc_status chain_small(const float *src, int d, int64_t *cur, const int *
 struct SideStream {
   hipStream_t s = nullptr;
   hipEvent_t fork[kMaxDim] = {}, join[kMaxDim] = {};
+  hipEvent_t tail_fork = nullptr, tail_join = nullptr;  // the deferred core step of a sweep
   bool ok = false;
 };
 
@@ -385,20 +387,71 @@ static SideStream *side_stream() {
       if (hipEventCreateWithFlags(&ss.fork[k], hipEventDisableTiming) != hipSuccess) return nullptr;
       if (hipEventCreateWithFlags(&ss.join[k], hipEventDisableTiming) != hipSuccess) return nullptr;
     }
+    if (hipEventCreateWithFlags(&ss.tail_fork, hipEventDisableTiming) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&ss.tail_join, hipEventDisableTiming) != hipSuccess) return nullptr;
     ss.ok = true;
   }
   return &ss;
 }
 
-static nnc_status fused_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, float *G,
-                              float *const *A, double eps, hipStream_t s, PassTimer *tm) {
+// The core step that closes a sweep: core numerator from the last mode's row-block
+// partials, Gram of the last factor, core update, and M for mode 0 of the next sweep.
+static nnc_status core_tail(const TuckerBufs &b, float *G, float *const *A, double eps, hipStream_t s) {
   const TuckerPlan &p = *b.p;
   const int d = p.d;
-  SideStream *ss = side_stream();
-  if (!ss) return fail(NNC_EHIP, "could not create the side stream");
+  NNC_TRY(launch_sum_parts(b.gpart(), (int)mu_rows_blocks(p.N[d - 1]), p.gsize, b.G(2), s));
+  CoreArgsHost h = core_args(b, G, A, eps);
+  h.gram_from = d - 1;
+  h.gram_to = d;
+  h.gram = b.gram();
+  h.gram_parts = (int)mu_rows_blocks(p.N[d - 1]);
+  h.do_core = 1;
+  h.nparts = (int)mu_rows_blocks(p.N[d - 1]);
+  h.next = 0;
+  return launch_core_step(h, s);
+}
+
+// Whether the single-workgroup core steps run on a second stream beside the sweep
+// (NNC_CORE_OVERLAP=1) or in line with it (default).  In a captured graph the runtime puts
+// the branches on different hardware queues, and each dependency between queues has cost
+// more than the overlap saves at the sizes measured so far.
+static bool core_overlap() {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = getenv("NNC_CORE_OVERLAP");
+    v = (e && atoi(e) > 0) ? 1 : 0;
+  }
+  return v == 1;
+}
+
+// Sweep flags (used with the overlap only).  kDeferIn: the previous sweep's core step is still to run; it runs on the side
+// stream next to pass 1 (which needs only the last factor) and mode 0 waits for it.
+// kDeferOut: leave this sweep's core step to the next call (or to core_tail).
+enum { kDeferIn = 1, kDeferOut = 2 };
+
+static nnc_status fused_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, float *G,
+                              float *const *A, double eps, hipStream_t s, PassTimer *tm,
+                              int flags = 0) {
+  const TuckerPlan &p = *b.p;
+  const int d = p.d;
+  const bool ov = core_overlap();
+  SideStream *ss = ov ? side_stream() : nullptr;
+  if (ov && !ss) return fail(NNC_EHIP, "could not create the side stream");
+  if (flags & kDeferIn) {
+    if (ov) {
+      NNC_HIP(hipEventRecord(ss->tail_fork, s));
+      NNC_HIP(hipStreamWaitEvent(ss->s, ss->tail_fork, 0));
+      NNC_TRY(core_tail(b, G, A, eps, ss->s));
+      NNC_HIP(hipEventRecord(ss->tail_join, ss->s));
+    } else {
+      NNC_TRY(core_tail(b, G, A, eps, s));
+    }
+  }
+  // with the overlap, the passes leave one CU to the core step running beside them
+  const int reserve1 = (ov && (flags & kDeferIn)) ? 1 : 0;
   if (tm) NNC_TRY(tm->start(s));
   NNC_TRY(launch_ttm(X, dt, p.size / p.N[d - 1], p.N[d - 1], 1, A[d - 1], p.R[d - 1], 1, p.R[d - 1],
-                     b.P(), s, true));
+                     b.P(), s, true, nullptr, reserve1));
   if (tm) NNC_TRY(tm->stop(s));
   const float *U = b.P();
   for (int n = 0; n < d - 1; ++n) {
@@ -410,20 +463,25 @@ static nnc_status fused_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, 
     memcpy(ycur, cur, sizeof ycur);
     const float *Y = nullptr;
     NNC_TRY(chain_small(U, d, ycur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
-    if (n > 0) NNC_HIP(hipStreamWaitEvent(s, ss->join[n - 1], 0));  // M_n from core step n-1
+    if (ov && n > 0) NNC_HIP(hipStreamWaitEvent(s, ss->join[n - 1], 0));  // M_n from core step n-1
+    if (ov && n == 0 && (flags & kDeferIn)) NNC_HIP(hipStreamWaitEvent(s, ss->tail_join, 0));  // G, M_0
     NNC_TRY(launch_mu_rows(Y, G, A[n], b.M(), prod(p.R, 0, n), p.N[n], prod(p.R, n + 1, d), p.R[n],
                            eps, b.clips(), b.gram(), nullptr, nullptr, s));
-    // core step n on the side stream: Gram of the new A_n and M_{n+1}
-    NNC_HIP(hipEventRecord(ss->fork[n], s));
-    NNC_HIP(hipStreamWaitEvent(ss->s, ss->fork[n], 0));
+    // core step n: Gram of the new A_n and M_{n+1}
     CoreArgsHost h = core_args(b, G, A, eps);
     h.gram_from = n;
     h.gram_to = n + 1;
     h.gram = b.gram();
     h.gram_parts = (int)mu_rows_blocks(p.N[n]);
     h.next = n + 1;
-    NNC_TRY(launch_core_step(h, ss->s));
-    NNC_HIP(hipEventRecord(ss->join[n], ss->s));
+    if (ov) {
+      NNC_HIP(hipEventRecord(ss->fork[n], s));
+      NNC_HIP(hipStreamWaitEvent(ss->s, ss->fork[n], 0));
+      NNC_TRY(launch_core_step(h, ss->s));
+      NNC_HIP(hipEventRecord(ss->join[n], ss->s));
+    } else {
+      NNC_TRY(launch_core_step(h, s));
+    }
     if (n < d - 2) {
       float *Un = b.U(n % 2);
       NNC_TRY(ttm_f32(U, d, cur, n, A[n], p.R[n], Un, s));
@@ -431,7 +489,8 @@ static nnc_status fused_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, 
     }
   }
   if (tm) NNC_TRY(tm->start(s));
-  NNC_TRY(launch_ttm(X, dt, 1, p.N[0], p.size / p.N[0], A[0], p.R[0], 1, p.R[0], b.T(), s, true));
+  NNC_TRY(launch_ttm(X, dt, 1, p.N[0], p.size / p.N[0], A[0], p.R[0], 1, p.R[0], b.T(), s, true,
+                     nullptr, ov ? 1 : 0));
   if (tm) NNC_TRY(tm->stop(s));
   int64_t cur[kMaxDim];
   for (int k = 0; k < d; ++k) cur[k] = (k == 0) ? p.R[0] : p.N[k];
@@ -439,19 +498,10 @@ static nnc_status fused_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, 
   for (int k = 1; k < d - 1; ++k) modes[nm++] = k;
   const float *Y = nullptr;
   NNC_TRY(chain_small(b.T(), d, cur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
-  NNC_HIP(hipStreamWaitEvent(s, ss->join[d - 2], 0));  // M_{d-1}; joins the side stream
+  if (ov) NNC_HIP(hipStreamWaitEvent(s, ss->join[d - 2], 0));  // M_{d-1}; joins the side stream
   NNC_TRY(launch_mu_rows(Y, G, A[d - 1], b.M(), prod(p.R, 0, d - 1), p.N[d - 1], 1, p.R[d - 1], eps,
                          b.clips(), b.gram(), b.gpart(), nullptr, s));
-  NNC_TRY(launch_sum_parts(b.gpart(), (int)mu_rows_blocks(p.N[d - 1]), p.gsize, b.G(2), s));
-  CoreArgsHost h = core_args(b, G, A, eps);
-  h.gram_from = d - 1;
-  h.gram_to = d;
-  h.gram = b.gram();
-  h.gram_parts = (int)mu_rows_blocks(p.N[d - 1]);
-  h.do_core = 1;
-  h.nparts = (int)mu_rows_blocks(p.N[d - 1]);
-  h.next = 0;
-  NNC_TRY(launch_core_step(h, s));
+  if (!(flags & kDeferOut)) NNC_TRY(core_tail(b, G, A, eps, s));
   return NNC_OK;
 }
 
@@ -644,8 +694,10 @@ nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *d
     if (ta >= tb) return NNC_OK;
     const bool every = o.objective_every > 0;
     if (!graphs) {
+      const bool rot = p.fast && !every && tb - ta >= 2 && core_overlap();
       for (int t = ta; t < tb; ++t) {
-        NNC_TRY(p.fast ? fused_sweep(b, Xs, dts, core, factors, eps, s, tm)
+        const int flags = rot ? ((t > ta ? kDeferIn : 0) | (t < tb - 1 ? kDeferOut : 0)) : 0;
+        NNC_TRY(p.fast ? fused_sweep(b, Xs, dts, core, factors, eps, s, tm, flags)
                        : tucker_sweep(b, Xs, dts, core, factors, eps, s, tm));
         if (every && (t + 1) % o.objective_every == 0) {
           NNC_TRY(tucker_resid(b, xres, dres, core, factors, s));
@@ -656,6 +708,10 @@ nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *d
       }
       return NNC_OK;
     }
+    // Fast path without intermediate objectives: sweeps as rotated units (see fused_sweep),
+    // captured as three graphs: first (defers its core step), middle (runs the previous
+    // one beside pass 1 and defers its own), last (runs both).
+    const bool rotate = p.fast && !every && tb - ta >= 2 && core_overlap();
     hipStream_t cs = s;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     if (!s) {
@@ -666,29 +722,57 @@ nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *d
       NNC_HIP(hipEventRecord(ev_in, s));
       NNC_HIP(hipStreamWaitEvent(cs, ev_in, 0));
     }
-    hipGraph_t g = nullptr;
-    hipGraphExec_t ge = nullptr;
-    NNC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    nnc_status st = p.fast ? fused_sweep(b, Xs, dts, core, factors, eps, cs, nullptr)
-                           : tucker_sweep(b, Xs, dts, core, factors, eps, cs, nullptr);
-    hipError_t ec = hipStreamEndCapture(cs, &g);
-    if (st != NNC_OK) {
-      if (g) (void)hipGraphDestroy(g);
-      return st;
-    }
-    if (ec != hipSuccess) return fail(NNC_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
-    NNC_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
-    for (int t = ta; t < tb; ++t) {
-      NNC_HIP(hipGraphLaunch(ge, cs));
-      if (every && (t + 1) % o.objective_every == 0) {
-        NNC_TRY(tucker_resid(b, xres, dres, core, factors, cs));
-        double red[2];
-        NNC_TRY(read_red(b, red, cs));
-        rep->objective_history[hist++] = rel_of(red);
+    // capture one sweep with the given flags into an executable graph
+    auto capture = [&](int flags, hipGraphExec_t *ge) -> nnc_status {
+      hipGraph_t g = nullptr;
+      NNC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      nnc_status st = p.fast ? fused_sweep(b, Xs, dts, core, factors, eps, cs, nullptr, flags)
+                             : tucker_sweep(b, Xs, dts, core, factors, eps, cs, nullptr);
+      hipError_t ec = hipStreamEndCapture(cs, &g);
+      if (st != NNC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
       }
+      if (ec != hipSuccess) return fail(NNC_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
+      const hipError_t ei = hipGraphInstantiate(ge, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) return fail(NNC_EHIP, "graph instantiation failed: %s", hipGetErrorString(ei));
+      return NNC_OK;
+    };
+    if (rotate) {
+      hipGraphExec_t gf = nullptr, gm = nullptr, gl = nullptr;
+      nnc_status st = capture(kDeferOut, &gf);
+      if (st == NNC_OK && tb - ta > 2) st = capture(kDeferIn | kDeferOut, &gm);
+      if (st == NNC_OK) st = capture(kDeferIn, &gl);
+      if (st == NNC_OK) {
+        if (hipGraphLaunch(gf, cs) != hipSuccess) st = fail(NNC_EHIP, "graph launch failed");
+        for (int t = ta + 1; st == NNC_OK && t < tb - 1; ++t)
+          if (hipGraphLaunch(gm, cs) != hipSuccess) st = fail(NNC_EHIP, "graph launch failed");
+        if (st == NNC_OK && hipGraphLaunch(gl, cs) != hipSuccess) st = fail(NNC_EHIP, "graph launch failed");
+      }
+      // an executable graph is destroyed only after its launches have finished: its
+      // resources must not be released (and reused by the next instantiation) while the
+      // queued launches still read them
+      if (hipStreamSynchronize(cs) != hipSuccess && st == NNC_OK)
+        st = fail(NNC_EHIP, "stream synchronization after the sweeps failed");
+      for (hipGraphExec_t e : {gf, gm, gl})
+        if (e) (void)hipGraphExecDestroy(e);
+      NNC_TRY(st);
+    } else {
+      hipGraphExec_t ge = nullptr;
+      NNC_TRY(capture(0, &ge));
+      for (int t = ta; t < tb; ++t) {
+        NNC_HIP(hipGraphLaunch(ge, cs));
+        if (every && (t + 1) % o.objective_every == 0) {
+          NNC_TRY(tucker_resid(b, xres, dres, core, factors, cs));
+          double red[2];
+          NNC_TRY(read_red(b, red, cs));
+          rep->objective_history[hist++] = rel_of(red);
+        }
+      }
+      NNC_HIP(hipStreamSynchronize(cs));  // see above: no destruction while launches are queued
+      NNC_HIP(hipGraphExecDestroy(ge));
     }
-    NNC_HIP(hipGraphExecDestroy(ge));
-    NNC_HIP(hipGraphDestroy(g));
     if (!s) {
       NNC_HIP(hipEventRecord(ev_out, cs));
       NNC_HIP(hipStreamWaitEvent(s, ev_out, 0));

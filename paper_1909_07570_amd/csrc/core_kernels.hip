@@ -1,0 +1,373 @@
+// Core-space steps of a sweep spread over several workgroups (cores up to kSliceMax entries).
+//
+// With S_k = A_k^T A_k (R_k x R_k, symmetric), a sweep needs, between factor updates,
+//   M_n   = unfold_n(G x_{k != n} S_k) unfold_n(G)^T          (R_n x R_n, used by mode n)
+// and at its end the core update with den_G = G x_0 S_0 x_1 ... x_{d-1} S_{d-1}.
+// Both split along one mode of the core:
+//   mrows_k : block a builds H_a = G[.., a, ..] x_{k != n} S_k (the slice with mode n fixed
+//             to a, contracted with the other Grams) and row a of M_n, M_n[a][b] = <H_a, G_b>;
+//   denA_k  : block i builds T_i = G[i, ..] x_1 S_1 ... x_{d-1} S_{d-1} (mode-0 slices);
+//   denB_k  : block i forms den[i] = sum_i' S_0[i'][i] T_i' and updates G[i] by the
+//             multiplicative rule with the core numerator.
+// A step that follows a factor update also needs that factor's new Gram: every block that
+// uses it sums the factor's row-block partials (gram[b][R][R], Gram of rows [8b, 8b+8))
+// itself, in one fixed order, and block 0 stores it.  The same order serves the start of a
+// fit, so a fit resumed from its outputs continues bit for bit.
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+
+#include "nnc_internal.h"
+
+namespace nnc {
+
+constexpr int kSliceThreads = 256;
+constexpr int kSliceMax = 16384;  // cores up to this many entries use these kernels
+
+struct SliceArgs {
+  int d;
+  int R[kMaxDim];
+  int gsize;
+  const float *G;      // core (read)
+  float *Gout;         // denB_k: updated core (same as G)
+  float *S[kMaxDim];   // Grams (global)
+  int gram;            // mode whose Gram is summed from partials here, or -1
+  const float *gram_part;
+  int gram_parts;
+  int n;               // mrows_k: mode of M; denA/denB: unused
+  float *M;            // mrows_k output (R_n x R_n)
+  float *T;            // denA_k output / denB_k input (gsize floats)
+  const float *numG;   // denB_k: core numerator
+  double eps;
+  unsigned long long *clips;
+};
+
+// LDS layout (floats): Sl[d][RM*RM] | red[kSliceThreads*4] | G[gsize] (mrows) | H0 | H1
+template <int RM>
+struct SliceLds {
+  static constexpr int kRed = kSliceThreads * 4;
+  static size_t bytes(int d, int gsize, int slice, bool whole_core) {
+    return sizeof(float) * ((size_t)d * RM * RM + kRed + (whole_core ? gsize : 0) + 2 * (size_t)slice);
+  }
+};
+
+// Grams into LDS (row stride RM, zero padding); the gram mode's Gram is summed from the
+// partials (entries in groups of 4 when R^2 is a multiple of 4, else one by one; each group
+// by kSliceThreads / groups threads over contiguous ranges of partials, added in order).
+template <int RM>
+static __device__ void stage_grams(const SliceArgs &a, float *Sl, float *red) {
+  const int tid = threadIdx.x;
+  for (int k = 0; k < a.d; ++k) {
+    if (k == a.gram) continue;
+    const int Rk = a.R[k];
+    for (int e = tid; e < RM * RM; e += kSliceThreads) {
+      const int l = e / RM, r = e - (e / RM) * RM;
+      Sl[k * RM * RM + e] = (l < Rk && r < Rk) ? a.S[k][l * Rk + r] : 0.f;
+    }
+  }
+  if (a.gram < 0) return;
+  const int k = a.gram, Rk = a.R[k], RR = Rk * Rk;
+  float *Sg = Sl + k * RM * RM;
+  for (int e = tid; e < RM * RM; e += kSliceThreads)  // padding only: the rest is written below
+    if (e / RM >= Rk || e % RM >= Rk) Sg[e] = 0.f;
+  const bool vec = (RR % 4) == 0;
+  const int W = vec ? 4 : 1;           // entries per group
+  const int ngrp = RR / W;
+  const int nch = ngrp >= kSliceThreads ? 1 : kSliceThreads / ngrp;
+  const int P = a.gram_parts;
+  constexpr int GPT = (RM * RM + kSliceThreads - 1) / kSliceThreads;  // groups per thread (nch == 1)
+  float4 acc[GPT];
+  const int ch = tid / (nch > 1 ? ngrp : kSliceThreads);
+  // thread's groups: nch > 1 -> group tid % ngrp, chunk tid / ngrp; nch == 1 -> groups tid + j*T
+#pragma unroll
+  for (int j = 0; j < GPT; ++j) acc[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (ch < nch) {
+    const int b0 = (int)((int64_t)P * ch / nch), b1 = (int)((int64_t)P * (ch + 1) / nch);
+#pragma unroll
+    for (int j = 0; j < GPT; ++j) {
+      const int grp = nch > 1 ? tid % ngrp : tid + j * kSliceThreads;
+      if ((nch > 1 && j > 0) || grp >= ngrp) continue;
+      float4 s4 = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int bb = b0; bb < b1; bb += 16) {
+        float4 v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int b = bb + u < b1 ? bb + u : b1 - 1;
+          const float *src = a.gram_part + (int64_t)b * RR + grp * W;
+          v[u] = vec ? *reinterpret_cast<const float4 *>(src) : make_float4(src[0], 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (bb + u < b1) {
+            s4.x += v[u].x;
+            s4.y += v[u].y;
+            s4.z += v[u].z;
+            s4.w += v[u].w;
+          }
+      }
+      acc[j] = s4;
+    }
+  }
+  auto put = [&](int grp, float4 v) {
+    const float vv[4] = {v.x, v.y, v.z, v.w};
+    for (int w = 0; w < W; ++w) {
+      const int e = grp * W + w;
+      Sg[(e / Rk) * RM + e % Rk] = vv[w];
+      if (blockIdx.x == 0) a.S[k][e] = vv[w];
+    }
+  };
+  if (nch > 1) {
+    if (ch < nch) reinterpret_cast<float4 *>(red)[tid] = acc[0];
+    __syncthreads();
+    if (tid < ngrp) {
+      float4 s4 = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int c = 0; c < nch; ++c) {
+        const float4 v = reinterpret_cast<const float4 *>(red)[c * ngrp + tid];
+        s4.x += v.x;
+        s4.y += v.y;
+        s4.z += v.z;
+        s4.w += v.w;
+      }
+      put(tid, s4);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < GPT; ++j) {
+      const int grp = tid + j * kSliceThreads;
+      if (grp < ngrp) put(grp, acc[j]);
+    }
+  }
+}
+
+// out[p][r][q] = sum_l S[l][r] in[p][l][q] on an LDS tensor whose mode of size Rk has pre
+// entries before it and post after it; one output per thread and step.
+template <int RM>
+static __device__ void slice_ttm(const float *in, float *out, int pre, int Rk, int post,
+                                 const float *S) {
+  const int total = pre * Rk * post;
+  for (int o = threadIdx.x; o < total; o += kSliceThreads) {
+    const int q = o % post, pr = o / post;
+    const int r = pr % Rk, p = pr / Rk;
+    const float *src = in + p * Rk * post + q;
+    float acc = 0.f;
+    for (int l = 0; l < Rk; ++l) acc = fmaf(S[l * RM + r], src[l * post], acc);
+    out[o] = acc;
+  }
+}
+
+// Contract the slice (modes of the core except `skip`, kept in order) with the Grams of its
+// modes; returns the LDS buffer holding the result (H0 or H1).
+template <int RM>
+static __device__ float *contract_slice(const SliceArgs &a, int skip, const float *Sl, float *H0,
+                                        float *H1) {
+  int dims[kMaxDim], nd = 0;
+  for (int k = 0; k < a.d; ++k)
+    if (k != skip) dims[nd++] = a.R[k];
+  float *cur = H0, *nxt = H1;
+  int j = 0;
+  for (int k = 0; k < a.d; ++k) {
+    if (k == skip) continue;
+    int pre = 1, post = 1;
+    for (int t = 0; t < j; ++t) pre *= dims[t];
+    for (int t = j + 1; t < nd; ++t) post *= dims[t];
+    slice_ttm<RM>(cur, nxt, pre, dims[j], post, Sl + k * RM * RM);
+    __syncthreads();
+    float *t2 = cur;
+    cur = nxt;
+    nxt = t2;
+    ++j;
+  }
+  return cur;
+}
+
+// Row a = blockIdx.x of M_n (and, with a.gram >= 0, the new Gram of mode a.gram).  With
+// a.n < 0 only the Gram is formed (one block).
+template <int RM>
+__global__ __launch_bounds__(kSliceThreads) void mrows_k(SliceArgs a) {
+  extern __shared__ __attribute__((aligned(16))) float lds[];
+  const int d = a.d, tid = threadIdx.x;
+  float *Sl = lds;
+  float *red = Sl + d * RM * RM;
+  float *G = red + SliceLds<RM>::kRed;
+  const int n = a.n;
+  const int Rn = n >= 0 ? a.R[n] : 1;
+  const int slice = a.gsize / Rn;
+  float *H0 = G + a.gsize, *H1 = H0 + slice;
+  // the whole core (for the dot products) and the Grams
+  if (n >= 0)
+    for (int e0 = 0; e0 < a.gsize; e0 += 32 * kSliceThreads) {
+      float v[32];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) {
+        const int e = e0 + tid + u * kSliceThreads;
+        v[u] = a.G[e < a.gsize ? e : a.gsize - 1];
+      }
+#pragma unroll
+      for (int u = 0; u < 32; ++u) {
+        const int e = e0 + tid + u * kSliceThreads;
+        if (e < a.gsize) G[e] = v[u];
+      }
+    }
+  stage_grams<RM>(a, Sl, red);
+  __syncthreads();
+  if (n < 0) return;
+  const int ia = blockIdx.x;
+  int pre = 1, post = 1;
+  for (int k = 0; k < n; ++k) pre *= a.R[k];
+  for (int k = n + 1; k < d; ++k) post *= a.R[k];
+  // slice with mode n fixed to ia, as [pre][post]
+  for (int c = tid; c < slice; c += kSliceThreads) {
+    const int pc = c / post, qc = c - (c / post) * post;
+    H0[c] = G[(pc * Rn + ia) * post + qc];
+  }
+  __syncthreads();
+  const float *H = contract_slice<RM>(a, n, Sl, H0, H1);
+  // M[ia][b] = sum_c H[c] G[(pc * Rn + b) * post + qc]; thread (b, chunk), chunks added in order
+  const int nchunk = kSliceThreads / Rn;
+  const int b = tid % Rn, ch = tid / Rn;
+  float acc = 0.f;
+  if (ch < nchunk) {
+    const int c0 = (int)((int64_t)slice * ch / nchunk), c1 = (int)((int64_t)slice * (ch + 1) / nchunk);
+    int pc = c0 / post, qc = c0 - (c0 / post) * post;
+    for (int c = c0; c < c1; ++c) {
+      acc = fmaf(H[c], G[(pc * Rn + b) * post + qc], acc);
+      if (++qc == post) {
+        qc = 0;
+        ++pc;
+      }
+    }
+  }
+  red[tid] = ch < nchunk ? acc : 0.f;
+  __syncthreads();
+  if (tid < Rn) {
+    float s = 0.f;
+    for (int c = 0; c < nchunk; ++c) s += red[c * Rn + tid];
+    a.M[ia * Rn + tid] = s;
+  }
+}
+
+// T_i = G[i, ..] x_1 S_1 ... x_{d-1} S_{d-1} for i = blockIdx.x (and the new Gram of a.gram).
+template <int RM>
+__global__ __launch_bounds__(kSliceThreads) void denA_k(SliceArgs a) {
+  extern __shared__ __attribute__((aligned(16))) float lds[];
+  const int d = a.d, tid = threadIdx.x;
+  float *Sl = lds;
+  float *red = Sl + d * RM * RM;
+  const int slice = a.gsize / a.R[0];
+  float *H0 = red + SliceLds<RM>::kRed, *H1 = H0 + slice;
+  const int i = blockIdx.x;
+  for (int c = tid; c < slice; c += kSliceThreads) H0[c] = a.G[(int64_t)i * slice + c];
+  stage_grams<RM>(a, Sl, red);
+  __syncthreads();
+  const float *T = contract_slice<RM>(a, 0, Sl, H0, H1);
+  for (int c = tid; c < slice; c += kSliceThreads) a.T[(int64_t)i * slice + c] = T[c];
+}
+
+// den[i] = sum_i' S_0[i'][i] T_i' and G[i] <- G[i] * numG[i] / max(den[i], eps) (FP64
+// division), for i = blockIdx.x; counts the clipped denominators.
+__global__ __launch_bounds__(kSliceThreads) void denB_k(SliceArgs a) {
+  __shared__ float s0[32];
+  __shared__ unsigned int nclip;
+  const int tid = threadIdx.x, i = blockIdx.x;
+  const int R0 = a.R[0];
+  const int slice = a.gsize / R0;
+  if (tid < R0) s0[tid] = a.S[0][tid * R0 + i];  // S_0[i'][i], i' = tid
+  if (tid == 0) nclip = 0;
+  __syncthreads();
+  unsigned int mine = 0;
+  for (int c = tid; c < slice; c += kSliceThreads) {
+    float den = 0.f;
+    for (int ip = 0; ip < R0; ++ip) den = fmaf(s0[ip], a.T[(int64_t)ip * slice + c], den);
+    double dd = (double)den;
+    if (dd < a.eps) {
+      dd = a.eps;
+      ++mine;
+    }
+    const int64_t e = (int64_t)i * slice + c;
+    a.Gout[e] = (float)(((double)a.G[e] * (double)a.numG[e]) / dd);
+  }
+  if (mine) atomicAdd(&nclip, mine);
+  __syncthreads();
+  if (tid == 0 && nclip) atomicAdd(a.clips, (unsigned long long)nclip);
+}
+
+static nnc_status allow_slice_lds(const void *kern, size_t bytes) {
+  static std::mutex mu;
+  static std::map<const void *, size_t> done;
+  if (bytes <= 64 * 1024) return NNC_OK;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = done.find(kern);
+  if (it != done.end() && it->second >= bytes) return NNC_OK;
+  NNC_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  done[kern] = bytes;
+  return NNC_OK;
+}
+
+template <int RM>
+static nnc_status slice_step(const CoreArgsHost &h, hipStream_t s) {
+  SliceArgs a;
+  memset(&a, 0, sizeof a);
+  a.d = h.d;
+  a.gsize = 1;
+  for (int k = 0; k < kMaxDim; ++k) {
+    a.R[k] = k < h.d ? (int)h.R[k] : 1;
+    a.S[k] = k < h.d ? h.S[k] : nullptr;
+  }
+  for (int k = 0; k < h.d; ++k) a.gsize *= a.R[k];
+  a.G = h.G;
+  a.gram = h.gram_to > h.gram_from ? h.gram_from : -1;
+  a.gram_part = h.gram;
+  a.gram_parts = h.gram_parts;
+  a.eps = h.eps;
+  a.clips = h.clips;
+  if (h.do_core) {
+    // T = G x_1 S_1 ... (the new Gram formed on the way), then the update
+    a.T = h.t0;
+    a.n = -1;
+    const int slice0 = a.gsize / a.R[0];
+    const size_t la = SliceLds<RM>::bytes(a.d, a.gsize, slice0, false);
+    NNC_TRY(allow_slice_lds(reinterpret_cast<const void *>(denA_k<RM>), la));
+    hipLaunchKernelGGL(denA_k<RM>, dim3(a.R[0]), dim3(kSliceThreads), la, s, a);
+    SliceArgs b = a;
+    b.gram = -1;
+    b.numG = h.numG;
+    b.Gout = h.G;
+    hipLaunchKernelGGL(denB_k, dim3(a.R[0]), dim3(kSliceThreads), 0, s, b);
+    a.gram = -1;  // its Gram is stored now
+  }
+  if (h.next >= 0 || a.gram >= 0) {
+    a.n = h.next;
+    a.M = h.M;
+    const int Rn = h.next >= 0 ? a.R[h.next] : 1;
+    const size_t lm = SliceLds<RM>::bytes(a.d, a.gsize, a.gsize / Rn, h.next >= 0);
+    NNC_TRY(allow_slice_lds(reinterpret_cast<const void *>(mrows_k<RM>), lm));
+    hipLaunchKernelGGL(mrows_k<RM>, dim3(h.next >= 0 ? Rn : 1), dim3(kSliceThreads), lm, s, a);
+  }
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+// Returns NNC_EUNSUPPORTED (no error recorded) when the core is too large for these kernels.
+nnc_status launch_slice_step(const CoreArgsHost &h, hipStream_t s) {
+  int64_t gsize = 1;
+  int maxr = 1;
+  for (int k = 0; k < h.d; ++k) {
+    gsize *= h.R[k];
+    maxr = std::max(maxr, (int)h.R[k]);
+  }
+  if (gsize > kSliceMax || maxr > 32 || h.gram_to - h.gram_from > 1) return NNC_EUNSUPPORTED;
+  // LDS of the largest launch (the whole core and two slices at worst)
+  const int RM = maxr <= 8 ? 8 : (maxr <= 16 ? 16 : (maxr <= 24 ? 24 : 32));
+  int64_t worst = 0;
+  for (int k = 0; k < h.d; ++k) worst = std::max(worst, gsize / h.R[k]);
+  const int64_t need = 4 * ((int64_t)h.d * RM * RM + 4 * kSliceThreads + gsize + 2 * worst);
+  if (need > 160 * 1024) return NNC_EUNSUPPORTED;
+  if (maxr <= 8) return slice_step<8>(h, s);
+  if (maxr <= 16) return slice_step<16>(h, s);
+  if (maxr <= 24) return slice_step<24>(h, s);
+  return slice_step<32>(h, s);
+}
+
+}  // namespace nnc

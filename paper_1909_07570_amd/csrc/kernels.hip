@@ -14,6 +14,8 @@
 #include <mutex>
 #include <map>
 
+#include <algorithm>
+
 #include "nnc_internal.h"
 
 namespace nnc {
@@ -383,11 +385,14 @@ static nnc_status allow_big_lds(const void *kern, size_t bytes) {
 }
 
 template <typename... KArgs, typename... Args>
-static nnc_status launch_stream(void (*kern)(KArgs...), size_t lds, int64_t tiles, hipStream_t s,
-                                Args... args) {
+static nnc_status launch_stream(void (*kern)(KArgs...), size_t lds, int64_t tiles, int reserve,
+                                hipStream_t s, Args... args) {
   NNC_TRY(allow_big_lds(reinterpret_cast<const void *>(kern), lds));
   const int waves = kTtmThreads / 64;
-  const int grid = grid_for(tiles, waves, kStreamBlocks);
+  int grid = grid_for(tiles, waves, kStreamBlocks);
+  // a CU stays free only if the grid fits one block per CU; with more blocks per CU the
+  // dispatcher leaves no CU empty anyway, so the grid is not cut
+  if (reserve > 0 && grid <= device_cu_count()) grid = std::max(1, std::min(grid, device_cu_count() - reserve));
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kTtmThreads), lds, s, static_cast<KArgs>(args)...);
   return NNC_OK;
 }
@@ -398,12 +403,12 @@ void set_use_pipe(int on) { g_use_pipe = on; }
 
 nnc_status launch_ttm(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64_t Q, const float *F,
                       int64_t ldl, int64_t ldr, int64_t R, float *out, hipStream_t s,
-                      bool allow_mfma, const char **kernel_name) {
+                      bool allow_mfma, const char **kernel_name, int reserve_cus) {
   const char *name = "ttm_generic";
   const int64_t total_rows = P * N * Q;
   if (total_rows == 0 || R == 0) return NNC_OK;
   if (allow_mfma && g_use_pipe) {
-    const nnc_status st = launch_pass(X, xdt, P, N, Q, F, ldl, ldr, R, out, s, kernel_name);
+    const nnc_status st = launch_pass(X, xdt, P, N, Q, F, ldl, ldr, R, out, s, kernel_name, reserve_cus);
     if (st != NNC_EUNSUPPORTED) return st;
   }
   const bool small_r = R <= 32;
@@ -420,9 +425,9 @@ nnc_status launch_ttm(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64_
         const size_t lds = (size_t)Kp * (16 * RT + 4) * sizeof(float);
         if (lds <= 96 * 1024) {
           if (RT == 1)
-            NNC_TRY(launch_stream(ttm_last_f32_k<1>, lds, tiles, s, X, M, K, F, ldl, ldr, (int)R, out));
+            NNC_TRY(launch_stream(ttm_last_f32_k<1>, lds, tiles, reserve_cus, s, X, M, K, F, ldl, ldr, (int)R, out));
           else
-            NNC_TRY(launch_stream(ttm_last_f32_k<2>, lds, tiles, s, X, M, K, F, ldl, ldr, (int)R, out));
+            NNC_TRY(launch_stream(ttm_last_f32_k<2>, lds, tiles, reserve_cus, s, X, M, K, F, ldl, ldr, (int)R, out));
           name = "ttm_last_f32";
           done = true;
         }
@@ -431,9 +436,9 @@ nnc_status launch_ttm(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64_
         const size_t lds = (size_t)2 * (16 * RT) * (Kp + 8) * sizeof(uint16_t);
         if (lds <= 96 * 1024) {
           if (RT == 1)
-            NNC_TRY(launch_stream(ttm_last_bf16_k<1, true>, lds, tiles, s, X, M, K, F, ldl, ldr, (int)R, out));
+            NNC_TRY(launch_stream(ttm_last_bf16_k<1, true>, lds, tiles, reserve_cus, s, X, M, K, F, ldl, ldr, (int)R, out));
           else
-            NNC_TRY(launch_stream(ttm_last_bf16_k<2, true>, lds, tiles, s, X, M, K, F, ldl, ldr, (int)R, out));
+            NNC_TRY(launch_stream(ttm_last_bf16_k<2, true>, lds, tiles, reserve_cus, s, X, M, K, F, ldl, ldr, (int)R, out));
           name = "ttm_last_bf16";
           done = true;
         }
@@ -445,9 +450,9 @@ nnc_status launch_ttm(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64_
         const int64_t tiles = P * ((Q + 63) / 64);
         if (lds <= 96 * 1024) {
           if (RT == 1)
-            NNC_TRY(launch_stream(ttm_mid_f32_k<1>, lds, tiles, s, X, P, N, Q, F, ldl, ldr, (int)R, out));
+            NNC_TRY(launch_stream(ttm_mid_f32_k<1>, lds, tiles, reserve_cus, s, X, P, N, Q, F, ldl, ldr, (int)R, out));
           else
-            NNC_TRY(launch_stream(ttm_mid_f32_k<2>, lds, tiles, s, X, P, N, Q, F, ldl, ldr, (int)R, out));
+            NNC_TRY(launch_stream(ttm_mid_f32_k<2>, lds, tiles, reserve_cus, s, X, P, N, Q, F, ldl, ldr, (int)R, out));
           name = "ttm_mid_f32";
           done = true;
         }
@@ -457,9 +462,9 @@ nnc_status launch_ttm(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64_
         const int64_t tiles = P * ((Q + 127) / 128);
         if (lds <= 96 * 1024) {
           if (RT == 1)
-            NNC_TRY(launch_stream(ttm_mid_bf16_k<1, true>, lds, tiles, s, X, P, N, Q, F, ldl, ldr, (int)R, out));
+            NNC_TRY(launch_stream(ttm_mid_bf16_k<1, true>, lds, tiles, reserve_cus, s, X, P, N, Q, F, ldl, ldr, (int)R, out));
           else
-            NNC_TRY(launch_stream(ttm_mid_bf16_k<2, true>, lds, tiles, s, X, P, N, Q, F, ldl, ldr, (int)R, out));
+            NNC_TRY(launch_stream(ttm_mid_bf16_k<2, true>, lds, tiles, reserve_cus, s, X, P, N, Q, F, ldl, ldr, (int)R, out));
           name = "ttm_mid_bf16";
           done = true;
         }

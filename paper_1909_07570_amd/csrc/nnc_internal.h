@@ -35,15 +35,19 @@ nnc_status fail(nnc_status st, const char *fmt, ...);
 // out[p][r][q] = sum_l F(l, r) * X[p][l][q], F(l, r) = F[l*ldl + r*ldr];
 // X is [P][N][Q] of dtype xdt; out is [P][R][Q] float.  Chooses an MFMA kernel when the
 // shape allows (allow_mfma) and a general kernel otherwise.
+// reserve_cus > 0 keeps the X-streaming kernels off that many CUs, so that a kernel on
+// another stream (the single-workgroup core step) finds a whole CU free while they run.
 nnc_status launch_ttm(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64_t Q, const float *F,
                       int64_t ldl, int64_t ldr, int64_t R, float *out, hipStream_t s,
-                      bool allow_mfma, const char **kernel_name = nullptr);
+                      bool allow_mfma, const char **kernel_name = nullptr, int reserve_cus = 0);
 
 // Software-pipelined X-streaming contractions (pass_kernels.hip).  Returns NNC_EUNSUPPORTED
 // without recording an error when the shape does not suit them.
 nnc_status launch_pass(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64_t Q, const float *F,
                        int64_t ldl, int64_t ldr, int64_t R, float *out, hipStream_t s,
-                       const char **kernel_name);
+                       const char **kernel_name, int reserve_cus);
+// Compute units of the current device (queried once).
+int device_cu_count();
 
 // out[i][j] = sum_{p<pre, q<post} U[(p*I+i)*post+q] * V[(p*J+j)*post+q]
 nnc_status launch_contract_except(const float *U, const float *V, int64_t pre, int64_t I, int64_t J,

@@ -556,7 +556,7 @@ static int g_last_lds = 1;
 void set_last_lds(int on) { g_last_lds = on; }
 constexpr size_t kCuLdsBytes = 160 * 1024;
 
-static int cu_count() {
+int device_cu_count() {
   static int n = 0;
   if (!n) {
     int dev = 0, c = 0;
@@ -579,7 +579,7 @@ size_t last_lds_bytes(bool bf, int RT, int CPR, int64_t K) {
 
 static nnc_status launch_last_lds(const void *X, bool bf, int64_t M, int64_t K, const float *F,
                                   int64_t ldl, int64_t ldr, int64_t R, float *out, hipStream_t s,
-                                  const char **kernel_name) {
+                                  const char **kernel_name, int reserve) {
   const int EPC = bf ? 8 : 4;
   if (K % EPC || K > (1 << 20) || K < 8 * EPC) return NNC_EUNSUPPORTED;
   const int CPR = K >= 32 * EPC ? 32 : (K >= 16 * EPC ? 16 : 8);
@@ -587,7 +587,8 @@ static nnc_status launch_last_lds(const void *X, bool bf, int64_t M, int64_t K, 
   const size_t lds = last_lds_bytes(bf, RT, CPR, K);
   if (lds > kCuLdsBytes) return NNC_EUNSUPPORTED;
   const int64_t tiles = (M + 15) / 16;
-  const int grid = (int)std::min<int64_t>((tiles + kLdsWaves - 1) / kLdsWaves, cu_count());
+  const int grid = (int)std::max<int64_t>(
+      1, std::min<int64_t>((tiles + kLdsWaves - 1) / kLdsWaves, device_cu_count() - std::max(reserve, 0)));
 #define NNC_LL(BFV, RTV, CPRV)                                                                    \
   do {                                                                                            \
     NNC_TRY(allow_lds_bytes(reinterpret_cast<const void *>(ttm_last_lds_k<BFV, RTV, CPRV>), lds)); \
@@ -622,7 +623,7 @@ static nnc_status launch_last_lds(const void *X, bool bf, int64_t M, int64_t K, 
 // pipelined kernels, so the caller can fall back.
 nnc_status launch_pass(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64_t Q, const float *F,
                        int64_t ldl, int64_t ldr, int64_t R, float *out, hipStream_t s,
-                       const char **kernel_name) {
+                       const char **kernel_name, int reserve_cus) {
   if (R > 32 || R < 1) return NNC_EUNSUPPORTED;
   if ((reinterpret_cast<uintptr_t>(X) & 15u) || (reinterpret_cast<uintptr_t>(out) & 15u))
     return NNC_EUNSUPPORTED;
@@ -630,7 +631,7 @@ nnc_status launch_pass(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64
   const int RT = R <= 16 ? 1 : 2;
   const int waves = kPassThreads / 64;
   if (Q == 1 && g_last_lds) {
-    const nnc_status st = launch_last_lds(X, bf, P, N, F, ldl, ldr, R, out, s, kernel_name);
+    const nnc_status st = launch_last_lds(X, bf, P, N, F, ldl, ldr, R, out, s, kernel_name, reserve_cus);
     if (st != NNC_EUNSUPPORTED) return st;
   }
   if (Q == 1) {

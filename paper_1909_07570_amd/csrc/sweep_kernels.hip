@@ -361,7 +361,7 @@ struct CoreArgs {
   int gsize;
 };
 
-constexpr int kCoreThreads = 1024;
+constexpr int kCoreThreads = 512;
 constexpr int kCoreLdsMax = 8192;  // cores up to this many entries are kept in LDS
 
 static __device__ inline void phase_sync(bool global) {
@@ -370,10 +370,13 @@ static __device__ inline void phase_sync(bool global) {
 }
 
 // out = in x_k S (S symmetric R_k x R_k, stored with row stride RM and zero padding),
-// core-shaped; one thread per (p, q, group of 4 output columns).
+// core-shaped.  Thread t owns column group g = t % ng (4 output columns r) for (p, q) pairs
+// t / ng, t / ng + kCoreThreads / ng, ...; it keeps its RM x 4 block of S in registers, so
+// a task reads only its RM inputs (rows l >= R_k read row R_k - 1 again, which the zero rows
+// of S cancel).
 template <int RM>
-static __device__ void core_ttm(const CoreArgs &a, const float *in, int k, const float *S,
-                                float *out) {
+static __device__ inline void core_ttm(const CoreArgs &a, const float *in, int k, const float *S,
+                                       float *out) {
   int pre = 1, post = 1;
 #pragma unroll
   for (int j = 0; j < kMaxDim; ++j) {
@@ -382,19 +385,31 @@ static __device__ void core_ttm(const CoreArgs &a, const float *in, int k, const
   }
   const int Rk = a.R[k];
   const int ng = (Rk + 3) / 4;
-  const int tasks = pre * post * ng;
-  for (int t = threadIdx.x; t < tasks; t += blockDim.x) {
-    const int g = t % ng, pq = t / ng;
+  const int lanes = kCoreThreads / ng;  // threads per column group
+  const int g = threadIdx.x % ng, t0 = threadIdx.x / ng;
+  if (t0 >= lanes) return;
+  float4 sb[RM];
+#pragma unroll
+  for (int l = 0; l < RM; ++l) sb[l] = reinterpret_cast<const float4 *>(S + l * RM)[g];
+  // row offsets, the same for every task; kept opaque (readfirstlane) so that the compiler
+  // does not fold them back into one multiply per load
+  int off[RM];
+#pragma unroll
+  for (int l = 0; l < RM; ++l) off[l] = __builtin_amdgcn_readfirstlane((l < Rk ? l : Rk - 1) * post);
+  const int npq = pre * post;
+  for (int pq = t0; pq < npq; pq += lanes) {
     const int p = pq / post, q = pq - (pq / post) * post;
     const float *src = in + p * Rk * post + q;
+    float x[RM];
+#pragma unroll
+    for (int l = 0; l < RM; ++l) x[l] = src[off[l]];
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int l = 0; l < Rk; ++l) {
-      const float x = src[l * post];
-      const float4 sv = reinterpret_cast<const float4 *>(S + l * RM)[g];
-      acc.x = fmaf(sv.x, x, acc.x);
-      acc.y = fmaf(sv.y, x, acc.y);
-      acc.z = fmaf(sv.z, x, acc.z);
-      acc.w = fmaf(sv.w, x, acc.w);
+#pragma unroll
+    for (int l = 0; l < RM; ++l) {
+      acc.x = fmaf(sb[l].x, x[l], acc.x);
+      acc.y = fmaf(sb[l].y, x[l], acc.y);
+      acc.z = fmaf(sb[l].z, x[l], acc.z);
+      acc.w = fmaf(sb[l].w, x[l], acc.w);
     }
     float *dst = out + p * Rk * post + q;
     const int r0 = 4 * g;
@@ -405,77 +420,136 @@ static __device__ void core_ttm(const CoreArgs &a, const float *in, int k, const
   }
 }
 
-template <int RM>
+// LDS: the core and its two temporaries live in LDS (G | t0 | t1 | partial-sum scratch), so
+// every access is an LDS access; otherwise they are global scratch (cores above 8192
+// entries) and each phase ends with a device-scope fence.
+template <int RM, bool LDS>
 __global__ __launch_bounds__(kCoreThreads) void core_step_k(CoreArgs a) {
   extern __shared__ __attribute__((aligned(16))) float dyn[];
   __shared__ float part[kCoreThreads];
+  __shared__ __attribute__((aligned(16))) float Sp[kMaxDim][32 * RM];
   const int tid = threadIdx.x;
   const int d = a.d;
-  const bool glb = !a.lds;
-  // working copies: G and its temporaries (LDS when they fit, else global scratch) and the
-  // Grams padded to RM columns in LDS (Sp), which every core contraction reads
-  __shared__ __attribute__((aligned(16))) float Sp[kMaxDim][32 * RM];
-  float *G = a.G, *t0 = a.t0, *t1 = a.t1;
-  if (a.lds) {
-    G = dyn;
-    t0 = dyn + a.gsize;
-    t1 = dyn + 2 * a.gsize;
-    for (int e0 = 0; e0 < a.gsize; e0 += 8 * kCoreThreads) {
-      float v[8];
+  constexpr bool glb = !LDS;
+  float *G = LDS ? dyn : a.G;
+  float *t0 = LDS ? dyn + a.gsize : a.t0;
+  float *t1 = LDS ? dyn + 2 * a.gsize : a.t1;
+  // ---- every global read of the step is issued before the first is used (each serial
+  // round of global loads costs microseconds here): the core (LDS form), the Grams padded
+  // to RM columns, the core numerator (core update), and the first 32 Gram partials of
+  // the entries this thread sums.
+  constexpr int GU = (kCoreLdsMax + kCoreThreads - 1) / kCoreThreads;  // core values per thread
+  constexpr int kPB = 32;                                              // partials per batch
+  const int nsp = 32 * RM;
+  // (every load reads a valid address, clamped where the index runs past the data, and is
+  // masked only where the value is used: a select right after a load would make the
+  // compiler wait for that load at once)
+  float gv[LDS ? GU : 1], nv[LDS ? GU : 1];
+  if (LDS) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + tid + u * kCoreThreads;
-        v[u] = e < a.gsize ? a.G[e] : 0.f;
-      }
+    for (int u = 0; u < GU; ++u) {
+      const int e = tid + u * kCoreThreads;
+      gv[u] = a.G[e < a.gsize ? e : a.gsize - 1];
+    }
+    if (a.do_core) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + tid + u * kCoreThreads;
-        if (e < a.gsize) G[e] = v[u];
+      for (int u = 0; u < GU; ++u) {
+        const int e = tid + u * kCoreThreads;
+        nv[u] = a.numG[e < a.gsize ? e : a.gsize - 1];
       }
     }
   }
-  for (int k = 0; k < d; ++k) {
-    const int Rk = a.R[k];
-    for (int e = tid; e < 32 * RM; e += kCoreThreads) {
-      const int l = e / RM, r = e - (e / RM) * RM;
-      Sp[k][e] = (l < Rk && r < Rk) ? a.S[k][l * Rk + r] : 0.f;
+  constexpr int SU = (32 * RM + kCoreThreads - 1) / kCoreThreads;
+  float sv[SU][kMaxDim];
+#pragma unroll
+  for (int u = 0; u < SU; ++u) {
+    const int e = tid + u * kCoreThreads;
+    const int l = e / RM, r = e - (e / RM) * RM;
+#pragma unroll
+    for (int k = 0; k < kMaxDim; ++k) {
+      const bool ok = k < d && e < nsp && l < a.R[k] && r < a.R[k];
+      sv[u][k] = a.S[k < d ? k : 0][ok ? l * a.R[k] + r : 0];
     }
   }
-  __syncthreads();
-  // ---- 1. Gram S_k = A_k^T A_k (k = gram_from .. gram_to-1) from per-block partials
-  // gram[b][R][R] (Gram of factor rows [8b, 8b+8), see mu_rows_k / gram_parts_k).  Thread
-  // (entry, chunk) sums a contiguous range of blocks; the chunks are then added in order.
-  // The partials and this order are the same at the start of a fit and within it, so a
-  // fit resumed from its outputs continues bit for bit.
+  // Gram partials: gram[b][R][R] holds the Gram of factor rows [8b, 8b+8) (see mu_rows_k /
+  // gram_parts_k); entry e is summed over b in order, by one thread (R_k^2 > kCoreThreads:
+  // entries tid, tid + kCoreThreads, ...) or by nch threads over contiguous ranges of b,
+  // whose sums are then added in order.  The partials and this order are the same at the
+  // start of a fit and within it, so a fit resumed from its outputs continues bit for bit.
+  const int gk_mode = a.gram_from;  // one Gram per step (gram_to == gram_from + 1) here
+  const bool has_gram = a.gram_to > a.gram_from;
+  const int Rg = has_gram ? a.R[gk_mode] : 1;
+  const int RRg = Rg * Rg;
+  const int nch = RRg > kCoreThreads ? 1 : kCoreThreads / RRg;
+  const int ge0 = RRg > kCoreThreads ? tid : tid % RRg, gch = RRg > kCoreThreads ? 0 : tid / RRg;
+  const bool gact = has_gram && gch < nch && ge0 < RRg;
+  const int gb0 = gact ? (int)((int64_t)a.gram_parts * gch / nch) : 0;
+  const int gb1 = gact ? (int)((int64_t)a.gram_parts * (gch + 1) / nch) : 0;
+  const float *gsrc = has_gram ? a.gram : a.G;  // a valid address even without a Gram
+  float pv[kPB];
+#pragma unroll
+  for (int u = 0; u < kPB; ++u)
+    pv[u] = gsrc[(gb0 + u < gb1) ? (int64_t)(gb0 + u) * RRg + ge0 : 0];
+  // ---- the values above land in LDS
+  if (LDS) {
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      const int e = tid + u * kCoreThreads;
+      if (e < a.gsize) G[e] = gv[u];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < SU; ++u) {
+    const int e = tid + u * kCoreThreads;
+    const int l = e / RM, r = e - (e / RM) * RM;
+#pragma unroll
+    for (int k = 0; k < kMaxDim; ++k)
+      if (k < d && e < nsp) Sp[k][e] = (l < a.R[k] && r < a.R[k]) ? sv[u][k] : 0.f;
+  }
+  __syncthreads();  // the staged (old) Grams are in place before the new one overwrites its own
+  // ---- 1. Gram of the factor updated before this step (gram_from; at most one per step)
   for (int k = a.gram_from; k < a.gram_to; ++k) {
-    const int Rk = a.R[k];
-    const int RR = Rk * Rk;
-    const int nch = kCoreThreads / RR;
-    const int e = tid % RR, ch = tid / RR;
-    const float *gk = a.gram + (int64_t)(k - a.gram_from) * a.gram_stride;
+    if (k != gk_mode) break;  // launch_core_step passes one mode at a time
+    auto finish = [&](int e, float v) {
+      Sp[k][(e / Rg) * RM + e % Rg] = v;
+      a.S[k][e] = v;
+    };
     float acc = 0.f;
-    if (ch < nch) {
-      const int b0 = (int)((int64_t)a.gram_parts * ch / nch);
-      const int b1 = (int)((int64_t)a.gram_parts * (ch + 1) / nch);
-      for (int bb = b0; bb < b1; bb += 16) {
-        float v[16];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) v[u] = (bb + u < b1) ? gk[(int64_t)(bb + u) * RR + e] : 0.f;
+    for (int u = 0; u < kPB; ++u)
+      if (gb0 + u < gb1) acc += pv[u];
+    for (int bb = gb0 + kPB; bb < gb1; bb += kPB) {
 #pragma unroll
-        for (int u = 0; u < 16; ++u)
-          if (bb + u < b1) acc += v[u];
+      for (int u = 0; u < kPB; ++u) pv[u] = (bb + u < gb1) ? a.gram[(int64_t)(bb + u) * RRg + ge0] : 0.f;
+#pragma unroll
+      for (int u = 0; u < kPB; ++u)
+        if (bb + u < gb1) acc += pv[u];
+    }
+    if (RRg > kCoreThreads) {
+      // one thread per entry; entries beyond the first kCoreThreads are summed here
+      if (gact) finish(ge0, acc);
+      for (int e = tid + kCoreThreads; e < RRg; e += kCoreThreads) {
+        float a2 = 0.f;
+        for (int bb = 0; bb < a.gram_parts; bb += kPB) {
+#pragma unroll
+          for (int u = 0; u < kPB; ++u) pv[u] = (bb + u < a.gram_parts) ? a.gram[(int64_t)(bb + u) * RRg + e] : 0.f;
+#pragma unroll
+          for (int u = 0; u < kPB; ++u)
+            if (bb + u < a.gram_parts) a2 += pv[u];
+        }
+        finish(e, a2);
+      }
+    } else {
+      part[tid] = gact ? acc : 0.f;
+      __syncthreads();
+      if (tid < RRg) {
+        float s2 = 0.f;
+        for (int c = 0; c < nch; ++c) s2 += part[c * RRg + tid];
+        finish(tid, s2);
       }
     }
-    part[tid] = (ch < nch) ? acc : 0.f;
-    __syncthreads();
-    if (tid < RR) {
-      float s2 = 0.f;
-      for (int c = 0; c < nch; ++c) s2 += part[c * RR + tid];
-      Sp[k][(tid / Rk) * RM + tid % Rk] = s2;
-      a.S[k][tid] = s2;
-    }
-    phase_sync(glb);
   }
+  phase_sync(glb);
   // ---- 2. core update
   if (a.do_core) {
     const float *numG = a.numG;  // summed from the row-block partials by sum_parts_k
@@ -487,15 +561,24 @@ __global__ __launch_bounds__(kCoreThreads) void core_step_k(CoreArgs a) {
       in = o;
     }
     unsigned int nclip = 0;
-    for (int e = tid; e < a.gsize; e += kCoreThreads) {
+    auto update = [&](int e, float num) {
       double dd = (double)in[e];
       if (dd < a.eps) {
         dd = a.eps;
         ++nclip;
       }
-      const float g = (float)(((double)G[e] * (double)numG[e]) / dd);
+      const float g = (float)(((double)G[e] * (double)num) / dd);
       G[e] = g;
-      if (a.lds) a.G[e] = g;
+      if (LDS) a.G[e] = g;
+    };
+    if (LDS) {
+#pragma unroll
+      for (int u = 0; u < GU; ++u) {
+        const int e = tid + u * kCoreThreads;
+        if (e < a.gsize) update(e, nv[u]);
+      }
+    } else {
+      for (int e = tid; e < a.gsize; e += kCoreThreads) update(e, numG[e]);
     }
     if (nclip) atomicAdd(a.clips, (unsigned long long)nclip);
     phase_sync(glb);
@@ -514,58 +597,84 @@ __global__ __launch_bounds__(kCoreThreads) void core_step_k(CoreArgs a) {
       ++cnt;
     }
     const float *H = in;
+    float *freebuf = (H == t0) ? t1 : t0;  // the temporary not holding H
     int pre = 1, post = 1;
     for (int j = 0; j < n; ++j) pre *= a.R[j];
     for (int j = n + 1; j < d; ++j) post *= a.R[j];
     const int Rn = a.R[n];
-    const int nb2 = (Rn + 1) / 2;           // 2x2 blocks of M per row/column
-    const int blocks2 = nb2 * nb2;
-    const int split = kCoreThreads / blocks2;
-    const int bi = tid % blocks2, sp = tid / blocks2;
-    const int x0 = 2 * (bi / nb2), y0 = 2 * (bi % nb2);
-    const int x1 = x0 + 1 < Rn ? x0 + 1 : x0, y1 = y0 + 1 < Rn ? y0 + 1 : y0;
-    float m00 = 0.f, m01 = 0.f, m10 = 0.f, m11 = 0.f;
+    // M[x][y] = sum_{c=(p,q)} H[p][x][q] G[p][y][q]: thread (4x4 block, split) sums a
+    // contiguous range of c for its block; the ranges are then added in order.  The partial
+    // sums go to the free temporary (gsize floats; split is lowered to fit).
+    const int nb4 = (Rn + 3) / 4;
+    const int blocks4 = nb4 * nb4;
+    const int C = pre * post;
+    int split = kCoreThreads / blocks4;
+    const int cap = a.gsize / (blocks4 * 16);
+    if (split > cap) split = cap > 0 ? cap : 1;
+    if (split > C) split = C;
+    float *pm = (a.gsize >= split * blocks4 * 16) ? freebuf : (LDS ? dyn + 3 * a.gsize : a.numG);
+    const int bi = tid % blocks4, sp = tid / blocks4;
+    const int x0 = 4 * (bi / nb4), y0 = 4 * (bi % nb4);
+    float m[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) m[i][j] = 0.f;
     if (sp < split) {
-      const int C = pre * post;
+      int xs[4], ys[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        xs[i] = (x0 + i < Rn ? x0 + i : Rn - 1) * post;
+        ys[i] = (y0 + i < Rn ? y0 + i : Rn - 1) * post;
+      }
       const int c0 = (int)((int64_t)C * sp / split), c1 = (int)((int64_t)C * (sp + 1) / split);
-      int pp = c0 / post, q = c0 - (c0 / post) * post;
+      int q = c0 - (c0 / post) * post;
+      int base = (c0 / post) * Rn * post + q;  // advanced in step with (p, q)
+      const int jump = (Rn - 1) * post;
       for (int c = c0; c < c1; ++c) {
-        const int base = pp * Rn * post + q;
-        const float h0 = H[base + x0 * post], h1 = H[base + x1 * post];
-        const float g0 = G[base + y0 * post], g1 = G[base + y1 * post];
-        m00 = fmaf(h0, g0, m00);
-        m01 = fmaf(h0, g1, m01);
-        m10 = fmaf(h1, g0, m10);
-        m11 = fmaf(h1, g1, m11);
+        float h[4], gg[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          h[i] = H[base + xs[i]];
+          gg[i] = G[base + ys[i]];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) m[i][j] = fmaf(h[i], gg[j], m[i][j]);
+        ++base;
         if (++q == post) {
           q = 0;
-          ++pp;
+          base += jump;
         }
       }
     }
-    // partial sums of the split ranges, added in order; 4 values per thread.  Scratch of
-    // kCoreThreads * 4 floats: LDS after G/t0/t1, or (global mode) numG, which is free here
-    // and has more than 8192 entries.
-    float *pm = a.lds ? dyn + 3 * a.gsize : a.numG;
-    __syncthreads();
+    if (pm != freebuf) __syncthreads();  // fallback scratch: wait until every thread is done
     if (sp < split) {
-      pm[(sp * blocks2 + bi) * 4 + 0] = m00;
-      pm[(sp * blocks2 + bi) * 4 + 1] = m01;
-      pm[(sp * blocks2 + bi) * 4 + 2] = m10;
-      pm[(sp * blocks2 + bi) * 4 + 3] = m11;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) pm[((sp * blocks4 + bi) * 4 + i) * 4 + j] = m[i][j];
     }
     phase_sync(glb);
     for (int e = tid; e < Rn * Rn; e += kCoreThreads) {
       const int x = e / Rn, y = e % Rn;
-      const int b2 = (x / 2) * nb2 + (y / 2), j = (x % 2) * 2 + (y % 2);
+      const int b4 = (x / 4) * nb4 + (y / 4), j = (x % 4) * 4 + (y % 4);
       float s2 = 0.f;
-      for (int c = 0; c < split; ++c) s2 += pm[(c * blocks2 + b2) * 4 + j];
+      for (int c = 0; c < split; ++c) s2 += pm[(c * blocks4 + b4) * 16 + j];
       a.M[e] = s2;
     }
   }
 }
 
+nnc_status launch_slice_step(const CoreArgsHost &h, hipStream_t s);
+
 nnc_status launch_core_step(const CoreArgsHost &h, hipStream_t s) {
+  // small cores: the work spread over one workgroup per slice (core_kernels.hip)
+  {
+    const nnc_status st = launch_slice_step(h, s);
+    if (st != NNC_EUNSUPPORTED) return st;
+  }
   CoreArgs a;
   memset(&a, 0, sizeof a);
   a.d = h.d;
@@ -606,16 +715,23 @@ nnc_status launch_core_step(const CoreArgsHost &h, hipStream_t s) {
     a.lds = 1;
     lds = (size_t)(3 * gsize + 4 * kCoreThreads) * sizeof(float);
   }
-#define NNC_CORE_LAUNCH(RM)                                                                     \
+#define NNC_CORE_LAUNCH2(RM, LDSV)                                                              \
   do {                                                                                          \
     static bool attr = false;                                                                   \
     if (!attr) {                                                                                \
-      NNC_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(core_step_k<RM>),              \
+      NNC_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(core_step_k<RM, LDSV>),        \
                                   hipFuncAttributeMaxDynamicSharedMemorySize,                   \
-                                  (int)((3 * kCoreLdsMax + 4 * kCoreThreads) * sizeof(float))));                     \
+                                  (int)((3 * kCoreLdsMax + 4 * kCoreThreads) * sizeof(float)))); \
       attr = true;                                                                              \
     }                                                                                           \
-    hipLaunchKernelGGL(core_step_k<RM>, dim3(1), dim3(kCoreThreads), lds, s, a);                \
+    hipLaunchKernelGGL((core_step_k<RM, LDSV>), dim3(1), dim3(kCoreThreads), lds, s, a);        \
+  } while (0)
+#define NNC_CORE_LAUNCH(RM)            \
+  do {                                 \
+    if (a.lds)                         \
+      NNC_CORE_LAUNCH2(RM, true);      \
+    else                               \
+      NNC_CORE_LAUNCH2(RM, false);     \
   } while (0)
   if (maxr <= 8)
     NNC_CORE_LAUNCH(8);
@@ -626,6 +742,7 @@ nnc_status launch_core_step(const CoreArgsHost &h, hipStream_t s) {
   else
     NNC_CORE_LAUNCH(32);
 #undef NNC_CORE_LAUNCH
+#undef NNC_CORE_LAUNCH2
   NNC_HIP(hipGetLastError());
   return NNC_OK;
 }
