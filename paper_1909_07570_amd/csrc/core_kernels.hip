@@ -23,7 +23,7 @@
 
 namespace nnc {
 
-constexpr int kSliceThreads = 256;
+constexpr int kSliceThreads = 1024;  // four waves per SIMD: these steps are latency-bound
 constexpr int kSliceMax = 16384;  // cores up to this many entries use these kernels
 
 struct SliceArgs {
@@ -32,7 +32,8 @@ struct SliceArgs {
   int gsize;
   const float *G;      // core (read)
   float *Gout;         // denB_k: updated core (same as G)
-  float *S[kMaxDim];   // Grams (global)
+  float *S[kMaxDim];   // Grams (global), packed: S[k] = S[0] + soff[k]
+  int soff[kMaxDim + 1];
   int gram;            // mode whose Gram is summed from partials here, or -1
   const float *gram_part;
   int gram_parts;
@@ -56,103 +57,149 @@ struct SliceLds {
 // Grams into LDS (row stride RM, zero padding); the gram mode's Gram is summed from the
 // partials (entries in groups of 4 when R^2 is a multiple of 4, else one by one; each group
 // by kSliceThreads / groups threads over contiguous ranges of partials, added in order).
+// issue() starts every global read (the stored Grams and the first kPB partials of this
+// thread); finish() consumes them, so a kernel can issue its own reads alongside and pay
+// one round of memory latency.
 template <int RM>
-static __device__ void stage_grams(const SliceArgs &a, float *Sl, float *red) {
-  const int tid = threadIdx.x;
-  for (int k = 0; k < a.d; ++k) {
-    if (k == a.gram) continue;
-    const int Rk = a.R[k];
-    for (int e = tid; e < RM * RM; e += kSliceThreads) {
-      const int l = e / RM, r = e - (e / RM) * RM;
-      Sl[k * RM * RM + e] = (l < Rk && r < Rk) ? a.S[k][l * Rk + r] : 0.f;
+struct GramStage {
+  static constexpr int SU = (kMaxDim * RM * RM + kSliceThreads - 1) / kSliceThreads;  // Gram entries
+  static constexpr int GPT = (RM * RM + kSliceThreads - 1) / kSliceThreads;  // groups (nch == 1)
+  static constexpr int kPB = 8;                                              // partials in flight
+  float sv[SU];
+  float4 pv[kPB];
+  int W, ngrp, nch, ch, b0, b1, RR, Rk;
+  bool vec;
+
+  __device__ void issue(const SliceArgs &a) {
+    const int tid = threadIdx.x;
+    // every stored Gram, as one flat packed array (entries past the end read the last one)
+    const int ns = a.soff[a.d];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int e = tid + u * kSliceThreads;
+      sv[u] = a.S[0][e < ns ? e : ns - 1];
     }
-  }
-  if (a.gram < 0) return;
-  const int k = a.gram, Rk = a.R[k], RR = Rk * Rk;
-  float *Sg = Sl + k * RM * RM;
-  for (int e = tid; e < RM * RM; e += kSliceThreads)  // padding only: the rest is written below
-    if (e / RM >= Rk || e % RM >= Rk) Sg[e] = 0.f;
-  const bool vec = (RR % 4) == 0;
-  const int W = vec ? 4 : 1;           // entries per group
-  const int ngrp = RR / W;
-  const int nch = ngrp >= kSliceThreads ? 1 : kSliceThreads / ngrp;
-  const int P = a.gram_parts;
-  constexpr int GPT = (RM * RM + kSliceThreads - 1) / kSliceThreads;  // groups per thread (nch == 1)
-  float4 acc[GPT];
-  const int ch = tid / (nch > 1 ? ngrp : kSliceThreads);
-  // thread's groups: nch > 1 -> group tid % ngrp, chunk tid / ngrp; nch == 1 -> groups tid + j*T
+    if (a.gram < 0) return;
+    Rk = a.R[a.gram];
+    RR = Rk * Rk;
+    vec = (RR % 4) == 0;
+    W = vec ? 4 : 1;
+    ngrp = RR / W;
+    nch = ngrp >= kSliceThreads ? 1 : kSliceThreads / ngrp;
+    ch = nch > 1 ? tid / ngrp : 0;
+    const int P = a.gram_parts;
+    b0 = (ch < nch) ? (int)((int64_t)P * ch / nch) : 0;
+    b1 = (ch < nch) ? (int)((int64_t)P * (ch + 1) / nch) : 0;
+    if (nch > 1) {  // one group per thread: its first kPB partials now
+      const int grp = tid % ngrp;
+      if (vec) {
 #pragma unroll
-  for (int j = 0; j < GPT; ++j) acc[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (ch < nch) {
-    const int b0 = (int)((int64_t)P * ch / nch), b1 = (int)((int64_t)P * (ch + 1) / nch);
-#pragma unroll
-    for (int j = 0; j < GPT; ++j) {
-      const int grp = nch > 1 ? tid % ngrp : tid + j * kSliceThreads;
-      if ((nch > 1 && j > 0) || grp >= ngrp) continue;
-      float4 s4 = make_float4(0.f, 0.f, 0.f, 0.f);
-      for (int bb = b0; bb < b1; bb += 16) {
-        float4 v[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          const int b = bb + u < b1 ? bb + u : b1 - 1;
-          const float *src = a.gram_part + (int64_t)b * RR + grp * W;
-          v[u] = vec ? *reinterpret_cast<const float4 *>(src) : make_float4(src[0], 0.f, 0.f, 0.f);
+        for (int u = 0; u < kPB; ++u) {
+          const int b = b0 + u < b1 ? b0 + u : (b1 > 0 ? b1 - 1 : 0);
+          pv[u] = *reinterpret_cast<const float4 *>(a.gram_part + (int64_t)b * RR + grp * 4);
         }
+      } else {
 #pragma unroll
-        for (int u = 0; u < 16; ++u)
-          if (bb + u < b1) {
-            s4.x += v[u].x;
-            s4.y += v[u].y;
-            s4.z += v[u].z;
-            s4.w += v[u].w;
-          }
+        for (int u = 0; u < kPB; ++u) {
+          const int b = b0 + u < b1 ? b0 + u : (b1 > 0 ? b1 - 1 : 0);
+          pv[u].x = a.gram_part[(int64_t)b * RR + grp];
+        }
       }
-      acc[j] = s4;
     }
   }
-  auto put = [&](int grp, float4 v) {
-    const float vv[4] = {v.x, v.y, v.z, v.w};
-    for (int w = 0; w < W; ++w) {
-      const int e = grp * W + w;
-      Sg[(e / Rk) * RM + e % Rk] = vv[w];
-      if (blockIdx.x == 0) a.S[k][e] = vv[w];
+
+  __device__ void finish(const SliceArgs &a, float *Sl, float *red) {
+    const int tid = threadIdx.x;
+    const int ns = a.soff[a.d];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const int e = tid + u * kSliceThreads;
+      if (e >= ns) continue;
+      int k = 0;
+#pragma unroll
+      for (int j = 1; j < kMaxDim; ++j)
+        if (j < a.d && e >= a.soff[j]) k = j;
+      if (k == a.gram) continue;  // formed below from the partials
+      const int loc = e - a.soff[k], Rm = a.R[k];
+      const int l = loc / Rm, r = loc - (loc / Rm) * Rm;
+      Sl[k * RM * RM + l * RM + r] = sv[u];
     }
-  };
-  if (nch > 1) {
-    if (ch < nch) reinterpret_cast<float4 *>(red)[tid] = acc[0];
-    __syncthreads();
-    if (tid < ngrp) {
+    // zero padding of every mode (entries l >= R_k or r >= R_k; none of them is written above)
+    for (int k = 0; k < a.d; ++k)
+      for (int e = tid; e < RM * RM; e += kSliceThreads)
+        if (e / RM >= a.R[k] || e % RM >= a.R[k]) Sl[k * RM * RM + e] = 0.f;
+    if (a.gram < 0) return;
+    const int k = a.gram;
+    float *Sg = Sl + k * RM * RM;
+    auto load = [&](int b, int grp) {
+      const float *src = a.gram_part + (int64_t)b * RR + grp * W;
+      return vec ? *reinterpret_cast<const float4 *>(src) : make_float4(src[0], 0.f, 0.f, 0.f);
+    };
+    auto add = [](float4 &s4, float4 v) {
+      s4.x += v.x;
+      s4.y += v.y;
+      s4.z += v.z;
+      s4.w += v.w;
+    };
+    auto put = [&](int grp, float4 v) {
+      const float vv[4] = {v.x, v.y, v.z, v.w};
+      for (int w = 0; w < W; ++w) {
+        const int e = grp * W + w;
+        Sg[(e / Rk) * RM + e % Rk] = vv[w];
+        if (blockIdx.x == 0) a.S[k][e] = vv[w];
+      }
+    };
+    if (nch > 1) {
       float4 s4 = make_float4(0.f, 0.f, 0.f, 0.f);
-      for (int c = 0; c < nch; ++c) {
-        const float4 v = reinterpret_cast<const float4 *>(red)[c * ngrp + tid];
-        s4.x += v.x;
-        s4.y += v.y;
-        s4.z += v.z;
-        s4.w += v.w;
-      }
-      put(tid, s4);
-    }
-  } else {
+      if (ch < nch) {
 #pragma unroll
-    for (int j = 0; j < GPT; ++j) {
-      const int grp = tid + j * kSliceThreads;
-      if (grp < ngrp) put(grp, acc[j]);
+        for (int u = 0; u < kPB; ++u)
+          if (b0 + u < b1) add(s4, vec ? pv[u] : make_float4(pv[u].x, 0.f, 0.f, 0.f));
+        for (int bb = b0 + kPB; bb < b1; ++bb) add(s4, load(bb, tid % ngrp));
+        reinterpret_cast<float4 *>(red)[tid] = s4;
+      }
+      __syncthreads();
+      if (tid < ngrp) {
+        float4 t4 = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int c = 0; c < nch; ++c) add(t4, reinterpret_cast<const float4 *>(red)[c * ngrp + tid]);
+        put(tid, t4);
+      }
+    } else {
+      for (int j = 0; j < GPT; ++j) {
+        const int grp = tid + j * kSliceThreads;
+        if (grp >= ngrp) break;
+        float4 s4 = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int bb = 0; bb < a.gram_parts; ++bb) add(s4, load(bb, grp));
+        put(grp, s4);
+      }
     }
   }
-}
+};
 
 // out[p][r][q] = sum_l S[l][r] in[p][l][q] on an LDS tensor whose mode of size Rk has pre
-// entries before it and post after it; one output per thread and step.
+// entries before it and post after it; one output per thread and step.  The RM inputs of an
+// output are loaded before the multiply-adds (rows l >= Rk read row Rk - 1, which the zero
+// rows of S cancel), so each output costs one LDS round trip.
 template <int RM>
 static __device__ void slice_ttm(const float *in, float *out, int pre, int Rk, int post,
                                  const float *S) {
   const int total = pre * Rk * post;
+  int off[RM];  // the same for every output; opaque so that it is not folded into multiplies
+#pragma unroll
+  for (int l = 0; l < RM; ++l) off[l] = __builtin_amdgcn_readfirstlane((l < Rk ? l : Rk - 1) * post);
   for (int o = threadIdx.x; o < total; o += kSliceThreads) {
     const int q = o % post, pr = o / post;
     const int r = pr % Rk, p = pr / Rk;
     const float *src = in + p * Rk * post + q;
+    float x[RM], sv[RM];
+#pragma unroll
+    for (int l = 0; l < RM; ++l) {
+      x[l] = src[off[l]];
+      sv[l] = S[l * RM + r];
+    }
     float acc = 0.f;
-    for (int l = 0; l < Rk; ++l) acc = fmaf(S[l * RM + r], src[l * post], acc);
+#pragma unroll
+    for (int l = 0; l < RM; ++l) acc = fmaf(sv[l], x[l], acc);
     out[o] = acc;
   }
 }
@@ -184,7 +231,7 @@ static __device__ float *contract_slice(const SliceArgs &a, int skip, const floa
 
 // Row a = blockIdx.x of M_n (and, with a.gram >= 0, the new Gram of mode a.gram).  With
 // a.n < 0 only the Gram is formed (one block).
-template <int RM>
+template <int RM, bool BIG>
 __global__ __launch_bounds__(kSliceThreads) void mrows_k(SliceArgs a) {
   extern __shared__ __attribute__((aligned(16))) float lds[];
   const int d = a.d, tid = threadIdx.x;
@@ -196,21 +243,27 @@ __global__ __launch_bounds__(kSliceThreads) void mrows_k(SliceArgs a) {
   const int slice = a.gsize / Rn;
   float *H0 = G + a.gsize, *H1 = H0 + slice;
   // the whole core (for the dot products) and the Grams
-  if (n >= 0)
-    for (int e0 = 0; e0 < a.gsize; e0 += 32 * kSliceThreads) {
-      float v[32];
+  // every global read first (the core, the Grams, the Gram partials), then their use
+  GramStage<RM> gs;
+  constexpr int GPTH = (BIG ? kSliceMax : kSliceMax / 2) / kSliceThreads;  // core values per thread
+  float gv[GPTH];
+  if (n >= 0) {
 #pragma unroll
-      for (int u = 0; u < 32; ++u) {
-        const int e = e0 + tid + u * kSliceThreads;
-        v[u] = a.G[e < a.gsize ? e : a.gsize - 1];
-      }
-#pragma unroll
-      for (int u = 0; u < 32; ++u) {
-        const int e = e0 + tid + u * kSliceThreads;
-        if (e < a.gsize) G[e] = v[u];
-      }
+    for (int u = 0; u < GPTH; ++u) {
+      const int e = tid + u * kSliceThreads;
+      gv[u] = a.G[e < a.gsize ? e : a.gsize - 1];
     }
-  stage_grams<RM>(a, Sl, red);
+  }
+  gs.issue(a);
+  __builtin_amdgcn_sched_barrier(0);  // every load above is issued before any is used
+  if (n >= 0) {
+#pragma unroll
+    for (int u = 0; u < GPTH; ++u) {
+      const int e = tid + u * kSliceThreads;
+      if (e < a.gsize) G[e] = gv[u];
+    }
+  }
+  gs.finish(a, Sl, red);
   __syncthreads();
   if (n < 0) return;
   const int ia = blockIdx.x;
@@ -225,12 +278,13 @@ __global__ __launch_bounds__(kSliceThreads) void mrows_k(SliceArgs a) {
   __syncthreads();
   const float *H = contract_slice<RM>(a, n, Sl, H0, H1);
   // M[ia][b] = sum_c H[c] G[(pc * Rn + b) * post + qc]; thread (b, chunk), chunks added in order
-  const int nchunk = kSliceThreads / Rn;
+  const int nchunk = std::min(16, kSliceThreads / Rn);
   const int b = tid % Rn, ch = tid / Rn;
   float acc = 0.f;
   if (ch < nchunk) {
     const int c0 = (int)((int64_t)slice * ch / nchunk), c1 = (int)((int64_t)slice * (ch + 1) / nchunk);
     int pc = c0 / post, qc = c0 - (c0 / post) * post;
+#pragma unroll 4
     for (int c = c0; c < c1; ++c) {
       acc = fmaf(H[c], G[(pc * Rn + b) * post + qc], acc);
       if (++qc == post) {
@@ -249,7 +303,7 @@ __global__ __launch_bounds__(kSliceThreads) void mrows_k(SliceArgs a) {
 }
 
 // T_i = G[i, ..] x_1 S_1 ... x_{d-1} S_{d-1} for i = blockIdx.x (and the new Gram of a.gram).
-template <int RM>
+template <int RM, bool BIG>
 __global__ __launch_bounds__(kSliceThreads) void denA_k(SliceArgs a) {
   extern __shared__ __attribute__((aligned(16))) float lds[];
   const int d = a.d, tid = threadIdx.x;
@@ -258,8 +312,22 @@ __global__ __launch_bounds__(kSliceThreads) void denA_k(SliceArgs a) {
   const int slice = a.gsize / a.R[0];
   float *H0 = red + SliceLds<RM>::kRed, *H1 = H0 + slice;
   const int i = blockIdx.x;
-  for (int c = tid; c < slice; c += kSliceThreads) H0[c] = a.G[(int64_t)i * slice + c];
-  stage_grams<RM>(a, Sl, red);
+  constexpr int SPT = (BIG ? kSliceMax : kSliceMax / 2) / kSliceThreads;  // slice values per thread
+  float hv[SPT];
+#pragma unroll
+  for (int u = 0; u < SPT; ++u) {
+    const int c = tid + u * kSliceThreads;
+    hv[u] = a.G[(int64_t)i * slice + (c < slice ? c : slice - 1)];
+  }
+  GramStage<RM> gs;
+  gs.issue(a);
+  __builtin_amdgcn_sched_barrier(0);  // every load above is issued before any is used
+#pragma unroll
+  for (int u = 0; u < SPT; ++u) {
+    const int c = tid + u * kSliceThreads;
+    if (c < slice) H0[c] = hv[u];
+  }
+  gs.finish(a, Sl, red);
   __syncthreads();
   const float *T = contract_slice<RM>(a, 0, Sl, H0, H1);
   for (int c = tid; c < slice; c += kSliceThreads) a.T[(int64_t)i * slice + c] = T[c];
@@ -305,7 +373,7 @@ static nnc_status allow_slice_lds(const void *kern, size_t bytes) {
   return NNC_OK;
 }
 
-template <int RM>
+template <int RM, bool BIG>
 static nnc_status slice_step(const CoreArgsHost &h, hipStream_t s) {
   SliceArgs a;
   memset(&a, 0, sizeof a);
@@ -316,6 +384,8 @@ static nnc_status slice_step(const CoreArgsHost &h, hipStream_t s) {
     a.S[k] = k < h.d ? h.S[k] : nullptr;
   }
   for (int k = 0; k < h.d; ++k) a.gsize *= a.R[k];
+  a.soff[0] = 0;
+  for (int k = 0; k < kMaxDim; ++k) a.soff[k + 1] = a.soff[k] + (k < h.d ? a.R[k] * a.R[k] : 0);
   a.G = h.G;
   a.gram = h.gram_to > h.gram_from ? h.gram_from : -1;
   a.gram_part = h.gram;
@@ -328,8 +398,8 @@ static nnc_status slice_step(const CoreArgsHost &h, hipStream_t s) {
     a.n = -1;
     const int slice0 = a.gsize / a.R[0];
     const size_t la = SliceLds<RM>::bytes(a.d, a.gsize, slice0, false);
-    NNC_TRY(allow_slice_lds(reinterpret_cast<const void *>(denA_k<RM>), la));
-    hipLaunchKernelGGL(denA_k<RM>, dim3(a.R[0]), dim3(kSliceThreads), la, s, a);
+    NNC_TRY(allow_slice_lds(reinterpret_cast<const void *>(denA_k<RM, BIG>), la));
+    hipLaunchKernelGGL((denA_k<RM, BIG>), dim3(a.R[0]), dim3(kSliceThreads), la, s, a);
     SliceArgs b = a;
     b.gram = -1;
     b.numG = h.numG;
@@ -342,8 +412,8 @@ static nnc_status slice_step(const CoreArgsHost &h, hipStream_t s) {
     a.M = h.M;
     const int Rn = h.next >= 0 ? a.R[h.next] : 1;
     const size_t lm = SliceLds<RM>::bytes(a.d, a.gsize, a.gsize / Rn, h.next >= 0);
-    NNC_TRY(allow_slice_lds(reinterpret_cast<const void *>(mrows_k<RM>), lm));
-    hipLaunchKernelGGL(mrows_k<RM>, dim3(h.next >= 0 ? Rn : 1), dim3(kSliceThreads), lm, s, a);
+    NNC_TRY(allow_slice_lds(reinterpret_cast<const void *>(mrows_k<RM, BIG>), lm));
+    hipLaunchKernelGGL((mrows_k<RM, BIG>), dim3(h.next >= 0 ? Rn : 1), dim3(kSliceThreads), lm, s, a);
   }
   NNC_HIP(hipGetLastError());
   return NNC_OK;
@@ -358,16 +428,22 @@ nnc_status launch_slice_step(const CoreArgsHost &h, hipStream_t s) {
     maxr = std::max(maxr, (int)h.R[k]);
   }
   if (gsize > kSliceMax || maxr > 32 || h.gram_to - h.gram_from > 1) return NNC_EUNSUPPORTED;
+  // the Grams must be packed one after another (the fit's workspace keeps them so)
+  for (int64_t k = 1, off = h.R[0] * h.R[0]; k < h.d; off += h.R[k] * h.R[k], ++k)
+    if (h.S[k] != h.S[0] + off) return NNC_EUNSUPPORTED;
   // LDS of the largest launch (the whole core and two slices at worst)
   const int RM = maxr <= 8 ? 8 : (maxr <= 16 ? 16 : (maxr <= 24 ? 24 : 32));
   int64_t worst = 0;
   for (int k = 0; k < h.d; ++k) worst = std::max(worst, gsize / h.R[k]);
   const int64_t need = 4 * ((int64_t)h.d * RM * RM + 4 * kSliceThreads + gsize + 2 * worst);
   if (need > 160 * 1024) return NNC_EUNSUPPORTED;
-  if (maxr <= 8) return slice_step<8>(h, s);
-  if (maxr <= 16) return slice_step<16>(h, s);
-  if (maxr <= 24) return slice_step<24>(h, s);
-  return slice_step<32>(h, s);
+  const bool big = gsize > kSliceMax / 2;
+#define NNC_SLICE(RMV) return big ? slice_step<RMV, true>(h, s) : slice_step<RMV, false>(h, s)
+  if (maxr <= 8) NNC_SLICE(8);
+  if (maxr <= 16) NNC_SLICE(16);
+  if (maxr <= 24) NNC_SLICE(24);
+  NNC_SLICE(32);
+#undef NNC_SLICE
 }
 
 }  // namespace nnc
