@@ -424,6 +424,9 @@ static bool core_overlap() {
   return v == 1;
 }
 
+// Sweeps captured in one graph when no objective is recorded in between.
+constexpr int kSweepsPerGraph = 8;
+
 // Sweep flags (used with the overlap only).  kDeferIn: the previous sweep's core step is still to run; it runs on the side
 // stream next to pass 1 (which needs only the last factor) and mode 0 waits for it.
 // kDeferOut: leave this sweep's core step to the next call (or to core_tail).
@@ -722,12 +725,14 @@ nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *d
       NNC_HIP(hipEventRecord(ev_in, s));
       NNC_HIP(hipStreamWaitEvent(cs, ev_in, 0));
     }
-    // capture one sweep with the given flags into an executable graph
-    auto capture = [&](int flags, hipGraphExec_t *ge) -> nnc_status {
+    // capture `count` sweeps with the given flags into an executable graph
+    auto capture = [&](int flags, hipGraphExec_t *ge, int count = 1) -> nnc_status {
       hipGraph_t g = nullptr;
       NNC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-      nnc_status st = p.fast ? fused_sweep(b, Xs, dts, core, factors, eps, cs, nullptr, flags)
-                             : tucker_sweep(b, Xs, dts, core, factors, eps, cs, nullptr);
+      nnc_status st = NNC_OK;
+      for (int c = 0; c < count && st == NNC_OK; ++c)
+        st = p.fast ? fused_sweep(b, Xs, dts, core, factors, eps, cs, nullptr, flags)
+                    : tucker_sweep(b, Xs, dts, core, factors, eps, cs, nullptr);
       hipError_t ec = hipStreamEndCapture(cs, &g);
       if (st != NNC_OK) {
         if (g) (void)hipGraphDestroy(g);
@@ -756,6 +761,22 @@ nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *d
       if (hipStreamSynchronize(cs) != hipSuccess && st == NNC_OK)
         st = fail(NNC_EHIP, "stream synchronization after the sweeps failed");
       for (hipGraphExec_t e : {gf, gm, gl})
+        if (e) (void)hipGraphExecDestroy(e);
+      NNC_TRY(st);
+    } else if (!every && tb - ta > 1) {
+      // several sweeps per graph: the turnaround between two graph launches (several
+      // microseconds) is paid once per kSweepsPerGraph sweeps
+      const int n = tb - ta;
+      const int per = std::min(n, kSweepsPerGraph);
+      hipGraphExec_t gb = nullptr, gr = nullptr;
+      nnc_status st = capture(0, &gb, per);
+      if (st == NNC_OK && n % per) st = capture(0, &gr, n % per);
+      for (int t = 0; st == NNC_OK && t + per <= n; t += per)
+        if (hipGraphLaunch(gb, cs) != hipSuccess) st = fail(NNC_EHIP, "graph launch failed");
+      if (st == NNC_OK && gr && hipGraphLaunch(gr, cs) != hipSuccess) st = fail(NNC_EHIP, "graph launch failed");
+      if (hipStreamSynchronize(cs) != hipSuccess && st == NNC_OK)
+        st = fail(NNC_EHIP, "stream synchronization after the sweeps failed");
+      for (hipGraphExec_t e : {gb, gr})
         if (e) (void)hipGraphExecDestroy(e);
       NNC_TRY(st);
     } else {

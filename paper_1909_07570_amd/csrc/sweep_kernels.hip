@@ -13,62 +13,77 @@ namespace nnc {
 
 // =====================================================================================
 // out[p][r][q] = sum_n F[n*ldl + r*ldr] * in[p][n][q]   (R <= 32, FP32)
-// A block owns 64 consecutive (p, q) pairs, one per lane.  The factor is staged in LDS in
-// chunks of kSmallChunk rows, zero-padded to RM columns (so the inner loop has no
-// branches and reads float4 broadcasts); the block's 8 waves take contiguous slices of
-// every chunk, load their X values 16 at a time, and their partial sums are added in a
-// fixed order at the end.
+// A block owns 64 consecutive (p, q) pairs, one per lane, and W = ceil(N / 32) waves (at
+// most 16), so that one round covers up to 512 rows of n with 32 rows per wave: each wave
+// issues its 32 X loads of the round before the first product, while the block stages the
+// round's factor rows in LDS (zero-padded to RM columns and past N, so rows past the end
+// contribute nothing).  The wave partial sums are added in wave order through LDS, which
+// the factor rows of the last round no longer need.  Adding splits of n in a second
+// pass or through a device-scope counter would give more blocks when P*Q is small, but
+// the release fence such a counter needs writes back the whole L2 of the XCD, which has
+// cost far more than the extra parallelism saves.
 // =====================================================================================
-constexpr int kSmallWaves = 8;
-constexpr int kSmallRows = 64;  // rows of one chunk per wave, all loaded before use
+constexpr int kSmallRows = 32;     // rows of n per wave and round
+constexpr int kSmallMaxWaves = 16;
+
+static int small_waves(int64_t N) {
+  const int64_t w = (N + kSmallRows - 1) / kSmallRows;
+  return (int)(w < 1 ? 1 : (w > kSmallMaxWaves ? kSmallMaxWaves : w));
+}
+// LDS of a block: the factor rows of a round (W*32 rows of RM) or the wave partial sums
+// (W of RM x 64), whichever is larger.
+static size_t small_lds(int W, int RM) { return (size_t)W * 64 * RM * sizeof(float); }
 
 template <int RM>
-__global__ __launch_bounds__(64 * kSmallWaves) void ttm_small_k(const float *__restrict__ in, int64_t P,
-                                                               int64_t N, int64_t Q,
-                                                               const float *__restrict__ F,
-                                                               int64_t ldl, int64_t ldr, int R,
-                                                               float *__restrict__ out) {
-  constexpr int kChunkRows = (RM <= 24 ? 512 : 256);  // factor rows staged per chunk
-  constexpr int RH = RM < 16 ? RM : (RM % 16 ? 8 : 16);  // LDS reduction slice width
-  __shared__ __attribute__((aligned(16))) float Fs[kChunkRows][RM];
-  __shared__ float red[kSmallWaves][RH][64];
+__global__ __launch_bounds__(64 * kSmallMaxWaves) void ttm_small_k(
+    const float *__restrict__ in, int64_t P, int64_t N, int64_t Q, const float *__restrict__ F,
+    int64_t ldl, int64_t ldr, int R, float *__restrict__ out) {
+  extern __shared__ __attribute__((aligned(16))) float sm[];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
+  const int W = blockDim.x >> 6;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t PQ = P * Q;
   const int64_t e = (int64_t)blockIdx.x * 64 + lane;
-  const bool valid = e < PQ;
-  const int64_t p = valid ? e / Q : 0, q = valid ? e - (e / Q) * Q : 0;
-  const float *src = in + p * N * Q + q;  // in bounds for every lane (invalid lanes read p=q=0)
+  const int64_t ee = e < PQ ? e : 0;
+  const int64_t p = ee / Q, q = ee - (ee / Q) * Q;
+  const float *src = in + p * N * Q + q;
+  const int span = W * kSmallRows;  // rows of a round
   float acc[RM];
 #pragma unroll
   for (int r = 0; r < RM; ++r) acc[r] = 0.f;
-  for (int64_t c0 = 0; c0 < N; c0 += kChunkRows) {
-    const int cn = (int)((N - c0) < kChunkRows ? (N - c0) : kChunkRows);
-    const int s0 = cn * w / kSmallWaves, s1 = cn * (w + 1) / kSmallWaves;  // <= 64 rows
-    // this wave's X values of the chunk, all loads in flight together
+  for (int64_t nb = 0; nb < N; nb += span) {
     float x[kSmallRows];
 #pragma unroll
-    for (int u = 0; u < kSmallRows; ++u) x[u] = (s0 + u < s1) ? src[(c0 + s0 + u) * Q] : 0.f;
-    // factor rows of the chunk, zero-padded to RM columns
-    constexpr int kStage = (RM * kChunkRows + 64 * kSmallWaves - 1) / (64 * kSmallWaves);
+    for (int u = 0; u < kSmallRows; ++u) {
+      int64_t n = nb + w * kSmallRows + u;
+      n = n < N ? n : N - 1;  // rows past N meet zero factor rows
+      x[u] = src[n * Q];
+    }
+    // factor rows [nb, nb + span): RM * 32 values per wave, the wave's own rows
+    constexpr int kStage = RM / 2;  // 32 * RM values over 64 lanes
     float v[kStage];
 #pragma unroll
     for (int u = 0; u < kStage; ++u) {
-      const int idx = tid + u * 64 * kSmallWaves;
-      const int n = idx / RM, r = idx - (idx / RM) * RM;
-      v[u] = (n < cn && r < R) ? F[(c0 + n) * ldl + r * ldr] : 0.f;
+      const int idx = lane + u * 64;
+      const int nn = idx / RM, r = idx - (idx / RM) * RM;
+      const int64_t n = nb + w * kSmallRows + nn;
+      const bool ok = n < N && r < R;
+      v[u] = F[(ok ? n : 0) * ldl + (ok ? r : 0) * ldr];
     }
+    float *Fw = sm + w * kSmallRows * RM;
 #pragma unroll
-    for (int u = 0; u < kStage; ++u) {
-      const int idx = tid + u * 64 * kSmallWaves;
-      if (idx < kChunkRows * RM) Fs[idx / RM][idx % RM] = v[u];
+    for (int u = 0; u < kStage; ++u) {  // zeros masked in here, where the values are awaited
+      const int idx = lane + u * 64;
+      const int nn = idx / RM, r = idx - (idx / RM) * RM;
+      Fw[idx] = (nb + w * kSmallRows + nn < N && r < R) ? v[u] : 0.f;
     }
-    __syncthreads();
+    // each wave reads only the rows it staged itself, and a wave's LDS operations take
+    // effect in issue order: the wave barrier only keeps the compiler from reordering
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int u = 0; u < kSmallRows; ++u) {
-      if (s0 + u >= s1) break;
-      const float4 *f4 = reinterpret_cast<const float4 *>(&Fs[s0 + u][0]);
+      const float4 *f4 = reinterpret_cast<const float4 *>(Fw + u * RM);
 #pragma unroll
       for (int r4 = 0; r4 < RM / 4; ++r4) {
         const float4 f = f4[r4];
@@ -78,41 +93,47 @@ __global__ __launch_bounds__(64 * kSmallWaves) void ttm_small_k(const float *__r
         acc[4 * r4 + 3] = fmaf(f.w, x[u], acc[4 * r4 + 3]);
       }
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
   }
+  __syncthreads();  // every wave is done with the factor rows
+  float *red = sm;  // red[w][r][64]
 #pragma unroll
-  for (int h = 0; h < RM; h += RH) {
-#pragma unroll
-    for (int r = 0; r < RH; ++r) red[w][r][lane] = acc[h + r];
-    __syncthreads();
-    for (int idx = tid; idx < RH * 64; idx += 64 * kSmallWaves) {
-      const int r = h + (idx >> 6), l = idx & 63;
-      const int64_t e2 = (int64_t)blockIdx.x * 64 + l;
-      if (r >= R || e2 >= PQ) continue;
-      float s2 = red[0][r - h][l];
-#pragma unroll
-      for (int ww = 1; ww < kSmallWaves; ++ww) s2 += red[ww][r - h][l];
-      const int64_t p2 = e2 / Q, q2 = e2 - (e2 / Q) * Q;
-      out[(p2 * R + r) * Q + q2] = s2;
-    }
-    __syncthreads();
+  for (int r = 0; r < RM; ++r) red[(w * RM + r) * 64 + lane] = acc[r];
+  __syncthreads();
+  for (int idx = tid; idx < RM * 64; idx += 64 * W) {
+    const int r = idx >> 6, l = idx & 63;
+    const int64_t e2 = (int64_t)blockIdx.x * 64 + l;
+    if (r >= R || e2 >= PQ) continue;
+    float s2 = red[r * 64 + l];
+    for (int ww = 1; ww < W; ++ww) s2 += red[(ww * RM + r) * 64 + l];
+    const int64_t p2 = e2 / Q, q2 = e2 - (e2 / Q) * Q;
+    out[(p2 * R + r) * Q + q2] = s2;
   }
 }
 
 nnc_status launch_ttm_small(const float *in, int64_t P, int64_t N, int64_t Q, const float *F,
                             int64_t ldl, int64_t ldr, int64_t R, float *out, hipStream_t s) {
   if (R > 32) return fail(NNC_EUNSUPPORTED, "ttm_small: R %lld above 32", (long long)R);
-  const int64_t blocks = (P * Q + 63) / 64;
-  if (blocks > 0x7fffffff) return fail(NNC_EUNSUPPORTED, "ttm_small: too many blocks");
-  const dim3 g((unsigned)blocks), b(64 * kSmallWaves);
-  if (R <= 8)
-    hipLaunchKernelGGL(ttm_small_k<8>, g, b, 0, s, in, P, N, Q, F, ldl, ldr, (int)R, out);
-  else if (R <= 16)
-    hipLaunchKernelGGL(ttm_small_k<16>, g, b, 0, s, in, P, N, Q, F, ldl, ldr, (int)R, out);
-  else if (R <= 24)
-    hipLaunchKernelGGL(ttm_small_k<24>, g, b, 0, s, in, P, N, Q, F, ldl, ldr, (int)R, out);
-  else
-    hipLaunchKernelGGL(ttm_small_k<32>, g, b, 0, s, in, P, N, Q, F, ldl, ldr, (int)R, out);
+  if (N < 1) return fail(NNC_EUNSUPPORTED, "ttm_small: empty contraction");
+  const int64_t tiles = (P * Q + 63) / 64;
+  if (tiles > 0x7fffffff) return fail(NNC_EUNSUPPORTED, "ttm_small: too many blocks");
+  const int W = small_waves(N);
+  const int RM = (int)((R + 3) / 4 * 4);
+  const size_t lds = small_lds(W, RM);
+  const dim3 g((unsigned)tiles), b(64 * W);
+#define NNC_SMALL(RMV) \
+  hipLaunchKernelGGL(ttm_small_k<RMV>, g, b, lds, s, in, P, N, Q, F, ldl, ldr, (int)R, out)
+  switch (RM / 4) {
+    case 1: NNC_SMALL(4); break;
+    case 2: NNC_SMALL(8); break;
+    case 3: NNC_SMALL(12); break;
+    case 4: NNC_SMALL(16); break;
+    case 5: NNC_SMALL(20); break;
+    case 6: NNC_SMALL(24); break;
+    case 7: NNC_SMALL(28); break;
+    default: NNC_SMALL(32); break;
+  }
+#undef NNC_SMALL
   NNC_HIP(hipGetLastError());
   return NNC_OK;
 }
@@ -126,6 +147,22 @@ nnc_status launch_ttm_small(const float *in, int64_t P, int64_t N, int64_t Q, co
 // fixed order) and, with gpart (last mode, q range 1), its share of the core numerator
 // gpart[block][p][r] = sum_{i in block} Y[p][i] * Anew[i][r].
 // =====================================================================================
+// Division of nonnegative ints below 2^31 by an invariant divisor d >= 1 through a
+// multiply-high and a shift (Granlund and Montgomery, PLDI 1994): with l = ceil(log2 d) and
+// m = floor(2^32 (2^l - d) / d) + 1, a / d = (mulhi(a, m) + a) >> l; the sum stays below 2^32.
+struct UDiv {
+  unsigned m, l;
+};
+static __device__ inline UDiv make_udiv(int d) {
+  const unsigned ud = (unsigned)d;
+  const unsigned l = ud <= 1 ? 0u : 32u - (unsigned)__clz(ud - 1);
+  const unsigned long long m = ((((1ull << l) - ud) << 32) / ud) + 1;
+  return {(unsigned)m, l};
+}
+static __device__ inline int udiv(int a, UDiv d) {
+  return (int)((__umulhi((unsigned)a, d.m) + (unsigned)a) >> d.l);
+}
+
 constexpr int kRB = 8;
 constexpr int kRowThreads = 512;
 constexpr int kRowBatch = 16;           // loads in flight per thread while staging
@@ -150,7 +187,11 @@ static __device__ inline void staged_copy(int n, Load ld, Store st) {
   }
 }
 
-// LDS: Gs[CH][R+1] | Ys[kRB][CH+1]  (dynamic), As, Ms (static)
+// LDS: Gs[CH][R+1] | Ys[kRB][CH+1]  (dynamic), As, Ms, red (static).
+// Every global read of a chunk (the core columns, the Y rows, and with the first chunk the
+// factor rows and M) is issued before the first is used.  Output (i, r) is summed by
+// kRowThreads / (kRB * R) threads over contiguous ranges of the chunk, each with eight
+// interleaved partial sums; the pieces are added in a fixed order.
 __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict__ Y,
                                                          const float *__restrict__ G,
                                                          float *__restrict__ A,
@@ -163,6 +204,7 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
   extern __shared__ __attribute__((aligned(16))) float dynr[];
   __shared__ float As[kRB][33];
   __shared__ float Ms[32][33];
+  __shared__ float red[kRowThreads];
   __shared__ unsigned int nclip;
   const int GS = R + 1, YS = CH + 1;
   float *Gs = dynr;
@@ -171,46 +213,89 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
   const int i0 = blockIdx.x * kRB;
   const int nr = (Nn - i0) < kRB ? (Nn - i0) : kRB;
   const int C = pre * post;
-  const int ii = tid / R, r = tid - (tid / R) * R;
-  const bool act = tid < nr * R;
+  const int OR = kRB * R;                               // outputs of a full block
+  const int SPL = kRowThreads / OR;                     // threads per output (>= 2 for R <= 32)
+  const int o = tid % OR, sp = tid / OR;
+  const int ii = o / R, r = o - (o / R) * R;
+  const bool act = sp < SPL && ii < nr;
   if (tid == 0) nclip = 0;
-  float acc = 0.f;
+  float acc8[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) acc8[j] = 0.f;
+  // factor rows and M (first round, with the first chunk's reads)
+  const int ai = tid < nr * R ? tid : 0;
+  const float av = A[(int64_t)(i0 + ai / R) * R + ai % R];
+  const int RR = R * R;
+  const float mv0 = M[tid < RR ? tid : 0];
+  const float mv1 = M[tid + kRowThreads < RR ? tid + kRowThreads : 0];
+  constexpr int kStage = 28;  // 14K staged floats over 512 threads
+  const UDiv dR = make_udiv(R), dpost = make_udiv(post);
   for (int c0 = 0; c0 < C; c0 += CH) {
     const int cn = (C - c0) < CH ? (C - c0) : CH;
-    staged_copy(
-        cn * R,
-        [&](int idx) {
-          const int cc = idx / R, rr = idx - (idx / R) * R;
-          const int c = c0 + cc, pp = c / post, q = c - (c / post) * post;
-          return G[((int64_t)pp * R + rr) * post + q];
-        },
-        [&](int idx, float v) { Gs[(idx / R) * GS + idx % R] = v; });
-    staged_copy(
-        nr * cn,
-        [&](int idx) {
-          const int i = idx / cn, cc = idx - (idx / cn) * cn;
-          const int c = c0 + cc, pp = c / post, q = c - (c / post) * post;
-          return Y[((int64_t)pp * Nn + i0 + i) * post + q];
-        },
-        [&](int idx, float v) { Ys[(idx / cn) * YS + idx % cn] = v; });
+    const int ng = cn * R, ny = nr * cn;
+    const int ntot = ng + ny;
+    const UDiv dcn = make_udiv(cn);
+    for (int base = 0; base < ntot; base += kStage * kRowThreads) {
+      float v[kStage];
+      int off[kStage];
+#pragma unroll
+      for (int u = 0; u < kStage; ++u) {
+        int idx = base + tid + u * kRowThreads;
+        idx = idx < ntot ? idx : ntot - 1;  // the last value again: same address, same value
+        const bool isg = idx < ng;
+        const int j = idx - ng;
+        int cc, rr, i;
+        if (isg) {
+          cc = udiv(idx, dR);
+          rr = idx - cc * R;
+          i = 0;
+        } else {
+          i = udiv(j, dcn);
+          cc = j - i * cn;
+          rr = 0;
+        }
+        const int c = c0 + cc, pp = udiv(c, dpost), q = c - pp * post;
+        const float *src = isg ? G + ((int64_t)pp * R + rr) * post + q
+                               : Y + ((int64_t)pp * Nn + i0 + i) * post + q;
+        v[u] = *src;
+        off[u] = isg ? cc * GS + rr : CH * GS + i * YS + cc;
+      }
+#pragma unroll
+      for (int u = 0; u < kStage; ++u) dynr[off[u]] = v[u];
+    }
+    if (c0 == 0) {
+      if (tid < nr * R) As[tid / R][tid % R] = av;
+      if (tid < RR) Ms[tid / R][tid % R] = mv0;
+      if (tid + kRowThreads < RR) Ms[(tid + kRowThreads) / R][(tid + kRowThreads) % R] = mv1;
+    }
     __syncthreads();
     if (act) {
       const float *yrow = Ys + ii * YS;
       const float *gcol = Gs + r;
-      for (int cc = 0; cc < cn; ++cc) acc = fmaf(yrow[cc], gcol[cc * GS], acc);
+      const int a0 = cn * sp / SPL, a1 = cn * (sp + 1) / SPL;
+      int cc = a0;
+      for (; cc + 8 <= a1; cc += 8) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc8[j] = fmaf(yrow[cc + j], gcol[(cc + j) * GS], acc8[j]);
+      }
+      for (int j = 0; cc < a1; ++cc, ++j) acc8[j] = fmaf(yrow[cc], gcol[cc * GS], acc8[j]);
     }
     __syncthreads();
   }
-  for (int idx = tid; idx < nr * R; idx += kRowThreads) {
-    const int i = idx / R, rr = idx - (idx / R) * R;
-    As[i][rr] = A[(int64_t)(i0 + i) * R + rr];
-  }
-  for (int idx = tid; idx < R * R; idx += kRowThreads) Ms[idx / R][idx % R] = M[idx];
+  // the pieces of output (i, r): eight partial sums per thread, then the threads in order
+  float accs = 0.f;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) accs += acc8[j];
+  red[tid] = act ? accs : 0.f;
   __syncthreads();
+  const bool own = tid < nr * R;  // thread tid owns output (tid / R, tid % R) from here
+  const int oi = tid / R, orr = tid - (tid / R) * R;
   float nv = 0.f;
-  if (act) {
+  if (own) {
+    float acc = 0.f;
+    for (int k = 0; k < SPL; ++k) acc += red[k * OR + tid];
     float den = 0.f;
-    for (int s2 = 0; s2 < R; ++s2) den = fmaf(As[ii][s2], Ms[s2][r], den);
+    for (int s2 = 0; s2 < R; ++s2) den = fmaf(As[oi][s2], Ms[s2][orr], den);
     if (grad) {
       nv = den - acc;
     } else {
@@ -219,22 +304,22 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
         dd = eps;
         atomicAdd(&nclip, 1u);
       }
-      nv = (float)(((double)As[ii][r] * (double)acc) / dd);
+      nv = (float)(((double)As[oi][orr] * (double)acc) / dd);
     }
   }
   __syncthreads();
-  if (act) {
+  if (own) {
     if (grad) {
-      grad[(int64_t)(i0 + ii) * R + r] = nv;
+      grad[(int64_t)(i0 + oi) * R + orr] = nv;
     } else {
-      A[(int64_t)(i0 + ii) * R + r] = nv;
-      As[ii][r] = nv;
+      A[(int64_t)(i0 + oi) * R + orr] = nv;
+      As[oi][orr] = nv;
     }
   }
   __syncthreads();
   if (tid == 0 && nclip) atomicAdd(clips, (unsigned long long)nclip);
   if (grad) return;
-  if (gram) {  // Gram of this block's new rows
+  if (gram) {  // Gram of this block's new rows (the arithmetic of gram_parts_k)
     float *gb = gram + (int64_t)blockIdx.x * R * R;
     for (int idx = tid; idx < R * R; idx += kRowThreads) {
       const int x = idx / R, y = idx - (idx / R) * R;
@@ -244,25 +329,35 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
     }
   }
   if (gpart) {
-    // last mode: Y is [pre][Nn] (post == 1); stage Y[p][i0..i0+nr) for chunks of p
+    // last mode: Y is [pre][Nn] (post == 1).  gpart[block][p][r] = sum_i Y[p][i0+i] Anew[i][r];
+    // with a single chunk the Y values are still in Ys (Ys[i][p]), else they are read again.
     float *gp = gpart + (int64_t)blockIdx.x * pre * R;
-    const int PC = (CH * GS + kRB * YS) / kRB;  // rows of p per chunk that fit
-    for (int p0 = 0; p0 < pre; p0 += PC) {
-      const int pn = (pre - p0) < PC ? (pre - p0) : PC;
-      __syncthreads();
-      staged_copy(
-          pn * nr,
-          [&](int idx) {
-            const int pp = idx / nr, i = idx - (idx / nr) * nr;
-            return Y[(int64_t)(p0 + pp) * Nn + i0 + i];
-          },
-          [&](int idx, float v) { dynr[idx] = v; });
-      __syncthreads();
-      for (int idx = tid; idx < pn * R; idx += kRowThreads) {
+    if (C <= CH) {
+      for (int idx = tid; idx < pre * R; idx += kRowThreads) {
         const int pp = idx / R, rr = idx - (idx / R) * R;
         float s2 = 0.f;
-        for (int i = 0; i < nr; ++i) s2 = fmaf(dynr[pp * nr + i], As[i][rr], s2);
-        gp[(int64_t)(p0 + pp) * R + rr] = s2;
+        for (int i = 0; i < nr; ++i) s2 = fmaf(Ys[i * YS + pp], As[i][rr], s2);
+        gp[(int64_t)pp * R + rr] = s2;
+      }
+    } else {
+      const int PC = (CH * GS + kRB * YS) / kRB;  // rows of p per chunk that fit
+      for (int p0 = 0; p0 < pre; p0 += PC) {
+        const int pn = (pre - p0) < PC ? (pre - p0) : PC;
+        __syncthreads();
+        staged_copy(
+            pn * nr,
+            [&](int idx) {
+              const int pp = idx / nr, i = idx - (idx / nr) * nr;
+              return Y[(int64_t)(p0 + pp) * Nn + i0 + i];
+            },
+            [&](int idx, float v) { dynr[idx] = v; });
+        __syncthreads();
+        for (int idx = tid; idx < pn * R; idx += kRowThreads) {
+          const int pp = idx / R, rr = idx - (idx / R) * R;
+          float s2 = 0.f;
+          for (int i = 0; i < nr; ++i) s2 = fmaf(dynr[pp * nr + i], As[i][rr], s2);
+          gp[(int64_t)(p0 + pp) * R + rr] = s2;
+        }
       }
     }
   }

@@ -129,7 +129,15 @@ def _fit_gpu(nnc, X, G0, A0, iters, dt="f32", **kw):
 
 @pytest.mark.parametrize("dims,ranks", [((40, 40, 40), (5, 5, 5)), ((37, 29, 18), (4, 3, 5)),
                                         ((12, 10, 9, 8), (3, 4, 2, 5)), ((6, 5, 8, 4, 7), (2, 3, 2, 2, 3)),
-                                        ((50, 44), (4, 6)), ((4, 4, 4), (5, 5, 5))])
+                                        ((50, 44), (4, 6)), ((4, 4, 4), (5, 5, 5)),
+                                        # core slices wider than one staged chunk of the row
+                                        # update (several chunks, a ragged last one)
+                                        ((14, 13, 12, 11), (10, 10, 10, 10)),
+                                        ((40, 36, 34), (32, 32, 32)),
+                                        # small contractions split over blocks along the
+                                        # contracted mode (ragged splits, two rounds each)
+                                        ((300, 40, 260), (4, 5, 6)),
+                                        ((45, 1100, 37), (3, 7, 2))])
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_nntucker_few_sweeps_match_oracle(dims, ranks, use_graph):
     nnc = need_gpu()
