@@ -457,6 +457,8 @@ static nnc_status fused_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, 
                      b.P(), s, true, nullptr, reserve1));
   if (tm) NNC_TRY(tm->stop(s));
   const float *U = b.P();
+  CoreArgsHost deferred;
+  bool have_deferred = false;
   for (int n = 0; n < d - 1; ++n) {
     int64_t cur[kMaxDim];
     for (int k = 0; k < d; ++k) cur[k] = (k < n || k == d - 1) ? p.R[k] : p.N[k];
@@ -482,13 +484,20 @@ static nnc_status fused_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, 
       NNC_HIP(hipStreamWaitEvent(ss->s, ss->fork[n], 0));
       NNC_TRY(launch_core_step(h, ss->s));
       NNC_HIP(hipEventRecord(ss->join[n], ss->s));
-    } else {
-      NNC_TRY(launch_core_step(h, s));
-    }
-    if (n < d - 2) {
+      if (n < d - 2) {
+        float *Un = b.U(n % 2);
+        NNC_TRY(ttm_f32(U, d, cur, n, A[n], p.R[n], Un, s));
+        U = Un;
+      }
+    } else if (n < d - 2) {
+      // the core step and U_{n+1} = U_n x_n A_n^T do not depend on each other: one launch
       float *Un = b.U(n % 2);
-      NNC_TRY(ttm_f32(U, d, cur, n, A[n], p.R[n], Un, s));
+      NNC_TRY(launch_small_with_core(U, prod(cur, 0, n), cur[n], prod(cur, n + 1, d), A[n], p.R[n],
+                                     1, p.R[n], Un, h, s));
       U = Un;
+    } else {
+      deferred = h;  // M_{d-1} is not needed before the last mode: it shares a later launch
+      have_deferred = true;
     }
   }
   if (tm) NNC_TRY(tm->start(s));
@@ -500,7 +509,20 @@ static nnc_status fused_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, 
   int modes[kMaxDim], nm = 0;
   for (int k = 1; k < d - 1; ++k) modes[nm++] = k;
   const float *Y = nullptr;
-  NNC_TRY(chain_small(b.T(), d, cur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
+  if (have_deferred && nm > 0) {
+    // the first contraction of the chain shares its launch with the deferred core step
+    const int k = modes[0];
+    float *out = (nm == 1) ? b.Y() : b.C(0);
+    NNC_TRY(launch_small_with_core(b.T(), prod(cur, 0, k), cur[k], prod(cur, k + 1, d), A[k], p.R[k],
+                                   1, p.R[k], out, deferred, s));
+    cur[k] = p.R[k];
+    // the rest of the chain continues from `out` (ping-pong buffers shifted by one)
+    NNC_TRY(chain_small(out, d, cur, modes + 1, nm - 1, A, p.R, b.C(1), b.C(0), b.Y(), &Y, s));
+    if (nm == 1) Y = out;
+  } else {
+    if (have_deferred) NNC_TRY(launch_core_step(deferred, s));
+    NNC_TRY(chain_small(b.T(), d, cur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
+  }
   if (ov) NNC_HIP(hipStreamWaitEvent(s, ss->join[d - 2], 0));  // M_{d-1}; joins the side stream
   NNC_TRY(launch_mu_rows(Y, G, A[d - 1], b.M(), prod(p.R, 0, d - 1), p.N[d - 1], 1, p.R[d - 1], eps,
                          b.clips(), b.gram(), b.gpart(), nullptr, s));
@@ -519,6 +541,8 @@ static nnc_status tucker_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt,
                      b.P(), s, true));
   if (tm) NNC_TRY(tm->stop(s));
   const float *U = b.P();
+  CoreArgsHost deferred;
+  bool have_deferred = false;
   for (int n = 0; n < d - 1; ++n) {
     int64_t cur[kMaxDim];
     for (int k = 0; k < d; ++k) cur[k] = (k < n || k == d - 1) ? p.R[k] : p.N[k];

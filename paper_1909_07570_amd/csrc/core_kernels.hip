@@ -232,7 +232,7 @@ static __device__ float *contract_slice(const SliceArgs &a, int skip, const floa
 // Row a = blockIdx.x of M_n (and, with a.gram >= 0, the new Gram of mode a.gram).  With
 // a.n < 0 only the Gram is formed (one block).
 template <int RM, bool BIG>
-__global__ __launch_bounds__(kSliceThreads) void mrows_k(SliceArgs a) {
+static __device__ void mrows_body(const SliceArgs &a, int ia) {
   extern __shared__ __attribute__((aligned(16))) float lds[];
   const int d = a.d, tid = threadIdx.x;
   float *Sl = lds;
@@ -266,7 +266,6 @@ __global__ __launch_bounds__(kSliceThreads) void mrows_k(SliceArgs a) {
   gs.finish(a, Sl, red);
   __syncthreads();
   if (n < 0) return;
-  const int ia = blockIdx.x;
   int pre = 1, post = 1;
   for (int k = 0; k < n; ++k) pre *= a.R[k];
   for (int k = n + 1; k < d; ++k) post *= a.R[k];
@@ -300,6 +299,11 @@ __global__ __launch_bounds__(kSliceThreads) void mrows_k(SliceArgs a) {
     for (int c = 0; c < nchunk; ++c) s += red[c * Rn + tid];
     a.M[ia * Rn + tid] = s;
   }
+}
+
+template <int RM, bool BIG>
+__global__ __launch_bounds__(kSliceThreads) void mrows_k(SliceArgs a) {
+  mrows_body<RM, BIG>(a, blockIdx.x);
 }
 
 // T_i = G[i, ..] x_1 S_1 ... x_{d-1} S_{d-1} for i = blockIdx.x (and the new Gram of a.gram).
@@ -361,6 +365,164 @@ __global__ __launch_bounds__(kSliceThreads) void denB_k(SliceArgs a) {
   if (tid == 0 && nclip) atomicAdd(a.clips, (unsigned long long)nclip);
 }
 
+// =====================================================================================
+// out[p][r][q] = sum_n F[n*ldl + r*ldr] * in[p][n][q]   (R <= 32, FP32)
+// A block owns 64 consecutive (p, q) pairs, one per lane, and W = ceil(N / 32) waves (at
+// most 16), so that one round covers up to 512 rows of n with 32 rows per wave: each wave
+// issues its 32 X loads of the round before the first product, while the block stages the
+// round's factor rows in LDS (zero-padded to RM columns and past N, so rows past the end
+// contribute nothing).  The wave partial sums are added in wave order through LDS, which
+// the factor rows of the last round no longer need.  Adding splits of n in a second
+// pass or through a device-scope counter would give more blocks when P*Q is small, but
+// the release fence such a counter needs writes back the whole L2 of the XCD, which has
+// cost far more than the extra parallelism saves.
+// =====================================================================================
+constexpr int kSmallRows = 32;     // rows of n per wave and round
+constexpr int kSmallMaxWaves = 16;
+
+static int small_waves(int64_t N) {
+  const int64_t w = (N + kSmallRows - 1) / kSmallRows;
+  return (int)(w < 1 ? 1 : (w > kSmallMaxWaves ? kSmallMaxWaves : w));
+}
+// LDS of a block: the factor rows of a round (W*32 rows of RM) or the wave partial sums
+// (W of RM x 64), whichever is larger.
+static size_t small_lds(int W, int RM) { return (size_t)W * 64 * RM * sizeof(float); }
+
+struct SmallArgs {
+  const float *in;
+  int64_t P, N, Q;
+  const float *F;
+  int64_t ldl, ldr;
+  int R;
+  float *out;
+  int W;  // waves that take rows (the block may hold more, which then only join barriers)
+};
+
+// Tile `tile` of the contraction; blockDim.x / 64 >= a.W.
+template <int RM>
+static __device__ void small_body(const SmallArgs &a, int64_t tile) {
+  extern __shared__ __attribute__((aligned(16))) float sm[];
+  const float *__restrict__ in = a.in;
+  const float *__restrict__ F = a.F;
+  float *__restrict__ out = a.out;
+  const int64_t P = a.P, N = a.N, Q = a.Q, ldl = a.ldl, ldr = a.ldr;
+  const int R = a.R, W = a.W;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const bool active = w < W;
+  const int64_t PQ = P * Q;
+  const int64_t e = tile * 64 + lane;
+  const int64_t ee = e < PQ ? e : 0;
+  const int64_t p = ee / Q, q = ee - (ee / Q) * Q;
+  const float *src = in + p * N * Q + q;
+  const int span = W * kSmallRows;  // rows of a round
+  float acc[RM];
+#pragma unroll
+  for (int r = 0; r < RM; ++r) acc[r] = 0.f;
+  for (int64_t nb = 0; active && nb < N; nb += span) {
+    float x[kSmallRows];
+#pragma unroll
+    for (int u = 0; u < kSmallRows; ++u) {
+      int64_t n = nb + w * kSmallRows + u;
+      n = n < N ? n : N - 1;  // rows past N meet zero factor rows
+      x[u] = src[n * Q];
+    }
+    // factor rows [nb, nb + span): RM * 32 values per wave, the wave's own rows
+    constexpr int kStage = RM / 2;  // 32 * RM values over 64 lanes
+    float v[kStage];
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      const int idx = lane + u * 64;
+      const int nn = idx / RM, r = idx - (idx / RM) * RM;
+      const int64_t n = nb + w * kSmallRows + nn;
+      const bool ok = n < N && r < R;
+      v[u] = F[(ok ? n : 0) * ldl + (ok ? r : 0) * ldr];
+    }
+    float *Fw = sm + w * kSmallRows * RM;
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {  // zeros masked in here, where the values are awaited
+      const int idx = lane + u * 64;
+      const int nn = idx / RM, r = idx - (idx / RM) * RM;
+      Fw[idx] = (nb + w * kSmallRows + nn < N && r < R) ? v[u] : 0.f;
+    }
+    // each wave reads only the rows it staged itself, and a wave's LDS operations take
+    // effect in issue order: the wave barrier only keeps the compiler from reordering
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int u = 0; u < kSmallRows; ++u) {
+      const float4 *f4 = reinterpret_cast<const float4 *>(Fw + u * RM);
+#pragma unroll
+      for (int r4 = 0; r4 < RM / 4; ++r4) {
+        const float4 f = f4[r4];
+        acc[4 * r4 + 0] = fmaf(f.x, x[u], acc[4 * r4 + 0]);
+        acc[4 * r4 + 1] = fmaf(f.y, x[u], acc[4 * r4 + 1]);
+        acc[4 * r4 + 2] = fmaf(f.z, x[u], acc[4 * r4 + 2]);
+        acc[4 * r4 + 3] = fmaf(f.w, x[u], acc[4 * r4 + 3]);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();  // every wave is done with the factor rows
+  float *red = sm;  // red[w][r][64]
+  if (active) {
+#pragma unroll
+    for (int r = 0; r < RM; ++r) red[(w * RM + r) * 64 + lane] = acc[r];
+  }
+  __syncthreads();
+  for (int idx = tid; idx < RM * 64; idx += blockDim.x) {
+    const int r = idx >> 6, l = idx & 63;
+    const int64_t e2 = tile * 64 + l;
+    if (r >= R || e2 >= PQ) continue;
+    float s2 = red[r * 64 + l];
+    for (int ww = 1; ww < W; ++ww) s2 += red[(ww * RM + r) * 64 + l];
+    const int64_t p2 = e2 / Q, q2 = e2 - (e2 / Q) * Q;
+    out[(p2 * R + r) * Q + q2] = s2;
+  }
+}
+
+template <int RM>
+__global__ __launch_bounds__(64 * kSmallMaxWaves) void ttm_small_k(SmallArgs a) {
+  small_body<RM>(a, blockIdx.x);
+}
+
+static bool small_args(const float *in, int64_t P, int64_t N, int64_t Q, const float *F,
+                       int64_t ldl, int64_t ldr, int64_t R, float *out, SmallArgs *a, int *RM,
+                       int64_t *tiles) {
+  if (R > 32 || R < 1 || N < 1) return false;
+  *tiles = (P * Q + 63) / 64;
+  if (*tiles > 0x7fffffff) return false;
+  *a = SmallArgs{in, P, N, Q, F, ldl, ldr, (int)R, out, small_waves(N)};
+  *RM = (int)((R + 3) / 4 * 4);
+  return true;
+}
+
+nnc_status launch_ttm_small(const float *in, int64_t P, int64_t N, int64_t Q, const float *F,
+                            int64_t ldl, int64_t ldr, int64_t R, float *out, hipStream_t s) {
+  SmallArgs a;
+  int RM;
+  int64_t tiles;
+  if (!small_args(in, P, N, Q, F, ldl, ldr, R, out, &a, &RM, &tiles))
+    return fail(NNC_EUNSUPPORTED, "ttm_small: R %lld, N %lld or P*Q out of range", (long long)R,
+                (long long)N);
+  const size_t lds = small_lds(a.W, RM);
+  const dim3 g((unsigned)tiles), b(64 * a.W);
+#define NNC_SMALL(RMV) hipLaunchKernelGGL(ttm_small_k<RMV>, g, b, lds, s, a)
+  switch (RM / 4) {
+    case 1: NNC_SMALL(4); break;
+    case 2: NNC_SMALL(8); break;
+    case 3: NNC_SMALL(12); break;
+    case 4: NNC_SMALL(16); break;
+    case 5: NNC_SMALL(20); break;
+    case 6: NNC_SMALL(24); break;
+    case 7: NNC_SMALL(28); break;
+    default: NNC_SMALL(32); break;
+  }
+#undef NNC_SMALL
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
 static nnc_status allow_slice_lds(const void *kern, size_t bytes) {
   static std::mutex mu;
   static std::map<const void *, size_t> done;
@@ -373,8 +535,7 @@ static nnc_status allow_slice_lds(const void *kern, size_t bytes) {
   return NNC_OK;
 }
 
-template <int RM, bool BIG>
-static nnc_status slice_step(const CoreArgsHost &h, hipStream_t s) {
+static SliceArgs slice_args(const CoreArgsHost &h) {
   SliceArgs a;
   memset(&a, 0, sizeof a);
   a.d = h.d;
@@ -392,6 +553,12 @@ static nnc_status slice_step(const CoreArgsHost &h, hipStream_t s) {
   a.gram_parts = h.gram_parts;
   a.eps = h.eps;
   a.clips = h.clips;
+  return a;
+}
+
+template <int RM, bool BIG>
+static nnc_status slice_step(const CoreArgsHost &h, hipStream_t s) {
+  SliceArgs a = slice_args(h);
   if (h.do_core) {
     // T = G x_1 S_1 ... (the new Gram formed on the way), then the update
     a.T = h.t0;
@@ -420,30 +587,98 @@ static nnc_status slice_step(const CoreArgsHost &h, hipStream_t s) {
 }
 
 // Returns NNC_EUNSUPPORTED (no error recorded) when the core is too large for these kernels.
-nnc_status launch_slice_step(const CoreArgsHost &h, hipStream_t s) {
+// Whether the slice kernels take this core; the Gram row stride RM and the core-size variant.
+static bool slice_fits(const CoreArgsHost &h, int *RMo, bool *bigo) {
   int64_t gsize = 1;
   int maxr = 1;
   for (int k = 0; k < h.d; ++k) {
     gsize *= h.R[k];
     maxr = std::max(maxr, (int)h.R[k]);
   }
-  if (gsize > kSliceMax || maxr > 32 || h.gram_to - h.gram_from > 1) return NNC_EUNSUPPORTED;
+  if (gsize > kSliceMax || maxr > 32 || h.gram_to - h.gram_from > 1) return false;
   // the Grams must be packed one after another (the fit's workspace keeps them so)
   for (int64_t k = 1, off = h.R[0] * h.R[0]; k < h.d; off += h.R[k] * h.R[k], ++k)
-    if (h.S[k] != h.S[0] + off) return NNC_EUNSUPPORTED;
+    if (h.S[k] != h.S[0] + off) return false;
   // LDS of the largest launch (the whole core and two slices at worst)
   const int RM = maxr <= 8 ? 8 : (maxr <= 16 ? 16 : (maxr <= 24 ? 24 : 32));
   int64_t worst = 0;
   for (int k = 0; k < h.d; ++k) worst = std::max(worst, gsize / h.R[k]);
   const int64_t need = 4 * ((int64_t)h.d * RM * RM + 4 * kSliceThreads + gsize + 2 * worst);
-  if (need > 160 * 1024) return NNC_EUNSUPPORTED;
-  const bool big = gsize > kSliceMax / 2;
+  if (need > 160 * 1024) return false;
+  *RMo = RM;
+  *bigo = gsize > kSliceMax / 2;
+  return true;
+}
+
+nnc_status launch_slice_step(const CoreArgsHost &h, hipStream_t s) {
+  int RM;
+  bool big;
+  if (!slice_fits(h, &RM, &big)) return NNC_EUNSUPPORTED;
 #define NNC_SLICE(RMV) return big ? slice_step<RMV, true>(h, s) : slice_step<RMV, false>(h, s)
-  if (maxr <= 8) NNC_SLICE(8);
-  if (maxr <= 16) NNC_SLICE(16);
-  if (maxr <= 24) NNC_SLICE(24);
+  if (RM == 8) NNC_SLICE(8);
+  if (RM == 16) NNC_SLICE(16);
+  if (RM == 24) NNC_SLICE(24);
   NNC_SLICE(32);
 #undef NNC_SLICE
+}
+
+// =====================================================================================
+// One launch for two independent steps: blocks [0, nm) build the rows of M_next (with the
+// new Gram of the factor just updated), blocks [nm, nm + tiles) contract a partial tensor
+// (small_body).  Each step alone leaves most CUs idle for most of its time, and the two
+// do not depend on each other, so sharing a launch runs them side by side without the
+// cost of a second stream.
+// =====================================================================================
+template <int RMS, int RMC, bool BIG>
+__global__ __launch_bounds__(kSliceThreads) void small_mrows_k(SmallArgs sa, SliceArgs ca, int nm) {
+  if ((int)blockIdx.x < nm)
+    mrows_body<RMC, BIG>(ca, blockIdx.x);
+  else
+    small_body<RMS>(sa, (int64_t)blockIdx.x - nm);
+}
+
+nnc_status launch_small_with_core(const float *in, int64_t P, int64_t N, int64_t Q, const float *F,
+                                  int64_t ldl, int64_t ldr, int64_t R, float *out,
+                                  const CoreArgsHost &h, hipStream_t s) {
+  SmallArgs sa;
+  int RMS, RMC;
+  int64_t tiles;
+  bool big;
+  // the shared launch covers a core step that only forms a Gram and M_next
+  const bool ok = !h.do_core && h.next >= 0 && slice_fits(h, &RMC, &big) &&
+                  small_args(in, P, N, Q, F, ldl, ldr, R, out, &sa, &RMS, &tiles) &&
+                  (RMS == RMC || RMS == RMC - 4) && tiles + h.R[h.next] <= 0x7fffffff;
+  if (!ok) {
+    NNC_TRY(launch_core_step(h, s));
+    return launch_ttm_small(in, P, N, Q, F, ldl, ldr, R, out, s);
+  }
+  SliceArgs ca = slice_args(h);
+  ca.n = h.next;
+  ca.M = h.M;
+  const int nm = (int)h.R[h.next];
+  size_t lds = 0;
+#define NNC_SM(RMSV, RMCV, BIGV)                                                                  \
+  do {                                                                                            \
+    lds = std::max(SliceLds<RMCV>::bytes(ca.d, ca.gsize, ca.gsize / nm, true), small_lds(sa.W, RMSV)); \
+    NNC_TRY(allow_slice_lds(reinterpret_cast<const void *>(small_mrows_k<RMSV, RMCV, BIGV>), lds)); \
+    hipLaunchKernelGGL((small_mrows_k<RMSV, RMCV, BIGV>), dim3((unsigned)(nm + tiles)),            \
+                       dim3(kSliceThreads), lds, s, sa, ca, nm);                                  \
+  } while (0)
+#define NNC_SM2(RMCV)                                  \
+  do {                                                 \
+    if (RMS == RMCV && big) NNC_SM(RMCV, RMCV, true);  \
+    else if (RMS == RMCV) NNC_SM(RMCV, RMCV, false);   \
+    else if (big) NNC_SM(RMCV - 4, RMCV, true);        \
+    else NNC_SM(RMCV - 4, RMCV, false);                \
+  } while (0)
+  if (RMC == 8) NNC_SM2(8);
+  else if (RMC == 16) NNC_SM2(16);
+  else if (RMC == 24) NNC_SM2(24);
+  else NNC_SM2(32);
+#undef NNC_SM2
+#undef NNC_SM
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
 }
 
 }  // namespace nnc

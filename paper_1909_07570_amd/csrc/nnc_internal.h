@@ -148,6 +148,11 @@ struct CoreArgsHost {
   int gram_from, gram_to, do_core, next;
 };
 nnc_status launch_core_step(const CoreArgsHost &h, hipStream_t s);
+// launch_core_step(h) and launch_ttm_small(...) (independent of each other) in one launch
+// when the core step only forms a Gram and M_next; two launches otherwise.
+nnc_status launch_small_with_core(const float *in, int64_t P, int64_t N, int64_t Q, const float *F,
+                                  int64_t ldl, int64_t ldr, int64_t R, float *out,
+                                  const CoreArgsHost &h, hipStream_t s);
 // out[e] = sum_{b < nparts} part[b][e] (fixed order)
 nnc_status launch_sum_parts(const float *part, int nparts, int64_t n, float *out, hipStream_t s);
 

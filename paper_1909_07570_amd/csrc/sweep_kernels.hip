@@ -1,5 +1,4 @@
 // Kernels for the small (non-X-streaming) steps of a multiplicative-update sweep:
-//   ttm_small_k : contraction of an FP32 partial tensor (P x_k A^T), split over waves
 //   mu_rows_k   : fused numerator, denominator and update of a block of factor rows
 //   core_step_k : one workgroup doing the core-space work between mode updates
 //                 (Gram of the new factor, the core update, the next mode's R x R matrix)
@@ -10,133 +9,6 @@
 #include "nnc_internal.h"
 
 namespace nnc {
-
-// =====================================================================================
-// out[p][r][q] = sum_n F[n*ldl + r*ldr] * in[p][n][q]   (R <= 32, FP32)
-// A block owns 64 consecutive (p, q) pairs, one per lane, and W = ceil(N / 32) waves (at
-// most 16), so that one round covers up to 512 rows of n with 32 rows per wave: each wave
-// issues its 32 X loads of the round before the first product, while the block stages the
-// round's factor rows in LDS (zero-padded to RM columns and past N, so rows past the end
-// contribute nothing).  The wave partial sums are added in wave order through LDS, which
-// the factor rows of the last round no longer need.  Adding splits of n in a second
-// pass or through a device-scope counter would give more blocks when P*Q is small, but
-// the release fence such a counter needs writes back the whole L2 of the XCD, which has
-// cost far more than the extra parallelism saves.
-// =====================================================================================
-constexpr int kSmallRows = 32;     // rows of n per wave and round
-constexpr int kSmallMaxWaves = 16;
-
-static int small_waves(int64_t N) {
-  const int64_t w = (N + kSmallRows - 1) / kSmallRows;
-  return (int)(w < 1 ? 1 : (w > kSmallMaxWaves ? kSmallMaxWaves : w));
-}
-// LDS of a block: the factor rows of a round (W*32 rows of RM) or the wave partial sums
-// (W of RM x 64), whichever is larger.
-static size_t small_lds(int W, int RM) { return (size_t)W * 64 * RM * sizeof(float); }
-
-template <int RM>
-__global__ __launch_bounds__(64 * kSmallMaxWaves) void ttm_small_k(
-    const float *__restrict__ in, int64_t P, int64_t N, int64_t Q, const float *__restrict__ F,
-    int64_t ldl, int64_t ldr, int R, float *__restrict__ out) {
-  extern __shared__ __attribute__((aligned(16))) float sm[];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int W = blockDim.x >> 6;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t PQ = P * Q;
-  const int64_t e = (int64_t)blockIdx.x * 64 + lane;
-  const int64_t ee = e < PQ ? e : 0;
-  const int64_t p = ee / Q, q = ee - (ee / Q) * Q;
-  const float *src = in + p * N * Q + q;
-  const int span = W * kSmallRows;  // rows of a round
-  float acc[RM];
-#pragma unroll
-  for (int r = 0; r < RM; ++r) acc[r] = 0.f;
-  for (int64_t nb = 0; nb < N; nb += span) {
-    float x[kSmallRows];
-#pragma unroll
-    for (int u = 0; u < kSmallRows; ++u) {
-      int64_t n = nb + w * kSmallRows + u;
-      n = n < N ? n : N - 1;  // rows past N meet zero factor rows
-      x[u] = src[n * Q];
-    }
-    // factor rows [nb, nb + span): RM * 32 values per wave, the wave's own rows
-    constexpr int kStage = RM / 2;  // 32 * RM values over 64 lanes
-    float v[kStage];
-#pragma unroll
-    for (int u = 0; u < kStage; ++u) {
-      const int idx = lane + u * 64;
-      const int nn = idx / RM, r = idx - (idx / RM) * RM;
-      const int64_t n = nb + w * kSmallRows + nn;
-      const bool ok = n < N && r < R;
-      v[u] = F[(ok ? n : 0) * ldl + (ok ? r : 0) * ldr];
-    }
-    float *Fw = sm + w * kSmallRows * RM;
-#pragma unroll
-    for (int u = 0; u < kStage; ++u) {  // zeros masked in here, where the values are awaited
-      const int idx = lane + u * 64;
-      const int nn = idx / RM, r = idx - (idx / RM) * RM;
-      Fw[idx] = (nb + w * kSmallRows + nn < N && r < R) ? v[u] : 0.f;
-    }
-    // each wave reads only the rows it staged itself, and a wave's LDS operations take
-    // effect in issue order: the wave barrier only keeps the compiler from reordering
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int u = 0; u < kSmallRows; ++u) {
-      const float4 *f4 = reinterpret_cast<const float4 *>(Fw + u * RM);
-#pragma unroll
-      for (int r4 = 0; r4 < RM / 4; ++r4) {
-        const float4 f = f4[r4];
-        acc[4 * r4 + 0] = fmaf(f.x, x[u], acc[4 * r4 + 0]);
-        acc[4 * r4 + 1] = fmaf(f.y, x[u], acc[4 * r4 + 1]);
-        acc[4 * r4 + 2] = fmaf(f.z, x[u], acc[4 * r4 + 2]);
-        acc[4 * r4 + 3] = fmaf(f.w, x[u], acc[4 * r4 + 3]);
-      }
-    }
-    __builtin_amdgcn_wave_barrier();
-  }
-  __syncthreads();  // every wave is done with the factor rows
-  float *red = sm;  // red[w][r][64]
-#pragma unroll
-  for (int r = 0; r < RM; ++r) red[(w * RM + r) * 64 + lane] = acc[r];
-  __syncthreads();
-  for (int idx = tid; idx < RM * 64; idx += 64 * W) {
-    const int r = idx >> 6, l = idx & 63;
-    const int64_t e2 = (int64_t)blockIdx.x * 64 + l;
-    if (r >= R || e2 >= PQ) continue;
-    float s2 = red[r * 64 + l];
-    for (int ww = 1; ww < W; ++ww) s2 += red[(ww * RM + r) * 64 + l];
-    const int64_t p2 = e2 / Q, q2 = e2 - (e2 / Q) * Q;
-    out[(p2 * R + r) * Q + q2] = s2;
-  }
-}
-
-nnc_status launch_ttm_small(const float *in, int64_t P, int64_t N, int64_t Q, const float *F,
-                            int64_t ldl, int64_t ldr, int64_t R, float *out, hipStream_t s) {
-  if (R > 32) return fail(NNC_EUNSUPPORTED, "ttm_small: R %lld above 32", (long long)R);
-  if (N < 1) return fail(NNC_EUNSUPPORTED, "ttm_small: empty contraction");
-  const int64_t tiles = (P * Q + 63) / 64;
-  if (tiles > 0x7fffffff) return fail(NNC_EUNSUPPORTED, "ttm_small: too many blocks");
-  const int W = small_waves(N);
-  const int RM = (int)((R + 3) / 4 * 4);
-  const size_t lds = small_lds(W, RM);
-  const dim3 g((unsigned)tiles), b(64 * W);
-#define NNC_SMALL(RMV) \
-  hipLaunchKernelGGL(ttm_small_k<RMV>, g, b, lds, s, in, P, N, Q, F, ldl, ldr, (int)R, out)
-  switch (RM / 4) {
-    case 1: NNC_SMALL(4); break;
-    case 2: NNC_SMALL(8); break;
-    case 3: NNC_SMALL(12); break;
-    case 4: NNC_SMALL(16); break;
-    case 5: NNC_SMALL(20); break;
-    case 6: NNC_SMALL(24); break;
-    case 7: NNC_SMALL(28); break;
-    default: NNC_SMALL(32); break;
-  }
-#undef NNC_SMALL
-  NNC_HIP(hipGetLastError());
-  return NNC_OK;
-}
 
 // =====================================================================================
 // Fused multiplicative update of rows [i0, i0 + kRB) of factor A_n (N_n x R, R <= 32):
