@@ -341,7 +341,7 @@ static nnc_status fused_prologue(const TuckerBufs &b, float *G, float *const *A,
     h.gram = b.gram();
     h.gram_parts = (int)mu_rows_blocks(p.N[k]);
     h.gram_stride = stride;
-    h.next = (k == p.d - 1) ? 0 : -1;
+    h.next = -1;
     NNC_TRY(launch_core_step(h, s));
   }
   return NNC_OK;
@@ -368,34 +368,9 @@ static nnc_status chain_small(const float *src, int d, int64_t *cur, const int *
   return NNC_OK;
 }
 
-// A second stream (default priority) and fork/join events: the core-space step of mode n
-// runs beside the next mode's contraction (or pass 2), which does not depend on it.
-struct SideStream {
-  hipStream_t s = nullptr;
-  hipEvent_t fork[kMaxDim] = {}, join[kMaxDim] = {};
-  hipEvent_t tail_fork = nullptr, tail_join = nullptr;  // the deferred core step of a sweep
-  bool ok = false;
-};
-
-static SideStream *side_stream() {
-  static std::mutex mu;
-  static SideStream ss;
-  std::lock_guard<std::mutex> lk(mu);
-  if (!ss.ok) {
-    if (hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking) != hipSuccess) return nullptr;
-    for (int k = 0; k < kMaxDim; ++k) {
-      if (hipEventCreateWithFlags(&ss.fork[k], hipEventDisableTiming) != hipSuccess) return nullptr;
-      if (hipEventCreateWithFlags(&ss.join[k], hipEventDisableTiming) != hipSuccess) return nullptr;
-    }
-    if (hipEventCreateWithFlags(&ss.tail_fork, hipEventDisableTiming) != hipSuccess) return nullptr;
-    if (hipEventCreateWithFlags(&ss.tail_join, hipEventDisableTiming) != hipSuccess) return nullptr;
-    ss.ok = true;
-  }
-  return &ss;
-}
-
 // The core step that closes a sweep: core numerator from the last mode's row-block
-// partials, Gram of the last factor, core update, and M for mode 0 of the next sweep.
+// partials, Gram of the last factor and the core update.  (M_0 of the next sweep is formed
+// at that sweep's start, beside its first small contraction.)
 static nnc_status core_tail(const TuckerBufs &b, float *G, float *const *A, double eps, hipStream_t s) {
   const TuckerPlan &p = *b.p;
   const int d = p.d;
@@ -407,58 +382,51 @@ static nnc_status core_tail(const TuckerBufs &b, float *G, float *const *A, doub
   h.gram_parts = (int)mu_rows_blocks(p.N[d - 1]);
   h.do_core = 1;
   h.nparts = (int)mu_rows_blocks(p.N[d - 1]);
-  h.next = 0;
+  h.next = -1;
   return launch_core_step(h, s);
-}
-
-// Whether the single-workgroup core steps run on a second stream beside the sweep
-// (NNC_CORE_OVERLAP=1) or in line with it (default).  In a captured graph the runtime puts
-// the branches on different hardware queues, and each dependency between queues has cost
-// more than the overlap saves at the sizes measured so far.
-static bool core_overlap() {
-  static int v = -1;
-  if (v < 0) {
-    const char *e = getenv("NNC_CORE_OVERLAP");
-    v = (e && atoi(e) > 0) ? 1 : 0;
-  }
-  return v == 1;
 }
 
 // Sweeps captured in one graph when no objective is recorded in between.
 constexpr int kSweepsPerGraph = 8;
 
-// Sweep flags (used with the overlap only).  kDeferIn: the previous sweep's core step is still to run; it runs on the side
-// stream next to pass 1 (which needs only the last factor) and mode 0 waits for it.
-// kDeferOut: leave this sweep's core step to the next call (or to core_tail).
-enum { kDeferIn = 1, kDeferOut = 2 };
+// Chain of small contractions (chain_small) whose first launch also carries the core step
+// `h` (independent of the chain); without contractions the core step runs alone.
+static nnc_status chain_with_core(const TuckerBufs &b, const float *src, int d, int64_t *cur,
+                                  const int *modes, int nm, float *const *A, const int64_t *R,
+                                  const CoreArgsHost &h, const float **result, hipStream_t s) {
+  if (nm == 0) {
+    NNC_TRY(launch_core_step(h, s));
+    *result = src;
+    return NNC_OK;
+  }
+  const int k = modes[0];
+  float *out = (nm == 1) ? b.Y() : b.C(0);
+  NNC_TRY(launch_small_with_core(src, prod(cur, 0, k), cur[k], prod(cur, k + 1, d), A[k], R[k], 1,
+                                 R[k], out, h, s));
+  cur[k] = R[k];
+  // the rest of the chain continues from `out` (ping-pong buffers shifted by one)
+  return chain_small(out, d, cur, modes + 1, nm - 1, A, R, b.C(1), b.C(0), b.Y(), result, s);
+}
 
+// One sweep of the fused schedule (every multirank <= 32).  Two X passes: pass 1
+// (P = X x_{d-1} A_{d-1}^T) feeds modes 0 .. d-2, pass 2 (T = X x_0 A_0^T, with the new
+// A_0) feeds mode d-1 and the core.  Each core step that only forms a Gram and the next
+// mode's R x R matrix shares a launch with a small contraction it does not depend on:
+//   M_0 (from G and every Gram)           with the first contraction of P,
+//   Gram of A_n, M_{n+1}  (n < d-2)       with U_{n+1} = U_n x_n A_n^T,
+//   Gram of A_{d-2}, M_{d-1}              with the first contraction of T.
 static nnc_status fused_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, float *G,
-                              float *const *A, double eps, hipStream_t s, PassTimer *tm,
-                              int flags = 0) {
+                              float *const *A, double eps, hipStream_t s, PassTimer *tm) {
   const TuckerPlan &p = *b.p;
   const int d = p.d;
-  const bool ov = core_overlap();
-  SideStream *ss = ov ? side_stream() : nullptr;
-  if (ov && !ss) return fail(NNC_EHIP, "could not create the side stream");
-  if (flags & kDeferIn) {
-    if (ov) {
-      NNC_HIP(hipEventRecord(ss->tail_fork, s));
-      NNC_HIP(hipStreamWaitEvent(ss->s, ss->tail_fork, 0));
-      NNC_TRY(core_tail(b, G, A, eps, ss->s));
-      NNC_HIP(hipEventRecord(ss->tail_join, ss->s));
-    } else {
-      NNC_TRY(core_tail(b, G, A, eps, s));
-    }
-  }
-  // with the overlap, the passes leave one CU to the core step running beside them
-  const int reserve1 = (ov && (flags & kDeferIn)) ? 1 : 0;
   if (tm) NNC_TRY(tm->start(s));
   NNC_TRY(launch_ttm(X, dt, p.size / p.N[d - 1], p.N[d - 1], 1, A[d - 1], p.R[d - 1], 1, p.R[d - 1],
-                     b.P(), s, true, nullptr, reserve1));
+                     b.P(), s, true));
   if (tm) NNC_TRY(tm->stop(s));
   const float *U = b.P();
-  CoreArgsHost deferred;
-  bool have_deferred = false;
+  CoreArgsHost pending = core_args(b, G, A, eps);  // M_0: no new Gram
+  pending.gram_from = pending.gram_to = 0;
+  pending.next = 0;
   for (int n = 0; n < d - 1; ++n) {
     int64_t cur[kMaxDim];
     for (int k = 0; k < d; ++k) cur[k] = (k < n || k == d - 1) ? p.R[k] : p.N[k];
@@ -467,9 +435,10 @@ static nnc_status fused_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, 
     int64_t ycur[kMaxDim];
     memcpy(ycur, cur, sizeof ycur);
     const float *Y = nullptr;
-    NNC_TRY(chain_small(U, d, ycur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
-    if (ov && n > 0) NNC_HIP(hipStreamWaitEvent(s, ss->join[n - 1], 0));  // M_n from core step n-1
-    if (ov && n == 0 && (flags & kDeferIn)) NNC_HIP(hipStreamWaitEvent(s, ss->tail_join, 0));  // G, M_0
+    if (n == 0)
+      NNC_TRY(chain_with_core(b, U, d, ycur, modes, nm, A, p.R, pending, &Y, s));
+    else
+      NNC_TRY(chain_small(U, d, ycur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
     NNC_TRY(launch_mu_rows(Y, G, A[n], b.M(), prod(p.R, 0, n), p.N[n], prod(p.R, n + 1, d), p.R[n],
                            eps, b.clips(), b.gram(), nullptr, nullptr, s));
     // core step n: Gram of the new A_n and M_{n+1}
@@ -479,55 +448,27 @@ static nnc_status fused_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, 
     h.gram = b.gram();
     h.gram_parts = (int)mu_rows_blocks(p.N[n]);
     h.next = n + 1;
-    if (ov) {
-      NNC_HIP(hipEventRecord(ss->fork[n], s));
-      NNC_HIP(hipStreamWaitEvent(ss->s, ss->fork[n], 0));
-      NNC_TRY(launch_core_step(h, ss->s));
-      NNC_HIP(hipEventRecord(ss->join[n], ss->s));
-      if (n < d - 2) {
-        float *Un = b.U(n % 2);
-        NNC_TRY(ttm_f32(U, d, cur, n, A[n], p.R[n], Un, s));
-        U = Un;
-      }
-    } else if (n < d - 2) {
-      // the core step and U_{n+1} = U_n x_n A_n^T do not depend on each other: one launch
+    if (n < d - 2) {
       float *Un = b.U(n % 2);
       NNC_TRY(launch_small_with_core(U, prod(cur, 0, n), cur[n], prod(cur, n + 1, d), A[n], p.R[n],
                                      1, p.R[n], Un, h, s));
       U = Un;
     } else {
-      deferred = h;  // M_{d-1} is not needed before the last mode: it shares a later launch
-      have_deferred = true;
+      pending = h;  // M_{d-1} is not needed before the last mode
     }
   }
   if (tm) NNC_TRY(tm->start(s));
-  NNC_TRY(launch_ttm(X, dt, 1, p.N[0], p.size / p.N[0], A[0], p.R[0], 1, p.R[0], b.T(), s, true,
-                     nullptr, ov ? 1 : 0));
+  NNC_TRY(launch_ttm(X, dt, 1, p.N[0], p.size / p.N[0], A[0], p.R[0], 1, p.R[0], b.T(), s, true));
   if (tm) NNC_TRY(tm->stop(s));
   int64_t cur[kMaxDim];
   for (int k = 0; k < d; ++k) cur[k] = (k == 0) ? p.R[0] : p.N[k];
   int modes[kMaxDim], nm = 0;
   for (int k = 1; k < d - 1; ++k) modes[nm++] = k;
   const float *Y = nullptr;
-  if (have_deferred && nm > 0) {
-    // the first contraction of the chain shares its launch with the deferred core step
-    const int k = modes[0];
-    float *out = (nm == 1) ? b.Y() : b.C(0);
-    NNC_TRY(launch_small_with_core(b.T(), prod(cur, 0, k), cur[k], prod(cur, k + 1, d), A[k], p.R[k],
-                                   1, p.R[k], out, deferred, s));
-    cur[k] = p.R[k];
-    // the rest of the chain continues from `out` (ping-pong buffers shifted by one)
-    NNC_TRY(chain_small(out, d, cur, modes + 1, nm - 1, A, p.R, b.C(1), b.C(0), b.Y(), &Y, s));
-    if (nm == 1) Y = out;
-  } else {
-    if (have_deferred) NNC_TRY(launch_core_step(deferred, s));
-    NNC_TRY(chain_small(b.T(), d, cur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
-  }
-  if (ov) NNC_HIP(hipStreamWaitEvent(s, ss->join[d - 2], 0));  // M_{d-1}; joins the side stream
+  NNC_TRY(chain_with_core(b, b.T(), d, cur, modes, nm, A, p.R, pending, &Y, s));
   NNC_TRY(launch_mu_rows(Y, G, A[d - 1], b.M(), prod(p.R, 0, d - 1), p.N[d - 1], 1, p.R[d - 1], eps,
                          b.clips(), b.gram(), b.gpart(), nullptr, s));
-  if (!(flags & kDeferOut)) NNC_TRY(core_tail(b, G, A, eps, s));
-  return NNC_OK;
+  return core_tail(b, G, A, eps, s);
 }
 
 // ------------------------------------------------------------------ one sweep
@@ -721,10 +662,8 @@ nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *d
     if (ta >= tb) return NNC_OK;
     const bool every = o.objective_every > 0;
     if (!graphs) {
-      const bool rot = p.fast && !every && tb - ta >= 2 && core_overlap();
       for (int t = ta; t < tb; ++t) {
-        const int flags = rot ? ((t > ta ? kDeferIn : 0) | (t < tb - 1 ? kDeferOut : 0)) : 0;
-        NNC_TRY(p.fast ? fused_sweep(b, Xs, dts, core, factors, eps, s, tm, flags)
+        NNC_TRY(p.fast ? fused_sweep(b, Xs, dts, core, factors, eps, s, tm)
                        : tucker_sweep(b, Xs, dts, core, factors, eps, s, tm));
         if (every && (t + 1) % o.objective_every == 0) {
           NNC_TRY(tucker_resid(b, xres, dres, core, factors, s));
@@ -735,10 +674,6 @@ nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *d
       }
       return NNC_OK;
     }
-    // Fast path without intermediate objectives: sweeps as rotated units (see fused_sweep),
-    // captured as three graphs: first (defers its core step), middle (runs the previous
-    // one beside pass 1 and defers its own), last (runs both).
-    const bool rotate = p.fast && !every && tb - ta >= 2 && core_overlap();
     hipStream_t cs = s;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     if (!s) {
@@ -749,13 +684,13 @@ nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *d
       NNC_HIP(hipEventRecord(ev_in, s));
       NNC_HIP(hipStreamWaitEvent(cs, ev_in, 0));
     }
-    // capture `count` sweeps with the given flags into an executable graph
-    auto capture = [&](int flags, hipGraphExec_t *ge, int count = 1) -> nnc_status {
+    // capture `count` sweeps into an executable graph
+    auto capture = [&](hipGraphExec_t *ge, int count) -> nnc_status {
       hipGraph_t g = nullptr;
       NNC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       nnc_status st = NNC_OK;
       for (int c = 0; c < count && st == NNC_OK; ++c)
-        st = p.fast ? fused_sweep(b, Xs, dts, core, factors, eps, cs, nullptr, flags)
+        st = p.fast ? fused_sweep(b, Xs, dts, core, factors, eps, cs, nullptr)
                     : tucker_sweep(b, Xs, dts, core, factors, eps, cs, nullptr);
       hipError_t ec = hipStreamEndCapture(cs, &g);
       if (st != NNC_OK) {
@@ -768,33 +703,16 @@ nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *d
       if (ei != hipSuccess) return fail(NNC_EHIP, "graph instantiation failed: %s", hipGetErrorString(ei));
       return NNC_OK;
     };
-    if (rotate) {
-      hipGraphExec_t gf = nullptr, gm = nullptr, gl = nullptr;
-      nnc_status st = capture(kDeferOut, &gf);
-      if (st == NNC_OK && tb - ta > 2) st = capture(kDeferIn | kDeferOut, &gm);
-      if (st == NNC_OK) st = capture(kDeferIn, &gl);
-      if (st == NNC_OK) {
-        if (hipGraphLaunch(gf, cs) != hipSuccess) st = fail(NNC_EHIP, "graph launch failed");
-        for (int t = ta + 1; st == NNC_OK && t < tb - 1; ++t)
-          if (hipGraphLaunch(gm, cs) != hipSuccess) st = fail(NNC_EHIP, "graph launch failed");
-        if (st == NNC_OK && hipGraphLaunch(gl, cs) != hipSuccess) st = fail(NNC_EHIP, "graph launch failed");
-      }
-      // an executable graph is destroyed only after its launches have finished: its
-      // resources must not be released (and reused by the next instantiation) while the
-      // queued launches still read them
-      if (hipStreamSynchronize(cs) != hipSuccess && st == NNC_OK)
-        st = fail(NNC_EHIP, "stream synchronization after the sweeps failed");
-      for (hipGraphExec_t e : {gf, gm, gl})
-        if (e) (void)hipGraphExecDestroy(e);
-      NNC_TRY(st);
-    } else if (!every && tb - ta > 1) {
+    if (!every && tb - ta > 1) {
       // several sweeps per graph: the turnaround between two graph launches (several
-      // microseconds) is paid once per kSweepsPerGraph sweeps
+      // microseconds) is paid once per kSweepsPerGraph sweeps.  An executable graph is
+      // destroyed only after its launches have finished: its resources must not be
+      // released (and reused by the next instantiation) while queued launches read them.
       const int n = tb - ta;
       const int per = std::min(n, kSweepsPerGraph);
       hipGraphExec_t gb = nullptr, gr = nullptr;
-      nnc_status st = capture(0, &gb, per);
-      if (st == NNC_OK && n % per) st = capture(0, &gr, n % per);
+      nnc_status st = capture(&gb, per);
+      if (st == NNC_OK && n % per) st = capture(&gr, n % per);
       for (int t = 0; st == NNC_OK && t + per <= n; t += per)
         if (hipGraphLaunch(gb, cs) != hipSuccess) st = fail(NNC_EHIP, "graph launch failed");
       if (st == NNC_OK && gr && hipGraphLaunch(gr, cs) != hipSuccess) st = fail(NNC_EHIP, "graph launch failed");
@@ -805,7 +723,7 @@ nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *d
       NNC_TRY(st);
     } else {
       hipGraphExec_t ge = nullptr;
-      NNC_TRY(capture(0, &ge));
+      NNC_TRY(capture(&ge, 1));
       for (int t = ta; t < tb; ++t) {
         NNC_HIP(hipGraphLaunch(ge, cs));
         if (every && (t + 1) % o.objective_every == 0) {
