@@ -100,40 +100,41 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
   const int RR = R * R;
   const float mv0 = M[tid < RR ? tid : 0];
   const float mv1 = M[tid + kRowThreads < RR ? tid + kRowThreads : 0];
-  constexpr int kStage = 28;  // 14K staged floats over 512 threads
-  const UDiv dR = make_udiv(R), dpost = make_udiv(post);
+  // staging rounds: kSG core values and kSY Y values per thread, all loads of a round in
+  // flight together; each region in its own branch-free loop (consecutive threads read
+  // consecutive addresses).  Indices past a region repeat its last element: the same value
+  // stored twice to the same place.
+  constexpr int kSG = 16, kSY = 8;
+  const UDiv dpost = make_udiv(post);
   for (int c0 = 0; c0 < C; c0 += CH) {
     const int cn = (C - c0) < CH ? (C - c0) : CH;
     const int ng = cn * R, ny = nr * cn;
-    const int ntot = ng + ny;
     const UDiv dcn = make_udiv(cn);
-    for (int base = 0; base < ntot; base += kStage * kRowThreads) {
-      float v[kStage];
-      int off[kStage];
+    for (int gb = 0, yb = 0; gb < ng || yb < ny; gb += kSG * kRowThreads, yb += kSY * kRowThreads) {
+      float vg[kSG], vy[kSY];
+      int og[kSG], oy[kSY];
 #pragma unroll
-      for (int u = 0; u < kStage; ++u) {
-        int idx = base + tid + u * kRowThreads;
-        idx = idx < ntot ? idx : ntot - 1;  // the last value again: same address, same value
-        const bool isg = idx < ng;
-        const int j = idx - ng;
-        int cc, rr, i;
-        if (isg) {
-          cc = udiv(idx, dR);
-          rr = idx - cc * R;
-          i = 0;
-        } else {
-          i = udiv(j, dcn);
-          cc = j - i * cn;
-          rr = 0;
-        }
+      for (int u = 0; u < kSG; ++u) {  // core column c0 + cc, row rr: G[p][rr][q] (c = p*post + q)
+        int idx = gb + tid + u * kRowThreads;
+        idx = idx < ng ? idx : ng - 1;
+        const int rr = udiv(idx, dcn), cc = idx - rr * cn;
         const int c = c0 + cc, pp = udiv(c, dpost), q = c - pp * post;
-        const float *src = isg ? G + ((int64_t)pp * R + rr) * post + q
-                               : Y + ((int64_t)pp * Nn + i0 + i) * post + q;
-        v[u] = *src;
-        off[u] = isg ? cc * GS + rr : CH * GS + i * YS + cc;
+        vg[u] = G[((int64_t)pp * R + rr) * post + q];
+        og[u] = cc * GS + rr;
       }
 #pragma unroll
-      for (int u = 0; u < kStage; ++u) dynr[off[u]] = v[u];
+      for (int u = 0; u < kSY; ++u) {  // row i, column c0 + cc: Y[p][i0 + i][q]
+        int idx = yb + tid + u * kRowThreads;
+        idx = idx < ny ? idx : ny - 1;
+        const int i = udiv(idx, dcn), cc = idx - i * cn;
+        const int c = c0 + cc, pp = udiv(c, dpost), q = c - pp * post;
+        vy[u] = Y[((int64_t)pp * Nn + i0 + i) * post + q];
+        oy[u] = CH * GS + i * YS + cc;
+      }
+#pragma unroll
+      for (int u = 0; u < kSG; ++u) dynr[og[u]] = vg[u];
+#pragma unroll
+      for (int u = 0; u < kSY; ++u) dynr[oy[u]] = vy[u];
     }
     if (c0 == 0) {
       if (tid < nr * R) As[tid / R][tid % R] = av;
