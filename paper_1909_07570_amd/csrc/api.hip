@@ -374,8 +374,7 @@ static nnc_status chain_small(const float *src, int d, int64_t *cur, const int *
 static nnc_status core_tail(const TuckerBufs &b, float *G, float *const *A, double eps, hipStream_t s) {
   const TuckerPlan &p = *b.p;
   const int d = p.d;
-  NNC_TRY(launch_sum_parts(b.gpart(), (int)mu_rows_blocks(p.N[d - 1]), p.gsize, b.G(2), s));
-  CoreArgsHost h = core_args(b, G, A, eps);
+  CoreArgsHost h = core_args(b, G, A, eps);  // core numerator summed from b.gpart() there
   h.gram_from = d - 1;
   h.gram_to = d;
   h.gram = b.gram();

@@ -306,16 +306,15 @@ __global__ __launch_bounds__(kSliceThreads) void mrows_k(SliceArgs a) {
   mrows_body<RM, BIG>(a, blockIdx.x);
 }
 
-// T_i = G[i, ..] x_1 S_1 ... x_{d-1} S_{d-1} for i = blockIdx.x (and the new Gram of a.gram).
+// T_i = G[i, ..] x_1 S_1 ... x_{d-1} S_{d-1} for slice i (and the new Gram of a.gram).
 template <int RM, bool BIG>
-__global__ __launch_bounds__(kSliceThreads) void denA_k(SliceArgs a) {
+static __device__ void denA_body(const SliceArgs &a, int i) {
   extern __shared__ __attribute__((aligned(16))) float lds[];
   const int d = a.d, tid = threadIdx.x;
   float *Sl = lds;
   float *red = Sl + d * RM * RM;
   const int slice = a.gsize / a.R[0];
   float *H0 = red + SliceLds<RM>::kRed, *H1 = H0 + slice;
-  const int i = blockIdx.x;
   constexpr int SPT = (BIG ? kSliceMax : kSliceMax / 2) / kSliceThreads;  // slice values per thread
   float hv[SPT];
 #pragma unroll
@@ -335,6 +334,43 @@ __global__ __launch_bounds__(kSliceThreads) void denA_k(SliceArgs a) {
   __syncthreads();
   const float *T = contract_slice<RM>(a, 0, Sl, H0, H1);
   for (int c = tid; c < slice; c += kSliceThreads) a.T[(int64_t)i * slice + c] = T[c];
+}
+
+template <int RM, bool BIG>
+__global__ __launch_bounds__(kSliceThreads) void denA_k(SliceArgs a) {
+  denA_body<RM, BIG>(a, blockIdx.x);
+}
+
+// numG[e] = sum_{b < nparts} part[b][e] (the core numerator from the last mode's row-block
+// partials), b in order from 0; the loads of a round of kSumB partials are all in flight.
+static __device__ void sum_body(const float *__restrict__ part, int nparts, int n,
+                                float *__restrict__ out, int e) {
+  if (e >= n) return;
+  constexpr int kSumB = 32;
+  float s2 = 0.f;
+  for (int b0 = 0; b0 < nparts; b0 += kSumB) {
+    float v[kSumB];
+#pragma unroll
+    for (int u = 0; u < kSumB; ++u) {
+      const int b = b0 + u < nparts ? b0 + u : nparts - 1;
+      v[u] = part[(int64_t)b * n + e];
+    }
+#pragma unroll
+    for (int u = 0; u < kSumB; ++u)
+      if (b0 + u < nparts) s2 += v[u];
+  }
+  out[e] = s2;
+}
+
+// denA_k's slices in blocks [0, na) and the core numerator's sum in the blocks after them:
+// the two do not depend on each other and each alone leaves most CUs idle.
+template <int RM, bool BIG>
+__global__ __launch_bounds__(kSliceThreads) void denA_sum_k(SliceArgs a, const float *part,
+                                                           int nparts, float *numG, int na) {
+  if ((int)blockIdx.x < na)
+    denA_body<RM, BIG>(a, blockIdx.x);
+  else
+    sum_body(part, nparts, a.gsize, numG, ((int)blockIdx.x - na) * kSliceThreads + threadIdx.x);
 }
 
 // den[i] = sum_i' S_0[i'][i] T_i' and G[i] <- G[i] * numG[i] / max(den[i], eps) (FP64
@@ -565,8 +601,15 @@ static nnc_status slice_step(const CoreArgsHost &h, hipStream_t s) {
     a.n = -1;
     const int slice0 = a.gsize / a.R[0];
     const size_t la = SliceLds<RM>::bytes(a.d, a.gsize, slice0, false);
-    NNC_TRY(allow_slice_lds(reinterpret_cast<const void *>(denA_k<RM, BIG>), la));
-    hipLaunchKernelGGL((denA_k<RM, BIG>), dim3(a.R[0]), dim3(kSliceThreads), la, s, a);
+    if (h.gpart && h.nparts > 0) {  // the numerator's sum rides along
+      NNC_TRY(allow_slice_lds(reinterpret_cast<const void *>(denA_sum_k<RM, BIG>), la));
+      const int nsum = (a.gsize + kSliceThreads - 1) / kSliceThreads;
+      hipLaunchKernelGGL((denA_sum_k<RM, BIG>), dim3(a.R[0] + nsum), dim3(kSliceThreads), la, s, a,
+                         h.gpart, h.nparts, h.numG, a.R[0]);
+    } else {
+      NNC_TRY(allow_slice_lds(reinterpret_cast<const void *>(denA_k<RM, BIG>), la));
+      hipLaunchKernelGGL((denA_k<RM, BIG>), dim3(a.R[0]), dim3(kSliceThreads), la, s, a);
+    }
     SliceArgs b = a;
     b.gram = -1;
     b.numG = h.numG;

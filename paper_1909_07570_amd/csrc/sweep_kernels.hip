@@ -638,10 +638,16 @@ __global__ __launch_bounds__(kCoreThreads) void core_step_k(CoreArgs a) {
 nnc_status launch_slice_step(const CoreArgsHost &h, hipStream_t s);
 
 nnc_status launch_core_step(const CoreArgsHost &h, hipStream_t s) {
-  // small cores: the work spread over one workgroup per slice (core_kernels.hip)
+  // small cores: the work spread over one workgroup per slice (core_kernels.hip), the core
+  // numerator summed from h.gpart there too
   {
     const nnc_status st = launch_slice_step(h, s);
     if (st != NNC_EUNSUPPORTED) return st;
+  }
+  if (h.do_core && h.gpart && h.nparts > 0) {
+    int64_t gs = 1;
+    for (int k = 0; k < h.d; ++k) gs *= h.R[k];
+    NNC_TRY(launch_sum_parts(h.gpart, h.nparts, gs, h.numG, s));
   }
   CoreArgs a;
   memset(&a, 0, sizeof a);
