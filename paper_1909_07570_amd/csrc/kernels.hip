@@ -667,11 +667,104 @@ constexpr int kResidMaxBlocks = 2048;
 
 int resid_stream_max_blocks() { return kResidMaxBlocks; }
 
-template <typename XT>
+// ||X - Xhat||^2 and ||X||^2 with Xhat[m][k] = sum_r W[m][r] Ad[k][r] (X viewed as M x K,
+// W the expansion of every mode but the last, Ad the last factor).  A block takes tiles of
+// kResidRows rows: the tile's W rows go to LDS, each thread keeps the factor rows of its
+// columns k = t + 256 j (j < kResidCols) in registers and reads X along rows (coalesced).
+// Each difference is formed and squared in FP64; sums are FP64 per thread, then per block.
+constexpr int kResidRows = 16;
+constexpr int kResidCols = 2;  // columns per thread per chunk (chunk = 512 columns)
+
+template <typename XT, int RB>
 __global__ __launch_bounds__(kResidThreads) void resid_stream_k(const XT *__restrict__ X, int64_t M,
                                                                 int64_t K, const float *__restrict__ W,
                                                                 const float *__restrict__ Ad,
-                                                                int64_t R, double *__restrict__ part) {
+                                                                int R, double *__restrict__ part) {
+  __shared__ __attribute__((aligned(16))) float Ws[kResidRows][RB];
+  __shared__ double s0[kResidThreads], s1[kResidThreads];
+  const int t = threadIdx.x;
+  double sr = 0.0, sx = 0.0;
+  const int64_t ntile = (M + kResidRows - 1) / kResidRows;
+  constexpr int64_t kChunk = (int64_t)kResidThreads * kResidCols;
+  for (int64_t k0 = 0; k0 < K; k0 += kChunk) {
+    float a[kResidCols][RB];
+    int64_t kc[kResidCols];
+    bool kv[kResidCols];
+#pragma unroll
+    for (int j = 0; j < kResidCols; ++j) {
+      const int64_t k = k0 + t + (int64_t)j * kResidThreads;
+      kv[j] = k < K;
+      kc[j] = kv[j] ? k : K - 1;
+#pragma unroll
+      for (int r = 0; r < RB; ++r) a[j][r] = (kv[j] && r < R) ? Ad[kc[j] * R + r] : 0.f;
+    }
+    for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+      const int64_t m0 = tile * kResidRows;
+      __syncthreads();  // the previous tile's W rows are no longer read
+      for (int e = t; e < kResidRows * RB; e += kResidThreads) {
+        const int row = e / RB, r = e - (e / RB) * RB;
+        const int64_t m = m0 + row;
+        Ws[row][r] = (m < M && r < R) ? W[m * R + r] : 0.f;
+      }
+      // the tile's X values, all loads in flight together
+      float xv[kResidRows][kResidCols];
+#pragma unroll
+      for (int row = 0; row < kResidRows; ++row) {
+        const int64_t m = (m0 + row) < M ? (m0 + row) : M - 1;
+#pragma unroll
+        for (int j = 0; j < kResidCols; ++j) xv[row][j] = load_x(X + m * K + kc[j]);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int row = 0; row < kResidRows; ++row) {
+        if (m0 + row >= M) break;
+        const float4 *w4 = reinterpret_cast<const float4 *>(&Ws[row][0]);
+        float xh[kResidCols];
+#pragma unroll
+        for (int j = 0; j < kResidCols; ++j) xh[j] = 0.f;
+#pragma unroll
+        for (int r4 = 0; r4 < RB / 4; ++r4) {
+          const float4 w = w4[r4];
+#pragma unroll
+          for (int j = 0; j < kResidCols; ++j) {
+            xh[j] = fmaf(w.x, a[j][4 * r4 + 0], xh[j]);
+            xh[j] = fmaf(w.y, a[j][4 * r4 + 1], xh[j]);
+            xh[j] = fmaf(w.z, a[j][4 * r4 + 2], xh[j]);
+            xh[j] = fmaf(w.w, a[j][4 * r4 + 3], xh[j]);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < kResidCols; ++j) {
+          if (!kv[j]) continue;
+          const double df = (double)xv[row][j] - (double)xh[j];
+          sr += df * df;
+          sx += (double)xv[row][j] * (double)xv[row][j];
+        }
+      }
+    }
+  }
+  s0[t] = sr;
+  s1[t] = sx;
+  __syncthreads();
+  for (int w = kResidThreads / 2; w > 0; w >>= 1) {
+    if (t < w) {
+      s0[t] += s0[t + w];
+      s1[t] += s1[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    part[2 * blockIdx.x] = s0[0];
+    part[2 * blockIdx.x + 1] = s1[0];
+  }
+}
+
+// Any rank: one thread per element, the rank loop from global memory (L1/L2 hits).
+template <typename XT>
+__global__ __launch_bounds__(kResidThreads) void resid_any_k(const XT *__restrict__ X, int64_t M,
+                                                             int64_t K, const float *__restrict__ W,
+                                                             const float *__restrict__ Ad,
+                                                             int64_t R, double *__restrict__ part) {
   __shared__ double s0[kResidThreads], s1[kResidThreads];
   double sr = 0.0, sx = 0.0;
   const int64_t total = M * K;
@@ -706,13 +799,37 @@ __global__ __launch_bounds__(kResidThreads) void resid_stream_k(const XT *__rest
 nnc_status launch_resid_stream(const void *X, nnc_dtype xdt, int64_t M, int64_t K, const float *W,
                                const float *Ad, int64_t R, double *part, int *nblocks_out,
                                hipStream_t s) {
-  const int grid = grid_for(M * K, kResidThreads, kResidMaxBlocks);
+  if (R < 1) return fail(NNC_EINVAL, "residual: rank %lld", (long long)R);
+  if (R > 32) {
+    const int grid = grid_for(M * K, kResidThreads, kResidMaxBlocks);
+    if (xdt == NNC_F32)
+      hipLaunchKernelGGL(resid_any_k<float>, dim3(grid), dim3(kResidThreads), 0, s,
+                         (const float *)X, M, K, W, Ad, R, part);
+    else
+      hipLaunchKernelGGL(resid_any_k<uint16_t>, dim3(grid), dim3(kResidThreads), 0, s,
+                         (const uint16_t *)X, M, K, W, Ad, R, part);
+    *nblocks_out = grid;
+    NNC_HIP(hipGetLastError());
+    return NNC_OK;
+  }
+  const int64_t ntile = (M + kResidRows - 1) / kResidRows;
+  const int grid = (int)std::min<int64_t>(std::max<int64_t>(ntile, 1), kResidMaxBlocks);
+#define NNC_RES(XT, RBV)                                                                          \
+  hipLaunchKernelGGL((resid_stream_k<XT, RBV>), dim3(grid), dim3(kResidThreads), 0, s,           \
+                     (const XT *)X, M, K, W, Ad, (int)R, part)
+#define NNC_RES2(XT)                    \
+  do {                                  \
+    if (R <= 8) NNC_RES(XT, 8);         \
+    else if (R <= 16) NNC_RES(XT, 16);  \
+    else if (R <= 24) NNC_RES(XT, 24);  \
+    else NNC_RES(XT, 32);               \
+  } while (0)
   if (xdt == NNC_F32)
-    hipLaunchKernelGGL(resid_stream_k<float>, dim3(grid), dim3(kResidThreads), 0, s,
-                       (const float *)X, M, K, W, Ad, R, part);
+    NNC_RES2(float);
   else
-    hipLaunchKernelGGL(resid_stream_k<uint16_t>, dim3(grid), dim3(kResidThreads), 0, s,
-                       (const uint16_t *)X, M, K, W, Ad, R, part);
+    NNC_RES2(uint16_t);
+#undef NNC_RES2
+#undef NNC_RES
   *nblocks_out = grid;
   NNC_HIP(hipGetLastError());
   return NNC_OK;
