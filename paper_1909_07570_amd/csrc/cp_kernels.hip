@@ -45,14 +45,14 @@ static __device__ inline float mu_cp(float x, float num, float den, double eps, 
 }
 
 // LDS floats of one fit of rank r with `threads` threads:
-//   [T if t_lds] B_k (dims[k] x r) | Gram_k (r x r) | H (r x r) | M (maxdim x r)
+//   [T if t_lds] B_k (dims[k] x r) | Gram_k (r x r) | H (r x r)
 //   | part (max(threads, maxdim * r)) | red (2 * threads doubles) | [Z (zmax x r) if z_lds]
 static int64_t cp_lds_floats(const CpArgs &a, int r, int threads, bool t_lds, bool z_lds) {
   int64_t s = t_lds ? a.size : 0;
   s = (s + 3) & ~(int64_t)3;  // factor rows are read as float4
   const int RM = r <= 8 ? 8 : (r <= 16 ? 16 : 32);  // factor rows and Z rows are padded to RM
   for (int k = 0; k < a.d; ++k) s += (int64_t)a.dims[k] * RM;
-  s += (int64_t)(a.d + 1) * r * r + (int64_t)a.maxdim * r;
+  s += (int64_t)(a.d + 1) * r * r;
   s += std::max<int64_t>(threads, (int64_t)a.maxdim * r);
   s += (s & 1);               // keep the doubles 8-byte aligned
   s += 4 * (int64_t)threads;  // 2 * threads doubles
@@ -95,8 +95,6 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
   p += d * r * r;
   float *H = p;
   p += r * r;
-  float *Mm = p;
-  p += a.maxdim * r;
   float *part = p;
   p += (nt > a.maxdim * r ? nt : a.maxdim * r);
   p += ((p - sm) & 1);
@@ -143,18 +141,23 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
       for (int k = L + 1; k < d; ++k) postL *= a.dims[k];
       const int zrows = a.size / mL;
       const float *BL = sB + boff[L];
-      // ---- stage 1: Z[o][rho] = sum_l T[(pre*mL + l)*postL + q] B_L[l][rho], o = pre*postL + q
-      for (int o = tid; o < zrows; o += nt) {
+      // ---- stage 1: Z[o][rho] = sum_l T[(pre*mL + l)*postL + q] B_L[l][rho], o = pre*postL + q;
+      // each row's columns in two halves (two threads), so twice as many threads share it.
+      // H_n (Hadamard product of the other Grams, final since the last update) in the
+      // same phase.
+      constexpr int RH = RM / 2;
+      for (int w = tid; w < 2 * zrows; w += nt) {
+        const int o = w >> 1, h0 = (w & 1) * RH;
         const int pre = o / postL, q = o - (o / postL) * postL;
         const float *t = T + pre * mL * postL + q;
-        float acc[RM];
+        float acc[RH];
 #pragma unroll
-        for (int rho = 0; rho < RM; ++rho) acc[rho] = 0.f;
+        for (int rho = 0; rho < RH; ++rho) acc[rho] = 0.f;
         for (int l = 0; l < mL; ++l) {
           const float x = t[l * postL];
-          const float4 *bl = reinterpret_cast<const float4 *>(BL + l * RM);
+          const float4 *bl = reinterpret_cast<const float4 *>(BL + l * RM + h0);
 #pragma unroll
-          for (int r4 = 0; r4 < RM / 4; ++r4) {
+          for (int r4 = 0; r4 < RH / 4; ++r4) {
             const float4 bv = bl[r4];
             acc[4 * r4 + 0] = fmaf(x, bv.x, acc[4 * r4 + 0]);
             acc[4 * r4 + 1] = fmaf(x, bv.y, acc[4 * r4 + 1]);
@@ -162,115 +165,132 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
             acc[4 * r4 + 3] = fmaf(x, bv.w, acc[4 * r4 + 3]);
           }
         }
-        float4 *zo = reinterpret_cast<float4 *>(Z + o * RM);
+        float4 *zo = reinterpret_cast<float4 *>(Z + o * RM + h0);
 #pragma unroll
-        for (int r4 = 0; r4 < RM / 4; ++r4)
+        for (int r4 = 0; r4 < RH / 4; ++r4)
           zo[r4] = make_float4(acc[4 * r4], acc[4 * r4 + 1], acc[4 * r4 + 2], acc[4 * r4 + 3]);
       }
-      if (!a.z_lds) __threadfence_block();
-      __syncthreads();
-      // ---- stage 2: M[i][rho] = sum over Z rows with i_n = i of Z[o][rho] prod_{k!=n,L} B_k[i_k][rho]
-      // Z's modes are T's modes without L (row-major).  zdims/zstride/zb/idx are indexed by
-      // unrolled loop counters only.
-      int zdims[kMaxDim], zstride[kMaxDim], zb[kMaxDim], idx[kMaxDim];
-      int nz = 0, npos = 0;
-#pragma unroll
-      for (int j = 0; j < kMaxDim; ++j) {
-        zdims[j] = 1;
-        zstride[j] = 0;
-        zb[j] = 0;
-        idx[j] = 0;
-      }
-#pragma unroll
-      for (int k = 0; k < kMaxDim; ++k) {
-        if (k < d && k != L) {
-          if (k == n) npos = nz;
-#pragma unroll
-          for (int j = 0; j < kMaxDim; ++j)
-            if (j == nz) {
-              zdims[j] = a.dims[k];
-              zb[j] = boff[k];
-            }
-          ++nz;
-        }
-      }
-      {
-        int st = 1;
-#pragma unroll
-        for (int j = kMaxDim - 1; j >= 0; --j)
-          if (j < nz) {
-            zstride[j] = st;
-            st *= zdims[j];
-          }
-      }
-      int nstride = 0;
-#pragma unroll
-      for (int j = 0; j < kMaxDim; ++j)
-        if (j == npos) nstride = zstride[j];
-      const int In = a.dims[n];
-      const int npairs = In * r;
-      const int other = zrows / In;
-      const int S = npairs >= nt ? 1 : nt / npairs;
-      for (int w = tid; w < npairs * S; w += nt) {
-        const int pr = w % npairs, s = w / npairs;
-        const int i = pr / r, rho = pr - (pr / r) * r;
-        const int o0 = (int)((int64_t)other * s / S), o1 = (int)((int64_t)other * (s + 1) / S);
-        int rem = o0, zoff = i * nstride;
-#pragma unroll
-        for (int j = kMaxDim - 1; j >= 0; --j) {
-          if (j < nz && j != npos) {
-            idx[j] = rem % zdims[j];
-            rem /= zdims[j];
-            zoff += idx[j] * zstride[j];
-          }
-        }
-        float acc = 0.f;
-        for (int o = o0; o < o1; ++o) {
-          float prod = Z[zoff * RM + rho];
-#pragma unroll
-          for (int j = 0; j < kMaxDim; ++j)
-            if (j < nz && j != npos) prod *= sB[zb[j] + idx[j] * RM + rho];
-          acc += prod;
-          bool carry = true;  // odometer over the modes != n of Z, last fastest
-#pragma unroll
-          for (int j = kMaxDim - 1; j >= 0; --j) {
-            if (carry && j < nz && j != npos) {
-              zoff += zstride[j];
-              if (++idx[j] == zdims[j]) {
-                zoff -= zdims[j] * zstride[j];
-                idx[j] = 0;
-              } else {
-                carry = false;
-              }
-            }
-          }
-        }
-        if (S == 1)
-          Mm[pr] = acc;
-        else
-          part[w] = acc;
-      }
-      __syncthreads();
-      if (S > 1)
-        for (int pr = tid; pr < npairs; pr += nt) {
-          float acc = 0.f;
-          for (int s = 0; s < S; ++s) acc += part[s * npairs + pr];
-          Mm[pr] = acc;
-        }
       for (int e = tid; e < r * r; e += nt) {
         float h = 1.f;
         for (int k = 0; k < d; ++k)
           if (k != n) h *= sW[k * r * r + e];
         H[e] = h;
       }
+      if (!a.z_lds) __threadfence_block();
+      __syncthreads();
+      // ---- stage 2: M[i][rho] = sum over Z rows with i_n = i of Z[o][rho] prod_{k!=n,L} B_k[i_k][rho]
+      // Z's modes are T's modes without L (row-major).  With one mode j besides n and L
+      // (d = 3), Z is 2-D and the sum runs over j's index directly; otherwise an odometer
+      // walks the modes other than n.  Pairs (i, rho) take S threads each, whose partial
+      // sums are added in split order by the update below.
+      const int In = a.dims[n];
+      const int npairs = In * r;
+      const int other = zrows / In;
+      const int S = npairs >= nt ? 1 : nt / npairs;
+      if (d <= 3) {
+        // position of n among Z's modes and the other mode (if any)
+        int jo = -1;
+        for (int k = 0; k < d; ++k)
+          if (k != n && k != L) jo = k;
+        const bool n_first = jo < 0 || n < jo;  // Z = [n][jo] or [jo][n]
+        const int Bo = jo >= 0 ? boff[jo] : 0;
+        for (int w = tid; w < npairs * S; w += nt) {
+          const int pr = w % npairs, s = w / npairs;
+          const int i = pr / r, rho = pr - (pr / r) * r;
+          const int j0 = (int)((int64_t)other * s / S), j1 = (int)((int64_t)other * (s + 1) / S);
+          const int zstep = n_first ? 1 : In;
+          int zoff = n_first ? i * other + j0 : j0 * In + i;
+          float acc = 0.f;
+          if (jo >= 0) {
+            for (int j = j0; j < j1; ++j, zoff += zstep) acc += Z[zoff * RM + rho] * sB[Bo + j * RM + rho];
+          } else {
+            for (int j = j0; j < j1; ++j, zoff += zstep) acc += Z[zoff * RM + rho];
+          }
+          part[w] = acc;
+        }
+      } else {
+        int zdims[kMaxDim], zstride[kMaxDim], zb[kMaxDim], idx[kMaxDim];
+        int nz = 0, npos = 0;
+#pragma unroll
+        for (int j = 0; j < kMaxDim; ++j) {
+          zdims[j] = 1;
+          zstride[j] = 0;
+          zb[j] = 0;
+          idx[j] = 0;
+        }
+#pragma unroll
+        for (int k = 0; k < kMaxDim; ++k) {
+          if (k < d && k != L) {
+            if (k == n) npos = nz;
+#pragma unroll
+            for (int j = 0; j < kMaxDim; ++j)
+              if (j == nz) {
+                zdims[j] = a.dims[k];
+                zb[j] = boff[k];
+              }
+            ++nz;
+          }
+        }
+        {
+          int st = 1;
+#pragma unroll
+          for (int j = kMaxDim - 1; j >= 0; --j)
+            if (j < nz) {
+              zstride[j] = st;
+              st *= zdims[j];
+            }
+        }
+        int nstride = 0;
+#pragma unroll
+        for (int j = 0; j < kMaxDim; ++j)
+          if (j == npos) nstride = zstride[j];
+        for (int w = tid; w < npairs * S; w += nt) {
+          const int pr = w % npairs, s = w / npairs;
+          const int i = pr / r, rho = pr - (pr / r) * r;
+          const int o0 = (int)((int64_t)other * s / S), o1 = (int)((int64_t)other * (s + 1) / S);
+          int rem = o0, zoff = i * nstride;
+#pragma unroll
+          for (int j = kMaxDim - 1; j >= 0; --j) {
+            if (j < nz && j != npos) {
+              idx[j] = rem % zdims[j];
+              rem /= zdims[j];
+              zoff += idx[j] * zstride[j];
+            }
+          }
+          float acc = 0.f;
+          for (int o = o0; o < o1; ++o) {
+            float prod = Z[zoff * RM + rho];
+#pragma unroll
+            for (int j = 0; j < kMaxDim; ++j)
+              if (j < nz && j != npos) prod *= sB[zb[j] + idx[j] * RM + rho];
+            acc += prod;
+            bool carry = true;  // odometer over the modes != n of Z, last fastest
+#pragma unroll
+            for (int j = kMaxDim - 1; j >= 0; --j) {
+              if (carry && j < nz && j != npos) {
+                zoff += zstride[j];
+                if (++idx[j] == zdims[j]) {
+                  zoff -= zdims[j] * zstride[j];
+                  idx[j] = 0;
+                } else {
+                  carry = false;
+                }
+              }
+            }
+          }
+          part[w] = acc;
+        }
+      }
       __syncthreads();
       // ---- B_n <- B_n * M / max(B_n H, eps): new values go to `part` first
       float *Bn = sB + boff[n];
       for (int e = tid; e < npairs; e += nt) {
         const int i = e / r, c = e - (e / r) * r;
+        float m = 0.f;  // the S partial sums of pair e, in split order
+        for (int s = 0; s < S; ++s) m += part[s * npairs + e];
         float den = 0.f;
         for (int s2 = 0; s2 < r; ++s2) den = fmaf(Bn[i * RM + s2], H[s2 * r + c], den);
-        part[e] = mu_cp(Bn[i * RM + c], Mm[e], den, eps, &nclip);
+        part[e] = mu_cp(Bn[i * RM + c], m, den, eps, &nclip);
       }
       __syncthreads();
       for (int e = tid; e < npairs; e += nt) Bn[(e / r) * RM + e % r] = part[e];
