@@ -142,33 +142,24 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
       const int zrows = a.size / mL;
       const float *BL = sB + boff[L];
       // ---- stage 1: Z[o][rho] = sum_l T[(pre*mL + l)*postL + q] B_L[l][rho], o = pre*postL + q;
-      // each row's columns in two halves (two threads), so twice as many threads share it.
-      // H_n (Hadamard product of the other Grams, final since the last update) in the
-      // same phase.
-      constexpr int RH = RM / 2;
-      for (int w = tid; w < 2 * zrows; w += nt) {
-        const int o = w >> 1, h0 = (w & 1) * RH;
+      // one thread per (row, quad of columns), quads past the rank left out.  H_n (Hadamard
+      // product of the other Grams, final since the last update) in the same phase.
+      const int nq = (r + 3) >> 2;
+      for (int w = tid; w < nq * zrows; w += nt) {
+        const int o = w / nq, c4 = (w - o * nq) * 4;
         const int pre = o / postL, q = o - (o / postL) * postL;
         const float *t = T + pre * mL * postL + q;
-        float acc[RH];
-#pragma unroll
-        for (int rho = 0; rho < RH; ++rho) acc[rho] = 0.f;
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 4
         for (int l = 0; l < mL; ++l) {
           const float x = t[l * postL];
-          const float4 *bl = reinterpret_cast<const float4 *>(BL + l * RM + h0);
-#pragma unroll
-          for (int r4 = 0; r4 < RH / 4; ++r4) {
-            const float4 bv = bl[r4];
-            acc[4 * r4 + 0] = fmaf(x, bv.x, acc[4 * r4 + 0]);
-            acc[4 * r4 + 1] = fmaf(x, bv.y, acc[4 * r4 + 1]);
-            acc[4 * r4 + 2] = fmaf(x, bv.z, acc[4 * r4 + 2]);
-            acc[4 * r4 + 3] = fmaf(x, bv.w, acc[4 * r4 + 3]);
-          }
+          const float4 bv = *reinterpret_cast<const float4 *>(BL + l * RM + c4);
+          acc.x = fmaf(x, bv.x, acc.x);
+          acc.y = fmaf(x, bv.y, acc.y);
+          acc.z = fmaf(x, bv.z, acc.z);
+          acc.w = fmaf(x, bv.w, acc.w);
         }
-        float4 *zo = reinterpret_cast<float4 *>(Z + o * RM + h0);
-#pragma unroll
-        for (int r4 = 0; r4 < RH / 4; ++r4)
-          zo[r4] = make_float4(acc[4 * r4], acc[4 * r4 + 1], acc[4 * r4 + 2], acc[4 * r4 + 3]);
+        *reinterpret_cast<float4 *>(Z + o * RM + c4) = acc;
       }
       for (int e = tid; e < r * r; e += nt) {
         float h = 1.f;
@@ -180,9 +171,10 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
       __syncthreads();
       // ---- stage 2: M[i][rho] = sum over Z rows with i_n = i of Z[o][rho] prod_{k!=n,L} B_k[i_k][rho]
       // Z's modes are T's modes without L (row-major).  With one mode j besides n and L
-      // (d = 3), Z is 2-D and the sum runs over j's index directly; otherwise an odometer
-      // walks the modes other than n.  Pairs (i, rho) take S threads each, whose partial
-      // sums are added in split order by the update below.
+      // (d = 3), Z is 2-D and the sum runs over j's index directly (split s taking the
+      // indices j = s (mod S)); otherwise an odometer walks the modes other than n over
+      // contiguous ranges.  Pairs (i, rho) take S threads each, whose partial sums are added
+      // in split order by the update below.
       const int In = a.dims[n];
       const int npairs = In * r;
       const int other = zrows / In;
@@ -194,17 +186,17 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
           if (k != n && k != L) jo = k;
         const bool n_first = jo < 0 || n < jo;  // Z = [n][jo] or [jo][n]
         const int Bo = jo >= 0 ? boff[jo] : 0;
+        const int zstep = (n_first ? 1 : In) * S;
         for (int w = tid; w < npairs * S; w += nt) {
-          const int pr = w % npairs, s = w / npairs;
+          const int s = w / npairs, pr = w - s * npairs;
           const int i = pr / r, rho = pr - (pr / r) * r;
-          const int j0 = (int)((int64_t)other * s / S), j1 = (int)((int64_t)other * (s + 1) / S);
-          const int zstep = n_first ? 1 : In;
-          int zoff = n_first ? i * other + j0 : j0 * In + i;
+          int zoff = n_first ? i * other + s : s * In + i;
           float acc = 0.f;
           if (jo >= 0) {
-            for (int j = j0; j < j1; ++j, zoff += zstep) acc += Z[zoff * RM + rho] * sB[Bo + j * RM + rho];
+            const float *bo = sB + Bo + rho;
+            for (int j = s; j < other; j += S, zoff += zstep) acc += Z[zoff * RM + rho] * bo[j * RM];
           } else {
-            for (int j = j0; j < j1; ++j, zoff += zstep) acc += Z[zoff * RM + rho];
+            for (int j = s; j < other; j += S, zoff += zstep) acc += Z[zoff * RM + rho];
           }
           part[w] = acc;
         }
@@ -287,8 +279,10 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
       for (int e = tid; e < npairs; e += nt) {
         const int i = e / r, c = e - (e / r) * r;
         float m = 0.f;  // the S partial sums of pair e, in split order
+#pragma unroll 4
         for (int s = 0; s < S; ++s) m += part[s * npairs + e];
         float den = 0.f;
+#pragma unroll 4
         for (int s2 = 0; s2 < r; ++s2) den = fmaf(Bn[i * RM + s2], H[s2 * r + c], den);
         part[e] = mu_cp(Bn[i * RM + c], m, den, eps, &nclip);
       }
@@ -298,6 +292,7 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
       for (int e = tid; e < r * r; e += nt) {
         const int x = e / r, y = e - (e / r) * r;
         float acc = 0.f;
+#pragma unroll 4
         for (int i = 0; i < In; ++i) acc = fmaf(Bn[i * RM + x], Bn[i * RM + y], acc);
         sW[n * r * r + e] = acc;
       }
