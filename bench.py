@@ -133,7 +133,7 @@ def summarize(args):
     res = {"source_sha": sources_sha(), "copy_fetch_kib": copy_f, "copy_write_kib": copy_w,
            "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
     alg = {}
-    for key, esz in (("ttm_last_lds_k<true", 2), ("ttm_mid_bf16_k", 2),
+    for key, esz in (("ttm_last_lds_k<true", 2), ("ttm_mid_lds_k", 2),
                      ("ttm_last_lds_k<false", 4), ("ttm_mid_f32_k", 4)):
         fk, wk = pick(fetch, key), pick(write, key)
         if fk is None or wk is None:
@@ -297,7 +297,7 @@ def main():
     traffic = None
     if os.path.exists(COUNTERS):
         cnt = json.load(open(COUNTERS))
-        key = {"ttm_last_bf16": "ttm_last_lds_k<true", "ttm_mid_bf16": "ttm_mid_bf16_k"}[dom]
+        key = {"ttm_last_bf16": "ttm_last_lds_k<true", "ttm_mid_bf16": "ttm_mid_lds_k"}[dom]
         if cnt.get("source_sha") == sources_sha() and key in cnt.get("kernels", {}):
             traffic = round(cnt["kernels"][key]["traffic_bytes"])
     roofline = {"bound": "hbm", "achieved": round(dk["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

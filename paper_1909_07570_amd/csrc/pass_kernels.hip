@@ -2,8 +2,8 @@
 // every wave keeps the loads of its next work unit in flight while the MFMAs consume the
 // current one, so each CU holds tens of KiB of X requests at any time.
 //
-//   ttm_last_pipe_k : out[m][r] = sum_k X[m][k] F(k, r)        (contraction index contiguous)
-//   ttm_mid_pipe_k  : out[p][r][q] = sum_n F(n, r) X[p][n][q]  (contraction index strided)
+//   ttm_last_pipe_k / ttm_last_lds_k : out[m][r] = sum_k X[m][k] F(k, r)  (contraction index contiguous)
+//   ttm_mid_lds_k   : out[p][r][q] = sum_n F(n, r) X[p][n][q]  (contraction index strided, bf16)
 // X is FP32 (v_mfma_f32_16x16x4_f32) or bfloat16 (v_mfma_f32_16x16x32_bf16, FP32
 // accumulation, factor applied as bf16 hi + lo parts).  The factor (R <= 32 columns,
 // zero-padded to 16-column tiles) lives in LDS.
@@ -167,147 +167,164 @@ __global__ __launch_bounds__(kPassThreads) void ttm_last_pipe_k(const void *__re
 }
 
 // =====================================================================================
-// Earlier-mode contraction.  A wave owns Q-tile (p, q0 .. q0 + QT) and walks the contracted
-// index n in steps; the loads of step s+1 are in flight during the MFMAs of step s.
-//   bf16 (QT = 128): a step is 32 rows n0 + 8 lg + j (j < 8); lane (li, lg) loads the 16 bytes
-//        X[p][n][q0 + 8 li ..] of each, transposes the 8 x 8 block in registers into eight
-//        A operands (one per q offset c: the 8 n values of that q), so MFMA c's output row i
-//        stands for q = q0 + 8 i + c and lane group lg owns q0 + 32 lg + [0, 32).
-//   f32  (QT = 64): a step is 32 rows n0 + lg + 4 s (s < 8); lane loads X[p][n][q0 + 4 li ..],
-//        component c feeds MFMA c whose output row i stands for q = q0 + 4 i + c; lane group
-//        lg owns q0 + 16 lg + [0, 16).
+// Earlier-mode contraction, bf16 X: out[p][r][q] = sum_n F(n, r) X[p][n][q].
+// A wave owns a Q-tile (p, q0 .. q0 + 128) and walks n in steps of 32 rows.  Lane (li, lg)
+// loads the 16 bytes X[p][n][q0 + 8 li ..] of rows n = 32 s + 8 lg + j (j < 8) and
+// transposes that 8 x 8 block in registers into eight A operands (operand c: the 8 n values
+// of q = q0 + 8 i + c, i = li), so MFMA c's output row i stands for q0 + 8 i + c.  Three
+// steps are in flight: each step refills its buffer for the step three ahead right after
+// its MFMAs, and every refill is issued on every path (rows past N and steps past the tile
+// read the tile's last row, which is cached), so the waits are exact.  Every block issues
+// its first tile's loads before it builds the factor's bf16 hi / lo rows in LDS, and a
+// wave issues its next tile's loads before it writes the current tile's output, which goes
+// through the wave's LDS region so that each store instruction covers two whole rows.
 // =====================================================================================
-template <bool BF, int RT>
-__global__ __launch_bounds__(kPassThreads) void ttm_mid_pipe_k(const void *__restrict__ Xv, int64_t P,
-                                                               int N, int64_t Q,
+constexpr int kMidWaves = 8;
+constexpr int kMidDepth = 3;
+
+template <int RT>
+__global__ __launch_bounds__(64 * kMidWaves) void ttm_mid_lds_k(const uint16_t *__restrict__ X,
+                                                               int64_t P, int N, int64_t Q,
                                                                const float *__restrict__ F,
                                                                int64_t ldl, int64_t ldr, int R,
                                                                float *__restrict__ out) {
-  extern __shared__ __attribute__((aligned(16))) uint16_t lds_u16[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_b[];
   constexpr int RP = 16 * RT;
-  constexpr int QT = BF ? 128 : 64;
-  constexpr int NSTEP = 32;
-  const int Np = (N + NSTEP - 1) / NSTEP * NSTEP;
-  const int NS = Np + 8;   // bf16: [RP][NS] hi then lo (transposed factor)
-  const int RS = RP + 4;   // f32: [Np][RS]
-  uint16_t *hi = lds_u16;
-  uint16_t *lo = lds_u16 + RP * NS;
-  float *fl = reinterpret_cast<float *>(lds_u16);
-  if (BF) {
-    for (int e = threadIdx.x; e < RP * Np; e += blockDim.x) {
-      const int r = e / Np, n = e - r * Np;
-      const float a = (n < N && r < R) ? F[n * ldl + r * ldr] : 0.f;
-      const uint16_t h = p_f2bf(a);
-      hi[r * NS + n] = h;
-      lo[r * NS + n] = p_f2bf(a - p_bf2f(h));
+  const int Np = (N + 31) & ~31;
+  const int NS = Np + 8;
+  uint16_t *hi = reinterpret_cast<uint16_t *>(lds_b);
+  uint16_t *lo = hi + RP * NS;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane & 15, lg = lane >> 4;
+  const int64_t qt = (Q + 127) >> 7;
+  const int64_t ntile = P * qt;
+  const int nsteps = Np >> 5;
+  float *stg = reinterpret_cast<float *>(lds_b + 2 * RP * NS * 2) + wave * (R * 128);
+  u4 v[kMidDepth][8];
+  const uint16_t *xp = X;  // lane's column of the current tile
+  int nlim = 0;            // last row a load may touch (0: one line, for loads past the work)
+  auto tile_base = [&](int64_t t) {
+    const int64_t p = t / qt;
+    const int64_t q0 = (t - p * qt) * 128;
+    const int64_t qa = q0 + 8 * li;
+    xp = X + p * (int64_t)N * Q + (qa < Q ? qa : Q - 8);
+    nlim = N - 1;
+  };
+  auto load = [&](u4 (&vv)[8], int s) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int n = min(32 * s + 8 * lg + j, nlim);
+      vv[j] = __builtin_nontemporal_load(reinterpret_cast<const u4 *>(xp + (int64_t)n * Q));
     }
-  } else {
-    for (int e = threadIdx.x; e < Np * RP; e += blockDim.x) {
-      const int n = e / RP, r = e - n * RP;
-      fl[n * RS + r] = (n < N && r < R) ? F[n * ldl + r * ldr] : 0.f;
+  };
+  int64_t t = (int64_t)blockIdx.x * kMidWaves + wave;
+  const int64_t tstride = (int64_t)gridDim.x * kMidWaves;
+  if (t < ntile) tile_base(t);
+#pragma unroll
+  for (int b = 0; b < kMidDepth; ++b) load(v[b], b);
+  __builtin_amdgcn_sched_barrier(0);  // the X loads go out before the factor is staged
+  {
+    const int total = RP * Np;
+    constexpr int kB = 8;
+    for (int e0 = 0; e0 < total; e0 += kB * 64 * kMidWaves) {
+      float fv[kB];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        const int e = e0 + threadIdx.x + u * 64 * kMidWaves;
+        const int n = e / RP, r = e - (e / RP) * RP;
+        const bool ok = e < total && n < N && r < R;
+        fv[u] = F[(ok ? n : 0) * ldl + (ok ? r : 0) * ldr];
+      }
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        const int e = e0 + threadIdx.x + u * 64 * kMidWaves;
+        const int n = e / RP, r = e - (e / RP) * RP;
+        const bool ok = e < total && n < N && r < R;
+        const float a = ok ? fv[u] : 0.f;  // masked where the value is awaited
+        const uint16_t h = p_f2bf(a);
+        if (e < total) {
+          hi[r * NS + n] = h;
+          lo[r * NS + n] = p_f2bf(a - p_bf2f(h));
+        }
+      }
     }
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane & 15, lg = lane >> 4;
-  const int nw = blockDim.x >> 6;
-  const int64_t qt = (Q + QT - 1) / QT;
-  const int64_t ntile = P * qt;
-  const int nsteps = Np / NSTEP;
-  constexpr int NC = BF ? 8 : 4;  // accumulator sets (q offsets) per 16-column tile
-  for (int64_t t = (int64_t)blockIdx.x * nw + wave; t < ntile; t += (int64_t)gridDim.x * nw) {
+  for (; t < ntile; t += tstride) {
     const int64_t p = t / qt;
-    const int64_t q0 = (t - p * qt) * QT;
-    const int64_t qa = q0 + (BF ? 8 : 4) * li;
-    const bool qv = qa < Q;
-    const char *xp = reinterpret_cast<const char *>(Xv) + (p * (int64_t)N * Q + (qv ? qa : 0)) * (BF ? 2 : 4);
-    const int64_t rowbytes = Q * (BF ? 2 : 4);
-    f4 acc[NC][RT];
+    const int64_t q0 = (t - p * qt) * 128;
+    f4 acc[8][RT];
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+    for (int c = 0; c < 8; ++c)
 #pragma unroll
       for (int nt = 0; nt < RT; ++nt) acc[c][nt] = f4{0.f, 0.f, 0.f, 0.f};
-    // row of slot j in step s: bf16 n0 + 8 lg + j, f32 n0 + lg + 4 j
-    auto load_step = [&](u4 (&v)[8], int s) {
-      const int n0 = s * NSTEP;
+    auto step = [&](u4 (&vv)[8], int s) {
+      u4 bh[RT], bl[RT];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int n = BF ? (n0 + 8 * lg + j) : (n0 + lg + 4 * j);
-        v[j] = (qv && n < N) ? *reinterpret_cast<const u4 *>(xp + (int64_t)n * rowbytes)
-                             : u4{0u, 0u, 0u, 0u};
+      for (int nt = 0; nt < RT; ++nt) {
+        const int off = (nt * 16 + li) * NS + s * 32 + 8 * lg;
+        bh[nt] = *reinterpret_cast<const u4 *>(hi + off);
+        bl[nt] = *reinterpret_cast<const u4 *>(lo + off);
       }
-    };
-    auto compute_step = [&](const u4 (&v)[8], int s) {
-      const int n0 = s * NSTEP;
-      if (BF) {
-        u4 bh[RT], bl[RT];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        u4 op;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const uint32_t a = vv[2 * w][c >> 1], b = vv[2 * w + 1][c >> 1];
+          op[w] = (c & 1) ? ((a >> 16) | (b & 0xffff0000u)) : ((a & 0xffffu) | (b << 16));
+        }
 #pragma unroll
         for (int nt = 0; nt < RT; ++nt) {
-          const int off = (nt * 16 + li) * NS + n0 + 8 * lg;
-          bh[nt] = *reinterpret_cast<const u4 *>(hi + off);
-          bl[nt] = *reinterpret_cast<const u4 *>(lo + off);
-        }
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          u4 op;
-#pragma unroll
-          for (int w = 0; w < 4; ++w) {
-            const uint32_t a = v[2 * w][c >> 1], b = v[2 * w + 1][c >> 1];
-            op[w] = (c & 1) ? ((a >> 16) | (b & 0xffff0000u)) : ((a & 0xffffu) | (b << 16));
-          }
-#pragma unroll
-          for (int nt = 0; nt < RT; ++nt) {
-            acc[c][nt] = p_mfma_bf16(op, bh[nt], acc[c][nt]);
-            acc[c][nt] = p_mfma_bf16(op, bl[nt], acc[c][nt]);
-          }
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int n = n0 + lg + 4 * j;
-          const f4 xv = __builtin_bit_cast(f4, v[j]);
-          const float *brow = fl + n * RS + li;
-#pragma unroll
-          for (int nt = 0; nt < RT; ++nt) {
-            const float b = brow[nt * 16];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) acc[c][nt] = p_mfma_f32(xv[c], b, acc[c][nt]);
-          }
+          acc[c][nt] = p_mfma_bf16(op, bh[nt], acc[c][nt]);
+          acc[c][nt] = p_mfma_bf16(op, bl[nt], acc[c][nt]);
         }
       }
+      load(vv, s + kMidDepth);
+      __builtin_amdgcn_sched_barrier(0);  // the refill stays ahead of the next step
     };
-    u4 v0[8], v1[8];
-    load_step(v0, 0);
-    for (int s = 0; s < nsteps; s += 2) {
-      if (s + 1 < nsteps) load_step(v1, s + 1);
-      compute_step(v0, s);
-      if (s + 1 >= nsteps) break;
-      if (s + 2 < nsteps) load_step(v0, s + 2);
-      compute_step(v1, s + 1);
+    int s = 0;
+    for (; s + kMidDepth <= nsteps; s += kMidDepth) {
+#pragma unroll
+      for (int b = 0; b < kMidDepth; ++b) step(v[b], s + b);
     }
+#pragma unroll
+    for (int b = 0; b < kMidDepth - 1; ++b)
+      if (s + b < nsteps) step(v[b], s + b);
+    // the next tile's first steps (or, after the last tile, one cached line) go out
+    // before this tile's output is written
+    const int64_t tn = t + tstride;
+    if (tn < ntile)
+      tile_base(tn);
+    else
+      nlim = 0;
+#pragma unroll
+    for (int b = 0; b < kMidDepth; ++b) load(v[b], b);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int nt = 0; nt < RT; ++nt) {
       const int r = nt * 16 + li;
-      if (r >= R) continue;
-      float *orow = out + (p * R + r) * Q;
+      if (r < R) {
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        if (BF) {
-          const int64_t q = q0 + 32 * lg + 8 * jj;
-          if (q < Q) {
-            *reinterpret_cast<f4 *>(orow + q) =
-                f4{acc[0][nt][jj], acc[1][nt][jj], acc[2][nt][jj], acc[3][nt][jj]};
-            *reinterpret_cast<f4 *>(orow + q + 4) =
-                f4{acc[4 % NC][nt][jj], acc[5 % NC][nt][jj], acc[6 % NC][nt][jj], acc[7 % NC][nt][jj]};
-          }
-        } else {
-          const int64_t q = q0 + 16 * lg + 4 * jj;
-          if (q < Q)
-            *reinterpret_cast<f4 *>(orow + q) =
-                f4{acc[0][nt][jj], acc[1][nt][jj], acc[2][nt][jj], acc[3][nt][jj]};
+        for (int jj = 0; jj < 4; ++jj) {
+          const int qq = 32 * lg + 8 * jj;
+          *reinterpret_cast<f4 *>(stg + r * 128 + qq) =
+              f4{acc[0][nt][jj], acc[1][nt][jj], acc[2][nt][jj], acc[3][nt][jj]};
+          *reinterpret_cast<f4 *>(stg + r * 128 + qq + 4) =
+              f4{acc[4][nt][jj], acc[5][nt][jj], acc[6][nt][jj], acc[7][nt][jj]};
         }
       }
     }
+    __builtin_amdgcn_wave_barrier();  // the wave reads back only what it wrote
+    for (int rr = 0; rr < R; rr += 2) {
+      const int r = rr + (lane >> 5);
+      const int qq = (lane & 31) * 4;
+      if (r < R && q0 + qq < Q)
+        *reinterpret_cast<f4 *>(out + (p * R + r) * Q + q0 + qq) =
+            *reinterpret_cast<const f4 *>(stg + r * 128 + qq);
+    }
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -532,7 +549,6 @@ static nnc_status allow_lds_bytes(const void *kern, size_t bytes) {
 }
 
 constexpr size_t kPassLdsMax = 96 * 1024;
-static int g_pipe_mid = 0;
 constexpr int kPassBlocks = 512;  // persistent: two blocks per CU
 
 size_t pass_last_lds(bool bf, int RT, int64_t K) {
@@ -544,10 +560,10 @@ size_t pass_last_lds(bool bf, int RT, int64_t K) {
   return (size_t)(Kp * (16 * RT + 4) * 4);
 }
 
-size_t pass_mid_lds(bool bf, int RT, int64_t N) {
+// Earlier-mode bf16 kernel: the factor's hi / lo rows plus each wave's output staging.
+size_t pass_mid_lds(int RT, int64_t N, int64_t R) {
   const int64_t Np = (N + 31) / 32 * 32;
-  if (bf) return (size_t)(2 * 16 * RT * (Np + 8) * 2);
-  return (size_t)(Np * (16 * RT + 4) * 4);
+  return (size_t)(2 * 16 * RT * (Np + 8) * 2 + (int64_t)kMidWaves * R * 128 * 4);
 }
 
 // Row-contiguous last-mode kernel: chunks per piece row (CPR) is the largest of 32, 16, 8
@@ -653,26 +669,24 @@ nnc_status launch_pass(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64
 #undef NNC_LAST
     if (kernel_name) *kernel_name = bf ? "ttm_last_pipe_bf16" : "ttm_last_pipe_f32";
   } else {
-    // the earlier-mode contraction keeps its single-buffered kernel (ttm_mid_*_k), which
-    // runs at two waves per SIMD; this pipelined form needs more registers than that
-    if (!g_pipe_mid) return NNC_EUNSUPPORTED;
-    if (Q % (bf ? 8 : 4)) return NNC_EUNSUPPORTED;
-    const size_t lds = pass_mid_lds(bf, RT, N);
-    if (lds > kPassLdsMax || N > (1 << 20)) return NNC_EUNSUPPORTED;
-    const int64_t tiles = P * ((Q + (bf ? 127 : 63)) / (bf ? 128 : 64));
-    const int grid = (int)std::min<int64_t>(std::max<int64_t>((tiles + waves - 1) / waves, 1), kPassBlocks);
-#define NNC_MID(BFV, RTV)                                                                         \
+    // earlier mode: bf16 X takes ttm_mid_lds_k; FP32 X keeps the single-buffered
+    // ttm_mid_f32_k (kernels.hip)
+    if (!bf || Q % 8) return NNC_EUNSUPPORTED;
+    const size_t lds = pass_mid_lds(RT, N, R);
+    if (lds > kCuLdsBytes || N > (1 << 20)) return NNC_EUNSUPPORTED;
+    const int64_t tiles = P * ((Q + 127) / 128);
+    int grid = (int)std::min<int64_t>((tiles + kMidWaves - 1) / kMidWaves, device_cu_count());
+    if (grid < 1) grid = 1;
+#define NNC_MID(RTV)                                                                              \
   do {                                                                                            \
-    NNC_TRY(allow_lds_bytes(reinterpret_cast<const void *>(ttm_mid_pipe_k<BFV, RTV>), lds));      \
-    hipLaunchKernelGGL((ttm_mid_pipe_k<BFV, RTV>), dim3(grid), dim3(kPassThreads), lds, s, X, P,  \
-                       (int)N, Q, F, ldl, ldr, (int)R, out);                                      \
+    NNC_TRY(allow_lds_bytes(reinterpret_cast<const void *>(ttm_mid_lds_k<RTV>), lds));            \
+    hipLaunchKernelGGL((ttm_mid_lds_k<RTV>), dim3(grid), dim3(64 * kMidWaves), lds, s,             \
+                       (const uint16_t *)X, P, (int)N, Q, F, ldl, ldr, (int)R, out);               \
   } while (0)
-    if (bf && RT == 1) NNC_MID(true, 1);
-    else if (bf) NNC_MID(true, 2);
-    else if (RT == 1) NNC_MID(false, 1);
-    else NNC_MID(false, 2);
+    if (RT == 1) NNC_MID(1);
+    else NNC_MID(2);
 #undef NNC_MID
-    if (kernel_name) *kernel_name = bf ? "ttm_mid_pipe_bf16" : "ttm_mid_pipe_f32";
+    if (kernel_name) *kernel_name = "ttm_mid_bf16";
   }
   NNC_HIP(hipGetLastError());
   return NNC_OK;
