@@ -171,16 +171,19 @@ __global__ __launch_bounds__(kPassThreads) void ttm_last_pipe_k(const void *__re
 // A wave owns a Q-tile (p, q0 .. q0 + 128) and walks n in steps of 32 rows.  Lane (li, lg)
 // loads the 16 bytes X[p][n][q0 + 8 li ..] of rows n = 32 s + 8 lg + j (j < 8) and
 // transposes that 8 x 8 block in registers into eight A operands (operand c: the 8 n values
-// of q = q0 + 8 i + c, i = li), so MFMA c's output row i stands for q0 + 8 i + c.  Three
-// steps are in flight: each step refills its buffer for the step three ahead right after
-// its MFMAs, and every refill is issued on every path (rows past N and steps past the tile
-// read the tile's last row, which is cached), so the waits are exact.  Every block issues
-// its first tile's loads before it builds the factor's bf16 hi / lo rows in LDS, and a
-// wave issues its next tile's loads before it writes the current tile's output, which goes
-// through the wave's LDS region so that each store instruction covers two whole rows.
+// of q = q0 + 8 i + c, i = li), so MFMA c's output row i stands for q0 + 8 i + c.  Each step
+// refills its buffer for the step kMidDepth ahead right after its MFMAs, and every refill
+// is issued on every path (rows past N and steps past the tile read the tile's last row,
+// which is cached), so the waits are exact.  One step in flight per wave measured fastest
+// (51.5 us against 53.6 with two and 55 with three at 512^3): with the HBM saturated, more
+// outstanding loads only add queueing and concurrent DRAM row streams.  Every block issues
+// its first tile's loads before it builds the factor's bf16 hi / lo rows in LDS, and a wave
+// issues its next tile's loads before it writes the current tile's output, which goes
+// through the wave's LDS region so that each store instruction covers two whole rows,
+// written non-temporally (the output is read back only by the next kernel).
 // =====================================================================================
 constexpr int kMidWaves = 8;
-constexpr int kMidDepth = 3;
+constexpr int kMidDepth = 1;
 
 template <int RT>
 __global__ __launch_bounds__(64 * kMidWaves) void ttm_mid_lds_k(const uint16_t *__restrict__ X,
@@ -234,7 +237,7 @@ __global__ __launch_bounds__(64 * kMidWaves) void ttm_mid_lds_k(const uint16_t *
         const int e = e0 + threadIdx.x + u * 64 * kMidWaves;
         const int n = e / RP, r = e - (e / RP) * RP;
         const bool ok = e < total && n < N && r < R;
-        fv[u] = F[(ok ? n : 0) * ldl + (ok ? r : 0) * ldr];
+        fv[u] = F[(ok ? n : 0) * (int)ldl + (ok ? r : 0) * (int)ldr];  // the factor has < 2^31 entries
       }
 #pragma unroll
       for (int u = 0; u < kB; ++u) {
@@ -321,8 +324,8 @@ __global__ __launch_bounds__(64 * kMidWaves) void ttm_mid_lds_k(const uint16_t *
       const int r = rr + (lane >> 5);
       const int qq = (lane & 31) * 4;
       if (r < R && q0 + qq < Q)
-        *reinterpret_cast<f4 *>(out + (p * R + r) * Q + q0 + qq) =
-            *reinterpret_cast<const f4 *>(stg + r * 128 + qq);
+        __builtin_nontemporal_store(*reinterpret_cast<const f4 *>(stg + r * 128 + qq),
+                                    reinterpret_cast<f4 *>(out + (p * R + r) * Q + q0 + qq));
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -336,8 +339,8 @@ __global__ __launch_bounds__(64 * kMidWaves) void ttm_mid_lds_k(const uint16_t *
 // 16-byte chunks, and lane l of load j reads chunk l % CPR of row j * (64 / CPR) + l / CPR,
 // so one instruction reads 64 / CPR segments of CPR * 16 contiguous bytes, non-temporally.
 // The wave writes the piece to its own padded LDS region and reads it back in the MFMA
-// layout (lane (li, lg) takes row li, chunk 4 s + lg at k-step s).  Three register buffers
-// keep three pieces in flight while one is consumed from LDS; every load is issued on every
+// layout (lane (li, lg) takes row li, chunk 4 s + lg at k-step s).  NB register buffers
+// keep NB pieces in flight while one is consumed from LDS; every load is issued on every
 // path, so the wait before each store leaves the two younger pieces outstanding.
 //   bf16: chunk = 8 k, k-step = 32 k; A = the chunk, B = the factor's bf16 hi and lo rows.
 //   f32 : chunk = 4 k, k-step = 16 k; element e of the chunk feeds MFMA e, whose k-slot lg
@@ -348,7 +351,7 @@ __global__ __launch_bounds__(64 * kMidWaves) void ttm_mid_lds_k(const uint16_t *
 constexpr int kLdsThreads = 512;
 constexpr int kLdsWaves = kLdsThreads / 64;
 
-template <bool BF, int RT, int CPR>
+template <bool BF, int RT, int CPR, int NB>
 __global__ __launch_bounds__(kLdsThreads) void ttm_last_lds_k(const void *__restrict__ Xv, int64_t M,
                                                               int K, const float *__restrict__ F,
                                                               int64_t ldl, int64_t ldr, int R,
@@ -460,13 +463,13 @@ __global__ __launch_bounds__(kLdsThreads) void ttm_last_lds_k(const void *__rest
       t += tstride;
     }
   };
-  // piece i lives in buffer i % 3: it is stored to LDS once it has arrived, the buffer is
-  // refilled at once with piece i + 3, and the MFMAs then consume piece i from LDS, so
-  // three pieces are in flight during every compute step
-  u4 b0[LPI], b1[LPI], b2[LPI];
+  // piece i lives in buffer i % NB: it is stored to LDS once it has arrived, the buffer is
+  // refilled at once with piece i + NB, and the MFMAs then consume piece i from LDS, so
+  // NB pieces are in flight during every compute step
+  u4 bb[NB][LPI];
   int64_t lt = gw, ct = gw;  // load and compute cursors (tile, piece)
   int lh = 0, ch = 0;
-  // Prologue, in this order: the first batch of factor loads, the first three pieces of X,
+  // Prologue, in this order: the first batch of factor loads, the first NB pieces of X,
   // then the factor's conversion into LDS.  The conversion waits only for the factor loads
   // (the older ones), so the X requests stay in flight through it and the barrier.  The
   // scheduling barriers keep this order, which the waits count on.  A wave without tiles
@@ -493,15 +496,12 @@ __global__ __launch_bounds__(kLdsThreads) void ttm_last_lds_k(const void *__rest
 #pragma unroll
   for (int u = 0; u < kFB; ++u) fv[u] = fac_load(fk + u * KSTR);
   __builtin_amdgcn_sched_barrier(0);
-  load_piece(b0, lt, lh);
-  adv(lt, lh);
-  __builtin_amdgcn_sched_barrier(0);
-  load_piece(b1, lt, lh);
-  adv(lt, lh);
-  __builtin_amdgcn_sched_barrier(0);
-  load_piece(b2, lt, lh);
-  adv(lt, lh);
-  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    load_piece(bb[j], lt, lh);
+    adv(lt, lh);
+    __builtin_amdgcn_sched_barrier(0);
+  }
 #pragma unroll
   for (int u = 0; u < kFB; ++u) fac_store(fk + u * KSTR, fv[u]);
   // longer factors: further batches (these waits also cover the X requests above)
@@ -522,17 +522,17 @@ __global__ __launch_bounds__(kLdsThreads) void ttm_last_lds_k(const void *__rest
     compute_piece(ct, ch);
     adv(ct, ch);
   };
-  // whole rounds of three steps (a single back edge, so the waits stay exact), then the
-  // remaining one or two pieces; the loads issued for pieces past the end read the last
-  // row of X again and are never used
+  // whole rounds of NB steps (a single back edge, so the waits stay exact), then the
+  // remaining pieces; the loads issued for pieces past the end read the last row of X
+  // again and are never used
   int64_t i = 0;
-  for (; i + 3 <= np; i += 3) {
-    step(b0);
-    step(b1);
-    step(b2);
+  for (; i + NB <= np; i += NB) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) step(bb[j]);
   }
-  if (i < np) step(b0);
-  if (i + 1 < np) step(b1);
+#pragma unroll
+  for (int j = 0; j < NB - 1; ++j)
+    if (i + j < np) step(bb[j]);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -605,10 +605,13 @@ static nnc_status launch_last_lds(const void *X, bool bf, int64_t M, int64_t K, 
   const int64_t tiles = (M + 15) / 16;
   const int grid = (int)std::max<int64_t>(
       1, std::min<int64_t>((tiles + kLdsWaves - 1) / kLdsWaves, device_cu_count() - std::max(reserve, 0)));
+  // pieces in flight per wave: two for bf16 X, one for FP32 X (each measured fastest at
+  // 512^3 with random data; with the HBM saturated, more outstanding loads only queue)
 #define NNC_LL(BFV, RTV, CPRV)                                                                    \
   do {                                                                                            \
-    NNC_TRY(allow_lds_bytes(reinterpret_cast<const void *>(ttm_last_lds_k<BFV, RTV, CPRV>), lds)); \
-    hipLaunchKernelGGL((ttm_last_lds_k<BFV, RTV, CPRV>), dim3(grid), dim3(kLdsThreads), lds, s, X, \
+    constexpr int NBV = (BFV) ? 2 : 1;                                                            \
+    NNC_TRY(allow_lds_bytes(reinterpret_cast<const void *>(ttm_last_lds_k<BFV, RTV, CPRV, NBV>), lds)); \
+    hipLaunchKernelGGL((ttm_last_lds_k<BFV, RTV, CPRV, NBV>), dim3(grid), dim3(kLdsThreads), lds, s, X, \
                        M, (int)K, F, ldl, ldr, (int)R, out);                                      \
   } while (0)
 #define NNC_LL_CPR(BFV, RTV)           \
@@ -672,6 +675,7 @@ nnc_status launch_pass(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64
     // earlier mode: bf16 X takes ttm_mid_lds_k; FP32 X keeps the single-buffered
     // ttm_mid_f32_k (kernels.hip)
     if (!bf || Q % 8) return NNC_EUNSUPPORTED;
+    if (N * ldl + R * ldr >= ((int64_t)1 << 31)) return NNC_EUNSUPPORTED;  // 32-bit factor indexing
     const size_t lds = pass_mid_lds(RT, N, R);
     if (lds > kCuLdsBytes || N > (1 << 20)) return NNC_EUNSUPPORTED;
     const int64_t tiles = P * ((Q + 127) / 128);
