@@ -57,6 +57,23 @@ def test_ttm_bf16_every_mode(shape, R):
         assert err <= 1e-4, (shape, R, n, err)
 
 
+# Earlier-mode bf16 pass with more 128-column tiles than waves (several tiles per wave, the
+# next tile's loads issued before the current tile's output) and a ragged last tile.
+@pytest.mark.parametrize("shape", [(16, 1000, 524), (24, 1000, 1048)])
+@pytest.mark.parametrize("R", [12, 20])
+def test_ttm_mid_bf16_several_tiles_per_wave(shape, R):
+    nnc = need_gpu()
+    rng = np.random.default_rng(hash((shape, R, 2)) % 2**32)
+    X64 = synth.round_bf16(rng.random(shape))
+    A = rng.random((shape[0], R)).astype(np.float32)
+    out = host(nnc.nnc_ttm(bf16_dev(X64), 0, dev(A)))
+    ref = oracle.ttm_t(X64, 0, A.astype(np.float64))
+    assert rel_fro(out, ref) <= 1e-4
+    # every column (tile) checked on its own, the ragged last one included
+    col_err = np.abs(out - ref).max(axis=0) / np.abs(ref).max(axis=0)
+    assert col_err.max() <= 1e-4, int(np.argmax(col_err))
+
+
 # Last-mode (contraction index contiguous) shapes chosen for the row-contiguous pass kernel:
 # every piece width (64/128/256 k for bf16, 32/64/128 for f32), partial last pieces, fewer
 # rows than one tile, ragged row counts, and enough tiles that waves get 1..3 pieces each.
