@@ -105,7 +105,10 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
   // consecutive addresses).  Indices past a region repeat its last element: the same value
   // stored twice to the same place.
   constexpr int kSG = 16, kSY = 8;
-  const UDiv dpost = make_udiv(post);
+  const UDiv dpost = make_udiv(post), dnr = make_udiv(nr);
+  // Y rows are contiguous along q when post > 1, but with post == 1 (last mode) only the
+  // block's nr rows of each column are adjacent: the row index then runs fastest
+  const bool rows_fast = post == 1;
   for (int c0 = 0; c0 < C; c0 += CH) {
     const int cn = (C - c0) < CH ? (C - c0) : CH;
     const int ng = cn * R, ny = nr * cn;
@@ -126,7 +129,8 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
       for (int u = 0; u < kSY; ++u) {  // row i, column c0 + cc: Y[p][i0 + i][q]
         int idx = yb + tid + u * kRowThreads;
         idx = idx < ny ? idx : ny - 1;
-        const int i = udiv(idx, dcn), cc = idx - i * cn;
+        const int ia = udiv(idx, dcn), ib = udiv(idx, dnr);
+        const int i = rows_fast ? idx - ib * nr : ia, cc = rows_fast ? ib : idx - ia * cn;
         const int c = c0 + cc, pp = udiv(c, dpost), q = c - pp * post;
         vy[u] = Y[((int64_t)pp * Nn + i0 + i) * post + q];
         oy[u] = CH * GS + i * YS + cc;
@@ -206,11 +210,20 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
     // with a single chunk the Y values are still in Ys (Ys[i][p]), else they are read again.
     float *gp = gpart + (int64_t)blockIdx.x * pre * R;
     if (C <= CH) {
-      for (int idx = tid; idx < pre * R; idx += kRowThreads) {
-        const int pp = idx / R, rr = idx - (idx / R) * R;
-        float s2 = 0.f;
-        for (int i = 0; i < nr; ++i) s2 = fmaf(Ys[i * YS + pp], As[i][rr], s2);
-        gp[(int64_t)pp * R + rr] = s2;
+      // thread (g, rr): column rr of the new rows in registers, columns p = g, g + ng, ...
+      const int ng2 = kRowThreads / R;
+      const int g = tid / R, rr = tid - (tid / R) * R;
+      if (g < ng2) {
+        float ar[kRB];
+#pragma unroll
+        for (int i = 0; i < kRB; ++i) ar[i] = i < nr ? As[i][rr] : 0.f;
+        for (int pp = g; pp < pre; pp += ng2) {
+          float s2 = 0.f;
+#pragma unroll
+          for (int i = 0; i < kRB; ++i)
+            if (i < nr) s2 = fmaf(Ys[i * YS + pp], ar[i], s2);
+          gp[(int64_t)pp * R + rr] = s2;
+        }
       }
     } else {
       const int PC = (CH * GS + kRB * YS) / kRB;  // rows of p per chunk that fit
