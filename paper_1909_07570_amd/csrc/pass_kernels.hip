@@ -184,6 +184,7 @@ __global__ __launch_bounds__(kPassThreads) void ttm_last_pipe_k(const void *__re
 // =====================================================================================
 constexpr int kMidWaves = 8;
 constexpr int kMidDepth = 1;
+constexpr int kMidDepthF32 = 1;  // steps in flight per wave, FP32 X (one measured fastest, as for bf16)
 
 template <int RT>
 __global__ __launch_bounds__(64 * kMidWaves) void ttm_mid_lds_k(const uint16_t *__restrict__ X,
@@ -325,6 +326,140 @@ __global__ __launch_bounds__(64 * kMidWaves) void ttm_mid_lds_k(const uint16_t *
       const int qq = (lane & 31) * 4;
       if (r < R && q0 + qq < Q)
         __builtin_nontemporal_store(*reinterpret_cast<const f4 *>(stg + r * 128 + qq),
+                                    reinterpret_cast<f4 *>(out + (p * R + r) * Q + q0 + qq));
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// =====================================================================================
+// Earlier-mode contraction, FP32 X (v_mfma_f32_16x16x4_f32), same schedule as ttm_mid_lds_k.
+// A wave owns a Q-tile of 64 columns.  Lane (li, lg) loads the 16 bytes X[p][n][q0 + 4 li ..]
+// of rows n = 32 s + 8 lg + j (j < 8); for each j, component c of that float4 is the A
+// operand of MFMA (j, c): its K index lg stands for row 32 s + 8 lg + j and its output row i
+// for column q0 + 4 i + c.  The factor (FP32, [n][RS] in LDS) is the B operand.  Lane
+// (li, lg) ends up holding, for output column r = 16 nt + li and i = 0..3, the four
+// adjacent columns q0 + 16 lg + 4 i + (0..3) of each accumulator set c.
+// =====================================================================================
+template <int RT, int DEPTH>
+__global__ __launch_bounds__(64 * kMidWaves) void ttm_mid_lds_f32_k(const float *__restrict__ X,
+                                                                   int64_t P, int N, int64_t Q,
+                                                                   const float *__restrict__ F,
+                                                                   int64_t ldl, int64_t ldr, int R,
+                                                                   float *__restrict__ out) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_b[];
+  constexpr int RP = 16 * RT;
+  constexpr int RS = RP + 2;  // factor row stride: the four row groups of a read land on
+                              // different banks
+  const int Np = (N + 31) & ~31;
+  float *fl = reinterpret_cast<float *>(lds_b);
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane & 15, lg = lane >> 4;
+  const int64_t qt = (Q + 63) >> 6;
+  const int64_t ntile = P * qt;
+  const int nsteps = Np >> 5;
+  float *stg = fl + Np * RS + wave * (R * 64);
+  u4 v[DEPTH][8];
+  const float *xp = X;
+  int nlim = 0;
+  auto tile_base = [&](int64_t t) {
+    const int64_t p = t / qt;
+    const int64_t q0 = (t - p * qt) * 64;
+    const int64_t qa = q0 + 4 * li;
+    xp = X + p * (int64_t)N * Q + (qa < Q ? qa : Q - 4);
+    nlim = N - 1;
+  };
+  auto load = [&](u4 (&vv)[8], int s) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int n = min(32 * s + 8 * lg + j, nlim);
+      vv[j] = __builtin_nontemporal_load(reinterpret_cast<const u4 *>(xp + (int64_t)n * Q));
+    }
+  };
+  int64_t t = (int64_t)blockIdx.x * kMidWaves + wave;
+  const int64_t tstride = (int64_t)gridDim.x * kMidWaves;
+  if (t < ntile) tile_base(t);
+#pragma unroll
+  for (int b = 0; b < DEPTH; ++b) load(v[b], b);
+  __builtin_amdgcn_sched_barrier(0);  // the X loads go out before the factor is staged
+  {
+    const int total = Np * RP;
+    constexpr int kB = 8;
+    for (int e0 = 0; e0 < total; e0 += kB * 64 * kMidWaves) {
+      float fv[kB];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        const int e = e0 + threadIdx.x + u * 64 * kMidWaves;
+        const int n = e / RP, r = e - (e / RP) * RP;
+        const bool ok = e < total && n < N && r < R;
+        fv[u] = F[(ok ? n : 0) * (int)ldl + (ok ? r : 0) * (int)ldr];
+      }
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        const int e = e0 + threadIdx.x + u * 64 * kMidWaves;
+        const int n = e / RP, r = e - (e / RP) * RP;
+        const bool ok = e < total && n < N && r < R;
+        if (e < total) fl[n * RS + r] = ok ? fv[u] : 0.f;  // masked where the value is awaited
+      }
+    }
+  }
+  __syncthreads();
+  for (; t < ntile; t += tstride) {
+    const int64_t p = t / qt;
+    const int64_t q0 = (t - p * qt) * 64;
+    f4 acc[4][RT];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int nt = 0; nt < RT; ++nt) acc[c][nt] = f4{0.f, 0.f, 0.f, 0.f};
+    auto step = [&](u4 (&vv)[8], int s) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const f4 xv = __builtin_bit_cast(f4, vv[j]);
+        const float *brow = fl + (32 * s + 8 * lg + j) * RS + li;
+#pragma unroll
+        for (int nt = 0; nt < RT; ++nt) {
+          const float b = brow[nt * 16];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[c][nt] = p_mfma_f32(xv[c], b, acc[c][nt]);
+        }
+      }
+      load(vv, s + DEPTH);
+      __builtin_amdgcn_sched_barrier(0);  // the refill stays ahead of the next step
+    };
+    int s = 0;
+    for (; s + DEPTH <= nsteps; s += DEPTH) {
+#pragma unroll
+      for (int b = 0; b < DEPTH; ++b) step(v[b], s + b);
+    }
+#pragma unroll
+    for (int b = 0; b < DEPTH - 1; ++b)
+      if (s + b < nsteps) step(v[b], s + b);
+    const int64_t tn = t + tstride;
+    if (tn < ntile)
+      tile_base(tn);
+    else
+      nlim = 0;
+#pragma unroll
+    for (int b = 0; b < DEPTH; ++b) load(v[b], b);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int nt = 0; nt < RT; ++nt) {
+      const int r = nt * 16 + li;
+      if (r < R) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          *reinterpret_cast<f4 *>(stg + r * 64 + 16 * lg + 4 * i) =
+              f4{acc[0][nt][i], acc[1][nt][i], acc[2][nt][i], acc[3][nt][i]};
+      }
+    }
+    __builtin_amdgcn_wave_barrier();  // the wave reads back only what it wrote
+    for (int rr = 0; rr < R; rr += 4) {  // four rows of 64 columns per instruction
+      const int r = rr + (lane >> 4);
+      const int qq = (lane & 15) * 4;
+      if (r < R && q0 + qq < Q)
+        __builtin_nontemporal_store(*reinterpret_cast<const f4 *>(stg + r * 64 + qq),
                                     reinterpret_cast<f4 *>(out + (p * R + r) * Q + q0 + qq));
     }
     __builtin_amdgcn_wave_barrier();
@@ -560,10 +695,12 @@ size_t pass_last_lds(bool bf, int RT, int64_t K) {
   return (size_t)(Kp * (16 * RT + 4) * 4);
 }
 
-// Earlier-mode bf16 kernel: the factor's hi / lo rows plus each wave's output staging.
-size_t pass_mid_lds(int RT, int64_t N, int64_t R) {
+// Earlier-mode kernels: the factor (bf16 hi / lo rows, or FP32 rows) plus each wave's
+// output staging.
+size_t pass_mid_lds(bool bf, int RT, int64_t N, int64_t R) {
   const int64_t Np = (N + 31) / 32 * 32;
-  return (size_t)(2 * 16 * RT * (Np + 8) * 2 + (int64_t)kMidWaves * R * 128 * 4);
+  if (bf) return (size_t)(2 * 16 * RT * (Np + 8) * 2 + (int64_t)kMidWaves * R * 128 * 4);
+  return (size_t)(Np * (16 * RT + 2) * 4 + (int64_t)kMidWaves * R * 64 * 4);
 }
 
 // Row-contiguous last-mode kernel: chunks per piece row (CPR) is the largest of 32, 16, 8
@@ -672,25 +809,33 @@ nnc_status launch_pass(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64
 #undef NNC_LAST
     if (kernel_name) *kernel_name = bf ? "ttm_last_pipe_bf16" : "ttm_last_pipe_f32";
   } else {
-    // earlier mode: bf16 X takes ttm_mid_lds_k; FP32 X keeps the single-buffered
-    // ttm_mid_f32_k (kernels.hip)
-    if (!bf || Q % 8) return NNC_EUNSUPPORTED;
+    // earlier mode: ttm_mid_lds_k (bf16 X) / ttm_mid_lds_f32_k (FP32 X)
+    if (Q % (bf ? 8 : 4)) return NNC_EUNSUPPORTED;
     if (N * ldl + R * ldr >= ((int64_t)1 << 31)) return NNC_EUNSUPPORTED;  // 32-bit factor indexing
-    const size_t lds = pass_mid_lds(RT, N, R);
+    const size_t lds = pass_mid_lds(bf, RT, N, R);
     if (lds > kCuLdsBytes || N > (1 << 20)) return NNC_EUNSUPPORTED;
-    const int64_t tiles = P * ((Q + 127) / 128);
+    const int64_t tiles = P * ((Q + (bf ? 127 : 63)) / (bf ? 128 : 64));
     int grid = (int)std::min<int64_t>((tiles + kMidWaves - 1) / kMidWaves, device_cu_count());
     if (grid < 1) grid = 1;
-#define NNC_MID(RTV)                                                                              \
+#define NNC_MID(KERN)                                                                             \
   do {                                                                                            \
-    NNC_TRY(allow_lds_bytes(reinterpret_cast<const void *>(ttm_mid_lds_k<RTV>), lds));            \
-    hipLaunchKernelGGL((ttm_mid_lds_k<RTV>), dim3(grid), dim3(64 * kMidWaves), lds, s,             \
-                       (const uint16_t *)X, P, (int)N, Q, F, ldl, ldr, (int)R, out);               \
+    NNC_TRY(allow_lds_bytes(reinterpret_cast<const void *>(KERN), lds));                          \
+    hipLaunchKernelGGL(KERN, dim3(grid), dim3(64 * kMidWaves), lds, s, XARG, P, (int)N, Q, F, ldl, \
+                       ldr, (int)R, out);                                                         \
   } while (0)
-    if (RT == 1) NNC_MID(1);
-    else NNC_MID(2);
+    if (bf) {
+#define XARG (const uint16_t *)X
+      if (RT == 1) NNC_MID(ttm_mid_lds_k<1>);
+      else NNC_MID(ttm_mid_lds_k<2>);
+#undef XARG
+    } else {
+#define XARG (const float *)X
+      if (RT == 1) NNC_MID((ttm_mid_lds_f32_k<1, kMidDepthF32>));
+      else NNC_MID((ttm_mid_lds_f32_k<2, kMidDepthF32>));
+#undef XARG
+    }
 #undef NNC_MID
-    if (kernel_name) *kernel_name = "ttm_mid_bf16";
+    if (kernel_name) *kernel_name = bf ? "ttm_mid_bf16" : "ttm_mid_f32";
   }
   NNC_HIP(hipGetLastError());
   return NNC_OK;
