@@ -569,7 +569,8 @@ __global__ __launch_bounds__(kLdsThreads) void ttm_last_lds_k(const void *__rest
     if (h == kpt - 1) {
       // The tile's output rows t*16 .. t*16+15 are one contiguous block of out: the wave
       // puts its accumulators into its staging region (free once the reads above are done;
-      // LDS operations of a wave complete in order) and writes the block in 16-byte pieces.
+      // LDS operations of a wave complete in order) and writes the block in 16-byte pieces,
+      // non-temporally (only the next kernel reads it).
       float *ot = reinterpret_cast<float *>(stg);
 #pragma unroll
       for (int nt = 0; nt < RT; ++nt) {
@@ -585,7 +586,7 @@ __global__ __launch_bounds__(kLdsThreads) void ttm_last_lds_k(const void *__rest
       for (int e0 = 0; e0 < 16 * RP; e0 += 256) {
         const int e = e0 + 4 * lane;
         if (e + 4 <= nfl) {
-          *reinterpret_cast<f4 *>(dst + e) = *reinterpret_cast<const f4 *>(ot + e);
+          __builtin_nontemporal_store(*reinterpret_cast<const f4 *>(ot + e), reinterpret_cast<f4 *>(dst + e));
         } else if (e < nfl) {
           for (int q = e; q < nfl; ++q) dst[q] = ot[q];
         }
@@ -742,11 +743,12 @@ static nnc_status launch_last_lds(const void *X, bool bf, int64_t M, int64_t K, 
   const int64_t tiles = (M + 15) / 16;
   const int grid = (int)std::max<int64_t>(
       1, std::min<int64_t>((tiles + kLdsWaves - 1) / kLdsWaves, device_cu_count() - std::max(reserve, 0)));
-  // pieces in flight per wave: two for bf16 X, one for FP32 X (each measured fastest at
-  // 512^3 with random data; with the HBM saturated, more outstanding loads only queue)
+  // one piece in flight per wave (measured fastest at 512^3 with random data, 51.5-52 us
+  // against 53.5-54 with two and 54-55 with three for bf16 X: with the HBM saturated, more
+  // outstanding loads only queue)
 #define NNC_LL(BFV, RTV, CPRV)                                                                    \
   do {                                                                                            \
-    constexpr int NBV = (BFV) ? 2 : 1;                                                            \
+    constexpr int NBV = 1;                                                                        \
     NNC_TRY(allow_lds_bytes(reinterpret_cast<const void *>(ttm_last_lds_k<BFV, RTV, CPRV, NBV>), lds)); \
     hipLaunchKernelGGL((ttm_last_lds_k<BFV, RTV, CPRV, NBV>), dim3(grid), dim3(kLdsThreads), lds, s, X, \
                        M, (int)K, F, ldl, ldr, (int)R, out);                                      \
