@@ -37,38 +37,28 @@ static __device__ inline int udiv(int a, UDiv d) {
 
 constexpr int kRB = 8;
 constexpr int kRowThreads = 512;
-constexpr int kRowBatch = 16;           // loads in flight per thread while staging
 constexpr int kRowLdsFloats = 14 * 1024;  // dynamic LDS budget of one block (floats)
+constexpr int kRowRed = 4096;             // partial sums of the contraction (floats)
 
-// Copy n values src[map(i)] -> dst[i] for i < n with every thread issuing kRowBatch loads
-// before storing them.
-template <typename Load, typename Store>
-static __device__ inline void staged_copy(int n, Load ld, Store st) {
-  for (int base = 0; base < n; base += kRowBatch * kRowThreads) {
-    float v[kRowBatch];
-#pragma unroll
-    for (int u = 0; u < kRowBatch; ++u) {
-      const int i = base + threadIdx.x + u * kRowThreads;
-      v[u] = i < n ? ld(i) : 0.f;
-    }
-#pragma unroll
-    for (int u = 0; u < kRowBatch; ++u) {
-      const int i = base + threadIdx.x + u * kRowThreads;
-      if (i < n) st(i, v[u]);
-    }
-  }
-}
+// Contraction paths (chosen per launch from the shape):
+//   kPathQ4: post % 4 == 0; a thread takes row i and columns r, r + 1 over a range of
+//            column quads (4 adjacent q of one p): 3 float4 LDS reads per 8 FMAs
+//   kPathP : post == 1, R % 4 == 0; a thread takes rows i, i + 1 and columns r .. r + 3
+//            over a range of p: 2 reads and one float4 read per 8 FMAs
+//   kPathS : anything else, one output per thread, scalar reads
+enum { kPathQ4 = 0, kPathP = 1, kPathS = 2 };
 
-// LDS: Gs[CH][R+1] | Ys[kRB][CH+1]  (dynamic), As, Ms, red (static).
-// Every global read of a chunk (the core columns, the Y rows, and with the first chunk the
-// factor rows and M) is issued before the first is used.  Output (i, r) is summed by
-// kRowThreads / (kRB * R) threads over contiguous ranges of the chunk, each with eight
-// interleaved partial sums; the pieces are added in a fixed order.
+// LDS (dynamic): the chunk of G and of the block's Y rows in their natural layouts,
+//   Gs[(pl * R + r) * qn + qq] = G[p0 + pl][r][q0 + qq]
+//   Ys[(pl * nr + i) * qn + qq] = Y[p0 + pl][i0 + i][q0 + qq]
+// A chunk is pn whole slices p (qn = post) when they fit, else a quad-aligned q range of
+// one slice.  Staging is a plain copy: consecutive threads read consecutive addresses.
+template <int PATH>
 __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict__ Y,
                                                          const float *__restrict__ G,
                                                          float *__restrict__ A,
                                                          const float *__restrict__ M, int pre,
-                                                         int Nn, int post, int R, int CH,
+                                                         int Nn, int post, int R, int PC, int QC,
                                                          double eps, unsigned long long *clips,
                                                          float *__restrict__ gram,
                                                          float *__restrict__ gpart,
@@ -76,112 +66,182 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
   extern __shared__ __attribute__((aligned(16))) float dynr[];
   __shared__ float As[kRB][33];
   __shared__ float Ms[32][33];
-  __shared__ float red[kRowThreads];
+  __shared__ __attribute__((aligned(16))) float red[kRowRed];
   __shared__ unsigned int nclip;
-  const int GS = R + 1, YS = CH + 1;
-  float *Gs = dynr;
-  float *Ys = dynr + CH * GS;
   const int tid = threadIdx.x;
   const int i0 = blockIdx.x * kRB;
   const int nr = (Nn - i0) < kRB ? (Nn - i0) : kRB;
-  const int C = pre * post;
-  const int OR = kRB * R;                               // outputs of a full block
-  const int SPL = kRowThreads / OR;                     // threads per output (>= 2 for R <= 32)
-  const int o = tid % OR, sp = tid / OR;
-  const int ii = o / R, r = o - (o / R) * R;
-  const bool act = sp < SPL && ii < nr;
   if (tid == 0) nclip = 0;
-  float acc8[8];
+  // work items and splits of the contraction (every chunk uses the same assignment, so a
+  // thread's partial sums carry across chunks)
+  const int RH = (R + 1) / 2, RQ = R / 4, NH = (nr + 1) / 2;
+  const int items = PATH == kPathQ4 ? nr * RH : (PATH == kPathP ? NH * RQ : nr * R);
+  const int SPL = kRowThreads / items;  // >= 1: items <= 8 * 32
+  const int item = tid % items, sp = tid / items;
+  const bool act = sp < SPL;
+  int ii, rr;  // first row / column of the item
+  if (PATH == kPathQ4) { ii = item / RH; rr = 2 * (item - ii * RH); }
+  else if (PATH == kPathP) { ii = 2 * (item / RQ); rr = 4 * (item - (item / RQ) * RQ); }
+  else { ii = item / R; rr = item - ii * R; }
+  constexpr int NO = PATH == kPathQ4 ? 2 : (PATH == kPathP ? 8 : 1);  // outputs per item
+  float acc[NO];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) acc8[j] = 0.f;
-  // factor rows and M (first round, with the first chunk's reads)
+  for (int o = 0; o < NO; ++o) acc[o] = 0.f;
+  // factor rows and M, loaded with the first chunk's reads
   const int ai = tid < nr * R ? tid : 0;
   const float av = A[(int64_t)(i0 + ai / R) * R + ai % R];
   const int RR = R * R;
   const float mv0 = M[tid < RR ? tid : 0];
   const float mv1 = M[tid + kRowThreads < RR ? tid + kRowThreads : 0];
-  // staging rounds: kSG core values and kSY Y values per thread, all loads of a round in
-  // flight together; each region in its own branch-free loop (consecutive threads read
-  // consecutive addresses).  Indices past a region repeat its last element: the same value
-  // stored twice to the same place.
-  constexpr int kSG = 16, kSY = 8;
-  const UDiv dpost = make_udiv(post), dnr = make_udiv(nr);
-  // Y rows are contiguous along q when post > 1, but with post == 1 (last mode) only the
-  // block's nr rows of each column are adjacent: the row index then runs fastest
-  const bool rows_fast = post == 1;
-  for (int c0 = 0; c0 < C; c0 += CH) {
-    const int cn = (C - c0) < CH ? (C - c0) : CH;
-    const int ng = cn * R, ny = nr * cn;
-    const UDiv dcn = make_udiv(cn);
-    for (int gb = 0, yb = 0; gb < ng || yb < ny; gb += kSG * kRowThreads, yb += kSY * kRowThreads) {
-      float vg[kSG], vy[kSY];
-      int og[kSG], oy[kSY];
+  constexpr int kSG = 16, kSY = 8;  // staged values per thread and round
+  bool first = true;
+  for (int p0 = 0; p0 < pre; p0 += PC) {
+    const int pn = (pre - p0) < PC ? (pre - p0) : PC;
+    for (int q0 = 0; q0 < post; q0 += QC) {
+      const int qn = (post - q0) < QC ? (post - q0) : QC;
+      const bool whole = qn == post;  // whole slices: G and Y chunk offsets are linear
+      const int ng = pn * R * qn, ny = pn * nr * qn;
+      float *Gs = dynr, *Ys = dynr + ng;
+      const UDiv dqn = make_udiv(qn), dyq = make_udiv(nr * qn);
+      __syncthreads();  // the previous chunk's reads are done
+      for (int gb = 0, yb = 0; gb < ng || yb < ny; gb += kSG * kRowThreads, yb += kSY * kRowThreads) {
+        float vg[kSG], vy[kSY];
 #pragma unroll
-      for (int u = 0; u < kSG; ++u) {  // core column c0 + cc, row rr: G[p][rr][q] (c = p*post + q)
-        int idx = gb + tid + u * kRowThreads;
-        idx = idx < ng ? idx : ng - 1;
-        const int rr = udiv(idx, dcn), cc = idx - rr * cn;
-        const int c = c0 + cc, pp = udiv(c, dpost), q = c - pp * post;
-        vg[u] = G[((int64_t)pp * R + rr) * post + q];
-        og[u] = cc * GS + rr;
+        for (int u = 0; u < kSG; ++u) {
+          int e = gb + tid + u * kRowThreads;
+          e = e < ng ? e : ng - 1;  // the last value again: same address, same value
+          int64_t gi;
+          if (whole) {
+            gi = (int64_t)p0 * R * post + e;
+          } else {  // pn == 1: e = r * qn + qq
+            const int r = udiv(e, dqn);
+            gi = ((int64_t)p0 * R + r) * post + q0 + (e - r * qn);
+          }
+          vg[u] = G[gi];
+        }
+#pragma unroll
+        for (int u = 0; u < kSY; ++u) {
+          int e = yb + tid + u * kRowThreads;
+          e = e < ny ? e : ny - 1;
+          const int pl = udiv(e, dyq), rem = e - pl * (nr * qn);  // rem = i * qn + qq
+          int64_t yi;
+          if (whole) {
+            yi = ((int64_t)(p0 + pl) * Nn + i0) * post + rem;
+          } else {
+            const int i = udiv(rem, dqn);
+            yi = ((int64_t)p0 * Nn + i0 + i) * post + q0 + (rem - i * qn);
+          }
+          vy[u] = Y[yi];
+        }
+#pragma unroll
+        for (int u = 0; u < kSG; ++u) {
+          const int e = gb + tid + u * kRowThreads;
+          Gs[e < ng ? e : ng - 1] = vg[u];
+        }
+#pragma unroll
+        for (int u = 0; u < kSY; ++u) {
+          const int e = yb + tid + u * kRowThreads;
+          Ys[e < ny ? e : ny - 1] = vy[u];
+        }
       }
-#pragma unroll
-      for (int u = 0; u < kSY; ++u) {  // row i, column c0 + cc: Y[p][i0 + i][q]
-        int idx = yb + tid + u * kRowThreads;
-        idx = idx < ny ? idx : ny - 1;
-        const int ia = udiv(idx, dcn), ib = udiv(idx, dnr);
-        const int i = rows_fast ? idx - ib * nr : ia, cc = rows_fast ? ib : idx - ia * cn;
-        const int c = c0 + cc, pp = udiv(c, dpost), q = c - pp * post;
-        vy[u] = Y[((int64_t)pp * Nn + i0 + i) * post + q];
-        oy[u] = CH * GS + i * YS + cc;
+      if (first) {
+        if (tid < nr * R) As[tid / R][tid % R] = av;
+        if (tid < RR) Ms[tid / R][tid % R] = mv0;
+        if (tid + kRowThreads < RR) Ms[(tid + kRowThreads) / R][(tid + kRowThreads) % R] = mv1;
+        first = false;
       }
-#pragma unroll
-      for (int u = 0; u < kSG; ++u) dynr[og[u]] = vg[u];
-#pragma unroll
-      for (int u = 0; u < kSY; ++u) dynr[oy[u]] = vy[u];
-    }
-    if (c0 == 0) {
-      if (tid < nr * R) As[tid / R][tid % R] = av;
-      if (tid < RR) Ms[tid / R][tid % R] = mv0;
-      if (tid + kRowThreads < RR) Ms[(tid + kRowThreads) / R][(tid + kRowThreads) % R] = mv1;
-    }
-    __syncthreads();
-    if (act) {
-      const float *yrow = Ys + ii * YS;
-      const float *gcol = Gs + r;
-      const int a0 = cn * sp / SPL, a1 = cn * (sp + 1) / SPL;
-      int cc = a0;
-      for (; cc + 8 <= a1; cc += 8) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) acc8[j] = fmaf(yrow[cc + j], gcol[(cc + j) * GS], acc8[j]);
+      __syncthreads();
+      if (act) {
+        if (PATH == kPathQ4) {
+          // quads u = pl * (qn / 4) + q4 over [u0, u1)
+          const int nq4 = qn >> 2, U = pn * nq4;
+          const int u0 = U * sp / SPL, u1 = U * (sp + 1) / SPL;
+          const bool two = rr + 1 < R;
+          int pl = u0 / nq4, q4 = u0 - pl * nq4;
+          for (int u = u0; u < u1; ++u) {
+            const float4 y = *reinterpret_cast<const float4 *>(Ys + (pl * nr + ii) * qn + 4 * q4);
+            const float4 ga = *reinterpret_cast<const float4 *>(Gs + (pl * R + rr) * qn + 4 * q4);
+            const float4 gb2 = *reinterpret_cast<const float4 *>(Gs + (pl * R + (two ? rr + 1 : rr)) * qn + 4 * q4);
+            acc[0] = fmaf(y.x, ga.x, acc[0]);
+            acc[0] = fmaf(y.y, ga.y, acc[0]);
+            acc[0] = fmaf(y.z, ga.z, acc[0]);
+            acc[0] = fmaf(y.w, ga.w, acc[0]);
+            acc[1] = fmaf(y.x, gb2.x, acc[1]);
+            acc[1] = fmaf(y.y, gb2.y, acc[1]);
+            acc[1] = fmaf(y.z, gb2.z, acc[1]);
+            acc[1] = fmaf(y.w, gb2.w, acc[1]);
+            if (++q4 == nq4) {
+              q4 = 0;
+              ++pl;
+            }
+          }
+        } else if (PATH == kPathP) {
+          // qn == 1: Ys[pl * nr + i], Gs[pl * R + r]
+          const int u0 = pn * sp / SPL, u1 = pn * (sp + 1) / SPL;
+          const bool two = ii + 1 < nr;
+          for (int pl = u0; pl < u1; ++pl) {
+            const float y0 = Ys[pl * nr + ii], y1 = Ys[pl * nr + (two ? ii + 1 : ii)];
+            const float4 g = *reinterpret_cast<const float4 *>(Gs + pl * R + rr);
+            acc[0] = fmaf(y0, g.x, acc[0]);
+            acc[1] = fmaf(y0, g.y, acc[1]);
+            acc[2] = fmaf(y0, g.z, acc[2]);
+            acc[3] = fmaf(y0, g.w, acc[3]);
+            acc[4] = fmaf(y1, g.x, acc[4]);
+            acc[5] = fmaf(y1, g.y, acc[5]);
+            acc[6] = fmaf(y1, g.z, acc[6]);
+            acc[7] = fmaf(y1, g.w, acc[7]);
+          }
+        } else {
+          const int Cn = pn * qn;
+          const int u0 = Cn * sp / SPL, u1 = Cn * (sp + 1) / SPL;
+          int pl = udiv(u0, dqn), qq = u0 - pl * qn;
+          for (int u = u0; u < u1; ++u) {
+            acc[0] = fmaf(Ys[(pl * nr + ii) * qn + qq], Gs[(pl * R + rr) * qn + qq], acc[0]);
+            if (++qq == qn) {
+              qq = 0;
+              ++pl;
+            }
+          }
+        }
       }
-      for (int j = 0; cc < a1; ++cc, ++j) acc8[j] = fmaf(yrow[cc], gcol[cc * GS], acc8[j]);
     }
-    __syncthreads();
   }
-  // the pieces of output (i, r): eight partial sums per thread, then the threads in order
-  float accs = 0.f;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) accs += acc8[j];
-  red[tid] = act ? accs : 0.f;
   __syncthreads();
-  const bool own = tid < nr * R;  // thread tid owns output (tid / R, tid % R) from here
+  // partial sums red[sp][i][r], added in split order by the output's owner
+  const int NRR = nr * R;
+  if (act) {
+    if (PATH == kPathQ4) {
+      red[sp * NRR + ii * R + rr] = acc[0];
+      if (rr + 1 < R) red[sp * NRR + ii * R + rr + 1] = acc[1];
+    } else if (PATH == kPathP) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) red[sp * NRR + ii * R + rr + k] = acc[k];
+      if (ii + 1 < nr) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) red[sp * NRR + (ii + 1) * R + rr + k] = acc[4 + k];
+      }
+    } else {
+      red[sp * NRR + ii * R + rr] = acc[0];
+    }
+  }
+  __syncthreads();
+  const bool own = tid < NRR;  // thread tid owns output (tid / R, tid % R) from here
   const int oi = tid / R, orr = tid - (tid / R) * R;
   float nv = 0.f;
   if (own) {
-    float acc = 0.f;
-    for (int k = 0; k < SPL; ++k) acc += red[k * OR + tid];
+    float num = 0.f;
+    for (int k = 0; k < SPL; ++k) num += red[k * NRR + tid];
     float den = 0.f;
     for (int s2 = 0; s2 < R; ++s2) den = fmaf(As[oi][s2], Ms[s2][orr], den);
     if (grad) {
-      nv = den - acc;
+      nv = den - num;
     } else {
       double dd = (double)den;
       if (dd < eps) {
         dd = eps;
         atomicAdd(&nclip, 1u);
       }
-      nv = (float)(((double)As[oi][orr] * (double)acc) / dd);
+      nv = (float)(((double)As[oi][orr] * (double)num) / dd);
     }
   }
   __syncthreads();
@@ -206,47 +266,87 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
     }
   }
   if (gpart) {
-    // last mode: Y is [pre][Nn] (post == 1).  gpart[block][p][r] = sum_i Y[p][i0+i] Anew[i][r];
-    // with a single chunk the Y values are still in Ys (Ys[i][p]), else they are read again.
+    // last mode (post == 1): gpart[block][p][r] = sum_i Y[p][i0 + i] Anew[i][r]
     float *gp = gpart + (int64_t)blockIdx.x * pre * R;
-    if (C <= CH) {
-      // thread (g, rr): column rr of the new rows in registers, columns p = g, g + ng, ...
-      const int ng2 = kRowThreads / R;
-      const int g = tid / R, rr = tid - (tid / R) * R;
+    if (PC >= pre) {
+      // one chunk: the Y rows are still in LDS, Ys[p * nr + i]; thread (g, r4) keeps
+      // columns r4 .. r4 + 3 of the new rows in registers
+      const float *Ys = dynr + pre * R;
+      const int RQ4 = (R + 3) / 4;
+      const int ng2 = kRowThreads / RQ4;
+      const int g = tid / RQ4, r4 = 4 * (tid - (tid / RQ4) * RQ4);
       if (g < ng2) {
-        float ar[kRB];
+        float ar[kRB][4];
 #pragma unroll
-        for (int i = 0; i < kRB; ++i) ar[i] = i < nr ? As[i][rr] : 0.f;
+        for (int i = 0; i < kRB; ++i)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) ar[i][k] = (i < nr && r4 + k < R) ? As[i][r4 + k] : 0.f;
         for (int pp = g; pp < pre; pp += ng2) {
-          float s2 = 0.f;
+          float s4[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int i = 0; i < kRB; ++i)
-            if (i < nr) s2 = fmaf(Ys[i * YS + pp], ar[i], s2);
-          gp[(int64_t)pp * R + rr] = s2;
+          for (int i = 0; i < kRB; ++i) {
+            const float y = i < nr ? Ys[pp * nr + i] : 0.f;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s4[k] = fmaf(y, ar[i][k], s4[k]);
+          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (r4 + k < R) gp[(int64_t)pp * R + r4 + k] = s4[k];
         }
       }
     } else {
-      const int PC = (CH * GS + kRB * YS) / kRB;  // rows of p per chunk that fit
-      for (int p0 = 0; p0 < pre; p0 += PC) {
-        const int pn = (pre - p0) < PC ? (pre - p0) : PC;
+      // several chunks: read the Y rows again, pieces of PC2 rows p
+      const int PC2 = kRowLdsFloats / kRB;
+      for (int p0 = 0; p0 < pre; p0 += PC2) {
+        const int pn = (pre - p0) < PC2 ? (pre - p0) : PC2;
         __syncthreads();
-        staged_copy(
-            pn * nr,
-            [&](int idx) {
-              const int pp = idx / nr, i = idx - (idx / nr) * nr;
-              return Y[(int64_t)(p0 + pp) * Nn + i0 + i];
-            },
-            [&](int idx, float v) { dynr[idx] = v; });
+        for (int idx = tid; idx < pn * nr; idx += kRowThreads) {
+          const int pp = idx / nr, i = idx - (idx / nr) * nr;
+          dynr[idx] = Y[(int64_t)(p0 + pp) * Nn + i0 + i];
+        }
         __syncthreads();
         for (int idx = tid; idx < pn * R; idx += kRowThreads) {
-          const int pp = idx / R, rr = idx - (idx / R) * R;
+          const int pp = idx / R, r = idx - (idx / R) * R;
           float s2 = 0.f;
-          for (int i = 0; i < nr; ++i) s2 = fmaf(dynr[pp * nr + i], As[i][rr], s2);
-          gp[(int64_t)(p0 + pp) * R + rr] = s2;
+          for (int i = 0; i < nr; ++i) s2 = fmaf(dynr[pp * nr + i], As[i][r], s2);
+          gp[(int64_t)(p0 + pp) * R + r] = s2;
         }
       }
     }
   }
+}
+
+nnc_status launch_mu_rows(const float *Y, const float *G, float *A, const float *M, int64_t pre,
+                          int64_t Nn, int64_t post, int64_t R, double eps, unsigned long long *clips,
+                          float *gram, float *gpart, float *grad, hipStream_t s) {
+  if (R > 32) return fail(NNC_EUNSUPPORTED, "mu_rows: R %lld above 32", (long long)R);
+  if (pre * post > (int64_t)1 << 30 || Nn > (int64_t)1 << 30)
+    return fail(NNC_EUNSUPPORTED, "mu_rows: sizes above 2^30");
+  if (gpart && post != 1) return fail(NNC_EINVAL, "mu_rows: core-numerator partials need post == 1");
+  // chunks: whole slices p when one fits, else quad-aligned q ranges of one slice
+  int64_t PC, QC;
+  const int64_t slice = (R + kRB) * post;
+  if (slice <= kRowLdsFloats) {
+    PC = kRowLdsFloats / slice;
+    if (PC > pre) PC = pre;
+    QC = post;
+  } else {
+    PC = 1;
+    QC = kRowLdsFloats / (R + kRB) / 4 * 4;
+  }
+  const size_t lds = (size_t)(PC * (R + kRB) * QC) * sizeof(float);
+  const int path = (post % 4 == 0) ? kPathQ4 : ((post == 1 && R % 4 == 0) ? kPathP : kPathS);
+  const int64_t blocks = (Nn + kRB - 1) / kRB;
+#define NNC_MU(PV)                                                                                \
+  hipLaunchKernelGGL(mu_rows_k<PV>, dim3((unsigned)blocks), dim3(kRowThreads), lds, s, Y, G, A, M, \
+                     (int)pre, (int)Nn, (int)post, (int)R, (int)PC, (int)QC, eps, clips, gram,    \
+                     gpart, grad)
+  if (path == kPathQ4) NNC_MU(kPathQ4);
+  else if (path == kPathP) NNC_MU(kPathP);
+  else NNC_MU(kPathS);
+#undef NNC_MU
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
 }
 
 // Gram partials of a factor from its rows: gram[b][x][y] = sum_{i in [8b, 8b+8)} A[i][x] A[i][y],
@@ -266,23 +366,6 @@ __global__ __launch_bounds__(256) void gram_parts_k(const float *__restrict__ A,
 nnc_status launch_gram_parts(const float *A, int64_t Nn, int64_t R, float *gram, hipStream_t s) {
   hipLaunchKernelGGL(gram_parts_k, dim3((unsigned)((Nn + kRB - 1) / kRB)), dim3(256), 0, s, A, (int)Nn,
                      (int)R, gram);
-  NNC_HIP(hipGetLastError());
-  return NNC_OK;
-}
-
-nnc_status launch_mu_rows(const float *Y, const float *G, float *A, const float *M, int64_t pre,
-                          int64_t Nn, int64_t post, int64_t R, double eps, unsigned long long *clips,
-                          float *gram, float *gpart, float *grad, hipStream_t s) {
-  if (R > 32) return fail(NNC_EUNSUPPORTED, "mu_rows: R %lld above 32", (long long)R);
-  if (pre * post > (int64_t)1 << 30 || Nn > (int64_t)1 << 30)
-    return fail(NNC_EUNSUPPORTED, "mu_rows: sizes above 2^30");
-  const int64_t C = pre * post;
-  int64_t CH = (kRowLdsFloats - kRB) / (R + 1 + kRB);
-  if (CH > C) CH = C;
-  const size_t lds = (size_t)(CH * (R + 1) + kRB * (CH + 1)) * sizeof(float);
-  const int64_t blocks = (Nn + kRB - 1) / kRB;
-  hipLaunchKernelGGL(mu_rows_k, dim3((unsigned)blocks), dim3(kRowThreads), lds, s, Y, G, A, M, (int)pre,
-                     (int)Nn, (int)post, (int)R, (int)CH, eps, clips, gram, gpart, grad);
   NNC_HIP(hipGetLastError());
   return NNC_OK;
 }
