@@ -104,46 +104,53 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
       float *Gs = dynr, *Ys = dynr + ng;
       const UDiv dqn = make_udiv(qn), dyq = make_udiv(nr * qn);
       __syncthreads();  // the previous chunk's reads are done
-      for (int gb = 0, yb = 0; gb < ng || yb < ny; gb += kSG * kRowThreads, yb += kSY * kRowThreads) {
-        float vg[kSG], vy[kSY];
+      // source index of staged element e (whole slices: linear in e; else one slice's
+      // q range, e = r * qn + qq for G and i * qn + qq for Y)
+      auto g_index = [&](int e) -> int64_t {
+        if (whole) return (int64_t)p0 * R * post + e;
+        const int r = udiv(e, dqn);
+        return ((int64_t)p0 * R + r) * post + q0 + (e - r * qn);
+      };
+      auto y_index = [&](int e) -> int64_t {
+        const int pl = udiv(e, dyq), rem = e - pl * (nr * qn);
+        if (whole) return ((int64_t)(p0 + pl) * Nn + i0) * post + rem;
+        const int i = udiv(rem, dqn);
+        return ((int64_t)p0 * Nn + i0 + i) * post + q0 + (rem - i * qn);
+      };
+      auto stage = [&](auto gidx, auto yidx) {
+        for (int gb = 0, yb = 0; gb < ng || yb < ny; gb += kSG * kRowThreads, yb += kSY * kRowThreads) {
+          float vg[kSG], vy[kSY];
 #pragma unroll
-        for (int u = 0; u < kSG; ++u) {
-          int e = gb + tid + u * kRowThreads;
-          e = e < ng ? e : ng - 1;  // the last value again: same address, same value
-          int64_t gi;
-          if (whole) {
-            gi = (int64_t)p0 * R * post + e;
-          } else {  // pn == 1: e = r * qn + qq
-            const int r = udiv(e, dqn);
-            gi = ((int64_t)p0 * R + r) * post + q0 + (e - r * qn);
+          for (int u = 0; u < kSG; ++u) {
+            const int e = gb + tid + u * kRowThreads;
+            vg[u] = G[gidx(e < ng ? e : ng - 1)];  // past the end: the last value again
           }
-          vg[u] = G[gi];
-        }
 #pragma unroll
-        for (int u = 0; u < kSY; ++u) {
-          int e = yb + tid + u * kRowThreads;
-          e = e < ny ? e : ny - 1;
-          const int pl = udiv(e, dyq), rem = e - pl * (nr * qn);  // rem = i * qn + qq
-          int64_t yi;
-          if (whole) {
-            yi = ((int64_t)(p0 + pl) * Nn + i0) * post + rem;
-          } else {
-            const int i = udiv(rem, dqn);
-            yi = ((int64_t)p0 * Nn + i0 + i) * post + q0 + (rem - i * qn);
+          for (int u = 0; u < kSY; ++u) {
+            const int e = yb + tid + u * kRowThreads;
+            vy[u] = Y[yidx(e < ny ? e : ny - 1)];
           }
-          vy[u] = Y[yi];
-        }
 #pragma unroll
-        for (int u = 0; u < kSG; ++u) {
-          const int e = gb + tid + u * kRowThreads;
-          Gs[e < ng ? e : ng - 1] = vg[u];
-        }
+          for (int u = 0; u < kSG; ++u) {
+            const int e = gb + tid + u * kRowThreads;
+            Gs[e < ng ? e : ng - 1] = vg[u];
+          }
 #pragma unroll
-        for (int u = 0; u < kSY; ++u) {
-          const int e = yb + tid + u * kRowThreads;
-          Ys[e < ny ? e : ny - 1] = vy[u];
+          for (int u = 0; u < kSY; ++u) {
+            const int e = yb + tid + u * kRowThreads;
+            Ys[e < ny ? e : ny - 1] = vy[u];
+          }
         }
-      }
+      };
+      // the uniform choice made once, outside the loads
+      if (whole)
+        stage([&](int e) -> int64_t { return (int64_t)p0 * R * post + e; },
+              [&](int e) -> int64_t {
+                const int pl = udiv(e, dyq);
+                return ((int64_t)(p0 + pl) * Nn + i0) * post + (e - pl * (nr * qn));
+              });
+      else
+        stage(g_index, y_index);
       if (first) {
         if (tid < nr * R) As[tid / R][tid % R] = av;
         if (tid < RR) Ms[tid / R][tid % R] = mv0;
