@@ -1,9 +1,11 @@
 // The X-streaming contractions of a sweep (the two passes over X), software-pipelined:
 // every wave keeps the loads of its next work unit in flight while the MFMAs consume the
-// current one, so each CU holds tens of KiB of X requests at any time.
+// current one.
 //
-//   ttm_last_pipe_k / ttm_last_lds_k : out[m][r] = sum_k X[m][k] F(k, r)  (contraction index contiguous)
-//   ttm_mid_lds_k   : out[p][r][q] = sum_n F(n, r) X[p][n][q]  (contraction index strided, bf16)
+//   ttm_last_lds_k     : out[m][r] = sum_k X[m][k] F(k, r)   (contraction index contiguous)
+//   ttm_last_pipe_k    : the same, for rows too short for ttm_last_lds_k's pieces
+//   ttm_mid_lds_k      : out[p][r][q] = sum_n F(n, r) X[p][n][q]  (contraction index strided, bf16)
+//   ttm_mid_lds_f32_k  : the same for FP32 X
 // X is FP32 (v_mfma_f32_16x16x4_f32) or bfloat16 (v_mfma_f32_16x16x32_bf16, FP32
 // accumulation, factor applied as bf16 hi + lo parts).  The factor (R <= 32 columns,
 // zero-padded to 16-column tiles) lives in LDS.
