@@ -85,7 +85,9 @@ def summarize(args):
     """Write the profiles/ summaries from three rocprofv3 CSV output folders (kernel trace
     with --stats; --pmc FETCH_SIZE; --pmc WRITE_SIZE).  Needs no GPU."""
     import csv
-    prof_dir, fetch_dir, write_dir = args.summarize
+    if len(args.summarize) not in (3, 5):
+        raise SystemExit("--summarize takes PROF FETCH WRITE [MFMA_UTIL MFMA_FLOPS]")
+    prof_dir, fetch_dir, write_dir = args.summarize[:3]
     lines = ["# Kernel time of one 512^3 bench step, both forms (rocprofv3 --kernel-trace --stats)", "",
              "Command (repo root):", "",
              "    rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof -o run -- "
@@ -134,7 +136,7 @@ def summarize(args):
            "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
     alg = {}
     for key, esz in (("ttm_last_lds_k<true", 2), ("ttm_mid_lds_k", 2),
-                     ("ttm_last_lds_k<false", 4), ("ttm_mid_f32_k", 4)):
+                     ("ttm_last_lds_k<false", 4), ("ttm_mid_lds_f32_k", 4)):
         fk, wk = pick(fetch, key), pick(write, key)
         if fk is None or wk is None:
             continue
@@ -164,7 +166,58 @@ def summarize(args):
            "Source hash of the pass kernels when measured: %s" % res["source_sha"]]
     with open(os.path.join(ROOT, "profiles", "pass_traffic_512cubed.md"), "w") as f:
         f.write("\n".join(md) + "\n")
+    if len(args.summarize) == 5:
+        res["mfma"] = summarize_mfma(args.summarize[3], args.summarize[4], rows, counter, pick)
+        with open(COUNTERS, "w") as f:
+            json.dump(res, f, indent=1)
     print(json.dumps(res, indent=1))
+
+
+PASS_KEYS = (("ttm_last_lds_k<true", "bf16"), ("ttm_mid_lds_k", "bf16"),
+             ("ttm_last_lds_k<false", "f32"), ("ttm_mid_lds_f32_k", "f32"))
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}
+
+
+def summarize_mfma(util_dir, flops_dir, stats_rows, counter, pick):
+    """MFMA busy fraction (rocprofv3 derived metric MfmaUtil) and MFMA FLOP per dispatch
+    (MfmaFlopsBF16 / MfmaFlopsF32) of the pass kernels; achieved MFMA TFLOP/s uses the
+    average kernel durations of the kernel-trace run."""
+    util = counter(util_dir, "MfmaUtil")
+    fb, ff = counter(flops_dir, "MfmaFlopsBF16"), counter(flops_dir, "MfmaFlopsF32")
+    alg = 2.0 * 512 ** 3 * 20
+    out = {}
+    md = ["# MFMA use of the X-streaming pass kernels, 512^3, R = 20 (rocprofv3 --pmc)", "",
+          "Commands (repo root), one counter set per run:", "",
+          "    rocprofv3 --pmc MfmaUtil --output-format csv -d gpurun_out/pmc_mfma_util -o run -- "
+          "python -u bench.py --kernel-only",
+          "    rocprofv3 --pmc MfmaFlopsBF16 MfmaFlopsF32 --output-format csv -d gpurun_out/pmc_mfma_flops "
+          "-o run -- python -u bench.py --kernel-only",
+          "    python bench.py --summarize gpurun_out/prof gpurun_out/pmc_fetch gpurun_out/pmc_write "
+          "gpurun_out/pmc_mfma_util gpurun_out/pmc_mfma_flops", "",
+          "MfmaUtil is rocprofv3's derived metric: summed SQ_VALU_MFMA_BUSY_CYCLES over "
+          "(max GRBM_GUI_ACTIVE x SIMD count), in percent.  MFMA FLOP counts what the matrix cores "
+          "executed: the rank is padded to 32 (two 16-wide tiles) and the BF16 kernels multiply each X "
+          "tile by the high and the low BF16 half of the FP32 factor (two MFMAs per tile), so they "
+          "execute 2 x 32/20 and the FP32 kernels 32/20 times the algorithmic 2 x 512^3 x 20.  Achieved MFMA TFLOP/s divides the counted FLOP by the kernel's average "
+          "duration in the kernel-trace run.", "",
+          "| kernel | MfmaUtil % | MFMA GFLOP | algorithmic GFLOP | avg us | MFMA TFLOP/s | peak (dtype) | frac |",
+          "|---|---|---|---|---|---|---|---|"]
+    for key, dt in PASS_KEYS:
+        u = pick(util, key)
+        fl = pick(fb if dt == "bf16" else ff, key)
+        hit = [r for r in stats_rows if key in r["Name"]]
+        if u is None or fl is None or not hit:
+            continue
+        avg_us = float(hit[0]["AverageNs"]) / 1e3
+        tf = fl / (avg_us * 1e-6) / 1e12
+        out[key] = {"mfma_util_pct": u, "mfma_flop": fl, "alg_flop": alg, "avg_us": avg_us,
+                    "mfma_tflops": tf, "peak_tflops": MFMA_PEAK_TFLOPS[dt]}
+        md.append("| %s | %.2f | %.2f | %.2f | %.2f | %.2f | %.0f (%s) | %.4f |" % (
+            key, u, fl / 1e9, alg / 1e9, avg_us, tf, MFMA_PEAK_TFLOPS[dt], dt, tf / MFMA_PEAK_TFLOPS[dt]))
+    md += ["", "Source hash of the pass kernels when measured: %s" % sources_sha()]
+    with open(os.path.join(ROOT, "profiles", "pass_mfma_512cubed.md"), "w") as f:
+        f.write("\n".join(md) + "\n")
+    return out
 
 
 def main():
@@ -182,8 +235,9 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--kernel-only", action="store_true",
                     help="only launch the pass kernels and a calibration copy (counter runs)")
-    ap.add_argument("--summarize", nargs=3, metavar=("PROF_DIR", "FETCH_DIR", "WRITE_DIR"),
-                    help="write profiles/ summaries from rocprofv3 CSV outputs (no GPU needed)")
+    ap.add_argument("--summarize", nargs="+", metavar="DIR",
+                    help="PROF FETCH WRITE [MFMA_UTIL MFMA_FLOPS]: write profiles/ summaries from "
+                         "rocprofv3 CSV output folders (no GPU needed)")
     args = ap.parse_args()
     if args.summarize:
         summarize(args)
