@@ -88,22 +88,23 @@ struct GramStage {
     nch = ngrp >= kSliceThreads ? 1 : kSliceThreads / ngrp;
     ch = nch > 1 ? tid / ngrp : 0;
     const int P = a.gram_parts;
-    b0 = (ch < nch) ? (int)((int64_t)P * ch / nch) : 0;
-    b1 = (ch < nch) ? (int)((int64_t)P * (ch + 1) / nch) : 0;
-    if (nch > 1) {  // one group per thread: its first kPB partials now
+    if (P < (1 << 21)) {  // P * nch < 2^31: the same bounds in 32-bit arithmetic
+      b0 = (ch < nch) ? P * ch / nch : 0;
+      b1 = (ch < nch) ? P * (ch + 1) / nch : 0;
+    } else {
+      b0 = (ch < nch) ? (int)((int64_t)P * ch / nch) : 0;
+      b1 = (ch < nch) ? (int)((int64_t)P * (ch + 1) / nch) : 0;
+    }
+    // one group per thread: its first kPB partials now.  Only the float4 form is issued here
+    // (single entries are read in finish()): with two load forms on two paths, the registers
+    // of one path's loads are live-out of the other, and the wait that protects them stalls
+    // every load above as well.
+    if (nch > 1 && vec) {
       const int grp = tid % ngrp;
-      if (vec) {
 #pragma unroll
-        for (int u = 0; u < kPB; ++u) {
-          const int b = b0 + u < b1 ? b0 + u : (b1 > 0 ? b1 - 1 : 0);
-          pv[u] = *reinterpret_cast<const float4 *>(a.gram_part + (int64_t)b * RR + grp * 4);
-        }
-      } else {
-#pragma unroll
-        for (int u = 0; u < kPB; ++u) {
-          const int b = b0 + u < b1 ? b0 + u : (b1 > 0 ? b1 - 1 : 0);
-          pv[u].x = a.gram_part[(int64_t)b * RR + grp];
-        }
+      for (int u = 0; u < kPB; ++u) {
+        const int b = b0 + u < b1 ? b0 + u : (b1 > 0 ? b1 - 1 : 0);
+        pv[u] = *reinterpret_cast<const float4 *>(a.gram_part + (int64_t)b * RR + grp * 4);
       }
     }
   }
@@ -115,19 +116,27 @@ struct GramStage {
     for (int u = 0; u < SU; ++u) {
       const int e = tid + u * kSliceThreads;
       if (e >= ns) continue;
-      int k = 0;
+      // the mode of entry e and its offset and size, by unrolled selects: an index that
+      // differs between lanes would read the kernel arguments through vector memory
+      int k = 0, base = 0, Rm = a.R[0];
 #pragma unroll
       for (int j = 1; j < kMaxDim; ++j)
-        if (j < a.d && e >= a.soff[j]) k = j;
+        if (j < a.d && e >= a.soff[j]) {
+          k = j;
+          base = a.soff[j];
+          Rm = a.R[j];
+        }
       if (k == a.gram) continue;  // formed below from the partials
-      const int loc = e - a.soff[k], Rm = a.R[k];
+      const int loc = e - base;
       const int l = loc / Rm, r = loc - (loc / Rm) * Rm;
       Sl[k * RM * RM + l * RM + r] = sv[u];
     }
     // zero padding of every mode (entries l >= R_k or r >= R_k; none of them is written above)
-    for (int k = 0; k < a.d; ++k)
-      for (int e = tid; e < RM * RM; e += kSliceThreads)
-        if (e / RM >= a.R[k] || e % RM >= a.R[k]) Sl[k * RM * RM + e] = 0.f;
+#pragma unroll
+    for (int k = 0; k < kMaxDim; ++k)
+      if (k < a.d)
+        for (int e = tid; e < RM * RM; e += kSliceThreads)
+          if (e / RM >= a.R[k] || e % RM >= a.R[k]) Sl[k * RM * RM + e] = 0.f;
     if (a.gram < 0) return;
     const int k = a.gram;
     float *Sg = Sl + k * RM * RM;
@@ -150,12 +159,21 @@ struct GramStage {
       }
     };
     if (nch > 1) {
-      float4 s4 = make_float4(0.f, 0.f, 0.f, 0.f);
+      // The sum starts from an opaque zero: a constant start lets the compiler compute the
+      // first addition right after its load is issued, which then waits for every load
+      // issued before it.
+      float z;
+      asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+      float4 s4 = make_float4(z, z, z, z);
       if (ch < nch) {
+        int bb = b0;
+        if (vec) {
 #pragma unroll
-        for (int u = 0; u < kPB; ++u)
-          if (b0 + u < b1) add(s4, vec ? pv[u] : make_float4(pv[u].x, 0.f, 0.f, 0.f));
-        for (int bb = b0 + kPB; bb < b1; ++bb) add(s4, load(bb, tid % ngrp));
+          for (int u = 0; u < kPB; ++u)
+            if (b0 + u < b1) add(s4, pv[u]);
+          bb = b0 + kPB;
+        }
+        for (; bb < b1; ++bb) add(s4, load(bb, tid % ngrp));
         reinterpret_cast<float4 *>(red)[tid] = s4;
       }
       __syncthreads();
@@ -457,14 +475,9 @@ static __device__ void small_body(const SmallArgs &a, int64_t tile) {
 #pragma unroll
   for (int r = 0; r < RM; ++r) acc[r] = 0.f;
   for (int64_t nb = 0; active && nb < N; nb += span) {
-    float x[kSmallRows];
-#pragma unroll
-    for (int u = 0; u < kSmallRows; ++u) {
-      int64_t n = nb + w * kSmallRows + u;
-      n = n < N ? n : N - 1;  // rows past N meet zero factor rows
-      x[u] = src[n * Q];
-    }
-    // factor rows [nb, nb + span): RM * 32 values per wave, the wave's own rows
+    // factor rows [nb, nb + span): RM * 32 values per wave, the wave's own rows.  They are
+    // loaded before the rows of `in`, so that staging them waits for them alone and the
+    // products of row u wait only for the first u + 1 rows of `in`.
     constexpr int kStage = RM / 2;  // 32 * RM values over 64 lanes
     float v[kStage];
 #pragma unroll
@@ -475,6 +488,15 @@ static __device__ void small_body(const SmallArgs &a, int64_t tile) {
       const bool ok = n < N && r < R;
       v[u] = F[(ok ? n : 0) * ldl + (ok ? r : 0) * ldr];
     }
+    __builtin_amdgcn_sched_barrier(0);
+    float x[kSmallRows];
+#pragma unroll
+    for (int u = 0; u < kSmallRows; ++u) {
+      int64_t n = nb + w * kSmallRows + u;
+      n = n < N ? n : N - 1;  // rows past N meet zero factor rows
+      x[u] = src[n * Q];
+    }
+    __builtin_amdgcn_sched_barrier(0);
     float *Fw = sm + w * kSmallRows * RM;
 #pragma unroll
     for (int u = 0; u < kStage; ++u) {  // zeros masked in here, where the values are awaited
