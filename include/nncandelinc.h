@@ -161,6 +161,42 @@ nnc_status nncp_fit_batched(const float *core, int ndim, const int64_t *core_dim
                             size_t workspace_bytes, void *stream);
 
 /*
+ * Nonnegative CP of the data tensor itself (the nnCPD step of Algorithm 2, which runs it on
+ * X and then factors each CP factor by NMF), exactly `iters` sweeps of the multiplicative
+ * update B_n <- B_n * M_n / max(B_n H_n, eps) (the nnCP rule above, applied to X, factors
+ * in order 0..d-1 within a sweep).  Two X-streaming contractions per sweep, run by the
+ * same kernels and with the same arithmetic as nntucker_fit (xdt = NNC_F32: FP32 MFMA;
+ * NNC_BF16: bf16 MFMA with FP32 accumulation): Z = X x_d B_d^T serves modes 1..d-1 and
+ * T = X x_1 B_1^T (after B_1's update) serves mode d; the MTTKRPs are rank-wise
+ * contractions of Z or T with the other factors.  rank <= 32.
+ *   factors  host array of ndim device pointers; factor n is dims[n] x rank;
+ *            in: initial B_n >= 0; out: fitted B_n.
+ *   opt      nullable (defaults); workspace (nncpx_workspace_bytes()) is required.
+ *            fp32_final_sweeps / x_fp32 / objective_every / use_graph as for nntucker_fit.
+ *   rep      nullable; non-NULL syncs and reports ||X - cp(B)||_F / ||X||_F.
+ */
+size_t nncpx_workspace_bytes(int ndim, const int64_t *dims, int rank);
+nnc_status nncpx_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *dims, int rank, int iters,
+                     float *const *factors, const nnc_options *opt, nnc_report *rep, void *stream);
+
+/*
+ * Nonnegative matrix factorization A ~ W H (the NMF step of Algorithm 2, applied to each CP
+ * factor A^(i) with m_i latent columns: A^(i) ~ F^(i) B^(i)), exactly `iters` Lee-Seung
+ * multiplicative sweeps, W first, then H:
+ *   W <- W * (A H^T) / max(W H H^T, eps),   H <- H * (W^T A) / max(W^T W H, eps),
+ * which is the two-way case of the nnCP rule (factors W and H^T), computed by the nnCP
+ * kernel in one workgroup.
+ *   A  rows x cols (float, entries >= 0).   W  rows x rank, in: initial; out: fitted.
+ *   H  rank x cols, in: initial; out: fitted.   rank <= 32.
+ *   rel_residual  host, nullable: ||A - W H||_F / ||A||_F; non-NULL syncs.
+ *   workspace     at least nmf_workspace_bytes().
+ */
+size_t nmf_workspace_bytes(int64_t rows, int64_t cols, int rank);
+nnc_status nmf_fit(const float *A, int64_t rows, int64_t cols, int rank, int iters, float *W, float *H,
+                   double eps, double *rel_residual, void *workspace, size_t workspace_bytes,
+                   void *stream);
+
+/*
  * Lift: C_n = A_n B_n for every mode (substituting the core's CP into the Tucker model,
  * Section 2.1 lemma proof and Section 2.2).  tucker_factors[n]: dims[n] x multirank[n];
  * cp_factors[n]: multirank[n] x rank; out_factors[n]: dims[n] x rank.  Host arrays of

@@ -269,3 +269,28 @@ def nncandelinc(X, G0, A0, B0, tucker_iters: int, cp_iters: int, eps: float = 1e
     C = lift(A, B)
     return dict(G=G, A=A, B=B, C=C, clips=c1 + c2,
                 tucker_rel=tucker_rel_residual(X, G, A), cp_rel=cp_rel_residual(X, C))
+
+
+def nmf(A, W0, H0, iters: int, eps: float = 1e-12):
+    """NMF A ~ W H by Lee-Seung multiplicative updates (the NMF step of Algorithm 2): each
+    sweep W <- W * (A H^T) / max(W H H^T, eps), then H <- H * (W^T A) / max(W^T W H, eps).
+    These are the two-way nnCP updates with factors W and H^T, so the nnCP routine computes
+    them.  Returns (W, H, clips)."""
+    (W, Ht), clips, _ = nncp(A, [W0, _f64(H0).T.copy()], iters, eps)
+    return W, Ht.T.copy(), clips
+
+
+def nncandelinc_alg2(X, B0, F0, H0, cp_iters: int, nmf_iters: int, eps: float = 1e-12):
+    """Algorithm 2 end to end: nnCP of X with initial factors B0 (dims[n] x r), then an NMF
+    of each fitted factor A^(n) ~ F^(n) B^(n) from initial F0[n] (dims[n] x m_n) and
+    H0[n] (m_n x r), the lift C_n = F^(n) B^(n) and the relative error of that model."""
+    Acp, c1, _ = nncp(X, B0, cp_iters, eps)
+    F, B, c2 = [], [], 0
+    for n in range(len(Acp)):
+        f, b, c = nmf(Acp[n], F0[n], H0[n], nmf_iters, eps)
+        F.append(f)
+        B.append(b)
+        c2 += c
+    C = lift(F, B)
+    return dict(Acp=Acp, F=F, B=B, C=C, clips=c1 + c2, cp_x_rel=cp_rel_residual(X, Acp),
+                cp_rel=cp_rel_residual(X, C))

@@ -57,7 +57,7 @@ EXPORTED = ["nnc_last_error", "nnc_device_ok", "nnc_set_timing", "nnc_ttm", "nnc
             "nntucker_workspace_bytes", "nntucker_fit", "nncp_workspace_bytes", "nncp_fit",
             "nncp_batched_workspace_bytes", "nncp_fit_batched", "nncandelinc_lift",
             "reconstruct_workspace_bytes", "reconstruct_residual", "reconstruct_sq_sums",
-            "nntucker_grad"]
+            "nntucker_grad", "nncpx_workspace_bytes", "nncpx_fit", "nmf_workspace_bytes", "nmf_fit"]
 
 _lib = None
 
@@ -88,6 +88,14 @@ def lib():
         L.nncp_fit_batched.argtypes = [_vp, ctypes.c_int, _i64p, ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_int), ctypes.c_int, _vpp,
                                        ctypes.c_double, _dp, ctypes.c_int, _vp, ctypes.c_size_t, _vp]
+        L.nncpx_workspace_bytes.argtypes = [ctypes.c_int, _i64p, ctypes.c_int]
+        L.nncpx_workspace_bytes.restype = ctypes.c_size_t
+        L.nncpx_fit.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _i64p, ctypes.c_int, ctypes.c_int, _vpp,
+                                _vp, _vp, _vp]
+        L.nmf_workspace_bytes.argtypes = [_i64, _i64, ctypes.c_int]
+        L.nmf_workspace_bytes.restype = ctypes.c_size_t
+        L.nmf_fit.argtypes = [_vp, _i64, _i64, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_double, _vp,
+                              _vp, ctypes.c_size_t, _vp]
         L.nncandelinc_lift.argtypes = [ctypes.c_int, _i64p, _i64p, ctypes.c_int, _vpp, _vpp, _vpp, _vp]
         L.reconstruct_workspace_bytes.argtypes = [ctypes.c_int, _i64p, _i64p, ctypes.c_int]
         L.reconstruct_workspace_bytes.restype = ctypes.c_size_t
@@ -248,6 +256,79 @@ def nncp_fit(core: torch.Tensor, rank: int, iters: int, cp_factors: Sequence[tor
                           _ptrs(cp_factors), float(eps), ctypes.byref(res) if residual else None,
                           ws.data_ptr(), ws.numel(), _stream()))
     return res.value if residual else None
+
+
+def nncpx_workspace_bytes(dims: Sequence[int], rank: int) -> int:
+    return int(lib().nncpx_workspace_bytes(len(dims), _dims(dims), int(rank)))
+
+
+def nncpx_fit(X: torch.Tensor, rank: int, iters: int, factors: Sequence[torch.Tensor], *,
+              x_fp32: Optional[torch.Tensor] = None, fp32_final_sweeps: int = 0, eps: float = 1e-12,
+              objective_every: int = 0, use_graph: bool = True, report: bool = True,
+              workspace: Optional[torch.Tensor] = None) -> Optional[FitReport]:
+    """nnCP of the data tensor X (the nnCPD step of Algorithm 2), `iters` multiplicative
+    sweeps, in place on the factors (dims[n] x rank)."""
+    _dev(X, "X", (torch.float32, torch.bfloat16))
+    for k, f in enumerate(factors):
+        _dev(f, "factors[%d]" % k)
+    d = X.dim()
+    need = nncpx_workspace_bytes(X.shape, rank)
+    if workspace is None:
+        workspace = _workspace(need, X.device)
+    opt = Options()
+    opt.fp32_final_sweeps = int(fp32_final_sweeps)
+    opt.x_fp32 = _dev(x_fp32, "x_fp32").data_ptr() if x_fp32 is not None else None
+    opt.eps = float(eps)
+    opt.objective_every = int(objective_every)
+    opt.use_graph = 1 if use_graph else 0
+    opt.workspace = workspace.data_ptr()
+    opt.workspace_bytes = workspace.numel()
+    rep = Report()
+    hist = None
+    if objective_every > 0:
+        hist = (ctypes.c_double * max(1, iters // objective_every + 1))()
+        rep.objective_history = ctypes.cast(hist, _dp)
+    st = lib().nncpx_fit(X.data_ptr(), _xdt(X), d, _dims(X.shape), int(rank), int(iters), _ptrs(factors),
+                         ctypes.byref(opt), ctypes.byref(rep) if (report or objective_every) else None,
+                         _stream())
+    _check(st)
+    if not (report or objective_every):
+        return None
+    return FitReport(rep.sweeps_done, rep.rel_residual, rep.eps_clips, rep.seconds,
+                     [hist[i] for i in range(rep.history_len)] if hist is not None else [],
+                     rep.ttm_pass_ms, rep.ttm_pass_launches)
+
+
+def nmf_fit(A: torch.Tensor, rank: int, iters: int, W: torch.Tensor, H: torch.Tensor, *,
+            eps: float = 1e-12, residual: bool = True) -> Optional[float]:
+    """NMF A ~ W H (the NMF step of Algorithm 2) by multiplicative updates, in place on W
+    (rows x rank) and H (rank x cols); returns ||A - W H|| / ||A|| when `residual`."""
+    _dev(A, "A")
+    _dev(W, "W")
+    _dev(H, "H")
+    if A.dim() != 2:
+        raise NncError(NNC_EINVAL, "A must be a matrix")
+    rows, cols = A.shape
+    ws = _workspace(lib().nmf_workspace_bytes(rows, cols, int(rank)), A.device)
+    res = ctypes.c_double(0.0)
+    _check(lib().nmf_fit(A.data_ptr(), rows, cols, int(rank), int(iters), W.data_ptr(), H.data_ptr(),
+                         float(eps), ctypes.byref(res) if residual else None, ws.data_ptr(), ws.numel(),
+                         _stream()))
+    return res.value if residual else None
+
+
+def nncandelinc_alg2(X: torch.Tensor, rank: int, multirank: Sequence[int], cp_iters: int, nmf_iters: int,
+                     cp_factors: Sequence[torch.Tensor], F: Sequence[torch.Tensor], B: Sequence[torch.Tensor],
+                     *, x_fp32: Optional[torch.Tensor] = None, fp32_final_sweeps: int = 0,
+                     eps: float = 1e-12) -> FitReport:
+    """Algorithm 2: nnCP of X (cp_factors, dims[n] x rank, in place), then NMF of each CP
+    factor into F[n] (dims[n] x multirank[n]) and B[n] (multirank[n] x rank), in place.  The
+    nnCANDELINC model is C_n = F[n] B[n] (nncandelinc_lift).  Returns the nnCP report."""
+    rep = nncpx_fit(X, rank, cp_iters, cp_factors, x_fp32=x_fp32, fp32_final_sweeps=fp32_final_sweeps,
+                    eps=eps)
+    for n in range(X.dim()):
+        nmf_fit(cp_factors[n], int(multirank[n]), nmf_iters, F[n], B[n], eps=eps, residual=False)
+    return rep
 
 
 def nncp_fit_batched(core: torch.Tensor, ranks: Sequence[int], iters: int,

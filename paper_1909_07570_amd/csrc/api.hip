@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -561,6 +562,177 @@ static hipStream_t capture_stream() {
   return st;
 }
 
+// Run `n` sweeps, each enqueued by `sweep(stream)`, captured kSweepsPerGraph at a time into
+// HIP graphs when `graphs` is set (a library stream stands in for the default stream, which
+// cannot be captured).  Returns after the sweeps are enqueued on `s` (synchronised once).
+static nnc_status run_sweeps(hipStream_t s, bool graphs, int n,
+                             const std::function<nnc_status(hipStream_t)> &sweep) {
+  if (n <= 0) return NNC_OK;
+  if (!graphs) {
+    for (int t = 0; t < n; ++t) NNC_TRY(sweep(s));
+    return NNC_OK;
+  }
+  hipStream_t cs = s;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  if (!s) {
+    cs = capture_stream();
+    if (!cs) return fail(NNC_EHIP, "could not create a capture stream");
+    NNC_HIP(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
+    NNC_HIP(hipEventCreateWithFlags(&ev_out, hipEventDisableTiming));
+    NNC_HIP(hipEventRecord(ev_in, s));
+    NNC_HIP(hipStreamWaitEvent(cs, ev_in, 0));
+  }
+  auto capture = [&](hipGraphExec_t *ge, int count) -> nnc_status {
+    hipGraph_t g = nullptr;
+    NNC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    nnc_status st = NNC_OK;
+    for (int c = 0; c < count && st == NNC_OK; ++c) st = sweep(cs);
+    const hipError_t ec = hipStreamEndCapture(cs, &g);
+    if (st != NNC_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (ec != hipSuccess) return fail(NNC_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
+    const hipError_t ei = hipGraphInstantiate(ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return fail(NNC_EHIP, "graph instantiation failed: %s", hipGetErrorString(ei));
+    return NNC_OK;
+  };
+  const int per = std::min(n, kSweepsPerGraph);
+  hipGraphExec_t gb = nullptr, gr = nullptr;
+  nnc_status st = capture(&gb, per);
+  if (st == NNC_OK && n % per) st = capture(&gr, n % per);
+  for (int t = 0; st == NNC_OK && t + per <= n; t += per)
+    if (hipGraphLaunch(gb, cs) != hipSuccess) st = fail(NNC_EHIP, "graph launch failed");
+  if (st == NNC_OK && gr && hipGraphLaunch(gr, cs) != hipSuccess) st = fail(NNC_EHIP, "graph launch failed");
+  // an executable graph is destroyed only after its queued launches have finished
+  if (hipStreamSynchronize(cs) != hipSuccess && st == NNC_OK)
+    st = fail(NNC_EHIP, "stream synchronization after the sweeps failed");
+  for (hipGraphExec_t e : {gb, gr})
+    if (e) (void)hipGraphExecDestroy(e);
+  NNC_TRY(st);
+  if (!s) {
+    NNC_HIP(hipEventRecord(ev_out, cs));
+    NNC_HIP(hipStreamWaitEvent(s, ev_out, 0));
+    NNC_HIP(hipEventDestroy(ev_in));
+    NNC_HIP(hipEventDestroy(ev_out));
+  }
+  return NNC_OK;
+}
+
+// ------------------------------------------------------------------ nnCP of the data tensor
+// (the nnCPD step of Algorithm 2).  Two X passes per sweep, as in the Tucker sweep:
+// Z = X x_{d-1} B_{d-1}^T serves modes 0 .. d-2 (B_{d-1} is unchanged until the last mode),
+// T = X x_0 B_0^T (new B_0) serves mode d-1.  Each mode: rank-wise contraction of Z or T with
+// the other current factors (MTTKRP), multiplicative update, new Gram.
+struct CpxPlan {
+  int d = 0, r = 0;
+  int64_t N[kMaxDim];
+  int64_t size = 0;
+  size_t oZ, oT, oM, oPart, oWA, oWC, oS, oClip, oFlag, oRed, oRpart, total;
+};
+
+static CpxPlan plan_cpx(int d, const int64_t *dims, int r) {
+  CpxPlan p;
+  p.d = d;
+  p.r = r;
+  p.size = prod(dims, 0, d);
+  int64_t maxN = 1, part = 0, wa = 0, wc = 0;
+  for (int k = 0; k < d; ++k) {
+    p.N[k] = dims[k];
+    maxN = std::max(maxN, dims[k]);
+  }
+  for (int n = 0; n < d - 1; ++n) {  // modes served by Z
+    const int64_t A = prod(dims, 0, n), C = prod(dims, n + 1, d - 1);
+    part = std::max(part, diag_part_floats(A, dims[n], C, r));
+    if (n >= 2) wa = std::max(wa, A * r);
+    if (d - 1 - (n + 1) >= 2) wc = std::max(wc, C * r);
+  }
+  {  // the last mode, served by T
+    const int64_t A = prod(dims, 1, d - 1);
+    part = std::max(part, diag_part_floats(A, dims[d - 1], 1, r));
+    if (d - 2 >= 2) wa = std::max(wa, A * r);
+  }
+  Layout L;
+  p.oZ = L.take(sizeof(float) * (size_t)(p.size / dims[d - 1] * r));  // also the residual's rows
+  p.oT = L.take(sizeof(float) * (size_t)(p.size / dims[0] * r));
+  p.oM = L.take(sizeof(float) * (size_t)(maxN * r));
+  p.oPart = L.take(sizeof(float) * (size_t)part);
+  p.oWA = L.take(sizeof(float) * (size_t)wa);
+  p.oWC = L.take(sizeof(float) * (size_t)wc);
+  p.oS = L.take(sizeof(float) * (size_t)(d * r * r));
+  p.oClip = L.take(sizeof(unsigned long long));
+  p.oFlag = L.take(sizeof(unsigned int));
+  p.oRed = L.take(2 * sizeof(double));
+  p.oRpart = L.take(2 * sizeof(double) * resid_stream_max_blocks());
+  p.total = L.off;
+  return p;
+}
+
+// Khatri-Rao rows of the factors of modes [lo, hi) (row-major over those modes): none -> NULL,
+// one -> the factor itself, more -> built into buf.
+static nnc_status kr_weights(float *const *B, const int64_t *N, int lo, int hi, int r, float *buf,
+                             const float **w, int64_t *rows, hipStream_t s) {
+  *rows = prod(N, lo, hi);
+  if (hi <= lo) {
+    *w = nullptr;
+    return NNC_OK;
+  }
+  if (hi - lo == 1) {
+    *w = B[lo];
+    return NNC_OK;
+  }
+  int64_t dims[kMaxDim];
+  const float *C[kMaxDim];
+  for (int k = lo; k < hi; ++k) {
+    dims[k - lo] = N[k];
+    C[k - lo] = B[k];
+  }
+  dims[hi - lo] = 1;  // the rows exclude the last listed mode of launch_kr_rows
+  C[hi - lo] = B[lo];
+  NNC_TRY(launch_kr_rows(hi - lo + 1, dims, r, C, buf, s));
+  *w = buf;
+  return NNC_OK;
+}
+
+static nnc_status cpx_sweep(const CpxPlan &p, char *base, const void *X, nnc_dtype dt, float *const *B,
+                            double eps, hipStream_t s) {
+  const int d = p.d, r = p.r;
+  float *Z = (float *)(base + p.oZ), *T = (float *)(base + p.oT), *M = (float *)(base + p.oM);
+  float *part = (float *)(base + p.oPart), *WA = (float *)(base + p.oWA), *WC = (float *)(base + p.oWC);
+  float *S = (float *)(base + p.oS);
+  unsigned long long *clips = (unsigned long long *)(base + p.oClip);
+  NNC_TRY(launch_ttm(X, dt, p.size / p.N[d - 1], p.N[d - 1], 1, B[d - 1], r, 1, r, Z, s, true));
+  for (int n = 0; n < d - 1; ++n) {
+    const float *wa, *wc;
+    int64_t A, C;
+    NNC_TRY(kr_weights(B, p.N, 0, n, r, WA, &wa, &A, s));
+    NNC_TRY(kr_weights(B, p.N, n + 1, d - 1, r, WC, &wc, &C, s));
+    NNC_TRY(launch_diag(Z, 0, A, p.N[n], C, wa, wc, r, M, part, s));
+    NNC_TRY(launch_cp_mu(B[n], M, S, d, n, p.N[n], r, eps, clips, s));
+    NNC_TRY(launch_gram_block(B[n], p.N[n], r, S + (size_t)n * r * r, s));
+  }
+  NNC_TRY(launch_ttm(X, dt, 1, p.N[0], p.size / p.N[0], B[0], r, 1, r, T, s, true));
+  const float *wa;
+  int64_t A;
+  NNC_TRY(kr_weights(B, p.N, 1, d - 1, r, WA, &wa, &A, s));
+  NNC_TRY(launch_diag(T, 1, A, p.N[d - 1], 1, wa, nullptr, r, M, part, s));
+  NNC_TRY(launch_cp_mu(B[d - 1], M, S, d, d - 1, p.N[d - 1], r, eps, clips, s));
+  NNC_TRY(launch_gram_block(B[d - 1], p.N[d - 1], r, S + (size_t)(d - 1) * r * r, s));
+  return NNC_OK;
+}
+
+// ||X - cp(B)||^2 and ||X||^2 into the plan's red buffer.
+static nnc_status cpx_resid(const CpxPlan &p, char *base, const void *X, nnc_dtype dt,
+                            float *const *B, hipStream_t s) {
+  float *W = (float *)(base + p.oZ);
+  NNC_TRY(launch_kr_rows(p.d, p.N, p.r, (const float *const *)B, W, s));
+  int nb = 0;
+  NNC_TRY(launch_resid_stream(X, dt, p.size / p.N[p.d - 1], p.N[p.d - 1], W, B[p.d - 1], p.r,
+                              (double *)(base + p.oRpart), &nb, s));
+  return launch_reduce_pairs((double *)(base + p.oRpart), nb, (double *)(base + p.oRed), s);
+}
+
 }  // namespace nnc
 
 using namespace nnc;
@@ -993,6 +1165,139 @@ nnc_status nncp_fit(const float *core, int ndim, const int64_t *core_dims, int r
     NNC_HIP(hipMemcpyAsync(rel_residual, base + w.oRes, sizeof(double), hipMemcpyDeviceToHost, s));
     NNC_HIP(hipStreamSynchronize(s));
     if (!std::isfinite(*rel_residual)) return fail(NNC_ENUMERIC, "non-finite nnCP residual");
+  }
+  return NNC_OK;
+}
+
+size_t nncpx_workspace_bytes(int ndim, const int64_t *dims, int rank) {
+  if (check_dims(ndim, dims, "dims") != NNC_OK || rank < 1 || rank > 32) return 0;
+  return plan_cpx(ndim, dims, rank).total;
+}
+
+nnc_status nncpx_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *dims, int rank, int iters,
+                     float *const *factors, const nnc_options *opt, nnc_report *rep, void *stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  NNC_TRY(check_dims(ndim, dims, "dims"));
+  if (!X) return fail(NNC_EINVAL, "X is NULL");
+  NNC_TRY(check_ptrs((const void *const *)factors, ndim, "factors"));
+  if (xdt != NNC_F32 && xdt != NNC_BF16) return fail(NNC_EINVAL, "unknown dtype %d", (int)xdt);
+  if (rank < 1) return fail(NNC_EINVAL, "rank %d < 1", rank);
+  if (rank > 32) return fail(NNC_EUNSUPPORTED, "rank %d above 32", rank);
+  if (iters < 0) return fail(NNC_EINVAL, "iters = %d < 0", iters);
+  nnc_options o;
+  memset(&o, 0, sizeof o);
+  if (opt) o = *opt;
+  if (o.eps < 0) return fail(NNC_EINVAL, "eps < 0");
+  const double eps = o.eps > 0 ? o.eps : 1e-12;
+  if (o.fp32_final_sweeps < 0) return fail(NNC_EINVAL, "fp32_final_sweeps < 0");
+  if (o.fp32_final_sweeps > 0 && xdt != NNC_BF16)
+    return fail(NNC_EINVAL, "fp32_final_sweeps needs X in NNC_BF16");
+  if (o.fp32_final_sweeps > 0 && !o.x_fp32) return fail(NNC_EINVAL, "fp32_final_sweeps > 0 needs x_fp32");
+  if (o.objective_every < 0) return fail(NNC_EINVAL, "objective_every < 0");
+  if (o.objective_every > 0 && (!rep || !rep->objective_history))
+    return fail(NNC_EINVAL, "objective_every > 0 needs rep->objective_history");
+  const CpxPlan p = plan_cpx(ndim, dims, rank);
+  if (!o.workspace) return fail(NNC_EWORKSPACE, "workspace is NULL (need %zu bytes)", p.total);
+  if (o.workspace_bytes < p.total)
+    return fail(NNC_EWORKSPACE, "workspace has %zu bytes, need %zu", o.workspace_bytes, p.total);
+
+  hipStream_t s = (hipStream_t)stream;
+  char *base = (char *)o.workspace;
+  NNC_TRY(launch_fill_u64((unsigned long long *)(base + p.oClip), 1, 0ull, s));
+  NNC_HIP(hipMemsetAsync(base + p.oFlag, 0, sizeof(unsigned int), s));
+  for (int k = 0; k < ndim; ++k)
+    NNC_TRY(launch_gram_block(factors[k], dims[k], rank, (float *)(base + p.oS) + (size_t)k * rank * rank, s));
+  const int split = (xdt == NNC_BF16 && o.fp32_final_sweeps > 0)
+                        ? (iters > o.fp32_final_sweeps ? iters - o.fp32_final_sweeps : 0)
+                        : iters;
+  const void *xres = o.x_fp32 ? (const void *)o.x_fp32 : X;
+  const nnc_dtype dres = o.x_fp32 ? NNC_F32 : xdt;
+  const bool graphs = o.use_graph && !g_timing && o.objective_every == 0;
+  int hist = 0;
+  auto run = [&](int ta, int tb, const void *Xs, nnc_dtype dts) -> nnc_status {
+    if (o.objective_every == 0)
+      return run_sweeps(s, graphs, tb - ta,
+                        [&](hipStream_t cs) { return cpx_sweep(p, base, Xs, dts, factors, eps, cs); });
+    for (int t = ta; t < tb; ++t) {
+      NNC_TRY(cpx_sweep(p, base, Xs, dts, factors, eps, s));
+      if ((t + 1) % o.objective_every == 0) {
+        NNC_TRY(cpx_resid(p, base, xres, dres, factors, s));
+        double red[2];
+        NNC_HIP(hipMemcpyAsync(red, base + p.oRed, sizeof red, hipMemcpyDeviceToHost, s));
+        NNC_HIP(hipStreamSynchronize(s));
+        rep->objective_history[hist++] = rel_of(red);
+      }
+    }
+    return NNC_OK;
+  };
+  NNC_TRY(run(0, split, X, xdt));
+  NNC_TRY(run(split, iters, o.x_fp32, NNC_F32));
+  if (rep) {
+    NNC_TRY(cpx_resid(p, base, xres, dres, factors, s));
+    for (int k = 0; k < ndim; ++k)
+      NNC_TRY(launch_check_finite(factors[k], dims[k] * rank, (unsigned int *)(base + p.oFlag), s));
+    double red[2];
+    unsigned long long clips = 0;
+    unsigned int flag = 0;
+    NNC_HIP(hipMemcpyAsync(red, base + p.oRed, sizeof red, hipMemcpyDeviceToHost, s));
+    NNC_HIP(hipMemcpyAsync(&clips, base + p.oClip, sizeof clips, hipMemcpyDeviceToHost, s));
+    NNC_HIP(hipMemcpyAsync(&flag, base + p.oFlag, sizeof flag, hipMemcpyDeviceToHost, s));
+    NNC_HIP(hipStreamSynchronize(s));
+    rep->sweeps_done = iters;
+    rep->rel_residual = rel_of(red);
+    rep->eps_clips = (long long)clips;
+    rep->history_len = hist;
+    rep->ttm_pass_ms = 0;
+    rep->ttm_pass_launches = 0;
+    rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (flag || !std::isfinite(rep->rel_residual))
+      return fail(NNC_ENUMERIC, "non-finite values in the fitted model (NaN or Inf in X?)");
+  }
+  return NNC_OK;
+}
+
+size_t nmf_workspace_bytes(int64_t rows, int64_t cols, int rank) {
+  if (rows < 1 || cols < 1 || rank < 1 || rank > 32) return 0;
+  const int64_t dims[2] = {rows, cols};
+  const CpProblem pb = cp_problem(2, dims);
+  Layout L;
+  L.take(cp_ws(pb, 1, &rank, false).total);
+  L.take(sizeof(float) * (size_t)(cols * rank));
+  return L.off;
+}
+
+nnc_status nmf_fit(const float *A, int64_t rows, int64_t cols, int rank, int iters, float *W, float *H,
+                   double eps, double *rel_residual, void *workspace, size_t workspace_bytes,
+                   void *stream) {
+  if (!A || !W || !H) return fail(NNC_EINVAL, "A, W and H must be non-NULL");
+  if (rows < 1 || cols < 1) return fail(NNC_EINVAL, "matrix %lld x %lld is empty", (long long)rows, (long long)cols);
+  if (rank < 1) return fail(NNC_EINVAL, "rank %d < 1", rank);
+  if (rank > 32) return fail(NNC_EUNSUPPORTED, "rank %d above 32", rank);
+  if (iters < 0) return fail(NNC_EINVAL, "iters = %d < 0", iters);
+  if (eps < 0) return fail(NNC_EINVAL, "eps < 0");
+  const size_t need = nmf_workspace_bytes(rows, cols, rank);
+  if (!workspace || workspace_bytes < need)
+    return fail(NNC_EWORKSPACE, "workspace has %zu bytes, need %zu", workspace ? workspace_bytes : 0, need);
+  const int64_t dims[2] = {rows, cols};
+  const CpProblem pb = cp_problem(2, dims);
+  const CpWs w = cp_ws(pb, 1, &rank, false);
+  Layout L;
+  L.take(w.total);
+  char *base = (char *)workspace;
+  float *Ht = (float *)(base + L.take(sizeof(float) * (size_t)(cols * rank)));
+  hipStream_t s = (hipStream_t)stream;
+  // A ~ W H is the two-way nonnegative CP with factors W (rows x rank) and H^T (cols x rank)
+  NNC_TRY(launch_transpose(H, rank, cols, Ht, s));
+  float *fac[2] = {W, Ht};
+  NNC_TRY(launch_fill_u64((unsigned long long *)(base + w.oClip), 1, 0ull, s));
+  NNC_TRY(launch_nncp(A, pb, 1, nullptr, rank, nullptr, fac, iters, eps > 0 ? eps : 1e-12,
+                      rel_residual ? (double *)(base + w.oRes) : nullptr,
+                      (unsigned long long *)(base + w.oClip), (float *)(base + w.oZ), 0, s));
+  NNC_TRY(launch_transpose(Ht, cols, rank, H, s));
+  if (rel_residual) {
+    NNC_HIP(hipMemcpyAsync(rel_residual, base + w.oRes, sizeof(double), hipMemcpyDeviceToHost, s));
+    NNC_HIP(hipStreamSynchronize(s));
+    if (!std::isfinite(*rel_residual)) return fail(NNC_ENUMERIC, "non-finite NMF residual");
   }
   return NNC_OK;
 }

@@ -1,0 +1,256 @@
+// Small steps of the nonnegative CP fit of the data tensor itself (the nnCPD step of
+// Algorithm 2), around the two X-streaming contractions it shares with the Tucker sweep.
+//
+// With Z = X x_{d-1} B_{d-1}^T (rank index last) and T = X x_0 B_0^T (rank index first), the
+// MTTKRP of every mode is a rank-wise ("diagonal") contraction of Z or T with the current
+// factors of the remaining modes:
+//   M_n[i][rho] = sum_{a, c} Y[a][i][c][rho] WA[a][rho] WC[c][rho]      (rank index last)
+//   M_n[i][rho] = sum_{a, c} Y[rho][a][i][c] WA[a][rho] WC[c][rho]      (rank index first)
+// where a runs over the modes of Y before mode n and c over those after it, and WA / WC are
+// the Khatri-Rao rows of those modes' factors.  The multiplicative update then uses
+// H_n = Hadamard product of the other factors' Grams (reading R1 applied to CP).
+#include <algorithm>
+
+#include "nnc_internal.h"
+
+namespace nnc {
+
+constexpr int kDiagThreads = 256;
+
+struct DiagArgs {
+  const float *Y;
+  const float *WA, *WC;  // null: weight 1
+  int64_t A, Nt, C;
+  int r;
+  int rho_first;
+  float *out;    // [Nt][r] (one slice) or partials [slices][Nt][r]
+  int slices;
+};
+
+static __device__ inline float diag_y(const DiagArgs &g, int64_t a, int64_t i, int64_t c, int rho) {
+  const int64_t e = (a * g.Nt + i) * g.C + c;
+  return g.rho_first ? g.Y[(int64_t)rho * g.A * g.Nt * g.C + e] : g.Y[e * g.r + rho];
+}
+
+static __device__ inline float diag_w(const DiagArgs &g, int64_t a, int64_t c, int rho) {
+  float w = g.WA ? g.WA[a * g.r + rho] : 1.f;
+  if (g.WC) w *= g.WC[c * g.r + rho];
+  return w;
+}
+
+// C > 1: block (i, slice); the threads stride over the flattened (a, c) range of the slice
+// (c fastest, contiguous in Y) and the partial sums are combined by a fixed pairwise tree.
+template <int RM>
+__global__ __launch_bounds__(kDiagThreads) void diag_inner_k(DiagArgs g) {
+  __shared__ float red[kDiagThreads * RM];
+  const int64_t i = blockIdx.x % g.Nt;
+  const int s = (int)(blockIdx.x / g.Nt);
+  const int64_t F = g.A * g.C;
+  const int64_t f0 = F * s / g.slices, f1 = F * (s + 1) / g.slices;
+  float acc[RM];
+#pragma unroll
+  for (int q = 0; q < RM; ++q) acc[q] = 0.f;
+  int64_t f = f0 + threadIdx.x;
+  int64_t a = f / g.C, c = f - a * g.C;  // advanced incrementally below
+  for (; f < f1; f += kDiagThreads) {
+#pragma unroll
+    for (int q = 0; q < RM; ++q)
+      if (q < g.r) acc[q] = fmaf(diag_y(g, a, i, c, q), diag_w(g, a, c, q), acc[q]);
+    c += kDiagThreads;
+    if (c >= g.C) {
+      a += c / g.C;
+      c %= g.C;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < RM; ++q) red[q * kDiagThreads + threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int h = kDiagThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+#pragma unroll
+      for (int q = 0; q < RM; ++q) red[q * kDiagThreads + threadIdx.x] += red[q * kDiagThreads + threadIdx.x + h];
+    __syncthreads();
+  }
+  if ((int)threadIdx.x < g.r) g.out[((int64_t)s * g.Nt + i) * g.r + threadIdx.x] = red[threadIdx.x * kDiagThreads];
+}
+
+// C == 1: block (tile of 64 consecutive i, slice of a); lane <-> i (contiguous in Y), the
+// four waves stride over a and their sums are added in wave order.
+template <int RM>
+__global__ __launch_bounds__(kDiagThreads) void diag_outer_k(DiagArgs g) {
+  __shared__ float red[kDiagThreads * RM];
+  const int64_t tiles = (g.Nt + 63) / 64;
+  const int64_t tile = blockIdx.x % tiles;
+  const int s = (int)(blockIdx.x / tiles);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i = tile * 64 + lane;
+  const bool live = i < g.Nt;
+  const int64_t a0 = g.A * s / g.slices, a1 = g.A * (s + 1) / g.slices;
+  float acc[RM];
+#pragma unroll
+  for (int q = 0; q < RM; ++q) acc[q] = 0.f;
+  if (live)
+    for (int64_t a = a0 + w; a < a1; a += kDiagThreads / 64) {
+#pragma unroll
+      for (int q = 0; q < RM; ++q)
+        if (q < g.r) acc[q] = fmaf(diag_y(g, a, i, 0, q), diag_w(g, a, 0, q), acc[q]);
+    }
+#pragma unroll
+  for (int q = 0; q < RM; ++q) red[(w * RM + q) * 64 + lane] = acc[q];
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < RM * 64; idx += kDiagThreads) {
+    const int q = idx >> 6, l = idx & 63;
+    const int64_t ii = tile * 64 + l;
+    if (q >= g.r || ii >= g.Nt) continue;
+    float t = red[q * 64 + l];
+    for (int ww = 1; ww < kDiagThreads / 64; ++ww) t += red[(ww * RM + q) * 64 + l];
+    g.out[((int64_t)s * g.Nt + ii) * g.r + q] = t;
+  }
+}
+
+// out[e] = sum_{s < slices} part[s][e], s in order.
+__global__ void diag_sum_k(const float *__restrict__ part, int slices, int64_t n, float *__restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  float t = part[e];
+  for (int s = 1; s < slices; ++s) t += part[(int64_t)s * n + e];
+  out[e] = t;
+}
+
+int64_t diag_slices(int64_t A, int64_t Nt, int64_t C) {
+  if (C > 1) {
+    const int64_t per = std::max<int64_t>(1, 512 / Nt);
+    return std::max<int64_t>(1, std::min<int64_t>(per, (A * C) / (kDiagThreads * 4)));
+  }
+  const int64_t tiles = (Nt + 63) / 64;
+  const int64_t per = std::max<int64_t>(1, 512 / tiles);
+  return std::max<int64_t>(1, std::min<int64_t>(per, A / 16));
+}
+
+nnc_status launch_diag(const float *Y, int rho_first, int64_t A, int64_t Nt, int64_t C, const float *WA,
+                       const float *WC, int r, float *out, float *part, hipStream_t s) {
+  if (r < 1 || r > 32) return fail(NNC_EUNSUPPORTED, "rank %d outside [1, 32]", r);
+  const int64_t S = diag_slices(A, Nt, C);
+  if (S > 1 && !part) return fail(NNC_EINVAL, "diag: partial buffer missing");
+  DiagArgs g{Y, WA, WC, A, Nt, C, r, rho_first, S > 1 ? part : out, (int)S};
+  const int64_t blocks = C > 1 ? Nt * S : ((Nt + 63) / 64) * S;
+  if (blocks > 0x7fffffff) return fail(NNC_EUNSUPPORTED, "diag: grid too large");
+  const int RM = r <= 8 ? 8 : (r <= 16 ? 16 : 32);
+#define NNC_DIAG(KERN)                                                                         \
+  do {                                                                                         \
+    if (RM == 8) hipLaunchKernelGGL(KERN<8>, dim3((unsigned)blocks), dim3(kDiagThreads), 0, s, g);   \
+    else if (RM == 16) hipLaunchKernelGGL(KERN<16>, dim3((unsigned)blocks), dim3(kDiagThreads), 0, s, g); \
+    else hipLaunchKernelGGL(KERN<32>, dim3((unsigned)blocks), dim3(kDiagThreads), 0, s, g);          \
+  } while (0)
+  if (C > 1) NNC_DIAG(diag_inner_k);
+  else NNC_DIAG(diag_outer_k);
+#undef NNC_DIAG
+  if (S > 1) {
+    const int64_t n = Nt * r;
+    hipLaunchKernelGGL(diag_sum_k, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, (int)S, n, out);
+  }
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+int64_t diag_part_floats(int64_t A, int64_t Nt, int64_t C, int r) {
+  const int64_t S = diag_slices(A, Nt, C);
+  return S > 1 ? S * Nt * r : 0;
+}
+
+// B <- B * M / max(B H, eps) with H = prod_{k != n} S_k (entrywise, S packed [d][r][r]);
+// FP64 division, clipped denominators counted.  Thread (row, rho), 256 / r rows per block.
+__global__ __launch_bounds__(256) void cp_mu_k(float *__restrict__ B, const float *__restrict__ M,
+                                               const float *__restrict__ S, int d, int n, int64_t N,
+                                               int r, double eps, unsigned long long *clips) {
+  __shared__ float H[32 * 32];
+  __shared__ unsigned int nclip;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < r * r; e += 256) {
+    float h = 1.f;
+    for (int k = 0; k < d; ++k)
+      if (k != n) h *= S[(int64_t)k * r * r + e];
+    H[e] = h;
+  }
+  if (tid == 0) nclip = 0;
+  __syncthreads();
+  const int rpb = 256 / r;
+  const int64_t i = (int64_t)blockIdx.x * rpb + tid / r;
+  const int q = tid % r;
+  const bool act = tid < rpb * r && i < N;
+  float nv = 0.f;
+  unsigned int mine = 0;
+  if (act) {
+    float den = 0.f;
+    for (int t = 0; t < r; ++t) den = fmaf(B[i * r + t], H[t * r + q], den);
+    double dd = (double)den;
+    if (dd < eps) {
+      dd = eps;
+      mine = 1;
+    }
+    nv = (float)(((double)B[i * r + q] * (double)M[i * r + q]) / dd);
+  }
+  if (mine) atomicAdd(&nclip, mine);
+  __syncthreads();  // every row of the block is read before any is written
+  if (act) B[i * r + q] = nv;
+  if (tid == 0 && nclip) atomicAdd(clips, (unsigned long long)nclip);
+}
+
+nnc_status launch_cp_mu(float *B, const float *M, const float *S, int d, int n, int64_t N, int r,
+                        double eps, unsigned long long *clips, hipStream_t s) {
+  if (r < 1 || r > 32) return fail(NNC_EUNSUPPORTED, "rank %d outside [1, 32]", r);
+  const int64_t rpb = 256 / r;
+  hipLaunchKernelGGL(cp_mu_k, dim3((unsigned)((N + rpb - 1) / rpb)), dim3(256), 0, s, B, M, S, d, n, N,
+                     r, eps, clips);
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+// S = A^T A (A: N x r, r <= 32) in one workgroup: thread (entry, split) sums the rows of its
+// split (rows j with j mod splits == split), the splits are added in order.
+__global__ __launch_bounds__(1024) void gram_block_k(const float *__restrict__ A, int64_t N, int r,
+                                                     float *__restrict__ S) {
+  __shared__ float part[1024];
+  const int tid = threadIdx.x;
+  const int rr = r * r;
+  const int splits = 1024 / rr;
+  const int e = tid % rr, sp = tid / rr;
+  float acc = 0.f;
+  if (sp < splits) {
+    const int a = e / r, b = e - (e / r) * r;
+#pragma unroll 4
+    for (int64_t j = sp; j < N; j += splits) acc = fmaf(A[j * r + a], A[j * r + b], acc);
+  }
+  part[tid] = acc;
+  __syncthreads();
+  if (tid < rr) {
+    float t = part[tid];
+    for (int k = 1; k < splits; ++k) t += part[k * rr + tid];
+    S[tid] = t;
+  }
+}
+
+nnc_status launch_gram_block(const float *A, int64_t N, int r, float *S, hipStream_t s) {
+  if (r < 1 || r > 32) return fail(NNC_EUNSUPPORTED, "rank %d outside [1, 32]", r);
+  hipLaunchKernelGGL(gram_block_k, dim3(1), dim3(1024), 0, s, A, N, r, S);
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+// out[j][i] = in[i][j] (rows x cols -> cols x rows), small matrices.
+__global__ void transpose_k(const float *__restrict__ in, int64_t rows, int64_t cols, float *__restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t i = e / cols, j = e - (e / cols) * cols;
+  out[j * rows + i] = in[e];
+}
+
+nnc_status launch_transpose(const float *in, int64_t rows, int64_t cols, float *out, hipStream_t s) {
+  const int64_t n = rows * cols;
+  if (n == 0) return NNC_OK;
+  hipLaunchKernelGGL(transpose_k, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, rows, cols, out);
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+}  // namespace nnc

@@ -154,6 +154,14 @@ nnc_status launch_small_with_core(const float *in, int64_t P, int64_t N, int64_t
                                   int64_t ldl, int64_t ldr, int64_t R, float *out,
                                   const CoreArgsHost &h, hipStream_t s);
 // out[e] = sum_{b < nparts} part[b][e] (fixed order)
+// Nonnegative CP of the data tensor (cpx_kernels.hip).
+nnc_status launch_diag(const float *Y, int rho_first, int64_t A, int64_t Nt, int64_t C, const float *WA,
+                       const float *WC, int r, float *out, float *part, hipStream_t s);
+int64_t diag_part_floats(int64_t A, int64_t Nt, int64_t C, int r);
+nnc_status launch_cp_mu(float *B, const float *M, const float *S, int d, int n, int64_t N, int r,
+                        double eps, unsigned long long *clips, hipStream_t s);
+nnc_status launch_gram_block(const float *A, int64_t N, int r, float *S, hipStream_t s);
+nnc_status launch_transpose(const float *in, int64_t rows, int64_t cols, float *out, hipStream_t s);
 nnc_status launch_sum_parts(const float *part, int nparts, int64_t n, float *out, hipStream_t s);
 
 }  // namespace nnc

@@ -18,7 +18,8 @@ generation, so any slice of a stream can be produced on its own.
 
 Stream ids (one per role):  planted factor n -> n;  zero mask of planted factor n ->
 16 + n;  additive noise -> 32;  initial core G0 -> 48;  initial Tucker factor n ->
-64 + n;  nnCP restart j, factor n -> 1024 + 16 j + n.
+64 + n;  nnCP restart j, factor n -> 1024 + 16 j + n;  NMF of factor n (Algorithm 2):
+W0 -> 2048 + n, H0 -> 2064 + n.
 """
 
 from __future__ import annotations
@@ -37,6 +38,8 @@ STREAM_NOISE = 32
 STREAM_CORE0 = 48
 STREAM_FACTOR0 = 64
 STREAM_CP_RESTART = 1024
+STREAM_NMF_W = 2048
+STREAM_NMF_H = 2064
 
 
 def _mix64_int(z: int) -> int:
@@ -118,6 +121,16 @@ def init_cp_factors(seed: int, core_dims, rank: int, restart: int = 0, dtype=np.
     """Initial nnCP factors B0_n ~ U[0,1), each core_dims[n] x rank."""
     return [uniform_matrix(seed, STREAM_CP_RESTART + 16 * restart + n, int(core_dims[n]), rank)
             .astype(dtype) for n in range(len(core_dims))]
+
+
+def init_nmf(seed: int, dims, ranks, rank: int, dtype=np.float32):
+    """Initial NMF factors of the CP factors A^(n) ~ W_n H_n (Algorithm 2): W0_n ~ U[0,1)
+    dims[n] x ranks[n] and H0_n ~ U[0,1) ranks[n] x rank."""
+    W = [uniform_matrix(seed, STREAM_NMF_W + n, int(dims[n]), int(ranks[n])).astype(dtype)
+         for n in range(len(dims))]
+    H = [uniform_matrix(seed, STREAM_NMF_H + n, int(ranks[n]), int(rank)).astype(dtype)
+         for n in range(len(dims))]
+    return W, H
 
 
 def planted_factors(seed: int, dims, R: int, zero_prob: float = 0.0):

@@ -103,6 +103,43 @@ def test_other_entry_points_validate():
     assert L.nntucker_grad(FAKE, 0, 3, D(4, 4, 4), D(2, 2, 2), FAKE, _ptrs(3), FAKE, _ptrs(3), None, FAKE, 8, None) == nnc.NNC_EWORKSPACE
 
 
+def test_algorithm2_entry_points_validate():
+    L = nnc.lib()
+    assert L.nncpx_workspace_bytes(3, D(40, 40, 40), 3) > 0
+    assert L.nncpx_workspace_bytes(3, D(40, 40, 40), 33) == 0
+    assert L.nmf_workspace_bytes(512, 10, 20) > 0
+    assert L.nmf_workspace_bytes(512, 0, 20) == 0
+    opt = nnc.Options()
+    opt.workspace = 0x1000
+    opt.workspace_bytes = 1 << 40
+    f = L.nncpx_fit
+    assert f(None, 0, 3, D(4, 4, 4), 2, 1, _ptrs(3), ctypes.byref(opt), None, None) == nnc.NNC_EINVAL
+    assert f(FAKE, 0, 3, D(4, 4, 4), 2, 1, _ptrs(3, 2), ctypes.byref(opt), None, None) == nnc.NNC_EINVAL
+    assert "factors[2]" in nnc.last_error()
+    assert f(FAKE, 0, 3, D(4, 0, 4), 2, 1, _ptrs(3), ctypes.byref(opt), None, None) == nnc.NNC_EINVAL
+    assert f(FAKE, 0, 3, D(4, 4, 4), 0, 1, _ptrs(3), ctypes.byref(opt), None, None) == nnc.NNC_EINVAL
+    assert f(FAKE, 0, 3, D(4, 4, 4), 33, 1, _ptrs(3), ctypes.byref(opt), None, None) == nnc.NNC_EUNSUPPORTED
+    assert f(FAKE, 0, 3, D(4, 4, 4), 2, -1, _ptrs(3), ctypes.byref(opt), None, None) == nnc.NNC_EINVAL
+    assert f(FAKE, 5, 3, D(4, 4, 4), 2, 1, _ptrs(3), ctypes.byref(opt), None, None) == nnc.NNC_EINVAL
+    o2 = nnc.Options()
+    o2.workspace, o2.workspace_bytes, o2.fp32_final_sweeps = 0x1000, 1 << 40, 5
+    assert f(FAKE, 0, 3, D(4, 4, 4), 2, 10, _ptrs(3), ctypes.byref(o2), None, None) == nnc.NNC_EINVAL
+    assert f(FAKE, 1, 3, D(4, 4, 4), 2, 10, _ptrs(3), ctypes.byref(o2), None, None) == nnc.NNC_EINVAL
+    o3 = nnc.Options()
+    assert f(FAKE, 0, 3, D(4, 4, 4), 2, 1, _ptrs(3), ctypes.byref(o3), None, None) == nnc.NNC_EWORKSPACE
+    o3.workspace, o3.workspace_bytes = 0x1000, 16
+    assert f(FAKE, 0, 3, D(4, 4, 4), 2, 1, _ptrs(3), ctypes.byref(o3), None, None) == nnc.NNC_EWORKSPACE
+    g = L.nmf_fit
+    assert g(None, 8, 3, 2, 5, FAKE, FAKE, 0.0, None, FAKE, 1 << 30, None) == nnc.NNC_EINVAL
+    assert g(FAKE, 8, 3, 2, 5, None, FAKE, 0.0, None, FAKE, 1 << 30, None) == nnc.NNC_EINVAL
+    assert g(FAKE, 0, 3, 2, 5, FAKE, FAKE, 0.0, None, FAKE, 1 << 30, None) == nnc.NNC_EINVAL
+    assert g(FAKE, 8, 3, 0, 5, FAKE, FAKE, 0.0, None, FAKE, 1 << 30, None) == nnc.NNC_EINVAL
+    assert g(FAKE, 8, 3, 40, 5, FAKE, FAKE, 0.0, None, FAKE, 1 << 30, None) == nnc.NNC_EUNSUPPORTED
+    assert g(FAKE, 8, 3, 2, -2, FAKE, FAKE, 0.0, None, FAKE, 1 << 30, None) == nnc.NNC_EINVAL
+    assert g(FAKE, 8, 3, 2, 5, FAKE, FAKE, -1.0, None, FAKE, 1 << 30, None) == nnc.NNC_EINVAL
+    assert g(FAKE, 8, 3, 2, 5, FAKE, FAKE, 0.0, None, FAKE, 8, None) == nnc.NNC_EWORKSPACE
+
+
 def test_binding_rejects_cpu_tensors():
     import torch
     with pytest.raises(ValueError):

@@ -382,3 +382,61 @@ def test_gradient_finite_differences_16cubed_core_4cubed():
         theta[idx] = old
         fd = (lp - lm) / (2 * h)
         assert abs(fd - g) <= 1e-6 * max(1.0, abs(g)), (blk, idx, fd, g)
+
+
+# --------------------------------------------------------------------------- Algorithm 2
+def _lee_seung(V, W, H, iters):
+    """Textbook Lee-Seung Frobenius NMF sweeps, W first, then H (written out here)."""
+    for _ in range(iters):
+        W = W * (V @ H.T) / (W @ H @ H.T)
+        H = H * (W.T @ V) / (W.T @ W @ H)
+    return W, H
+
+
+def test_nmf_is_lee_seung():
+    rng = _rng(21)
+    V = rng.random((11, 4))
+    W0, H0 = rng.random((11, 6)), rng.random((6, 4))
+    W, H, clips = oracle.nmf(V, W0, H0, 7)
+    We, He = _lee_seung(V, W0, H0, 7)
+    assert clips == 0
+    np.testing.assert_allclose(W, We, rtol=1e-12)
+    np.testing.assert_allclose(H, He, rtol=1e-12)
+
+
+def test_alg2_is_nncp_of_x_then_nmf_of_each_factor():
+    """Algorithm 2: nnCP of X first, then an NMF of each fitted CP factor (not of its initial
+    value), then the lift C_n = F_n B_n; the NMF sweeps here are the explicit textbook loop."""
+    rng = _rng(22)
+    X = rng.random((5, 6, 4))
+    r, m = 3, (4, 2, 3)
+    B0 = [rng.random((n, r)) for n in X.shape]
+    F0 = [rng.random((X.shape[k], m[k])) for k in range(3)]
+    H0 = [rng.random((m[k], r)) for k in range(3)]
+    out = oracle.nncandelinc_alg2(X, B0, F0, H0, 9, 5)
+    Acp, _, _ = oracle.nncp(X, B0, 9)
+    for k in range(3):
+        np.testing.assert_array_equal(out["Acp"][k], Acp[k])
+        We, He = _lee_seung(Acp[k], F0[k], H0[k], 5)
+        np.testing.assert_allclose(out["F"][k], We, rtol=1e-12)
+        np.testing.assert_allclose(out["B"][k], He, rtol=1e-12)
+        np.testing.assert_allclose(out["C"][k], We @ He, rtol=1e-12)
+    Xhat = np.einsum("ir,jr,kr->ijk", *out["C"])
+    assert abs(out["cp_rel"] - np.linalg.norm(X - Xhat) / np.linalg.norm(X)) <= 1e-12
+
+
+def test_alg2_fixed_point_at_exact_integer_factorizations():
+    """X = cp(F_n B_n) with integer F_n, B_n: starting Algorithm 2 at (F_n B_n, F_n, B_n) every
+    multiplicative ratio is exactly 1, so nothing moves and the lifted model is exact."""
+    rng = _rng(23)
+    dims, m, r = (4, 5, 3), (3, 2, 3), 2
+    F = [rng.integers(1, 4, (dims[k], m[k])).astype(np.float64) for k in range(3)]
+    B = [rng.integers(1, 4, (m[k], r)).astype(np.float64) for k in range(3)]
+    A = [f @ b for f, b in zip(F, B)]
+    X = oracle.cp_full(A)
+    out = oracle.nncandelinc_alg2(X, A, F, B, 3, 3)
+    for k in range(3):
+        assert np.array_equal(out["Acp"][k], A[k])
+        assert np.array_equal(out["F"][k], F[k])
+        assert np.array_equal(out["B"][k], B[k])
+    assert out["cp_rel"] == 0.0 and out["clips"] == 0
