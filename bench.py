@@ -10,6 +10,10 @@ way and reported under "fp32_form"; both start from identical initial values and
 same number of sweeps, and their final relative residuals (both measured against the FP32
 X) are reported with their difference.
 
+The "alg2" object times Algorithm 2 on the same tensor (nnCP of X at rank 10 with the same
+sweep count and refinement, then an NMF of each CP factor with m = 20, lift, residuals), both
+forms, beside one oracle sweep of the nnCP of X.
+
 The roofline object describes the dominant kernel (the X-streaming contraction of the BF16
 form, timed per launch with HIP events on the stream it runs on).  The cpu_baseline object
 times the FP64 oracle on a bounded sample (a few sweeps of the same 512^3 problem).
@@ -93,7 +97,8 @@ def summarize(args):
              "    rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof -o run -- "
              "python -u bench.py --steps 1 --warmup 0 --no-cpu", "",
              "The step runs 500 nnTucker sweeps per form (BF16 form: 480 on BF16 X + 20 on FP32 X),",
-             "nnCP rank 10 x 300 sweeps, lift and residuals; bench.py then times each X-streaming",
+             "nnCP rank 10 x 300 sweeps, lift and residuals; then Algorithm 2 twice per form (nnCP of",
+             "X rank 10 x 500 sweeps, NMF of each factor, lift); bench.py then times each X-streaming",
              "pass kernel over 23 launches and runs a 20-sweep eager fit.", "",
              "| kernel | calls | total ms | avg us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
     with open(_find(prof_dir, "kernel_stats.csv")) as f:
@@ -312,6 +317,54 @@ def main():
         log("%s: %.1f ms/step, %.0f sweeps/s, tucker rel %.6g, lifted rel %.6g"
             % (form, results[form]["ms_per_step"], results[form]["sweeps_per_s"], tucker_rel, cp_rel))
 
+    # ---- Algorithm 2 on the same tensor: nnCP of X (rank 10), NMF of each factor (m = 20),
+    # lift, residual; both forms from identical initial values.
+    Bx0 = [torch.from_numpy(b).to(dev) for b in synth.init_cp_factors(SEED, dims, rank)]
+    W0, H0 = synth.init_nmf(SEED, dims, ranks, rank)
+    W0 = [torch.from_numpy(w).to(dev) for w in W0]
+    H0 = [torch.from_numpy(h).to(dev) for h in H0]
+    wsx = torch.empty(nnc.nncpx_workspace_bytes(dims, rank), dtype=torch.uint8, device=dev)
+    Bx = [torch.empty_like(b) for b in Bx0]
+    Wf = [torch.empty_like(w) for w in W0]
+    Hf = [torch.empty_like(h) for h in H0]
+
+    def alg2_step(bf16: bool):
+        for b, b0 in zip(Bx, Bx0):
+            b.copy_(b0)
+        for w, w0 in zip(Wf, W0):
+            w.copy_(w0)
+        for h, h0 in zip(Hf, H0):
+            h.copy_(h0)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        if bf16:
+            nnc.nncpx_fit(Xb, rank, args.sweeps, Bx, x_fp32=X32, fp32_final_sweeps=args.fp32_final,
+                          report=False, workspace=wsx)
+        else:
+            nnc.nncpx_fit(X32, rank, args.sweeps, Bx, report=False, workspace=wsx)
+        torch.cuda.synchronize()
+        t_cp = time.perf_counter() - t
+        t = time.perf_counter()
+        for n in range(3):
+            nnc.nmf_fit(Bx[n], R, args.cp_sweeps, Wf[n], Hf[n], residual=False)
+        C = nnc.nncandelinc_lift(Wf, Hf)
+        torch.cuda.synchronize()
+        t_nmf = time.perf_counter() - t
+        return t_cp, t_nmf, nnc.reconstruct_residual(X32, Bx), nnc.reconstruct_residual(X32, C)
+
+    alg2 = {}
+    for form, bf16 in (("bf16", True), ("fp32", False)):
+        alg2_step(bf16)  # warm-up
+        t_cp, t_nmf, rel_x, rel_l = alg2_step(bf16)
+        alg2[form] = {"sweeps_per_s": round(args.sweeps / t_cp, 2), "nncp_x_ms": round(t_cp * 1e3, 3),
+                      "nmf_lift_ms": round(t_nmf * 1e3, 3), "cp_x_rel": rel_x, "lifted_rel": rel_l}
+        log("alg2 %s: nnCP of X %.1f ms (%.0f sweeps/s), NMF+lift %.1f ms, rel %.6g, lifted rel %.6g"
+            % (form, t_cp * 1e3, args.sweeps / t_cp, t_nmf * 1e3, rel_x, rel_l))
+    alg2["abs_diff_cp_x_rel"] = abs(alg2["bf16"]["cp_x_rel"] - alg2["fp32"]["cp_x_rel"])
+    alg2["config"] = ("Algorithm 2 on the same 512^3 tensor: nnCP rank %d, %d MU sweeps (BF16 form: last %d "
+                      "on FP32 X); NMF of each factor with m = %d, %d sweeps; lift; residuals"
+                      % (rank, args.sweeps, args.fp32_final, R, args.cp_sweeps))
+
     # ---- per-launch timing of the two X-streaming contractions (same kernels, same launch
     # configuration as inside the fit), HIP events on the stream they are launched on.
     size = N ** 3
@@ -376,6 +429,13 @@ def main():
                "kind": "oracle",
                "sample": "%d FP64 nnTucker sweeps of the same 512^3 problem (multirank 20^3) from the "
                          "same initial values, %.1f s" % (done, el)}
+        t = time.perf_counter()
+        b0x = [b.astype(np.float64) for b in synth.init_cp_factors(SEED, dims, rank)]
+        oracle.nncp(X64, b0x, 1)
+        el = time.perf_counter() - t
+        alg2["cpu_baseline"] = {"value": round(1.0 / el, 5), "unit": "nnCP-of-X MU sweeps/s",
+                                "cores": oracle.get_threads(), "kind": "oracle",
+                                "sample": "1 FP64 nnCP sweep of the 512^3 tensor, rank %d, %.1f s" % (rank, el)}
         del X64
 
     bf, fp = results["bf16"], results["fp32"]
@@ -404,6 +464,7 @@ def main():
         "x_to_bf16_ms": round(convert_ms, 3),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "alg2": alg2,
     }
     print(json.dumps(line), flush=True)
 
