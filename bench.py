@@ -345,8 +345,7 @@ def main():
         torch.cuda.synchronize()
         t_cp = time.perf_counter() - t
         t = time.perf_counter()
-        for n in range(3):
-            nnc.nmf_fit(Bx[n], R, args.cp_sweeps, Wf[n], Hf[n], residual=False)
+        nnc.nmf_fit_batched(Bx, [R] * 3, args.cp_sweeps, Wf, Hf, residual=False)
         C = nnc.nncandelinc_lift(Wf, Hf)
         torch.cuda.synchronize()
         t_nmf = time.perf_counter() - t

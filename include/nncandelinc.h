@@ -184,8 +184,9 @@ nnc_status nncpx_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *dims
  * factor A^(i) with m_i latent columns: A^(i) ~ F^(i) B^(i)), exactly `iters` Lee-Seung
  * multiplicative sweeps, W first, then H:
  *   W <- W * (A H^T) / max(W H H^T, eps),   H <- H * (W^T A) / max(W^T W H, eps),
- * which is the two-way case of the nnCP rule (factors W and H^T), computed by the nnCP
- * kernel in one workgroup.
+ * which is the two-way case of the nnCP rule (factors W and H^T).  One workgroup computes
+ * it with A, W and H in LDS when they fit (rows * rank <= 32768, cols <= 32, about 159 KiB),
+ * else the nnCP kernel runs it as a two-way nnCP.
  *   A  rows x cols (float, entries >= 0).   W  rows x rank, in: initial; out: fitted.
  *   H  rank x cols, in: initial; out: fitted.   rank <= 32.
  *   rel_residual  host, nullable: ||A - W H||_F / ||A||_F; non-NULL syncs.
@@ -195,6 +196,20 @@ size_t nmf_workspace_bytes(int64_t rows, int64_t cols, int rank);
 nnc_status nmf_fit(const float *A, int64_t rows, int64_t cols, int rank, int iters, float *W, float *H,
                    double eps, double *rel_residual, void *workspace, size_t workspace_bytes,
                    void *stream);
+
+/*
+ * Several independent NMFs with a common column count in one call (Algorithm 2 factors
+ * every CP factor A^(i), i = 1..d, each with its own m_i): problem j factors A[j]
+ * (rows[j] x cols) with rank ranks[j] into W[j] (rows[j] x ranks[j]) and H[j]
+ * (ranks[j] x cols), in place.  Problems small enough for one workgroup's LDS run side by
+ * side in one launch; the others run one after another as in nmf_fit.  A, W, H: host arrays
+ * of nbatch device pointers; rows, ranks: host arrays.  rel_residuals: host, nullable,
+ * nbatch entries (syncs).  workspace: nmf_batched_workspace_bytes().
+ */
+size_t nmf_batched_workspace_bytes(int nbatch, const int64_t *rows, int64_t cols, const int *ranks);
+nnc_status nmf_fit_batched(int nbatch, const float *const *A, const int64_t *rows, int64_t cols,
+                           const int *ranks, int iters, float *const *W, float *const *H, double eps,
+                           double *rel_residuals, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
  * Lift: C_n = A_n B_n for every mode (substituting the core's CP into the Tucker model,

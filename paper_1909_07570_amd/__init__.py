@@ -57,7 +57,8 @@ EXPORTED = ["nnc_last_error", "nnc_device_ok", "nnc_set_timing", "nnc_ttm", "nnc
             "nntucker_workspace_bytes", "nntucker_fit", "nncp_workspace_bytes", "nncp_fit",
             "nncp_batched_workspace_bytes", "nncp_fit_batched", "nncandelinc_lift",
             "reconstruct_workspace_bytes", "reconstruct_residual", "reconstruct_sq_sums",
-            "nntucker_grad", "nncpx_workspace_bytes", "nncpx_fit", "nmf_workspace_bytes", "nmf_fit"]
+            "nntucker_grad", "nncpx_workspace_bytes", "nncpx_fit", "nmf_workspace_bytes", "nmf_fit",
+            "nmf_batched_workspace_bytes", "nmf_fit_batched"]
 
 _lib = None
 
@@ -96,6 +97,10 @@ def lib():
         L.nmf_workspace_bytes.restype = ctypes.c_size_t
         L.nmf_fit.argtypes = [_vp, _i64, _i64, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_double, _vp,
                               _vp, ctypes.c_size_t, _vp]
+        L.nmf_batched_workspace_bytes.argtypes = [ctypes.c_int, _i64p, _i64, ctypes.POINTER(ctypes.c_int)]
+        L.nmf_batched_workspace_bytes.restype = ctypes.c_size_t
+        L.nmf_fit_batched.argtypes = [ctypes.c_int, _vpp, _i64p, _i64, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                      _vpp, _vpp, ctypes.c_double, _dp, _vp, ctypes.c_size_t, _vp]
         L.nncandelinc_lift.argtypes = [ctypes.c_int, _i64p, _i64p, ctypes.c_int, _vpp, _vpp, _vpp, _vp]
         L.reconstruct_workspace_bytes.argtypes = [ctypes.c_int, _i64p, _i64p, ctypes.c_int]
         L.reconstruct_workspace_bytes.restype = ctypes.c_size_t
@@ -317,6 +322,25 @@ def nmf_fit(A: torch.Tensor, rank: int, iters: int, W: torch.Tensor, H: torch.Te
     return res.value if residual else None
 
 
+def nmf_fit_batched(A: Sequence[torch.Tensor], ranks: Sequence[int], iters: int, W: Sequence[torch.Tensor],
+                    H: Sequence[torch.Tensor], *, eps: float = 1e-12, residual: bool = True) -> Optional[List[float]]:
+    """Several NMFs A[j] ~ W[j] H[j] with a common column count, in place; returns the
+    relative residuals when `residual`."""
+    n = len(A)
+    for j in range(n):
+        _dev(A[j], "A[%d]" % j)
+        _dev(W[j], "W[%d]" % j)
+        _dev(H[j], "H[%d]" % j)
+    cols = int(A[0].shape[1])
+    rows = _dims([int(a.shape[0]) for a in A])
+    rk = (ctypes.c_int * n)(*[int(r) for r in ranks])
+    ws = _workspace(lib().nmf_batched_workspace_bytes(n, rows, cols, rk), A[0].device)
+    res = (ctypes.c_double * n)()
+    _check(lib().nmf_fit_batched(n, _ptrs(A), rows, cols, rk, int(iters), _ptrs(W), _ptrs(H), float(eps),
+                                 res if residual else None, ws.data_ptr(), ws.numel(), _stream()))
+    return [res[j] for j in range(n)] if residual else None
+
+
 def nncandelinc_alg2(X: torch.Tensor, rank: int, multirank: Sequence[int], cp_iters: int, nmf_iters: int,
                      cp_factors: Sequence[torch.Tensor], F: Sequence[torch.Tensor], B: Sequence[torch.Tensor],
                      *, x_fp32: Optional[torch.Tensor] = None, fp32_final_sweeps: int = 0,
@@ -326,8 +350,8 @@ def nncandelinc_alg2(X: torch.Tensor, rank: int, multirank: Sequence[int], cp_it
     nnCANDELINC model is C_n = F[n] B[n] (nncandelinc_lift).  Returns the nnCP report."""
     rep = nncpx_fit(X, rank, cp_iters, cp_factors, x_fp32=x_fp32, fp32_final_sweeps=fp32_final_sweeps,
                     eps=eps)
-    for n in range(X.dim()):
-        nmf_fit(cp_factors[n], int(multirank[n]), nmf_iters, F[n], B[n], eps=eps, residual=False)
+    nmf_fit_batched(list(cp_factors), [int(m) for m in multirank], nmf_iters, list(F), list(B), eps=eps,
+                    residual=False)
     return rep
 
 

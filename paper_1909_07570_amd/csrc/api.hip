@@ -1263,7 +1263,49 @@ size_t nmf_workspace_bytes(int64_t rows, int64_t cols, int rank) {
   Layout L;
   L.take(cp_ws(pb, 1, &rank, false).total);
   L.take(sizeof(float) * (size_t)(cols * rank));
+  L.take(sizeof(unsigned long long));
+  L.take(2 * sizeof(double));
   return L.off;
+}
+
+// One NMF on the one-workgroup kernel when it fits (clip counter and FP64 sums at the end of
+// the workspace), else as the two-way nnCP.
+static nnc_status nmf_one(const float *A, int64_t rows, int64_t cols, int rank, int iters, float *W,
+                          float *H, double eps, double *rel_residual, char *base, hipStream_t s) {
+  const int64_t dims[2] = {rows, cols};
+  const CpProblem pb = cp_problem(2, dims);
+  const CpWs w = cp_ws(pb, 1, &rank, false);
+  Layout L;
+  L.take(w.total);
+  float *Ht = (float *)(base + L.take(sizeof(float) * (size_t)(cols * rank)));
+  unsigned long long *clips = (unsigned long long *)(base + L.take(sizeof(unsigned long long)));
+  double *red = (double *)(base + L.take(2 * sizeof(double)));
+  if (rows < (1 << 30) && nmf_block_fits((int)rows, (int)cols, rank)) {
+    const int r32 = (int)rows, m32 = rank;
+    NNC_TRY(launch_fill_u64(clips, 1, 0ull, s));
+    NNC_TRY(launch_nmf_block(1, &A, &r32, (int)cols, &m32, iters, &W, &H, eps, clips,
+                             rel_residual ? red : nullptr, s));
+    if (rel_residual) {
+      double h[2];
+      NNC_HIP(hipMemcpyAsync(h, red, sizeof h, hipMemcpyDeviceToHost, s));
+      NNC_HIP(hipStreamSynchronize(s));
+      *rel_residual = rel_of(h);
+    }
+    return NNC_OK;
+  }
+  // A ~ W H is the two-way nonnegative CP with factors W (rows x rank) and H^T (cols x rank)
+  NNC_TRY(launch_transpose(H, rank, cols, Ht, s));
+  float *fac[2] = {W, Ht};
+  NNC_TRY(launch_fill_u64((unsigned long long *)(base + w.oClip), 1, 0ull, s));
+  NNC_TRY(launch_nncp(A, pb, 1, nullptr, rank, nullptr, fac, iters, eps,
+                      rel_residual ? (double *)(base + w.oRes) : nullptr,
+                      (unsigned long long *)(base + w.oClip), (float *)(base + w.oZ), 0, s));
+  NNC_TRY(launch_transpose(Ht, cols, rank, H, s));
+  if (rel_residual) {
+    NNC_HIP(hipMemcpyAsync(rel_residual, base + w.oRes, sizeof(double), hipMemcpyDeviceToHost, s));
+    NNC_HIP(hipStreamSynchronize(s));
+  }
+  return NNC_OK;
 }
 
 nnc_status nmf_fit(const float *A, int64_t rows, int64_t cols, int rank, int iters, float *W, float *H,
@@ -1278,26 +1320,88 @@ nnc_status nmf_fit(const float *A, int64_t rows, int64_t cols, int rank, int ite
   const size_t need = nmf_workspace_bytes(rows, cols, rank);
   if (!workspace || workspace_bytes < need)
     return fail(NNC_EWORKSPACE, "workspace has %zu bytes, need %zu", workspace ? workspace_bytes : 0, need);
-  const int64_t dims[2] = {rows, cols};
-  const CpProblem pb = cp_problem(2, dims);
-  const CpWs w = cp_ws(pb, 1, &rank, false);
+  NNC_TRY(nmf_one(A, rows, cols, rank, iters, W, H, eps > 0 ? eps : 1e-12, rel_residual,
+                  (char *)workspace, (hipStream_t)stream));
+  if (rel_residual && !std::isfinite(*rel_residual)) return fail(NNC_ENUMERIC, "non-finite NMF residual");
+  return NNC_OK;
+}
+
+size_t nmf_batched_workspace_bytes(int nbatch, const int64_t *rows, int64_t cols, const int *ranks) {
+  if (nbatch < 1 || !rows || !ranks) return 0;
+  size_t one = 0;
+  for (int j = 0; j < nbatch; ++j) {
+    const size_t b = nmf_workspace_bytes(rows[j], cols, ranks[j]);
+    if (b == 0) return 0;
+    one = std::max(one, b);
+  }
   Layout L;
-  L.take(w.total);
-  char *base = (char *)workspace;
-  float *Ht = (float *)(base + L.take(sizeof(float) * (size_t)(cols * rank)));
+  L.take(one);
+  L.take(sizeof(unsigned long long));
+  L.take(2 * sizeof(double) * (size_t)nbatch);
+  return L.off;
+}
+
+nnc_status nmf_fit_batched(int nbatch, const float *const *A, const int64_t *rows, int64_t cols,
+                           const int *ranks, int iters, float *const *W, float *const *H, double eps,
+                           double *rel_residuals, void *workspace, size_t workspace_bytes, void *stream) {
+  if (nbatch < 1 || !rows || !ranks) return fail(NNC_EINVAL, "nbatch %d < 1 or NULL rows / ranks", nbatch);
+  NNC_TRY(check_ptrs((const void *const *)A, nbatch, "A"));
+  NNC_TRY(check_ptrs((const void *const *)W, nbatch, "W"));
+  NNC_TRY(check_ptrs((const void *const *)H, nbatch, "H"));
+  if (cols < 1) return fail(NNC_EINVAL, "cols %lld < 1", (long long)cols);
+  for (int j = 0; j < nbatch; ++j) {
+    if (rows[j] < 1) return fail(NNC_EINVAL, "rows[%d] = %lld < 1", j, (long long)rows[j]);
+    if (ranks[j] < 1) return fail(NNC_EINVAL, "ranks[%d] = %d < 1", j, ranks[j]);
+    if (ranks[j] > 32) return fail(NNC_EUNSUPPORTED, "ranks[%d] = %d above 32", j, ranks[j]);
+  }
+  if (iters < 0) return fail(NNC_EINVAL, "iters = %d < 0", iters);
+  if (eps < 0) return fail(NNC_EINVAL, "eps < 0");
+  const size_t need = nmf_batched_workspace_bytes(nbatch, rows, cols, ranks);
+  if (!workspace || workspace_bytes < need)
+    return fail(NNC_EWORKSPACE, "workspace has %zu bytes, need %zu", workspace ? workspace_bytes : 0, need);
   hipStream_t s = (hipStream_t)stream;
-  // A ~ W H is the two-way nonnegative CP with factors W (rows x rank) and H^T (cols x rank)
-  NNC_TRY(launch_transpose(H, rank, cols, Ht, s));
-  float *fac[2] = {W, Ht};
-  NNC_TRY(launch_fill_u64((unsigned long long *)(base + w.oClip), 1, 0ull, s));
-  NNC_TRY(launch_nncp(A, pb, 1, nullptr, rank, nullptr, fac, iters, eps > 0 ? eps : 1e-12,
-                      rel_residual ? (double *)(base + w.oRes) : nullptr,
-                      (unsigned long long *)(base + w.oClip), (float *)(base + w.oZ), 0, s));
-  NNC_TRY(launch_transpose(Ht, cols, rank, H, s));
-  if (rel_residual) {
-    NNC_HIP(hipMemcpyAsync(rel_residual, base + w.oRes, sizeof(double), hipMemcpyDeviceToHost, s));
+  const double e = eps > 0 ? eps : 1e-12;
+  char *base = (char *)workspace;
+  Layout L;
+  size_t one = 0;
+  for (int j = 0; j < nbatch; ++j) one = std::max(one, nmf_workspace_bytes(rows[j], cols, ranks[j]));
+  L.take(one);
+  unsigned long long *clips = (unsigned long long *)(base + L.take(sizeof(unsigned long long)));
+  double *red = (double *)(base + L.take(2 * sizeof(double) * (size_t)nbatch));
+  NNC_TRY(launch_fill_u64(clips, 1, 0ull, s));
+  // the problems the one-workgroup kernel takes run side by side, kNmfMax per launch
+  std::vector<int> fast, slow;
+  for (int j = 0; j < nbatch; ++j)
+    (rows[j] < (1 << 30) && nmf_block_fits((int)rows[j], (int)cols, ranks[j]) ? fast : slow).push_back(j);
+  for (size_t i0 = 0; i0 < fast.size(); i0 += 8) {
+    const int n = (int)std::min<size_t>(8, fast.size() - i0);
+    const float *a[8];
+    float *w[8], *h[8];
+    int rr[8], mm[8];
+    for (int k = 0; k < n; ++k) {
+      const int j = fast[i0 + k];
+      a[k] = A[j];
+      w[k] = W[j];
+      h[k] = H[j];
+      rr[k] = (int)rows[j];
+      mm[k] = ranks[j];
+    }
+    NNC_TRY(launch_nmf_block(n, a, rr, (int)cols, mm, iters, w, h, e, clips,
+                             rel_residuals ? red + 2 * i0 : nullptr, s));  // by position in `fast`
+  }
+  std::vector<double> res(nbatch, 0.0);
+  for (int j : slow)
+    NNC_TRY(nmf_one(A[j], rows[j], cols, ranks[j], iters, W[j], H[j], e,
+                    rel_residuals ? &res[j] : nullptr, base, s));
+  if (rel_residuals) {
+    std::vector<double> h(2 * (size_t)nbatch);
+    NNC_HIP(hipMemcpyAsync(h.data(), red, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
     NNC_HIP(hipStreamSynchronize(s));
-    if (!std::isfinite(*rel_residual)) return fail(NNC_ENUMERIC, "non-finite NMF residual");
+    for (size_t i = 0; i < fast.size(); ++i) res[fast[i]] = rel_of(&h[2 * i]);
+    for (int j = 0; j < nbatch; ++j) {
+      rel_residuals[j] = res[j];
+      if (!std::isfinite(res[j])) return fail(NNC_ENUMERIC, "non-finite NMF residual (problem %d)", j);
+    }
   }
   return NNC_OK;
 }

@@ -9,6 +9,8 @@
 // where a runs over the modes of Y before mode n and c over those after it, and WA / WC are
 // the Khatri-Rao rows of those modes' factors.  The multiplicative update then uses
 // H_n = Hadamard product of the other factors' Grams (reading R1 applied to CP).
+#include <string.h>
+
 #include <algorithm>
 
 #include "nnc_internal.h"
@@ -249,6 +251,201 @@ nnc_status launch_transpose(const float *in, int64_t rows, int64_t cols, float *
   const int64_t n = rows * cols;
   if (n == 0) return NNC_OK;
   hipLaunchKernelGGL(transpose_k, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, rows, cols, out);
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+}  // namespace nnc
+
+namespace nnc {
+
+// =====================================================================================
+// NMF A ~ W H (Lee-Seung multiplicative sweeps, W first, then H) of up to kNmfMax
+// independent problems with a common column count, one workgroup per problem with A, W, H
+// and the small products in LDS:
+//   G = H H^T;  W <- W * (A H^T) / max(W G, eps);
+//   G = W^T W, P = W^T A (sums over the rows split in kNmfSplit ranges added in order);
+//   H <- H * P / max(G H, eps).
+// A is rows x cols, W rows x m, H m x cols; FP32 products, FP64 divisions, clipped
+// denominators counted; ||A - W H||^2 and ||A||^2 in FP64 at the end.
+// =====================================================================================
+constexpr int kNmfMax = 8;
+constexpr int kNmfThreads = 1024;
+constexpr int kNmfSplit = 4;
+constexpr int kNmfVals = 32;  // W entries per thread: rows * m <= kNmfThreads * kNmfVals
+constexpr size_t kNmfLdsMax = 159 * 1024;  // dynamic LDS; the static part (counters) stays below 1 KiB
+
+struct NmfArgs {
+  const float *A[kNmfMax];
+  float *W[kNmfMax];
+  float *H[kNmfMax];
+  int rows[kNmfMax], m[kNmfMax];
+  int cols, iters;
+  double eps;
+  unsigned long long *clips;
+  double *red;  // [problem][2] (||A - W H||^2, ||A||^2) or null
+};
+
+size_t nmf_lds_floats(int rows, int cols, int m) {
+  const size_t pairs = (size_t)kNmfSplit * (m * m + m * cols);
+  return (size_t)rows * cols + (size_t)rows * m + (size_t)m * cols + (size_t)m * m + (size_t)m * cols + pairs;
+}
+
+bool nmf_block_fits(int rows, int cols, int m) {
+  return cols <= 32 && m <= 32 && (int64_t)rows * m <= (int64_t)kNmfThreads * kNmfVals &&
+         m * cols <= kNmfThreads && nmf_lds_floats(rows, cols, m) * 4 <= kNmfLdsMax;
+}
+
+__global__ __launch_bounds__(kNmfThreads) void nmf_block_k(NmfArgs g) {
+  extern __shared__ __attribute__((aligned(16))) float sm[];
+  __shared__ unsigned int nclip;
+  __shared__ double dred[2][kNmfThreads / 64];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int N = g.rows[b], m = g.m[b], r = g.cols;
+  const float *__restrict__ Ag = g.A[b];
+  float *__restrict__ Wg = g.W[b];
+  float *__restrict__ Hg = g.H[b];
+  float *A = sm, *W = A + N * r, *H = W + N * m, *G = H + m * r, *P = G + m * m, *part = P + m * r;
+  for (int e = tid; e < N * r; e += kNmfThreads) A[e] = Ag[e];
+  for (int e = tid; e < N * m; e += kNmfThreads) W[e] = Wg[e];
+  for (int e = tid; e < m * r; e += kNmfThreads) H[e] = Hg[e];
+  if (tid == 0) nclip = 0;
+  __syncthreads();
+  unsigned int mine = 0;
+  const double eps = g.eps;
+  auto mu = [&](float x, float num, float den) {
+    double dd = (double)den;
+    if (dd < eps) {
+      dd = eps;
+      ++mine;
+    }
+    return (float)(((double)x * (double)num) / dd);
+  };
+  const int O = m * m + m * r;  // outputs of the row reduction
+  for (int it = 0; it < g.iters; ++it) {
+    for (int e = tid; e < m * m; e += kNmfThreads) {  // G = H H^T
+      const int j = e / m, k = e - (e / m) * m;
+      float s = 0.f;
+      for (int q = 0; q < r; ++q) s = fmaf(H[j * r + q], H[k * r + q], s);
+      G[e] = s;
+    }
+    __syncthreads();
+    float nv[kNmfVals];
+#pragma unroll
+    for (int u = 0; u < kNmfVals; ++u) {  // W <- W * (A H^T) / max(W G, eps)
+      const int e = tid + u * kNmfThreads;
+      if (e < N * m) {
+        const int i = e / m, j = e - (e / m) * m;
+        float num = 0.f, den = 0.f;
+        for (int q = 0; q < r; ++q) num = fmaf(A[i * r + q], H[j * r + q], num);
+        for (int k = 0; k < m; ++k) den = fmaf(W[i * m + k], G[k * m + j], den);
+        nv[u] = mu(W[e], num, den);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kNmfVals; ++u) {
+      const int e = tid + u * kNmfThreads;
+      if (e < N * m) W[e] = nv[u];
+    }
+    __syncthreads();
+    for (int pidx = tid; pidx < kNmfSplit * O; pidx += kNmfThreads) {  // W^T W and W^T A, split rows
+      const int sp = pidx / O, o = pidx - (pidx / O) * O;
+      const int i0 = N * sp / kNmfSplit, i1 = N * (sp + 1) / kNmfSplit;
+      float s = 0.f;
+      if (o < m * m) {
+        const int j = o / m, k = o - (o / m) * m;
+        for (int i = i0; i < i1; ++i) s = fmaf(W[i * m + j], W[i * m + k], s);
+      } else {
+        const int o2 = o - m * m, j = o2 / r, q = o2 - (o2 / r) * r;
+        for (int i = i0; i < i1; ++i) s = fmaf(W[i * m + j], A[i * r + q], s);
+      }
+      part[pidx] = s;
+    }
+    __syncthreads();
+    for (int o = tid; o < O; o += kNmfThreads) {
+      float s = part[o];
+      for (int sp = 1; sp < kNmfSplit; ++sp) s += part[sp * O + o];
+      if (o < m * m) G[o] = s;
+      else P[o - m * m] = s;
+    }
+    __syncthreads();
+    float hv = 0.f;  // H <- H * (W^T A) / max(W^T W H, eps)
+    if (tid < m * r) {
+      const int j = tid / r, q = tid - (tid / r) * r;
+      float den = 0.f;
+      for (int k = 0; k < m; ++k) den = fmaf(G[j * m + k], H[k * r + q], den);
+      hv = mu(H[tid], P[tid], den);
+    }
+    __syncthreads();
+    if (tid < m * r) H[tid] = hv;
+    __syncthreads();
+  }
+  for (int e = tid; e < N * m; e += kNmfThreads) Wg[e] = W[e];
+  for (int e = tid; e < m * r; e += kNmfThreads) Hg[e] = H[e];
+  if (mine) atomicAdd(&nclip, mine);
+  if (g.red) {  // ||A - W H||^2 and ||A||^2, FP64
+    double se = 0.0, sa = 0.0;
+    for (int e = tid; e < N * r; e += kNmfThreads) {
+      const int i = e / r, q = e - (e / r) * r;
+      float x = 0.f;
+      for (int k = 0; k < m; ++k) x = fmaf(W[i * m + k], H[k * r + q], x);
+      const double dlt = (double)A[e] - (double)x;
+      se += dlt * dlt;
+      sa += (double)A[e] * (double)A[e];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      se += __shfl_down(se, off);
+      sa += __shfl_down(sa, off);
+    }
+    if ((tid & 63) == 0) {
+      dred[0][tid >> 6] = se;
+      dred[1][tid >> 6] = sa;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (nclip) atomicAdd(g.clips, (unsigned long long)nclip);
+    if (g.red) {
+      double a = 0.0, c = 0.0;
+      for (int w = 0; w < kNmfThreads / 64; ++w) {
+        a += dred[0][w];
+        c += dred[1][w];
+      }
+      g.red[2 * b] = a;
+      g.red[2 * b + 1] = c;
+    }
+  }
+}
+
+nnc_status launch_nmf_block(int n, const float *const *A, const int *rows, int cols, const int *m,
+                            int iters, float *const *W, float *const *H, double eps,
+                            unsigned long long *clips, double *red, hipStream_t s) {
+  if (n < 1 || n > kNmfMax) return fail(NNC_EUNSUPPORTED, "nmf: %d problems per launch", n);
+  NmfArgs g;
+  memset(&g, 0, sizeof g);
+  size_t lds = 0;
+  for (int b = 0; b < n; ++b) {
+    if (!nmf_block_fits(rows[b], cols, m[b])) return NNC_EUNSUPPORTED;
+    g.A[b] = A[b];
+    g.W[b] = W[b];
+    g.H[b] = H[b];
+    g.rows[b] = rows[b];
+    g.m[b] = m[b];
+    lds = std::max(lds, nmf_lds_floats(rows[b], cols, m[b]) * 4);
+  }
+  g.cols = cols;
+  g.iters = iters;
+  g.eps = eps;
+  g.clips = clips;
+  g.red = red;
+  static bool raised = false;
+  if (!raised) {
+    NNC_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(nmf_block_k),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kNmfLdsMax));
+    raised = true;
+  }
+  hipLaunchKernelGGL(nmf_block_k, dim3(n), dim3(kNmfThreads), lds, s, g);
   NNC_HIP(hipGetLastError());
   return NNC_OK;
 }

@@ -161,6 +161,10 @@ int64_t diag_part_floats(int64_t A, int64_t Nt, int64_t C, int r);
 nnc_status launch_cp_mu(float *B, const float *M, const float *S, int d, int n, int64_t N, int r,
                         double eps, unsigned long long *clips, hipStream_t s);
 nnc_status launch_gram_block(const float *A, int64_t N, int r, float *S, hipStream_t s);
+bool nmf_block_fits(int rows, int cols, int m);
+nnc_status launch_nmf_block(int n, const float *const *A, const int *rows, int cols, const int *m,
+                            int iters, float *const *W, float *const *H, double eps,
+                            unsigned long long *clips, double *red, hipStream_t s);
 nnc_status launch_transpose(const float *in, int64_t rows, int64_t cols, float *out, hipStream_t s);
 nnc_status launch_sum_parts(const float *part, int nparts, int64_t n, float *out, hipStream_t s);
 

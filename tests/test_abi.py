@@ -138,6 +138,15 @@ def test_algorithm2_entry_points_validate():
     assert g(FAKE, 8, 3, 2, -2, FAKE, FAKE, 0.0, None, FAKE, 1 << 30, None) == nnc.NNC_EINVAL
     assert g(FAKE, 8, 3, 2, 5, FAKE, FAKE, -1.0, None, FAKE, 1 << 30, None) == nnc.NNC_EINVAL
     assert g(FAKE, 8, 3, 2, 5, FAKE, FAKE, 0.0, None, FAKE, 8, None) == nnc.NNC_EWORKSPACE
+    h = L.nmf_fit_batched
+    rk = (ctypes.c_int * 2)(2, 3)
+    assert L.nmf_batched_workspace_bytes(2, D(8, 9), 3, rk) > 0
+    assert h(0, _ptrs(2), D(8, 9), 3, rk, 5, _ptrs(2), _ptrs(2), 0.0, None, FAKE, 1 << 30, None) == nnc.NNC_EINVAL
+    assert h(2, _ptrs(2, 1), D(8, 9), 3, rk, 5, _ptrs(2), _ptrs(2), 0.0, None, FAKE, 1 << 30, None) == nnc.NNC_EINVAL
+    assert h(2, _ptrs(2), D(8, 0), 3, rk, 5, _ptrs(2), _ptrs(2), 0.0, None, FAKE, 1 << 30, None) == nnc.NNC_EINVAL
+    rk40 = (ctypes.c_int * 2)(2, 40)
+    assert h(2, _ptrs(2), D(8, 9), 3, rk40, 5, _ptrs(2), _ptrs(2), 0.0, None, FAKE, 1 << 30, None) == nnc.NNC_EUNSUPPORTED
+    assert h(2, _ptrs(2), D(8, 9), 3, rk, 5, _ptrs(2), _ptrs(2), 0.0, None, FAKE, 8, None) == nnc.NNC_EWORKSPACE
 
 
 def test_binding_rejects_cpu_tensors():

@@ -105,7 +105,8 @@ def test_nncpx_long_run_residual(dims, r):
     assert all(float(b.min()) >= 0 for b in B)
 
 
-@pytest.mark.parametrize("rows,cols,m", [(40, 3, 5), (512, 10, 20), (37, 9, 4), (200, 32, 32)])
+@pytest.mark.parametrize("rows,cols,m", [(40, 3, 5), (512, 10, 20), (37, 9, 4), (200, 32, 32),
+                                          (60, 40, 32)])  # the last one runs as a two-way nnCP
 def test_nmf_matches_oracle(rows, cols, m):
     nnc = need_gpu()
     rng = np.random.default_rng(rows * 100 + m)
@@ -122,6 +123,37 @@ def test_nmf_matches_oracle(rows, cols, m):
     res = nnc.nmf_fit(dev(A), m, 300, W, H)
     Wo, Ho, _ = oracle.nmf(A.astype(np.float64), W0, H0, 300)
     assert abs(res - np.linalg.norm(A - Wo @ Ho) / np.linalg.norm(A)) <= 1e-3
+
+
+def test_nmf_too_large_for_one_workgroup_is_unsupported():
+    """5000 x 10 at rank 8 fits neither the one-workgroup NMF kernel nor the nnCP kernel's LDS:
+    a clean NNC_EUNSUPPORTED, inputs untouched."""
+    nnc = need_gpu()
+    rng = np.random.default_rng(8)
+    A = dev(rng.random((5000, 10)).astype(np.float32))
+    W0 = rng.random((5000, 8)).astype(np.float32)
+    W, H = dev(W0), dev(rng.random((8, 10)).astype(np.float32))
+    with pytest.raises(nnc.NncError) as e:
+        nnc.nmf_fit(A, 8, 5, W, H)
+    assert e.value.status == nnc.NNC_EUNSUPPORTED
+    assert np.array_equal(host(W), W0.astype(np.float64))
+
+
+def test_nmf_batched_matches_single():
+    """Uneven problems in one call equal the single calls bit for bit, residuals included."""
+    nnc = need_gpu()
+    rng = np.random.default_rng(7)
+    shapes = [(40, 5), (512, 20), (1000, 12), (33, 3)]
+    A = [dev(rng.random((n, 10)).astype(np.float32)) for n, _ in shapes]
+    W0 = [rng.random((n, m)).astype(np.float32) for n, m in shapes]
+    H0 = [rng.random((m, 10)).astype(np.float32) for _, m in shapes]
+    W, H = [dev(w) for w in W0], [dev(h) for h in H0]
+    res = nnc.nmf_fit_batched(A, [m for _, m in shapes], 20, W, H)
+    for j, (n, m) in enumerate(shapes):
+        w, h = dev(W0[j]), dev(H0[j])
+        r1 = nnc.nmf_fit(A[j], m, 20, w, h)
+        assert torch.equal(w, W[j]) and torch.equal(h, H[j]), j
+        assert res[j] == r1, (j, res[j], r1)
 
 
 def test_alg2_end_to_end_40cubed():
