@@ -263,16 +263,17 @@ namespace nnc {
 // NMF A ~ W H (Lee-Seung multiplicative sweeps, W first, then H) of up to kNmfMax
 // independent problems with a common column count, one workgroup per problem with A, W, H
 // and the small products in LDS:
-//   G = H H^T;  W <- W * (A H^T) / max(W G, eps);
-//   G = W^T W, P = W^T A (sums over the rows split in kNmfSplit ranges added in order);
+//   G = H H^T;  W <- W * (A H^T) / max(W G, eps)          (a thread per row of W)
+//   G = W^T W, P = W^T A                                    (a thread per (column j of W,
+//                                                            row range), ranges added in order)
 //   H <- H * P / max(G H, eps).
 // A is rows x cols, W rows x m, H m x cols; FP32 products, FP64 divisions, clipped
-// denominators counted; ||A - W H||^2 and ||A||^2 in FP64 at the end.
+// denominators counted; ||A - W H||^2 and ||A||^2 in FP64 at the end.  RC / MC bound cols / m
+// (8, 16 or 32) so that a row of A, of W and its new values stay in registers.
 // =====================================================================================
 constexpr int kNmfMax = 8;
-constexpr int kNmfThreads = 1024;
-constexpr int kNmfSplit = 4;
-constexpr int kNmfVals = 32;  // W entries per thread: rows * m <= kNmfThreads * kNmfVals
+constexpr int kNmfThreads = 512;
+constexpr int kNmfSplitMax = 32;
 constexpr size_t kNmfLdsMax = 159 * 1024;  // dynamic LDS; the static part (counters) stays below 1 KiB
 
 struct NmfArgs {
@@ -286,16 +287,18 @@ struct NmfArgs {
   double *red;  // [problem][2] (||A - W H||^2, ||A||^2) or null
 };
 
+__host__ __device__ static inline int nmf_splits(int m) { return kNmfThreads / m < kNmfSplitMax ? kNmfThreads / m : kNmfSplitMax; }
+
 size_t nmf_lds_floats(int rows, int cols, int m) {
-  const size_t pairs = (size_t)kNmfSplit * (m * m + m * cols);
-  return (size_t)rows * cols + (size_t)rows * m + (size_t)m * cols + (size_t)m * m + (size_t)m * cols + pairs;
+  return (size_t)rows * (cols + m) + (size_t)m * cols * 2 + (size_t)m * m +
+         (size_t)nmf_splits(m) * m * (m + cols);
 }
 
 bool nmf_block_fits(int rows, int cols, int m) {
-  return cols <= 32 && m <= 32 && (int64_t)rows * m <= (int64_t)kNmfThreads * kNmfVals &&
-         m * cols <= kNmfThreads && nmf_lds_floats(rows, cols, m) * 4 <= kNmfLdsMax;
+  return cols <= 32 && m <= 32 && nmf_lds_floats(rows, cols, m) * 4 <= kNmfLdsMax;
 }
 
+template <int RC, int MC>
 __global__ __launch_bounds__(kNmfThreads) void nmf_block_k(NmfArgs g) {
   extern __shared__ __attribute__((aligned(16))) float sm[];
   __shared__ unsigned int nclip;
@@ -305,7 +308,8 @@ __global__ __launch_bounds__(kNmfThreads) void nmf_block_k(NmfArgs g) {
   const float *__restrict__ Ag = g.A[b];
   float *__restrict__ Wg = g.W[b];
   float *__restrict__ Hg = g.H[b];
-  float *A = sm, *W = A + N * r, *H = W + N * m, *G = H + m * r, *P = G + m * m, *part = P + m * r;
+  const int S = nmf_splits(m), O = m + r;
+  float *A = sm, *W = A + N * r, *H = W + N * m, *P = H + m * r, *G = P + m * r, *part = G + m * m;
   for (int e = tid; e < N * r; e += kNmfThreads) A[e] = Ag[e];
   for (int e = tid; e < N * m; e += kNmfThreads) W[e] = Wg[e];
   for (int e = tid; e < m * r; e += kNmfThreads) H[e] = Hg[e];
@@ -321,64 +325,108 @@ __global__ __launch_bounds__(kNmfThreads) void nmf_block_k(NmfArgs g) {
     }
     return (float)(((double)x * (double)num) / dd);
   };
-  const int O = m * m + m * r;  // outputs of the row reduction
   for (int it = 0; it < g.iters; ++it) {
-    for (int e = tid; e < m * m; e += kNmfThreads) {  // G = H H^T
+    // Loads below use clamped indices and zero the padded terms by selection instead of
+    // guarding them: guarded loads in unrolled loops become one branch and one full LDS
+    // wait each.
+    for (int e = tid; e < m * m; e += kNmfThreads) {  // G = H H^T (symmetric)
       const int j = e / m, k = e - (e / m) * m;
-      float s = 0.f;
-      for (int q = 0; q < r; ++q) s = fmaf(H[j * r + q], H[k * r + q], s);
-      G[e] = s;
+      float sacc = 0.f;
+#pragma unroll
+      for (int q = 0; q < RC; ++q) {
+        const int qq = q < r ? q : r - 1;
+        sacc = fmaf(q < r ? H[j * r + qq] : 0.f, H[k * r + qq], sacc);
+      }
+      G[e] = sacc;
     }
     __syncthreads();
-    float nv[kNmfVals];
+#pragma unroll 1
+    for (int i = tid; i < N; i += kNmfThreads) {  // row i of W
+      float a[RC], w[MC];
 #pragma unroll
-    for (int u = 0; u < kNmfVals; ++u) {  // W <- W * (A H^T) / max(W G, eps)
+      for (int q = 0; q < RC; ++q) {
+        const float v = A[i * r + (q < r ? q : r - 1)];
+        a[q] = q < r ? v : 0.f;
+      }
+#pragma unroll
+      for (int k = 0; k < MC; ++k) {
+        const float v = W[i * m + (k < m ? k : m - 1)];
+        w[k] = k < m ? v : 0.f;
+      }
+#pragma unroll 1
+      for (int j = 0; j < m; ++j) {
+        {
+          float num = 0.f, den = 0.f;
+#pragma unroll
+          for (int q = 0; q < RC; ++q) num = fmaf(a[q], H[j * r + (q < r ? q : r - 1)], num);
+#pragma unroll
+          for (int k = 0; k < MC; ++k)  // G[k][j] = G[j][k]
+            den = fmaf(w[k], G[j * m + (k < m ? k : m - 1)], den);
+          // the row belongs to this thread alone: entry j still holds its old value (also in w[])
+          W[i * m + j] = mu(W[i * m + j], num, den);
+        }
+      }
+    }
+    __syncthreads();
+    if (tid < S * m) {  // column j of W against rows [i0, i1) of W and A
+      const int j = tid % m, sp = tid / m;
+      const int i0 = N * sp / S, i1 = N * (sp + 1) / S;
+      float acc[MC + RC];
+#pragma unroll
+      for (int o = 0; o < MC + RC; ++o) acc[o] = 0.f;
+#pragma unroll 1
+      for (int i = i0; i < i1; ++i) {  // padded accumulators collect unused values
+        const float wj = W[i * m + j];
+#pragma unroll
+        for (int k = 0; k < MC; ++k) acc[k] = fmaf(wj, W[i * m + (k < m ? k : m - 1)], acc[k]);
+#pragma unroll
+        for (int q = 0; q < RC; ++q) acc[MC + q] = fmaf(wj, A[i * r + (q < r ? q : r - 1)], acc[MC + q]);
+      }
+      float *pp = part + (sp * m + j) * O;
+#pragma unroll
+      for (int k = 0; k < MC; ++k)
+        if (k < m) pp[k] = acc[k];
+#pragma unroll
+      for (int q = 0; q < RC; ++q)
+        if (q < r) pp[m + q] = acc[MC + q];
+    }
+    __syncthreads();
+    for (int e = tid; e < m * O; e += kNmfThreads) {
+      const int j = e / O, o = e - (e / O) * O;
+      float t = part[j * O + o];
+#pragma unroll
+      for (int sp = 1; sp < kNmfSplitMax; ++sp) {  // in order; adding 0 past S changes nothing
+        const float v = part[((sp < S ? sp : S - 1) * m + j) * O + o];
+        t += sp < S ? v : 0.f;
+      }
+      if (o < m) G[j * m + o] = t;
+      else P[j * r + (o - m)] = t;
+    }
+    __syncthreads();
+    // H <- H * (W^T A) / max(W^T W H, eps): m * cols <= 1024 entries, kHv per thread
+    constexpr int kHv = (32 * 32 + kNmfThreads - 1) / kNmfThreads;
+    float hv[kHv];
+#pragma unroll
+    for (int u = 0; u < kHv; ++u) {
       const int e = tid + u * kNmfThreads;
-      if (e < N * m) {
-        const int i = e / m, j = e - (e / m) * m;
-        float num = 0.f, den = 0.f;
-        for (int q = 0; q < r; ++q) num = fmaf(A[i * r + q], H[j * r + q], num);
-        for (int k = 0; k < m; ++k) den = fmaf(W[i * m + k], G[k * m + j], den);
-        nv[u] = mu(W[e], num, den);
+      hv[u] = 0.f;
+      if (e < m * r) {
+        const int j = e / r, q = e - (e / r) * r;
+        float den = 0.f;
+#pragma unroll
+        for (int k = 0; k < MC; ++k) {
+          const int kk = k < m ? k : m - 1;
+          den = fmaf(k < m ? G[j * m + kk] : 0.f, H[kk * r + q], den);
+        }
+        hv[u] = mu(H[e], P[e], den);
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < kNmfVals; ++u) {
+    for (int u = 0; u < kHv; ++u) {
       const int e = tid + u * kNmfThreads;
-      if (e < N * m) W[e] = nv[u];
+      if (e < m * r) H[e] = hv[u];
     }
-    __syncthreads();
-    for (int pidx = tid; pidx < kNmfSplit * O; pidx += kNmfThreads) {  // W^T W and W^T A, split rows
-      const int sp = pidx / O, o = pidx - (pidx / O) * O;
-      const int i0 = N * sp / kNmfSplit, i1 = N * (sp + 1) / kNmfSplit;
-      float s = 0.f;
-      if (o < m * m) {
-        const int j = o / m, k = o - (o / m) * m;
-        for (int i = i0; i < i1; ++i) s = fmaf(W[i * m + j], W[i * m + k], s);
-      } else {
-        const int o2 = o - m * m, j = o2 / r, q = o2 - (o2 / r) * r;
-        for (int i = i0; i < i1; ++i) s = fmaf(W[i * m + j], A[i * r + q], s);
-      }
-      part[pidx] = s;
-    }
-    __syncthreads();
-    for (int o = tid; o < O; o += kNmfThreads) {
-      float s = part[o];
-      for (int sp = 1; sp < kNmfSplit; ++sp) s += part[sp * O + o];
-      if (o < m * m) G[o] = s;
-      else P[o - m * m] = s;
-    }
-    __syncthreads();
-    float hv = 0.f;  // H <- H * (W^T A) / max(W^T W H, eps)
-    if (tid < m * r) {
-      const int j = tid / r, q = tid - (tid / r) * r;
-      float den = 0.f;
-      for (int k = 0; k < m; ++k) den = fmaf(G[j * m + k], H[k * r + q], den);
-      hv = mu(H[tid], P[tid], den);
-    }
-    __syncthreads();
-    if (tid < m * r) H[tid] = hv;
     __syncthreads();
   }
   for (int e = tid; e < N * m; e += kNmfThreads) Wg[e] = W[e];
@@ -439,13 +487,30 @@ nnc_status launch_nmf_block(int n, const float *const *A, const int *rows, int c
   g.eps = eps;
   g.clips = clips;
   g.red = red;
-  static bool raised = false;
-  if (!raised) {
-    NNC_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(nmf_block_k),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kNmfLdsMax));
-    raised = true;
-  }
-  hipLaunchKernelGGL(nmf_block_k, dim3(n), dim3(kNmfThreads), lds, s, g);
+  int mmax = 1;
+  for (int k = 0; k < n; ++k) mmax = std::max(mmax, m[k]);
+  const int RC = cols <= 8 ? 8 : (cols <= 16 ? 16 : 32), MC = mmax <= 8 ? 8 : (mmax <= 16 ? 16 : 32);
+#define NNC_NMF(RCV, MCV)                                                                         \
+  do {                                                                                            \
+    static bool raised = false;                                                                   \
+    if (!raised) {                                                                                \
+      NNC_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(nmf_block_k<RCV, MCV>),          \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kNmfLdsMax)); \
+      raised = true;                                                                              \
+    }                                                                                             \
+    hipLaunchKernelGGL((nmf_block_k<RCV, MCV>), dim3(n), dim3(kNmfThreads), lds, s, g);           \
+  } while (0)
+#define NNC_NMF_M(RCV)                \
+  do {                                \
+    if (MC == 8) NNC_NMF(RCV, 8);     \
+    else if (MC == 16) NNC_NMF(RCV, 16); \
+    else NNC_NMF(RCV, 32);            \
+  } while (0)
+  if (RC == 8) NNC_NMF_M(8);
+  else if (RC == 16) NNC_NMF_M(16);
+  else NNC_NMF_M(32);
+#undef NNC_NMF_M
+#undef NNC_NMF
   NNC_HIP(hipGetLastError());
   return NNC_OK;
 }
