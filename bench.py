@@ -238,6 +238,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="the oracle baseline runs whole sweeps until this much time has passed")
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--restarts", type=int, default=1000)
+    ap.add_argument("--restart-sweeps", type=int, default=5000)
     ap.add_argument("--kernel-only", action="store_true",
                     help="only launch the pass kernels and a calibration copy (counter runs)")
     ap.add_argument("--summarize", nargs="+", metavar="DIR",
@@ -364,6 +366,36 @@ def main():
                       "on FP32 X); NMF of each factor with m = %d, %d sweeps; lift; residuals"
                       % (rank, args.sweeps, args.fp32_final, R, args.cp_sweeps))
 
+    # ---- the Section 4.2 study: 1000 starts x 5000 sweeps per sub-fit, both algorithms, four
+    # assumed multiranks, on the 4x4x4 example with known nnCPD (rank 4)
+    from tests.paper_fixtures import examples
+    ex = examples()["ex5_rank_not_preserved_nn"]
+    At = [np.asarray(ex[k], dtype=np.float64) for k in ("A1", "A2", "A3")]
+    Xs = torch.from_numpy(np.einsum("ir,jr,kr->ijk", *At).astype(np.float32)).to(dev)
+    truth = [torch.from_numpy(a.astype(np.float32)).to(dev) for a in At]
+    study = {"config": "Section 4.2: the 4x4x4 example (nonnegative rank 4, unique nnCPD), %d random starts "
+                       "per (algorithm, multirank), %d sweeps per sub-fit, one launch per configuration"
+                       % (args.restarts, args.restart_sweeps), "runs": []}
+    for alg in (1, 2):
+        for m in ((3, 3, 3), (3, 4, 4), (4, 4, 4), (5, 5, 5)):
+            inits = torch.from_numpy(synth.init_restarts(SEED, alg, (4, 4, 4), m, 4, args.restarts)).to(dev)
+            nnc.nncandelinc_restarts(Xs, alg, m, 4, inits[:8], 10, 10, truth=truth)  # warm-up
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            res = nnc.nncandelinc_restarts(Xs, alg, m, 4, inits, args.restart_sweeps, args.restart_sweeps,
+                                           truth=truth)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+            rel = res.rel_errors.cpu().numpy()
+            cg = res.congruences.cpu().numpy()
+            study["runs"].append({"algorithm": alg, "multirank": list(m), "seconds": round(el, 4),
+                                  "starts_per_s": round(args.restarts / el, 1),
+                                  "rel_error": {"mean": float(rel.mean()), "median": float(np.median(rel)),
+                                                "std": float(rel.std()), "min": float(rel.min())},
+                                  "congruence": {"mean": float(cg.mean()), "std": float(cg.std())}})
+            log("study alg %d m %s: %.1f ms, rel mean %.4g median %.4g, congruence %.4f"
+                % (alg, m, el * 1e3, rel.mean(), np.median(rel), cg.mean()))
+
     # ---- per-launch timing of the two X-streaming contractions (same kernels, same launch
     # configuration as inside the fit), HIP events on the stream they are launched on.
     size = N ** 3
@@ -432,6 +464,19 @@ def main():
         b0x = [b.astype(np.float64) for b in synth.init_cp_factors(SEED, dims, rank)]
         oracle.nncp(X64, b0x, 1)
         el = time.perf_counter() - t
+        t = time.perf_counter()
+        done = 0
+        Xe = np.einsum("ir,jr,kr->ijk", *At)
+        inits1 = synth.init_restarts(SEED, 1, (4, 4, 4), (4, 4, 4), 4, 2)
+        for j in range(2):
+            parts = synth.unpack_restart(inits1[j].astype(np.float64), 1, (4, 4, 4), (4, 4, 4), 4)
+            oracle.restart_fit(Xe, 1, parts, args.restart_sweeps, args.restart_sweeps, truth=At)
+            done += 1
+        el = time.perf_counter() - t
+        study["cpu_baseline"] = {"value": round(done / el, 3), "unit": "starts/s (Algorithm 1, multirank [4,4,4])",
+                                 "cores": oracle.get_threads(), "kind": "oracle",
+                                 "sample": "%d starts of %d + %d sweeps, %.1f s" % (done, args.restart_sweeps,
+                                                                                   args.restart_sweeps, el)}
         alg2["cpu_baseline"] = {"value": round(1.0 / el, 5), "unit": "nnCP-of-X MU sweeps/s",
                                 "cores": oracle.get_threads(), "kind": "oracle",
                                 "sample": "1 FP64 nnCP sweep of the 512^3 tensor, rank %d, %.1f s" % (rank, el)}
@@ -464,6 +509,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "alg2": alg2,
+        "restart_study": study,
     }
     print(json.dumps(line), flush=True)
 

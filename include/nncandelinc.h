@@ -212,6 +212,35 @@ nnc_status nmf_fit_batched(int nbatch, const float *const *A, const int64_t *row
                            double *rel_residuals, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * The random-restart study of Section 4.2: `nrestarts` complete nnCANDELINC fits of one small
+ * 3-way tensor in a single launch, one workgroup per start, every fit in on-chip memory.
+ *   algorithm 1: nnTucker (multirank) for outer_iters sweeps, nnCP of the core (rank) for
+ *                inner_iters sweeps, lift C_n = A_n B_n.
+ *   algorithm 2: nnCP of X (rank) for outer_iters sweeps, NMF of each CP factor with
+ *                multirank[n] columns for inner_iters sweeps, lift C_n = W_n H_n.
+ * The multiplicative rules are those of nntucker_fit, nncp_fit and nmf_fit.  dims, multirank
+ * and rank are at most 8 (the study's tensor is 4 x 4 x 4).
+ *   X            device, dims[0] x dims[1] x dims[2] floats.
+ *   inits        device, nrestarts x nncandelinc_restart_init_floats() floats; per start:
+ *                algorithm 1: A_0, A_1, A_2 (dims[n] x multirank[n]), G (prod multirank),
+ *                             B_0, B_1, B_2 (multirank[n] x rank);
+ *                algorithm 2: B_0, B_1, B_2 (dims[n] x rank, CP of X), W_0, W_1, W_2
+ *                             (dims[n] x multirank[n]), H_0, H_1, H_2 (multirank[n] x rank).
+ *   true_factors host array of 3 device pointers (dims[n] x rank), nullable: the known CP
+ *                factors; congruences[j] is then the mean congruence of start j's rank-one
+ *                terms with them under the best matching (Section 4.1 scoring).
+ *   rel_errors   device, nrestarts doubles: ||X - cp(C)||_F / ||X||_F of every start.
+ *   lifted       device, nullable: nrestarts x (dims[0] + dims[1] + dims[2]) x rank floats.
+ *   clips        device, nullable: clipped denominators are added to *clips.
+ * nrestarts = 0 validates the sizes and returns NNC_OK without reading any buffer.
+ */
+int64_t nncandelinc_restart_init_floats(int algorithm, const int64_t *dims, const int64_t *multirank, int rank);
+nnc_status nncandelinc_restarts(const float *X, const int64_t *dims, int algorithm, const int64_t *multirank,
+                                int rank, int nrestarts, int outer_iters, int inner_iters, const float *inits,
+                                const float *const *true_factors, double eps, double *rel_errors,
+                                double *congruences, float *lifted, unsigned long long *clips, void *stream);
+
+/*
  * Lift: C_n = A_n B_n for every mode (substituting the core's CP into the Tucker model,
  * Section 2.1 lemma proof and Section 2.2).  tucker_factors[n]: dims[n] x multirank[n];
  * cp_factors[n]: multirank[n] x rank; out_factors[n]: dims[n] x rank.  Host arrays of

@@ -294,3 +294,16 @@ def nncandelinc_alg2(X, B0, F0, H0, cp_iters: int, nmf_iters: int, eps: float = 
     C = lift(F, B)
     return dict(Acp=Acp, F=F, B=B, C=C, clips=c1 + c2, cp_x_rel=cp_rel_residual(X, Acp),
                 cp_rel=cp_rel_residual(X, C))
+
+
+def restart_fit(X, alg: int, parts, outer: int, inner: int, truth=None, eps: float = 1e-12):
+    """One start of the Section 4.2 study: Algorithm 1 (parts = A_0..A_2, G, B_0..B_2) or
+    Algorithm 2 (parts = B_0..B_2, W_0..W_2, H_0..H_2) with `outer` sweeps of the first fit and
+    `inner` of the second; returns (relative error of the lifted CP, mean congruence with
+    `truth` or None, lifted factors)."""
+    if alg == 1:
+        out = nncandelinc(X, parts[3], parts[0:3], parts[4:7], outer, inner, eps)
+    else:
+        out = nncandelinc_alg2(X, parts[0:3], parts[3:6], parts[6:9], outer, inner, eps)
+    C = out["C"]
+    return out["cp_rel"], (mean_congruence(C, truth) if truth is not None else None), C

@@ -58,7 +58,8 @@ EXPORTED = ["nnc_last_error", "nnc_device_ok", "nnc_set_timing", "nnc_ttm", "nnc
             "nncp_batched_workspace_bytes", "nncp_fit_batched", "nncandelinc_lift",
             "reconstruct_workspace_bytes", "reconstruct_residual", "reconstruct_sq_sums",
             "nntucker_grad", "nncpx_workspace_bytes", "nncpx_fit", "nmf_workspace_bytes", "nmf_fit",
-            "nmf_batched_workspace_bytes", "nmf_fit_batched"]
+            "nmf_batched_workspace_bytes", "nmf_fit_batched", "nncandelinc_restart_init_floats",
+            "nncandelinc_restarts"]
 
 _lib = None
 
@@ -101,6 +102,10 @@ def lib():
         L.nmf_batched_workspace_bytes.restype = ctypes.c_size_t
         L.nmf_fit_batched.argtypes = [ctypes.c_int, _vpp, _i64p, _i64, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
                                       _vpp, _vpp, ctypes.c_double, _dp, _vp, ctypes.c_size_t, _vp]
+        L.nncandelinc_restart_init_floats.argtypes = [ctypes.c_int, _i64p, _i64p, ctypes.c_int]
+        L.nncandelinc_restart_init_floats.restype = ctypes.c_int64
+        L.nncandelinc_restarts.argtypes = [_vp, _i64p, ctypes.c_int, _i64p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int, _vp, _vpp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]
         L.nncandelinc_lift.argtypes = [ctypes.c_int, _i64p, _i64p, ctypes.c_int, _vpp, _vpp, _vpp, _vp]
         L.reconstruct_workspace_bytes.argtypes = [ctypes.c_int, _i64p, _i64p, ctypes.c_int]
         L.reconstruct_workspace_bytes.restype = ctypes.c_size_t
@@ -112,7 +117,7 @@ def lib():
                                     _vpp, _dp, _vp, ctypes.c_size_t, _vp]
         for name in EXPORTED:
             if name not in ("nnc_last_error", "nnc_device_ok", "nnc_set_timing") and \
-                    not name.endswith("_bytes"):
+                    not name.endswith("_bytes") and not name.endswith("_floats"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -339,6 +344,46 @@ def nmf_fit_batched(A: Sequence[torch.Tensor], ranks: Sequence[int], iters: int,
     _check(lib().nmf_fit_batched(n, _ptrs(A), rows, cols, rk, int(iters), _ptrs(W), _ptrs(H), float(eps),
                                  res if residual else None, ws.data_ptr(), ws.numel(), _stream()))
     return [res[j] for j in range(n)] if residual else None
+
+
+@dataclass
+class RestartResult:
+    rel_errors: "torch.Tensor"            # [nrestarts] float64 (device)
+    congruences: Optional["torch.Tensor"]  # [nrestarts] float64 (device) or None
+    lifted: Optional["torch.Tensor"]       # [nrestarts, sum(dims), rank] or None
+    clips: int
+
+
+def nncandelinc_restarts(X: torch.Tensor, algorithm: int, multirank: Sequence[int], rank: int,
+                         inits: torch.Tensor, outer_iters: int, inner_iters: int, *,
+                         truth: Optional[Sequence[torch.Tensor]] = None, eps: float = 1e-12,
+                         lifted: bool = False) -> RestartResult:
+    """The Section 4.2 study: inits.shape[0] complete fits of the small 3-way tensor X (Algorithm 1
+    or 2) in one launch, one workgroup per start (inits: [nrestarts, per-start floats])."""
+    _dev(X, "X")
+    _dev(inits, "inits")
+    if X.dim() != 3 or inits.dim() != 2:
+        raise NncError(NNC_EINVAL, "X must be 3-way and inits a [nrestarts, floats] matrix")
+    dims = _dims(X.shape)
+    mr = _dims(multirank)
+    per = int(lib().nncandelinc_restart_init_floats(int(algorithm), dims, mr, int(rank)))
+    if per <= 0 or inits.shape[1] != per:
+        raise NncError(NNC_EINVAL, "inits must have %d floats per start" % per)
+    n = int(inits.shape[0])
+    rel = torch.empty(n, dtype=torch.float64, device=X.device)
+    cong = torch.empty(n, dtype=torch.float64, device=X.device) if truth is not None else None
+    out = torch.empty(n, sum(X.shape), int(rank), dtype=torch.float32, device=X.device) if lifted else None
+    clips = torch.zeros(1, dtype=torch.int64, device=X.device)
+    tp = None
+    if truth is not None:
+        for k, t in enumerate(truth):
+            _dev(t, "truth[%d]" % k)
+        tp = _ptrs(truth)
+    _check(lib().nncandelinc_restarts(X.data_ptr(), dims, int(algorithm), mr, int(rank), n, int(outer_iters),
+                                      int(inner_iters), inits.data_ptr(), tp, float(eps), rel.data_ptr(),
+                                      cong.data_ptr() if cong is not None else None,
+                                      out.data_ptr() if out is not None else None, clips.data_ptr(), _stream()))
+    return RestartResult(rel, cong, out, int(clips.item()))
 
 
 def nncandelinc_alg2(X: torch.Tensor, rank: int, multirank: Sequence[int], cp_iters: int, nmf_iters: int,

@@ -1406,6 +1406,47 @@ nnc_status nmf_fit_batched(int nbatch, const float *const *A, const int64_t *row
   return NNC_OK;
 }
 
+int64_t nncandelinc_restart_init_floats(int algorithm, const int64_t *dims, const int64_t *multirank, int rank) {
+  if (!dims || !multirank || (algorithm != 1 && algorithm != 2) || rank < 1) return 0;
+  int N[3], M[3];
+  for (int n = 0; n < 3; ++n) {
+    if (dims[n] < 1 || multirank[n] < 1) return 0;
+    N[n] = (int)dims[n];
+    M[n] = (int)multirank[n];
+  }
+  return tiny_init_floats(algorithm, N, M, rank);
+}
+
+nnc_status nncandelinc_restarts(const float *X, const int64_t *dims, int algorithm, const int64_t *multirank,
+                                int rank, int nrestarts, int outer_iters, int inner_iters, const float *inits,
+                                const float *const *true_factors, double eps, double *rel_errors,
+                                double *congruences, float *lifted, unsigned long long *clips, void *stream) {
+  NNC_TRY(check_dims(3, dims, "dims"));
+  NNC_TRY(check_dims(3, multirank, "multirank"));
+  if (algorithm != 1 && algorithm != 2) return fail(NNC_EINVAL, "algorithm %d is neither 1 nor 2", algorithm);
+  if (rank < 1) return fail(NNC_EINVAL, "rank %d < 1", rank);
+  if (nrestarts < 0 || outer_iters < 0 || inner_iters < 0)
+    return fail(NNC_EINVAL, "negative restart or sweep count");
+  if (eps < 0) return fail(NNC_EINVAL, "eps < 0");
+  int N[3], M[3];
+  for (int n = 0; n < 3; ++n) {
+    if (dims[n] > 8 || multirank[n] > 8)
+      return fail(NNC_EUNSUPPORTED, "dims and multirank above 8 (mode %d)", n);
+    N[n] = (int)dims[n];
+    M[n] = (int)multirank[n];
+  }
+  if (rank > 8) return fail(NNC_EUNSUPPORTED, "rank %d above 8", rank);
+  if (nrestarts == 0) return NNC_OK;  // nothing to read or write
+  if (!X || !inits || !rel_errors) return fail(NNC_EINVAL, "X, inits and rel_errors must be non-NULL");
+  if (true_factors) {
+    NNC_TRY(check_ptrs((const void *const *)true_factors, 3, "true_factors"));
+    if (!congruences) return fail(NNC_EINVAL, "true_factors given without congruences");
+  }
+  return launch_tiny_candelinc(X, N, M, rank, algorithm, nrestarts, outer_iters, inner_iters, inits,
+                               true_factors, eps > 0 ? eps : 1e-12, rel_errors, true_factors ? congruences : nullptr,
+                               lifted, clips, (hipStream_t)stream);
+}
+
 // ---- tuner for the batched launch: threads per fit, timed on scratch factors, cached per
 // (core shape, rank multiset) for the life of the process.
 static std::mutex g_tune_mu;

@@ -165,6 +165,11 @@ bool nmf_block_fits(int rows, int cols, int m);
 nnc_status launch_nmf_block(int n, const float *const *A, const int *rows, int cols, const int *m,
                             int iters, float *const *W, float *const *H, double eps,
                             unsigned long long *clips, double *red, hipStream_t s);
+int64_t tiny_init_floats(int alg, const int *N, const int *M, int r);
+nnc_status launch_tiny_candelinc(const float *X, const int *N, const int *M, int r, int alg, int nres,
+                                 int outer, int inner, const float *inits, const float *const *truth,
+                                 double eps, double *rel, double *cong, float *fout,
+                                 unsigned long long *clips, hipStream_t s);
 nnc_status launch_transpose(const float *in, int64_t rows, int64_t cols, float *out, hipStream_t s);
 nnc_status launch_sum_parts(const float *part, int nparts, int64_t n, float *out, hipStream_t s);
 

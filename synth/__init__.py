@@ -19,7 +19,8 @@ generation, so any slice of a stream can be produced on its own.
 Stream ids (one per role):  planted factor n -> n;  zero mask of planted factor n ->
 16 + n;  additive noise -> 32;  initial core G0 -> 48;  initial Tucker factor n ->
 64 + n;  nnCP restart j, factor n -> 1024 + 16 j + n;  NMF of factor n (Algorithm 2):
-W0 -> 2048 + n, H0 -> 2064 + n.
+W0 -> 2048 + n, H0 -> 2064 + n;  restart j of the small-tensor study -> 4096 + j (one stream per
+start, laid out as unpack_restart() splits it).
 """
 
 from __future__ import annotations
@@ -40,6 +41,7 @@ STREAM_FACTOR0 = 64
 STREAM_CP_RESTART = 1024
 STREAM_NMF_W = 2048
 STREAM_NMF_H = 2064
+STREAM_RESTART = 4096
 
 
 def _mix64_int(z: int) -> int:
@@ -131,6 +133,32 @@ def init_nmf(seed: int, dims, ranks, rank: int, dtype=np.float32):
     H = [uniform_matrix(seed, STREAM_NMF_H + n, int(ranks[n]), int(rank)).astype(dtype)
          for n in range(len(dims))]
     return W, H
+
+
+def restart_init_sizes(alg: int, dims, multirank, rank: int):
+    """Shapes of the initial values of one start of the small-tensor study, in storage order:
+    Algorithm 1: A_n (dims[n] x m_n), G (m), B_n (m_n x r); Algorithm 2: B_n (dims[n] x r),
+    W_n (dims[n] x m_n), H_n (m_n x r)."""
+    d, m = [int(x) for x in dims], [int(x) for x in multirank]
+    if alg == 1:
+        return [(d[n], m[n]) for n in range(3)] + [tuple(m)] + [(m[n], rank) for n in range(3)]
+    return [(d[n], rank) for n in range(3)] + [(d[n], m[n]) for n in range(3)] + [(m[n], rank) for n in range(3)]
+
+
+def init_restarts(seed: int, alg: int, dims, multirank, rank: int, nres: int, dtype=np.float32):
+    """U[0,1) initial values of `nres` starts, one stream each, as an nres x per-start array."""
+    size = sum(int(np.prod(s)) for s in restart_init_sizes(alg, dims, multirank, rank))
+    return np.stack([uniform(seed, STREAM_RESTART + j, size) for j in range(nres)]).astype(dtype)
+
+
+def unpack_restart(vec, alg: int, dims, multirank, rank: int):
+    """Split one start's vector into its arrays (storage order of restart_init_sizes)."""
+    out, off = [], 0
+    for shp in restart_init_sizes(alg, dims, multirank, rank):
+        k = int(np.prod(shp))
+        out.append(np.asarray(vec[off:off + k]).reshape(shp))
+        off += k
+    return out
 
 
 def planted_factors(seed: int, dims, R: int, zero_prob: float = 0.0):

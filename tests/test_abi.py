@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     src = open(os.path.join(ROOT, "include", "nncandelinc.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\*?\s*([a-z_0-9]+)\s*\(", src, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", src, flags=re.M)))
 
 
 def test_every_declared_symbol_is_exported():
@@ -147,6 +147,37 @@ def test_algorithm2_entry_points_validate():
     rk40 = (ctypes.c_int * 2)(2, 40)
     assert h(2, _ptrs(2), D(8, 9), 3, rk40, 5, _ptrs(2), _ptrs(2), 0.0, None, FAKE, 1 << 30, None) == nnc.NNC_EUNSUPPORTED
     assert h(2, _ptrs(2), D(8, 9), 3, rk, 5, _ptrs(2), _ptrs(2), 0.0, None, FAKE, 8, None) == nnc.NNC_EWORKSPACE
+
+
+def test_restart_study_validates():
+    L = nnc.lib()
+    assert L.nncandelinc_restart_init_floats(1, D(4, 4, 4), D(4, 4, 4), 4) == 160
+    assert L.nncandelinc_restart_init_floats(2, D(4, 4, 4), D(3, 4, 4), 4) == 136
+    assert L.nncandelinc_restart_init_floats(3, D(4, 4, 4), D(3, 4, 4), 4) == 0
+    f = L.nncandelinc_restarts
+    ok = dict(X=FAKE, dims=D(4, 4, 4), alg=1, m=D(3, 3, 3), r=4, n=8, o=10, i=10, inits=FAKE, truth=None,
+              eps=0.0, rel=FAKE, cong=None, lifted=None, clips=None)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return f(a["X"], a["dims"], a["alg"], a["m"], a["r"], a["n"], a["o"], a["i"], a["inits"], a["truth"],
+                 a["eps"], a["rel"], a["cong"], a["lifted"], a["clips"], None)
+    assert call(X=None) == nnc.NNC_EINVAL
+    assert call(rel=None) == nnc.NNC_EINVAL
+    assert call(alg=3) == nnc.NNC_EINVAL
+    assert call(r=0) == nnc.NNC_EINVAL
+    assert call(n=-1) == nnc.NNC_EINVAL
+    assert call(o=-1) == nnc.NNC_EINVAL
+    assert call(eps=-1.0) == nnc.NNC_EINVAL
+    assert call(dims=D(4, 0, 4)) == nnc.NNC_EINVAL
+    assert call(truth=_ptrs(3)) == nnc.NNC_EINVAL          # truth without congruences
+    assert call(truth=_ptrs(3, 1), cong=FAKE) == nnc.NNC_EINVAL
+    assert call(dims=D(9, 4, 4)) == nnc.NNC_EUNSUPPORTED
+    assert call(m=D(3, 9, 3)) == nnc.NNC_EUNSUPPORTED
+    assert call(r=9) == nnc.NNC_EUNSUPPORTED
+    assert call(n=0) == nnc.NNC_OK                        # nothing to launch
+    assert call(n=0, X=None, inits=None, rel=None) == nnc.NNC_OK
+    assert call(n=0, dims=D(9, 4, 4)) == nnc.NNC_EUNSUPPORTED
 
 
 def test_binding_rejects_cpu_tensors():

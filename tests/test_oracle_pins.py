@@ -440,3 +440,43 @@ def test_alg2_fixed_point_at_exact_integer_factorizations():
         assert np.array_equal(out["F"][k], F[k])
         assert np.array_equal(out["B"][k], B[k])
     assert out["cp_rel"] == 0.0 and out["clips"] == 0
+
+
+def test_mean_congruence_brute_force_and_invariances():
+    """Mean congruence (Section 4.1 scoring): 1 for a model compared with itself, invariant
+    under a permutation of its components and under a positive rescaling of a factor column;
+    brute force over all matchings written out here for a random pair."""
+    rng = _rng(24)
+    P = [rng.random((4, 3)) for _ in range(3)]
+    assert abs(oracle.mean_congruence(P, P) - 1.0) <= 1e-14
+    perm = [2, 0, 1]
+    Pp = [p[:, perm] * np.array([1.0, 3.0, 0.5]) for p in P]
+    assert abs(oracle.mean_congruence(P, Pp) - 1.0) <= 1e-14
+    Q = [rng.random((4, 3)) for _ in range(3)]
+    best = -1.0
+    for pm in itertools.permutations(range(3)):
+        s = 0.0
+        for i in range(3):
+            c = 1.0
+            for p, q in zip(P, Q):
+                a, b = p[:, i], q[:, pm[i]]
+                c *= a @ b / np.sqrt((a @ a) * (b @ b))
+            s += c
+        best = max(best, s / 3)
+    assert abs(oracle.mean_congruence(P, Q) - best) <= 1e-14
+
+
+def test_restart_fit_exact_fixed_points_of_the_example():
+    """The Section 4.2 tensor (the 4x4x4 example with unique nnCPD): its exact factorizations are
+    fixed points of both algorithms (relative error 0, congruence 1)."""
+    e = examples()["ex5_rank_not_preserved_nn"]
+    A = [arr(e["A1"]), arr(e["A2"]), arr(e["A3"])]
+    X = oracle.cp_full(A)
+    D = np.zeros((4, 4, 4))
+    for i in range(4):
+        D[i, i, i] = 1.0
+    I4 = np.eye(4)
+    rel, cong, C = oracle.restart_fit(X, 1, A + [D] + [I4] * 3, 20, 20, truth=A)
+    assert rel == 0.0 and abs(cong - 1.0) <= 1e-14 and all(np.array_equal(c, a) for c, a in zip(C, A))
+    rel, cong, C = oracle.restart_fit(X, 2, A + A + [I4] * 3, 20, 20, truth=A)
+    assert rel == 0.0 and abs(cong - 1.0) <= 1e-14 and all(np.array_equal(c, a) for c, a in zip(C, A))
