@@ -289,13 +289,24 @@ struct NmfArgs {
 
 __host__ __device__ static inline int nmf_splits(int m) { return kNmfThreads / m < kNmfSplitMax ? kNmfThreads / m : kNmfSplitMax; }
 
+static inline int pad4(int x) { return (x + 3) & ~3; }
+
+// LDS floats: A [rows][rp] | W [rows][mp] | H [m][rp] | P [m][rp] | G [m][mp] |
+// partial sums [splits][m][mp + rp]   (rp, mp: cols and m rounded up to 4, zero padding)
 size_t nmf_lds_floats(int rows, int cols, int m) {
-  return (size_t)rows * (cols + m) + (size_t)m * cols * 2 + (size_t)m * m +
-         (size_t)nmf_splits(m) * m * (m + cols);
+  const size_t rp = pad4(cols), mp = pad4(m);
+  return (size_t)rows * (rp + mp) + 2 * (size_t)m * rp + (size_t)m * mp + (size_t)nmf_splits(m) * m * (mp + rp);
 }
 
 bool nmf_block_fits(int rows, int cols, int m) {
   return cols <= 32 && m <= 32 && nmf_lds_floats(rows, cols, m) * 4 <= kNmfLdsMax;
+}
+
+static __device__ inline float dot4(float4 a, float4 b, float s) {
+  s = fmaf(a.x, b.x, s);
+  s = fmaf(a.y, b.y, s);
+  s = fmaf(a.z, b.z, s);
+  return fmaf(a.w, b.w, s);
 }
 
 template <int RC, int MC>
@@ -303,16 +314,29 @@ __global__ __launch_bounds__(kNmfThreads) void nmf_block_k(NmfArgs g) {
   extern __shared__ __attribute__((aligned(16))) float sm[];
   __shared__ unsigned int nclip;
   __shared__ double dred[2][kNmfThreads / 64];
+  constexpr int R4 = RC / 4, M4 = MC / 4;
   const int b = blockIdx.x, tid = threadIdx.x;
   const int N = g.rows[b], m = g.m[b], r = g.cols;
+  const int rp = (r + 3) & ~3, mp = (m + 3) & ~3, rq = rp / 4, mq = mp / 4;
   const float *__restrict__ Ag = g.A[b];
   float *__restrict__ Wg = g.W[b];
   float *__restrict__ Hg = g.H[b];
-  const int S = nmf_splits(m), O = m + r;
-  float *A = sm, *W = A + N * r, *H = W + N * m, *P = H + m * r, *G = P + m * r, *part = G + m * m;
-  for (int e = tid; e < N * r; e += kNmfThreads) A[e] = Ag[e];
-  for (int e = tid; e < N * m; e += kNmfThreads) W[e] = Wg[e];
-  for (int e = tid; e < m * r; e += kNmfThreads) H[e] = Hg[e];
+  const int S = nmf_splits(m), O = mp + rp;
+  float *A = sm, *W = A + N * rp, *H = W + N * mp, *P = H + m * rp, *G = P + m * rp, *part = G + m * mp;
+  for (int e = tid; e < N * rp; e += kNmfThreads) {
+    const int i = e / rp, q = e - (e / rp) * rp;
+    A[e] = q < r ? Ag[i * r + q] : 0.f;
+  }
+  for (int e = tid; e < N * mp; e += kNmfThreads) {
+    const int i = e / mp, k = e - (e / mp) * mp;
+    W[e] = k < m ? Wg[i * m + k] : 0.f;
+  }
+  for (int e = tid; e < m * rp; e += kNmfThreads) {
+    const int j = e / rp, q = e - (e / rp) * rp;
+    H[e] = q < r ? Hg[j * r + q] : 0.f;
+    P[e] = 0.f;
+  }
+  for (int e = tid; e < m * mp; e += kNmfThreads) G[e] = 0.f;  // the padding stays zero
   if (tid == 0) nclip = 0;
   __syncthreads();
   unsigned int mine = 0;
@@ -325,82 +349,99 @@ __global__ __launch_bounds__(kNmfThreads) void nmf_block_k(NmfArgs g) {
     }
     return (float)(((double)x * (double)num) / dd);
   };
+  const float4 *A4 = reinterpret_cast<const float4 *>(A);
+  const float4 *H4 = reinterpret_cast<const float4 *>(H);
+  const float4 *G4 = reinterpret_cast<const float4 *>(G);
+  const float4 *W4 = reinterpret_cast<const float4 *>(W);
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
   for (int it = 0; it < g.iters; ++it) {
-    // Loads below use clamped indices and zero the padded terms by selection instead of
-    // guarding them: guarded loads in unrolled loops become one branch and one full LDS
-    // wait each.
+    // Rows are read four entries at a time.  Loops run to the compile-time bounds RC / MC
+    // with the group index clamped; a group past the row is multiplied by zeros (the
+    // padded registers) or replaced by zeros, never guarded by a branch.
     for (int e = tid; e < m * m; e += kNmfThreads) {  // G = H H^T (symmetric)
       const int j = e / m, k = e - (e / m) * m;
       float sacc = 0.f;
 #pragma unroll
-      for (int q = 0; q < RC; ++q) {
-        const int qq = q < r ? q : r - 1;
-        sacc = fmaf(q < r ? H[j * r + qq] : 0.f, H[k * r + qq], sacc);
+      for (int q4 = 0; q4 < R4; ++q4) {
+        const int qq = q4 < rq ? q4 : rq - 1;
+        const float4 hj = H4[j * rq + qq];
+        sacc = dot4(q4 < rq ? hj : z4, H4[k * rq + qq], sacc);
       }
-      G[e] = sacc;
+      G[j * mp + k] = sacc;
     }
     __syncthreads();
 #pragma unroll 1
     for (int i = tid; i < N; i += kNmfThreads) {  // row i of W
-      float a[RC], w[MC];
+      float4 a[R4], w[M4];
 #pragma unroll
-      for (int q = 0; q < RC; ++q) {
-        const float v = A[i * r + (q < r ? q : r - 1)];
-        a[q] = q < r ? v : 0.f;
+      for (int q4 = 0; q4 < R4; ++q4) {
+        const float4 v = A4[i * rq + (q4 < rq ? q4 : rq - 1)];
+        a[q4] = q4 < rq ? v : z4;
       }
 #pragma unroll
-      for (int k = 0; k < MC; ++k) {
-        const float v = W[i * m + (k < m ? k : m - 1)];
-        w[k] = k < m ? v : 0.f;
+      for (int k4 = 0; k4 < M4; ++k4) {
+        const float4 v = W4[i * mq + (k4 < mq ? k4 : mq - 1)];
+        w[k4] = k4 < mq ? v : z4;
       }
 #pragma unroll 1
       for (int j = 0; j < m; ++j) {
-        {
-          float num = 0.f, den = 0.f;
+        float num = 0.f, den = 0.f;
 #pragma unroll
-          for (int q = 0; q < RC; ++q) num = fmaf(a[q], H[j * r + (q < r ? q : r - 1)], num);
+        for (int q4 = 0; q4 < R4; ++q4) num = dot4(a[q4], H4[j * rq + (q4 < rq ? q4 : rq - 1)], num);
 #pragma unroll
-          for (int k = 0; k < MC; ++k)  // G[k][j] = G[j][k]
-            den = fmaf(w[k], G[j * m + (k < m ? k : m - 1)], den);
-          // the row belongs to this thread alone: entry j still holds its old value (also in w[])
-          W[i * m + j] = mu(W[i * m + j], num, den);
-        }
+        for (int k4 = 0; k4 < M4; ++k4)  // G[k][j] = G[j][k]
+          den = dot4(w[k4], G4[j * mq + (k4 < mq ? k4 : mq - 1)], den);
+        // the row belongs to this thread alone: entry j still holds its old value
+        W[i * mp + j] = mu(W[i * mp + j], num, den);
       }
     }
     __syncthreads();
     if (tid < S * m) {  // column j of W against rows [i0, i1) of W and A
       const int j = tid % m, sp = tid / m;
       const int i0 = N * sp / S, i1 = N * (sp + 1) / S;
-      float acc[MC + RC];
+      float4 acc[M4 + R4];
 #pragma unroll
-      for (int o = 0; o < MC + RC; ++o) acc[o] = 0.f;
+      for (int o = 0; o < M4 + R4; ++o) acc[o] = z4;
 #pragma unroll 1
-      for (int i = i0; i < i1; ++i) {  // padded accumulators collect unused values
-        const float wj = W[i * m + j];
+      for (int i = i0; i < i1; ++i) {  // accumulators past the row collect unused values
+        const float wj = W[i * mp + j];
 #pragma unroll
-        for (int k = 0; k < MC; ++k) acc[k] = fmaf(wj, W[i * m + (k < m ? k : m - 1)], acc[k]);
+        for (int k4 = 0; k4 < M4; ++k4) {
+          const float4 v = W4[i * mq + (k4 < mq ? k4 : mq - 1)];
+          acc[k4].x = fmaf(wj, v.x, acc[k4].x);
+          acc[k4].y = fmaf(wj, v.y, acc[k4].y);
+          acc[k4].z = fmaf(wj, v.z, acc[k4].z);
+          acc[k4].w = fmaf(wj, v.w, acc[k4].w);
+        }
 #pragma unroll
-        for (int q = 0; q < RC; ++q) acc[MC + q] = fmaf(wj, A[i * r + (q < r ? q : r - 1)], acc[MC + q]);
+        for (int q4 = 0; q4 < R4; ++q4) {
+          const float4 v = A4[i * rq + (q4 < rq ? q4 : rq - 1)];
+          acc[M4 + q4].x = fmaf(wj, v.x, acc[M4 + q4].x);
+          acc[M4 + q4].y = fmaf(wj, v.y, acc[M4 + q4].y);
+          acc[M4 + q4].z = fmaf(wj, v.z, acc[M4 + q4].z);
+          acc[M4 + q4].w = fmaf(wj, v.w, acc[M4 + q4].w);
+        }
       }
-      float *pp = part + (sp * m + j) * O;
+      float4 *pp = reinterpret_cast<float4 *>(part + (sp * m + j) * O);
 #pragma unroll
-      for (int k = 0; k < MC; ++k)
-        if (k < m) pp[k] = acc[k];
+      for (int k4 = 0; k4 < M4; ++k4)
+        if (k4 < mq) pp[k4] = acc[k4];
 #pragma unroll
-      for (int q = 0; q < RC; ++q)
-        if (q < r) pp[m + q] = acc[MC + q];
+      for (int q4 = 0; q4 < R4; ++q4)
+        if (q4 < rq) pp[mq + q4] = acc[M4 + q4];
     }
     __syncthreads();
-    for (int e = tid; e < m * O; e += kNmfThreads) {
-      const int j = e / O, o = e - (e / O) * O;
-      float t = part[j * O + o];
+    for (int e = tid; e < m * (m + r); e += kNmfThreads) {  // splits added in order
+      const int j = e / (m + r), o = e - (e / (m + r)) * (m + r);
+      const int col = o < m ? o : mp + (o - m);
+      float t = part[j * O + col];
 #pragma unroll
-      for (int sp = 1; sp < kNmfSplitMax; ++sp) {  // in order; adding 0 past S changes nothing
-        const float v = part[((sp < S ? sp : S - 1) * m + j) * O + o];
+      for (int sp = 1; sp < kNmfSplitMax; ++sp) {  // adding 0 past S changes nothing
+        const float v = part[((sp < S ? sp : S - 1) * m + j) * O + col];
         t += sp < S ? v : 0.f;
       }
-      if (o < m) G[j * m + o] = t;
-      else P[j * r + (o - m)] = t;
+      if (o < m) G[j * mp + o] = t;
+      else P[j * rp + (o - m)] = t;
     }
     __syncthreads();
     // H <- H * (W^T A) / max(W^T W H, eps): m * cols <= 1024 entries, kHv per thread
@@ -416,31 +457,32 @@ __global__ __launch_bounds__(kNmfThreads) void nmf_block_k(NmfArgs g) {
 #pragma unroll
         for (int k = 0; k < MC; ++k) {
           const int kk = k < m ? k : m - 1;
-          den = fmaf(k < m ? G[j * m + kk] : 0.f, H[kk * r + q], den);
+          den = fmaf(k < m ? G[j * mp + kk] : 0.f, H[kk * rp + q], den);
         }
-        hv[u] = mu(H[e], P[e], den);
+        hv[u] = mu(H[j * rp + q], P[j * rp + q], den);
       }
     }
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < kHv; ++u) {
       const int e = tid + u * kNmfThreads;
-      if (e < m * r) H[e] = hv[u];
+      if (e < m * r) H[(e / r) * rp + e % r] = hv[u];
     }
     __syncthreads();
   }
-  for (int e = tid; e < N * m; e += kNmfThreads) Wg[e] = W[e];
-  for (int e = tid; e < m * r; e += kNmfThreads) Hg[e] = H[e];
+  for (int e = tid; e < N * m; e += kNmfThreads) Wg[e] = W[(e / m) * mp + e % m];
+  for (int e = tid; e < m * r; e += kNmfThreads) Hg[e] = H[(e / r) * rp + e % r];
   if (mine) atomicAdd(&nclip, mine);
   if (g.red) {  // ||A - W H||^2 and ||A||^2, FP64
     double se = 0.0, sa = 0.0;
     for (int e = tid; e < N * r; e += kNmfThreads) {
       const int i = e / r, q = e - (e / r) * r;
       float x = 0.f;
-      for (int k = 0; k < m; ++k) x = fmaf(W[i * m + k], H[k * r + q], x);
-      const double dlt = (double)A[e] - (double)x;
+      for (int k = 0; k < m; ++k) x = fmaf(W[i * mp + k], H[k * rp + q], x);
+      const float av = A[i * rp + q];
+      const double dlt = (double)av - (double)x;
       se += dlt * dlt;
-      sa += (double)A[e] * (double)A[e];
+      sa += (double)av * (double)av;
     }
     for (int off = 32; off > 0; off >>= 1) {
       se += __shfl_down(se, off);
