@@ -41,6 +41,9 @@ def log(*a):
 PASS_SOURCES = ["paper_1909_07570_amd/csrc/pass_kernels.hip", "paper_1909_07570_amd/csrc/kernels.hip"]
 COUNTERS = os.path.join(ROOT, "profiles", "pass_counters_512cubed.json")
 N_COPY = 128 << 20
+# The R = 20 (two 16-wide rank tiles) instantiations of the four pass kernels, X bytes per entry.
+PASS_BYTES = (("ttm_last_lds_k<true, 2", 2), ("ttm_mid_lds_k<2>", 2),
+              ("ttm_last_lds_k<false, 2", 4), ("ttm_mid_lds_f32_k<2", 4))
 
 
 def sources_sha():
@@ -98,8 +101,10 @@ def summarize(args):
              "python -u bench.py --steps 1 --warmup 0 --no-cpu", "",
              "The step runs 500 nnTucker sweeps per form (BF16 form: 480 on BF16 X + 20 on FP32 X),",
              "nnCP rank 10 x 300 sweeps, lift and residuals; then Algorithm 2 twice per form (nnCP of",
-             "X rank 10 x 500 sweeps, NMF of each factor, lift); bench.py then times each X-streaming",
-             "pass kernel over 23 launches and runs a 20-sweep eager fit.", "",
+             "X rank 10 x 500 sweeps with the R = 10 pass instantiations, NMF of each factor, lift), the",
+             "Section 4.2 study (tiny_candelinc_k: 8 launches of 1000 starts x 5000 + 5000 sweeps, plus",
+             "8 warm-up launches); bench.py then times each X-streaming pass kernel over 23 launches",
+             "and runs a 20-sweep eager fit.", "",
              "| kernel | calls | total ms | avg us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
     with open(_find(prof_dir, "kernel_stats.csv")) as f:
         rows = list(csv.DictReader(f))
@@ -140,8 +145,7 @@ def summarize(args):
     res = {"source_sha": sources_sha(), "copy_fetch_kib": copy_f, "copy_write_kib": copy_w,
            "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
     alg = {}
-    for key, esz in (("ttm_last_lds_k<true", 2), ("ttm_mid_lds_k", 2),
-                     ("ttm_last_lds_k<false", 4), ("ttm_mid_lds_f32_k", 4)):
+    for key, esz in PASS_BYTES:
         fk, wk = pick(fetch, key), pick(write, key)
         if fk is None or wk is None:
             continue
@@ -178,8 +182,8 @@ def summarize(args):
     print(json.dumps(res, indent=1))
 
 
-PASS_KEYS = (("ttm_last_lds_k<true", "bf16"), ("ttm_mid_lds_k", "bf16"),
-             ("ttm_last_lds_k<false", "f32"), ("ttm_mid_lds_f32_k", "f32"))
+PASS_KEYS = (("ttm_last_lds_k<true, 2", "bf16"), ("ttm_mid_lds_k<2>", "bf16"),
+             ("ttm_last_lds_k<false, 2", "f32"), ("ttm_mid_lds_f32_k<2", "f32"))
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}
 
 
@@ -435,7 +439,7 @@ def main():
     traffic = None
     if os.path.exists(COUNTERS):
         cnt = json.load(open(COUNTERS))
-        key = {"ttm_last_bf16": "ttm_last_lds_k<true", "ttm_mid_bf16": "ttm_mid_lds_k"}[dom]
+        key = {"ttm_last_bf16": "ttm_last_lds_k<true, 2", "ttm_mid_bf16": "ttm_mid_lds_k<2>"}[dom]
         if cnt.get("source_sha") == sources_sha() and key in cnt.get("kernels", {}):
             traffic = round(cnt["kernels"][key]["traffic_bytes"])
     roofline = {"bound": "hbm", "achieved": round(dk["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
