@@ -95,10 +95,11 @@ def summarize(args):
     if len(args.summarize) not in (3, 5):
         raise SystemExit("--summarize takes PROF FETCH WRITE [MFMA_UTIL MFMA_FLOPS]")
     prof_dir, fetch_dir, write_dir = args.summarize[:3]
+    dirs = " ".join(args.summarize)
     lines = ["# Kernel time of one 512^3 bench step, both forms (rocprofv3 --kernel-trace --stats)", "",
              "Command (repo root):", "",
-             "    rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof -o run -- "
-             "python -u bench.py --steps 1 --warmup 0 --no-cpu", "",
+             "    rocprofv3 --kernel-trace --stats --output-format csv -d %s -o run -- "
+             "python -u bench.py --steps 1 --warmup 0 --no-cpu" % prof_dir, "",
              "The step runs 500 nnTucker sweeps per form (BF16 form: 480 on BF16 X + 20 on FP32 X),",
              "nnCP rank 10 x 300 sweeps, lift and residuals; then Algorithm 2 twice per form (nnCP of",
              "X rank 10 x 500 sweeps with the R = 10 pass instantiations, NMF of each factor, lift), the",
@@ -157,11 +158,11 @@ def summarize(args):
         json.dump(res, f, indent=1)
     md = ["# HBM traffic of the X-streaming pass kernels, 512^3, R = 20 (rocprofv3 --pmc)", "",
           "Commands (repo root), one counter per run:", "",
-          "    rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o run -- "
-          "python -u bench.py --kernel-only",
-          "    rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o run -- "
-          "python -u bench.py --kernel-only",
-          "    python bench.py --summarize gpurun_out/prof gpurun_out/pmc_fetch gpurun_out/pmc_write", "",
+          "    rocprofv3 --pmc FETCH_SIZE --output-format csv -d %s -o run -- "
+          "python -u bench.py --kernel-only" % fetch_dir,
+          "    rocprofv3 --pmc WRITE_SIZE --output-format csv -d %s -o run -- "
+          "python -u bench.py --kernel-only" % write_dir,
+          "    python bench.py --summarize %s" % dirs, "",
           "Calibration: a plain elementwise copy of %d MiB (FP32 multiply by 1) reads FETCH_SIZE = %.0f KiB "
           "and writes WRITE_SIZE = %.0f KiB per dispatch (the torch fill that creates its source is not used); "
           "counter KiB are scaled by %.4f (fetch) and "
@@ -176,7 +177,7 @@ def summarize(args):
     with open(os.path.join(ROOT, "profiles", "pass_traffic_512cubed.md"), "w") as f:
         f.write("\n".join(md) + "\n")
     if len(args.summarize) == 5:
-        res["mfma"] = summarize_mfma(args.summarize[3], args.summarize[4], rows, counter, pick)
+        res["mfma"] = summarize_mfma(args.summarize[3], args.summarize[4], rows, counter, pick, dirs)
         with open(COUNTERS, "w") as f:
             json.dump(res, f, indent=1)
     print(json.dumps(res, indent=1))
@@ -187,7 +188,7 @@ PASS_KEYS = (("ttm_last_lds_k<true, 2", "bf16"), ("ttm_mid_lds_k<2>", "bf16"),
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}
 
 
-def summarize_mfma(util_dir, flops_dir, stats_rows, counter, pick):
+def summarize_mfma(util_dir, flops_dir, stats_rows, counter, pick, dirs):
     """MFMA busy fraction (rocprofv3 derived metric MfmaUtil) and MFMA FLOP per dispatch
     (MfmaFlopsBF16 / MfmaFlopsF32) of the pass kernels; achieved MFMA TFLOP/s uses the
     average kernel durations of the kernel-trace run."""
@@ -197,12 +198,11 @@ def summarize_mfma(util_dir, flops_dir, stats_rows, counter, pick):
     out = {}
     md = ["# MFMA use of the X-streaming pass kernels, 512^3, R = 20 (rocprofv3 --pmc)", "",
           "Commands (repo root), one counter set per run:", "",
-          "    rocprofv3 --pmc MfmaUtil --output-format csv -d gpurun_out/pmc_mfma_util -o run -- "
-          "python -u bench.py --kernel-only",
-          "    rocprofv3 --pmc MfmaFlopsBF16 MfmaFlopsF32 --output-format csv -d gpurun_out/pmc_mfma_flops "
-          "-o run -- python -u bench.py --kernel-only",
-          "    python bench.py --summarize gpurun_out/prof gpurun_out/pmc_fetch gpurun_out/pmc_write "
-          "gpurun_out/pmc_mfma_util gpurun_out/pmc_mfma_flops", "",
+          "    rocprofv3 --pmc MfmaUtil --output-format csv -d %s -o run -- "
+          "python -u bench.py --kernel-only" % util_dir,
+          "    rocprofv3 --pmc MfmaFlopsBF16 MfmaFlopsF32 --output-format csv -d %s "
+          "-o run -- python -u bench.py --kernel-only" % flops_dir,
+          "    python bench.py --summarize %s" % dirs, "",
           "MfmaUtil is rocprofv3's derived metric: summed SQ_VALU_MFMA_BUSY_CYCLES over "
           "(max GRBM_GUI_ACTIVE x SIMD count), in percent.  MFMA FLOP counts what the matrix cores "
           "executed: the rank is padded to 32 (two 16-wide tiles) and the BF16 kernels multiply each X "
@@ -257,7 +257,7 @@ def main():
         kernel_only(args)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 

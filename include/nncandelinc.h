@@ -50,7 +50,7 @@ extern "C" {
 typedef enum {
   NNC_OK = 0,
   NNC_EINVAL = -1,       /* invalid argument (null pointer, bad size, bad enum)            */
-  NNC_EUNSUPPORTED = -2, /* valid request this build does not implement                    */
+  NNC_EUNSUPPORTED = -2, /* valid request the library does not implement                   */
   NNC_EWORKSPACE = -3,   /* workspace missing or smaller than the query says               */
   NNC_EHIP = -4,         /* a HIP runtime call failed (message in nnc_last_error)          */
   NNC_ENUMERIC = -5      /* non-finite value in the result (e.g. NaN or Inf in X)          */
