@@ -229,6 +229,60 @@ def summarize_mfma(util_dir, flops_dir, stats_rows, counter, pick, dirs):
     return out
 
 
+def sec43_study(nnc, dev, n_tensors: int, sweeps: int, progress_every: int = 0):
+    """The Section 4.3 study on tensors 0 .. n_tensors - 1 of its generator: 40^3, nonnegative
+    rank 5, canonical multiranks [3, 4, 5] (factors C_n = F_n B_n meeting Kruskal's criterion);
+    Algorithms 1 and 2 on each, `sweeps` sweeps per sub-fit, scored against the generating C_n."""
+    import torch
+
+    import synth
+    d43, m43, r43 = (40, 40, 40), (3, 4, 5), 5
+    rows43, t43 = [], {1: 0.0, 2: 0.0}
+
+    def T(a):
+        return torch.from_numpy(a).to(dev)
+    for j in range(n_tensors):
+        X43, _, _, Ctrue = synth.rank_deficient_tensor(43, j, d43, m43, r43)
+        ini = synth.init_sec43(43, j, d43, m43, r43)
+        Xd43 = T(X43)
+        Ct = [T(c) for c in Ctrue]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        G43, A43, Bc43 = T(ini["G"]), [T(a) for a in ini["A"]], [T(b) for b in ini["Bc"]]
+        nnc.nntucker_fit(Xd43, m43, sweeps, G43, A43, report=False)
+        nnc.nncp_fit(G43, r43, sweeps, Bc43, residual=False)
+        C1 = nnc.nncandelinc_lift(A43, Bc43)
+        torch.cuda.synchronize()
+        t43[1] += time.perf_counter() - t
+        t = time.perf_counter()
+        Bx43, W43, H43 = [T(b) for b in ini["Bx"]], [T(w) for w in ini["W"]], [T(h) for h in ini["H"]]
+        nnc.nncandelinc_alg2(Xd43, r43, m43, sweeps, sweeps, Bx43, W43, H43)
+        C2 = nnc.nncandelinc_lift(W43, H43)
+        torch.cuda.synchronize()
+        t43[2] += time.perf_counter() - t
+        rows43.append((nnc.reconstruct_residual(Xd43, C1), nnc.mean_congruence(C1, Ct),
+                       nnc.reconstruct_residual(Xd43, C2), nnc.mean_congruence(C2, Ct)))
+        if progress_every and (j + 1) % progress_every == 0:
+            log("sec43: %d / %d tensors" % (j + 1, n_tensors))
+    a43 = np.array(rows43)
+    out = {"config": "Section 4.3: %d generated 40^3 tensors (nonnegative rank 5, canonical multiranks "
+                     "[3,4,5], Kruskal criterion), Algorithms 1 and 2 at multirank [3,4,5], rank 5, %d sweeps "
+                     "per sub-fit" % (n_tensors, sweeps)}
+    for alg, (cr, cc) in ((1, (0, 1)), (2, (2, 3))):
+        out["algorithm_%d" % alg] = {
+            "seconds_per_tensor": round(t43[alg] / max(1, n_tensors), 4),
+            "rel_error": {"mean": float(a43[:, cr].mean()), "median": float(np.median(a43[:, cr])),
+                          "p90": float(np.percentile(a43[:, cr], 90))},
+            "congruence": {"mean": float(a43[:, cc].mean()), "median": float(np.median(a43[:, cc])),
+                           "p10": float(np.percentile(a43[:, cc], 10))}}
+    out["alg2_lower_error_fraction"] = float(np.mean(a43[:, 2] < a43[:, 0]))
+    out["alg2_higher_congruence_fraction"] = float(np.mean(a43[:, 3] > a43[:, 1]))
+    log("sec43: alg1 rel median %.3g cong %.4f (%.2f s/tensor); alg2 rel median %.3g cong %.4f (%.2f s/tensor)"
+        % (np.median(a43[:, 0]), a43[:, 1].mean(), t43[1] / max(1, n_tensors), np.median(a43[:, 2]),
+           a43[:, 3].mean(), t43[2] / max(1, n_tensors)))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,6 +298,9 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--restarts", type=int, default=1000)
     ap.add_argument("--restart-sweeps", type=int, default=5000)
+    ap.add_argument("--sec43-tensors", type=int, default=8)
+    ap.add_argument("--sec43-only", action="store_true",
+                    help="only the Section 4.3 study (progress on stderr, one JSON line)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only launch the pass kernels and a calibration copy (counter runs)")
     ap.add_argument("--summarize", nargs="+", metavar="DIR",
@@ -255,6 +312,15 @@ def main():
         return
     if args.kernel_only:
         kernel_only(args)
+        return
+    if args.sec43_only:
+        import torch
+
+        import paper_1909_07570_amd as nnc
+        if not torch.cuda.is_available() or not nnc.device_ok():
+            raise SystemExit("bench.py needs an MI355X (gfx950) GPU and the built library")
+        print(json.dumps(sec43_study(nnc, torch.device("cuda:0"), args.sec43_tensors, args.restart_sweeps,
+                                     progress_every=25)), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -400,6 +466,8 @@ def main():
             log("study alg %d m %s: %.1f ms, rel mean %.4g median %.4g, congruence %.4f"
                 % (alg, m, el * 1e3, rel.mean(), np.median(rel), cg.mean()))
 
+    sec43 = sec43_study(nnc, dev, args.sec43_tensors, args.restart_sweeps)
+
     # ---- per-launch timing of the two X-streaming contractions (same kernels, same launch
     # configuration as inside the fit), HIP events on the stream they are launched on.
     size = N ** 3
@@ -514,6 +582,7 @@ def main():
         "cpu_baseline": cpu,
         "alg2": alg2,
         "restart_study": study,
+        "sec43_study": sec43,
     }
     print(json.dumps(line), flush=True)
 

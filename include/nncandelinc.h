@@ -241,6 +241,16 @@ nnc_status nncandelinc_restarts(const float *X, const int64_t *dims, int algorit
                                 double *congruences, float *lifted, unsigned long long *clips, void *stream);
 
 /*
+ * Mean congruence of two CP models of rank <= 8 (Section 4.1 scoring): the congruence of two
+ * rank-one terms is the product over modes of the cosines of their factor columns, and the
+ * score is the mean over components under the matching that maximises it (every permutation
+ * is tried).  P, Q: host arrays of ndim device pointers, factor n dims[n] x rank.  congruence:
+ * device, one double (no synchronisation).  A zero column has cosine 0.
+ */
+nnc_status nnc_mean_congruence(int ndim, const int64_t *dims, int rank, const float *const *P,
+                               const float *const *Q, double *congruence, void *stream);
+
+/*
  * Lift: C_n = A_n B_n for every mode (substituting the core's CP into the Tucker model,
  * Section 2.1 lemma proof and Section 2.2).  tucker_factors[n]: dims[n] x multirank[n];
  * cp_factors[n]: multirank[n] x rank; out_factors[n]: dims[n] x rank.  Host arrays of

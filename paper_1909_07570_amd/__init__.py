@@ -59,7 +59,7 @@ EXPORTED = ["nnc_last_error", "nnc_device_ok", "nnc_set_timing", "nnc_ttm", "nnc
             "reconstruct_workspace_bytes", "reconstruct_residual", "reconstruct_sq_sums",
             "nntucker_grad", "nncpx_workspace_bytes", "nncpx_fit", "nmf_workspace_bytes", "nmf_fit",
             "nmf_batched_workspace_bytes", "nmf_fit_batched", "nncandelinc_restart_init_floats",
-            "nncandelinc_restarts"]
+            "nncandelinc_restarts", "nnc_mean_congruence"]
 
 _lib = None
 
@@ -106,6 +106,7 @@ def lib():
         L.nncandelinc_restart_init_floats.restype = ctypes.c_int64
         L.nncandelinc_restarts.argtypes = [_vp, _i64p, ctypes.c_int, _i64p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_int, _vp, _vpp, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]
+        L.nnc_mean_congruence.argtypes = [ctypes.c_int, _i64p, ctypes.c_int, _vpp, _vpp, _vp, _vp]
         L.nncandelinc_lift.argtypes = [ctypes.c_int, _i64p, _i64p, ctypes.c_int, _vpp, _vpp, _vpp, _vp]
         L.reconstruct_workspace_bytes.argtypes = [ctypes.c_int, _i64p, _i64p, ctypes.c_int]
         L.reconstruct_workspace_bytes.restype = ctypes.c_size_t
@@ -344,6 +345,18 @@ def nmf_fit_batched(A: Sequence[torch.Tensor], ranks: Sequence[int], iters: int,
     _check(lib().nmf_fit_batched(n, _ptrs(A), rows, cols, rk, int(iters), _ptrs(W), _ptrs(H), float(eps),
                                  res if residual else None, ws.data_ptr(), ws.numel(), _stream()))
     return [res[j] for j in range(n)] if residual else None
+
+
+def mean_congruence(P: Sequence[torch.Tensor], Q: Sequence[torch.Tensor]) -> float:
+    """Mean congruence of two CP models (factor n: dims[n] x rank, rank <= 8) under the best
+    matching of their components (Section 4.1 scoring)."""
+    for k in range(len(P)):
+        _dev(P[k], "P[%d]" % k)
+        _dev(Q[k], "Q[%d]" % k)
+    out = torch.empty(1, dtype=torch.float64, device=P[0].device)
+    _check(lib().nnc_mean_congruence(len(P), _dims([p.shape[0] for p in P]), int(P[0].shape[1]), _ptrs(P),
+                                     _ptrs(Q), out.data_ptr(), _stream()))
+    return float(out.item())
 
 
 @dataclass

@@ -1447,6 +1447,17 @@ nnc_status nncandelinc_restarts(const float *X, const int64_t *dims, int algorit
                                lifted, clips, (hipStream_t)stream);
 }
 
+nnc_status nnc_mean_congruence(int ndim, const int64_t *dims, int rank, const float *const *P,
+                               const float *const *Q, double *congruence, void *stream) {
+  NNC_TRY(check_dims(ndim, dims, "dims"));
+  if (rank < 1) return fail(NNC_EINVAL, "rank %d < 1", rank);
+  if (rank > 8) return fail(NNC_EUNSUPPORTED, "rank %d above 8", rank);
+  if (!congruence) return fail(NNC_EINVAL, "congruence is NULL");
+  NNC_TRY(check_ptrs((const void *const *)P, ndim, "P"));
+  NNC_TRY(check_ptrs((const void *const *)Q, ndim, "Q"));
+  return launch_congruence(ndim, dims, rank, P, Q, congruence, (hipStream_t)stream);
+}
+
 // ---- tuner for the batched launch: threads per fit, timed on scratch factors, cached per
 // (core shape, rank multiset) for the life of the process.
 static std::mutex g_tune_mu;

@@ -170,6 +170,8 @@ nnc_status launch_tiny_candelinc(const float *X, const int *N, const int *M, int
                                  int outer, int inner, const float *inits, const float *const *truth,
                                  double eps, double *rel, double *cong, float *fout,
                                  unsigned long long *clips, hipStream_t s);
+nnc_status launch_congruence(int d, const int64_t *dims, int r, const float *const *P, const float *const *Q,
+                             double *out, hipStream_t s);
 nnc_status launch_transpose(const float *in, int64_t rows, int64_t cols, float *out, hipStream_t s);
 nnc_status launch_sum_parts(const float *part, int nparts, int64_t n, float *out, hipStream_t s);
 

@@ -398,3 +398,83 @@ nnc_status launch_tiny_candelinc(const float *X, const int *N, const int *M, int
 }
 
 }  // namespace nnc
+
+namespace nnc {
+
+// Mean congruence of two rank-r CP models with factors P[n], Q[n] (dims[n] x r): the
+// congruence of components rho and sigma is the product over modes of the cosines of their
+// factor columns (FP64), and the score is the largest mean over the matchings of components
+// (every permutation).  One workgroup; a zero column has cosine 0.
+struct CongArgs {
+  int d, r;
+  int64_t dims[kMaxDim];
+  const float *P[kMaxDim], *Q[kMaxDim];
+  double *out;
+};
+
+__global__ __launch_bounds__(256) void congruence_k(CongArgs a) {
+  __shared__ double cg[kTinyDim * kTinyDim];
+  __shared__ double best[256];
+  const int tid = threadIdx.x, r = a.r;
+  if (tid < r * r) {
+    const int rho = tid / r, sg = tid % r;
+    double prod = 1.0;
+    for (int n = 0; n < a.d; ++n) {
+      double dot = 0.0, n1 = 0.0, n2 = 0.0;
+      for (int64_t i = 0; i < a.dims[n]; ++i) {
+        const double u = a.P[n][i * r + rho], v = a.Q[n][i * r + sg];
+        dot += u * v;
+        n1 += u * u;
+        n2 += v * v;
+      }
+      prod *= (n1 > 0 && n2 > 0) ? dot / sqrt(n1 * n2) : 0.0;
+    }
+    cg[tid] = prod;
+  }
+  __syncthreads();
+  int nperm = 1;
+  for (int k = 2; k <= r; ++k) nperm *= k;
+  double b = -1e300;
+  for (int pidx = tid; pidx < nperm; pidx += 256) {
+    int avail[kTinyDim];
+    for (int k = 0; k < r; ++k) avail[k] = k;
+    int code = pidx, left = r;
+    double s = 0.0;
+    for (int rho = 0; rho < r; ++rho) {  // factorial-base digits pick the unused targets
+      int f = 1;
+      for (int k = 2; k < left; ++k) f *= k;
+      const int dgt = code / f;
+      code -= dgt * f;
+      s += cg[rho * r + avail[dgt]];
+      for (int k = dgt; k < left - 1; ++k) avail[k] = avail[k + 1];
+      --left;
+    }
+    b = fmax(b, s / r);
+  }
+  best[tid] = b;
+  __syncthreads();
+  if (tid == 0) {
+    double m = -1e300;
+    for (int t = 0; t < 256; ++t) m = fmax(m, best[t]);
+    *a.out = m;
+  }
+}
+
+nnc_status launch_congruence(int d, const int64_t *dims, int r, const float *const *P, const float *const *Q,
+                             double *out, hipStream_t s) {
+  CongArgs a;
+  memset(&a, 0, sizeof a);
+  a.d = d;
+  a.r = r;
+  for (int n = 0; n < d; ++n) {
+    a.dims[n] = dims[n];
+    a.P[n] = P[n];
+    a.Q[n] = Q[n];
+  }
+  a.out = out;
+  hipLaunchKernelGGL(congruence_k, dim3(1), dim3(256), 0, s, a);
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+}  // namespace nnc

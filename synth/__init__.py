@@ -20,7 +20,9 @@ Stream ids (one per role):  planted factor n -> n;  zero mask of planted factor 
 16 + n;  additive noise -> 32;  initial core G0 -> 48;  initial Tucker factor n ->
 64 + n;  nnCP restart j, factor n -> 1024 + 16 j + n;  NMF of factor n (Algorithm 2):
 W0 -> 2048 + n, H0 -> 2064 + n;  restart j of the small-tensor study -> 4096 + j (one stream per
-start, laid out as unpack_restart() splits it).
+start, laid out as unpack_restart() splits it);  generated tensor j of the rank-deficient study,
+attempt a, its F_n / B_n -> 1 << 20 + 64 (16 j + a) + n / + 8 + n, and the fits' initial values
+-> 1 << 24 + 64 j + role.
 """
 
 from __future__ import annotations
@@ -42,6 +44,8 @@ STREAM_CP_RESTART = 1024
 STREAM_NMF_W = 2048
 STREAM_NMF_H = 2064
 STREAM_RESTART = 4096
+STREAM_GEN43 = 1 << 20
+STREAM_INIT43 = 1 << 24
 
 
 def _mix64_int(z: int) -> int:
@@ -159,6 +163,52 @@ def unpack_restart(vec, alg: int, dims, multirank, rank: int):
         out.append(np.asarray(vec[off:off + k]).reshape(shp))
         off += k
     return out
+
+
+def kruskal_rank(M) -> int:
+    """Largest k such that every set of k columns of M is linearly independent."""
+    import itertools
+    M = np.asarray(M, dtype=np.float64)
+    k = 0
+    for size in range(1, M.shape[1] + 1):
+        if all(np.linalg.matrix_rank(M[:, list(c)]) == size
+               for c in itertools.combinations(range(M.shape[1]), size)):
+            k = size
+        else:
+            break
+    return k
+
+
+def rank_deficient_tensor(seed: int, j: int, dims=(40, 40, 40), ranks=(3, 4, 5), r: int = 5,
+                          max_attempts: int = 16):
+    """Tensor j of the rank-deficient study: X = sum_rho outer(C_1[:, rho], .., C_3[:, rho]) with
+    C_n = F_n B_n, F_n ~ U[0,1) dims[n] x ranks[n] and B_n ~ U[0,1) ranks[n] x r, redrawn until the
+    Kruskal ranks of the C_n sum to at least 2r + 2.  Returns (X float32, F, B, C) with F, B and
+    C float32 and X formed in float64 from the float32 C and rounded once."""
+    for a in range(max_attempts):
+        base = STREAM_GEN43 + 64 * (16 * j + a)
+        F = [uniform_matrix(seed, base + n, int(dims[n]), int(ranks[n])).astype(np.float32) for n in range(3)]
+        B = [uniform_matrix(seed, base + 8 + n, int(ranks[n]), r).astype(np.float32) for n in range(3)]
+        C64 = [f.astype(np.float64) @ b.astype(np.float64) for f, b in zip(F, B)]
+        # the criterion on the exact products (rounding them to float32 would add full rank)
+        if sum(kruskal_rank(c) for c in C64) >= 2 * r + 2:
+            C = [c.astype(np.float32) for c in C64]
+            X = np.einsum("ir,jr,kr->ijk", *[c.astype(np.float64) for c in C])
+            return X.astype(np.float32), F, B, C
+    raise RuntimeError("no draw met the Kruskal criterion")
+
+
+def init_sec43(seed: int, j: int, dims, ranks, r: int, dtype=np.float32):
+    """Initial values of both algorithms on tensor j: Algorithm 1 (A_n dims[n] x ranks[n], G,
+    core CP factors ranks[n] x r) and Algorithm 2 (CP factors dims[n] x r, NMF W_n, H_n)."""
+    base = STREAM_INIT43 + 64 * j
+    A = [uniform_matrix(seed, base + n, int(dims[n]), int(ranks[n])).astype(dtype) for n in range(3)]
+    G = uniform(seed, base + 3, int(np.prod(ranks))).reshape(tuple(int(x) for x in ranks)).astype(dtype)
+    Bc = [uniform_matrix(seed, base + 4 + n, int(ranks[n]), r).astype(dtype) for n in range(3)]
+    Bx = [uniform_matrix(seed, base + 8 + n, int(dims[n]), r).astype(dtype) for n in range(3)]
+    W = [uniform_matrix(seed, base + 12 + n, int(dims[n]), int(ranks[n])).astype(dtype) for n in range(3)]
+    H = [uniform_matrix(seed, base + 16 + n, int(ranks[n]), r).astype(dtype) for n in range(3)]
+    return dict(A=A, G=G, Bc=Bc, Bx=Bx, W=W, H=H)
 
 
 def planted_factors(seed: int, dims, R: int, zero_prob: float = 0.0):

@@ -37,3 +37,31 @@ def test_planted_tensor_shapes_and_chunking():
     assert all((f[:, c] != 0).any() for f in f1 for c in range(3))
     X32, _ = synth.planted_tensor(5, (6, 5, 4), 3, zero_prob=0.5, dtype="f32")
     assert np.array_equal(X32, X2.astype(np.float32))
+
+
+def test_kruskal_rank_small_cases():
+    assert synth.kruskal_rank(np.eye(4)) == 4
+    M = np.array([[1.0, 2.0, 1.0], [0.0, 0.0, 1.0], [1.0, 2.0, 0.0]])  # columns 0 and 1 parallel
+    assert synth.kruskal_rank(M) == 1
+    Z = np.array([[0.0, 1.0], [0.0, 2.0]])  # a zero column
+    assert synth.kruskal_rank(Z) == 0
+    V = np.array([[1.0, 0.0, 1.0], [0.0, 1.0, 1.0]])  # any two independent, three not
+    assert synth.kruskal_rank(V) == 2
+
+
+def test_rank_deficient_generator():
+    """Tensors of the rank-deficient study: C_n = F_n B_n with Kruskal ranks (3, 4, 5) meeting
+    k_1 + k_2 + k_3 >= 2r + 2, and X the rank-5 CP of the float32 C_n."""
+    for j in range(3):
+        X, F, B, C = synth.rank_deficient_tensor(7, j)
+        assert X.shape == (40, 40, 40) and X.dtype == np.float32
+        ks = [synth.kruskal_rank(f.astype(np.float64) @ b.astype(np.float64)) for f, b in zip(F, B)]
+        assert ks == [3, 4, 5] and sum(ks) >= 12
+        for f, b, c in zip(F, B, C):
+            assert np.array_equal(c, (f.astype(np.float64) @ b.astype(np.float64)).astype(np.float32))
+        Xr = np.zeros((40, 40, 40))
+        for rho in range(5):
+            Xr += np.multiply.outer(np.multiply.outer(C[0][:, rho].astype(np.float64), C[1][:, rho]), C[2][:, rho])
+        assert np.array_equal(X, Xr.astype(np.float32))
+    a, b = synth.rank_deficient_tensor(7, 0), synth.rank_deficient_tensor(7, 0)
+    assert np.array_equal(a[0], b[0])
