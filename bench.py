@@ -229,6 +229,93 @@ def summarize_mfma(util_dir, flops_dir, stats_rows, counter, pick, dirs):
     return out
 
 
+def extra_studies(args, nnc, dev, Xb, X32, dims, ranks, rank, R):
+    """Algorithm 2 on the 512^3 tensor, the Section 4.2 study and a sample of the Section 4.3
+    study (the objects "alg2", "restart_study" and "sec43_study" of the JSON line)."""
+    import torch
+
+    import synth
+    # ---- Algorithm 2 on the same tensor: nnCP of X (rank 10), NMF of each factor (m = 20),
+    # lift, residual; both forms from identical initial values.
+    Bx0 = [torch.from_numpy(b).to(dev) for b in synth.init_cp_factors(SEED, dims, rank)]
+    W0, H0 = synth.init_nmf(SEED, dims, ranks, rank)
+    W0 = [torch.from_numpy(w).to(dev) for w in W0]
+    H0 = [torch.from_numpy(h).to(dev) for h in H0]
+    wsx = torch.empty(nnc.nncpx_workspace_bytes(dims, rank), dtype=torch.uint8, device=dev)
+    Bx = [torch.empty_like(b) for b in Bx0]
+    Wf = [torch.empty_like(w) for w in W0]
+    Hf = [torch.empty_like(h) for h in H0]
+
+    def alg2_step(bf16: bool):
+        for b, b0 in zip(Bx, Bx0):
+            b.copy_(b0)
+        for w, w0 in zip(Wf, W0):
+            w.copy_(w0)
+        for h, h0 in zip(Hf, H0):
+            h.copy_(h0)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        if bf16:
+            nnc.nncpx_fit(Xb, rank, args.sweeps, Bx, x_fp32=X32, fp32_final_sweeps=args.fp32_final,
+                          report=False, workspace=wsx)
+        else:
+            nnc.nncpx_fit(X32, rank, args.sweeps, Bx, report=False, workspace=wsx)
+        torch.cuda.synchronize()
+        t_cp = time.perf_counter() - t
+        t = time.perf_counter()
+        nnc.nmf_fit_batched(Bx, [R] * 3, args.cp_sweeps, Wf, Hf, residual=False)
+        C = nnc.nncandelinc_lift(Wf, Hf)
+        torch.cuda.synchronize()
+        t_nmf = time.perf_counter() - t
+        return t_cp, t_nmf, nnc.reconstruct_residual(X32, Bx), nnc.reconstruct_residual(X32, C)
+
+    alg2 = {}
+    for form, bf16 in (("bf16", True), ("fp32", False)):
+        alg2_step(bf16)  # warm-up
+        t_cp, t_nmf, rel_x, rel_l = alg2_step(bf16)
+        alg2[form] = {"sweeps_per_s": round(args.sweeps / t_cp, 2), "nncp_x_ms": round(t_cp * 1e3, 3),
+                      "nmf_lift_ms": round(t_nmf * 1e3, 3), "cp_x_rel": rel_x, "lifted_rel": rel_l}
+        log("alg2 %s: nnCP of X %.1f ms (%.0f sweeps/s), NMF+lift %.1f ms, rel %.6g, lifted rel %.6g"
+            % (form, t_cp * 1e3, args.sweeps / t_cp, t_nmf * 1e3, rel_x, rel_l))
+    alg2["abs_diff_cp_x_rel"] = abs(alg2["bf16"]["cp_x_rel"] - alg2["fp32"]["cp_x_rel"])
+    alg2["config"] = ("Algorithm 2 on the same 512^3 tensor: nnCP rank %d, %d MU sweeps (BF16 form: last %d "
+                      "on FP32 X); NMF of each factor with m = %d, %d sweeps; lift; residuals"
+                      % (rank, args.sweeps, args.fp32_final, R, args.cp_sweeps))
+
+    # ---- the Section 4.2 study: 1000 starts x 5000 sweeps per sub-fit, both algorithms, four
+    # assumed multiranks, on the 4x4x4 example with known nnCPD (rank 4)
+    from tests.paper_fixtures import examples
+    ex = examples()["ex5_rank_not_preserved_nn"]
+    At = [np.asarray(ex[k], dtype=np.float64) for k in ("A1", "A2", "A3")]
+    Xs = torch.from_numpy(np.einsum("ir,jr,kr->ijk", *At).astype(np.float32)).to(dev)
+    truth = [torch.from_numpy(a.astype(np.float32)).to(dev) for a in At]
+    study = {"config": "Section 4.2: the 4x4x4 example (nonnegative rank 4, unique nnCPD), %d random starts "
+                       "per (algorithm, multirank), %d sweeps per sub-fit, one launch per configuration"
+                       % (args.restarts, args.restart_sweeps), "runs": []}
+    for alg in (1, 2):
+        for m in ((3, 3, 3), (3, 4, 4), (4, 4, 4), (5, 5, 5)):
+            inits = torch.from_numpy(synth.init_restarts(SEED, alg, (4, 4, 4), m, 4, args.restarts)).to(dev)
+            nnc.nncandelinc_restarts(Xs, alg, m, 4, inits[:8], 10, 10, truth=truth)  # warm-up
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            res = nnc.nncandelinc_restarts(Xs, alg, m, 4, inits, args.restart_sweeps, args.restart_sweeps,
+                                           truth=truth)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+            rel = res.rel_errors.cpu().numpy()
+            cg = res.congruences.cpu().numpy()
+            study["runs"].append({"algorithm": alg, "multirank": list(m), "seconds": round(el, 4),
+                                  "starts_per_s": round(args.restarts / el, 1),
+                                  "rel_error": {"mean": float(rel.mean()), "median": float(np.median(rel)),
+                                                "std": float(rel.std()), "min": float(rel.min())},
+                                  "congruence": {"mean": float(cg.mean()), "std": float(cg.std())}})
+            log("study alg %d m %s: %.1f ms, rel mean %.4g median %.4g, congruence %.4f"
+                % (alg, m, el * 1e3, rel.mean(), np.median(rel), cg.mean()))
+
+    sec43 = sec43_study(nnc, dev, args.sec43_tensors, args.restart_sweeps)
+    return alg2, study, sec43
+
+
 def sec43_study(nnc, dev, n_tensors: int, sweeps: int, progress_every: int = 0):
     """The Section 4.3 study on tensors 0 .. n_tensors - 1 of its generator: 40^3, nonnegative
     rank 5, canonical multiranks [3, 4, 5] (factors C_n = F_n B_n meeting Kruskal's criterion);
@@ -299,6 +386,8 @@ def main():
     ap.add_argument("--restarts", type=int, default=1000)
     ap.add_argument("--restart-sweeps", type=int, default=5000)
     ap.add_argument("--sec43-tensors", type=int, default=8)
+    ap.add_argument("--no-studies", action="store_true",
+                    help="skip Algorithm 2 and the Section 4.2 / 4.3 studies (diagnostic runs)")
     ap.add_argument("--sec43-only", action="store_true",
                     help="only the Section 4.3 study (progress on stderr, one JSON line)")
     ap.add_argument("--kernel-only", action="store_true",
@@ -389,84 +478,9 @@ def main():
         log("%s: %.1f ms/step, %.0f sweeps/s, tucker rel %.6g, lifted rel %.6g"
             % (form, results[form]["ms_per_step"], results[form]["sweeps_per_s"], tucker_rel, cp_rel))
 
-    # ---- Algorithm 2 on the same tensor: nnCP of X (rank 10), NMF of each factor (m = 20),
-    # lift, residual; both forms from identical initial values.
-    Bx0 = [torch.from_numpy(b).to(dev) for b in synth.init_cp_factors(SEED, dims, rank)]
-    W0, H0 = synth.init_nmf(SEED, dims, ranks, rank)
-    W0 = [torch.from_numpy(w).to(dev) for w in W0]
-    H0 = [torch.from_numpy(h).to(dev) for h in H0]
-    wsx = torch.empty(nnc.nncpx_workspace_bytes(dims, rank), dtype=torch.uint8, device=dev)
-    Bx = [torch.empty_like(b) for b in Bx0]
-    Wf = [torch.empty_like(w) for w in W0]
-    Hf = [torch.empty_like(h) for h in H0]
-
-    def alg2_step(bf16: bool):
-        for b, b0 in zip(Bx, Bx0):
-            b.copy_(b0)
-        for w, w0 in zip(Wf, W0):
-            w.copy_(w0)
-        for h, h0 in zip(Hf, H0):
-            h.copy_(h0)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        if bf16:
-            nnc.nncpx_fit(Xb, rank, args.sweeps, Bx, x_fp32=X32, fp32_final_sweeps=args.fp32_final,
-                          report=False, workspace=wsx)
-        else:
-            nnc.nncpx_fit(X32, rank, args.sweeps, Bx, report=False, workspace=wsx)
-        torch.cuda.synchronize()
-        t_cp = time.perf_counter() - t
-        t = time.perf_counter()
-        nnc.nmf_fit_batched(Bx, [R] * 3, args.cp_sweeps, Wf, Hf, residual=False)
-        C = nnc.nncandelinc_lift(Wf, Hf)
-        torch.cuda.synchronize()
-        t_nmf = time.perf_counter() - t
-        return t_cp, t_nmf, nnc.reconstruct_residual(X32, Bx), nnc.reconstruct_residual(X32, C)
-
-    alg2 = {}
-    for form, bf16 in (("bf16", True), ("fp32", False)):
-        alg2_step(bf16)  # warm-up
-        t_cp, t_nmf, rel_x, rel_l = alg2_step(bf16)
-        alg2[form] = {"sweeps_per_s": round(args.sweeps / t_cp, 2), "nncp_x_ms": round(t_cp * 1e3, 3),
-                      "nmf_lift_ms": round(t_nmf * 1e3, 3), "cp_x_rel": rel_x, "lifted_rel": rel_l}
-        log("alg2 %s: nnCP of X %.1f ms (%.0f sweeps/s), NMF+lift %.1f ms, rel %.6g, lifted rel %.6g"
-            % (form, t_cp * 1e3, args.sweeps / t_cp, t_nmf * 1e3, rel_x, rel_l))
-    alg2["abs_diff_cp_x_rel"] = abs(alg2["bf16"]["cp_x_rel"] - alg2["fp32"]["cp_x_rel"])
-    alg2["config"] = ("Algorithm 2 on the same 512^3 tensor: nnCP rank %d, %d MU sweeps (BF16 form: last %d "
-                      "on FP32 X); NMF of each factor with m = %d, %d sweeps; lift; residuals"
-                      % (rank, args.sweeps, args.fp32_final, R, args.cp_sweeps))
-
-    # ---- the Section 4.2 study: 1000 starts x 5000 sweeps per sub-fit, both algorithms, four
-    # assumed multiranks, on the 4x4x4 example with known nnCPD (rank 4)
-    from tests.paper_fixtures import examples
-    ex = examples()["ex5_rank_not_preserved_nn"]
-    At = [np.asarray(ex[k], dtype=np.float64) for k in ("A1", "A2", "A3")]
-    Xs = torch.from_numpy(np.einsum("ir,jr,kr->ijk", *At).astype(np.float32)).to(dev)
-    truth = [torch.from_numpy(a.astype(np.float32)).to(dev) for a in At]
-    study = {"config": "Section 4.2: the 4x4x4 example (nonnegative rank 4, unique nnCPD), %d random starts "
-                       "per (algorithm, multirank), %d sweeps per sub-fit, one launch per configuration"
-                       % (args.restarts, args.restart_sweeps), "runs": []}
-    for alg in (1, 2):
-        for m in ((3, 3, 3), (3, 4, 4), (4, 4, 4), (5, 5, 5)):
-            inits = torch.from_numpy(synth.init_restarts(SEED, alg, (4, 4, 4), m, 4, args.restarts)).to(dev)
-            nnc.nncandelinc_restarts(Xs, alg, m, 4, inits[:8], 10, 10, truth=truth)  # warm-up
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            res = nnc.nncandelinc_restarts(Xs, alg, m, 4, inits, args.restart_sweeps, args.restart_sweeps,
-                                           truth=truth)
-            torch.cuda.synchronize()
-            el = time.perf_counter() - t
-            rel = res.rel_errors.cpu().numpy()
-            cg = res.congruences.cpu().numpy()
-            study["runs"].append({"algorithm": alg, "multirank": list(m), "seconds": round(el, 4),
-                                  "starts_per_s": round(args.restarts / el, 1),
-                                  "rel_error": {"mean": float(rel.mean()), "median": float(np.median(rel)),
-                                                "std": float(rel.std()), "min": float(rel.min())},
-                                  "congruence": {"mean": float(cg.mean()), "std": float(cg.std())}})
-            log("study alg %d m %s: %.1f ms, rel mean %.4g median %.4g, congruence %.4f"
-                % (alg, m, el * 1e3, rel.mean(), np.median(rel), cg.mean()))
-
-    sec43 = sec43_study(nnc, dev, args.sec43_tensors, args.restart_sweeps)
+    alg2, study, sec43 = {}, {}, {}
+    if not args.no_studies:
+        alg2, study, sec43 = extra_studies(args, nnc, dev, Xb, X32, dims, ranks, rank, R)
 
     # ---- per-launch timing of the two X-streaming contractions (same kernels, same launch
     # configuration as inside the fit), HIP events on the stream they are launched on.
@@ -532,26 +546,32 @@ def main():
                "kind": "oracle",
                "sample": "%d FP64 nnTucker sweeps of the same 512^3 problem (multirank 20^3) from the "
                          "same initial values, %.1f s" % (done, el)}
-        t = time.perf_counter()
-        b0x = [b.astype(np.float64) for b in synth.init_cp_factors(SEED, dims, rank)]
-        oracle.nncp(X64, b0x, 1)
-        el = time.perf_counter() - t
-        t = time.perf_counter()
-        done = 0
-        Xe = np.einsum("ir,jr,kr->ijk", *At)
-        inits1 = synth.init_restarts(SEED, 1, (4, 4, 4), (4, 4, 4), 4, 2)
-        for j in range(2):
-            parts = synth.unpack_restart(inits1[j].astype(np.float64), 1, (4, 4, 4), (4, 4, 4), 4)
-            oracle.restart_fit(Xe, 1, parts, args.restart_sweeps, args.restart_sweeps, truth=At)
-            done += 1
-        el = time.perf_counter() - t
-        study["cpu_baseline"] = {"value": round(done / el, 3), "unit": "starts/s (Algorithm 1, multirank [4,4,4])",
-                                 "cores": oracle.get_threads(), "kind": "oracle",
-                                 "sample": "%d starts of %d + %d sweeps, %.1f s" % (done, args.restart_sweeps,
-                                                                                   args.restart_sweeps, el)}
-        alg2["cpu_baseline"] = {"value": round(1.0 / el, 5), "unit": "nnCP-of-X MU sweeps/s",
-                                "cores": oracle.get_threads(), "kind": "oracle",
-                                "sample": "1 FP64 nnCP sweep of the 512^3 tensor, rank %d, %.1f s" % (rank, el)}
+        if not args.no_studies:
+            t = time.perf_counter()
+            b0x = [b.astype(np.float64) for b in synth.init_cp_factors(SEED, dims, rank)]
+            oracle.nncp(X64, b0x, 1)
+            el_cpx = time.perf_counter() - t
+            alg2["cpu_baseline"] = {"value": round(1.0 / el_cpx, 5), "unit": "nnCP-of-X MU sweeps/s",
+                                    "cores": oracle.get_threads(), "kind": "oracle",
+                                    "sample": "1 FP64 nnCP sweep of the 512^3 tensor, rank %d, %.1f s"
+                                              % (rank, el_cpx)}
+            from tests.paper_fixtures import examples
+            ex = examples()["ex5_rank_not_preserved_nn"]
+            At = [np.asarray(ex[k], dtype=np.float64) for k in ("A1", "A2", "A3")]
+            Xe = np.einsum("ir,jr,kr->ijk", *At)
+            inits1 = synth.init_restarts(SEED, 1, (4, 4, 4), (4, 4, 4), 4, 2)
+            t = time.perf_counter()
+            done = 0
+            for j in range(2):
+                parts = synth.unpack_restart(inits1[j].astype(np.float64), 1, (4, 4, 4), (4, 4, 4), 4)
+                oracle.restart_fit(Xe, 1, parts, args.restart_sweeps, args.restart_sweeps, truth=At)
+                done += 1
+            el_rs = time.perf_counter() - t
+            study["cpu_baseline"] = {"value": round(done / el_rs, 3),
+                                     "unit": "starts/s (Algorithm 1, multirank [4,4,4])",
+                                     "cores": oracle.get_threads(), "kind": "oracle",
+                                     "sample": "%d starts of %d + %d sweeps, %.1f s"
+                                               % (done, args.restart_sweeps, args.restart_sweeps, el_rs)}
         del X64
 
     bf, fp = results["bf16"], results["fp32"]

@@ -1,10 +1,15 @@
 /*
  * nncandelinc.h -- C ABI of the MI355X (gfx950) library for nonnegative CANDELINC
- * computed as in Algorithm 1 of Alexandrov, DeSantis, Manzini, Skau, "Nonnegative
- * Canonical Tensor Decomposition with Linear Constraints: nnCANDELINC" (arXiv 1909.07570):
- * a nonnegative Tucker compression X ~ G x_1 F1 x_2 F2 ... x_d Fd, a nonnegative CP of the
- * core G ~ I x_1 B1 ... x_d Bd, and the lift C_n = F_n B_n, which together solve the
- * constrained least-squares problem of Section 4 (eq. nnCANDELINC).
+ * (Alexandrov, DeSantis, Manzini, Skau, "Nonnegative Canonical Tensor Decomposition with
+ * Linear Constraints: nnCANDELINC", arXiv 1909.07570), which solves the constrained
+ * least-squares problem of Section 4 (eq. nnCANDELINC) in two ways:
+ *   Algorithm 1: a nonnegative Tucker compression X ~ G x_1 F1 x_2 F2 ... x_d Fd
+ *                (nntucker_fit), a nonnegative CP of the core G ~ I x_1 B1 ... x_d Bd
+ *                (nncp_fit), and the lift C_n = F_n B_n (nncandelinc_lift);
+ *   Algorithm 2: a nonnegative CP of X itself (nncpx_fit), then an NMF of each CP factor,
+ *                A_n ~ F_n B_n (nmf_fit, nmf_fit_batched), and the same lift.
+ * Scoring (Section 4.1): reconstruct_residual and nnc_mean_congruence.  The random-restart
+ * study of Section 4.2 runs as one launch (nncandelinc_restarts).
  *
  * Conventions shared by every entry point
  *   - Tensors are dense and row-major (last index fastest): element (i_1, ..., i_d) of a

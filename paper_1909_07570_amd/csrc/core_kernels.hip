@@ -54,6 +54,11 @@ struct SliceLds {
   }
 };
 
+// a / b for 0 <= a < 2^22 and b >= 1 through the float reciprocal: (a + 0.5) / b lies at
+// least 0.5 / b from the nearest integer, and the rounding of inv_b and of the product moves
+// it by less than (a + 0.5) / b * 2^-23, which is smaller for such a.
+static __device__ inline int qdiv(int a, float inv_b) { return (int)(((float)a + 0.5f) * inv_b); }
+
 // Grams into LDS (row stride RM, zero padding); the gram mode's Gram is summed from the
 // partials (entries in groups of 4 when R^2 is a multiple of 4, else one by one; each group
 // by kSliceThreads / groups threads over contiguous ranges of partials, added in order).
@@ -150,11 +155,13 @@ struct GramStage {
       s4.z += v.z;
       s4.w += v.w;
     };
+    const float inv_rk = 1.0f / Rk;
     auto put = [&](int grp, float4 v) {
       const float vv[4] = {v.x, v.y, v.z, v.w};
       for (int w = 0; w < W; ++w) {
         const int e = grp * W + w;
-        Sg[(e / Rk) * RM + e % Rk] = vv[w];
+        const int row = qdiv(e, inv_rk);
+        Sg[row * RM + (e - row * Rk)] = vv[w];
         if (blockIdx.x == 0) a.S[k][e] = vv[w];
       }
     };
@@ -179,6 +186,7 @@ struct GramStage {
       __syncthreads();
       if (tid < ngrp) {
         float4 t4 = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 4
         for (int c = 0; c < nch; ++c) add(t4, reinterpret_cast<const float4 *>(red)[c * ngrp + tid]);
         put(tid, t4);
       }
@@ -205,9 +213,10 @@ static __device__ void slice_ttm(const float *in, float *out, int pre, int Rk, i
   int off[RM];  // the same for every output; opaque so that it is not folded into multiplies
 #pragma unroll
   for (int l = 0; l < RM; ++l) off[l] = __builtin_amdgcn_readfirstlane((l < Rk ? l : Rk - 1) * post);
-  for (int o = threadIdx.x; o < total; o += kSliceThreads) {
-    const int q = o % post, pr = o / post;
-    const int r = pr % Rk, p = pr / Rk;
+  const float inv_post = 1.0f / post, inv_rk = 1.0f / Rk;
+  for (int o = threadIdx.x; o < total; o += kSliceThreads) {  // total <= kSliceMax < 2^22
+    const int pr = qdiv(o, inv_post), q = o - pr * post;
+    const int p = qdiv(pr, inv_rk), r = pr - p * Rk;
     const float *src = in + p * Rk * post + q;
     float x[RM], sv[RM];
 #pragma unroll
@@ -294,28 +303,22 @@ static __device__ void mrows_body(const SliceArgs &a, int ia) {
   }
   __syncthreads();
   const float *H = contract_slice<RM>(a, n, Sl, H0, H1);
-  // M[ia][b] = sum_c H[c] G[(pc * Rn + b) * post + qc]; thread (b, chunk), chunks added in order
-  const int nchunk = std::min(16, kSliceThreads / Rn);
-  const int b = tid % Rn, ch = tid / Rn;
-  float acc = 0.f;
-  if (ch < nchunk) {
-    const int c0 = (int)((int64_t)slice * ch / nchunk), c1 = (int)((int64_t)slice * (ch + 1) / nchunk);
-    int pc = c0 / post, qc = c0 - (c0 / post) * post;
+  // M[ia][b] = sum_c H[c] G[(pc * Rn + b) * post + qc]: half a wave per b (Rn <= 32 halves of
+  // 32 lanes in the block); lane j adds c = j, j + 32, ... in order, and the 32 partial sums
+  // meet in a fixed butterfly within the half.
+  const int half = tid >> 5, l32 = tid & 31;
+  if (half < Rn) {
+    const int b = half;
+    const float inv_post = 1.0f / post;
+    float acc = 0.f;
 #pragma unroll 4
-    for (int c = c0; c < c1; ++c) {
+    for (int c = l32; c < slice; c += 32) {
+      const int pc = qdiv(c, inv_post), qc = c - pc * post;
       acc = fmaf(H[c], G[(pc * Rn + b) * post + qc], acc);
-      if (++qc == post) {
-        qc = 0;
-        ++pc;
-      }
     }
-  }
-  red[tid] = ch < nchunk ? acc : 0.f;
-  __syncthreads();
-  if (tid < Rn) {
-    float s = 0.f;
-    for (int c = 0; c < nchunk; ++c) s += red[c * Rn + tid];
-    a.M[ia * Rn + tid] = s;
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 32);
+    if (l32 == 0) a.M[ia * Rn + b] = acc;
   }
 }
 
@@ -399,20 +402,44 @@ __global__ __launch_bounds__(kSliceThreads) void denB_k(SliceArgs a) {
   const int tid = threadIdx.x, i = blockIdx.x;
   const int R0 = a.R[0];
   const int slice = a.gsize / R0;
-  if (tid < R0) s0[tid] = a.S[0][tid * R0 + i];  // S_0[i'][i], i' = tid
+  // A slice that one pass of the block covers (the usual case) has every global read of its
+  // entry issued before the barrier, beside S_0's: one memory round trip in all.  The R0
+  // terms are unrolled to 32 with clamped rows and zero weights past R0, so the sum runs in
+  // the same order as the general loop below.
+  const bool one = slice <= kSliceThreads;
+  float tv[32], gv = 0.f, nv = 0.f;
+  if (one && tid < slice) {
+#pragma unroll
+    for (int ip = 0; ip < 32; ++ip) tv[ip] = a.T[(int64_t)(ip < R0 ? ip : R0 - 1) * slice + tid];
+    gv = a.G[(int64_t)i * slice + tid];
+    nv = a.numG[(int64_t)i * slice + tid];
+  }
+  if (tid < 32) s0[tid] = tid < R0 ? a.S[0][tid * R0 + i] : 0.f;  // S_0[i'][i], i' = tid
   if (tid == 0) nclip = 0;
   __syncthreads();
   unsigned int mine = 0;
-  for (int c = tid; c < slice; c += kSliceThreads) {
-    float den = 0.f;
-    for (int ip = 0; ip < R0; ++ip) den = fmaf(s0[ip], a.T[(int64_t)ip * slice + c], den);
+  auto update = [&](int c, float den, float g, float num) {
     double dd = (double)den;
     if (dd < a.eps) {
       dd = a.eps;
       ++mine;
     }
-    const int64_t e = (int64_t)i * slice + c;
-    a.Gout[e] = (float)(((double)a.G[e] * (double)a.numG[e]) / dd);
+    a.Gout[(int64_t)i * slice + c] = (float)(((double)g * (double)num) / dd);
+  };
+  if (one) {
+    if (tid < slice) {
+      float den = 0.f;
+#pragma unroll
+      for (int ip = 0; ip < 32; ++ip) den = fmaf(s0[ip], tv[ip], den);
+      update(tid, den, gv, nv);
+    }
+  } else {
+    for (int c = tid; c < slice; c += kSliceThreads) {
+      float den = 0.f;
+      for (int ip = 0; ip < R0; ++ip) den = fmaf(s0[ip], a.T[(int64_t)ip * slice + c], den);
+      const int64_t e = (int64_t)i * slice + c;
+      update(c, den, a.G[e], a.numG[e]);
+    }
   }
   if (mine) atomicAdd(&nclip, mine);
   __syncthreads();
@@ -421,12 +448,12 @@ __global__ __launch_bounds__(kSliceThreads) void denB_k(SliceArgs a) {
 
 // =====================================================================================
 // out[p][r][q] = sum_n F[n*ldl + r*ldr] * in[p][n][q]   (R <= 32, FP32)
-// A block owns 64 consecutive (p, q) pairs, one per lane, and W = ceil(N / 32) waves (at
-// most 16), so that one round covers up to 512 rows of n with 32 rows per wave: each wave
-// issues its 32 X loads of the round before the first product, while the block stages the
-// round's factor rows in LDS (zero-padded to RM columns and past N, so rows past the end
-// contribute nothing).  The wave partial sums are added in wave order through LDS, which
-// the factor rows of the last round no longer need.  Adding splits of n in a second
+// A block owns 64 consecutive (p, q) pairs and W = ceil(N / 32) waves (at most 16), so that
+// one round covers up to 512 rows of n with 32 rows per wave; each wave multiplies its rows
+// on the FP32 matrix cores (the 64 pairs as four 16-row tiles of the product, the rank as one
+// or two 16-column tiles) with every load of the round issued before the first product.
+// Factor entries past R or N are zero, so rows past the end contribute nothing.  The wave
+// partial sums are added in wave order through LDS.  Adding splits of n in a second
 // pass or through a device-scope counter would give more blocks when P*Q is small, but
 // the release fence such a counter needs writes back the whole L2 of the XCD, which has
 // cost far more than the extra parallelism saves.
@@ -438,8 +465,7 @@ static int small_waves(int64_t N) {
   const int64_t w = (N + kSmallRows - 1) / kSmallRows;
   return (int)(w < 1 ? 1 : (w > kSmallMaxWaves ? kSmallMaxWaves : w));
 }
-// LDS of a block: the factor rows of a round (W*32 rows of RM) or the wave partial sums
-// (W of RM x 64), whichever is larger.
+// LDS of a block: the wave partial sums (W of RM x 64).
 static size_t small_lds(int W, int RM) { return (size_t)W * 64 * RM * sizeof(float); }
 
 struct SmallArgs {
@@ -452,80 +478,92 @@ struct SmallArgs {
   int W;  // waves that take rows (the block may hold more, which then only join barriers)
 };
 
-// Tile `tile` of the contraction; blockDim.x / 64 >= a.W.
+typedef float smf4 __attribute__((ext_vector_type(4)));
+
+// Tile `tile` of the contraction; blockDim.x / 64 >= a.W.  The products run on the FP32
+// matrix cores (v_mfma_f32_16x16x4_f32): in a wave, lane (li, lg) supplies the entry of the
+// partial tensor in column 16 c + li (c = 0..3, the tile's 64 columns) and row 4 s + lg of its
+// rows, and the factor entry of that row in rank column 16 t + li (t = 0, 1); its result
+// holds columns 16 c + 4 lg + v (v = 0..3) of rank column 16 t + li.  The factor entries
+// come from global memory (every block reads the same few kilobytes, held in L2) and are
+// loaded before the rows of `in`, so that the products of step s wait only for step s's
+// loads.
 template <int RM>
 static __device__ void small_body(const SmallArgs &a, int64_t tile) {
   extern __shared__ __attribute__((aligned(16))) float sm[];
+  constexpr int RT = RM > 16 ? 2 : 1;
   const float *__restrict__ in = a.in;
   const float *__restrict__ F = a.F;
   float *__restrict__ out = a.out;
   const int64_t P = a.P, N = a.N, Q = a.Q, ldl = a.ldl, ldr = a.ldr;
   const int R = a.R, W = a.W;
   const int tid = threadIdx.x;
-  const int lane = tid & 63;
+  const int lane = tid & 63, li = lane & 15, lg = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const bool active = w < W;
   const int64_t PQ = P * Q;
-  const int64_t e = tile * 64 + lane;
-  const int64_t ee = e < PQ ? e : 0;
-  const int64_t p = ee / Q, q = ee - (ee / Q) * Q;
-  const float *src = in + p * N * Q + q;
+  const float *src[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {  // the lane's column of each 16-column group
+    const int64_t e = tile * 64 + 16 * c + li;
+    const int64_t ee = e < PQ ? e : 0;
+    const int64_t p = ee / Q, q = ee - (ee / Q) * Q;
+    src[c] = in + p * N * Q + q;
+  }
   const int span = W * kSmallRows;  // rows of a round
-  float acc[RM];
+  smf4 acc[4][RT];
 #pragma unroll
-  for (int r = 0; r < RM; ++r) acc[r] = 0.f;
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int t = 0; t < RT; ++t) acc[c][t] = smf4{0.f, 0.f, 0.f, 0.f};
   for (int64_t nb = 0; active && nb < N; nb += span) {
-    // factor rows [nb, nb + span): RM * 32 values per wave, the wave's own rows.  They are
-    // loaded before the rows of `in`, so that staging them waits for them alone and the
-    // products of row u wait only for the first u + 1 rows of `in`.
-    constexpr int kStage = RM / 2;  // 32 * RM values over 64 lanes
-    float v[kStage];
+    constexpr int kSteps = kSmallRows / 4;
+    float fb[kSteps][RT];
 #pragma unroll
-    for (int u = 0; u < kStage; ++u) {
-      const int idx = lane + u * 64;
-      const int nn = idx / RM, r = idx - (idx / RM) * RM;
-      const int64_t n = nb + w * kSmallRows + nn;
-      const bool ok = n < N && r < R;
-      v[u] = F[(ok ? n : 0) * ldl + (ok ? r : 0) * ldr];
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    float x[kSmallRows];
+    for (int st = 0; st < kSteps; ++st) {
+      const int64_t n = nb + w * kSmallRows + 4 * st + lg;
 #pragma unroll
-    for (int u = 0; u < kSmallRows; ++u) {
-      int64_t n = nb + w * kSmallRows + u;
-      n = n < N ? n : N - 1;  // rows past N meet zero factor rows
-      x[u] = src[n * Q];
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    float *Fw = sm + w * kSmallRows * RM;
-#pragma unroll
-    for (int u = 0; u < kStage; ++u) {  // zeros masked in here, where the values are awaited
-      const int idx = lane + u * 64;
-      const int nn = idx / RM, r = idx - (idx / RM) * RM;
-      Fw[idx] = (nb + w * kSmallRows + nn < N && r < R) ? v[u] : 0.f;
-    }
-    // each wave reads only the rows it staged itself, and a wave's LDS operations take
-    // effect in issue order: the wave barrier only keeps the compiler from reordering
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int u = 0; u < kSmallRows; ++u) {
-      const float4 *f4 = reinterpret_cast<const float4 *>(Fw + u * RM);
-#pragma unroll
-      for (int r4 = 0; r4 < RM / 4; ++r4) {
-        const float4 f = f4[r4];
-        acc[4 * r4 + 0] = fmaf(f.x, x[u], acc[4 * r4 + 0]);
-        acc[4 * r4 + 1] = fmaf(f.y, x[u], acc[4 * r4 + 1]);
-        acc[4 * r4 + 2] = fmaf(f.z, x[u], acc[4 * r4 + 2]);
-        acc[4 * r4 + 3] = fmaf(f.w, x[u], acc[4 * r4 + 3]);
+      for (int t = 0; t < RT; ++t) {
+        const int r = 16 * t + li;
+        const bool ok = n < N && r < R;
+        fb[st][t] = F[(ok ? n : 0) * ldl + (ok ? r : 0) * ldr];
       }
     }
-    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+    float xv[kSteps][4];
+#pragma unroll
+    for (int st = 0; st < kSteps; ++st) {
+      int64_t n = nb + w * kSmallRows + 4 * st + lg;
+      n = n < N ? n : N - 1;  // rows past N meet zero factor entries
+#pragma unroll
+      for (int c = 0; c < 4; ++c) xv[st][c] = src[c][n * Q];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int st = 0; st < kSteps; ++st) {
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        // zero factor entries (past R or N) are selected here, where the values are awaited
+        const int64_t n = nb + w * kSmallRows + 4 * st + lg;
+        const float b = (n < N && 16 * t + li < R) ? fb[st][t] : 0.f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          acc[c][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[st][c], b, acc[c][t], 0, 0, 0);
+      }
+    }
   }
-  __syncthreads();  // every wave is done with the factor rows
   float *red = sm;  // red[w][r][64]
   if (active) {
 #pragma unroll
-    for (int r = 0; r < RM; ++r) red[(w * RM + r) * 64 + lane] = acc[r];
+    for (int t = 0; t < RT; ++t) {
+      const int r = 16 * t + li;
+      if (r < RM) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) red[(w * RM + r) * 64 + 16 * c + 4 * lg + v] = acc[c][t][v];
+      }
+    }
   }
   __syncthreads();
   for (int idx = tid; idx < RM * 64; idx += blockDim.x) {
