@@ -54,11 +54,6 @@ struct SliceLds {
   }
 };
 
-// a / b for 0 <= a < 2^22 and b >= 1 through the float reciprocal: (a + 0.5) / b lies at
-// least 0.5 / b from the nearest integer, and the rounding of inv_b and of the product moves
-// it by less than (a + 0.5) / b * 2^-23, which is smaller for such a.
-static __device__ inline int qdiv(int a, float inv_b) { return (int)(((float)a + 0.5f) * inv_b); }
-
 // Grams into LDS (row stride RM, zero padding); the gram mode's Gram is summed from the
 // partials (entries in groups of 4 when R^2 is a multiple of 4, else one by one; each group
 // by kSliceThreads / groups threads over contiguous ranges of partials, added in order).
@@ -363,11 +358,12 @@ __global__ __launch_bounds__(kSliceThreads) void denA_k(SliceArgs a) {
 }
 
 // numG[e] = sum_{b < nparts} part[b][e] (the core numerator from the last mode's row-block
-// partials), b in order from 0; the loads of a round of kSumB partials are all in flight.
+// partials), b in order from 0; the loads of a round of kSumB partials are all in flight
+// (one round for factors up to 512 rows).
 static __device__ void sum_body(const float *__restrict__ part, int nparts, int n,
                                 float *__restrict__ out, int e) {
   if (e >= n) return;
-  constexpr int kSumB = 32;
+  constexpr int kSumB = 64;
   float s2 = 0.f;
   for (int b0 = 0; b0 < nparts; b0 += kSumB) {
     float v[kSumB];

@@ -12,6 +12,11 @@ namespace nnc {
 
 constexpr int kMaxDim = 8;
 
+// a / b for 0 <= a < 2^22 and b >= 1 through the float reciprocal: (a + 0.5) / b lies at
+// least 0.5 / b from the nearest integer, and the rounding of inv_b and of the product moves
+// it by less than (a + 0.5) / b * 2^-23, which is smaller for such a.
+static __device__ inline int qdiv(int a, float inv_b) { return (int)(((float)a + 0.5f) * inv_b); }
+
 // Sets the thread-local error message and returns `st`.
 nnc_status fail(nnc_status st, const char *fmt, ...);
 

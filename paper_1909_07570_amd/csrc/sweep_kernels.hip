@@ -48,11 +48,20 @@ constexpr int kRowRed = 4096;             // partial sums of the contraction (fl
 //   kPathS : anything else, one output per thread, scalar reads
 enum { kPathQ4 = 0, kPathP = 1, kPathS = 2 };
 
-// LDS (dynamic): the chunk of G and of the block's Y rows in their natural layouts,
-//   Gs[(pl * R + r) * qn + qq] = G[p0 + pl][r][q0 + qq]
-//   Ys[(pl * nr + i) * qn + qq] = Y[p0 + pl][i0 + i][q0 + qq]
+// LDS (dynamic): the chunk of G and of the block's Y rows in their natural layouts, rows of
+// qn values at a stride of qs floats,
+//   Gs[(pl * R + r) * qs + qq] = G[p0 + pl][r][q0 + qq]
+//   Ys[(pl * nr + i) * qs + qq] = Y[p0 + pl][i0 + i][q0 + qq]
 // A chunk is pn whole slices p (qn = post) when they fit, else a quad-aligned q range of
-// one slice.  Staging is a plain copy: consecutive threads read consecutive addresses.
+// one slice.  Staging is a copy: consecutive threads read consecutive addresses.  In the
+// quad path qs is an odd number of quads (qn, or qn + 4), so the rows that one wave's
+// 16-byte reads touch start in different bank groups.  Elsewhere qs = qn.
+// Index arithmetic is kept off the quarter-rate integer multiplier: divisions go through
+// float reciprocals (qdiv), and the contraction walks LDS pointers with a fixed jump at the
+// end of a slice.  The contraction issues the reads of kUn steps before their products, so
+// one LDS latency covers kUn steps; each accumulator still takes its terms in c order.
+constexpr int kUn = 4;
+
 template <int PATH>
 __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict__ Y,
                                                          const float *__restrict__ G,
@@ -72,25 +81,28 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
   const int i0 = blockIdx.x * kRB;
   const int nr = (Nn - i0) < kRB ? (Nn - i0) : kRB;
   if (tid == 0) nclip = 0;
+  const float inv_R = 1.0f / (float)R;
   // work items and splits of the contraction (every chunk uses the same assignment, so a
   // thread's partial sums carry across chunks)
   const int RH = (R + 1) / 2, RQ = R / 4, NH = (nr + 1) / 2;
   const int items = PATH == kPathQ4 ? nr * RH : (PATH == kPathP ? NH * RQ : nr * R);
-  const int SPL = kRowThreads / items;  // >= 1: items <= 8 * 32
-  const int item = tid % items, sp = tid / items;
+  const float inv_items = 1.0f / (float)items;
+  const int SPL = qdiv(kRowThreads, inv_items);  // >= 1: items <= 8 * 32
+  const int sp = qdiv(tid, inv_items), item = tid - sp * items;
   const bool act = sp < SPL;
+  const float inv_spl = 1.0f / (float)SPL;
   int ii, rr;  // first row / column of the item
-  if (PATH == kPathQ4) { ii = item / RH; rr = 2 * (item - ii * RH); }
-  else if (PATH == kPathP) { ii = 2 * (item / RQ); rr = 4 * (item - (item / RQ) * RQ); }
-  else { ii = item / R; rr = item - ii * R; }
+  if (PATH == kPathQ4) { ii = qdiv(item, 1.0f / (float)RH); rr = 2 * (item - ii * RH); }
+  else if (PATH == kPathP) { const int g = qdiv(item, 1.0f / (float)RQ); ii = 2 * g; rr = 4 * (item - g * RQ); }
+  else { ii = qdiv(item, inv_R); rr = item - ii * R; }
   constexpr int NO = PATH == kPathQ4 ? 2 : (PATH == kPathP ? 8 : 1);  // outputs per item
   float acc[NO];
 #pragma unroll
   for (int o = 0; o < NO; ++o) acc[o] = 0.f;
-  // factor rows and M, loaded with the first chunk's reads
-  const int ai = tid < nr * R ? tid : 0;
-  const float av = A[(int64_t)(i0 + ai / R) * R + ai % R];
+  // factor rows and M, loaded with the first chunk's reads (rows i0 .. i0 + nr are
+  // contiguous: element tid of the block's rows is A[i0 * R + tid])
   const int RR = R * R;
+  const float av = A[(int64_t)i0 * R + (tid < nr * R ? tid : 0)];
   const float mv0 = M[tid < RR ? tid : 0];
   const float mv1 = M[tid + kRowThreads < RR ? tid + kRowThreads : 0];
   constexpr int kSG = 16, kSY = 8;  // staged values per thread and round
@@ -100,61 +112,134 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
     for (int q0 = 0; q0 < post; q0 += QC) {
       const int qn = (post - q0) < QC ? (post - q0) : QC;
       const bool whole = qn == post;  // whole slices: G and Y chunk offsets are linear
-      const int ng = pn * R * qn, ny = pn * nr * qn;
-      float *Gs = dynr, *Ys = dynr + ng;
-      const UDiv dqn = make_udiv(qn), dyq = make_udiv(nr * qn);
+      const int ng = pn * R * qn, ny = pn * nr * qn;  // both below 2^14 (the LDS budget)
+      const int nrq = nr * qn;
+      const int qs = PATH == kPathQ4 && ((qn >> 2) & 1) == 0 ? qn + 4 : qn;
+      float *Gs = dynr, *Ys = dynr + pn * R * qs;
+      const float inv_qn = 1.0f / (float)qn, inv_nrq = 1.0f / (float)nrq;
+      const float *Gc = G + (int64_t)p0 * R * post + q0;
+      const float *Yc = Y + ((int64_t)p0 * Nn + i0) * post + q0;
+      const int64_t ystride = (int64_t)Nn * post;  // from one slice p of Y to the next
       __syncthreads();  // the previous chunk's reads are done
-      // source index of staged element e (whole slices: linear in e; else one slice's
-      // q range, e = r * qn + qq for G and i * qn + qq for Y)
-      auto g_index = [&](int e) -> int64_t {
-        if (whole) return (int64_t)p0 * R * post + e;
-        const int r = udiv(e, dqn);
-        return ((int64_t)p0 * R + r) * post + q0 + (e - r * qn);
+      auto lds_index = [&](int e) -> int {  // row e / qn at stride qs
+        if (PATH != kPathQ4) return e;
+        return e + (qs - qn) * qdiv(e, inv_qn);
       };
-      auto y_index = [&](int e) -> int64_t {
-        const int pl = udiv(e, dyq), rem = e - pl * (nr * qn);
-        if (whole) return ((int64_t)(p0 + pl) * Nn + i0) * post + rem;
-        const int i = udiv(rem, dqn);
-        return ((int64_t)p0 * Nn + i0 + i) * post + q0 + (rem - i * qn);
-      };
-      auto stage = [&](auto gidx, auto yidx) {
+      auto stage = [&](auto goff, auto yoff) {
         for (int gb = 0, yb = 0; gb < ng || yb < ny; gb += kSG * kRowThreads, yb += kSY * kRowThreads) {
           float vg[kSG], vy[kSY];
 #pragma unroll
           for (int u = 0; u < kSG; ++u) {
             const int e = gb + tid + u * kRowThreads;
-            vg[u] = G[gidx(e < ng ? e : ng - 1)];  // past the end: the last value again
+            vg[u] = Gc[goff(e < ng ? e : ng - 1)];  // past the end: the last value again
           }
 #pragma unroll
           for (int u = 0; u < kSY; ++u) {
             const int e = yb + tid + u * kRowThreads;
-            vy[u] = Y[yidx(e < ny ? e : ny - 1)];
+            vy[u] = Yc[yoff(e < ny ? e : ny - 1)];
           }
 #pragma unroll
           for (int u = 0; u < kSG; ++u) {
             const int e = gb + tid + u * kRowThreads;
-            Gs[e < ng ? e : ng - 1] = vg[u];
+            Gs[lds_index(e < ng ? e : ng - 1)] = vg[u];
           }
 #pragma unroll
           for (int u = 0; u < kSY; ++u) {
             const int e = yb + tid + u * kRowThreads;
-            Ys[e < ny ? e : ny - 1] = vy[u];
+            Ys[lds_index(e < ny ? e : ny - 1)] = vy[u];
           }
         }
       };
-      // the uniform choice made once, outside the loads
-      if (whole)
-        stage([&](int e) -> int64_t { return (int64_t)p0 * R * post + e; },
+      // 16-byte staging when G and Y are 16-byte aligned: the quad path (rows of qn / 4 quads,
+      // at qs / 4 in LDS) and the slice path when its rows come in whole quads (nr and Nn
+      // multiples of 4).  Offsets and LDS indices count quads; G and Y rows are
+      // row_G = pl * R + r and row_Y = pl * nr + i of the chunk.
+      const bool al = ((reinterpret_cast<uintptr_t>(G) | reinterpret_cast<uintptr_t>(Y)) & 15) == 0;
+      if (al && (PATH == kPathQ4 || (PATH == kPathP && (nr & 3) == 0 && (Nn & 3) == 0))) {
+        const int nq = PATH == kPathQ4 ? qn >> 2 : nr >> 2;  // quads of a row / of one p
+        const int sq = qs >> 2, post4 = post >> 2;
+        const float inv_nq = 1.0f / (float)nq, inv_nr = 1.0f / (float)nr;
+        const int64_t ys4 = ystride >> 2;
+        const int ngq = ng >> 2, nyq = ny >> 2;
+        const float4 *G4 = reinterpret_cast<const float4 *>(Gc);
+        const float4 *Y4 = reinterpret_cast<const float4 *>(Yc);
+        float4 *Gs4 = reinterpret_cast<float4 *>(Gs), *Ys4 = reinterpret_cast<float4 *>(Ys);
+        constexpr int kQG = 4, kQY = 2;
+        for (int gb = 0, yb = 0; gb < ngq || yb < nyq; gb += kQG * kRowThreads, yb += kQY * kRowThreads) {
+          float4 vg[kQG], vy[kQY];
+          int gl[kQG], yl[kQY];
+#pragma unroll
+          for (int u = 0; u < kQG; ++u) {
+            const int e = min(gb + tid + u * kRowThreads, ngq - 1);  // past the end: the last again
+            int64_t off = e;
+            int l = e;
+            if (PATH == kPathQ4) {
+              const int row = qdiv(e, inv_nq), c = e - __umul24(row, nq);
+              off = (int64_t)row * post4 + c;
+              l = __umul24(row, sq) + c;
+            }
+            vg[u] = G4[off];
+            gl[u] = l;
+          }
+#pragma unroll
+          for (int u = 0; u < kQY; ++u) {
+            const int e = min(yb + tid + u * kRowThreads, nyq - 1);
+            int64_t off;
+            int l = e;
+            if (PATH == kPathQ4) {
+              const int row = qdiv(e, inv_nq), c = e - __umul24(row, nq);
+              const int pl = qdiv(row, inv_nr), i = row - __umul24(pl, nr);
+              off = (int64_t)pl * ys4 + (int64_t)i * post4 + c;
+              l = __umul24(row, sq) + c;
+            } else {
+              const int pl = qdiv(e, inv_nq);
+              off = (int64_t)pl * ys4 + (e - __umul24(pl, nq));
+            }
+            vy[u] = Y4[off];
+            yl[u] = l;
+          }
+#pragma unroll
+          for (int u = 0; u < kQG; ++u) Gs4[gl[u]] = vg[u];
+#pragma unroll
+          for (int u = 0; u < kQY; ++u) Ys4[yl[u]] = vy[u];
+        }
+      } else if (whole && ystride < ((int64_t)1 << 32)) {
+        // the uniform choice made once, outside the loads; whole slices: e = pl * nr * qn +
+        // (i * qn + qq) in Y, one 32 x 32 -> 64-bit multiply when the slice stride allows
+        const unsigned ys = (unsigned)ystride;
+        stage([&](int e) -> int64_t { return e; },
               [&](int e) -> int64_t {
-                const int pl = udiv(e, dyq);
-                return ((int64_t)(p0 + pl) * Nn + i0) * post + (e - pl * (nr * qn));
+                const int pl = qdiv(e, inv_nrq);
+                return (int64_t)((uint64_t)(unsigned)pl * ys) + (e - __umul24(pl, nrq));
               });
-      else
-        stage(g_index, y_index);
+      } else if (whole) {
+        stage([&](int e) -> int64_t { return e; },
+              [&](int e) -> int64_t {
+                const int pl = qdiv(e, inv_nrq);
+                return (int64_t)pl * ystride + (e - __umul24(pl, nrq));
+              });
+      } else  // one slice, e = r * qn + qq (G) or i * qn + qq (Y)
+        stage([&](int e) -> int64_t {
+                const int r = qdiv(e, inv_qn);
+                return (int64_t)r * post + (e - __umul24(r, qn));
+              },
+              [&](int e) -> int64_t {
+                const int i = qdiv(e, inv_qn);
+                return (int64_t)i * post + (e - __umul24(i, qn));
+              });
       if (first) {
-        if (tid < nr * R) As[tid / R][tid % R] = av;
-        if (tid < RR) Ms[tid / R][tid % R] = mv0;
-        if (tid + kRowThreads < RR) Ms[(tid + kRowThreads) / R][(tid + kRowThreads) % R] = mv1;
+        if (tid < nr * R) {
+          const int i = qdiv(tid, inv_R);
+          As[i][tid - i * R] = av;
+        }
+        if (tid < RR) {
+          const int s = qdiv(tid, inv_R);
+          Ms[s][tid - s * R] = mv0;
+        }
+        if (tid + kRowThreads < RR) {
+          const int s = qdiv(tid + kRowThreads, inv_R);
+          Ms[s][tid + kRowThreads - s * R] = mv1;
+        }
         first = false;
       }
       __syncthreads();
@@ -162,33 +247,60 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
         if (PATH == kPathQ4) {
           // quads u = pl * (qn / 4) + q4 over [u0, u1)
           const int nq4 = qn >> 2, U = pn * nq4;
-          const int u0 = U * sp / SPL, u1 = U * (sp + 1) / SPL;
-          const bool two = rr + 1 < R;
-          int pl = u0 / nq4, q4 = u0 - pl * nq4;
-          for (int u = u0; u < u1; ++u) {
-            const float4 y = *reinterpret_cast<const float4 *>(Ys + (pl * nr + ii) * qn + 4 * q4);
-            const float4 ga = *reinterpret_cast<const float4 *>(Gs + (pl * R + rr) * qn + 4 * q4);
-            const float4 gb2 = *reinterpret_cast<const float4 *>(Gs + (pl * R + (two ? rr + 1 : rr)) * qn + 4 * q4);
+          const int u0 = qdiv(U * sp, inv_spl), u1 = qdiv(U * (sp + 1), inv_spl);
+          int pl = qdiv(u0, 1.0f / (float)nq4), q4 = u0 - pl * nq4;
+          const float *yp = Ys + (pl * nr + ii) * qs + 4 * q4;
+          const float *gp = Gs + (pl * R + rr) * qs + 4 * q4;
+          const int go = rr + 1 < R ? qs : 0;                   // the item's second column
+          const int yj = nr * qs - qn, gj = R * qs - qn;        // row end -> same row, next slice
+          auto step = [&](float4 &y, float4 &ga, float4 &gb) {
+            y = *reinterpret_cast<const float4 *>(yp);
+            ga = *reinterpret_cast<const float4 *>(gp);
+            gb = *reinterpret_cast<const float4 *>(gp + go);
+            yp += 4;
+            gp += 4;
+            const bool wrap = ++q4 == nq4;
+            q4 = wrap ? 0 : q4;
+            yp += wrap ? yj : 0;
+            gp += wrap ? gj : 0;
+          };
+          auto prod = [&](const float4 &y, const float4 &ga, const float4 &gb) {
             acc[0] = fmaf(y.x, ga.x, acc[0]);
             acc[0] = fmaf(y.y, ga.y, acc[0]);
             acc[0] = fmaf(y.z, ga.z, acc[0]);
             acc[0] = fmaf(y.w, ga.w, acc[0]);
-            acc[1] = fmaf(y.x, gb2.x, acc[1]);
-            acc[1] = fmaf(y.y, gb2.y, acc[1]);
-            acc[1] = fmaf(y.z, gb2.z, acc[1]);
-            acc[1] = fmaf(y.w, gb2.w, acc[1]);
-            if (++q4 == nq4) {
-              q4 = 0;
-              ++pl;
-            }
+            acc[1] = fmaf(y.x, gb.x, acc[1]);
+            acc[1] = fmaf(y.y, gb.y, acc[1]);
+            acc[1] = fmaf(y.z, gb.z, acc[1]);
+            acc[1] = fmaf(y.w, gb.w, acc[1]);
+          };
+          int u = u0;
+          for (; u + kUn <= u1; u += kUn) {
+            float4 y[kUn], ga[kUn], gb[kUn];
+#pragma unroll
+            for (int k = 0; k < kUn; ++k) step(y[k], ga[k], gb[k]);
+#pragma unroll
+            for (int k = 0; k < kUn; ++k) prod(y[k], ga[k], gb[k]);
+          }
+          for (; u < u1; ++u) {
+            float4 y, ga, gb;
+            step(y, ga, gb);
+            prod(y, ga, gb);
           }
         } else if (PATH == kPathP) {
           // qn == 1: Ys[pl * nr + i], Gs[pl * R + r]
-          const int u0 = pn * sp / SPL, u1 = pn * (sp + 1) / SPL;
-          const bool two = ii + 1 < nr;
-          for (int pl = u0; pl < u1; ++pl) {
-            const float y0 = Ys[pl * nr + ii], y1 = Ys[pl * nr + (two ? ii + 1 : ii)];
-            const float4 g = *reinterpret_cast<const float4 *>(Gs + pl * R + rr);
+          const int u0 = qdiv(pn * sp, inv_spl), u1 = qdiv(pn * (sp + 1), inv_spl);
+          const int yo = ii + 1 < nr ? 1 : 0;  // the item's second row
+          const float *yp = Ys + u0 * nr + ii;
+          const float *gp = Gs + u0 * R + rr;
+          auto step = [&](float &y0, float &y1, float4 &g) {
+            y0 = yp[0];
+            y1 = yp[yo];
+            g = *reinterpret_cast<const float4 *>(gp);
+            yp += nr;
+            gp += R;
+          };
+          auto prod = [&](float y0, float y1, const float4 &g) {
             acc[0] = fmaf(y0, g.x, acc[0]);
             acc[1] = fmaf(y0, g.y, acc[1]);
             acc[2] = fmaf(y0, g.z, acc[2]);
@@ -197,17 +309,50 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
             acc[5] = fmaf(y1, g.y, acc[5]);
             acc[6] = fmaf(y1, g.z, acc[6]);
             acc[7] = fmaf(y1, g.w, acc[7]);
+          };
+          int u = u0;
+          for (; u + kUn <= u1; u += kUn) {
+            float y0[kUn], y1[kUn];
+            float4 g[kUn];
+#pragma unroll
+            for (int k = 0; k < kUn; ++k) step(y0[k], y1[k], g[k]);
+#pragma unroll
+            for (int k = 0; k < kUn; ++k) prod(y0[k], y1[k], g[k]);
+          }
+          for (; u < u1; ++u) {
+            float y0, y1;
+            float4 g;
+            step(y0, y1, g);
+            prod(y0, y1, g);
           }
         } else {
+          // c = pl * qn + qq over [u0, u1), one output
           const int Cn = pn * qn;
-          const int u0 = Cn * sp / SPL, u1 = Cn * (sp + 1) / SPL;
-          int pl = udiv(u0, dqn), qq = u0 - pl * qn;
-          for (int u = u0; u < u1; ++u) {
-            acc[0] = fmaf(Ys[(pl * nr + ii) * qn + qq], Gs[(pl * R + rr) * qn + qq], acc[0]);
-            if (++qq == qn) {
-              qq = 0;
-              ++pl;
-            }
+          const int u0 = qdiv(Cn * sp, inv_spl), u1 = qdiv(Cn * (sp + 1), inv_spl);
+          int pl = qdiv(u0, inv_qn), qq = u0 - pl * qn;
+          const float *yp = Ys + (pl * nr + ii) * qn + qq;
+          const float *gp = Gs + (pl * R + rr) * qn + qq;
+          const int yj = (nr - 1) * qn, gj = (R - 1) * qn;
+          auto step = [&](float &y, float &g) {
+            y = *yp++;
+            g = *gp++;
+            const bool wrap = ++qq == qn;
+            qq = wrap ? 0 : qq;
+            yp += wrap ? yj : 0;
+            gp += wrap ? gj : 0;
+          };
+          int u = u0;
+          for (; u + kUn <= u1; u += kUn) {
+            float y[kUn], g[kUn];
+#pragma unroll
+            for (int k = 0; k < kUn; ++k) step(y[k], g[k]);
+#pragma unroll
+            for (int k = 0; k < kUn; ++k) acc[0] = fmaf(y[k], g[k], acc[0]);
+          }
+          for (; u < u1; ++u) {
+            float y, g;
+            step(y, g);
+            acc[0] = fmaf(y, g, acc[0]);
           }
         }
       }
@@ -233,12 +378,14 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
   }
   __syncthreads();
   const bool own = tid < NRR;  // thread tid owns output (tid / R, tid % R) from here
-  const int oi = tid / R, orr = tid - (tid / R) * R;
+  const int oi = qdiv(tid, inv_R), orr = tid - oi * R;
   float nv = 0.f;
   if (own) {
     float num = 0.f;
+#pragma unroll 8
     for (int k = 0; k < SPL; ++k) num += red[k * NRR + tid];
     float den = 0.f;
+#pragma unroll 4
     for (int s2 = 0; s2 < R; ++s2) den = fmaf(As[oi][s2], Ms[s2][orr], den);
     if (grad) {
       nv = den - num;
@@ -254,9 +401,9 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
   __syncthreads();
   if (own) {
     if (grad) {
-      grad[(int64_t)(i0 + oi) * R + orr] = nv;
+      grad[(int64_t)i0 * R + tid] = nv;
     } else {
-      A[(int64_t)(i0 + oi) * R + orr] = nv;
+      A[(int64_t)i0 * R + tid] = nv;
       As[oi][orr] = nv;
     }
   }
@@ -265,10 +412,15 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
   if (grad) return;
   if (gram) {  // Gram of this block's new rows (the arithmetic of gram_parts_k)
     float *gb = gram + (int64_t)blockIdx.x * R * R;
-    for (int idx = tid; idx < R * R; idx += kRowThreads) {
-      const int x = idx / R, y = idx - (idx / R) * R;
+    for (int idx = tid; idx < RR; idx += kRowThreads) {
+      const int x = qdiv(idx, inv_R), y = idx - x * R;
       float s2 = 0.f;
-      for (int i = 0; i < nr; ++i) s2 = fmaf(As[i][x], As[i][y], s2);
+#pragma unroll
+      for (int i = 0; i < kRB; ++i) {  // rows past nr read row nr - 1 and are not added
+        const int ic = i < nr ? i : nr - 1;
+        const float t = fmaf(As[ic][x], As[ic][y], s2);
+        s2 = i < nr ? t : s2;
+      }
       gb[idx] = s2;
     }
   }
@@ -277,33 +429,49 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
     float *gp = gpart + (int64_t)blockIdx.x * pre * R;
     if (PC >= pre) {
       // one chunk: the Y rows are still in LDS, Ys[p * nr + i]; thread (g, r4) keeps
-      // columns r4 .. r4 + 3 of the new rows in registers
+      // columns r4 .. r4 + 3 of the new rows in registers (zero past R)
       const float *Ys = dynr + pre * R;
       const int RQ4 = (R + 3) / 4;
-      const int ng2 = kRowThreads / RQ4;
-      const int g = tid / RQ4, r4 = 4 * (tid - (tid / RQ4) * RQ4);
+      const float inv_rq4 = 1.0f / (float)RQ4;
+      const int ng2 = qdiv(kRowThreads, inv_rq4);
+      const int g = qdiv(tid, inv_rq4), r4 = 4 * (tid - g * RQ4);
+      const bool vec = (R & 3) == 0;  // whole float4 rows (gpart is 16-byte aligned)
       if (g < ng2) {
         float ar[kRB][4];
 #pragma unroll
         for (int i = 0; i < kRB; ++i)
 #pragma unroll
-          for (int k = 0; k < 4; ++k) ar[i][k] = (i < nr && r4 + k < R) ? As[i][r4 + k] : 0.f;
+          for (int k = 0; k < 4; ++k) {
+            const int ic = i < nr ? i : nr - 1, kc = r4 + k < R ? r4 + k : R - 1;
+            const float a = As[ic][kc];
+            ar[i][k] = r4 + k < R ? a : 0.f;
+          }
         for (int pp = g; pp < pre; pp += ng2) {
           float s4[4] = {0.f, 0.f, 0.f, 0.f};
+          const float *yr = Ys + pp * nr;
 #pragma unroll
           for (int i = 0; i < kRB; ++i) {
-            const float y = i < nr ? Ys[pp * nr + i] : 0.f;
+            const float y = yr[i < nr ? i : nr - 1];  // rows past nr are not added
 #pragma unroll
-            for (int k = 0; k < 4; ++k) s4[k] = fmaf(y, ar[i][k], s4[k]);
+            for (int k = 0; k < 4; ++k) {
+              const float t = fmaf(y, ar[i][k], s4[k]);
+              s4[k] = i < nr ? t : s4[k];
+            }
           }
+          float *dst = gp + (int64_t)pp * R + r4;
+          if (vec) {
+            *reinterpret_cast<float4 *>(dst) = make_float4(s4[0], s4[1], s4[2], s4[3]);
+          } else {
 #pragma unroll
-          for (int k = 0; k < 4; ++k)
-            if (r4 + k < R) gp[(int64_t)pp * R + r4 + k] = s4[k];
+            for (int k = 0; k < 4; ++k)
+              if (r4 + k < R) dst[k] = s4[k];
+          }
         }
       }
     } else {
-      // several chunks: read the Y rows again, pieces of PC2 rows p
-      const int PC2 = kRowLdsFloats / kRB;
+      // several chunks: read the Y rows again, pieces of PC2 rows p (the block's dynamic LDS
+      // holds PC * (R + kRB) floats when post == 1)
+      const int PC2 = PC * (R + kRB) / kRB;
       for (int p0 = 0; p0 < pre; p0 += PC2) {
         const int pn = (pre - p0) < PC2 ? (pre - p0) : PC2;
         __syncthreads();
@@ -330,19 +498,21 @@ nnc_status launch_mu_rows(const float *Y, const float *G, float *A, const float 
   if (pre * post > (int64_t)1 << 30 || Nn > (int64_t)1 << 30)
     return fail(NNC_EUNSUPPORTED, "mu_rows: sizes above 2^30");
   if (gpart && post != 1) return fail(NNC_EINVAL, "mu_rows: core-numerator partials need post == 1");
-  // chunks: whole slices p when one fits, else quad-aligned q ranges of one slice
+  // chunks: whole slices p when one fits, else quad-aligned q ranges of one slice; rows
+  // in the quad path take up to 4 floats of padding in LDS
+  const int path = (post % 4 == 0) ? kPathQ4 : ((post == 1 && R % 4 == 0) ? kPathP : kPathS);
+  const int64_t pad = path == kPathQ4 ? 4 : 0;
   int64_t PC, QC;
-  const int64_t slice = (R + kRB) * post;
+  const int64_t slice = (R + kRB) * (post + pad);
   if (slice <= kRowLdsFloats) {
     PC = kRowLdsFloats / slice;
     if (PC > pre) PC = pre;
     QC = post;
   } else {
     PC = 1;
-    QC = kRowLdsFloats / (R + kRB) / 4 * 4;
+    QC = (kRowLdsFloats / (R + kRB) - pad) / 4 * 4;
   }
-  const size_t lds = (size_t)(PC * (R + kRB) * QC) * sizeof(float);
-  const int path = (post % 4 == 0) ? kPathQ4 : ((post == 1 && R % 4 == 0) ? kPathP : kPathS);
+  const size_t lds = (size_t)(PC * (R + kRB) * (QC + pad)) * sizeof(float);
   const int64_t blocks = (Nn + kRB - 1) / kRB;
 #define NNC_MU(PV)                                                                                \
   hipLaunchKernelGGL(mu_rows_k<PV>, dim3((unsigned)blocks), dim3(kRowThreads), lds, s, Y, G, A, M, \
