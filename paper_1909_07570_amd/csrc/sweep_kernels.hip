@@ -73,8 +73,10 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
                                                          float *__restrict__ gpart,
                                                          float *__restrict__ grad) {
   extern __shared__ __attribute__((aligned(16))) float dynr[];
-  __shared__ float As[kRB][33];
-  __shared__ float Ms[32][33];
+  // the block's rows of A_n and M_n transposed, zero past nr / R, rows of 36 floats (an odd
+  // number of 16-byte quads) for the 16-byte reads of the denominator
+  __shared__ __attribute__((aligned(16))) float As[kRB][36];
+  __shared__ __attribute__((aligned(16))) float MsT[32][36];
   __shared__ __attribute__((aligned(16))) float red[kRowRed];
   __shared__ unsigned int nclip;
   const int tid = threadIdx.x;
@@ -99,12 +101,16 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
   float acc[NO];
 #pragma unroll
   for (int o = 0; o < NO; ++o) acc[o] = 0.f;
-  // factor rows and M, loaded with the first chunk's reads (rows i0 .. i0 + nr are
-  // contiguous: element tid of the block's rows is A[i0 * R + tid])
+  // factor rows and M, loaded with the first chunk's reads: thread t < 256 takes As[t / 32]
+  // [t % 32], and entries t and t + 512 of MsT[r][s] = M[s][r] (32 x 32 with zero padding)
   const int RR = R * R;
-  const float av = A[(int64_t)i0 * R + (tid < nr * R ? tid : 0)];
-  const float mv0 = M[tid < RR ? tid : 0];
-  const float mv1 = M[tid + kRowThreads < RR ? tid + kRowThreads : 0];
+  const int ai = tid >> 5, ac = tid & 31;
+  const bool aok = tid < kRB * 32 && ai < nr && ac < R;
+  const float av0 = A[(int64_t)i0 * R + (aok ? ai * R + ac : 0)];
+  const int mr0 = tid >> 5, ms0 = tid & 31, mr1 = mr0 + 16;
+  const bool mok0 = mr0 < R && ms0 < R, mok1 = mr1 < R && ms0 < R;
+  const float mv0 = M[mok0 ? ms0 * R + mr0 : 0];
+  const float mv1 = M[mok1 ? ms0 * R + mr1 : 0];
   constexpr int kSG = 16, kSY = 8;  // staged values per thread and round
   bool first = true;
   for (int p0 = 0; p0 < pre; p0 += PC) {
@@ -228,18 +234,9 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
                 return (int64_t)i * post + (e - __umul24(i, qn));
               });
       if (first) {
-        if (tid < nr * R) {
-          const int i = qdiv(tid, inv_R);
-          As[i][tid - i * R] = av;
-        }
-        if (tid < RR) {
-          const int s = qdiv(tid, inv_R);
-          Ms[s][tid - s * R] = mv0;
-        }
-        if (tid + kRowThreads < RR) {
-          const int s = qdiv(tid + kRowThreads, inv_R);
-          Ms[s][tid + kRowThreads - s * R] = mv1;
-        }
+        if (tid < kRB * 32) As[ai][ac] = aok ? av0 : 0.f;
+        MsT[mr0][ms0] = mok0 ? mv0 : 0.f;
+        MsT[mr1][ms0] = mok1 ? mv1 : 0.f;
         first = false;
       }
       __syncthreads();
@@ -384,9 +381,18 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
     float num = 0.f;
 #pragma unroll 8
     for (int k = 0; k < SPL; ++k) num += red[k * NRR + tid];
+    // s = 0 .. 31 in order; the terms past R are zero times zero and leave den unchanged
+    const float4 *arow = reinterpret_cast<const float4 *>(As[oi]);
+    const float4 *mrow = reinterpret_cast<const float4 *>(MsT[orr]);
     float den = 0.f;
-#pragma unroll 4
-    for (int s2 = 0; s2 < R; ++s2) den = fmaf(As[oi][s2], Ms[s2][orr], den);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const float4 a = arow[q], m = mrow[q];
+      den = fmaf(a.x, m.x, den);
+      den = fmaf(a.y, m.y, den);
+      den = fmaf(a.z, m.z, den);
+      den = fmaf(a.w, m.w, den);
+    }
     if (grad) {
       nv = den - num;
     } else {
@@ -446,18 +452,7 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
             const float a = As[ic][kc];
             ar[i][k] = r4 + k < R ? a : 0.f;
           }
-        for (int pp = g; pp < pre; pp += ng2) {
-          float s4[4] = {0.f, 0.f, 0.f, 0.f};
-          const float *yr = Ys + pp * nr;
-#pragma unroll
-          for (int i = 0; i < kRB; ++i) {
-            const float y = yr[i < nr ? i : nr - 1];  // rows past nr are not added
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              const float t = fmaf(y, ar[i][k], s4[k]);
-              s4[k] = i < nr ? t : s4[k];
-            }
-          }
+        auto put = [&](int pp, const float (&s4)[4]) {
           float *dst = gp + (int64_t)pp * R + r4;
           if (vec) {
             *reinterpret_cast<float4 *>(dst) = make_float4(s4[0], s4[1], s4[2], s4[3]);
@@ -465,6 +460,35 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
 #pragma unroll
             for (int k = 0; k < 4; ++k)
               if (r4 + k < R) dst[k] = s4[k];
+          }
+        };
+        if (nr == kRB && vec) {
+          // whole blocks: the 8 values of row p are two 16-byte reads (Ys is 16-byte aligned)
+          for (int pp = g; pp < pre; pp += ng2) {
+            const float4 *yr = reinterpret_cast<const float4 *>(Ys + pp * kRB);
+            const float4 y0 = yr[0], y1 = yr[1];
+            const float yv[kRB] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w};
+            float s4[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int i = 0; i < kRB; ++i)
+#pragma unroll
+              for (int k = 0; k < 4; ++k) s4[k] = fmaf(yv[i], ar[i][k], s4[k]);
+            put(pp, s4);
+          }
+        } else {
+          for (int pp = g; pp < pre; pp += ng2) {
+            float s4[4] = {0.f, 0.f, 0.f, 0.f};
+            const float *yr = Ys + pp * nr;
+#pragma unroll
+            for (int i = 0; i < kRB; ++i) {
+              const float y = yr[i < nr ? i : nr - 1];  // rows past nr are not added
+#pragma unroll
+              for (int k = 0; k < 4; ++k) {
+                const float t = fmaf(y, ar[i][k], s4[k]);
+                s4[k] = i < nr ? t : s4[k];
+              }
+            }
+            put(pp, s4);
           }
         }
       }
