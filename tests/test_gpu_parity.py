@@ -170,6 +170,36 @@ def test_nntucker_few_sweeps_match_oracle(dims, ranks, use_graph):
     assert rep.eps_clips == 0
 
 
+def _offset_view(a):
+    """Device copy of `a` starting one float past a 256-byte boundary (4-byte aligned only)."""
+    buf = torch.zeros(a.size + 1, device="cuda", dtype=torch.float32)
+    v = buf[1:].view(a.shape)
+    v.copy_(torch.from_numpy(np.ascontiguousarray(a, np.float32)))
+    return v
+
+
+@pytest.mark.parametrize("dims,ranks", [((12, 10, 9, 8), (3, 4, 2, 5)),      # quad rows, padded
+                                        ((14, 13, 12, 11), (10, 10, 10, 10)),  # several chunks
+                                        ((40, 36, 34), (32, 32, 32))])
+def test_nntucker_unaligned_core_and_factors(dims, ranks):
+    """Core and factors 4 bytes off a 16-byte boundary take the row update's scalar staging;
+    staging only moves data, so the fit equals the aligned one bit for bit and the oracle
+    to the usual bar."""
+    nnc = need_gpu()
+    X, _, G0, A0 = problem(37, dims, 3, ranks)
+    Xd = dev(X)
+    G, A = dev(G0), [dev(a) for a in A0]
+    nnc.nntucker_fit(Xd, G0.shape, 3, G, A)
+    Gu, Au = _offset_view(G0), [_offset_view(a) for a in A0]
+    assert Gu.data_ptr() % 16 == 4
+    rep = nnc.nntucker_fit(Xd, G0.shape, 3, Gu, Au)
+    assert torch.equal(Gu, G) and all(torch.equal(x, y) for x, y in zip(Au, A))
+    Go, Ao, _, _ = oracle.nntucker(X.astype(np.float64), G0, A0, 3)
+    assert rel_fro(oracle.tucker_full(host(Gu), [host(a) for a in Au]),
+                   oracle.tucker_full(Go, Ao)) <= 1e-4
+    assert rep.eps_clips == 0
+
+
 def test_c1_workload_final_residual_matches_oracle():
     """40^3, planted rank 3, multirank (5,5,5), 200 sweeps; nnCP rank 3, 300 sweeps; lift."""
     nnc = need_gpu()
