@@ -461,8 +461,10 @@ static int small_waves(int64_t N) {
   const int64_t w = (N + kSmallRows - 1) / kSmallRows;
   return (int)(w < 1 ? 1 : (w > kSmallMaxWaves ? kSmallMaxWaves : w));
 }
-// LDS of a block: the wave partial sums (W of RM x 64).
-static size_t small_lds(int W, int RM) { return (size_t)W * 64 * RM * sizeof(float); }
+// LDS of a block: the wave partial sums (W of RM rows of 64, kRedStride floats apart: with
+// rows 64 floats apart every 16-row group of a wave's writes fell on the same banks).
+constexpr int kRedStride = 68;
+static size_t small_lds(int W, int RM) { return (size_t)W * kRedStride * RM * sizeof(float); }
 
 struct SmallArgs {
   const float *in;
@@ -512,27 +514,37 @@ static __device__ void small_body(const SmallArgs &a, int64_t tile) {
   for (int c = 0; c < 4; ++c)
 #pragma unroll
     for (int t = 0; t < RT; ++t) acc[c][t] = smf4{0.f, 0.f, 0.f, 0.f};
+  // Addresses: one 64-bit product per pointer and round; step st adds 4 st rows, a
+  // wave-uniform offset, so the loads cost no per-load integer multiplies.
+  const float *flast[RT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) flast[t] = F + (16 * t + li < R ? (16 * t + li) * ldr : 0);
   for (int64_t nb = 0; active && nb < N; nb += span) {
     constexpr int kSteps = kSmallRows / 4;
+    const int64_t n0 = nb + w * kSmallRows + lg;  // the lane's row of step 0
     float fb[kSteps][RT];
 #pragma unroll
-    for (int st = 0; st < kSteps; ++st) {
-      const int64_t n = nb + w * kSmallRows + 4 * st + lg;
+    for (int t = 0; t < RT; ++t) {
+      const float *f0 = flast[t] + n0 * ldl;
 #pragma unroll
-      for (int t = 0; t < RT; ++t) {
-        const int r = 16 * t + li;
-        const bool ok = n < N && r < R;
-        fb[st][t] = F[(ok ? n : 0) * ldl + (ok ? r : 0) * ldr];
+      for (int st = 0; st < kSteps; ++st) {
+        const bool ok = n0 + 4 * st < N && 16 * t + li < R;
+        fb[st][t] = *(ok ? f0 + 4 * st * ldl : F);
       }
     }
     __builtin_amdgcn_sched_barrier(0);
     float xv[kSteps][4];
+    const float *x0[4], *xl[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      x0[c] = src[c] + n0 * Q;
+      xl[c] = src[c] + (N - 1) * Q;  // rows past N meet zero factor entries
+    }
 #pragma unroll
     for (int st = 0; st < kSteps; ++st) {
-      int64_t n = nb + w * kSmallRows + 4 * st + lg;
-      n = n < N ? n : N - 1;  // rows past N meet zero factor entries
+      const bool inside = n0 + 4 * st < N;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) xv[st][c] = src[c][n * Q];
+      for (int c = 0; c < 4; ++c) xv[st][c] = *(inside ? x0[c] + 4 * st * Q : xl[c]);
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -548,16 +560,15 @@ static __device__ void small_body(const SmallArgs &a, int64_t tile) {
       }
     }
   }
-  float *red = sm;  // red[w][r][64]
+  float *red = sm;  // red[w][r][kRedStride], columns 0 .. 63 used
   if (active) {
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
       const int r = 16 * t + li;
       if (r < RM) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) red[(w * RM + r) * 64 + 16 * c + 4 * lg + v] = acc[c][t][v];
+        for (int c = 0; c < 4; ++c)  // columns 16 c + 4 lg .. + 3: one 16-byte write
+          *reinterpret_cast<smf4 *>(red + (w * RM + r) * kRedStride + 16 * c + 4 * lg) = acc[c][t];
       }
     }
   }
@@ -566,8 +577,8 @@ static __device__ void small_body(const SmallArgs &a, int64_t tile) {
     const int r = idx >> 6, l = idx & 63;
     const int64_t e2 = tile * 64 + l;
     if (r >= R || e2 >= PQ) continue;
-    float s2 = red[r * 64 + l];
-    for (int ww = 1; ww < W; ++ww) s2 += red[(ww * RM + r) * 64 + l];
+    float s2 = red[r * kRedStride + l];
+    for (int ww = 1; ww < W; ++ww) s2 += red[(ww * RM + r) * kRedStride + l];
     const int64_t p2 = e2 / Q, q2 = e2 - (e2 / Q) * Q;
     out[(p2 * R + r) * Q + q2] = s2;
   }
