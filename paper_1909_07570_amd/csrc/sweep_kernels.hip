@@ -19,22 +19,6 @@ namespace nnc {
 // fixed order) and, with gpart (last mode, q range 1), its share of the core numerator
 // gpart[block][p][r] = sum_{i in block} Y[p][i] * Anew[i][r].
 // =====================================================================================
-// Division of nonnegative ints below 2^31 by an invariant divisor d >= 1 through a
-// multiply-high and a shift (Granlund and Montgomery, PLDI 1994): with l = ceil(log2 d) and
-// m = floor(2^32 (2^l - d) / d) + 1, a / d = (mulhi(a, m) + a) >> l; the sum stays below 2^32.
-struct UDiv {
-  unsigned m, l;
-};
-static __device__ inline UDiv make_udiv(int d) {
-  const unsigned ud = (unsigned)d;
-  const unsigned l = ud <= 1 ? 0u : 32u - (unsigned)__clz(ud - 1);
-  const unsigned long long m = ((((1ull << l) - ud) << 32) / ud) + 1;
-  return {(unsigned)m, l};
-}
-static __device__ inline int udiv(int a, UDiv d) {
-  return (int)((__umulhi((unsigned)a, d.m) + (unsigned)a) >> d.l);
-}
-
 constexpr int kRB = 8;
 constexpr int kRowThreads = 512;
 constexpr int kRowLdsFloats = 14 * 1024;  // dynamic LDS budget of one block (floats)
