@@ -114,8 +114,18 @@ __global__ __launch_bounds__(kDiagThreads) void diag_outer_k(DiagArgs g) {
 __global__ void diag_sum_k(const float *__restrict__ part, int slices, int64_t n, float *__restrict__ out) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
+  // slices in order; the loads of a group of kB are all in flight before the adds
+  constexpr int kB = 16;
   float t = part[e];
-  for (int s = 1; s < slices; ++s) t += part[(int64_t)s * n + e];
+  int s = 1;
+  for (; s + kB <= slices; s += kB) {
+    float v[kB];
+#pragma unroll
+    for (int k = 0; k < kB; ++k) v[k] = part[(int64_t)(s + k) * n + e];
+#pragma unroll
+    for (int k = 0; k < kB; ++k) t += v[k];
+  }
+  for (; s < slices; ++s) t += part[(int64_t)s * n + e];
   out[e] = t;
 }
 
@@ -209,19 +219,43 @@ nnc_status launch_cp_mu(float *B, const float *M, const float *S, int d, int n, 
 }
 
 // S = A^T A (A: N x r, r <= 32) in one workgroup: thread (entry, split) sums the rows of its
-// split (rows j with j mod splits == split), the splits are added in order.
+// split (rows j with j mod splits == split) in ascending order, the splits are added in
+// order.  Rows come through LDS in chunks of a multiple of `splits` rows, each chunk one
+// round of coalesced loads: read from global memory, the sum waited on one load latency per
+// few rows.
+constexpr int kGramLds = 8192;  // floats of A staged per chunk
 __global__ __launch_bounds__(1024) void gram_block_k(const float *__restrict__ A, int64_t N, int r,
                                                      float *__restrict__ S) {
   __shared__ float part[1024];
+  __shared__ float As[kGramLds];
   const int tid = threadIdx.x;
   const int rr = r * r;
   const int splits = 1024 / rr;
   const int e = tid % rr, sp = tid / rr;
+  const int a = e / r, b = e - (e / r) * r;
+  const int64_t crows = (int64_t)(kGramLds / r / splits) * splits;  // rows per chunk
   float acc = 0.f;
-  if (sp < splits) {
-    const int a = e / r, b = e - (e / r) * r;
-#pragma unroll 4
-    for (int64_t j = sp; j < N; j += splits) acc = fmaf(A[j * r + a], A[j * r + b], acc);
+  for (int64_t c0 = 0; c0 < N; c0 += crows) {
+    const int64_t nrow = N - c0 < crows ? N - c0 : crows;
+    const int nv = (int)(nrow * r);
+    __syncthreads();  // the previous chunk is consumed
+    constexpr int kPer = kGramLds / 1024;
+    float v[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int i = tid + u * 1024;
+      v[u] = A[c0 * r + (i < nv ? i : 0)];
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int i = tid + u * 1024;
+      if (i < nv) As[i] = v[u];
+    }
+    __syncthreads();
+    if (sp < splits) {
+#pragma unroll 8
+      for (int j = sp; j < nrow; j += splits) acc = fmaf(As[j * r + a], As[j * r + b], acc);
+    }
   }
   part[tid] = acc;
   __syncthreads();
