@@ -77,26 +77,55 @@ __global__ __launch_bounds__(kDiagThreads) void diag_inner_k(DiagArgs g) {
 }
 
 // C == 1: block (tile of 64 consecutive i, slice of a); lane <-> i (contiguous in Y), the
-// four waves stride over a and their sums are added in wave order.
+// four waves stride over a and their sums are added in wave order.  A wave issues the loads
+// of kU steps of a before their products (each accumulator still takes its terms in
+// ascending a); the rank index of a load is clamped instead of guarded, so no load waits on
+// a branch (accumulators past r are never stored), and lanes past Nt read row Nt - 1 and
+// are not stored either.
 template <int RM>
 __global__ __launch_bounds__(kDiagThreads) void diag_outer_k(DiagArgs g) {
   __shared__ float red[kDiagThreads * RM];
   const int64_t tiles = (g.Nt + 63) / 64;
   const int64_t tile = blockIdx.x % tiles;
   const int s = (int)(blockIdx.x / tiles);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t i = tile * 64 + lane;
-  const bool live = i < g.Nt;
+  const int64_t ic = i < g.Nt ? i : g.Nt - 1;
   const int64_t a0 = g.A * s / g.slices, a1 = g.A * (s + 1) / g.slices;
+  constexpr int kW = kDiagThreads / 64;
+  constexpr int kU = RM <= 16 ? 4 : 2;
+  // rank entry q of row a for this lane: Y[(a Nt + i) r + q] (rank last) or
+  // Y[q A Nt + a Nt + i] (rank first)
+  const int64_t qstride = g.rho_first ? g.A * g.Nt : 1;
+  const int64_t astride = g.rho_first ? g.Nt : g.Nt * g.r;
+  const float *ylane = g.Y + (g.rho_first ? ic : ic * g.r);
   float acc[RM];
 #pragma unroll
   for (int q = 0; q < RM; ++q) acc[q] = 0.f;
-  if (live)
-    for (int64_t a = a0 + w; a < a1; a += kDiagThreads / 64) {
+  for (int64_t ab = a0 + w; ab < a1; ab += kU * kW) {
+    float y[kU][RM], wt[kU][RM];
 #pragma unroll
-      for (int q = 0; q < RM; ++q)
-        if (q < g.r) acc[q] = fmaf(diag_y(g, a, i, 0, q), diag_w(g, a, 0, q), acc[q]);
+    for (int u = 0; u < kU; ++u) {
+      const int64_t a = ab + u * kW;
+      const int64_t ac = a < a1 ? a : a1 - 1;
+      const float *yr = ylane + ac * astride;
+#pragma unroll
+      for (int q = 0; q < RM; ++q) {
+        const int qc = q < g.r ? q : g.r - 1;
+        y[u][q] = yr[qc * qstride];
+        wt[u][q] = diag_w(g, ac, 0, qc);
+      }
     }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const bool ok = ab + u * kW < a1;
+#pragma unroll
+      for (int q = 0; q < RM; ++q) {
+        const float t = fmaf(y[u][q], wt[u][q], acc[q]);
+        acc[q] = ok ? t : acc[q];
+      }
+    }
+  }
 #pragma unroll
   for (int q = 0; q < RM; ++q) red[(w * RM + q) * 64 + lane] = acc[q];
   __syncthreads();
@@ -105,11 +134,10 @@ __global__ __launch_bounds__(kDiagThreads) void diag_outer_k(DiagArgs g) {
     const int64_t ii = tile * 64 + l;
     if (q >= g.r || ii >= g.Nt) continue;
     float t = red[q * 64 + l];
-    for (int ww = 1; ww < kDiagThreads / 64; ++ww) t += red[(ww * RM + q) * 64 + l];
+    for (int ww = 1; ww < kW; ++ww) t += red[(ww * RM + q) * 64 + l];
     g.out[((int64_t)s * g.Nt + ii) * g.r + q] = t;
   }
 }
-
 // out[e] = sum_{s < slices} part[s][e], s in order.
 __global__ void diag_sum_k(const float *__restrict__ part, int slices, int64_t n, float *__restrict__ out) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
