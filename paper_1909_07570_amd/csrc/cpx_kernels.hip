@@ -41,10 +41,14 @@ static __device__ inline float diag_w(const DiagArgs &g, int64_t a, int64_t c, i
 }
 
 // C > 1: block (i, slice); the threads stride over the flattened (a, c) range of the slice
-// (c fastest, contiguous in Y) and the partial sums are combined by a fixed pairwise tree.
+// (c fastest, contiguous in Y) and the partial sums are combined by a fixed pairwise tree
+// (thread t adds thread t + h for h = 128, 64, ..., 1).  The tree's two cross-wave steps
+// go through LDS; its steps inside wave 0 are shuffles that pair the same lanes.
 template <int RM>
 __global__ __launch_bounds__(kDiagThreads) void diag_inner_k(DiagArgs g) {
+  static_assert(kDiagThreads == 256, "the tree below has two cross-wave steps");
   __shared__ float red[kDiagThreads * RM];
+  const int t = threadIdx.x;
   const int64_t i = blockIdx.x % g.Nt;
   const int s = (int)(blockIdx.x / g.Nt);
   const int64_t F = g.A * g.C;
@@ -52,7 +56,7 @@ __global__ __launch_bounds__(kDiagThreads) void diag_inner_k(DiagArgs g) {
   float acc[RM];
 #pragma unroll
   for (int q = 0; q < RM; ++q) acc[q] = 0.f;
-  int64_t f = f0 + threadIdx.x;
+  int64_t f = f0 + t;
   int64_t a = f / g.C, c = f - a * g.C;  // advanced incrementally below
   for (; f < f1; f += kDiagThreads) {
 #pragma unroll
@@ -65,17 +69,26 @@ __global__ __launch_bounds__(kDiagThreads) void diag_inner_k(DiagArgs g) {
     }
   }
 #pragma unroll
-  for (int q = 0; q < RM; ++q) red[q * kDiagThreads + threadIdx.x] = acc[q];
+  for (int q = 0; q < RM; ++q) red[q * kDiagThreads + t] = acc[q];
   __syncthreads();
-  for (int h = kDiagThreads / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h)
+  if (t < 128)
 #pragma unroll
-      for (int q = 0; q < RM; ++q) red[q * kDiagThreads + threadIdx.x] += red[q * kDiagThreads + threadIdx.x + h];
-    __syncthreads();
+    for (int q = 0; q < RM; ++q) red[q * kDiagThreads + t] += red[q * kDiagThreads + t + 128];
+  __syncthreads();
+  if (t < 64) {
+    float v[RM];
+#pragma unroll
+    for (int q = 0; q < RM; ++q) v[q] = red[q * kDiagThreads + t] + red[q * kDiagThreads + t + 64];
+#pragma unroll
+    for (int h = 32; h > 0; h >>= 1)
+#pragma unroll
+      for (int q = 0; q < RM; ++q) v[q] += __shfl_down(v[q], h, 64);
+    if (t == 0)
+#pragma unroll
+      for (int q = 0; q < RM; ++q)
+        if (q < g.r) g.out[((int64_t)s * g.Nt + i) * g.r + q] = v[q];
   }
-  if ((int)threadIdx.x < g.r) g.out[((int64_t)s * g.Nt + i) * g.r + threadIdx.x] = red[threadIdx.x * kDiagThreads];
 }
-
 // C == 1: block (tile of 64 consecutive i, slice of a); lane <-> i (contiguous in Y), the
 // four waves stride over a and their sums are added in wave order.  A wave issues the loads
 // of kU steps of a before their products (each accumulator still takes its terms in
