@@ -145,9 +145,11 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
       // one thread per (row, quad of columns), quads past the rank left out.  H_n (Hadamard
       // product of the other Grams, final since the last update) in the same phase.
       const int nq = (r + 3) >> 2;
+      // index divisions through float reciprocals (qdiv; every index here is below 2^22)
+      const float inv_nq = 1.0f / (float)nq, inv_postL = 1.0f / (float)postL;
       for (int w = tid; w < nq * zrows; w += nt) {
-        const int o = w / nq, c4 = (w - o * nq) * 4;
-        const int pre = o / postL, q = o - (o / postL) * postL;
+        const int o = qdiv(w, inv_nq), c4 = (w - o * nq) * 4;
+        const int pre = qdiv(o, inv_postL), q = o - pre * postL;
         const float *t = T + pre * mL * postL + q;
         float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll 4
@@ -179,6 +181,7 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
       const int npairs = In * r;
       const int other = zrows / In;
       const int S = npairs >= nt ? 1 : nt / npairs;
+      const float inv_npairs = 1.0f / (float)npairs, inv_r = 1.0f / (float)r;
       if (d <= 3) {
         // position of n among Z's modes and the other mode (if any)
         int jo = -1;
@@ -188,8 +191,8 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
         const int Bo = jo >= 0 ? boff[jo] : 0;
         const int zstep = (n_first ? 1 : In) * S;
         for (int w = tid; w < npairs * S; w += nt) {
-          const int s = w / npairs, pr = w - s * npairs;
-          const int i = pr / r, rho = pr - (pr / r) * r;
+          const int s = qdiv(w, inv_npairs), pr = w - s * npairs;
+          const int i = qdiv(pr, inv_r), rho = pr - i * r;
           int zoff = n_first ? i * other + s : s * In + i;
           float acc = 0.f;
           if (jo >= 0) {
@@ -237,8 +240,8 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
         for (int j = 0; j < kMaxDim; ++j)
           if (j == npos) nstride = zstride[j];
         for (int w = tid; w < npairs * S; w += nt) {
-          const int pr = w % npairs, s = w / npairs;
-          const int i = pr / r, rho = pr - (pr / r) * r;
+          const int s = qdiv(w, inv_npairs), pr = w - s * npairs;
+          const int i = qdiv(pr, inv_r), rho = pr - i * r;
           const int o0 = (int)((int64_t)other * s / S), o1 = (int)((int64_t)other * (s + 1) / S);
           int rem = o0, zoff = i * nstride;
 #pragma unroll
@@ -277,7 +280,7 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
       // ---- B_n <- B_n * M / max(B_n H, eps): new values go to `part` first
       float *Bn = sB + boff[n];
       for (int e = tid; e < npairs; e += nt) {
-        const int i = e / r, c = e - (e / r) * r;
+        const int i = qdiv(e, inv_r), c = e - i * r;
         float m = 0.f;  // the S partial sums of pair e, in split order
 #pragma unroll 4
         for (int s = 0; s < S; ++s) m += part[s * npairs + e];
@@ -287,10 +290,13 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
         part[e] = mu_cp(Bn[i * RM + c], m, den, eps, &nclip);
       }
       __syncthreads();
-      for (int e = tid; e < npairs; e += nt) Bn[(e / r) * RM + e % r] = part[e];
+      for (int e = tid; e < npairs; e += nt) {
+        const int i = qdiv(e, inv_r);
+        Bn[i * RM + (e - i * r)] = part[e];
+      }
       __syncthreads();
       for (int e = tid; e < r * r; e += nt) {
-        const int x = e / r, y = e - (e / r) * r;
+        const int x = qdiv(e, inv_r), y = e - x * r;
         float acc = 0.f;
 #pragma unroll 4
         for (int i = 0; i < In; ++i) acc = fmaf(Bn[i * RM + x], Bn[i * RM + y], acc);
