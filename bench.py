@@ -485,28 +485,35 @@ def main():
         alg2, study, sec43 = extra_studies(args, nnc, dev, Xb, X32, dims, ranks, rank, R)
 
     # ---- per-launch timing of the two X-streaming contractions (same kernels, same launch
-    # configuration as inside the fit), HIP events on the stream they are launched on.
+    # configuration as inside the fit), HIP events on the stream they are launched on:
+    # kGroups groups of back-to-back launches, each group's average, and the median group
+    # (one disturbed group of launches does not move it; every group is reported).
     size = N ** 3
+    kGroups = 5
     def time_kernel(Xt, mode, A_):
         out = torch.empty([N, N, R] if mode == 2 else [R, N, N], dtype=torch.float32, device=dev)
         for _ in range(3):
             nnc.nnc_ttm(Xt, mode, A_, out)
         s = torch.cuda.current_stream()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(s)
-        for _ in range(args.kernel_reps):
-            nnc.nnc_ttm(Xt, mode, A_, out)
-        e1.record(s)
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / args.kernel_reps
+        groups = []
+        for _ in range(kGroups):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(args.kernel_reps):
+                nnc.nnc_ttm(Xt, mode, A_, out)
+            e1.record(s)
+            torch.cuda.synchronize()
+            groups.append(e0.elapsed_time(e1) / args.kernel_reps)
+        return sorted(groups)[kGroups // 2], groups
     kern = {}
     for name, Xt, esz in (("bf16", Xb, 2), ("fp32", X32, 4)):
         for mode, kname in ((2, "ttm_last"), (0, "ttm_mid")):
-            ms = time_kernel(Xt, mode, A0[mode])
+            ms, groups = time_kernel(Xt, mode, A0[mode])
             bytes_ = size * esz + size // N * R * 4
             kern["%s_%s" % (kname, name)] = dict(
                 avg_us=ms * 1e3, gbs=bytes_ / (ms * 1e-3) / 1e9,
-                tflops=2.0 * size * R / (ms * 1e-3) / 1e12, alg_bytes=bytes_)
+                tflops=2.0 * size * R / (ms * 1e-3) / 1e12, alg_bytes=bytes_,
+                group_avg_us=[round(g * 1e3, 2) for g in groups])
             log("%s_%s: %.1f us, %.0f GB/s, %.1f TFLOP/s" % (kname, name, ms * 1e3,
                 kern["%s_%s" % (kname, name)]["gbs"], kern["%s_%s" % (kname, name)]["tflops"]))
     # in-fit cross-check: event-timed passes of an eager BF16 fit
@@ -591,7 +598,8 @@ def main():
                    "sweeps": args.sweeps, "fp32_final_sweeps": args.fp32_final},
         "ttm_tflops": round(sweep_flops * args.sweeps / (bf["seconds"] / args.steps) / 1e12, 2),
         "ttm_kernel_tflops": {k: round(v["tflops"], 2) for k, v in kern.items()},
-        "kernels": {k: {"avg_us": round(v["avg_us"], 2), "GB/s": round(v["gbs"], 1)} for k, v in kern.items()},
+        "kernels": {k: {"avg_us": round(v["avg_us"], 2), "GB/s": round(v["gbs"], 1),
+                        "group_avg_us": v["group_avg_us"]} for k, v in kern.items()},
         "infit_pass_avg_us_bf16": round(infit_pass_us, 2),
         "residuals": {"bf16_tucker": bf["tucker_rel"], "fp32_tucker": fp["tucker_rel"],
                       "bf16_lifted_cp": bf["cp_rel"], "fp32_lifted_cp": fp["cp_rel"],
