@@ -29,6 +29,8 @@ CPX_CASES = [
     ((6, 7, 5, 6, 4), 3),     # 5-way
     ((50, 70), 6),            # 2-way: plain NMF of X
     ((300, 40, 260), 10),     # several diagonal slices
+    ((600, 12, 10), 32),      # the one-workgroup Gram in three LDS chunks of 256 rows (ragged)
+    ((2000, 9, 7), 10),       # ... and of 810 rows
 ]
 
 
