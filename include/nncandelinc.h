@@ -119,6 +119,27 @@ nnc_status nnc_ttm(const void *X, nnc_dtype xdt, int ndim, const int64_t *dims, 
 nnc_status nnc_convert_f32_bf16(const float *in, uint16_t *out, int64_t count, void *stream);
 
 /*
+ * Seeded uniform draws for initial values and synthetic inputs.  The paper starts every
+ * solver from a random initialisation (Section 4.1) and draws the random factor matrices of
+ * its generated tensors (Section 4.3); this library takes initial values as inputs, and these
+ * helpers draw them on the device from a counter-based SplitMix64 stream (Steele, Lea &
+ * Flood, OOPSLA 2014):
+ *   key      = mix64(mix64(seed + G) ^ (stream_id * 0xD1B54A32D192ED03)),  G = 0x9E3779B97F4A7C15,
+ *   draw(i)  = mix64(key + (i + 1) * G)   (arithmetic mod 2^64; mix64 = SplitMix64's finaliser),
+ *   value(i) = (draw(i) >> 11) * 2^-53, a double in [0, 1).
+ * Element i depends only on (seed, stream_id, i), so the values are the same whatever the
+ * launch shape, and a slice can be drawn on its own.
+ *   nnc_fill_uniform:      ptr[i] = value(i) rounded to float (nearest, ties to even),
+ *                          i < n.  ptr: device, n floats.
+ *   nnc_fill_uniform_f64:  ptr[i] = value(offset + i) as a double, i < n.  ptr: device.
+ * n = 0 does nothing; n < 0, offset < 0 or a NULL ptr (with n > 0) -> NNC_EINVAL.
+ * Asynchronous on `stream`.
+ */
+nnc_status nnc_fill_uniform(uint64_t seed, uint64_t stream_id, float *ptr, int64_t n, void *stream);
+nnc_status nnc_fill_uniform_f64(uint64_t seed, uint64_t stream_id, int64_t offset, double *ptr, int64_t n,
+                                void *stream);
+
+/*
  * Nonnegative Tucker decomposition by multiplicative updates (the nnTD step of
  * Algorithm 1), exactly `iters` sweeps, no early stop (Section 4.1).  The arithmetic of the
  * two X-streaming contractions of every sweep follows xdt: NNC_F32 runs FP32 MFMA;
@@ -145,13 +166,14 @@ nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *d
  *   core        core_dims[0..ndim-1] floats.
  *   cp_factors  host array of ndim device pointers; factor n is core_dims[n] x rank;
  *               in: initial B_n >= 0; out: fitted B_n.
- *   rel_residual  host, nullable: ||core - cp(B)|| / ||core||; non-NULL syncs.
- *   workspace     at least nncp_workspace_bytes().
+ *   opt         eps and the workspace (at least nncp_workspace_bytes()) are used; the other
+ *               fields are ignored.  NULL or a short workspace -> NNC_EWORKSPACE.
+ *   rep         nullable; non-NULL syncs and reports sweeps_done, eps_clips, seconds and
+ *               rel_residual = ||core - cp(B)||_F / ||core||_F.
  */
 size_t nncp_workspace_bytes(int ndim, const int64_t *core_dims, int rank);
 nnc_status nncp_fit(const float *core, int ndim, const int64_t *core_dims, int rank, int iters,
-                    float *const *cp_factors, double eps, double *rel_residual, void *workspace,
-                    size_t workspace_bytes, void *stream);
+                    float *const *cp_factors, const nnc_options *opt, nnc_report *rep, void *stream);
 
 /*
  * Many independent nnCP fits of one core (random restarts, possibly different ranks) in a

@@ -59,7 +59,7 @@ EXPORTED = ["nnc_last_error", "nnc_device_ok", "nnc_set_timing", "nnc_ttm", "nnc
             "reconstruct_workspace_bytes", "reconstruct_residual", "reconstruct_sq_sums",
             "nntucker_grad", "nncpx_workspace_bytes", "nncpx_fit", "nmf_workspace_bytes", "nmf_fit",
             "nmf_batched_workspace_bytes", "nmf_fit_batched", "nncandelinc_restart_init_floats",
-            "nncandelinc_restarts", "nnc_mean_congruence"]
+            "nncandelinc_restarts", "nnc_mean_congruence", "nnc_fill_uniform", "nnc_fill_uniform_f64"]
 
 _lib = None
 
@@ -76,6 +76,8 @@ def lib():
         L.nnc_set_timing.argtypes = [ctypes.c_int]
         L.nnc_ttm.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _i64p, ctypes.c_int, _vp, _i64, _vp, _vp]
         L.nnc_convert_f32_bf16.argtypes = [_vp, _vp, _i64, _vp]
+        L.nnc_fill_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint64, _vp, _i64, _vp]
+        L.nnc_fill_uniform_f64.argtypes = [ctypes.c_uint64, ctypes.c_uint64, _i64, _vp, _i64, _vp]
         L.nntucker_workspace_bytes.argtypes = [ctypes.c_int, _i64p, _i64p]
         L.nntucker_workspace_bytes.restype = ctypes.c_size_t
         L.nntucker_fit.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _i64p, _i64p, ctypes.c_int, _vp,
@@ -83,7 +85,7 @@ def lib():
         L.nncp_workspace_bytes.argtypes = [ctypes.c_int, _i64p, ctypes.c_int]
         L.nncp_workspace_bytes.restype = ctypes.c_size_t
         L.nncp_fit.argtypes = [_vp, ctypes.c_int, _i64p, ctypes.c_int, ctypes.c_int, _vpp,
-                               ctypes.c_double, _dp, _vp, ctypes.c_size_t, _vp]
+                               ctypes.POINTER(Options), ctypes.POINTER(Report), _vp]
         L.nncp_batched_workspace_bytes.argtypes = [ctypes.c_int, _i64p, ctypes.c_int,
                                                    ctypes.POINTER(ctypes.c_int)]
         L.nncp_batched_workspace_bytes.restype = ctypes.c_size_t
@@ -199,6 +201,29 @@ def nnc_convert_f32_bf16(x: torch.Tensor) -> torch.Tensor:
     return out
 
 
+def nnc_fill_uniform(seed: int, stream_id: int, n_or_out, device="cuda") -> torch.Tensor:
+    """Seeded U[0,1) float32 draws (counter-based SplitMix64, rounded to nearest) on the GPU.
+    Pass a length (a new tensor is returned) or a contiguous float32 device tensor to fill."""
+    if isinstance(n_or_out, torch.Tensor):
+        out = _dev(n_or_out, "out")
+    else:
+        out = torch.empty(int(n_or_out), dtype=torch.float32, device=device)
+    _check(lib().nnc_fill_uniform(int(seed) & (2**64 - 1), int(stream_id) & (2**64 - 1), out.data_ptr(),
+                                  out.numel(), _stream()))
+    return out
+
+
+def nnc_fill_uniform_f64(seed: int, stream_id: int, n_or_out, offset: int = 0, device="cuda") -> torch.Tensor:
+    """Seeded U[0,1) float64 draws of elements offset .. offset + n - 1 of a stream."""
+    if isinstance(n_or_out, torch.Tensor):
+        out = _dev(n_or_out, "out", (torch.float64,))
+    else:
+        out = torch.empty(int(n_or_out), dtype=torch.float64, device=device)
+    _check(lib().nnc_fill_uniform_f64(int(seed) & (2**64 - 1), int(stream_id) & (2**64 - 1), int(offset),
+                                      out.data_ptr(), out.numel(), _stream()))
+    return out
+
+
 # ------------------------------------------------------------------------------- nnTucker
 @dataclass
 class FitReport:
@@ -254,19 +279,31 @@ def nntucker_fit(X: torch.Tensor, multirank: Sequence[int], iters: int, core: to
 
 
 # ------------------------------------------------------------------------------- nnCP
+def _cp_report(rep, full: bool):
+    if full:
+        return FitReport(rep.sweeps_done, rep.rel_residual, rep.eps_clips, rep.seconds)
+    return rep.rel_residual
+
+
 def nncp_fit(core: torch.Tensor, rank: int, iters: int, cp_factors: Sequence[torch.Tensor], *,
-             eps: float = 1e-12, residual: bool = True) -> Optional[float]:
-    """nnCP of the core by multiplicative updates in one persistent launch, in place."""
+             eps: float = 1e-12, residual: bool = True, report: bool = False):
+    """nnCP of the core by multiplicative updates in one persistent launch, in place.
+    Returns the relative residual ||core - cp(B)|| / ||core|| (residual=True), the full
+    FitReport with the clip count (report=True), or None."""
     _dev(core, "core")
     for k, f in enumerate(cp_factors):
         _dev(f, "cp_factors[%d]" % k)
     d = core.dim()
     ws = _workspace(lib().nncp_workspace_bytes(d, _dims(core.shape), int(rank)), core.device)
-    res = ctypes.c_double(0.0)
-    _check(lib().nncp_fit(core.data_ptr(), d, _dims(core.shape), int(rank), int(iters),
-                          _ptrs(cp_factors), float(eps), ctypes.byref(res) if residual else None,
-                          ws.data_ptr(), ws.numel(), _stream()))
-    return res.value if residual else None
+    opt = Options()
+    opt.eps = float(eps)
+    opt.workspace = ws.data_ptr()
+    opt.workspace_bytes = ws.numel()
+    rep = Report()
+    want = residual or report
+    _check(lib().nncp_fit(core.data_ptr(), d, _dims(core.shape), int(rank), int(iters), _ptrs(cp_factors),
+                          ctypes.byref(opt), ctypes.byref(rep) if want else None, _stream()))
+    return _cp_report(rep, report) if want else None
 
 
 def nncpx_workspace_bytes(dims: Sequence[int], rank: int) -> int:

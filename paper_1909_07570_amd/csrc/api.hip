@@ -771,6 +771,22 @@ nnc_status nnc_convert_f32_bf16(const float *in, uint16_t *out, int64_t count, v
   return launch_convert_bf16(in, out, count, (hipStream_t)stream);
 }
 
+nnc_status nnc_fill_uniform(uint64_t seed, uint64_t stream_id, float *ptr, int64_t n, void *stream) {
+  if (n < 0) return fail(NNC_EINVAL, "n = %lld < 0", (long long)n);
+  if (n == 0) return NNC_OK;
+  if (!ptr) return fail(NNC_EINVAL, "ptr is NULL");
+  return launch_fill_uniform(uniform_stream_key(seed, stream_id), 0, n, ptr, nullptr, (hipStream_t)stream);
+}
+
+nnc_status nnc_fill_uniform_f64(uint64_t seed, uint64_t stream_id, int64_t offset, double *ptr, int64_t n,
+                                void *stream) {
+  if (n < 0 || offset < 0) return fail(NNC_EINVAL, "n = %lld and offset = %lld must be >= 0", (long long)n,
+                                       (long long)offset);
+  if (n == 0) return NNC_OK;
+  if (!ptr) return fail(NNC_EINVAL, "ptr is NULL");
+  return launch_fill_uniform(uniform_stream_key(seed, stream_id), offset, n, nullptr, ptr, (hipStream_t)stream);
+}
+
 size_t nntucker_workspace_bytes(int ndim, const int64_t *dims, const int64_t *multirank) {
   if (check_dims(ndim, dims, "dims") != NNC_OK) return 0;
   if (check_dims(ndim, multirank, "multirank") != NNC_OK) return 0;
@@ -1143,30 +1159,54 @@ size_t nncp_batched_workspace_bytes(int ndim, const int64_t *core_dims, int nbat
   return cp_ws(cp_problem(ndim, core_dims), nbatch, ranks, true).total;
 }
 
-nnc_status nncp_fit(const float *core, int ndim, const int64_t *core_dims, int rank, int iters,
-                    float *const *cp_factors, double eps, double *rel_residual, void *workspace,
-                    size_t workspace_bytes, void *stream) {
+static nnc_status check_nncp_args(const float *core, int ndim, const int64_t *core_dims, int rank, int iters,
+                                  float *const *cp_factors, double eps) {
   NNC_TRY(check_cp(core, ndim, core_dims, rank, iters));
   NNC_TRY(check_ptrs((const void *const *)cp_factors, ndim, "cp_factors"));
   if (eps < 0) return fail(NNC_EINVAL, "eps < 0");
   if (rank > 32) return fail(NNC_EUNSUPPORTED, "rank %d above 32", rank);
+  return nncp_check_shape(cp_problem(ndim, core_dims), rank, 0);
+}
+
+// One nnCP fit with its scratch (layout cp_ws) at `base`; fills `rep` (and syncs) if given.
+static nnc_status nncp_fit_at(const float *core, int ndim, const int64_t *core_dims, int rank, int iters,
+                              float *const *cp_factors, double eps, nnc_report *rep, char *base,
+                              hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
   const CpProblem pb = cp_problem(ndim, core_dims);
   const CpWs w = cp_ws(pb, 1, &rank, false);
-  if (!workspace || workspace_bytes < w.total)
-    return fail(NNC_EWORKSPACE, "workspace has %zu bytes, need %zu", workspace ? workspace_bytes : 0,
-                w.total);
-  hipStream_t s = (hipStream_t)stream;
-  char *base = (char *)workspace;
-  NNC_TRY(launch_fill_u64((unsigned long long *)(base + w.oClip), 1, 0ull, s));
+  unsigned long long *clips = (unsigned long long *)(base + w.oClip);
+  NNC_TRY(launch_fill_u64(clips, 1, 0ull, s));
   NNC_TRY(launch_nncp(core, pb, 1, nullptr, rank, nullptr, cp_factors, iters, eps > 0 ? eps : 1e-12,
-                      rel_residual ? (double *)(base + w.oRes) : nullptr,
-                      (unsigned long long *)(base + w.oClip), (float *)(base + w.oZ), 0, s));
-  if (rel_residual) {
-    NNC_HIP(hipMemcpyAsync(rel_residual, base + w.oRes, sizeof(double), hipMemcpyDeviceToHost, s));
+                      rep ? (double *)(base + w.oRes) : nullptr, clips, (float *)(base + w.oZ), 0, s));
+  if (rep) {
+    double res = 0.0;
+    unsigned long long nclip = 0;
+    NNC_HIP(hipMemcpyAsync(&res, base + w.oRes, sizeof(double), hipMemcpyDeviceToHost, s));
+    NNC_HIP(hipMemcpyAsync(&nclip, clips, sizeof nclip, hipMemcpyDeviceToHost, s));
     NNC_HIP(hipStreamSynchronize(s));
-    if (!std::isfinite(*rel_residual)) return fail(NNC_ENUMERIC, "non-finite nnCP residual");
+    rep->sweeps_done = iters;
+    rep->rel_residual = res;
+    rep->eps_clips = (long long)nclip;
+    rep->history_len = 0;
+    rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    rep->ttm_pass_ms = 0.0;
+    rep->ttm_pass_launches = 0;
+    if (!std::isfinite(res)) return fail(NNC_ENUMERIC, "non-finite nnCP residual");
   }
   return NNC_OK;
+}
+
+nnc_status nncp_fit(const float *core, int ndim, const int64_t *core_dims, int rank, int iters,
+                    float *const *cp_factors, const nnc_options *opt, nnc_report *rep, void *stream) {
+  const double eps = opt ? opt->eps : 0.0;
+  NNC_TRY(check_nncp_args(core, ndim, core_dims, rank, iters, cp_factors, eps));
+  const CpWs w = cp_ws(cp_problem(ndim, core_dims), 1, &rank, false);
+  if (!opt || !opt->workspace || opt->workspace_bytes < w.total)
+    return fail(NNC_EWORKSPACE, "workspace has %zu bytes, need %zu",
+                (opt && opt->workspace) ? opt->workspace_bytes : 0, w.total);
+  return nncp_fit_at(core, ndim, core_dims, rank, iters, cp_factors, eps, rep, (char *)opt->workspace,
+                     (hipStream_t)stream);
 }
 
 size_t nncpx_workspace_bytes(int ndim, const int64_t *dims, int rank) {
@@ -1294,6 +1334,7 @@ static nnc_status nmf_one(const float *A, int64_t rows, int64_t cols, int rank, 
     return NNC_OK;
   }
   // A ~ W H is the two-way nonnegative CP with factors W (rows x rank) and H^T (cols x rank)
+  NNC_TRY(nncp_check_shape(pb, rank, 0));
   NNC_TRY(launch_transpose(H, rank, cols, Ht, s));
   float *fac[2] = {W, Ht};
   NNC_TRY(launch_fill_u64((unsigned long long *)(base + w.oClip), 1, 0ull, s));
@@ -1542,6 +1583,7 @@ nnc_status nncp_fit_batched(const float *core, int ndim, const int64_t *core_dim
   if (threads_per_fit != 0 && (threads_per_fit < 64 || threads_per_fit > 1024 || threads_per_fit % 64))
     return fail(NNC_EINVAL, "threads_per_fit must be 0 or a multiple of 64 in [64, 1024]");
   const CpProblem pb = cp_problem(ndim, core_dims);
+  NNC_TRY(nncp_check_shape(pb, maxr, threads_per_fit));
   const CpWs w = cp_ws(pb, nbatch, ranks, true);
   if (!workspace || workspace_bytes < w.total)
     return fail(NNC_EWORKSPACE, "workspace has %zu bytes, need %zu", workspace ? workspace_bytes : 0,

@@ -145,7 +145,8 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
       // one thread per (row, quad of columns), quads past the rank left out.  H_n (Hadamard
       // product of the other Grams, final since the last update) in the same phase.
       const int nq = (r + 3) >> 2;
-      // index divisions through float reciprocals (qdiv; every index here is below 2^22)
+      // index divisions through float reciprocals (qdiv; nncp_check_shape keeps every
+      // index here below 2^22)
       const float inv_nq = 1.0f / (float)nq, inv_postL = 1.0f / (float)postL;
       for (int w = tid; w < nq * zrows; w += nt) {
         const int o = qdiv(w, inv_nq), c4 = (w - o * nq) * 4;
@@ -423,12 +424,28 @@ static nnc_status allow_lds(const void *kern, int64_t bytes) {
   return NNC_OK;
 }
 
-nnc_status launch_nncp(const float *T, const CpProblem &pb, int nbatch, const int *d_ranks,
-                       int max_rank, float *const *d_factor_ptrs, float *const *single_ptrs,
-                       int iters, double eps, double *d_resid, unsigned long long *clips,
-                       float *zscratch, int threads, hipStream_t s) {
+// The kernel splits its loop indices with qdiv, exact below 2^22: stage 1 runs
+// ceil(r/4) * size / dims[L] items (L = the contracted mode of that update), stage 2 and the
+// update run dims[n] * r pairs (times a split factor only while that stays below the thread
+// count).  Shapes whose index ranges reach 2^22 are refused here, before any HIP call.
+nnc_status nncp_check_shape(const CpProblem &pb, int max_rank, int threads) {
+  if (pb.d < 2 || pb.size < 1) return fail(NNC_EINVAL, "nnCP needs a tensor of 2 or more modes");
   if (pb.size > (1 << 26)) return fail(NNC_EUNSUPPORTED, "nnCP tensor too large for one workgroup");
+  if (max_rank < 1) return fail(NNC_EINVAL, "nnCP rank %d < 1", max_rank);
   if (max_rank > 32) return fail(NNC_EUNSUPPORTED, "nnCP rank above 32");
+  constexpr int64_t kIdxLimit = (int64_t)1 << 22;
+  const int64_t nq = (max_rank + 3) / 4;
+  for (int n = 0; n < pb.d; ++n) {
+    const int L = (n == pb.d - 1) ? pb.d - 2 : pb.d - 1;
+    const int64_t zrows = pb.size / pb.dims[L];
+    if (nq * zrows >= kIdxLimit)
+      return fail(NNC_EUNSUPPORTED,
+                  "nnCP tensor of %lld entries at rank %d: %lld contraction items reach the 2^22 index limit",
+                  (long long)pb.size, max_rank, (long long)(nq * zrows));
+    if (pb.dims[n] * max_rank >= kIdxLimit)
+      return fail(NNC_EUNSUPPORTED, "nnCP mode %d of length %lld at rank %d reaches the 2^22 index limit", n,
+                  (long long)pb.dims[n], max_rank);
+  }
   if (threads <= 0) threads = nncp_default_threads(pb, max_rank);
   if (threads > 1024 || threads % 64)
     return fail(NNC_EINVAL, "threads_per_fit must be a multiple of 64 <= 1024");
@@ -436,6 +453,16 @@ nnc_status launch_nncp(const float *T, const CpProblem &pb, int nbatch, const in
   if (L.lds_bytes > kCpLdsBudget)
     return fail(NNC_EUNSUPPORTED, "nnCP working set %lld bytes exceeds the LDS budget",
                 (long long)L.lds_bytes);
+  return NNC_OK;
+}
+
+nnc_status launch_nncp(const float *T, const CpProblem &pb, int nbatch, const int *d_ranks,
+                       int max_rank, float *const *d_factor_ptrs, float *const *single_ptrs,
+                       int iters, double eps, double *d_resid, unsigned long long *clips,
+                       float *zscratch, int threads, hipStream_t s) {
+  NNC_TRY(nncp_check_shape(pb, max_rank, threads));
+  if (threads <= 0) threads = nncp_default_threads(pb, max_rank);
+  const CpLayout L = cp_layout(pb, max_rank, threads);
   if (!L.a.z_lds && !zscratch) return fail(NNC_EWORKSPACE, "nnCP needs Z scratch in the workspace");
   CpPtrs p0;
   for (int k = 0; k < kMaxDim; ++k) p0.p[k] = (single_ptrs && k < pb.d) ? single_ptrs[k] : nullptr;

@@ -870,6 +870,45 @@ __global__ void convert_bf16_k(const float *__restrict__ in, uint16_t *__restric
     out[i] = f2bf_rne(in[i]);
 }
 
+// =====================================================================================
+// Counter-based SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): element i of a stream with
+// key K is mix64(K + (i + 1) * GAMMA), mix64 being SplitMix64's finaliser; a uniform double
+// in [0, 1) is its top 53 bits times 2^-53.  Each element depends only on (K, i), so any
+// slice of a stream is generated on its own, in any order.
+// =====================================================================================
+constexpr uint64_t kSmGamma = 0x9E3779B97F4A7C15ull;
+
+static __host__ __device__ inline uint64_t sm_mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+uint64_t uniform_stream_key(uint64_t seed, uint64_t stream_id) {
+  return sm_mix64(sm_mix64(seed + kSmGamma) ^ (stream_id * 0xD1B54A32D192ED03ull));
+}
+
+__global__ void fill_uniform_k(uint64_t key, int64_t offset, int64_t n, float *__restrict__ out32,
+                               double *__restrict__ out64) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t z = sm_mix64(key + (uint64_t)(offset + i + 1) * kSmGamma);
+    const double u = (double)(z >> 11) * 0x1.0p-53;  // exact: 53-bit integer times 2^-53
+    if (out32)
+      out32[i] = (float)u;  // round to nearest even
+    else
+      out64[i] = u;
+  }
+}
+
+nnc_status launch_fill_uniform(uint64_t key, int64_t offset, int64_t n, float *out32, double *out64,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(fill_uniform_k, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, key, offset, n,
+                     out32, out64);
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
 nnc_status launch_convert_bf16(const float *in, uint16_t *out, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(convert_bf16_k, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, in, out, n);
   NNC_HIP(hipGetLastError());

@@ -91,6 +91,12 @@ int resid_stream_max_blocks();
 
 nnc_status launch_convert_bf16(const float *in, uint16_t *out, int64_t n, hipStream_t s);
 
+// Counter-based SplitMix64 streams: key of (seed, stream id); element offset + i of the stream
+// as a uniform double in [0, 1), written as float (RNE) to out32 or as double to out64.
+uint64_t uniform_stream_key(uint64_t seed, uint64_t stream_id);
+nnc_status launch_fill_uniform(uint64_t key, int64_t offset, int64_t n, float *out32, double *out64,
+                               hipStream_t s);
+
 // flag |= 1 if any of x[0..n) is not finite.
 nnc_status launch_check_finite(const float *x, int64_t n, unsigned int *flag, hipStream_t s);
 
@@ -114,6 +120,8 @@ nnc_status launch_nncp(const float *T, const CpProblem &pb, int nbatch, const in
                        int max_rank, float *const *d_factor_ptrs, float *const *single_ptrs,
                        int iters, double eps, double *d_resid, unsigned long long *clips,
                        float *zscratch, int threads, hipStream_t s);
+// Host-side check of a shape for launch_nncp (index ranges, rank, LDS); records the error.
+nnc_status nncp_check_shape(const CpProblem &pb, int max_rank, int threads);
 int64_t nncp_lds_bytes(const CpProblem &pb, int max_rank, int threads);
 int64_t nncp_zscratch_floats(const CpProblem &pb, int max_rank);
 int nncp_default_threads(const CpProblem &pb, int max_rank);

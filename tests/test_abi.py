@@ -82,10 +82,19 @@ def test_other_entry_points_validate():
     assert L.nnc_ttm(FAKE, 2, 3, D(4, 4, 4), 0, FAKE, 2, FAKE, None) == nnc.NNC_EINVAL
     assert L.nnc_convert_f32_bf16(None, FAKE, 4, None) == nnc.NNC_EINVAL
     assert L.nnc_convert_f32_bf16(FAKE, FAKE, -1, None) == nnc.NNC_EINVAL
-    assert L.nncp_fit(FAKE, 3, D(5, 5, 5), 0, 10, _ptrs(3), 0.0, None, FAKE, 1 << 20, None) == nnc.NNC_EINVAL
-    assert L.nncp_fit(FAKE, 3, D(5, 5, 5), 3, 10, _ptrs(3, 2), 0.0, None, FAKE, 1 << 20, None) == nnc.NNC_EINVAL
-    assert L.nncp_fit(FAKE, 3, D(5, 5, 5), 3, 10, _ptrs(3), 0.0, None, None, 0, None) == nnc.NNC_EWORKSPACE
-    assert L.nncp_fit(FAKE, 3, D(5, 5, 5), 65, 10, _ptrs(3), 0.0, None, FAKE, 1 << 20, None) == nnc.NNC_EUNSUPPORTED
+    wopt = nnc.Options()
+    wopt.workspace = 0x1000
+    wopt.workspace_bytes = 1 << 20
+    W = ctypes.byref(wopt)
+    assert L.nncp_fit(FAKE, 3, D(5, 5, 5), 0, 10, _ptrs(3), W, None, None) == nnc.NNC_EINVAL
+    assert L.nncp_fit(FAKE, 3, D(5, 5, 5), 3, 10, _ptrs(3, 2), W, None, None) == nnc.NNC_EINVAL
+    assert L.nncp_fit(FAKE, 3, D(5, 5, 5), 3, 10, _ptrs(3), None, None, None) == nnc.NNC_EWORKSPACE
+    assert L.nncp_fit(FAKE, 3, D(5, 5, 5), 65, 10, _ptrs(3), W, None, None) == nnc.NNC_EUNSUPPORTED
+    neg = nnc.Options()
+    neg.eps = -1.0
+    neg.workspace = 0x1000
+    neg.workspace_bytes = 1 << 20
+    assert L.nncp_fit(FAKE, 3, D(5, 5, 5), 3, 10, _ptrs(3), ctypes.byref(neg), None, None) == nnc.NNC_EINVAL
     rk = (ctypes.c_int * 2)(3, 40)
     res = (ctypes.c_double * 2)()
     assert L.nncp_fit_batched(FAKE, 3, D(5, 5, 5), 2, rk, 10, _ptrs(6), 0.0, res, 0, FAKE, 1 << 20, None) == nnc.NNC_EUNSUPPORTED
@@ -184,3 +193,49 @@ def test_binding_rejects_cpu_tensors():
     import torch
     with pytest.raises(ValueError):
         nnc.nnc_ttm(torch.zeros(4, 4, 4), 0, torch.zeros(4, 2))
+
+
+def test_nncp_refuses_index_ranges_past_2_22():
+    """The nnCP kernel splits loop indices with a float-reciprocal division that is exact
+    below 2^22; cores whose index ranges reach it are refused before any HIP call."""
+    L = nnc.lib()
+    big = nnc.Options()
+    big.workspace = 0x1000
+    big.workspace_bytes = 1 << 40
+    B = ctypes.byref(big)
+    # 256 x 256 x 256 x 4 core at rank 4: the first updates contract mode 3 and run
+    # ceil(4/4) * 2^26 / 4 = 2^24 items
+    st = L.nncp_fit(FAKE, 4, D(256, 256, 256, 4), 4, 10, _ptrs(4), B, None, None)
+    assert st == nnc.NNC_EUNSUPPORTED, st
+    assert "2^22" in nnc.last_error()
+    rk = (ctypes.c_int * 2)(4, 2)
+    res = (ctypes.c_double * 2)()
+    st = L.nncp_fit_batched(FAKE, 4, D(256, 256, 256, 4), 2, rk, 10, _ptrs(8), 0.0, res, 0, FAKE, 1 << 40, None)
+    assert st == nnc.NNC_EUNSUPPORTED, st
+    # a mode of 2^20 rows at rank 4 reaches the limit in the update's pairs
+    st = L.nncp_fit(FAKE, 2, D(1 << 20, 2), 4, 10, _ptrs(2), B, None, None)
+    assert st == nnc.NNC_EUNSUPPORTED, st
+
+
+def test_qdiv_float_reciprocal_division_exact_below_2_22():
+    """Brute force of the kernels' index division (a + 0.5) * RN(1/b) truncated, in IEEE
+    float32 with round-to-nearest-even, against integer division for every a < 2^22 and
+    a spread of divisors b (all of 1..96, then sampled up to 2^22)."""
+    import numpy as np
+    a = np.arange(1 << 22, dtype=np.int64)
+    af = a.astype(np.float32) + np.float32(0.5)
+    rng = np.random.default_rng(22)
+    bs = list(range(1, 97)) + [int(b) for b in rng.integers(97, 1 << 22, 40)] + [(1 << 22) - 1, 4093, 65521]
+    for b in bs:
+        inv = np.float32(1.0) / np.float32(b)
+        q = (af * inv).astype(np.int64)
+        assert np.array_equal(q, a // b), b
+
+
+def test_fill_uniform_validation():
+    L = nnc.lib()
+    assert L.nnc_fill_uniform(1, 2, None, 4, None) == nnc.NNC_EINVAL
+    assert L.nnc_fill_uniform(1, 2, FAKE, -1, None) == nnc.NNC_EINVAL
+    assert L.nnc_fill_uniform(1, 2, None, 0, None) == nnc.NNC_OK
+    assert L.nnc_fill_uniform_f64(1, 2, -1, FAKE, 4, None) == nnc.NNC_EINVAL
+    assert L.nnc_fill_uniform_f64(1, 2, 0, None, 4, None) == nnc.NNC_EINVAL

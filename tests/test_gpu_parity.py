@@ -5,6 +5,8 @@ the factor as a hi+lo bf16 pair, so in practice only X's rounding matters and th
 error is far below that bar); final relative residual within 1e-3 of the oracle after equal
 sweeps; integer work (conversion, exact examples, fixed points) bit-exact.
 """
+import zlib
+
 import numpy as np
 import pytest
 import torch
@@ -30,7 +32,7 @@ TTM_SHAPES = [
 @pytest.mark.parametrize("R", [1, 5, 16, 20, 32, 40])
 def test_ttm_fp32_every_mode(shape, R):
     nnc = need_gpu()
-    rng = np.random.default_rng(hash((shape, R)) % 2**32)
+    rng = np.random.default_rng(zlib.crc32(repr((shape, R)).encode()))
     X = rng.random(shape).astype(np.float32)
     Xd = dev(X)
     for n in range(len(shape)):
@@ -44,7 +46,7 @@ def test_ttm_fp32_every_mode(shape, R):
 @pytest.mark.parametrize("R", [3, 16, 20, 32])
 def test_ttm_bf16_every_mode(shape, R):
     nnc = need_gpu()
-    rng = np.random.default_rng(hash((shape, R, 1)) % 2**32)
+    rng = np.random.default_rng(zlib.crc32(repr((shape, R, 1)).encode()))
     X64 = synth.round_bf16(rng.random(shape))
     Xd = bf16_dev(X64)
     for n in range(len(shape)):
@@ -63,7 +65,7 @@ def test_ttm_bf16_every_mode(shape, R):
 @pytest.mark.parametrize("R", [12, 20])
 def test_ttm_mid_bf16_several_tiles_per_wave(shape, R):
     nnc = need_gpu()
-    rng = np.random.default_rng(hash((shape, R, 2)) % 2**32)
+    rng = np.random.default_rng(zlib.crc32(repr((shape, R, 2)).encode()))
     X64 = synth.round_bf16(rng.random(shape))
     A = rng.random((shape[0], R)).astype(np.float32)
     out = host(nnc.nnc_ttm(bf16_dev(X64), 0, dev(A)))
@@ -85,7 +87,7 @@ LAST_SHAPES = [(5, 64), (77, 520), (45, 136), (1000, 256), (70001, 128), (3000, 
 @pytest.mark.parametrize("dt", ["f32", "bf16"])
 def test_ttm_last_mode_row_contiguous(shape, R, dt):
     nnc = need_gpu()
-    rng = np.random.default_rng(hash((shape, R, dt)) % 2**32)
+    rng = np.random.default_rng(zlib.crc32(repr((shape, R, dt)).encode()))
     M, K = shape
     A = rng.random((K, R)).astype(np.float32)
     if dt == "bf16":
