@@ -176,6 +176,21 @@ nnc_status nncp_fit(const float *core, int ndim, const int64_t *core_dims, int r
                     float *const *cp_factors, const nnc_options *opt, nnc_report *rep, void *stream);
 
 /*
+ * nncp_fit for callers that cannot allocate device memory or pass a workspace: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
+ * kernels and results as nncp_fit, except that opt is nullable and only its eps is read
+ * (the workspace fields are ignored).  Its scratch is a static device array of
+ * nncp_noalloc_max_scratch_bytes() bytes (8 MiB) that each device holds from library load
+ * to process exit; a fit whose nncp_workspace_bytes() exceeds it is refused with
+ * NNC_EUNSUPPORTED before any HIP call.  The call itself allocates nothing.  Every call on a
+ * device shares that device's array, so calls that overlap on one device (from several host
+ * threads, or on several streams without ordering) race; calls in one stream order are safe.
+ */
+size_t nncp_noalloc_max_scratch_bytes(void);
+nnc_status nncp_fit_noalloc(const float *core, int ndim, const int64_t *core_dims, int rank, int iters,
+                            float *const *cp_factors, const nnc_options *opt, nnc_report *rep, void *stream);
+
+/*
  * Many independent nnCP fits of one core (random restarts, possibly different ranks) in a
  * single persistent launch: restart j has rank ranks[j] (host array) and factors
  * cp_factors[j*ndim + n] (core_dims[n] x ranks[j]).  rel_residuals: host, nbatch entries

@@ -59,7 +59,8 @@ EXPORTED = ["nnc_last_error", "nnc_device_ok", "nnc_set_timing", "nnc_ttm", "nnc
             "reconstruct_workspace_bytes", "reconstruct_residual", "reconstruct_sq_sums",
             "nntucker_grad", "nncpx_workspace_bytes", "nncpx_fit", "nmf_workspace_bytes", "nmf_fit",
             "nmf_batched_workspace_bytes", "nmf_fit_batched", "nncandelinc_restart_init_floats",
-            "nncandelinc_restarts", "nnc_mean_congruence", "nnc_fill_uniform", "nnc_fill_uniform_f64"]
+            "nncandelinc_restarts", "nnc_mean_congruence", "nnc_fill_uniform", "nnc_fill_uniform_f64",
+            "nncp_noalloc_max_scratch_bytes", "nncp_fit_noalloc"]
 
 _lib = None
 
@@ -86,6 +87,10 @@ def lib():
         L.nncp_workspace_bytes.restype = ctypes.c_size_t
         L.nncp_fit.argtypes = [_vp, ctypes.c_int, _i64p, ctypes.c_int, ctypes.c_int, _vpp,
                                ctypes.POINTER(Options), ctypes.POINTER(Report), _vp]
+        L.nncp_noalloc_max_scratch_bytes.argtypes = []
+        L.nncp_noalloc_max_scratch_bytes.restype = ctypes.c_size_t
+        L.nncp_fit_noalloc.argtypes = [_vp, ctypes.c_int, _i64p, ctypes.c_int, ctypes.c_int, _vpp,
+                                       ctypes.POINTER(Options), ctypes.POINTER(Report), _vp]
         L.nncp_batched_workspace_bytes.argtypes = [ctypes.c_int, _i64p, ctypes.c_int,
                                                    ctypes.POINTER(ctypes.c_int)]
         L.nncp_batched_workspace_bytes.restype = ctypes.c_size_t
@@ -303,6 +308,24 @@ def nncp_fit(core: torch.Tensor, rank: int, iters: int, cp_factors: Sequence[tor
     want = residual or report
     _check(lib().nncp_fit(core.data_ptr(), d, _dims(core.shape), int(rank), int(iters), _ptrs(cp_factors),
                           ctypes.byref(opt), ctypes.byref(rep) if want else None, _stream()))
+    return _cp_report(rep, report) if want else None
+
+
+def nncp_fit_noalloc(core: torch.Tensor, rank: int, iters: int, cp_factors: Sequence[torch.Tensor], *,
+                     eps: float = 1e-12, residual: bool = True, report: bool = False):
+    """nncp_fit without a workspace: the library's static device scratch serves instead, so
+    the call allocates no device memory.  Returns as nncp_fit."""
+    _dev(core, "core")
+    for k, f in enumerate(cp_factors):
+        _dev(f, "cp_factors[%d]" % k)
+    d = core.dim()
+    opt = Options()
+    opt.eps = float(eps)
+    rep = Report()
+    want = residual or report
+    _check(lib().nncp_fit_noalloc(core.data_ptr(), d, _dims(core.shape), int(rank), int(iters),
+                                  _ptrs(cp_factors), ctypes.byref(opt), ctypes.byref(rep) if want else None,
+                                  _stream()))
     return _cp_report(rep, report) if want else None
 
 

@@ -67,6 +67,34 @@ static nnc_status check_ptrs(const void *const *ptrs, int n, const char *what) {
   return NNC_OK;
 }
 
+// ------------------------------------------------------------------ static scratch
+// Scratch of the entry point that allocates nothing (nncp_fit_noalloc).  In host code the
+// name `scratch` is only a stand-in for the symbol: its device address is looked up once
+// per device, with that device current, and only that address is passed to kernels.  Every
+// call on one device shares that device's copy, so calls that overlap on a device race.
+constexpr size_t kStaticScratchBytes = (size_t)8 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static char *g_scratch_ptr[kMaxDevices];
+
+static nnc_status static_scratch(char **out) {
+  int dev = -1;
+  NNC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(NNC_EUNSUPPORTED, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(NNC_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = (char *)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return NNC_OK;
+}
+
 // ------------------------------------------------------------------ workspace layout
 struct Layout {
   size_t off = 0;
@@ -1207,6 +1235,21 @@ nnc_status nncp_fit(const float *core, int ndim, const int64_t *core_dims, int r
                 (opt && opt->workspace) ? opt->workspace_bytes : 0, w.total);
   return nncp_fit_at(core, ndim, core_dims, rank, iters, cp_factors, eps, rep, (char *)opt->workspace,
                      (hipStream_t)stream);
+}
+
+size_t nncp_noalloc_max_scratch_bytes(void) { return kStaticScratchBytes; }
+
+nnc_status nncp_fit_noalloc(const float *core, int ndim, const int64_t *core_dims, int rank, int iters,
+                            float *const *cp_factors, const nnc_options *opt, nnc_report *rep, void *stream) {
+  const double eps = opt ? opt->eps : 0.0;
+  NNC_TRY(check_nncp_args(core, ndim, core_dims, rank, iters, cp_factors, eps));
+  const CpWs w = cp_ws(cp_problem(ndim, core_dims), 1, &rank, false);
+  if (w.total > kStaticScratchBytes)
+    return fail(NNC_EUNSUPPORTED, "this nnCP needs %zu bytes of scratch, above the %zu-byte static maximum "
+                "of nncp_fit_noalloc (use nncp_fit with a workspace)", w.total, kStaticScratchBytes);
+  char *base = nullptr;
+  NNC_TRY(static_scratch(&base));
+  return nncp_fit_at(core, ndim, core_dims, rank, iters, cp_factors, eps, rep, base, (hipStream_t)stream);
 }
 
 size_t nncpx_workspace_bytes(int ndim, const int64_t *dims, int rank) {

@@ -232,6 +232,19 @@ def test_qdiv_float_reciprocal_division_exact_below_2_22():
         assert np.array_equal(q, a // b), b
 
 
+def test_nncp_noalloc_validation():
+    L = nnc.lib()
+    assert L.nncp_noalloc_max_scratch_bytes() == 8 << 20
+    assert L.nncp_fit_noalloc(None, 3, D(5, 5, 5), 3, 10, _ptrs(3), None, None, None) == nnc.NNC_EINVAL
+    assert L.nncp_fit_noalloc(FAKE, 3, D(5, 5, 5), 3, -1, _ptrs(3), None, None, None) == nnc.NNC_EINVAL
+    assert L.nncp_fit_noalloc(FAKE, 3, D(5, 5, 5), 40, 10, _ptrs(3), None, None, None) == nnc.NNC_EUNSUPPORTED
+    # 64 x 64 x 64 x 16 at rank 32: the contraction scratch alone is 2^16 rows x 32 floats =
+    # 8 MiB, so the total is above the maximum
+    assert L.nncp_workspace_bytes(4, D(64, 64, 64, 16), 32) > (8 << 20)
+    st = L.nncp_fit_noalloc(FAKE, 4, D(64, 64, 64, 16), 32, 10, _ptrs(4), None, None, None)
+    assert st == nnc.NNC_EUNSUPPORTED and "static maximum" in nnc.last_error()
+
+
 def test_fill_uniform_validation():
     L = nnc.lib()
     assert L.nnc_fill_uniform(1, 2, None, 4, None) == nnc.NNC_EINVAL

@@ -59,7 +59,7 @@ def test_nncp_zero_column_clips_match_oracle(core_dims, rank):
     B0[1][:, 1] = 0.0
     Bo, clips_o, _ = oracle.nncp(T, B0, 20)
     assert clips_o > 0
-    for fit in (nnc.nncp_fit,):
+    for fit in (nnc.nncp_fit, nnc.nncp_fit_noalloc):
         B = [dev(b) for b in B0]
         rep = fit(dev(T), rank, 20, B, report=True)
         assert rep.eps_clips == clips_o, (fit.__name__, rep.eps_clips, clips_o)
