@@ -499,6 +499,80 @@ static nnc_status fused_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, 
   return core_tail(b, G, A, eps, s);
 }
 
+// ------------------------------------------------------------------ fused three-way sweep
+// d = 3 with both X passes carrying the next small contraction (fused3_kernels.hip):
+//   pass 1:  Y0 = X x_2 A2^T x_1 A1^T         (side blocks: M_0)          -> rows of A0
+//   pass 2:  T = X x_0 A0^T, Y1 = T x_2 A2^T  (side blocks: S_0, M_1)     -> rows of A1
+//   Y2 = T x_1 A1^T beside the Gram of A1, M_2 and U = G x_0 S_0 x_1 S_1   -> rows of A2
+//   core update in one launch: den_G = U x_2 S_2 (its numerator from the last rows' partials).
+// P = X x_2 A2^T is never stored; seven launches per sweep.  NNC_NO_FUSED3 in the
+// environment selects the general fused schedule instead (for comparisons).
+static bool fused3_ok(const TuckerPlan &p, nnc_dtype dt, const void *X, const float *G, float *const *A) {
+  // FP32 X: the general schedule measured faster (the FP32 passes are already near their
+  // matrix-core bound, so the in-pass contractions lengthen them more than they save)
+  if (p.d != 3 || !p.fast || dt != NNC_BF16 || getenv("NNC_NO_FUSED3")) return false;
+  for (const void *ptr : {X, (const void *)A[0], (const void *)A[1], (const void *)A[2]})
+    if (reinterpret_cast<uintptr_t>(ptr) & 15u) return false;
+  if (reinterpret_cast<uintptr_t>(G) & 15u) return false;
+  return pass1y_ok(dt, p.N[0], p.N[1], p.N[2], p.R[0], p.R[1], p.R[2]) &&
+         pass2y_ok(dt, p.N[0], p.N[1], p.N[2], p.R[0], p.R[1], p.R[2]);
+}
+
+static Side3 side3(const TuckerBufs &b, const float *G, int n) {
+  const TuckerPlan &p = *b.p;
+  Side3 sd;
+  memset(&sd, 0, sizeof sd);
+  sd.nrows = (int)p.R[n];
+  sd.n = n;
+  for (int k = 0; k < 3; ++k) {
+    sd.R[k] = (int)p.R[k];
+    sd.S[k] = b.S(k);
+  }
+  sd.G = G;
+  sd.M = b.M();
+  sd.gmode = -1;
+  return sd;
+}
+
+static nnc_status fused3_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, float *G,
+                               float *const *A, double eps, hipStream_t s, PassTimer *tm) {
+  const TuckerPlan &p = *b.p;
+  if (tm) NNC_TRY(tm->start(s));
+  NNC_TRY(launch_pass1y(X, dt, p.N[0], p.N[1], p.N[2], A[2], p.R[2], A[1], p.R[1], b.Y(), side3(b, G, 0), s));
+  if (tm) NNC_TRY(tm->stop(s));
+  NNC_TRY(launch_mu_rows(b.Y(), G, A[0], b.M(), 1, p.N[0], p.R[1] * p.R[2], p.R[0], eps, b.clips(), b.gram(),
+                         nullptr, nullptr, s));
+  Side3 s1 = side3(b, G, 1);
+  s1.gram_part = b.gram();
+  s1.gmode = 0;
+  s1.gram_parts = (int)mu_rows_blocks(p.N[0]);
+  s1.S_store = b.S(0);
+  if (tm) NNC_TRY(tm->start(s));
+  NNC_TRY(launch_pass2y(X, dt, p.N[0], p.N[1], p.N[2], A[0], p.R[0], A[2], p.R[2], b.T(), b.Y(), s1, s));
+  if (tm) NNC_TRY(tm->stop(s));
+  NNC_TRY(launch_mu_rows(b.Y(), G, A[1], b.M(), p.R[0], p.N[1], p.R[2], p.R[1], eps, b.clips(), b.gram(),
+                         nullptr, nullptr, s));
+  CoreArgsHost h = core_args(b, G, A, eps);  // Gram of A1 and M_2 beside Y2 = T x_1 A1^T
+  h.gram_from = 1;
+  h.gram_to = 2;
+  h.gram = b.gram();
+  h.gram_parts = (int)mu_rows_blocks(p.N[1]);
+  h.next = 2;
+  h.u_out = b.G(0);  // U = G x_0 S_0 x_1 S_1 for the core update
+  NNC_TRY(launch_small_with_core(b.T(), p.R[0], p.N[1], p.N[2], A[1], p.R[1], 1, p.R[1], b.Y(), h, s));
+  NNC_TRY(launch_mu_rows(b.Y(), G, A[2], b.M(), p.R[0] * p.R[1], p.N[2], 1, p.R[2], eps, b.clips(), b.gram(),
+                         b.gpart(), nullptr, s));
+  CoreArgsHost c = core_args(b, G, A, eps);  // numerator, Gram of A2, den = U x_2 S_2, update
+  c.gram_from = 2;
+  c.gram_to = 3;
+  c.gram = b.gram();
+  c.gram_parts = (int)mu_rows_blocks(p.N[2]);
+  c.do_core = 1;
+  c.nparts = (int)mu_rows_blocks(p.N[2]);
+  c.next = -1;
+  return launch_core_last(c, s);
+}
+
 // ------------------------------------------------------------------ one sweep
 static nnc_status tucker_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, float *G,
                                float *const *A, double eps, hipStream_t s, PassTimer *tm) {
@@ -547,6 +621,14 @@ static nnc_status tucker_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt,
   NNC_TRY(core_chain(b, G, -1, b.G(3), &den, s));
   NNC_TRY(launch_mu_elem(G, b.G(2), den, p.gsize, eps, b.clips(), s));
   return NNC_OK;
+}
+
+// One sweep by the schedule that fits the shape.
+static nnc_status any_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, float *G, float *const *A,
+                            double eps, hipStream_t s, PassTimer *tm) {
+  if (fused3_ok(*b.p, dt, X, G, A)) return fused3_sweep(b, X, dt, G, A, eps, s, tm);
+  if (b.p->fast) return fused_sweep(b, X, dt, G, A, eps, s, tm);
+  return tucker_sweep(b, X, dt, G, A, eps, s, tm);
 }
 
 // ||X - G x {A}||^2 and ||X||^2 into b.red() (device), Tucker model.
@@ -878,8 +960,7 @@ nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *d
     const bool every = o.objective_every > 0;
     if (!graphs) {
       for (int t = ta; t < tb; ++t) {
-        NNC_TRY(p.fast ? fused_sweep(b, Xs, dts, core, factors, eps, s, tm)
-                       : tucker_sweep(b, Xs, dts, core, factors, eps, s, tm));
+        NNC_TRY(any_sweep(b, Xs, dts, core, factors, eps, s, tm));
         if (every && (t + 1) % o.objective_every == 0) {
           NNC_TRY(tucker_resid(b, xres, dres, core, factors, s));
           double red[2];
@@ -905,8 +986,7 @@ nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *d
       NNC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       nnc_status st = NNC_OK;
       for (int c = 0; c < count && st == NNC_OK; ++c)
-        st = p.fast ? fused_sweep(b, Xs, dts, core, factors, eps, cs, nullptr)
-                    : tucker_sweep(b, Xs, dts, core, factors, eps, cs, nullptr);
+        st = any_sweep(b, Xs, dts, core, factors, eps, cs, nullptr);
       hipError_t ec = hipStreamEndCapture(cs, &g);
       if (st != NNC_OK) {
         if (g) (void)hipGraphDestroy(g);

@@ -733,18 +733,148 @@ nnc_status launch_slice_step(const CoreArgsHost &h, hipStream_t s) {
 }
 
 // =====================================================================================
-// One launch for two independent steps: blocks [0, nm) build the rows of M_next (with the
-// new Gram of the factor just updated), blocks [nm, nm + tiles) contract a partial tensor
-// (small_body).  Each step alone leaves most CUs idle for most of its time, and the two
+// The core update in one launch when the last mode's Gram is the only one still changing:
+// with U = G x_0 S_0 x_1 S_1 ... x_{d-2} S_{d-2} formed beforehand (uslice_body, beside the
+// last mode's small contraction), den_G = U x_{d-1} S_{d-1}, and block i only needs slice i
+// of U, of G and of the numerator partials, so nothing crosses blocks:
+//   num[i] = sum_b part[b][i]  (b in order),  den[i] = U[i] x_{last} S_{d-1},
+//   G[i] <- G[i] * num[i] / max(den[i], eps)  (FP64 division, clips counted).
+// S_{d-1} is summed from its row-block partials in every block (block 0 stores it).
+// =====================================================================================
+// Slice i of U = (sum_i' S_0[i][i'] G[i']) x_1 S_1 ... x_{d-2} S_{d-2}, into a.T (the Gram of
+// a.gram, if any, summed on the way as in the other slice kernels).
+template <int RM, bool BIG>
+static __device__ void uslice_body(const SliceArgs &a, int i) {
+  extern __shared__ __attribute__((aligned(16))) float lds[];
+  const int d = a.d, tid = threadIdx.x;
+  float *Sl = lds;
+  float *red = Sl + d * RM * RM;
+  float *G = red + SliceLds<RM>::kRed;
+  const int R0 = a.R[0];
+  const int slice = a.gsize / R0;
+  float *H0 = G + a.gsize, *H1 = H0 + slice;
+  GramStage<RM> gs;
+  constexpr int GPTH = (BIG ? kSliceMax : kSliceMax / 2) / kSliceThreads;  // core values per thread
+  float gv[GPTH];
+#pragma unroll
+  for (int u = 0; u < GPTH; ++u) {
+    const int e = tid + u * kSliceThreads;
+    gv[u] = a.G[e < a.gsize ? e : a.gsize - 1];
+  }
+  gs.issue(a);
+  __builtin_amdgcn_sched_barrier(0);  // every load above is issued before any is used
+#pragma unroll
+  for (int u = 0; u < GPTH; ++u) {
+    const int e = tid + u * kSliceThreads;
+    if (e < a.gsize) G[e] = gv[u];
+  }
+  gs.finish(a, Sl, red);
+  __syncthreads();
+  for (int c = tid; c < slice; c += kSliceThreads) {  // mode 0 first: S_0 row i
+    float acc = 0.f;
+    for (int ip = 0; ip < R0; ++ip) acc = fmaf(Sl[i * RM + ip], G[ip * slice + c], acc);
+    H0[c] = acc;
+  }
+  __syncthreads();
+  float *cur = H0, *nxt = H1;
+  for (int k = 1; k < d - 1; ++k) {  // then modes 1 .. d-2 of the slice (modes 1 .. d-1)
+    int pre = 1, post = 1;
+    for (int t = 1; t < k; ++t) pre *= a.R[t];
+    for (int t = k + 1; t < d; ++t) post *= a.R[t];
+    slice_ttm<RM>(cur, nxt, pre, a.R[k], post, Sl + k * RM * RM);
+    __syncthreads();
+    float *t2 = cur;
+    cur = nxt;
+    nxt = t2;
+  }
+  for (int c = tid; c < slice; c += kSliceThreads) a.T[(int64_t)i * slice + c] = cur[c];
+}
+
+template <int RM, bool BIG>
+__global__ __launch_bounds__(kSliceThreads) void coreL_k(SliceArgs a, const float *__restrict__ part,
+                                                        int nparts) {
+  extern __shared__ __attribute__((aligned(16))) float lds[];
+  __shared__ unsigned int nclip;
+  const int d = a.d, tid = threadIdx.x, i = blockIdx.x;
+  float *Sl = lds;
+  float *red = Sl + d * RM * RM;
+  const int slice = a.gsize / a.R[0];
+  float *H0 = red + SliceLds<RM>::kRed, *H1 = H0 + slice;
+  constexpr int SPT = (BIG ? kSliceMax : kSliceMax / 2) / kSliceThreads;  // slice values per thread
+  constexpr int kNB = 64;                                                  // partials in flight
+  float uv[SPT];
+#pragma unroll
+  for (int u = 0; u < SPT; ++u) {
+    const int c = tid + u * kSliceThreads;
+    uv[u] = a.T[(int64_t)i * slice + (c < slice ? c : slice - 1)];
+  }
+  // the numerator of the thread's first entry: its first kNB partials now
+  const int c0 = tid < slice ? tid : slice - 1;
+  float pv[kNB];
+#pragma unroll
+  for (int u = 0; u < kNB; ++u) pv[u] = part[(int64_t)(u < nparts ? u : nparts - 1) * a.gsize + (int64_t)i * slice + c0];
+  GramStage<RM> gs;
+  gs.issue(a);
+  __builtin_amdgcn_sched_barrier(0);  // every load above is issued before any is used
+  if (tid == 0) nclip = 0;
+#pragma unroll
+  for (int u = 0; u < SPT; ++u) {
+    const int c = tid + u * kSliceThreads;
+    if (c < slice) H0[c] = uv[u];
+  }
+  gs.finish(a, Sl, red);
+  __syncthreads();
+  const int Rl = a.R[d - 1];
+  slice_ttm<RM>(H0, H1, slice / Rl, Rl, 1, Sl + (d - 1) * RM * RM);  // den = U[i] x_last S_last
+  __syncthreads();
+  unsigned int mine = 0;
+  for (int c = tid; c < slice; c += kSliceThreads) {
+    const int64_t e = (int64_t)i * slice + c;
+    float num = 0.f;  // partials in order from 0, kNB loads in flight per round
+    int b0 = 0;
+    if (c == tid) {
+#pragma unroll
+      for (int u = 0; u < kNB; ++u)
+        if (u < nparts) num += pv[u];
+      b0 = kNB;
+    }
+    for (; b0 < nparts; b0 += kNB) {
+      float v[kNB];
+#pragma unroll
+      for (int u = 0; u < kNB; ++u) v[u] = part[(int64_t)(b0 + u < nparts ? b0 + u : nparts - 1) * a.gsize + e];
+#pragma unroll
+      for (int u = 0; u < kNB; ++u)
+        if (b0 + u < nparts) num += v[u];
+    }
+    double dd = (double)H1[c];
+    if (dd < a.eps) {
+      dd = a.eps;
+      ++mine;
+    }
+    a.Gout[e] = (float)(((double)a.G[e] * (double)num) / dd);
+  }
+  if (mine) atomicAdd(&nclip, mine);
+  __syncthreads();
+  if (tid == 0 && nclip) atomicAdd(a.clips, (unsigned long long)nclip);
+}
+
+// =====================================================================================
+// One launch for independent steps: blocks [0, nm) build the rows of M_next (with the new
+// Gram of the factor just updated), blocks [nm, nm + tiles) contract a partial tensor
+// (small_body) and, when h.u_out is set, the R_0 blocks after them form the slices of
+// U = G x_0 S_0 ... x_{d-2} S_{d-2} for coreL_k.  Each step alone leaves most CUs idle for most of its time, and the two
 // do not depend on each other, so sharing a launch runs them side by side without the
 // cost of a second stream.
 // =====================================================================================
 template <int RMS, int RMC, bool BIG>
-__global__ __launch_bounds__(kSliceThreads) void small_mrows_k(SmallArgs sa, SliceArgs ca, int nm) {
+__global__ __launch_bounds__(kSliceThreads) void small_mrows_k(SmallArgs sa, SliceArgs ca, int nm,
+                                                              int64_t tiles) {
   if ((int)blockIdx.x < nm)
     mrows_body<RMC, BIG>(ca, blockIdx.x);
-  else
+  else if ((int64_t)blockIdx.x - nm < tiles)
     small_body<RMS>(sa, (int64_t)blockIdx.x - nm);
+  else
+    uslice_body<RMC, BIG>(ca, (int)((int64_t)blockIdx.x - nm - tiles));
 }
 
 nnc_status launch_small_with_core(const float *in, int64_t P, int64_t N, int64_t Q, const float *F,
@@ -755,24 +885,31 @@ nnc_status launch_small_with_core(const float *in, int64_t P, int64_t N, int64_t
   int64_t tiles;
   bool big;
   // the shared launch covers a core step that only forms a Gram and M_next
+  // the contraction's rank tile is padded up to RMC - 4 when smaller (rows past R are masked,
+  // so the values are the same), which keeps the instantiations to two per core tile
   const bool ok = !h.do_core && h.next >= 0 && slice_fits(h, &RMC, &big) &&
-                  small_args(in, P, N, Q, F, ldl, ldr, R, out, &sa, &RMS, &tiles) &&
-                  (RMS == RMC || RMS == RMC - 4) && tiles + h.R[h.next] <= 0x7fffffff;
+                  small_args(in, P, N, Q, F, ldl, ldr, R, out, &sa, &RMS, &tiles) && RMS <= RMC &&
+                  tiles + h.R[h.next] + h.R[0] <= 0x7fffffff;
+  if (ok && RMS < RMC - 4) RMS = RMC - 4;
   if (!ok) {
+    if (h.u_out) return fail(NNC_EUNSUPPORTED, "U slices need the shared small-contraction launch");
     NNC_TRY(launch_core_step(h, s));
     return launch_ttm_small(in, P, N, Q, F, ldl, ldr, R, out, s);
   }
   SliceArgs ca = slice_args(h);
   ca.n = h.next;
   ca.M = h.M;
+  ca.T = h.u_out;
   const int nm = (int)h.R[h.next];
+  const int nu = h.u_out ? (int)h.R[0] : 0;
   size_t lds = 0;
 #define NNC_SM(RMSV, RMCV, BIGV)                                                                  \
   do {                                                                                            \
-    lds = std::max(SliceLds<RMCV>::bytes(ca.d, ca.gsize, ca.gsize / nm, true), small_lds(sa.W, RMSV)); \
+    lds = std::max(SliceLds<RMCV>::bytes(ca.d, ca.gsize, std::max(ca.gsize / nm, ca.gsize / ca.R[0]), true), \
+                   small_lds(sa.W, RMSV));                                                        \
     NNC_TRY(allow_slice_lds(reinterpret_cast<const void *>(small_mrows_k<RMSV, RMCV, BIGV>), lds)); \
-    hipLaunchKernelGGL((small_mrows_k<RMSV, RMCV, BIGV>), dim3((unsigned)(nm + tiles)),            \
-                       dim3(kSliceThreads), lds, s, sa, ca, nm);                                  \
+    hipLaunchKernelGGL((small_mrows_k<RMSV, RMCV, BIGV>), dim3((unsigned)(nm + tiles + nu)),       \
+                       dim3(kSliceThreads), lds, s, sa, ca, nm, tiles);                           \
   } while (0)
 #define NNC_SM2(RMCV)                                  \
   do {                                                 \
@@ -787,6 +924,37 @@ nnc_status launch_small_with_core(const float *in, int64_t P, int64_t N, int64_t
   else NNC_SM2(32);
 #undef NNC_SM2
 #undef NNC_SM
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+nnc_status launch_core_last(const CoreArgsHost &h, hipStream_t s) {
+  int RM;
+  bool big;
+  if (!h.do_core || h.gram_to != h.d || h.gram_from != h.d - 1 || !h.gpart || h.nparts < 1 || !h.t0 ||
+      !slice_fits(h, &RM, &big))
+    return fail(NNC_EUNSUPPORTED, "core update in one launch: unsupported arguments");
+  SliceArgs a = slice_args(h);
+  a.T = h.t0;
+  a.Gout = h.G;
+#define NNC_CL(RMV, BIGV)                                                                         \
+  do {                                                                                            \
+    const size_t lds = SliceLds<RMV>::bytes(a.d, a.gsize, a.gsize / a.R[0], false);               \
+    NNC_TRY(allow_slice_lds(reinterpret_cast<const void *>(coreL_k<RMV, BIGV>), lds));            \
+    hipLaunchKernelGGL((coreL_k<RMV, BIGV>), dim3(a.R[0]), dim3(kSliceThreads), lds, s, a, h.gpart, \
+                       h.nparts);                                                                 \
+  } while (0)
+#define NNC_CL2(RMV)                  \
+  do {                                \
+    if (big) NNC_CL(RMV, true);       \
+    else NNC_CL(RMV, false);          \
+  } while (0)
+  if (RM == 8) NNC_CL2(8);
+  else if (RM == 16) NNC_CL2(16);
+  else if (RM == 24) NNC_CL2(24);
+  else NNC_CL2(32);
+#undef NNC_CL2
+#undef NNC_CL
   NNC_HIP(hipGetLastError());
   return NNC_OK;
 }

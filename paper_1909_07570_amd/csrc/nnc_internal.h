@@ -104,6 +104,32 @@ nnc_status launch_check_finite(const float *x, int64_t n, unsigned int *flag, hi
 nnc_status launch_fill_u64(unsigned long long *x, int64_t n, unsigned long long v, hipStream_t s);
 nnc_status launch_fill_f32(float *x, int64_t n, float v, hipStream_t s);
 
+// ------------------------------------------------------------------ fused3_kernels.hip
+// Side job of the fused three-way passes: blocks [0, nrows) each compute row blockIdx.x of
+// M_n = unfold_n(G x_{k!=n} S_k) unfold_n(G)^T for the core G (R[0] x R[1] x R[2]).  S[k] are
+// the stored Grams; with gram_part set, the Gram of mode gmode is summed from gram_parts
+// row-block partials instead (block 0 stores it to S_store).
+struct Side3 {
+  int nrows;
+  int n;
+  int R[3];
+  const float *G;
+  const float *S[3];
+  const float *gram_part;
+  int gmode, gram_parts;
+  float *S_store;
+  float *M;
+};
+// Y0 = X x_2 A2^T x_1 A1^T (N0 x R1 x R2) without storing X x_2 A2^T.
+bool pass1y_ok(nnc_dtype dt, int64_t N0, int64_t N1, int64_t N2, int64_t R0, int64_t R1, int64_t R2);
+nnc_status launch_pass1y(const void *X, nnc_dtype dt, int64_t N0, int64_t N1, int64_t N2, const float *A2,
+                         int64_t R2, const float *A1, int64_t R1, float *Y0, const Side3 &side, hipStream_t s);
+// T = X x_0 A0^T (R0 x N1 x N2) and Y1 = T x_2 A2^T (R0 x N1 x R2).
+bool pass2y_ok(nnc_dtype dt, int64_t N0, int64_t N1, int64_t N2, int64_t R0, int64_t R1, int64_t R2);
+nnc_status launch_pass2y(const void *X, nnc_dtype dt, int64_t N0, int64_t N1, int64_t N2, const float *A0,
+                         int64_t R0, const float *A2, int64_t R2, float *T, float *Y1, const Side3 &side,
+                         hipStream_t s);
+
 // ------------------------------------------------------------------ nnCP (cp_kernels.hip)
 struct CpProblem {
   int d;
@@ -159,8 +185,12 @@ struct CoreArgsHost {
   double eps;
   unsigned long long *clips;
   int gram_from, gram_to, do_core, next;
+  float *u_out;  // launch_small_with_core: also U = G x_0 S_0 ... x_{d-2} S_{d-2} here (R_0 blocks)
 };
 nnc_status launch_core_step(const CoreArgsHost &h, hipStream_t s);
+// The core update in one launch (numerator from h.gpart, Gram of the last factor from its
+// partials, den_G = U x_{d-1} S_{d-1} with U in h.t0, formed by launch_small_with_core).
+nnc_status launch_core_last(const CoreArgsHost &h, hipStream_t s);
 // launch_core_step(h) and launch_ttm_small(...) (independent of each other) in one launch
 // when the core step only forms a Gram and M_next; two launches otherwise.
 nnc_status launch_small_with_core(const float *in, int64_t P, int64_t N, int64_t Q, const float *F,
