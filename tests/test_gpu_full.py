@@ -8,6 +8,7 @@
   final relative residuals within 1e-3 of the oracle's, stored in tests/golden/c2_reference.json
   by tests/golden/make_c2_reference.py (oracle only).
 - The adjoint at 256^3 with a 32^3 core against the oracle gradient.
+- The two X-streaming passes of the 64^5 workload on sampled outputs.
 """
 import json
 import os
@@ -153,18 +154,15 @@ def test_c4_adjoint_full_size():
         assert rel_fro(host(g), go) <= 1e-4
 
 
-def test_c5_5way_full_size():
+def test_c5_5way_passes_sampled():
     """64^5 FP32 (4.3 GB), multirank 8^5: the two X-streaming passes on sampled outputs, each
-    recomputed by the oracle from its slice of X; three sweeps with a non-increasing relative
-    residual, nonnegative iterates and no clipped denominators; 64 nnCP restarts of the fitted
-    8^5 core at ranks 2..16 in one batched launch, four of them against the oracle."""
+    recomputed by the oracle from its slice of X (the full-sweep fit and the 64 batched
+    restarts are in test_gpu_c5.py)."""
     nnc = need_gpu()
-    import torch
     dims, ranks = (64,) * 5, (8,) * 5
     X32, _ = synth.planted_tensor(5, dims, 6, noise=1e-3, dtype="f32")
     Xd = dev(X32)
     A0 = synth.init_factors(5, dims, ranks)
-    G0 = synth.init_core(5, ranks)
     rng = np.random.default_rng(5)
     rows = X32.reshape(64 ** 4, 64)     # last mode contiguous
     cols = X32.reshape(64, 64 ** 4)     # first mode leading
@@ -179,25 +177,3 @@ def test_c5_5way_full_size():
         q = int(rng.integers(64 ** 4))
         ref = oracle.ttm_t(cols[:, q].astype(np.float64)[:, None], 0, A0[0].astype(np.float64))[:, 0]
         assert rel_fro(T[:, q], ref) <= 1e-5
-    del P, T
-    G = dev(G0)
-    A = [dev(a) for a in A0]
-    rep = nnc.nntucker_fit(Xd, ranks, 3, G, A, objective_every=1)
-    h = rep.history
-    assert len(h) == 3 and all(np.isfinite(h))
-    assert all(h[i + 1] <= h[i] * (1 + 1e-6) for i in range(len(h) - 1)), h
-    assert rep.eps_clips == 0
-    assert float(G.min()) >= 0 and all(float(a.min()) >= 0 for a in A)
-    del Xd
-    torch.cuda.empty_cache()
-    core = G
-    core_h = host(core)
-    cp_ranks = [2 + (j % 15) for j in range(64)]
-    inits = [synth.init_cp_factors(5, ranks, r, restart=j) for j, r in enumerate(cp_ranks)]
-    facs = [[dev(b) for b in B0] for B0 in inits]
-    res = nnc.nncp_fit_batched(core, cp_ranks, 50, facs)
-    for j in (0, 13, 31, 63):
-        Bo, _, _ = oracle.nncp(core_h, inits[j], 50)
-        assert abs(res[j] - oracle.cp_rel_residual(core_h, Bo)) <= 1e-4, (j, res[j])
-        for b, bo in zip(facs[j], Bo):
-            assert rel_fro(host(b), bo) <= 1e-3
