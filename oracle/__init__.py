@@ -307,3 +307,117 @@ def restart_fit(X, alg: int, parts, outer: int, inner: int, truth=None, eps: flo
         out = nncandelinc_alg2(X, parts[0:3], parts[3:6], parts[6:9], outer, inner, eps)
     C = out["C"]
     return out["cp_rel"], (mean_congruence(C, truth) if truth is not None else None), C
+
+
+# ------------------------------------------------------------------ real-valued CANDELINC
+# Section 2.2: a (minimal) Tucker decomposition of X, a CPD of its core, and the substitution
+# of that CPD into the Tucker model, which gives a CPD of X with factors F^(i) A_G^(i).  The
+# paper names no algorithm for either fit ("readily available tools", Section 4, beside the
+# optimization problem nnCANDELINC without its constraints).  The reading taken here is
+# alternating least squares for both, in the same Gauss-Seidel order as the nonnegative
+# sweep (Tucker factors 1..d, then the core; CP factors 1..d).  Each block update is the exact
+# minimizer of 0.5 ||X - model||_F^2 over that block with the others fixed, written with a
+# dense solve (numpy.linalg.solve) as the library step.  After each Tucker factor's step the
+# factor is replaced by the Q of its thin QR (R with a positive diagonal) and R is absorbed
+# into the core: the model is unchanged, the factors stay orthonormal, so the core's CP fit
+# measures the same error as the lifted CP fit of X.
+
+
+def mode_solve(T, n: int, S) -> np.ndarray:
+    """T x_n S^{-1} for a nonsingular S (R x R, R = T.shape[n]): every mode-n fibre of T
+    replaced by the solution of S y = fibre."""
+    T, S = _f64(T), _f64(S)
+    assert S.shape == (T.shape[n], T.shape[n])
+    moved = np.moveaxis(T, n, 0)
+    sol = np.linalg.solve(S, moved.reshape(T.shape[n], -1))
+    return np.ascontiguousarray(np.moveaxis(sol.reshape(moved.shape), 0, n))
+
+
+def qr_pos(A):
+    """Thin QR A = Q R with R upper triangular and its diagonal positive (unique for a full
+    column rank A): numpy's Householder QR with the signs of R's rows fixed."""
+    Q, R = np.linalg.qr(_f64(A))
+    sg = np.where(np.diag(R) < 0, -1.0, 1.0)
+    return np.ascontiguousarray(Q * sg), np.ascontiguousarray(R * sg[:, None])
+
+
+def tucker_ls_factor(X, G, A, n: int) -> np.ndarray:
+    """Least-squares update of F^(n) (= A_n) with the core and the other factors fixed.
+    Writing the model's mode-n unfolding as A_n G_(n) Z^T (Z the Kronecker product of the
+    other factors), the minimizer is A_n = X_(n) Z G_(n)^T K_n^{-1} with
+    X_(n) Z G_(n)^T = contraction of Y = X x_{k!=n} A_k^T with G over every mode but n, and
+    K_n = G_(n) (Z^T Z) G_(n)^T = contraction of G x_{k!=n} S_k with G over every mode but n
+    (S_k = A_k^T A_k)."""
+    d = len(A)
+    Y = _f64(X)
+    H = _f64(G)
+    for k in range(d):
+        if k != n:
+            Y = ttm_t(Y, k, A[k])
+            H = nmode(H, k, gram(A[k]))
+    num = contract_except(Y, G, n)
+    K = contract_except(H, G, n)
+    return np.ascontiguousarray(np.linalg.solve(K, num.T).T)
+
+
+def tucker_ls_core(X, A) -> np.ndarray:
+    """Least-squares update of the core with every factor fixed: the normal equations read
+    G x_1 S_1 ... x_d S_d = X x_1 A_1^T ... x_d A_d^T, solved one mode at a time."""
+    num = _f64(X)
+    for k in range(len(A)):
+        num = ttm_t(num, k, A[k])
+    G = num
+    for k in range(len(A)):
+        G = mode_solve(G, k, gram(A[k]))
+    return G
+
+
+def tucker_ls(X, G0, A0, iters: int, history: bool = False):
+    """Real Tucker fit by alternating least squares with orthonormalized factors; returns
+    (G, [A_n], f_hist or None) with f_t = 0.5 ||X - G x {A}||_F^2 after sweep t."""
+    X = _f64(X)
+    G = _f64(G0).copy()
+    A = [_f64(a).copy() for a in A0]
+    hist = []
+    for _ in range(iters):
+        for n in range(len(A)):
+            A[n], R = qr_pos(tucker_ls_factor(X, G, A, n))
+            G = nmode(G, n, R)
+        G = tucker_ls_core(X, A)
+        if history:
+            hist.append(0.5 * tucker_rel_residual(X, G, A) ** 2 * sumsq(X))
+    return G, A, (np.array(hist) if history else None)
+
+
+def cp_ls_factor(T, B, n: int) -> np.ndarray:
+    """Least-squares update of CP factor n with the others fixed: B_n = M_n H_n^{-1}, with
+    M_n the MTTKRP of T with the other factors and H_n the Hadamard product of their Grams."""
+    H = np.ones((B[0].shape[1], B[0].shape[1]))
+    for k in range(len(B)):
+        if k != n:
+            H = H * gram(B[k])
+    M = mttkrp(T, n, B)
+    return np.ascontiguousarray(np.linalg.solve(H, M.T).T)
+
+
+def cp_ls(T, B0, iters: int, history: bool = False):
+    """Real CP fit of T by alternating least squares; returns ([B_n], f_hist or None)."""
+    T = _f64(T)
+    B = [_f64(b).copy() for b in B0]
+    hist = []
+    for _ in range(iters):
+        for n in range(len(B)):
+            B[n] = cp_ls_factor(T, B, n)
+        if history:
+            hist.append(0.5 * cp_rel_residual(T, B) ** 2 * sumsq(T))
+    return B, (np.array(hist) if history else None)
+
+
+def candelinc(X, G0, A0, B0, tucker_iters: int, cp_iters: int):
+    """Real-valued CANDELINC end to end (Section 2.2): Tucker fit, CP fit of its core, lift
+    C_n = F^(n) A_G^(n), residuals of the three models."""
+    G, A, _ = tucker_ls(X, G0, A0, tucker_iters)
+    B, _ = cp_ls(G, B0, cp_iters)
+    C = lift(A, B)
+    return dict(G=G, A=A, B=B, C=C, tucker_rel=tucker_rel_residual(X, G, A),
+                core_rel=cp_rel_residual(G, B), cp_rel=cp_rel_residual(X, C))
