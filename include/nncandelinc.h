@@ -10,6 +10,9 @@
  *                A_n ~ F_n B_n (nmf_fit, nmf_fit_batched), and the same lift.
  * Scoring (Section 4.1): reconstruct_residual and nnc_mean_congruence.  The random-restart
  * study of Section 4.2 runs as one launch (nncandelinc_restarts).
+ * Real-valued CANDELINC (Section 2.2, the same problem without the nonnegativity
+ * constraints): a Tucker fit by alternating least squares (tucker_ls_fit), a CP fit of its
+ * core by alternating least squares (cp_ls_fit), and the same lift.
  *
  * Conventions shared by every entry point
  *   - Tensors are dense and row-major (last index fastest): element (i_1, ..., i_d) of a
@@ -189,6 +192,46 @@ nnc_status nncp_fit(const float *core, int ndim, const int64_t *core_dims, int r
 size_t nncp_noalloc_max_scratch_bytes(void);
 nnc_status nncp_fit_noalloc(const float *core, int ndim, const int64_t *core_dims, int rank, int iters,
                             float *const *cp_factors, const nnc_options *opt, nnc_report *rep, void *stream);
+
+/*
+ * Real-valued Tucker fit (the Tucker step of CANDELINC, Section 2.2; the paper leaves the
+ * algorithm to standard tools).  Exactly `iters` sweeps of alternating least squares in the
+ * nonnegative fit's order, each block replaced by the exact minimizer of
+ * 0.5 ||X - G x {A}||_F^2 over that block:
+ *   factor n:  A* = num_n K_n^{-1},  num_n as in nntucker_fit,
+ *              K_n = unfold_n(G x_{k!=n} A_k^T A_k) unfold_n(G)^T;
+ *              then the thin QR A* = Q R (R upper triangular, positive diagonal, by Cholesky
+ *              of A*^T A* in FP64): A_n <- Q and G <- G x_n R, which leaves the model as is;
+ *   core:      G <- (X x_1 A_1^T ... x_d A_d^T) x_1 (A_1^T A_1)^{-1} ... x_d (A_d^T A_d)^{-1}.
+ * Before the first sweep each initial factor is orthonormalized the same way (the initial
+ * model is unchanged), so the systems are well conditioned from the first step on.
+ * On return every factor has orthonormal columns (to FP32 rounding), so the CP error of the
+ * core equals the error of the lifted CP against the Tucker model.  The R x R systems are
+ * solved in FP64 (Gauss-Jordan inverses, no pivoting).
+ * Arguments as nntucker_fit, except: every multirank[n] <= 32 (else NNC_EUNSUPPORTED);
+ * entries may have any sign; eps is ignored and eps_clips reports 0.  With rep non-NULL a
+ * system that was not positive definite (a rank-deficient core unfolding or factor, e.g. a
+ * multirank above the data's multilinear rank with no noise) returns NNC_ENUMERIC, and the
+ * outputs are then unspecified.  Workspace: tucker_ls_workspace_bytes() (the same size as
+ * nntucker_workspace_bytes()).
+ */
+size_t tucker_ls_workspace_bytes(int ndim, const int64_t *dims, const int64_t *multirank);
+nnc_status tucker_ls_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *dims,
+                         const int64_t *multirank, int iters, float *core, float *const *factors,
+                         const nnc_options *opt, nnc_report *rep, void *stream);
+
+/*
+ * Real-valued CP of a (small) tensor, here the Tucker core (the CPD step of CANDELINC,
+ * Section 2.2): exactly `iters` sweeps of alternating least squares in one persistent launch,
+ * factor n (n = 1..d in order):  B_n <- M_n H_n^{-1}  (M_n, H_n as in nncp_fit; H_n inverted
+ * in FP64 by Gauss-Jordan elimination).  rank <= 32.  Arguments and report as nncp_fit
+ * (workspace at least cp_ls_workspace_bytes(), the same size as nncp_workspace_bytes());
+ * eps is ignored.  With rep non-NULL an H_n that was not positive definite returns
+ * NNC_ENUMERIC.
+ */
+size_t cp_ls_workspace_bytes(int ndim, const int64_t *core_dims, int rank);
+nnc_status cp_ls_fit(const float *core, int ndim, const int64_t *core_dims, int rank, int iters,
+                     float *const *cp_factors, const nnc_options *opt, nnc_report *rep, void *stream);
 
 /*
  * Many independent nnCP fits of one core (random restarts, possibly different ranks) in a

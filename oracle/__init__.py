@@ -374,10 +374,15 @@ def tucker_ls_core(X, A) -> np.ndarray:
 
 def tucker_ls(X, G0, A0, iters: int, history: bool = False):
     """Real Tucker fit by alternating least squares with orthonormalized factors; returns
-    (G, [A_n], f_hist or None) with f_t = 0.5 ||X - G x {A}||_F^2 after sweep t."""
+    (G, [A_n], f_hist or None) with f_t = 0.5 ||X - G x {A}||_F^2 after sweep t.  The initial
+    factors are orthonormalized first (A_n = Q R, A_n <- Q, G <- G x_n R): the same initial
+    model, with well-conditioned least-squares systems from the first step on."""
     X = _f64(X)
     G = _f64(G0).copy()
     A = [_f64(a).copy() for a in A0]
+    for n in range(len(A)):
+        A[n], R = qr_pos(A[n])
+        G = nmode(G, n, R)
     hist = []
     for _ in range(iters):
         for n in range(len(A)):

@@ -60,7 +60,8 @@ EXPORTED = ["nnc_last_error", "nnc_device_ok", "nnc_set_timing", "nnc_ttm", "nnc
             "nntucker_grad", "nncpx_workspace_bytes", "nncpx_fit", "nmf_workspace_bytes", "nmf_fit",
             "nmf_batched_workspace_bytes", "nmf_fit_batched", "nncandelinc_restart_init_floats",
             "nncandelinc_restarts", "nnc_mean_congruence", "nnc_fill_uniform", "nnc_fill_uniform_f64",
-            "nncp_noalloc_max_scratch_bytes", "nncp_fit_noalloc"]
+            "nncp_noalloc_max_scratch_bytes", "nncp_fit_noalloc", "tucker_ls_workspace_bytes",
+            "tucker_ls_fit", "cp_ls_workspace_bytes", "cp_ls_fit"]
 
 _lib = None
 
@@ -83,6 +84,13 @@ def lib():
         L.nntucker_workspace_bytes.restype = ctypes.c_size_t
         L.nntucker_fit.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _i64p, _i64p, ctypes.c_int, _vp,
                                    _vpp, ctypes.POINTER(Options), ctypes.POINTER(Report), _vp]
+        L.tucker_ls_workspace_bytes.argtypes = [ctypes.c_int, _i64p, _i64p]
+        L.tucker_ls_workspace_bytes.restype = ctypes.c_size_t
+        L.tucker_ls_fit.argtypes = L.nntucker_fit.argtypes
+        L.cp_ls_workspace_bytes.argtypes = [ctypes.c_int, _i64p, ctypes.c_int]
+        L.cp_ls_workspace_bytes.restype = ctypes.c_size_t
+        L.cp_ls_fit.argtypes = [_vp, ctypes.c_int, _i64p, ctypes.c_int, ctypes.c_int, _vpp,
+                                ctypes.POINTER(Options), ctypes.POINTER(Report), _vp]
         L.nncp_workspace_bytes.argtypes = [ctypes.c_int, _i64p, ctypes.c_int]
         L.nncp_workspace_bytes.restype = ctypes.c_size_t
         L.nncp_fit.argtypes = [_vp, ctypes.c_int, _i64p, ctypes.c_int, ctypes.c_int, _vpp,
@@ -251,6 +259,22 @@ def nntucker_fit(X: torch.Tensor, multirank: Sequence[int], iters: int, core: to
                  use_graph: bool = True, report: bool = True,
                  workspace: Optional[torch.Tensor] = None) -> Optional[FitReport]:
     """nnTucker by multiplicative updates, `iters` sweeps, in place on core and factors."""
+    return _tucker_fit(lib().nntucker_fit, X, multirank, iters, core, factors, x_fp32, fp32_final_sweeps,
+                       eps, objective_every, use_graph, report, workspace)
+
+
+def tucker_ls_fit(X: torch.Tensor, multirank: Sequence[int], iters: int, core: torch.Tensor,
+                  factors: Sequence[torch.Tensor], *, x_fp32: Optional[torch.Tensor] = None,
+                  fp32_final_sweeps: int = 0, objective_every: int = 0, use_graph: bool = True,
+                  report: bool = True, workspace: Optional[torch.Tensor] = None) -> Optional[FitReport]:
+    """Real-valued Tucker fit by alternating least squares with orthonormalized factors,
+    `iters` sweeps, in place (the Tucker step of CANDELINC, Section 2.2)."""
+    return _tucker_fit(lib().tucker_ls_fit, X, multirank, iters, core, factors, x_fp32, fp32_final_sweeps,
+                       0.0, objective_every, use_graph, report, workspace)
+
+
+def _tucker_fit(fn, X, multirank, iters, core, factors, x_fp32, fp32_final_sweeps, eps, objective_every,
+                use_graph, report, workspace):
     _dev(X, "X", (torch.float32, torch.bfloat16))
     _dev(core, "core")
     for k, f in enumerate(factors):
@@ -272,9 +296,9 @@ def nntucker_fit(X: torch.Tensor, multirank: Sequence[int], iters: int, core: to
     if objective_every > 0:
         hist = (ctypes.c_double * max(1, iters // objective_every + 1))()
         rep.objective_history = ctypes.cast(hist, _dp)
-    st = lib().nntucker_fit(X.data_ptr(), _xdt(X), d, _dims(X.shape), _dims(multirank), int(iters),
-                            core.data_ptr(), _ptrs(factors), ctypes.byref(opt),
-                            ctypes.byref(rep) if (report or objective_every) else None, _stream())
+    st = fn(X.data_ptr(), _xdt(X), d, _dims(X.shape), _dims(multirank), int(iters),
+            core.data_ptr(), _ptrs(factors), ctypes.byref(opt),
+            ctypes.byref(rep) if (report or objective_every) else None, _stream())
     _check(st)
     if not (report or objective_every):
         return None
@@ -308,6 +332,25 @@ def nncp_fit(core: torch.Tensor, rank: int, iters: int, cp_factors: Sequence[tor
     want = residual or report
     _check(lib().nncp_fit(core.data_ptr(), d, _dims(core.shape), int(rank), int(iters), _ptrs(cp_factors),
                           ctypes.byref(opt), ctypes.byref(rep) if want else None, _stream()))
+    return _cp_report(rep, report) if want else None
+
+
+def cp_ls_fit(core: torch.Tensor, rank: int, iters: int, cp_factors: Sequence[torch.Tensor], *,
+              residual: bool = True, report: bool = False):
+    """Real-valued CP of the core by alternating least squares in one persistent launch, in
+    place (the CPD step of CANDELINC, Section 2.2).  Returns as nncp_fit."""
+    _dev(core, "core")
+    for k, f in enumerate(cp_factors):
+        _dev(f, "cp_factors[%d]" % k)
+    d = core.dim()
+    ws = _workspace(lib().cp_ls_workspace_bytes(d, _dims(core.shape), int(rank)), core.device)
+    opt = Options()
+    opt.workspace = ws.data_ptr()
+    opt.workspace_bytes = ws.numel()
+    rep = Report()
+    want = residual or report
+    _check(lib().cp_ls_fit(core.data_ptr(), d, _dims(core.shape), int(rank), int(iters), _ptrs(cp_factors),
+                           ctypes.byref(opt), ctypes.byref(rep) if want else None, _stream()))
     return _cp_report(rep, report) if want else None
 
 

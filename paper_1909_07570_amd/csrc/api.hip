@@ -631,6 +631,62 @@ static nnc_status any_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, fl
   return tucker_sweep(b, X, dt, G, A, eps, s, tm);
 }
 
+// ------------------------------------------------------------------ real Tucker sweep
+// One sweep of the real-valued Tucker fit (alternating least squares with orthonormalized
+// factors, Section 2.2): the X passes and small contractions of the general sweep above, with
+// the least-squares updates of ls_kernels.hip in place of the multiplicative ones.
+static nnc_status ls_factor(const TuckerBufs &b, int n, const float *Y, float *G, float *A, hipStream_t s) {
+  const TuckerPlan &p = *b.p;
+  const int64_t pre = prod(p.R, 0, n), post = prod(p.R, n + 1, p.d);
+  NNC_TRY(launch_contract_except(Y, G, pre, p.N[n], p.R[n], post, b.num(), s));  // num_n
+  const float *H = nullptr;
+  NNC_TRY(core_chain(b, G, n, nullptr, &H, s));
+  NNC_TRY(launch_contract_except(H, G, pre, p.R[n], p.R[n], post, b.M(), s));  // K_n
+  return launch_ls_factor(b.num(), b.M(), p.N[n], p.R[n], A, G, pre, post, b.S(n), b.clips(), s);
+}
+
+static nnc_status ls_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, float *G, float *const *A,
+                           hipStream_t s, PassTimer *tm) {
+  const TuckerPlan &p = *b.p;
+  const int d = p.d;
+  if (tm) NNC_TRY(tm->start(s));
+  NNC_TRY(launch_ttm(X, dt, p.size / p.N[d - 1], p.N[d - 1], 1, A[d - 1], p.R[d - 1], 1, p.R[d - 1],
+                     b.P(), s, true));
+  if (tm) NNC_TRY(tm->stop(s));
+  const float *U = b.P();
+  for (int n = 0; n < d - 1; ++n) {
+    int64_t cur[kMaxDim];
+    for (int k = 0; k < d; ++k) cur[k] = (k < n || k == d - 1) ? p.R[k] : p.N[k];
+    int modes[kMaxDim], nm = 0;
+    for (int k = n + 1; k < d - 1; ++k) modes[nm++] = k;
+    const float *Y = nullptr;
+    int64_t ycur[kMaxDim];
+    memcpy(ycur, cur, sizeof ycur);
+    NNC_TRY(chain(U, d, ycur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
+    NNC_TRY(ls_factor(b, n, Y, G, A[n], s));
+    if (n < d - 2) {
+      float *Un = b.U(n % 2);
+      NNC_TRY(ttm_mode(U, NNC_F32, d, cur, n, A[n], p.R[n], Un, s));
+      U = Un;
+    }
+  }
+  if (tm) NNC_TRY(tm->start(s));
+  NNC_TRY(launch_ttm(X, dt, 1, p.N[0], p.size / p.N[0], A[0], p.R[0], 1, p.R[0], b.T(), s, true));
+  if (tm) NNC_TRY(tm->stop(s));
+  int64_t cur[kMaxDim];
+  for (int k = 0; k < d; ++k) cur[k] = (k == 0) ? p.R[0] : p.N[k];
+  int modes[kMaxDim], nm = 0;
+  for (int k = 1; k < d - 1; ++k) modes[nm++] = k;
+  const float *Y = nullptr;
+  NNC_TRY(chain(b.T(), d, cur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
+  NNC_TRY(ls_factor(b, d - 1, Y, G, A[d - 1], s));
+  // core: numerator X x_k A_k^T (every factor new), then the solves with the Grams
+  NNC_TRY(ttm_mode(Y, NNC_F32, d, cur, d - 1, A[d - 1], p.R[d - 1], b.G(2), s, false));
+  float *S[kMaxDim];
+  for (int k = 0; k < d; ++k) S[k] = b.S(k);
+  return launch_ls_core(b.G(2), d, p.R, S, G, b.clips(), s);
+}
+
 // ||X - G x {A}||^2 and ||X||^2 into b.red() (device), Tucker model.
 static nnc_status tucker_resid(const TuckerBufs &b, const void *X, nnc_dtype dt, const float *G,
                                const float *const *A, hipStream_t s) {
@@ -903,9 +959,12 @@ size_t nntucker_workspace_bytes(int ndim, const int64_t *dims, const int64_t *mu
   return plan_tucker(ndim, dims, multirank).total;
 }
 
-nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *dims,
-                        const int64_t *multirank, int iters, float *core, float *const *factors,
-                        const nnc_options *opt, nnc_report *rep, void *stream) {
+// The driver shared by the nonnegative fit (multiplicative updates) and the real-valued fit
+// (least squares, `ls`): argument checks, sweeps (optionally in graphs), objective history
+// and the final report.
+static nnc_status tucker_fit_impl(bool ls, const void *X, nnc_dtype xdt, int ndim, const int64_t *dims,
+                                  const int64_t *multirank, int iters, float *core, float *const *factors,
+                                  const nnc_options *opt, nnc_report *rep, void *stream) {
   const auto t0 = std::chrono::steady_clock::now();
   NNC_TRY(check_dims(ndim, dims, "dims"));
   NNC_TRY(check_dims(ndim, multirank, "multirank"));
@@ -914,9 +973,11 @@ nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *d
   NNC_TRY(check_ptrs((const void *const *)factors, ndim, "factors"));
   if (xdt != NNC_F32 && xdt != NNC_BF16) return fail(NNC_EINVAL, "unknown dtype %d", (int)xdt);
   if (iters < 0) return fail(NNC_EINVAL, "iters = %d < 0", iters);
+  const int64_t max_rank = ls ? 32 : 256;
   for (int k = 0; k < ndim; ++k)
-    if (multirank[k] > 256)
-      return fail(NNC_EUNSUPPORTED, "multirank[%d] = %lld above 256", k, (long long)multirank[k]);
+    if (multirank[k] > max_rank)
+      return fail(NNC_EUNSUPPORTED, "multirank[%d] = %lld above %lld", k, (long long)multirank[k],
+                  (long long)max_rank);
   nnc_options o;
   memset(&o, 0, sizeof o);
   if (opt) o = *opt;
@@ -939,10 +1000,17 @@ nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *d
   TuckerBufs b{(char *)o.workspace, &p};
   NNC_HIP(hipMemsetAsync(b.clips(), 0, sizeof(unsigned long long), s));
   NNC_HIP(hipMemsetAsync(b.flag(), 0, sizeof(unsigned int), s));
-  if (p.fast)
+  if (ls)  // orthonormal initial factors (A_n = Q R, G <- G x_n R: the same initial model)
+    for (int k = 0; k < ndim; ++k)
+      NNC_TRY(launch_ls_factor(nullptr, nullptr, p.N[k], p.R[k], factors[k], core, prod(p.R, 0, k),
+                               prod(p.R, k + 1, ndim), b.S(k), b.clips(), s));
+  else if (p.fast)
     NNC_TRY(fused_prologue(b, core, factors, eps, s));
   else
     for (int k = 0; k < ndim; ++k) NNC_TRY(launch_gram(factors[k], p.N[k], p.R[k], b.S(k), s));
+  auto sweep = [&](const void *Xs, nnc_dtype dts, hipStream_t st, PassTimer *t) -> nnc_status {
+    return ls ? ls_sweep(b, Xs, dts, core, factors, st, t) : any_sweep(b, Xs, dts, core, factors, eps, st, t);
+  };
 
   PassTimer timer;
   PassTimer *tm = g_timing ? &timer : nullptr;
@@ -960,7 +1028,7 @@ nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *d
     const bool every = o.objective_every > 0;
     if (!graphs) {
       for (int t = ta; t < tb; ++t) {
-        NNC_TRY(any_sweep(b, Xs, dts, core, factors, eps, s, tm));
+        NNC_TRY(sweep(Xs, dts, s, tm));
         if (every && (t + 1) % o.objective_every == 0) {
           NNC_TRY(tucker_resid(b, xres, dres, core, factors, s));
           double red[2];
@@ -986,7 +1054,7 @@ nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *d
       NNC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       nnc_status st = NNC_OK;
       for (int c = 0; c < count && st == NNC_OK; ++c)
-        st = any_sweep(b, Xs, dts, core, factors, eps, cs, nullptr);
+        st = sweep(Xs, dts, cs, nullptr);
       hipError_t ec = hipStreamEndCapture(cs, &g);
       if (st != NNC_OK) {
         if (g) (void)hipGraphDestroy(g);
@@ -1055,16 +1123,35 @@ nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *d
     NNC_HIP(hipStreamSynchronize(s));
     rep->sweeps_done = iters;
     rep->rel_residual = rel_of(red);
-    rep->eps_clips = (long long)clips;
+    rep->eps_clips = ls ? 0 : (long long)clips;
     rep->history_len = hist;
     rep->ttm_pass_ms = 0;
     rep->ttm_pass_launches = (long long)(timer.used / 2);
     if (tm) NNC_TRY(timer.total_ms(&rep->ttm_pass_ms));
     rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (ls && clips)
+      return fail(NNC_ENUMERIC, "%llu least-squares systems were not positive definite (rank-deficient "
+                  "core or factor: lower the multirank)", clips);
     if (flag || !std::isfinite(rep->rel_residual))
       return fail(NNC_ENUMERIC, "non-finite values in the fitted model (NaN or Inf in X?)");
   }
   return NNC_OK;
+}
+
+nnc_status nntucker_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *dims,
+                        const int64_t *multirank, int iters, float *core, float *const *factors,
+                        const nnc_options *opt, nnc_report *rep, void *stream) {
+  return tucker_fit_impl(false, X, xdt, ndim, dims, multirank, iters, core, factors, opt, rep, stream);
+}
+
+size_t tucker_ls_workspace_bytes(int ndim, const int64_t *dims, const int64_t *multirank) {
+  return nntucker_workspace_bytes(ndim, dims, multirank);
+}
+
+nnc_status tucker_ls_fit(const void *X, nnc_dtype xdt, int ndim, const int64_t *dims,
+                         const int64_t *multirank, int iters, float *core, float *const *factors,
+                         const nnc_options *opt, nnc_report *rep, void *stream) {
+  return tucker_fit_impl(true, X, xdt, ndim, dims, multirank, iters, core, factors, opt, rep, stream);
 }
 
 size_t reconstruct_workspace_bytes(int ndim, const int64_t *dims, const int64_t *model_dims,
@@ -1276,17 +1363,19 @@ static nnc_status check_nncp_args(const float *core, int ndim, const int64_t *co
   return nncp_check_shape(cp_problem(ndim, core_dims), rank, 0);
 }
 
-// One nnCP fit with its scratch (layout cp_ws) at `base`; fills `rep` (and syncs) if given.
+// One CP fit of the core with its scratch (layout cp_ws) at `base`: multiplicative updates,
+// or least-squares ones (`als`); fills `rep` (and syncs) if given.
 static nnc_status nncp_fit_at(const float *core, int ndim, const int64_t *core_dims, int rank, int iters,
                               float *const *cp_factors, double eps, nnc_report *rep, char *base,
-                              hipStream_t s) {
+                              hipStream_t s, bool als = false) {
   const auto t0 = std::chrono::steady_clock::now();
   const CpProblem pb = cp_problem(ndim, core_dims);
   const CpWs w = cp_ws(pb, 1, &rank, false);
   unsigned long long *clips = (unsigned long long *)(base + w.oClip);
   NNC_TRY(launch_fill_u64(clips, 1, 0ull, s));
   NNC_TRY(launch_nncp(core, pb, 1, nullptr, rank, nullptr, cp_factors, iters, eps > 0 ? eps : 1e-12,
-                      rep ? (double *)(base + w.oRes) : nullptr, clips, (float *)(base + w.oZ), 0, s));
+                      rep ? (double *)(base + w.oRes) : nullptr, clips, (float *)(base + w.oZ), 0, s,
+                      als));
   if (rep) {
     double res = 0.0;
     unsigned long long nclip = 0;
@@ -1295,12 +1384,14 @@ static nnc_status nncp_fit_at(const float *core, int ndim, const int64_t *core_d
     NNC_HIP(hipStreamSynchronize(s));
     rep->sweeps_done = iters;
     rep->rel_residual = res;
-    rep->eps_clips = (long long)nclip;
+    rep->eps_clips = als ? 0 : (long long)nclip;
     rep->history_len = 0;
     rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     rep->ttm_pass_ms = 0.0;
     rep->ttm_pass_launches = 0;
-    if (!std::isfinite(res)) return fail(NNC_ENUMERIC, "non-finite nnCP residual");
+    if (als && nclip)
+      return fail(NNC_ENUMERIC, "%llu least-squares systems of the CP fit were not positive definite", nclip);
+    if (!std::isfinite(res)) return fail(NNC_ENUMERIC, "non-finite CP residual");
   }
   return NNC_OK;
 }
@@ -1315,6 +1406,24 @@ nnc_status nncp_fit(const float *core, int ndim, const int64_t *core_dims, int r
                 (opt && opt->workspace) ? opt->workspace_bytes : 0, w.total);
   return nncp_fit_at(core, ndim, core_dims, rank, iters, cp_factors, eps, rep, (char *)opt->workspace,
                      (hipStream_t)stream);
+}
+
+size_t cp_ls_workspace_bytes(int ndim, const int64_t *core_dims, int rank) {
+  return nncp_workspace_bytes(ndim, core_dims, rank);
+}
+
+nnc_status cp_ls_fit(const float *core, int ndim, const int64_t *core_dims, int rank, int iters,
+                     float *const *cp_factors, const nnc_options *opt, nnc_report *rep, void *stream) {
+  NNC_TRY(check_cp(core, ndim, core_dims, rank, iters));
+  NNC_TRY(check_ptrs((const void *const *)cp_factors, ndim, "cp_factors"));
+  if (rank > 32) return fail(NNC_EUNSUPPORTED, "rank %d above 32", rank);
+  NNC_TRY(nncp_check_shape(cp_problem(ndim, core_dims), rank, 0, true));
+  const CpWs w = cp_ws(cp_problem(ndim, core_dims), 1, &rank, false);
+  if (!opt || !opt->workspace || opt->workspace_bytes < w.total)
+    return fail(NNC_EWORKSPACE, "workspace has %zu bytes, need %zu",
+                (opt && opt->workspace) ? opt->workspace_bytes : 0, w.total);
+  return nncp_fit_at(core, ndim, core_dims, rank, iters, cp_factors, 0.0, rep, (char *)opt->workspace,
+                     (hipStream_t)stream, true);
 }
 
 size_t nncp_noalloc_max_scratch_bytes(void) { return kStaticScratchBytes; }

@@ -6,6 +6,8 @@
 //
 // Sweep (factors 1..d in order):  M_n = MTTKRP(T, {B_k}_{k!=n}),  H_n = Hadamard_{k!=n} B_k^T B_k,
 //   B_n <- B_n * M_n / max(B_n H_n, eps),  then B_n^T B_n is refreshed.
+// With ALS set (the real-valued CP fit of the core, Section 2.2) the update is the least-squares
+// step B_n <- M_n H_n^{-1} instead, H_n inverted in FP64 by Gauss-Jordan elimination.
 // MTTKRP M_n[i, rho] = sum over entries with i_n = i of T[idx] prod_{k!=n} B_k[i_k, rho] is
 // evaluated in two stages: first the last mode L != n is contracted for every rho at once,
 //   Z[o][rho] = sum_l T[.., l (mode L), ..] B_L[l, rho]        (o = the other indices of T),
@@ -46,8 +48,9 @@ static __device__ inline float mu_cp(float x, float num, float den, double eps, 
 
 // LDS floats of one fit of rank r with `threads` threads:
 //   [T if t_lds] B_k (dims[k] x r) | Gram_k (r x r) | H (r x r)
-//   | part (max(threads, maxdim * r)) | red (2 * threads doubles) | [Z (zmax x r) if z_lds]
-static int64_t cp_lds_floats(const CpArgs &a, int r, int threads, bool t_lds, bool z_lds) {
+//   | part (max(threads, maxdim * r)) | red (2 * threads doubles) | [2 r x r doubles if ALS]
+//   | [Z (zmax x r) if z_lds]
+static int64_t cp_lds_floats(const CpArgs &a, int r, int threads, bool t_lds, bool z_lds, bool als) {
   int64_t s = t_lds ? a.size : 0;
   s = (s + 3) & ~(int64_t)3;  // factor rows are read as float4
   const int RM = r <= 8 ? 8 : (r <= 16 ? 16 : 32);  // factor rows and Z rows are padded to RM
@@ -56,6 +59,7 @@ static int64_t cp_lds_floats(const CpArgs &a, int r, int threads, bool t_lds, bo
   s += std::max<int64_t>(threads, (int64_t)a.maxdim * r);
   s += (s & 1);               // keep the doubles 8-byte aligned
   s += 4 * (int64_t)threads;  // 2 * threads doubles
+  if (als) s += 4 * (int64_t)r * r;  // two r x r double buffers for the inverse of H
   s = (s + 3) & ~(int64_t)3;  // Z rows are written as float4
   if (z_lds) s += (int64_t)a.zmax * RM;
   return s;
@@ -64,7 +68,7 @@ static int64_t cp_lds_floats(const CpArgs &a, int r, int threads, bool t_lds, bo
 // Every per-mode array below is indexed only by loop counters of fully unrolled loops over
 // kMaxDim, so it lives in registers (no scratch memory); factor blocks are addressed by
 // offsets kept in LDS.
-template <int RM>
+template <int RM, bool ALS>
 __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpArgs a, int rank0,
                                                CpPtrs ptr0, const int *__restrict__ ranks,
                                                float *const *__restrict__ fptrs, int iters,
@@ -100,6 +104,8 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
   p += ((p - sm) & 1);
   double *red = reinterpret_cast<double *>(p);
   p += 4 * nt;
+  double *Hd = reinterpret_cast<double *>(p);  // ALS: two r x r buffers
+  if (ALS) p += 4 * r * r;
   p += (4 - ((p - sm) & 3)) & 3;
   float *Z = a.z_lds ? p : zg + (int64_t)b * a.zmax * RM;
   if (tid == 0) {
@@ -278,8 +284,37 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
         }
       }
       __syncthreads();
-      // ---- B_n <- B_n * M / max(B_n H, eps): new values go to `part` first
       float *Bn = sB + boff[n];
+      if (ALS) {
+        // ---- B_n <- M H^{-1}: the S partial sums of each pair (split order) into part[e]
+        // (a thread reads only its own pair's partials, and part[e] is one of them)
+        for (int e = tid; e < npairs; e += nt) {
+          float m = 0.f;
+#pragma unroll 4
+          for (int s = 0; s < S; ++s) m += part[s * npairs + e];
+          part[e] = m;
+        }
+        for (int e = tid; e < r * r; e += nt) Hd[e] = (double)H[e];
+        __syncthreads();
+        const double *Hinv = gj_inverse(Hd, Hd + r * r, r, &nclip);
+        for (int e = tid; e < npairs; e += nt) {
+          const int i = qdiv(e, inv_r), c = e - i * r;
+          double v = 0.0;
+          for (int s2 = 0; s2 < r; ++s2) v += (double)part[i * r + s2] * Hinv[s2 * r + c];
+          Bn[i * RM + c] = (float)v;
+        }
+        __syncthreads();
+        for (int e = tid; e < r * r; e += nt) {
+          const int x = qdiv(e, inv_r), y = e - x * r;
+          float acc = 0.f;
+#pragma unroll 4
+          for (int i = 0; i < In; ++i) acc = fmaf(Bn[i * RM + x], Bn[i * RM + y], acc);
+          sW[n * r * r + e] = acc;
+        }
+        __syncthreads();
+        continue;
+      }
+      // ---- B_n <- B_n * M / max(B_n H, eps): new values go to `part` first
       for (int e = tid; e < npairs; e += nt) {
         const int i = qdiv(e, inv_r), c = e - i * r;
         float m = 0.f;  // the S partial sums of pair e, in split order
@@ -378,12 +413,12 @@ struct CpLayout {
 };
 
 // Keep T in LDS when possible (it is read every stage), then Z.
-static CpLayout cp_layout(const CpProblem &pb, int max_rank, int threads) {
+static CpLayout cp_layout(const CpProblem &pb, int max_rank, int threads, bool als) {
   CpLayout L;
   L.a = make_args(pb);
   const bool opts[4][2] = {{true, true}, {true, false}, {false, true}, {false, false}};
   for (const auto &o : opts) {
-    const int64_t bytes = cp_lds_floats(L.a, max_rank, threads, o[0], o[1]) * 4;
+    const int64_t bytes = cp_lds_floats(L.a, max_rank, threads, o[0], o[1], als) * 4;
     if (bytes <= kCpLdsBudget || (!o[0] && !o[1])) {
       L.a.t_lds = o[0];
       L.a.z_lds = o[1];
@@ -394,8 +429,8 @@ static CpLayout cp_layout(const CpProblem &pb, int max_rank, int threads) {
   return L;
 }
 
-int64_t nncp_lds_bytes(const CpProblem &pb, int max_rank, int threads) {
-  return cp_layout(pb, max_rank, threads).lds_bytes;
+int64_t nncp_lds_bytes(const CpProblem &pb, int max_rank, int threads, bool als) {
+  return cp_layout(pb, max_rank, threads, als).lds_bytes;
 }
 
 int64_t nncp_zscratch_floats(const CpProblem &pb, int max_rank) {
@@ -428,7 +463,7 @@ static nnc_status allow_lds(const void *kern, int64_t bytes) {
 // ceil(r/4) * size / dims[L] items (L = the contracted mode of that update), stage 2 and the
 // update run dims[n] * r pairs (times a split factor only while that stays below the thread
 // count).  Shapes whose index ranges reach 2^22 are refused here, before any HIP call.
-nnc_status nncp_check_shape(const CpProblem &pb, int max_rank, int threads) {
+nnc_status nncp_check_shape(const CpProblem &pb, int max_rank, int threads, bool als) {
   if (pb.d < 2 || pb.size < 1) return fail(NNC_EINVAL, "nnCP needs a tensor of 2 or more modes");
   if (pb.size > (1 << 26)) return fail(NNC_EUNSUPPORTED, "nnCP tensor too large for one workgroup");
   if (max_rank < 1) return fail(NNC_EINVAL, "nnCP rank %d < 1", max_rank);
@@ -449,7 +484,7 @@ nnc_status nncp_check_shape(const CpProblem &pb, int max_rank, int threads) {
   if (threads <= 0) threads = nncp_default_threads(pb, max_rank);
   if (threads > 1024 || threads % 64)
     return fail(NNC_EINVAL, "threads_per_fit must be a multiple of 64 <= 1024");
-  const CpLayout L = cp_layout(pb, max_rank, threads);
+  const CpLayout L = cp_layout(pb, max_rank, threads, als);
   if (L.lds_bytes > kCpLdsBudget)
     return fail(NNC_EUNSUPPORTED, "nnCP working set %lld bytes exceeds the LDS budget",
                 (long long)L.lds_bytes);
@@ -459,26 +494,35 @@ nnc_status nncp_check_shape(const CpProblem &pb, int max_rank, int threads) {
 nnc_status launch_nncp(const float *T, const CpProblem &pb, int nbatch, const int *d_ranks,
                        int max_rank, float *const *d_factor_ptrs, float *const *single_ptrs,
                        int iters, double eps, double *d_resid, unsigned long long *clips,
-                       float *zscratch, int threads, hipStream_t s) {
-  NNC_TRY(nncp_check_shape(pb, max_rank, threads));
+                       float *zscratch, int threads, hipStream_t s, bool als) {
+  NNC_TRY(nncp_check_shape(pb, max_rank, threads, als));
   if (threads <= 0) threads = nncp_default_threads(pb, max_rank);
-  const CpLayout L = cp_layout(pb, max_rank, threads);
+  const CpLayout L = cp_layout(pb, max_rank, threads, als);
   if (!L.a.z_lds && !zscratch) return fail(NNC_EWORKSPACE, "nnCP needs Z scratch in the workspace");
   CpPtrs p0;
   for (int k = 0; k < kMaxDim; ++k) p0.p[k] = (single_ptrs && k < pb.d) ? single_ptrs[k] : nullptr;
   const size_t lds = (size_t)L.lds_bytes;
-#define NNC_CP_LAUNCH(RM)                                                                      \
-  do {                                                                                         \
-    NNC_TRY(allow_lds(reinterpret_cast<const void *>(nncp_k<RM>), L.lds_bytes));                            \
-    hipLaunchKernelGGL(nncp_k<RM>, dim3(nbatch), dim3(threads), lds, s, T, L.a, max_rank, p0,  \
-                       d_ranks, d_factor_ptrs, iters, eps, d_resid, clips, zscratch);          \
+#define NNC_CP_LAUNCH(RM, ALSV)                                                                   \
+  do {                                                                                            \
+    NNC_TRY(allow_lds(reinterpret_cast<const void *>(nncp_k<RM, ALSV>), L.lds_bytes));            \
+    hipLaunchKernelGGL((nncp_k<RM, ALSV>), dim3(nbatch), dim3(threads), lds, s, T, L.a, max_rank, \
+                       p0, d_ranks, d_factor_ptrs, iters, eps, d_resid, clips, zscratch);         \
   } while (0)
-  if (max_rank <= 8)
-    NNC_CP_LAUNCH(8);
-  else if (max_rank <= 16)
-    NNC_CP_LAUNCH(16);
-  else
-    NNC_CP_LAUNCH(32);
+  if (als) {
+    if (max_rank <= 8)
+      NNC_CP_LAUNCH(8, true);
+    else if (max_rank <= 16)
+      NNC_CP_LAUNCH(16, true);
+    else
+      NNC_CP_LAUNCH(32, true);
+  } else {
+    if (max_rank <= 8)
+      NNC_CP_LAUNCH(8, false);
+    else if (max_rank <= 16)
+      NNC_CP_LAUNCH(16, false);
+    else
+      NNC_CP_LAUNCH(32, false);
+  }
 #undef NNC_CP_LAUNCH
   NNC_HIP(hipGetLastError());
   return NNC_OK;

@@ -17,6 +17,37 @@ constexpr int kMaxDim = 8;
 // it by less than (a + 0.5) / b * 2^-23, which is smaller for such a.
 static __device__ inline int qdiv(int a, float inv_b) { return (int)(((float)a + 0.5f) * inv_b); }
 
+// Inverse of the r x r matrix in a (double, LDS) by Gauss-Jordan elimination without
+// pivoting, ping-ponging between a and b with one barrier per pivot (every thread of the
+// block takes part); returns the buffer that holds the inverse.  The pivots are those of the
+// matrix's LDL^T factorization: all positive exactly when a symmetric matrix is positive
+// definite (and, for a triangular matrix, its diagonal).  Thread 0 counts the pivots that are
+// not positive in *bad.
+static __device__ inline double *gj_inverse(double *a, double *b, int r, unsigned int *bad) {
+  double *src = a, *dst = b;
+  for (int k = 0; k < r; ++k) {
+    const double p = src[k * r + k];
+    const double ip = 1.0 / p;
+    for (int t = threadIdx.x; t < r * r; t += blockDim.x) {
+      const int i = t / r, j = t - (t / r) * r;
+      double v;
+      if (i == k)
+        v = (j == k) ? ip : src[k * r + j] * ip;
+      else if (j == k)
+        v = -src[i * r + k] * ip;
+      else
+        v = src[t] - src[i * r + k] * src[k * r + j] * ip;
+      dst[t] = v;
+    }
+    if (threadIdx.x == 0 && !(p > 0.0)) atomicAdd(bad, 1u);
+    __syncthreads();
+    double *x = src;
+    src = dst;
+    dst = x;
+  }
+  return src;
+}
+
 // Sets the thread-local error message and returns `st`.
 nnc_status fail(nnc_status st, const char *fmt, ...);
 
@@ -104,6 +135,18 @@ nnc_status launch_check_finite(const float *x, int64_t n, unsigned int *flag, hi
 nnc_status launch_fill_u64(unsigned long long *x, int64_t n, unsigned long long v, hipStream_t s);
 nnc_status launch_fill_f32(float *x, int64_t n, float v, hipStream_t s);
 
+// ------------------------------------------------------------------ ls_kernels.hip
+// Least-squares factor step of the real Tucker fit in one workgroup: A* = num K^{-1},
+// Cholesky QR A* = Q L^T, A <- Q, G <- G x_n L^T (G viewed as gpre x R x gpost), S_out = Q^T Q.
+// Pivots of K or of A*^T A* that are not positive are counted in *fails.  R <= 32.
+// num == nullptr (K unused): A* = A, the orthonormalization of the given factor alone.
+nnc_status launch_ls_factor(const float *num, const float *K, int64_t N, int64_t R, float *A, float *G,
+                            int64_t gpre, int64_t gpost, float *S_out, unsigned long long *fails,
+                            hipStream_t s);
+// Least-squares core step: G = numG x_1 S_1^{-1} ... x_d S_d^{-1} (every R[k] <= 32).
+nnc_status launch_ls_core(const float *numG, int d, const int64_t *R, float *const *S, float *G,
+                          unsigned long long *fails, hipStream_t s);
+
 // ------------------------------------------------------------------ fused3_kernels.hip
 // Side job of the fused three-way passes: blocks [0, nrows) each compute row blockIdx.x of
 // M_n = unfold_n(G x_{k!=n} S_k) unfold_n(G)^T for the core G (R[0] x R[1] x R[2]).  S[k] are
@@ -142,13 +185,15 @@ struct CpProblem {
 // nbatch == 1, rank max_rank and host array single_ptrs (passed by value).
 // d_resid (nullable) receives each fit's relative residual.  zscratch: nbatch *
 // nncp_zscratch_floats() floats, used when the contraction temporaries do not fit in LDS.
+// als: least-squares updates B_n <- M_n H_n^{-1} (real CP) instead of the multiplicative
+// ones; `clips` then counts pivots of H_n that were not positive.
 nnc_status launch_nncp(const float *T, const CpProblem &pb, int nbatch, const int *d_ranks,
                        int max_rank, float *const *d_factor_ptrs, float *const *single_ptrs,
                        int iters, double eps, double *d_resid, unsigned long long *clips,
-                       float *zscratch, int threads, hipStream_t s);
+                       float *zscratch, int threads, hipStream_t s, bool als = false);
 // Host-side check of a shape for launch_nncp (index ranges, rank, LDS); records the error.
-nnc_status nncp_check_shape(const CpProblem &pb, int max_rank, int threads);
-int64_t nncp_lds_bytes(const CpProblem &pb, int max_rank, int threads);
+nnc_status nncp_check_shape(const CpProblem &pb, int max_rank, int threads, bool als = false);
+int64_t nncp_lds_bytes(const CpProblem &pb, int max_rank, int threads, bool als = false);
 int64_t nncp_zscratch_floats(const CpProblem &pb, int max_rank);
 int nncp_default_threads(const CpProblem &pb, int max_rank);
 

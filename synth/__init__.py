@@ -271,3 +271,43 @@ def planted_tensor(seed: int, dims, R: int, zero_prob: float = 0.0, noise: float
         else:
             X[flat0:flat1] = to_bf16_bits(round_bf16(blk.ravel()))
     return X.reshape(dims), facs
+
+
+STREAM_SIGNED = 1 << 28
+
+
+def signed_planted(seed: int, dims, R: int, noise: float = 1e-2, deficient_mode: int = -1):
+    """Real-valued planted CP tensor for the unconstrained (real) CANDELINC path:
+    X = sum_rho outer(a_1[:,rho], ..., a_d[:,rho]) + E with factor entries 2u - 1 and
+    E = noise * (2u - 1).  With deficient_mode = k the last column of a_k is the mean of its
+    other columns, so the CPD factor of mode k has rank R - 1 (the rank-deficient factor
+    that Section 2.2 discusses).  Returns (X float64, planted factors)."""
+    dims = [int(n) for n in dims]
+    facs = [2.0 * uniform_matrix(seed, STREAM_SIGNED + n, N, R) - 1.0 for n, N in enumerate(dims)]
+    if deficient_mode >= 0:
+        a = facs[deficient_mode]
+        a[:, R - 1] = a[:, :R - 1].mean(axis=1)
+    X = np.zeros(dims)
+    for rho in range(R):
+        t = facs[0][:, rho]
+        for a in facs[1:]:
+            t = np.multiply.outer(t, a[:, rho])
+        X += t
+    if noise > 0.0:
+        X += noise * (2.0 * uniform(seed, STREAM_SIGNED + 16, int(np.prod(dims))).reshape(dims) - 1.0)
+    return X, facs
+
+
+def signed_planted_tucker(seed: int, dims, ranks, noise: float = 1e-2):
+    """Real-valued planted Tucker tensor X = G x_1 A_1 ... x_d A_d + E with core and factor
+    entries 2u - 1 and E = noise * (2u - 1): multilinear rank `ranks` up to the noise.
+    Returns X as float64."""
+    dims = [int(n) for n in dims]
+    ranks = [int(r) for r in ranks]
+    X = 2.0 * uniform(seed, STREAM_SIGNED + 32, int(np.prod(ranks))).reshape(ranks) - 1.0
+    for n, (N, R) in enumerate(zip(dims, ranks)):
+        A = 2.0 * uniform_matrix(seed, STREAM_SIGNED + 40 + n, N, R) - 1.0
+        X = np.moveaxis(np.tensordot(A, X, axes=([1], [n])), 0, n)
+    if noise > 0.0:
+        X = X + noise * (2.0 * uniform(seed, STREAM_SIGNED + 17, int(np.prod(dims))).reshape(dims) - 1.0)
+    return np.ascontiguousarray(X)

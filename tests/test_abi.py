@@ -252,3 +252,25 @@ def test_fill_uniform_validation():
     assert L.nnc_fill_uniform(1, 2, None, 0, None) == nnc.NNC_OK
     assert L.nnc_fill_uniform_f64(1, 2, -1, FAKE, 4, None) == nnc.NNC_EINVAL
     assert L.nnc_fill_uniform_f64(1, 2, 0, None, 4, None) == nnc.NNC_EINVAL
+
+
+def test_real_valued_fits_validate():
+    """The least-squares fits share the nonnegative fits' checks, with ranks capped at 32."""
+    L = nnc.lib()
+    opt = nnc.Options()
+    opt.workspace = 0x1000
+    opt.workspace_bytes = 1 << 40
+    f = L.tucker_ls_fit
+    assert L.tucker_ls_workspace_bytes(3, D(64, 48, 40), D(5, 6, 7)) == L.nntucker_workspace_bytes(
+        3, D(64, 48, 40), D(5, 6, 7)) > 0
+    assert f(FAKE, 0, 3, D(4, 4, 4), D(2, 2, 2), 1, FAKE, _ptrs(3, 2), ctypes.byref(opt), None, None) == nnc.NNC_EINVAL
+    assert f(FAKE, 0, 3, D(40, 40, 40), D(33, 2, 2), 1, FAKE, _ptrs(3), ctypes.byref(opt), None, None) == nnc.NNC_EUNSUPPORTED
+    assert "above 32" in nnc.last_error()
+    assert f(FAKE, 0, 3, D(4, 4, 4), D(2, 2, 2), -1, FAKE, _ptrs(3), ctypes.byref(opt), None, None) == nnc.NNC_EINVAL
+    assert f(FAKE, 0, 3, D(4, 4, 4), D(2, 2, 2), 1, FAKE, _ptrs(3), None, None, None) == nnc.NNC_EWORKSPACE
+    g = L.cp_ls_fit
+    assert L.cp_ls_workspace_bytes(3, D(5, 5, 5), 3) == L.nncp_workspace_bytes(3, D(5, 5, 5), 3) > 0
+    assert g(FAKE, 3, D(5, 5, 5), 0, 10, _ptrs(3), ctypes.byref(opt), None, None) == nnc.NNC_EINVAL
+    assert g(FAKE, 3, D(5, 5, 5), 33, 10, _ptrs(3), ctypes.byref(opt), None, None) == nnc.NNC_EUNSUPPORTED
+    assert g(FAKE, 3, D(5, 5, 5), 3, 10, _ptrs(3, 0), ctypes.byref(opt), None, None) == nnc.NNC_EINVAL
+    assert g(FAKE, 3, D(5, 5, 5), 3, 10, _ptrs(3), None, None, None) == nnc.NNC_EWORKSPACE

@@ -162,6 +162,11 @@ def test_orthonormalization_leaves_the_model_sequence_unchanged():
         G = oracle.tucker_ls_core(X, A)
     Go, Ao, _ = oracle.tucker_ls(X, G0, A0, 3)
     np.testing.assert_allclose(oracle.tucker_full(Go, Ao), oracle.tucker_full(G, A), rtol=0, atol=1e-11)
+    # zero sweeps: the orthonormalized initial factors carry the initial model
+    Gz, Az, _ = oracle.tucker_ls(X, G0, A0, 0)
+    np.testing.assert_allclose(oracle.tucker_full(Gz, Az), oracle.tucker_full(G0, A0), rtol=0, atol=1e-12)
+    for a in Az:
+        np.testing.assert_allclose(a.T @ a, np.eye(a.shape[1]), rtol=0, atol=1e-14)
 
 
 # --------------------------------------------------------------------------- special cases
