@@ -73,3 +73,33 @@ def planted_tensor_dev(seed, dims, R, zero_prob=0.0, noise=1e-3, chunk_rows=1 <<
         X[r0 * last:r1 * last] = blk.reshape(-1).to(torch.float32)
         del kr, blk
     return X.view(dims)
+
+
+def signed_planted_dev(seed, dims, R, noise=1e-3, chunk_rows=1 << 18):
+    """FP32 device copy of synth.signed_planted(seed, dims, R, noise) rounded to float32, built
+    on the GPU from the same planted factors and the same counter-based noise draws; each
+    chunk of leading rows is formed in float64 and rounded once.  The sum over components
+    runs in a different order than the host's, so a rare entry may differ in its last bit."""
+    import paper_1909_07570_amd as nnc
+    dims = [int(n) for n in dims]
+    d = len(dims)
+    facs = [torch.from_numpy(2.0 * synth.uniform_matrix(seed, synth.STREAM_SIGNED + n, N, R) - 1.0).to("cuda")
+            for n, N in enumerate(dims)]
+    last = dims[-1]
+    lead = int(np.prod(dims[:-1]))
+    X = torch.empty(lead * last, dtype=torch.float32, device="cuda")
+    for r0 in range(0, lead, chunk_rows):
+        r1 = min(lead, r0 + chunk_rows)
+        rem = torch.arange(r0, r1, dtype=torch.int64, device="cuda")
+        kr = torch.ones((r1 - r0, R), dtype=torch.float64, device="cuda")
+        for k in range(d - 2, -1, -1):
+            ik = rem % dims[k]
+            rem = rem // dims[k]
+            kr *= facs[k][ik, :]
+        blk = kr @ facs[-1].T.contiguous()
+        if noise > 0.0:
+            u = nnc.nnc_fill_uniform_f64(seed, synth.STREAM_SIGNED + 16, (r1 - r0) * last, offset=r0 * last)
+            blk += noise * (2.0 * u.view(blk.shape) - 1.0)
+        X[r0 * last:r1 * last] = blk.reshape(-1).to(torch.float32)
+        del kr, blk
+    return X.view(dims)
