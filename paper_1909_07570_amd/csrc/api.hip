@@ -112,7 +112,7 @@ struct TuckerPlan {
   int64_t nP = 0, nT = 0, nU = 0, nC = 0, nY = 0, nNum = 0, nS = 0, nM = 0, nGp = 0, nGr = 0;
   bool fast = false;  // every multirank <= 32: fused small-step kernels
   size_t oP, oT, oU0, oU1, oC0, oC1, oY, oNum, oDen, oS, oM, oG0, oG1, oG2, oG3, oGp, oGr, oClip,
-      oFlag, oRed, oPart, total;
+      oFlag, oRed, oPart, oLsT, oLsL, oLsS, total;
 };
 
 static void grow(int64_t &v, int64_t x) {
@@ -186,6 +186,9 @@ static TuckerPlan plan_tucker(int d, const int64_t *dims, const int64_t *rk) {
   p.oFlag = L.take(sizeof(unsigned int));
   p.oRed = L.take(2 * sizeof(double));
   p.oPart = L.take(2 * sizeof(double) * resid_stream_max_blocks());
+  p.oLsT = L.take(sizeof(double) * 32 * 32);         // the real-valued fit's R x R transform,
+  p.oLsL = L.take(sizeof(float) * 32 * 32);          // its Cholesky factor
+  p.oLsS = L.take(sizeof(float) * kMaxDim * 32 * 32);  // and the inverse Grams
   p.total = L.off;
   return p;
 }
@@ -217,6 +220,9 @@ struct TuckerBufs {
   unsigned int *flag() const { return reinterpret_cast<unsigned int *>(base + p->oFlag); }
   double *red() const { return reinterpret_cast<double *>(base + p->oRed); }
   double *part() const { return reinterpret_cast<double *>(base + p->oPart); }
+  double *lsT() const { return reinterpret_cast<double *>(base + p->oLsT); }
+  float *lsL() const { return f(p->oLsL); }
+  float *lsSinv(int k) const { return f(p->oLsS + sizeof(float) * 32 * 32 * k); }
 };
 
 // ------------------------------------------------------------------ TTM helpers
@@ -635,16 +641,40 @@ static nnc_status any_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, fl
 // One sweep of the real-valued Tucker fit (alternating least squares with orthonormalized
 // factors, Section 2.2): the X passes and small contractions of the general sweep above, with
 // the least-squares updates of ls_kernels.hip in place of the multiplicative ones.
-static nnc_status ls_factor(const TuckerBufs &b, int n, const float *Y, float *G, float *A, hipStream_t s) {
+// G <- G x_n L^T for the Cholesky factor L of the last factor step: the small contraction
+// with "factor" L (out[.., i, ..] = sum_l L[l][i] G[.., l, ..]) into G(3), copied back.
+static nnc_status ls_core_rotate(const TuckerBufs &b, int n, float *G, hipStream_t s) {
+  const TuckerPlan &p = *b.p;
+  NNC_TRY(launch_ttm_small(G, prod(p.R, 0, n), p.R[n], prod(p.R, n + 1, p.d), b.lsL(), p.R[n], 1, p.R[n],
+                           b.G(3), s));
+  NNC_HIP(hipMemcpyAsync(G, b.G(3), sizeof(float) * p.gsize, hipMemcpyDeviceToDevice, s));
+  return NNC_OK;
+}
+
+// Orthonormalization of a given factor (Q of its positive-diagonal QR replaces it, R goes
+// into the core): the factor is copied to num first, since the row kernel writes A apart
+// from its input.
+static nnc_status ls_orthonormalize(const TuckerBufs &b, int n, float *G, float *A, hipStream_t s) {
+  const TuckerPlan &p = *b.p;
+  NNC_HIP(hipMemcpyAsync(b.num(), A, sizeof(float) * p.N[n] * p.R[n], hipMemcpyDeviceToDevice, s));
+  NNC_TRY(launch_ls_factor(b.num(), nullptr, p.N[n], p.R[n], A, b.lsT(), b.lsL(), b.S(n), b.clips(), s));
+  return ls_core_rotate(b, n, G, s);
+}
+
+static nnc_status ls_factor(const TuckerBufs &b, int n, const float *Y, float *G, float *const *A,
+                            hipStream_t s) {
   const TuckerPlan &p = *b.p;
   const int64_t pre = prod(p.R, 0, n), post = prod(p.R, n + 1, p.d);
   NNC_TRY(launch_contract_except(Y, G, pre, p.N[n], p.R[n], post, b.num(), s));  // num_n
-  const float *H = nullptr;
-  NNC_TRY(core_chain(b, G, n, nullptr, &H, s));
-  NNC_TRY(launch_contract_except(H, G, pre, p.R[n], p.R[n], post, b.M(), s));  // K_n
-  return launch_ls_factor(b.num(), b.M(), p.N[n], p.R[n], A, G, pre, post, b.S(n), b.clips(), s);
+  CoreArgsHost h = core_args(b, G, A, 0.0);  // K_n (the M_n of the multiplicative sweep)
+  h.gram_from = h.gram_to = 0;
+  h.next = n;
+  NNC_TRY(launch_core_step(h, s));
+  NNC_TRY(launch_ls_factor(b.num(), b.M(), p.N[n], p.R[n], A[n], b.lsT(), b.lsL(), b.S(n), b.clips(), s));
+  return ls_core_rotate(b, n, G, s);
 }
 
+// Every multirank <= 32 here, so the small contractions are those of the fused sweep.
 static nnc_status ls_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, float *G, float *const *A,
                            hipStream_t s, PassTimer *tm) {
   const TuckerPlan &p = *b.p;
@@ -662,11 +692,11 @@ static nnc_status ls_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, flo
     const float *Y = nullptr;
     int64_t ycur[kMaxDim];
     memcpy(ycur, cur, sizeof ycur);
-    NNC_TRY(chain(U, d, ycur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
-    NNC_TRY(ls_factor(b, n, Y, G, A[n], s));
+    NNC_TRY(chain_small(U, d, ycur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
+    NNC_TRY(ls_factor(b, n, Y, G, A, s));
     if (n < d - 2) {
       float *Un = b.U(n % 2);
-      NNC_TRY(ttm_mode(U, NNC_F32, d, cur, n, A[n], p.R[n], Un, s));
+      NNC_TRY(ttm_f32(U, d, cur, n, A[n], p.R[n], Un, s));
       U = Un;
     }
   }
@@ -678,13 +708,25 @@ static nnc_status ls_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, flo
   int modes[kMaxDim], nm = 0;
   for (int k = 1; k < d - 1; ++k) modes[nm++] = k;
   const float *Y = nullptr;
-  NNC_TRY(chain(b.T(), d, cur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
-  NNC_TRY(ls_factor(b, d - 1, Y, G, A[d - 1], s));
-  // core: numerator X x_k A_k^T (every factor new), then the solves with the Grams
-  NNC_TRY(ttm_mode(Y, NNC_F32, d, cur, d - 1, A[d - 1], p.R[d - 1], b.G(2), s, false));
-  float *S[kMaxDim];
-  for (int k = 0; k < d; ++k) S[k] = b.S(k);
-  return launch_ls_core(b.G(2), d, p.R, S, G, b.clips(), s);
+  NNC_TRY(chain_small(b.T(), d, cur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
+  NNC_TRY(ls_factor(b, d - 1, Y, G, A, s));
+  // core: numerator X x_k A_k^T (every factor new), then G = numerator x_k S_k^{-1}
+  NNC_TRY(ttm_f32(Y, d, cur, d - 1, A[d - 1], p.R[d - 1], b.G(2), s));
+  float *S[kMaxDim], *Sinv[kMaxDim];
+  for (int k = 0; k < d; ++k) {
+    S[k] = b.S(k);
+    Sinv[k] = b.lsSinv(k);
+  }
+  NNC_TRY(launch_ls_inverses(d, p.R, S, Sinv, b.clips(), s));
+  int64_t gc[kMaxDim];
+  for (int k = 0; k < d; ++k) gc[k] = p.R[k];
+  const float *src = b.G(2);
+  for (int k = 0; k < d; ++k) {  // S_k^{-1} is symmetric: the contraction with it as "factor"
+    float *dst = (k == d - 1) ? G : b.G(k % 2);
+    NNC_TRY(ttm_f32(src, d, gc, k, Sinv[k], p.R[k], dst, s));
+    src = dst;
+  }
+  return NNC_OK;
 }
 
 // ||X - G x {A}||^2 and ||X||^2 into b.red() (device), Tucker model.
@@ -1002,8 +1044,7 @@ static nnc_status tucker_fit_impl(bool ls, const void *X, nnc_dtype xdt, int ndi
   NNC_HIP(hipMemsetAsync(b.flag(), 0, sizeof(unsigned int), s));
   if (ls)  // orthonormal initial factors (A_n = Q R, G <- G x_n R: the same initial model)
     for (int k = 0; k < ndim; ++k)
-      NNC_TRY(launch_ls_factor(nullptr, nullptr, p.N[k], p.R[k], factors[k], core, prod(p.R, 0, k),
-                               prod(p.R, k + 1, ndim), b.S(k), b.clips(), s));
+      NNC_TRY(ls_orthonormalize(b, k, core, factors[k], s));
   else if (p.fast)
     NNC_TRY(fused_prologue(b, core, factors, eps, s));
   else

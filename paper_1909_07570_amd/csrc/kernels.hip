@@ -504,8 +504,88 @@ __global__ void contract_except_k(const float *__restrict__ U, const float *__re
   out[idx] = acc;
 }
 
+// The same contraction for J <= JM (<= 32): one wave per output row i, its lanes striding
+// over the flattened summation index t = p * post + q (lane l takes t = l, l + 64, ...) with
+// JM partial sums each, then a butterfly over the wave.  V (pre x J x post) is staged in LDS
+// when it fits (vlds); U's loads are issued four steps ahead of their products.  Every sum
+// runs in a fixed order.
+constexpr int kCeVlds = 8192;  // floats of V staged in LDS (32 KB)
+
+template <int JM>
+__global__ __launch_bounds__(256) void contract_except_rows_k(const float *__restrict__ U,
+                                                              const float *__restrict__ V, int pre,
+                                                              int64_t I, int J, int post, int vlds,
+                                                              float *__restrict__ out) {
+  __shared__ float Vs[kCeVlds];
+  const int nv = pre * J * post;
+  if (vlds) {
+    for (int e = threadIdx.x; e < nv; e += blockDim.x) Vs[e] = V[e];
+    __syncthreads();
+  }
+  const float *Vb = vlds ? Vs : V;
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= I) return;
+  float acc[JM];
+#pragma unroll
+  for (int j = 0; j < JM; ++j) acc[j] = 0.f;
+  // (p, q) of t = lane, advanced by 64 per step without divisions
+  const int dp = 64 / post, dq = 64 - (64 / post) * post;
+  int p = lane / post, q = lane - (lane / post) * post;
+  while (p < pre) {
+    float u[4];
+    int vo[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const bool ok = p < pre;
+      u[k] = ok ? U[((int64_t)p * I + i) * post + q] : 0.f;
+      vo[k] = ok ? (p * J) * post + q : 0;
+      p += dp;
+      q += dq;
+      if (q >= post) {
+        q -= post;
+        ++p;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+      for (int j = 0; j < JM; ++j)
+        if (j < J) acc[j] = fmaf(u[k], Vb[vo[k] + j * post], acc[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < JM; ++j) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) acc[j] += __shfl_xor(acc[j], m, 64);
+  }
+  if (lane < J) {
+    float v = 0.f;
+#pragma unroll
+    for (int j = 0; j < JM; ++j)
+      if (j == lane) v = acc[j];
+    out[i * J + lane] = v;
+  }
+}
+
 nnc_status launch_contract_except(const float *U, const float *V, int64_t pre, int64_t I, int64_t J,
                                   int64_t post, float *out, hipStream_t s) {
+  if (J <= 32 && pre * J * post < INT32_MAX && I < ((int64_t)1 << 31) / 64) {
+    const int grid = (int)((I + 3) / 4);
+    const int vlds = pre * J * post <= kCeVlds ? 1 : 0;
+#define NNC_CE_ROWS(JM)                                                                              \
+  hipLaunchKernelGGL(contract_except_rows_k<JM>, dim3(grid), dim3(256), 0, s, U, V, (int)pre, I, (int)J, \
+                     (int)post, vlds, out)
+    if (J <= 8)
+      NNC_CE_ROWS(8);
+    else if (J <= 16)
+      NNC_CE_ROWS(16);
+    else
+      NNC_CE_ROWS(32);
+#undef NNC_CE_ROWS
+    NNC_HIP(hipGetLastError());
+    return NNC_OK;
+  }
   const int64_t n = I * J;
   hipLaunchKernelGGL(contract_except_k, dim3(grid_for(n, 128, 1 << 30)), dim3(128), 0, s, U, V, pre,
                      I, J, post, out);

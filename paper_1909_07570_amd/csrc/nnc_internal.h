@@ -25,19 +25,29 @@ static __device__ inline int qdiv(int a, float inv_b) { return (int)(((float)a +
 // not positive in *bad.
 static __device__ inline double *gj_inverse(double *a, double *b, int r, unsigned int *bad) {
   double *src = a, *dst = b;
+  const int rr = r * r;
   for (int k = 0; k < r; ++k) {
     const double p = src[k * r + k];
     const double ip = 1.0 / p;
-    for (int t = threadIdx.x; t < r * r; t += blockDim.x) {
-      const int i = t / r, j = t - (t / r) * r;
-      double v;
-      if (i == k)
-        v = (j == k) ? ip : src[k * r + j] * ip;
-      else if (j == k)
-        v = -src[i * r + k] * ip;
+    for (int e0 = threadIdx.x; e0 < rr; e0 += 2 * blockDim.x) {
+      // two entries per step, their LDS reads issued before any product
+      const int e1 = e0 + blockDim.x;
+      const bool has1 = e1 < rr;
+      const int i0 = e0 / r, j0 = e0 - i0 * r;
+      const int i1 = has1 ? e1 / r : i0, j1 = has1 ? e1 - i1 * r : j0;
+      const double a0 = src[e0], rk0 = src[k * r + j0], ck0 = src[i0 * r + k];
+      const double a1 = src[has1 ? e1 : e0], rk1 = src[k * r + j1], ck1 = src[i1 * r + k];
+      double v0, v1;
+      if (i0 == k)
+        v0 = (j0 == k) ? ip : rk0 * ip;
       else
-        v = src[t] - src[i * r + k] * src[k * r + j] * ip;
-      dst[t] = v;
+        v0 = (j0 == k) ? -ck0 * ip : a0 - ck0 * rk0 * ip;
+      if (i1 == k)
+        v1 = (j1 == k) ? ip : rk1 * ip;
+      else
+        v1 = (j1 == k) ? -ck1 * ip : a1 - ck1 * rk1 * ip;
+      dst[e0] = v0;
+      if (has1) dst[e1] = v1;
     }
     if (threadIdx.x == 0 && !(p > 0.0)) atomicAdd(bad, 1u);
     __syncthreads();
@@ -136,16 +146,16 @@ nnc_status launch_fill_u64(unsigned long long *x, int64_t n, unsigned long long 
 nnc_status launch_fill_f32(float *x, int64_t n, float v, hipStream_t s);
 
 // ------------------------------------------------------------------ ls_kernels.hip
-// Least-squares factor step of the real Tucker fit in one workgroup: A* = num K^{-1},
-// Cholesky QR A* = Q L^T, A <- Q, G <- G x_n L^T (G viewed as gpre x R x gpost), S_out = Q^T Q.
-// Pivots of K or of A*^T A* that are not positive are counted in *fails.  R <= 32.
-// num == nullptr (K unused): A* = A, the orthonormalization of the given factor alone.
-nnc_status launch_ls_factor(const float *num, const float *K, int64_t N, int64_t R, float *A, float *G,
-                            int64_t gpre, int64_t gpost, float *S_out, unsigned long long *fails,
-                            hipStream_t s);
-// Least-squares core step: G = numG x_1 S_1^{-1} ... x_d S_d^{-1} (every R[k] <= 32).
-nnc_status launch_ls_core(const float *numG, int d, const int64_t *R, float *const *S, float *G,
-                          unsigned long long *fails, hipStream_t s);
+// Least-squares factor step of the real Tucker fit (two launches): A* = num K^{-1}, Cholesky
+// QR A* = Q L^T, A <- Q (num and A distinct), T <- K^{-1} L^{-T} (R x R doubles),
+// Lf <- L (R x R floats, for the core's G x_n L^T), S_out <- Q^T Q.  Pivots of K or of
+// A*^T A* that are not positive are counted in *fails.  R <= 32.  K == nullptr: A* = num,
+// the orthonormalization of a given factor alone.
+nnc_status launch_ls_factor(const float *num, const float *K, int64_t N, int64_t R, float *A,
+                            double *T, float *Lf, float *S_out, unsigned long long *fails, hipStream_t s);
+// Sinv[k] = S[k]^{-1} for k < d (R[k] x R[k] floats, every R[k] <= 32), one launch.
+nnc_status launch_ls_inverses(int d, const int64_t *R, float *const *S, float *const *Sinv,
+                              unsigned long long *fails, hipStream_t s);
 
 // ------------------------------------------------------------------ fused3_kernels.hip
 // Side job of the fused three-way passes: blocks [0, nrows) each compute row blockIdx.x of
