@@ -14,9 +14,16 @@ The "alg2" object times Algorithm 2 on the same tensor (nnCP of X at rank 10 wit
 sweep count and refinement, then an NMF of each CP factor with m = 20, lift, residuals), both
 forms, beside one oracle sweep of the nnCP of X.
 
-The roofline object describes the dominant kernel (the X-streaming contraction of the BF16
-form, timed per launch with HIP events on the stream it runs on).  The cpu_baseline object
-times the FP64 oracle on a bounded sample (a few sweeps of the same 512^3 problem).
+The roofline object describes the dominant kernel of the BF16 fit (its second X pass,
+pass2y_k of the fused three-way schedule, which also forms Y_1, S_0 and M_1), timed per
+launch with HIP events on the fit's stream around every pass (nnc_set_timing), median of five
+eager 20-sweep fits.  The plain pass kernels (the FP32 form's) are timed the same way through
+nnc_ttm.  The cpu_baseline object times the FP64 oracle on a bounded sample (whole sweeps of
+the same 512^3 problem), with a 1-thread estimate from one n-mode product of X.
+
+"other_configs" measures the rest of the benchmark set, never the headline: 128^4 stored as
+BF16, the 256^3 adjoint (forward + backward), 64^5 with 64 batched nnCP restarts, and the
+real-valued CANDELINC path at 512^3.
 """
 import argparse
 import json
@@ -38,12 +45,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-PASS_SOURCES = ["paper_1909_07570_amd/csrc/pass_kernels.hip", "paper_1909_07570_amd/csrc/kernels.hip"]
+PASS_SOURCES = ["paper_1909_07570_amd/csrc/pass_kernels.hip", "paper_1909_07570_amd/csrc/kernels.hip",
+                "paper_1909_07570_amd/csrc/fused3_kernels.hip"]
 COUNTERS = os.path.join(ROOT, "profiles", "pass_counters_512cubed.json")
 N_COPY = 128 << 20
 # The R = 20 (two 16-wide rank tiles) instantiations of the four pass kernels, X bytes per entry.
-PASS_BYTES = (("ttm_last_lds_k<true, 2", 2), ("ttm_mid_lds_k<2>", 2),
-              ("ttm_last_lds_k<false, 2", 4), ("ttm_mid_lds_f32_k<2", 4))
+PASS_BYTES = (("ttm_last_lds_k<true, 2", 512 ** 3 * 2 + 512 * 512 * 20 * 4),
+              ("ttm_mid_lds_k<2>", 512 ** 3 * 2 + 512 * 512 * 20 * 4),
+              ("ttm_last_lds_k<false, 2", 512 ** 3 * 4 + 512 * 512 * 20 * 4),
+              ("ttm_mid_lds_f32_k<2", 512 ** 3 * 4 + 512 * 512 * 20 * 4),
+              # fused three-way passes of the BF16 fit: X once, plus Y_0 (pass 1) or T and Y_1 (pass 2)
+              ("pass1y_k", 512 ** 3 * 2 + 512 * 400 * 4),
+              ("pass2y_k", 512 ** 3 * 2 + 512 * 512 * 20 * 4 + 512 * 400 * 4))
 
 
 def sources_sha():
@@ -56,8 +69,9 @@ def sources_sha():
 
 
 def kernel_only(args):
-    """Launch each X-streaming pass kernel (512^3, R = 20, both forms) and a plain 512 MiB
-    device copy a few times: the workload of the rocprofv3 counter runs."""
+    """Launch each plain X-streaming pass kernel (512^3, R = 20, both forms) and a plain
+    512 MiB device copy a few times, then three sweeps of the BF16 fit (its fused passes):
+    the workload of the rocprofv3 counter runs."""
     import torch
 
     import paper_1909_07570_amd as nnc
@@ -68,6 +82,7 @@ def kernel_only(args):
                                                 dtype="f32")[0]).to(dev)
     Xb = nnc.nnc_convert_f32_bf16(X32)
     A = [torch.from_numpy(a).to(dev) for a in synth.init_factors(SEED, (N, N, N), (R, R, R))]
+    G = torch.from_numpy(synth.init_core(SEED, (R, R, R))).to(dev)
     src = torch.ones(N_COPY, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
@@ -76,6 +91,8 @@ def kernel_only(args):
         for Xt in (Xb, X32):
             nnc.nnc_ttm(Xt, 2, A[2])
             nnc.nnc_ttm(Xt, 0, A[0])
+    # three eager sweeps of the BF16 fit: the fused passes pass1y_k / pass2y_k
+    nnc.nntucker_fit(Xb, (R, R, R), 3, G, A, use_graph=False, report=False)
     torch.cuda.synchronize()
     print("kernel-only done", flush=True)
 
@@ -148,11 +165,11 @@ def summarize(args):
     res = {"source_sha": sources_sha(), "copy_fetch_kib": copy_f, "copy_write_kib": copy_w,
            "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
     alg = {}
-    for key, esz in PASS_BYTES:
+    for key, ab in PASS_BYTES:
         fk, wk = pick(fetch, key), pick(write, key)
         if fk is None or wk is None:
             continue
-        alg[key] = 512 ** 3 * esz + 512 * 512 * 20 * 4
+        alg[key] = ab
         res["kernels"][key] = {"fetch_kib": fk, "write_kib": wk,
                                "traffic_bytes": fk * 1024 * f_scale + wk * 1024 * w_scale,
                                "alg_bytes": alg[key]}
@@ -174,7 +191,8 @@ def summarize(args):
     for k, v in res["kernels"].items():
         md.append("| %s | %.0f | %.0f | %.0f | %d | %.3f |" % (
             k, v["fetch_kib"], v["write_kib"], v["traffic_bytes"], alg[k], v["traffic_bytes"] / alg[k]))
-    md += ["", "Algorithmic bytes: X once (2 B or 4 B per entry) + the FP32 output (512 x 512 x 20).",
+    md += ["", "Algorithmic bytes: X once (2 B or 4 B per entry) + the FP32 outputs (512 x 512 x 20 for the "
+           "plain passes; Y_0 = 512 x 20 x 20 for pass1y_k, T and Y_1 = 20 x 512 x 20 for pass2y_k).",
            "Source hash of the pass kernels when measured: %s" % res["source_sha"]]
     with open(os.path.join(ROOT, "profiles", "pass_traffic_512cubed.md"), "w") as f:
         f.write("\n".join(md) + "\n")
@@ -372,6 +390,215 @@ def sec43_study(nnc, dev, n_tensors: int, sweeps: int, progress_every: int = 0):
     return out
 
 
+def pass_split(nnc, fit):
+    """Run `fit()` (a fit with a report) with per-pass timing on: ((ms, launches) of pass 1,
+    (ms, launches) of pass 2), HIP events on the fit's stream around every X-pass launch."""
+    nnc.set_timing(True)
+    try:
+        fit()
+    finally:
+        nnc.set_timing(False)
+    return nnc.last_pass_times()
+
+
+def pass_roofline(times, bytes1, bytes2, names):
+    """Per-pass average launch time and achieved HBM rate from pass_split's result."""
+    out = {}
+    for (ms, n), b, name in zip(times, (bytes1, bytes2), names):
+        if n <= 0:
+            continue
+        us = ms / n * 1e3
+        out[name] = {"avg_us": round(us, 2), "alg_bytes_per_launch": int(b),
+                     "GB/s": round(b / (us * 1e-6) / 1e9, 1), "frac": round(b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                     "launches": int(n)}
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def one_thread_ratio(oracle, X64, A):
+    """Seconds of one n-mode product of X (the oracle's unit of work on X) at all cores and at
+    1 thread; their ratio scales an all-cores rate to a 1-thread estimate."""
+    n = X64.ndim - 1
+    t = time.perf_counter()
+    oracle.ttm_t(X64, n, A)
+    t_all = time.perf_counter() - t
+    threads = oracle.get_threads()
+    oracle.set_threads(1)
+    try:
+        t = time.perf_counter()
+        oracle.ttm_t(X64, n, A)
+        t_one = time.perf_counter() - t
+    finally:
+        oracle.set_threads(threads)
+    return t_all, t_one
+
+
+def extra_workloads(args, nnc, dev):
+    """The other configurations of the benchmark set, each with its own timing (never the
+    headline): 128^4 stored BF16, the 256^3 adjoint, 64^5 with batched nnCP restarts, and the
+    real-valued CANDELINC path at 512^3."""
+    import torch
+
+    import synth
+    from tests.gpu_util import planted_tensor_dev, signed_planted_dev
+    out = {}
+
+    def timed(fn, reps=1):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps, r
+
+    # ---- 128^4 stored as BF16: nnTucker 16^4, 500 sweeps (BF16 form: last 20 on the exact FP32
+    # widening of the stored values; FP32 form: every sweep on that widening), nnCP rank 8, lift
+    dims, ranks, seed = (128,) * 4, (16,) * 4, 3
+    Xb = nnc.nnc_convert_f32_bf16(planted_tensor_dev(seed, dims, 8))
+    X32 = Xb.float()
+    G0 = torch.from_numpy(synth.init_core(seed, ranks)).to(dev)
+    A0 = [torch.from_numpy(a).to(dev) for a in synth.init_factors(seed, dims, ranks)]
+    B0 = [torch.from_numpy(b).to(dev) for b in synth.init_cp_factors(seed, ranks, 8)]
+    ws = torch.empty(nnc.nntucker_workspace_bytes(dims, ranks), dtype=torch.uint8, device=dev)
+    c3 = {"workload": "128^4 planted rank-8 tensor stored as BF16 (X formed on the GPU from the seeded draws); "
+                      "nnTucker multirank 16^4, %d sweeps; nnCP rank 8, 300 sweeps; lift" % args.sweeps}
+    for form, bf in (("bf16", True), ("fp32", False)):
+        G = G0.clone()
+        A = [a.clone() for a in A0]
+        B = [b.clone() for b in B0]
+        if bf:
+            fit = lambda: nnc.nntucker_fit(Xb, ranks, args.sweeps, G, A, x_fp32=X32, fp32_final_sweeps=20,
+                                           report=False, workspace=ws)
+        else:
+            fit = lambda: nnc.nntucker_fit(X32, ranks, args.sweeps, G, A, report=False, workspace=ws)
+        el, _ = timed(fit)
+        elc, _ = timed(lambda: nnc.nncp_fit(G, 8, 300, B, residual=False))
+        C = nnc.nncandelinc_lift(A, B)
+        c3[form] = {"sweeps_per_s": round(args.sweeps / el, 1), "nncp_ms": round(elc * 1e3, 3),
+                    "tucker_rel": nnc.reconstruct_residual(X32, A, G), "lifted_rel": nnc.reconstruct_residual(X32, C)}
+        G = G0.clone()
+        A = [a.clone() for a in A0]
+        Xs = Xb if bf else X32
+        times = pass_split(nnc, lambda: nnc.nntucker_fit(Xs, ranks, 20, G, A, workspace=ws))
+        size, esz = 128 ** 4, (2 if bf else 4)
+        c3[form]["passes"] = pass_roofline(times, size * esz + size // 128 * 16 * 4, size * esz + size // 128 * 16 * 4,
+                                           ("pass1_x_x3", "pass2_x_x0"))
+        log("c3 %s: %s" % (form, json.dumps(c3[form])))
+    del Xb, X32, ws
+    out["c3_128x4_bf16"] = c3
+
+    # ---- 256^3 adjoint: L = 0.5 ||X - G x {A}||^2 and its gradient (core 32^3, factors 256 x 32)
+    dims, ranks, seed = (256,) * 3, (32,) * 3, 4
+    X = planted_tensor_dev(seed, dims, 12, zero_prob=0.3)
+    G = torch.from_numpy(synth.init_core(seed, ranks)).to(dev).requires_grad_(True)
+    A = [torch.from_numpy(a).to(dev).requires_grad_(True) for a in synth.init_factors(seed, dims, ranks)]
+
+    def fwd_bwd():
+        for t in [G] + A:
+            t.grad = None
+        loss = nnc.nntucker_loss(X, G, A)
+        loss.backward()
+        return loss
+    timed(fwd_bwd, 3)
+    el, loss = timed(fwd_bwd, 20)
+    size = 256 ** 3
+    alg = 3 * size * 4 + 2 * (size // 256) * 32 * 4  # three reads of X, P and T written once each
+    out["c4_256x3_adjoint"] = {
+        "workload": "256^3 FP32 planted rank-12 tensor (30 % zeros); loss and gradient at the seeded point, "
+                    "core 32^3, factors 256 x 32 (autograd: forward residual pass + nntucker_grad)",
+        "fwd_bwd_ms": round(el * 1e3, 3), "loss": float(loss.detach()),
+        "alg_bytes": alg, "GB/s": round(alg / el / 1e9, 1), "frac_of_hbm": round(alg / el / 1e9 / HBM_PEAK_GBS, 4),
+        "note": "X (64 MiB) fits in the 256 MiB MALL, so the three reads of one call can exceed the HBM rate"}
+    log("c4: %s" % json.dumps(out["c4_256x3_adjoint"]))
+    del X, G, A
+
+    # ---- 64^5 FP32 (4 GiB): nnTucker 8^5, 300 sweeps; 64 batched nnCP restarts of its core
+    dims, ranks, seed = (64,) * 5, (8,) * 5, 5
+    X = planted_tensor_dev(seed, dims, 6)
+    G = torch.from_numpy(synth.init_core(seed, ranks)).to(dev)
+    A = [torch.from_numpy(a).to(dev) for a in synth.init_factors(seed, dims, ranks)]
+    A5 = [a.clone() for a in A]
+    ws = torch.empty(nnc.nntucker_workspace_bytes(dims, ranks), dtype=torch.uint8, device=dev)
+    el, _ = timed(lambda: nnc.nntucker_fit(X, ranks, 300, G, A, report=False, workspace=ws))
+    rks = [2 + (j % 15) for j in range(64)]
+    Bs = [[torch.from_numpy(b).to(dev) for b in synth.init_cp_factors(seed, ranks, r, restart=j)]
+          for j, r in enumerate(rks)]
+    elb, res = timed(lambda: nnc.nncp_fit_batched(G, rks, 300, Bs))
+    Gt = torch.from_numpy(synth.init_core(seed, ranks)).to(dev)
+    At = [a.clone() for a in A5]
+    times = pass_split(nnc, lambda: nnc.nntucker_fit(X, ranks, 10, Gt, At, workspace=ws))
+    size = 64 ** 5
+    out["c5_64x5"] = {
+        "workload": "64^5 FP32 planted rank-6 tensor (4 GiB, formed on the GPU); nnTucker multirank 8^5, "
+                    "300 sweeps; 64 nnCP restarts of the 8^5 core (ranks 2..16), 300 sweeps each, one launch",
+        "sweeps_per_s": round(300 / el, 1), "tucker_rel": nnc.reconstruct_residual(X, A, G),
+        "batched_nncp_ms": round(elb * 1e3, 3), "best_restart_rel": float(min(res)),
+        "passes": pass_roofline(times, size * 4 + size // 64 * 8 * 4, size * 4 + size // 64 * 8 * 4,
+                                ("pass1_x_x4", "pass2_x_x0"))}
+    log("c5: %s" % json.dumps(out["c5_64x5"]))
+    del X, ws
+
+    # ---- real-valued CANDELINC, 512^3 signed planted rank-20 CP: Tucker 20^3 by alternating
+    # least squares (25 sweeps), CP rank 20 of the core by alternating least squares (300), lift
+    dims, ranks, seed = (512,) * 3, (20,) * 3, 7
+    X = signed_planted_dev(seed, dims, 20, noise=1e-3)
+    Xb = nnc.nnc_convert_f32_bf16(X)
+    G0 = torch.from_numpy(synth.init_core(seed, ranks)).to(dev)
+    A0 = [torch.from_numpy(a).to(dev) for a in synth.init_factors(seed, dims, ranks)]
+    B0 = [torch.from_numpy(2.0 * b - 1.0).to(dev) for b in synth.init_cp_factors(seed, ranks, 20)]
+    real = {"workload": "512^3 FP32 real tensor: planted rank-20 CP with U[-1,1) factors + U[-1e-3,1e-3) noise; "
+                        "Tucker 20^3 by alternating least squares with orthonormalized factors, 25 sweeps; "
+                        "CP rank 20 of the core by alternating least squares, 300 sweeps; lift"}
+    for form, bf in (("bf16", True), ("fp32", False)):
+        G = G0.clone()
+        A = [a.clone() for a in A0]
+        B = [b.clone() for b in B0]
+        if bf:
+            fit = lambda: nnc.tucker_ls_fit(Xb, ranks, 25, G, A, x_fp32=X, fp32_final_sweeps=5, report=False)
+        else:
+            fit = lambda: nnc.tucker_ls_fit(X, ranks, 25, G, A, report=False)
+        el, _ = timed(fit)
+        elc, _ = timed(lambda: nnc.cp_ls_fit(G, 20, 300, B, residual=False))
+        C = nnc.nncandelinc_lift(A, B)
+        real[form] = {"sweeps_per_s": round(25 / el, 1), "cp_ls_ms": round(elc * 1e3, 3),
+                      "tucker_rel": nnc.reconstruct_residual(X, A, G), "lifted_rel": nnc.reconstruct_residual(X, C)}
+        log("real %s: %s" % (form, json.dumps(real[form])))
+    out["real_candelinc_512"] = real
+
+    if not args.no_cpu:
+        import oracle
+        cpu = {"cpu_model": cpu_model(), "threads": oracle.get_threads()}
+        # the real path: one oracle sweep at all cores, the 1-thread figure from one n-mode product
+        X64 = X.double().cpu().numpy()
+        g0 = synth.init_core(seed, ranks).astype(np.float64)
+        a0 = [a.astype(np.float64) for a in synth.init_factors(seed, dims, ranks)]
+        t = time.perf_counter()
+        oracle.tucker_ls(X64, g0, a0, 1)
+        el = time.perf_counter() - t
+        t_all, t_one = one_thread_ratio(oracle, X64, a0[2])
+        cpu["real_candelinc_512"] = {
+            "value": round(1.0 / el, 4), "unit": "least-squares sweeps/s", "kind": "oracle",
+            "sample": "1 FP64 sweep (with the orthonormalization of the initial factors), %.1f s" % el,
+            "one_thread_estimate": round(1.0 / el * t_all / t_one, 5),
+            "one_thread_basis": "one 512^3 x 20 n-mode product of X: %.2f s at %d threads, %.2f s at 1 thread; "
+                                "the all-cores rate scaled by that ratio" % (t_all, oracle.get_threads(), t_one)}
+        del X64
+        log("cpu extras: %s" % json.dumps(cpu))
+        out["cpu_baseline"] = cpu
+    del X, Xb
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -390,6 +617,8 @@ def main():
     ap.add_argument("--sec43-tensors", type=int, default=8)
     ap.add_argument("--no-studies", action="store_true",
                     help="skip Algorithm 2 and the Section 4.2 / 4.3 studies (diagnostic runs)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 128^4, 256^3 adjoint, 64^5 and real-valued CANDELINC measurements")
     ap.add_argument("--sec43-only", action="store_true",
                     help="only the Section 4.3 study (progress on stderr, one JSON line)")
     ap.add_argument("--kernel-only", action="store_true",
@@ -483,6 +712,9 @@ def main():
     alg2, study, sec43 = {}, {}, {}
     if not args.no_studies:
         alg2, study, sec43 = extra_studies(args, nnc, dev, Xb, X32, dims, ranks, rank, R)
+    extras = {}
+    if not args.no_extras:
+        extras = extra_workloads(args, nnc, dev)
 
     # ---- per-launch timing of the two X-streaming contractions (same kernels, same launch
     # configuration as inside the fit), HIP events on the stream they are launched on:
@@ -516,26 +748,38 @@ def main():
                 group_avg_us=[round(g * 1e3, 2) for g in groups])
             log("%s_%s: %.1f us, %.0f GB/s, %.1f TFLOP/s" % (kname, name, ms * 1e3,
                 kern["%s_%s" % (kname, name)]["gbs"], kern["%s_%s" % (kname, name)]["tflops"]))
-    # in-fit cross-check: event-timed passes of an eager BF16 fit
-    nnc.set_timing(True)
-    G.copy_(G0)
-    for a, a0 in zip(A, A0):
-        a.copy_(a0)
-    rep = nnc.nntucker_fit(Xb, ranks, 20, G, A, workspace=ws)
-    nnc.set_timing(False)
-    infit_pass_us = rep.ttm_pass_ms / max(1, rep.ttm_pass_launches) * 1e3
-
-    dom = max(("ttm_last_bf16", "ttm_mid_bf16"), key=lambda k: kern[k]["avg_us"])
-    dk = kern[dom]
+    # The BF16 fit's own passes (the fused three-way schedule: pass1y_k forms Y_0 = X x_2 A_2^T
+    # x_1 A_1^T and M_0, pass2y_k writes T = X x_0 A_0^T and forms Y_1, S_0 and M_1), timed
+    # per launch with HIP events around each pass on the fit's stream, over an eager fit of
+    # 20 sweeps: kGroups such fits, the median group's per-launch averages.
+    size_yx = N * R * R  # Y_0 = N x R x R,  Y_1 = R x N x R
+    alg_p1 = size * 2 + size_yx * 4
+    alg_p2 = size * 2 + size // N * R * 4 + size_yx * 4
+    fused = []
+    for _ in range(kGroups):
+        G.copy_(G0)
+        for a, a0 in zip(A, A0):
+            a.copy_(a0)
+        fused.append(pass_roofline(pass_split(nnc, lambda: nnc.nntucker_fit(Xb, ranks, 20, G, A, workspace=ws)),
+                                   alg_p1, alg_p2, ("pass1y_k", "pass2y_k")))
+    infit = {}
+    for key in ("pass1y_k", "pass2y_k"):
+        us = sorted(f[key]["avg_us"] for f in fused)
+        med = us[kGroups // 2]
+        b = fused[0][key]["alg_bytes_per_launch"]
+        infit[key] = {"avg_us": med, "group_avg_us": us, "alg_bytes_per_launch": b,
+                      "GB/s": round(b / (med * 1e-6) / 1e9, 1), "frac": round(b / (med * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+        log("%s in the BF16 fit: %.2f us, %.0f GB/s" % (key, med, infit[key]["GB/s"]))
+    dom = max(infit, key=lambda k: infit[k]["avg_us"])
+    dk = infit[dom]
     traffic = None
     if os.path.exists(COUNTERS):
         cnt = json.load(open(COUNTERS))
-        key = {"ttm_last_bf16": "ttm_last_lds_k<true, 2", "ttm_mid_bf16": "ttm_mid_lds_k<2>"}[dom]
-        if cnt.get("source_sha") == sources_sha() and key in cnt.get("kernels", {}):
-            traffic = round(cnt["kernels"][key]["traffic_bytes"])
-    roofline = {"bound": "hbm", "achieved": round(dk["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(dk["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-                "avg_us": round(dk["avg_us"], 2), "alg_bytes_per_launch": dk["alg_bytes"]}
+        if cnt.get("source_sha") == sources_sha() and dom in cnt.get("kernels", {}):
+            traffic = round(cnt["kernels"][dom]["traffic_bytes"])
+    roofline = {"bound": "hbm", "achieved": dk["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": dk["frac"], "traffic": traffic, "kernel": dom,
+                "avg_us": dk["avg_us"], "alg_bytes_per_launch": dk["alg_bytes_per_launch"]}
 
     cpu = None
     if not args.no_cpu:
@@ -551,10 +795,15 @@ def main():
             el = time.perf_counter() - t
             if el >= args.cpu_seconds:
                 break
+        t_all, t_one = one_thread_ratio(oracle, X64, a0[2])
         cpu = {"value": round(done / el, 5), "unit": "MU sweeps/s", "cores": oracle.get_threads(),
-               "kind": "oracle",
-               "sample": "%d FP64 nnTucker sweeps of the same 512^3 problem (multirank 20^3) from the "
-                         "same initial values, %.1f s" % (done, el)}
+               "kind": "oracle", "cpu_model": cpu_model(),
+               "sample": "%d whole FP64 nnTucker sweeps of the same 512^3 problem (multirank 20^3) from the "
+                         "same initial values, %.1f s (no extrapolation)" % (done, el),
+               "one_thread_estimate": round(done / el * t_all / t_one, 5),
+               "one_thread_basis": "one 512^3 x 20 n-mode product of X: %.2f s at %d threads, %.2f s at 1 "
+                                   "thread; the all-cores rate scaled by that ratio"
+                                   % (t_all, oracle.get_threads(), t_one)}
         if not args.no_studies:
             t = time.perf_counter()
             b0x = [b.astype(np.float64) for b in synth.init_cp_factors(SEED, dims, rank)]
@@ -598,9 +847,10 @@ def main():
                    "sweeps": args.sweeps, "fp32_final_sweeps": args.fp32_final},
         "ttm_tflops": round(sweep_flops * args.sweeps / (bf["seconds"] / args.steps) / 1e12, 2),
         "ttm_kernel_tflops": {k: round(v["tflops"], 2) for k, v in kern.items()},
-        "kernels": {k: {"avg_us": round(v["avg_us"], 2), "GB/s": round(v["gbs"], 1),
-                        "group_avg_us": v["group_avg_us"]} for k, v in kern.items()},
-        "infit_pass_avg_us_bf16": round(infit_pass_us, 2),
+        "plain_pass_kernels": {k: {"avg_us": round(v["avg_us"], 2), "GB/s": round(v["gbs"], 1),
+                                   "frac": round(v["gbs"] / HBM_PEAK_GBS, 4),
+                                   "group_avg_us": v["group_avg_us"]} for k, v in kern.items()},
+        "bf16_fit_passes": infit,
         "residuals": {"bf16_tucker": bf["tucker_rel"], "fp32_tucker": fp["tucker_rel"],
                       "bf16_lifted_cp": bf["cp_rel"], "fp32_lifted_cp": fp["cp_rel"],
                       "abs_diff_tucker": abs(bf["tucker_rel"] - fp["tucker_rel"])},
@@ -613,6 +863,7 @@ def main():
         "alg2": alg2,
         "restart_study": study,
         "sec43_study": sec43,
+        "other_configs": extras,
     }
     print(json.dumps(line), flush=True)
 

@@ -106,6 +106,13 @@ int nnc_device_ok(void);
  * reports their summed duration. */
 void nnc_set_timing(int on);
 
+/* The per-pass split of the last timed fit on the calling thread (a fit run while timing
+ * was on and with rep != NULL): ms[0] / launches[0] for the first X pass of each sweep
+ * (X x_d A_d^T; in the fused three-way BF16 schedule the pass that also forms Y_0 and M_0),
+ * ms[1] / launches[1] for the second (X x_1 A_1^T; fused: also Y_1, S_1 and M_1).  Host
+ * arrays of 2, either may be NULL. */
+void nnc_last_pass_times(double *ms, long long *launches);
+
 /*
  * n-mode product with a transposed factor, out = X x_n A^T (Appendix A, definition of
  * n-mode multiplication, with the matrix A^T):

@@ -61,7 +61,7 @@ EXPORTED = ["nnc_last_error", "nnc_device_ok", "nnc_set_timing", "nnc_ttm", "nnc
             "nmf_batched_workspace_bytes", "nmf_fit_batched", "nncandelinc_restart_init_floats",
             "nncandelinc_restarts", "nnc_mean_congruence", "nnc_fill_uniform", "nnc_fill_uniform_f64",
             "nncp_noalloc_max_scratch_bytes", "nncp_fit_noalloc", "tucker_ls_workspace_bytes",
-            "tucker_ls_fit", "cp_ls_workspace_bytes", "cp_ls_fit"]
+            "tucker_ls_fit", "cp_ls_workspace_bytes", "cp_ls_fit", "nnc_last_pass_times"]
 
 _lib = None
 
@@ -76,6 +76,8 @@ def lib():
         L.nnc_last_error.restype = ctypes.c_char_p
         L.nnc_device_ok.restype = ctypes.c_int
         L.nnc_set_timing.argtypes = [ctypes.c_int]
+        L.nnc_last_pass_times.argtypes = [_dp, ctypes.POINTER(ctypes.c_longlong)]
+        L.nnc_last_pass_times.restype = None
         L.nnc_ttm.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _i64p, ctypes.c_int, _vp, _i64, _vp, _vp]
         L.nnc_convert_f32_bf16.argtypes = [_vp, _vp, _i64, _vp]
         L.nnc_fill_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint64, _vp, _i64, _vp]
@@ -132,7 +134,7 @@ def lib():
         L.nntucker_grad.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _i64p, _i64p, _vp, _vpp, _vp,
                                     _vpp, _dp, _vp, ctypes.c_size_t, _vp]
         for name in EXPORTED:
-            if name not in ("nnc_last_error", "nnc_device_ok", "nnc_set_timing") and \
+            if name not in ("nnc_last_error", "nnc_device_ok", "nnc_set_timing", "nnc_last_pass_times") and \
                     not name.endswith("_bytes") and not name.endswith("_floats"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -185,6 +187,14 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 def set_timing(on: bool) -> None:
     lib().nnc_set_timing(1 if on else 0)
+
+
+def last_pass_times():
+    """((ms of pass 1, launches), (ms of pass 2, launches)) of this thread's last timed fit."""
+    ms = (ctypes.c_double * 2)()
+    n = (ctypes.c_longlong * 2)()
+    lib().nnc_last_pass_times(ms, n)
+    return (ms[0], n[0]), (ms[1], n[1])
 
 
 def device_ok() -> bool:

@@ -304,8 +304,9 @@ static nnc_status factor_block(const TuckerBufs &b, int n, const float *Y, const
 // ------------------------------------------------------------------ pass timing
 struct PassTimer {
   std::vector<hipEvent_t> ev;
+  std::vector<int> kind;  // 0: the sweep's first X pass, 1: its second
   size_t used = 0;
-  nnc_status start(hipStream_t s) {
+  nnc_status start(hipStream_t s, int k) {
     if (used + 2 > ev.size()) {
       for (int i = 0; i < 64; ++i) {
         hipEvent_t e;
@@ -314,6 +315,7 @@ struct PassTimer {
       }
     }
     NNC_HIP(hipEventRecord(ev[used], s));
+    kind.push_back(k);
     return NNC_OK;
   }
   nnc_status stop(hipStream_t s) {
@@ -321,13 +323,18 @@ struct PassTimer {
     used += 2;
     return NNC_OK;
   }
-  nnc_status total_ms(double *ms) {
+  // total and per-kind milliseconds and launch counts
+  nnc_status total_ms(double *ms, double per_ms[2], long long per_n[2]) {
     double t = 0;
+    per_ms[0] = per_ms[1] = 0.0;
+    per_n[0] = per_n[1] = 0;
     for (size_t i = 0; i + 1 < used; i += 2) {
       NNC_HIP(hipEventSynchronize(ev[i + 1]));
       float x = 0.f;
       NNC_HIP(hipEventElapsedTime(&x, ev[i], ev[i + 1]));
       t += x;
+      per_ms[kind[i / 2]] += x;
+      per_n[kind[i / 2]] += 1;
     }
     *ms = t;
     return NNC_OK;
@@ -336,6 +343,10 @@ struct PassTimer {
     for (auto e : ev) (void)hipEventDestroy(e);
   }
 };
+
+// Per-pass timing of this thread's last timed fit (nnc_last_pass_times).
+static thread_local double g_pass_ms[2] = {0.0, 0.0};
+static thread_local long long g_pass_n[2] = {0, 0};
 
 // ------------------------------------------------------------------ fused sweep (R <= 32)
 static CoreArgsHost core_args(const TuckerBufs &b, float *G, float *const *A, double eps) {
@@ -453,7 +464,7 @@ static nnc_status fused_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, 
                               float *const *A, double eps, hipStream_t s, PassTimer *tm) {
   const TuckerPlan &p = *b.p;
   const int d = p.d;
-  if (tm) NNC_TRY(tm->start(s));
+  if (tm) NNC_TRY(tm->start(s, 0));
   NNC_TRY(launch_ttm(X, dt, p.size / p.N[d - 1], p.N[d - 1], 1, A[d - 1], p.R[d - 1], 1, p.R[d - 1],
                      b.P(), s, true));
   if (tm) NNC_TRY(tm->stop(s));
@@ -491,7 +502,7 @@ static nnc_status fused_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, 
       pending = h;  // M_{d-1} is not needed before the last mode
     }
   }
-  if (tm) NNC_TRY(tm->start(s));
+  if (tm) NNC_TRY(tm->start(s, 1));
   NNC_TRY(launch_ttm(X, dt, 1, p.N[0], p.size / p.N[0], A[0], p.R[0], 1, p.R[0], b.T(), s, true));
   if (tm) NNC_TRY(tm->stop(s));
   int64_t cur[kMaxDim];
@@ -543,7 +554,7 @@ static Side3 side3(const TuckerBufs &b, const float *G, int n) {
 static nnc_status fused3_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, float *G,
                                float *const *A, double eps, hipStream_t s, PassTimer *tm) {
   const TuckerPlan &p = *b.p;
-  if (tm) NNC_TRY(tm->start(s));
+  if (tm) NNC_TRY(tm->start(s, 0));
   NNC_TRY(launch_pass1y(X, dt, p.N[0], p.N[1], p.N[2], A[2], p.R[2], A[1], p.R[1], b.Y(), side3(b, G, 0), s));
   if (tm) NNC_TRY(tm->stop(s));
   NNC_TRY(launch_mu_rows(b.Y(), G, A[0], b.M(), 1, p.N[0], p.R[1] * p.R[2], p.R[0], eps, b.clips(), b.gram(),
@@ -553,7 +564,7 @@ static nnc_status fused3_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt,
   s1.gmode = 0;
   s1.gram_parts = (int)mu_rows_blocks(p.N[0]);
   s1.S_store = b.S(0);
-  if (tm) NNC_TRY(tm->start(s));
+  if (tm) NNC_TRY(tm->start(s, 1));
   NNC_TRY(launch_pass2y(X, dt, p.N[0], p.N[1], p.N[2], A[0], p.R[0], A[2], p.R[2], b.T(), b.Y(), s1, s));
   if (tm) NNC_TRY(tm->stop(s));
   NNC_TRY(launch_mu_rows(b.Y(), G, A[1], b.M(), p.R[0], p.N[1], p.R[2], p.R[1], eps, b.clips(), b.gram(),
@@ -585,7 +596,7 @@ static nnc_status tucker_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt,
   const TuckerPlan &p = *b.p;
   const int d = p.d;
   // pass 1
-  if (tm) NNC_TRY(tm->start(s));
+  if (tm) NNC_TRY(tm->start(s, 0));
   NNC_TRY(launch_ttm(X, dt, p.size / p.N[d - 1], p.N[d - 1], 1, A[d - 1], p.R[d - 1], 1, p.R[d - 1],
                      b.P(), s, true));
   if (tm) NNC_TRY(tm->stop(s));
@@ -609,7 +620,7 @@ static nnc_status tucker_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt,
     }
   }
   // pass 2
-  if (tm) NNC_TRY(tm->start(s));
+  if (tm) NNC_TRY(tm->start(s, 1));
   NNC_TRY(launch_ttm(X, dt, 1, p.N[0], p.size / p.N[0], A[0], p.R[0], 1, p.R[0], b.T(), s, true));
   if (tm) NNC_TRY(tm->stop(s));
   {
@@ -679,7 +690,7 @@ static nnc_status ls_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, flo
                            hipStream_t s, PassTimer *tm) {
   const TuckerPlan &p = *b.p;
   const int d = p.d;
-  if (tm) NNC_TRY(tm->start(s));
+  if (tm) NNC_TRY(tm->start(s, 0));
   NNC_TRY(launch_ttm(X, dt, p.size / p.N[d - 1], p.N[d - 1], 1, A[d - 1], p.R[d - 1], 1, p.R[d - 1],
                      b.P(), s, true));
   if (tm) NNC_TRY(tm->stop(s));
@@ -700,7 +711,7 @@ static nnc_status ls_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, flo
       U = Un;
     }
   }
-  if (tm) NNC_TRY(tm->start(s));
+  if (tm) NNC_TRY(tm->start(s, 1));
   NNC_TRY(launch_ttm(X, dt, 1, p.N[0], p.size / p.N[0], A[0], p.R[0], 1, p.R[0], b.T(), s, true));
   if (tm) NNC_TRY(tm->stop(s));
   int64_t cur[kMaxDim];
@@ -951,6 +962,13 @@ const char *nnc_last_error(void) { return g_err.c_str(); }
 
 void nnc_set_timing(int on) { g_timing = on ? 1 : 0; }
 
+void nnc_last_pass_times(double *ms, long long *launches) {
+  for (int k = 0; k < 2; ++k) {
+    if (ms) ms[k] = g_pass_ms[k];
+    if (launches) launches[k] = g_pass_n[k];
+  }
+}
+
 int nnc_device_ok(void) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return 0;
@@ -1168,7 +1186,9 @@ static nnc_status tucker_fit_impl(bool ls, const void *X, nnc_dtype xdt, int ndi
     rep->history_len = hist;
     rep->ttm_pass_ms = 0;
     rep->ttm_pass_launches = (long long)(timer.used / 2);
-    if (tm) NNC_TRY(timer.total_ms(&rep->ttm_pass_ms));
+    if (tm) {
+      NNC_TRY(timer.total_ms(&rep->ttm_pass_ms, g_pass_ms, g_pass_n));
+    }
     rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (ls && clips)
       return fail(NNC_ENUMERIC, "%llu least-squares systems were not positive definite (rank-deficient "
