@@ -124,6 +124,12 @@ void nnc_last_pass_times(double *ms, long long *launches);
 nnc_status nnc_ttm(const void *X, nnc_dtype xdt, int ndim, const int64_t *dims, int n,
                    const float *A, int64_t R, float *out, void *stream);
 
+/* The kernel the calling thread's last nnc_ttm launched: "ttm_last_lds_bf16",
+ * "ttm_mid_f32", ... for the matrix-core X-streaming kernels ("(chunked)" when the contracted
+ * index was split into several launches), "ttm_generic" for the general kernel.  A static
+ * string, never NULL. */
+const char *nnc_last_ttm_kernel(void);
+
 /* Round FP32 to bfloat16 (round to nearest, ties to even; NaN stays NaN).  out holds
  * count uint16 bit patterns. */
 nnc_status nnc_convert_f32_bf16(const float *in, uint16_t *out, int64_t count, void *stream);

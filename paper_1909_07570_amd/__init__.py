@@ -61,7 +61,7 @@ EXPORTED = ["nnc_last_error", "nnc_device_ok", "nnc_set_timing", "nnc_ttm", "nnc
             "nmf_batched_workspace_bytes", "nmf_fit_batched", "nncandelinc_restart_init_floats",
             "nncandelinc_restarts", "nnc_mean_congruence", "nnc_fill_uniform", "nnc_fill_uniform_f64",
             "nncp_noalloc_max_scratch_bytes", "nncp_fit_noalloc", "tucker_ls_workspace_bytes",
-            "tucker_ls_fit", "cp_ls_workspace_bytes", "cp_ls_fit", "nnc_last_pass_times"]
+            "tucker_ls_fit", "cp_ls_workspace_bytes", "cp_ls_fit", "nnc_last_pass_times", "nnc_last_ttm_kernel"]
 
 _lib = None
 
@@ -78,6 +78,8 @@ def lib():
         L.nnc_set_timing.argtypes = [ctypes.c_int]
         L.nnc_last_pass_times.argtypes = [_dp, ctypes.POINTER(ctypes.c_longlong)]
         L.nnc_last_pass_times.restype = None
+        L.nnc_last_ttm_kernel.argtypes = []
+        L.nnc_last_ttm_kernel.restype = ctypes.c_char_p
         L.nnc_ttm.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _i64p, ctypes.c_int, _vp, _i64, _vp, _vp]
         L.nnc_convert_f32_bf16.argtypes = [_vp, _vp, _i64, _vp]
         L.nnc_fill_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint64, _vp, _i64, _vp]
@@ -134,7 +136,8 @@ def lib():
         L.nntucker_grad.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _i64p, _i64p, _vp, _vpp, _vp,
                                     _vpp, _dp, _vp, ctypes.c_size_t, _vp]
         for name in EXPORTED:
-            if name not in ("nnc_last_error", "nnc_device_ok", "nnc_set_timing", "nnc_last_pass_times") and \
+            if name not in ("nnc_last_error", "nnc_device_ok", "nnc_set_timing", "nnc_last_pass_times",
+                            "nnc_last_ttm_kernel") and \
                     not name.endswith("_bytes") and not name.endswith("_floats"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -187,6 +190,11 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 def set_timing(on: bool) -> None:
     lib().nnc_set_timing(1 if on else 0)
+
+
+def last_ttm_kernel() -> str:
+    """The kernel this thread's last nnc_ttm launched."""
+    return lib().nnc_last_ttm_kernel().decode()
 
 
 def last_pass_times():

@@ -979,6 +979,8 @@ int nnc_device_ok(void) {
   return strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
 }
 
+static thread_local const char *g_last_ttm_kernel = "";
+
 nnc_status nnc_ttm(const void *X, nnc_dtype xdt, int ndim, const int64_t *dims, int n,
                    const float *A, int64_t R, float *out, void *stream) {
   NNC_TRY(check_dims(ndim, dims, "dims"));
@@ -986,9 +988,12 @@ nnc_status nnc_ttm(const void *X, nnc_dtype xdt, int ndim, const int64_t *dims, 
   if (xdt != NNC_F32 && xdt != NNC_BF16) return fail(NNC_EINVAL, "unknown dtype %d", (int)xdt);
   if (n < 0 || n >= ndim) return fail(NNC_EINVAL, "mode %d outside [0, %d)", n, ndim);
   if (R < 1) return fail(NNC_EINVAL, "R = %lld < 1", (long long)R);
+  g_last_ttm_kernel = "";
   return launch_ttm(X, xdt, prod(dims, 0, n), dims[n], prod(dims, n + 1, ndim), A, R, 1, R, out,
-                    (hipStream_t)stream, true);
+                    (hipStream_t)stream, true, &g_last_ttm_kernel);
 }
+
+const char *nnc_last_ttm_kernel(void) { return g_last_ttm_kernel; }
 
 nnc_status nnc_convert_f32_bf16(const float *in, uint16_t *out, int64_t count, void *stream) {
   if (!in || !out) return fail(NNC_EINVAL, "in and out must be non-NULL");

@@ -1,13 +1,12 @@
-// HIP kernels for gfx950 (CDNA4): tensor-times-matrix contractions on MFMA, multiplicative
-// update steps, residual reductions and conversions.
+// HIP kernels for gfx950 (CDNA4): the contraction dispatcher, multiplicative update steps,
+// residual reductions and conversions.
 //
 // Contraction forms (n-mode product with a transposed factor, Appendix A):
 //   X viewed as [P][N][Q] (N = the contracted mode, Q = product of the later modes):
 //     out[p][r][q] = sum_n F(n, r) * X[p][n][q].
-//   Q == 1 (last mode, contraction index contiguous)  -> ttm_last_*  (X is an M x K matrix)
-//   Q  > 1 (earlier mode, contraction index strided)  -> ttm_mid_*   (coalesced along q)
-// The MFMA kernels keep the factor (<= 32 columns, zero-padded to 16-column tiles) in LDS
-// and stream X once in its natural layout.
+// The matrix-core X-streaming kernels (pass_kernels.hip) take every shape with rank <= 32,
+// 16-byte aligned X and output and rows of a whole number of 16-byte chunks; the general
+// kernel here takes the rest.
 #include <stdarg.h>
 #include <stdio.h>
 
@@ -39,289 +38,6 @@ static __device__ inline bf8 as_bf8(u4 v) { return __builtin_bit_cast(bf8, v); }
 
 static __device__ inline f4 mfma_bf16(u4 a, u4 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(a), as_bf8(b), c, 0, 0, 0);
-}
-
-// =====================================================================================
-// Last-mode contraction, FP32 MFMA (v_mfma_f32_16x16x4_f32).
-// out[m][r] = sum_k X[m][k] F(k, r);  X is M x K row-major, K % 4 == 0.
-// A wave owns 16-row tiles.  Lane (li = lane%16, lg = lane/16) loads the float4
-// X[row li][k0 + 4 lg .. +3]; component c feeds the MFMA whose k-slot lg stands for
-// k = k0 + 4 lg + c, paired with the factor row k from LDS.
-// =====================================================================================
-constexpr int kTtmThreads = 512;
-
-template <int RT>
-__global__ __launch_bounds__(kTtmThreads) void ttm_last_f32_k(const float *__restrict__ X, int64_t M,
-                                                              int K, const float *__restrict__ F,
-                                                              int64_t ldl, int64_t ldr, int R,
-                                                              float *__restrict__ out) {
-  extern __shared__ __attribute__((aligned(16))) float lds[];
-  constexpr int RP = 16 * RT;
-  constexpr int RS = RP + 4;  // row stride: the four lane groups hit distinct bank ranges
-  const int Kp = (K + 15) & ~15;
-  for (int e = threadIdx.x; e < Kp * RP; e += blockDim.x) {
-    const int k = e / RP, r = e - k * RP;
-    lds[k * RS + r] = (k < K && r < R) ? F[k * ldl + r * ldr] : 0.f;
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane & 15, lg = lane >> 4;
-  const int nw = blockDim.x >> 6;
-  const int64_t ntile = (M + 15) >> 4;
-  for (int64_t t = (int64_t)blockIdx.x * nw + wave; t < ntile; t += (int64_t)gridDim.x * nw) {
-    const int64_t row = t * 16 + li;
-    const bool rv = row < M;
-    const float *xr = X + (rv ? row : 0) * (int64_t)K;
-    f4 acc[RT];
-#pragma unroll
-    for (int nt = 0; nt < RT; ++nt) acc[nt] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
-    for (int k0 = 0; k0 < Kp; k0 += 16) {
-      const int kk = k0 + 4 * lg;
-      f4 xv = f4{0.f, 0.f, 0.f, 0.f};
-      if (rv && kk < K) xv = *reinterpret_cast<const f4 *>(xr + kk);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const float *brow = lds + (kk + c) * RS + li;
-#pragma unroll
-        for (int nt = 0; nt < RT; ++nt)
-          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[c], brow[nt * 16], acc[nt], 0, 0, 0);
-      }
-    }
-#pragma unroll
-    for (int nt = 0; nt < RT; ++nt) {
-      const int r = nt * 16 + li;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int64_t m = t * 16 + 4 * lg + j;
-        if (m < M && r < R) out[m * R + r] = acc[nt][j];
-      }
-    }
-  }
-}
-
-// =====================================================================================
-// Last-mode contraction, BF16 MFMA (v_mfma_f32_16x16x32_bf16), FP32 accumulation.
-// X is bfloat16 M x K, K % 8 == 0.  Lane (li, lg) loads 8 bf16 X[row li][k0 + 8 lg .. +7]
-// (16 bytes) as its A operand.  The factor is staged transposed in LDS as bf16 rows of k
-// so that each lane reads its 8-k B operand with one 16-byte load.  With SPLIT the factor
-// is carried as hi + lo bf16 parts (hi = bf16(f), lo = bf16(f - hi)) and both are applied,
-// so only the rounding of X remains.
-// =====================================================================================
-template <int RT, bool SPLIT>
-__global__ __launch_bounds__(kTtmThreads) void ttm_last_bf16_k(const uint16_t *__restrict__ X,
-                                                               int64_t M, int K,
-                                                               const float *__restrict__ F,
-                                                               int64_t ldl, int64_t ldr, int R,
-                                                               float *__restrict__ out) {
-  extern __shared__ __attribute__((aligned(16))) uint16_t ldsb[];
-  constexpr int RP = 16 * RT;
-  const int Kp = (K + 31) & ~31;
-  const int KS = Kp + 8;  // 16-byte pad per row
-  uint16_t *hi = ldsb;
-  uint16_t *lo = ldsb + RP * KS;
-  for (int e = threadIdx.x; e < RP * Kp; e += blockDim.x) {
-    const int r = e / Kp, k = e - r * Kp;
-    const float a = (k < K && r < R) ? F[k * ldl + r * ldr] : 0.f;
-    const uint16_t h = f2bf_rne(a);
-    hi[r * KS + k] = h;
-    if (SPLIT) lo[r * KS + k] = f2bf_rne(a - bf2f(h));
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane & 15, lg = lane >> 4;
-  const int nw = blockDim.x >> 6;
-  const int64_t ntile = (M + 15) >> 4;
-  for (int64_t t = (int64_t)blockIdx.x * nw + wave; t < ntile; t += (int64_t)gridDim.x * nw) {
-    const int64_t row = t * 16 + li;
-    const bool rv = row < M;
-    const uint16_t *xr = X + (rv ? row : 0) * (int64_t)K;
-    f4 acc[RT];
-#pragma unroll
-    for (int nt = 0; nt < RT; ++nt) acc[nt] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
-    for (int k0 = 0; k0 < Kp; k0 += 32) {
-      const int kk = k0 + 8 * lg;
-      u4 xv = u4{0u, 0u, 0u, 0u};
-      if (rv && kk < K) xv = *reinterpret_cast<const u4 *>(xr + kk);
-#pragma unroll
-      for (int nt = 0; nt < RT; ++nt) {
-        const int off = (nt * 16 + li) * KS + kk;
-        acc[nt] = mfma_bf16(xv, *reinterpret_cast<const u4 *>(hi + off), acc[nt]);
-        if (SPLIT) acc[nt] = mfma_bf16(xv, *reinterpret_cast<const u4 *>(lo + off), acc[nt]);
-      }
-    }
-#pragma unroll
-    for (int nt = 0; nt < RT; ++nt) {
-      const int r = nt * 16 + li;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int64_t m = t * 16 + 4 * lg + j;
-        if (m < M && r < R) out[m * R + r] = acc[nt][j];
-      }
-    }
-  }
-}
-
-// =====================================================================================
-// Earlier-mode contraction, FP32 MFMA.  X is [P][N][Q], Q % 4 == 0.
-// A wave owns 64 consecutive q of one p.  Lane (li, lg) loads the float4
-// X[p][n0 + lg][q0 + 4 li .. +3] (16 lanes read 256 contiguous bytes of one row n);
-// component c feeds MFMA c, whose output row i stands for q = q0 + 4 i + c.
-// Output rows of lane group lg are then q0 + 16 lg + [0, 16): stored as float4s.
-// =====================================================================================
-template <int RT>
-__global__ __launch_bounds__(kTtmThreads) void ttm_mid_f32_k(const float *__restrict__ X, int64_t P,
-                                                             int N, int64_t Q,
-                                                             const float *__restrict__ F,
-                                                             int64_t ldl, int64_t ldr, int R,
-                                                             float *__restrict__ out) {
-  extern __shared__ __attribute__((aligned(16))) float lds[];
-  constexpr int RP = 16 * RT;
-  constexpr int RS = RP + 4;  // row pad: the four lane groups read rows 4 banks apart
-  const int Np = (N + 3) & ~3;
-  for (int e = threadIdx.x; e < Np * RP; e += blockDim.x) {
-    const int n = e / RP, r = e - n * RP;
-    lds[n * RS + r] = (n < N && r < R) ? F[n * ldl + r * ldr] : 0.f;
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane & 15, lg = lane >> 4;
-  const int nw = blockDim.x >> 6;
-  const int64_t qt = (Q + 63) >> 6;
-  const int64_t ntile = P * qt;
-  for (int64_t t = (int64_t)blockIdx.x * nw + wave; t < ntile; t += (int64_t)gridDim.x * nw) {
-    const int64_t p = t / qt;
-    const int64_t q0 = (t - p * qt) * 64;
-    const int64_t qa = q0 + 4 * li;
-    const bool qv = qa < Q;
-    const float *xp = X + p * (int64_t)N * Q + (qv ? qa : 0);
-    f4 acc[4][RT];
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-      for (int nt = 0; nt < RT; ++nt) acc[c][nt] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
-    for (int n0 = 0; n0 < Np; n0 += 4) {
-      const int n = n0 + lg;
-      f4 xv = f4{0.f, 0.f, 0.f, 0.f};
-      if (qv && n < N) xv = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(xp + (int64_t)n * Q));
-      const float *brow = lds + n * RS + li;
-#pragma unroll
-      for (int nt = 0; nt < RT; ++nt) {
-        const float b = brow[nt * 16];
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-          acc[c][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv[c], b, acc[c][nt], 0, 0, 0);
-      }
-    }
-#pragma unroll
-    for (int nt = 0; nt < RT; ++nt) {
-      const int r = nt * 16 + li;
-      if (r >= R) continue;
-      float *orow = out + (p * R + r) * Q;
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const int64_t q = q0 + 16 * lg + 4 * jj;
-        if (q < Q)
-          *reinterpret_cast<f4 *>(orow + q) =
-              f4{acc[0][nt][jj], acc[1][nt][jj], acc[2][nt][jj], acc[3][nt][jj]};
-      }
-    }
-  }
-}
-
-// =====================================================================================
-// Earlier-mode contraction, BF16 MFMA.  X is bf16 [P][N][Q], Q % 8 == 0.
-// A wave owns 128 consecutive q of one p.  Lane (li, lg) loads eight 16-byte rows
-// X[p][n0 + 8 lg + j][q0 + 8 li .. +7], j = 0..7, i.e. an 8 (n) x 8 (q) block, and
-// transposes it in registers into eight A operands (one per q offset c, each holding the
-// 8 n values of that q).  MFMA c's output row i stands for q = q0 + 8 i + c, so lane group
-// lg ends up owning q0 + 32 lg + [0, 32).
-// =====================================================================================
-template <int RT, bool SPLIT>
-__global__ __launch_bounds__(kTtmThreads) void ttm_mid_bf16_k(const uint16_t *__restrict__ X,
-                                                              int64_t P, int N, int64_t Q,
-                                                              const float *__restrict__ F,
-                                                              int64_t ldl, int64_t ldr, int R,
-                                                              float *__restrict__ out) {
-  extern __shared__ __attribute__((aligned(16))) uint16_t ldsb[];
-  constexpr int RP = 16 * RT;
-  const int Np = (N + 31) & ~31;
-  const int NS = Np + 8;
-  uint16_t *hi = ldsb;
-  uint16_t *lo = ldsb + RP * NS;
-  for (int e = threadIdx.x; e < RP * Np; e += blockDim.x) {
-    const int r = e / Np, n = e - r * Np;
-    const float a = (n < N && r < R) ? F[n * ldl + r * ldr] : 0.f;
-    const uint16_t h = f2bf_rne(a);
-    hi[r * NS + n] = h;
-    if (SPLIT) lo[r * NS + n] = f2bf_rne(a - bf2f(h));
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane & 15, lg = lane >> 4;
-  const int nw = blockDim.x >> 6;
-  const int64_t qt = (Q + 127) >> 7;
-  const int64_t ntile = P * qt;
-  for (int64_t t = (int64_t)blockIdx.x * nw + wave; t < ntile; t += (int64_t)gridDim.x * nw) {
-    const int64_t p = t / qt;
-    const int64_t q0 = (t - p * qt) * 128;
-    const int64_t qa = q0 + 8 * li;
-    const bool qv = qa < Q;
-    const uint16_t *xp = X + p * (int64_t)N * Q + (qv ? qa : 0);
-    f4 acc[8][RT];
-#pragma unroll
-    for (int c = 0; c < 8; ++c)
-#pragma unroll
-      for (int nt = 0; nt < RT; ++nt) acc[c][nt] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int n0 = 0; n0 < Np; n0 += 32) {
-      u4 v[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int n = n0 + 8 * lg + j;
-        v[j] = (qv && n < N) ? __builtin_nontemporal_load(reinterpret_cast<const u4 *>(xp + (int64_t)n * Q))
-                             : u4{0u, 0u, 0u, 0u};
-      }
-      u4 bh[RT], bl[RT];
-#pragma unroll
-      for (int nt = 0; nt < RT; ++nt) {
-        const int off = (nt * 16 + li) * NS + n0 + 8 * lg;
-        bh[nt] = *reinterpret_cast<const u4 *>(hi + off);
-        if (SPLIT) bl[nt] = *reinterpret_cast<const u4 *>(lo + off);
-      }
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        u4 op;
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-          const uint32_t a = v[2 * w][c >> 1], b = v[2 * w + 1][c >> 1];
-          op[w] = (c & 1) ? ((a >> 16) | (b & 0xffff0000u)) : ((a & 0xffffu) | (b << 16));
-        }
-#pragma unroll
-        for (int nt = 0; nt < RT; ++nt) {
-          acc[c][nt] = mfma_bf16(op, bh[nt], acc[c][nt]);
-          if (SPLIT) acc[c][nt] = mfma_bf16(op, bl[nt], acc[c][nt]);
-        }
-      }
-    }
-#pragma unroll
-    for (int nt = 0; nt < RT; ++nt) {
-      const int r = nt * 16 + li;
-      if (r >= R) continue;
-      float *orow = out + (p * R + r) * Q;
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const int64_t q = q0 + 32 * lg + 8 * jj;
-        if (q < Q) {
-          *reinterpret_cast<f4 *>(orow + q) =
-              f4{acc[0][nt][jj], acc[1][nt][jj], acc[2][nt][jj], acc[3][nt][jj]};
-          *reinterpret_cast<f4 *>(orow + q + 4) =
-              f4{acc[4][nt][jj], acc[5][nt][jj], acc[6][nt][jj], acc[7][nt][jj]};
-        }
-      }
-    }
-  }
 }
 
 // =====================================================================================
@@ -367,111 +83,19 @@ static int grid_for(int64_t work, int threads, int cap) {
 
 static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-// Blocks for the streaming MFMA kernels: enough to fill 256 CUs several times while each
-// block still amortises its LDS staging of the factor over many tiles.
-constexpr int kStreamBlocks = 1024;
-
-// Dynamic LDS above 64 KiB must be allowed per kernel (once per larger size).
-static nnc_status allow_big_lds(const void *kern, size_t bytes) {
-  static std::mutex mu;
-  static std::map<const void *, size_t> done;
-  if (bytes <= 64 * 1024) return NNC_OK;
-  std::lock_guard<std::mutex> lk(mu);
-  auto it = done.find(kern);
-  if (it != done.end() && it->second >= bytes) return NNC_OK;
-  NNC_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-  done[kern] = bytes;
-  return NNC_OK;
-}
-
-template <typename... KArgs, typename... Args>
-static nnc_status launch_stream(void (*kern)(KArgs...), size_t lds, int64_t tiles, int reserve,
-                                hipStream_t s, Args... args) {
-  NNC_TRY(allow_big_lds(reinterpret_cast<const void *>(kern), lds));
-  const int waves = kTtmThreads / 64;
-  int grid = grid_for(tiles, waves, kStreamBlocks);
-  // a CU stays free only if the grid fits one block per CU; with more blocks per CU the
-  // dispatcher leaves no CU empty anyway, so the grid is not cut
-  if (reserve > 0 && grid <= device_cu_count()) grid = std::max(1, std::min(grid, device_cu_count() - reserve));
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kTtmThreads), lds, s, static_cast<KArgs>(args)...);
-  return NNC_OK;
-}
-
-// 1: X-streaming contractions use the software-pipelined kernels when the shape allows.
-static int g_use_pipe = 1;
-void set_use_pipe(int on) { g_use_pipe = on; }
-
 nnc_status launch_ttm(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64_t Q, const float *F,
                       int64_t ldl, int64_t ldr, int64_t R, float *out, hipStream_t s,
                       bool allow_mfma, const char **kernel_name, int reserve_cus) {
   const char *name = "ttm_generic";
   const int64_t total_rows = P * N * Q;
   if (total_rows == 0 || R == 0) return NNC_OK;
-  if (allow_mfma && g_use_pipe) {
+  if (allow_mfma) {
     const nnc_status st = launch_pass(X, xdt, P, N, Q, F, ldl, ldr, R, out, s, kernel_name, reserve_cus);
     if (st != NNC_EUNSUPPORTED) return st;
   }
-  const bool small_r = R <= 32;
-  const int RT = R <= 16 ? 1 : 2;
-  bool done = false;
-  if (allow_mfma && small_r && aligned16(X) && aligned16(out) && N <= 2048 && N < (1 << 20)) {
-    if (Q == 1) {
-      // last-mode contraction: X is (P) x (N) with contiguous rows
-      const int64_t M = P;
-      const int K = (int)N;
-      const int64_t tiles = (M + 15) / 16;
-      if (xdt == NNC_F32 && K % 4 == 0) {
-        const int Kp = (K + 15) & ~15;
-        const size_t lds = (size_t)Kp * (16 * RT + 4) * sizeof(float);
-        if (lds <= 96 * 1024) {
-          if (RT == 1)
-            NNC_TRY(launch_stream(ttm_last_f32_k<1>, lds, tiles, reserve_cus, s, X, M, K, F, ldl, ldr, (int)R, out));
-          else
-            NNC_TRY(launch_stream(ttm_last_f32_k<2>, lds, tiles, reserve_cus, s, X, M, K, F, ldl, ldr, (int)R, out));
-          name = "ttm_last_f32";
-          done = true;
-        }
-      } else if (xdt == NNC_BF16 && K % 8 == 0) {
-        const int Kp = (K + 31) & ~31;
-        const size_t lds = (size_t)2 * (16 * RT) * (Kp + 8) * sizeof(uint16_t);
-        if (lds <= 96 * 1024) {
-          if (RT == 1)
-            NNC_TRY(launch_stream(ttm_last_bf16_k<1, true>, lds, tiles, reserve_cus, s, X, M, K, F, ldl, ldr, (int)R, out));
-          else
-            NNC_TRY(launch_stream(ttm_last_bf16_k<2, true>, lds, tiles, reserve_cus, s, X, M, K, F, ldl, ldr, (int)R, out));
-          name = "ttm_last_bf16";
-          done = true;
-        }
-      }
-    } else {
-      if (xdt == NNC_F32 && Q % 4 == 0) {
-        const int Np = ((int)N + 3) & ~3;
-        const size_t lds = (size_t)Np * (16 * RT + 4) * sizeof(float);
-        const int64_t tiles = P * ((Q + 63) / 64);
-        if (lds <= 96 * 1024) {
-          if (RT == 1)
-            NNC_TRY(launch_stream(ttm_mid_f32_k<1>, lds, tiles, reserve_cus, s, X, P, N, Q, F, ldl, ldr, (int)R, out));
-          else
-            NNC_TRY(launch_stream(ttm_mid_f32_k<2>, lds, tiles, reserve_cus, s, X, P, N, Q, F, ldl, ldr, (int)R, out));
-          name = "ttm_mid_f32";
-          done = true;
-        }
-      } else if (xdt == NNC_BF16 && Q % 8 == 0) {
-        const int Np = ((int)N + 31) & ~31;
-        const size_t lds = (size_t)2 * (16 * RT) * (Np + 8) * sizeof(uint16_t);
-        const int64_t tiles = P * ((Q + 127) / 128);
-        if (lds <= 96 * 1024) {
-          if (RT == 1)
-            NNC_TRY(launch_stream(ttm_mid_bf16_k<1, true>, lds, tiles, reserve_cus, s, X, P, N, Q, F, ldl, ldr, (int)R, out));
-          else
-            NNC_TRY(launch_stream(ttm_mid_bf16_k<2, true>, lds, tiles, reserve_cus, s, X, P, N, Q, F, ldl, ldr, (int)R, out));
-          name = "ttm_mid_bf16";
-          done = true;
-        }
-      }
-    }
-  }
-  if (!done) {
+  // every other shape (rank above 32, unaligned pointers, rows of a length the matrix-core
+  // kernels do not take): one thread per (p, 4 columns r, q)
+  {
     const int64_t work = P * ((R + 3) / 4) * Q;
     const int grid = grid_for(work, 256, 65536);
     if (xdt == NNC_F32)

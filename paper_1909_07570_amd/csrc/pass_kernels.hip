@@ -193,7 +193,8 @@ __global__ __launch_bounds__(64 * kMidWaves) void ttm_mid_lds_k(const uint16_t *
                                                                int64_t P, int N, int64_t Q,
                                                                const float *__restrict__ F,
                                                                int64_t ldl, int64_t ldr, int R,
-                                                               float *__restrict__ out) {
+                                                               float *__restrict__ out, int64_t ldp,
+                                                               int acc_out) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_b[];
   constexpr int RP = 16 * RT;
   const int Np = (N + 31) & ~31;
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(64 * kMidWaves) void ttm_mid_lds_k(const uint16_t *
     const int64_t p = t / qt;
     const int64_t q0 = (t - p * qt) * 128;
     const int64_t qa = q0 + 8 * li;
-    xp = X + p * (int64_t)N * Q + (qa < Q ? qa : Q - 8);
+    xp = X + p * ldp + (qa < Q ? qa : Q - 8);
     nlim = N - 1;
   };
   auto load = [&](u4 (&vv)[8], int s) {
@@ -326,9 +327,16 @@ __global__ __launch_bounds__(64 * kMidWaves) void ttm_mid_lds_k(const uint16_t *
     for (int rr = 0; rr < R; rr += 2) {
       const int r = rr + (lane >> 5);
       const int qq = (lane & 31) * 4;
-      if (r < R && q0 + qq < Q)
-        __builtin_nontemporal_store(*reinterpret_cast<const f4 *>(stg + r * 128 + qq),
-                                    reinterpret_cast<f4 *>(out + (p * R + r) * Q + q0 + qq));
+      if (r < R && q0 + qq < Q) {
+        f4 *o = reinterpret_cast<f4 *>(out + (p * R + r) * Q + q0 + qq);
+        f4 val = *reinterpret_cast<const f4 *>(stg + r * 128 + qq);
+        if (acc_out) {
+          val += *o;  // a later chunk of the contracted index: added in chunk order
+          *o = val;
+        } else {
+          __builtin_nontemporal_store(val, o);
+        }
+      }
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -348,7 +356,8 @@ __global__ __launch_bounds__(64 * kMidWaves) void ttm_mid_lds_f32_k(const float 
                                                                    int64_t P, int N, int64_t Q,
                                                                    const float *__restrict__ F,
                                                                    int64_t ldl, int64_t ldr, int R,
-                                                                   float *__restrict__ out) {
+                                                                   float *__restrict__ out, int64_t ldp,
+                                                                   int acc_out) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_b[];
   constexpr int RP = 16 * RT;
   constexpr int RS = RP + 2;  // factor row stride: the four row groups of a read land on
@@ -369,7 +378,7 @@ __global__ __launch_bounds__(64 * kMidWaves) void ttm_mid_lds_f32_k(const float 
     const int64_t p = t / qt;
     const int64_t q0 = (t - p * qt) * 64;
     const int64_t qa = q0 + 4 * li;
-    xp = X + p * (int64_t)N * Q + (qa < Q ? qa : Q - 4);
+    xp = X + p * ldp + (qa < Q ? qa : Q - 4);
     nlim = N - 1;
   };
   auto load = [&](u4 (&vv)[8], int s) {
@@ -460,9 +469,16 @@ __global__ __launch_bounds__(64 * kMidWaves) void ttm_mid_lds_f32_k(const float 
     for (int rr = 0; rr < R; rr += 4) {  // four rows of 64 columns per instruction
       const int r = rr + (lane >> 4);
       const int qq = (lane & 15) * 4;
-      if (r < R && q0 + qq < Q)
-        __builtin_nontemporal_store(*reinterpret_cast<const f4 *>(stg + r * 64 + qq),
-                                    reinterpret_cast<f4 *>(out + (p * R + r) * Q + q0 + qq));
+      if (r < R && q0 + qq < Q) {
+        f4 *o = reinterpret_cast<f4 *>(out + (p * R + r) * Q + q0 + qq);
+        f4 val = *reinterpret_cast<const f4 *>(stg + r * 64 + qq);
+        if (acc_out) {
+          val += *o;  // a later chunk of the contracted index: added in chunk order
+          *o = val;
+        } else {
+          __builtin_nontemporal_store(val, o);
+        }
+      }
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -492,7 +508,8 @@ template <bool BF, int RT, int CPR, int NB>
 __global__ __launch_bounds__(kLdsThreads) void ttm_last_lds_k(const void *__restrict__ Xv, int64_t M,
                                                               int K, const float *__restrict__ F,
                                                               int64_t ldl, int64_t ldr, int R,
-                                                              float *__restrict__ out) {
+                                                              float *__restrict__ out, int64_t ldx,
+                                                              int acc_out) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_b[];
   constexpr int EPC = BF ? 8 : 4;    // elements per 16-byte chunk
   constexpr int ESZ = BF ? 2 : 4;    // bytes per element
@@ -532,7 +549,7 @@ __global__ __launch_bounds__(kLdsThreads) void ttm_last_lds_k(const void *__rest
       int64_t row = t * 16 + j * RPI + crow;
       row = row < M ? row : M - 1;
       b[j] = __builtin_nontemporal_load(reinterpret_cast<const u4 *>(
-          reinterpret_cast<const char *>(Xv) + (row * (int64_t)K + kc) * ESZ));
+          reinterpret_cast<const char *>(Xv) + (row * ldx + kc) * ESZ));
     }
   };
   auto store_piece = [&](const u4 (&b)[LPI]) {
@@ -588,9 +605,15 @@ __global__ __launch_bounds__(kLdsThreads) void ttm_last_lds_k(const void *__rest
       for (int e0 = 0; e0 < 16 * RP; e0 += 256) {
         const int e = e0 + 4 * lane;
         if (e + 4 <= nfl) {
-          __builtin_nontemporal_store(*reinterpret_cast<const f4 *>(ot + e), reinterpret_cast<f4 *>(dst + e));
+          f4 val = *reinterpret_cast<const f4 *>(ot + e);
+          if (acc_out) {  // a later chunk of the contracted index: added in chunk order
+            val += *reinterpret_cast<const f4 *>(dst + e);
+            *reinterpret_cast<f4 *>(dst + e) = val;
+          } else {
+            __builtin_nontemporal_store(val, reinterpret_cast<f4 *>(dst + e));
+          }
         } else if (e < nfl) {
-          for (int q = e; q < nfl; ++q) dst[q] = ot[q];
+          for (int q = e; q < nfl; ++q) dst[q] = acc_out ? dst[q] + ot[q] : ot[q];
         }
       }
     }
@@ -708,8 +731,6 @@ size_t pass_mid_lds(bool bf, int RT, int64_t N, int64_t R) {
 
 // Row-contiguous last-mode kernel: chunks per piece row (CPR) is the largest of 32, 16, 8
 // whose piece width does not exceed K; the whole LDS (factor + staging) must fit a CU.
-static int g_last_lds = 1;
-void set_last_lds(int on) { g_last_lds = on; }
 constexpr size_t kCuLdsBytes = 160 * 1024;
 
 int device_cu_count() {
@@ -735,7 +756,7 @@ size_t last_lds_bytes(bool bf, int RT, int CPR, int64_t K) {
 
 static nnc_status launch_last_lds(const void *X, bool bf, int64_t M, int64_t K, const float *F,
                                   int64_t ldl, int64_t ldr, int64_t R, float *out, hipStream_t s,
-                                  const char **kernel_name, int reserve) {
+                                  const char **kernel_name, int reserve, int64_t ldx, int acc_out) {
   const int EPC = bf ? 8 : 4;
   if (K % EPC || K > (1 << 20) || K < 8 * EPC) return NNC_EUNSUPPORTED;
   const int CPR = K >= 32 * EPC ? 32 : (K >= 16 * EPC ? 16 : 8);
@@ -753,7 +774,7 @@ static nnc_status launch_last_lds(const void *X, bool bf, int64_t M, int64_t K, 
     constexpr int NBV = 1;                                                                        \
     NNC_TRY(allow_lds_bytes(reinterpret_cast<const void *>(ttm_last_lds_k<BFV, RTV, CPRV, NBV>), lds)); \
     hipLaunchKernelGGL((ttm_last_lds_k<BFV, RTV, CPRV, NBV>), dim3(grid), dim3(kLdsThreads), lds, s, X, \
-                       M, (int)K, F, ldl, ldr, (int)R, out);                                      \
+                       M, (int)K, F, ldl, ldr, (int)R, out, ldx, acc_out);                        \
   } while (0)
 #define NNC_LL_CPR(BFV, RTV)           \
   do {                                 \
@@ -780,7 +801,9 @@ static nnc_status launch_last_lds(const void *X, bool bf, int64_t M, int64_t K, 
 }
 
 // Returns NNC_EUNSUPPORTED (without recording an error) when the shape does not suit the
-// pipelined kernels, so the caller can fall back.
+// pipelined kernels, so the caller can fall back.  A contracted index too long for the
+// factor to fit in LDS is split into chunks, each a launch on its slab of X (with X's own
+// strides) whose output is added to the previous chunks' in chunk order.
 nnc_status launch_pass(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64_t Q, const float *F,
                        int64_t ldl, int64_t ldr, int64_t R, float *out, hipStream_t s,
                        const char **kernel_name, int reserve_cus) {
@@ -788,16 +811,37 @@ nnc_status launch_pass(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64
   if ((reinterpret_cast<uintptr_t>(X) & 15u) || (reinterpret_cast<uintptr_t>(out) & 15u))
     return NNC_EUNSUPPORTED;
   const bool bf = xdt == NNC_BF16;
+  const int esz = bf ? 2 : 4;
   const int RT = R <= 16 ? 1 : 2;
   const int waves = kPassThreads / 64;
-  if (Q == 1 && g_last_lds) {
-    const nnc_status st = launch_last_lds(X, bf, P, N, F, ldl, ldr, R, out, s, kernel_name, reserve_cus);
-    if (st != NNC_EUNSUPPORTED) return st;
-  }
   if (Q == 1) {
+    if (N > (1 << 20)) return NNC_EUNSUPPORTED;
+    nnc_status st = launch_last_lds(X, bf, P, N, F, ldl, ldr, R, out, s, kernel_name, reserve_cus, N, 0);
+    if (st != NNC_EUNSUPPORTED) return st;
+    const int EPC = bf ? 8 : 4, KC = 32 * EPC;
+    if (N % EPC == 0 && N >= 8 * EPC && last_lds_bytes(bf, RT, 32, KC) <= kCuLdsBytes) {
+      // chunks of Kc (a multiple of the 32-chunk piece width, so every slab starts 16-byte
+      // aligned), the last one long enough for the kernel's pieces
+      int64_t Kmax = KC;
+      while (last_lds_bytes(bf, RT, 32, Kmax + KC) <= kCuLdsBytes) Kmax += KC;
+      int64_t Kc = Kmax, nch = 1;
+      for (; Kc >= KC; Kc -= KC) {
+        nch = (N + Kc - 1) / Kc;
+        if (N - (nch - 1) * Kc >= 8 * EPC) break;
+      }
+      if (Kc >= KC) {
+        for (int64_t c = 0; c < nch; ++c) {
+          const int64_t k0 = c * Kc, kc = std::min(Kc, N - k0);
+          NNC_TRY(launch_last_lds(static_cast<const char *>(X) + k0 * esz, bf, P, kc, F + k0 * ldl, ldl, ldr, R,
+                                  out, s, nullptr, reserve_cus, N, c > 0));
+        }
+        if (kernel_name) *kernel_name = bf ? "ttm_last_lds_bf16 (chunked)" : "ttm_last_lds_f32 (chunked)";
+        return NNC_OK;
+      }
+    }
     if (N % (bf ? 8 : 4)) return NNC_EUNSUPPORTED;
     const size_t lds = pass_last_lds(bf, RT, N);
-    if (lds > kPassLdsMax || N > (1 << 20)) return NNC_EUNSUPPORTED;
+    if (lds > kPassLdsMax) return NNC_EUNSUPPORTED;
     const int64_t tiles = (P + 15) / 16;
     const int grid = (int)std::min<int64_t>(std::max<int64_t>((tiles + waves - 1) / waves, 1), kPassBlocks);
 #define NNC_LAST(BFV, RTV)                                                                        \
@@ -815,31 +859,46 @@ nnc_status launch_pass(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64
   } else {
     // earlier mode: ttm_mid_lds_k (bf16 X) / ttm_mid_lds_f32_k (FP32 X)
     if (Q % (bf ? 8 : 4)) return NNC_EUNSUPPORTED;
-    if (N * ldl + R * ldr >= ((int64_t)1 << 31)) return NNC_EUNSUPPORTED;  // 32-bit factor indexing
-    const size_t lds = pass_mid_lds(bf, RT, N, R);
-    if (lds > kCuLdsBytes || N > (1 << 20)) return NNC_EUNSUPPORTED;
+    if (N > (1 << 20) || N * ldl + R * ldr >= ((int64_t)1 << 31)) return NNC_EUNSUPPORTED;  // 32-bit factor indexing
+    // rows of the factor per launch: all of them, or chunks of a multiple of 32
+    int64_t Nc = N;
+    if (pass_mid_lds(bf, RT, N, R) > kCuLdsBytes) {
+      int64_t Nmax = 0;
+      while (pass_mid_lds(bf, RT, Nmax + 32, R) <= kCuLdsBytes) Nmax += 32;
+      if (Nmax == 0) return NNC_EUNSUPPORTED;
+      const int64_t nch = (N + Nmax - 1) / Nmax;
+      Nc = ((N + nch - 1) / nch + 31) / 32 * 32;
+    }
+    const size_t lds = pass_mid_lds(bf, RT, Nc, R);
     const int64_t tiles = P * ((Q + (bf ? 127 : 63)) / (bf ? 128 : 64));
     int grid = (int)std::min<int64_t>((tiles + kMidWaves - 1) / kMidWaves, device_cu_count());
     if (grid < 1) grid = 1;
-#define NNC_MID(KERN)                                                                             \
-  do {                                                                                            \
-    NNC_TRY(allow_lds_bytes(reinterpret_cast<const void *>(KERN), lds));                          \
-    hipLaunchKernelGGL(KERN, dim3(grid), dim3(64 * kMidWaves), lds, s, XARG, P, (int)N, Q, F, ldl, \
-                       ldr, (int)R, out);                                                         \
+    for (int64_t n0 = 0; n0 < N; n0 += Nc) {
+      const int64_t nc = std::min(Nc, N - n0);
+      const void *Xc = static_cast<const char *>(X) + n0 * Q * esz;
+      const float *Fc = F + n0 * ldl;
+      const int acc = n0 > 0;
+#define NNC_MID(KERN)                                                                                \
+  do {                                                                                               \
+    NNC_TRY(allow_lds_bytes(reinterpret_cast<const void *>(KERN), lds));                             \
+    hipLaunchKernelGGL(KERN, dim3(grid), dim3(64 * kMidWaves), lds, s, XARG, P, (int)nc, Q, Fc, ldl, \
+                       ldr, (int)R, out, N * Q, acc);                                                \
   } while (0)
-    if (bf) {
-#define XARG (const uint16_t *)X
-      if (RT == 1) NNC_MID(ttm_mid_lds_k<1>);
-      else NNC_MID(ttm_mid_lds_k<2>);
+      if (bf) {
+#define XARG (const uint16_t *)Xc
+        if (RT == 1) NNC_MID(ttm_mid_lds_k<1>);
+        else NNC_MID(ttm_mid_lds_k<2>);
 #undef XARG
-    } else {
-#define XARG (const float *)X
-      if (RT == 1) NNC_MID((ttm_mid_lds_f32_k<1, kMidDepthF32>));
-      else NNC_MID((ttm_mid_lds_f32_k<2, kMidDepthF32>));
+      } else {
+#define XARG (const float *)Xc
+        if (RT == 1) NNC_MID((ttm_mid_lds_f32_k<1, kMidDepthF32>));
+        else NNC_MID((ttm_mid_lds_f32_k<2, kMidDepthF32>));
 #undef XARG
-    }
+      }
 #undef NNC_MID
-    if (kernel_name) *kernel_name = bf ? "ttm_mid_bf16" : "ttm_mid_f32";
+    }
+    if (kernel_name)
+      *kernel_name = Nc < N ? (bf ? "ttm_mid_bf16 (chunked)" : "ttm_mid_f32 (chunked)") : (bf ? "ttm_mid_bf16" : "ttm_mid_f32");
   }
   NNC_HIP(hipGetLastError());
   return NNC_OK;
