@@ -533,6 +533,8 @@ def extra_workloads(args, nnc, dev):
     rks = [2 + (j % 15) for j in range(64)]
     Bs = [[torch.from_numpy(b).to(dev) for b in synth.init_cp_factors(seed, ranks, r, restart=j)]
           for j, r in enumerate(rks)]
+    nnc.nncp_fit_batched(G, rks, 1, [[b.clone() for b in bs] for bs in Bs])  # tunes (or reads the cache)
+    tune = nnc.last_tune()
     elb, res = timed(lambda: nnc.nncp_fit_batched(G, rks, 300, Bs))
     Gt = torch.from_numpy(synth.init_core(seed, ranks)).to(dev)
     At = [a.clone() for a in A5]
@@ -543,10 +545,32 @@ def extra_workloads(args, nnc, dev):
                     "300 sweeps; 64 nnCP restarts of the 8^5 core (ranks 2..16), 300 sweeps each, one launch",
         "sweeps_per_s": round(300 / el, 1), "tucker_rel": nnc.reconstruct_residual(X, A, G),
         "batched_nncp_ms": round(elb * 1e3, 3), "best_restart_rel": float(min(res)),
+        "batched_nncp_launch": tune,
         "passes": pass_roofline(times, size * 4 + size // 64 * 8 * 4, size * 4 + size // 64 * 8 * 4,
                                 ("pass1_x_x4", "pass2_x_x0"))}
     log("c5: %s" % json.dumps(out["c5_64x5"]))
     del X, ws
+
+    # ---- X passes over modes longer than one launch's factor in LDS (chunked contracted index)
+    longm = {}
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(11)
+    for shape, mode in (((1024, 512, 512), 0), ((512, 512, 1024), 2)):
+        X = torch.rand(shape, generator=gen, device=dev)
+        Fm = torch.rand((shape[mode], 20), generator=gen, device=dev)
+        for form, Xt, esz in (("bf16", nnc.nnc_convert_f32_bf16(X), 2), ("fp32", X, 4)):
+            o_t = nnc.nnc_ttm(Xt, mode, Fm)
+            timed(lambda: nnc.nnc_ttm(Xt, mode, Fm, o_t), 3)
+            el, _ = timed(lambda: nnc.nnc_ttm(Xt, mode, Fm, o_t), 10)
+            b = X.numel() * esz + o_t.numel() * 4
+            longm["%dx%dx%d_mode%d_%s" % (shape + (mode, form))] = {
+                "kernel": nnc.last_ttm_kernel(), "avg_us": round(el * 1e6, 2), "alg_bytes": b,
+                "GB/s": round(b / el / 1e9, 1), "frac": round(b / el / 1e9 / HBM_PEAK_GBS, 4),
+                "note": "back-to-back launches timed with host clocks around a synchronize"}
+            del o_t
+        del X
+    out["long_mode_passes"] = longm
+    log("long modes: %s" % json.dumps(longm))
 
     # ---- real-valued CANDELINC, 512^3 signed planted rank-20 CP: Tucker 20^3 by alternating
     # least squares (25 sweeps), CP rank 20 of the core by alternating least squares (300), lift

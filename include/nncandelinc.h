@@ -258,6 +258,16 @@ nnc_status nncp_fit_batched(const float *core, int ndim, const int64_t *core_dim
                             double *rel_residuals, int threads_per_fit, void *workspace,
                             size_t workspace_bytes, void *stream);
 
+/* The launch configuration the calling thread's last nncp_fit_batched used, as a JSON
+ * object: {"threads": T, "t_global": 0|1, "lpt": 0|1, "ms": x, "source": "measured" | "cache"
+ * | "caller"} -- threads per fit, the tensor read from global memory instead of LDS, the
+ * fits ordered by descending rank, the tuner's timing of a few sweeps, and where the choice
+ * came from.  The tuner (threads_per_fit = 0) times each candidate once per (device, core
+ * shape, rank multiset) and keeps the choice in a JSON-lines file: $NNC_TUNE_CACHE, else
+ * $XDG_CACHE_HOME/nncandelinc/tune.json, else ~/.cache/nncandelinc/tune.json; "off" keeps
+ * it in the process only.  A static thread-local string, never NULL. */
+const char *nnc_last_tune(void);
+
 /*
  * Nonnegative CP of the data tensor itself (the nnCPD step of Algorithm 2, which runs it on
  * X and then factors each CP factor by NMF), exactly `iters` sweeps of the multiplicative

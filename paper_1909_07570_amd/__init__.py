@@ -61,7 +61,8 @@ EXPORTED = ["nnc_last_error", "nnc_device_ok", "nnc_set_timing", "nnc_ttm", "nnc
             "nmf_batched_workspace_bytes", "nmf_fit_batched", "nncandelinc_restart_init_floats",
             "nncandelinc_restarts", "nnc_mean_congruence", "nnc_fill_uniform", "nnc_fill_uniform_f64",
             "nncp_noalloc_max_scratch_bytes", "nncp_fit_noalloc", "tucker_ls_workspace_bytes",
-            "tucker_ls_fit", "cp_ls_workspace_bytes", "cp_ls_fit", "nnc_last_pass_times", "nnc_last_ttm_kernel"]
+            "tucker_ls_fit", "cp_ls_workspace_bytes", "cp_ls_fit", "nnc_last_pass_times", "nnc_last_ttm_kernel",
+            "nnc_last_tune"]
 
 _lib = None
 
@@ -80,6 +81,8 @@ def lib():
         L.nnc_last_pass_times.restype = None
         L.nnc_last_ttm_kernel.argtypes = []
         L.nnc_last_ttm_kernel.restype = ctypes.c_char_p
+        L.nnc_last_tune.argtypes = []
+        L.nnc_last_tune.restype = ctypes.c_char_p
         L.nnc_ttm.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _i64p, ctypes.c_int, _vp, _i64, _vp, _vp]
         L.nnc_convert_f32_bf16.argtypes = [_vp, _vp, _i64, _vp]
         L.nnc_fill_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint64, _vp, _i64, _vp]
@@ -137,7 +140,7 @@ def lib():
                                     _vpp, _dp, _vp, ctypes.c_size_t, _vp]
         for name in EXPORTED:
             if name not in ("nnc_last_error", "nnc_device_ok", "nnc_set_timing", "nnc_last_pass_times",
-                            "nnc_last_ttm_kernel") and \
+                            "nnc_last_ttm_kernel", "nnc_last_tune") and \
                     not name.endswith("_bytes") and not name.endswith("_floats"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -190,6 +193,12 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 def set_timing(on: bool) -> None:
     lib().nnc_set_timing(1 if on else 0)
+
+
+def last_tune() -> dict:
+    """The launch configuration of this thread's last nncp_fit_batched."""
+    import json
+    return json.loads(lib().nnc_last_tune().decode())
 
 
 def last_ttm_kernel() -> str:

@@ -16,6 +16,8 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <sys/stat.h>
+#include <unistd.h>
 
 #include <algorithm>
 #include <chrono>
@@ -1383,7 +1385,7 @@ static CpProblem cp_problem(int ndim, const int64_t *core_dims) {
 // contraction scratch (used when it does not fit in LDS) and, for the batched entry point,
 // the tuner's scratch factors and their pointer table.
 struct CpWs {
-  size_t oRank, oPtr, oRes, oClip, oZ, oTune, oTunePtr, total;
+  size_t oRank, oPtr, oRes, oClip, oZ, oTune, oTunePtr, oTuneRank, total;
 };
 
 static CpWs cp_ws(const CpProblem &pb, int nbatch, const int *ranks, bool tune) {
@@ -1402,6 +1404,7 @@ static CpWs cp_ws(const CpProblem &pb, int nbatch, const int *ranks, bool tune) 
   w.oZ = L.take(sizeof(float) * (size_t)(nbatch * nncp_zscratch_floats(pb, maxr)));
   w.oTune = L.take(tune ? sizeof(float) * (size_t)facs : 0);
   w.oTunePtr = L.take(tune ? sizeof(float *) * (size_t)nbatch * pb.d : 0);
+  w.oTuneRank = L.take(tune ? sizeof(int) * (size_t)nbatch : 0);
   w.total = L.off;
   return w;
 }
@@ -1799,67 +1802,199 @@ nnc_status nnc_mean_congruence(int ndim, const int64_t *dims, int rank, const fl
 
 // ---- tuner for the batched launch: threads per fit, timed on scratch factors, cached per
 // (core shape, rank multiset) for the life of the process.
+// ------------------------------------------------------------------ batched nnCP tuner
+// A launch configuration of the batched nnCP: threads per fit, the tensor read from global
+// memory instead of LDS, and the fits ordered by descending rank (longest first, which
+// shortens the tail when there are more fits than compute units).  The tuner times every
+// candidate on scratch factors for a few sweeps and keeps the fastest; choices persist in a
+// JSON-lines file keyed by (device, core shape, rank multiset): $NNC_TUNE_CACHE, else
+// $XDG_CACHE_HOME/nncandelinc/tune.json, else ~/.cache/nncandelinc/tune.json ("off"
+// disables the file; the in-process cache remains).
+struct TuneChoice {
+  int threads = 0;
+  int t_global = 0;
+  int lpt = 0;
+  double ms = 0.0;
+};
+
 static std::mutex g_tune_mu;
-static std::map<std::string, int> g_tune_cache;
+static std::map<std::string, TuneChoice> g_tune_cache;
+static std::string g_tune_file_read = "\x01";  // the cache file last read (none yet)
+static thread_local std::string g_last_tune = "{}";
+
+static std::string tune_file() {
+  const char *e = getenv("NNC_TUNE_CACHE");
+  if (e && *e) return strcmp(e, "off") == 0 ? std::string() : std::string(e);
+  const char *x = getenv("XDG_CACHE_HOME");
+  if (x && *x) return std::string(x) + "/nncandelinc/tune.json";
+  const char *h = getenv("HOME");
+  if (h && *h) return std::string(h) + "/.cache/nncandelinc/tune.json";
+  return std::string();
+}
+
+static std::string device_tag() {
+  int dev = 0;
+  hipDeviceProp_t pr;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&pr, dev) != hipSuccess) return "unknown";
+  std::string arch(pr.gcnArchName);
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch.resize(colon);
+  return arch + "/" + std::to_string(pr.multiProcessorCount) + "cu";
+}
 
 static std::string tune_key(const CpProblem &pb, int nbatch, const int *ranks) {
-  std::string k = std::to_string(pb.d);
-  for (int i = 0; i < pb.d; ++i) k += "x" + std::to_string(pb.dims[i]);
+  std::string k = device_tag() + "|";
+  for (int i = 0; i < pb.d; ++i) k += (i ? "x" : "") + std::to_string(pb.dims[i]);
+  k += "|";
   std::vector<int> rs(ranks, ranks + nbatch);
   std::sort(rs.begin(), rs.end());
-  for (int r : rs) k += "," + std::to_string(r);
+  for (size_t i = 0; i < rs.size(); ++i) k += (i ? "," : "") + std::to_string(rs[i]);
   return k;
 }
 
-static nnc_status tune_threads(const float *core, const CpProblem &pb, int nbatch, const int *ranks,
+// One JSON object per line: {"key": "...", "threads": T, "t_global": 0, "lpt": 0, "ms": x}
+static bool json_int(const std::string &line, const char *name, int *v) {
+  const std::string pat = std::string("\"") + name + "\":";
+  const size_t p = line.find(pat);
+  if (p == std::string::npos) return false;
+  *v = atoi(line.c_str() + p + pat.size());
+  return true;
+}
+
+// Reads the cache file when its path differs from the one read last (entries already in the
+// process are kept; the file's win for equal keys).
+static void tune_file_load() {
+  const std::string path = tune_file();
+  if (path == g_tune_file_read) return;
+  g_tune_file_read = path;
+  if (path.empty()) return;
+  FILE *f = fopen(path.c_str(), "r");
+  if (!f) return;
+  char buf[4096];
+  while (fgets(buf, sizeof buf, f)) {
+    const std::string line(buf);
+    const size_t k0 = line.find("\"key\": \"");
+    if (k0 == std::string::npos) continue;
+    const size_t ks = k0 + 8, ke = line.find('"', ks);
+    if (ke == std::string::npos) continue;
+    TuneChoice c;
+    if (!json_int(line, "threads", &c.threads) || !json_int(line, "t_global", &c.t_global) ||
+        !json_int(line, "lpt", &c.lpt))
+      continue;
+    if (c.threads < 64 || c.threads > 1024 || c.threads % 64) continue;
+    g_tune_cache[line.substr(ks, ke - ks)] = c;
+  }
+  fclose(f);
+}
+
+static void tune_file_store() {
+  const std::string path = tune_file();
+  if (path.empty()) return;
+  for (size_t p = path.find('/', 1); p != std::string::npos; p = path.find('/', p + 1))
+    (void)mkdir(path.substr(0, p).c_str(), 0755);
+  const std::string tmp = path + ".tmp" + std::to_string((long long)getpid());
+  FILE *f = fopen(tmp.c_str(), "w");
+  if (!f) return;
+  for (const auto &kv : g_tune_cache)
+    fprintf(f, "{\"key\": \"%s\", \"threads\": %d, \"t_global\": %d, \"lpt\": %d, \"ms\": %.4f}\n",
+            kv.first.c_str(), kv.second.threads, kv.second.t_global, kv.second.lpt, kv.second.ms);
+  const bool ok = fclose(f) == 0;
+  if (ok)
+    (void)rename(tmp.c_str(), path.c_str());
+  else
+    (void)remove(tmp.c_str());
+}
+
+static void note_tune(const TuneChoice &c, const char *source) {
+  char buf[160];
+  snprintf(buf, sizeof buf, "{\"threads\": %d, \"t_global\": %d, \"lpt\": %d, \"ms\": %.4f, \"source\": \"%s\"}",
+           c.threads, c.t_global, c.lpt, c.ms, source);
+  g_last_tune = buf;
+}
+
+// The order of the fits under a choice: as given, or by descending rank (stable).
+static std::vector<int> fit_order(int nbatch, const int *ranks, bool lpt) {
+  std::vector<int> o(nbatch);
+  for (int j = 0; j < nbatch; ++j) o[j] = j;
+  if (lpt) std::stable_sort(o.begin(), o.end(), [&](int a, int b) { return ranks[a] > ranks[b]; });
+  return o;
+}
+
+static nnc_status tune_batched(const float *core, const CpProblem &pb, int nbatch, const int *ranks,
                                int maxr, const CpWs &w, char *base, int iters, hipStream_t s,
-                               int *best) {
+                               TuneChoice *best) {
   const std::string key = tune_key(pb, nbatch, ranks);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_file_load();
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
       *best = it->second;
+      note_tune(*best, "cache");
       return NNC_OK;
     }
   }
-  // scratch factors (constant 0.5) and their pointer table
-  std::vector<float *> ptrs((size_t)nbatch * pb.d);
-  float *fbase = (float *)(base + w.oTune);
-  int64_t off = 0;
-  for (int j = 0; j < nbatch; ++j)
-    for (int k = 0; k < pb.d; ++k) {
-      ptrs[(size_t)j * pb.d + k] = fbase + off;
-      off += pb.dims[k] * ranks[j];
-    }
-  NNC_HIP(hipMemcpy(base + w.oTunePtr, ptrs.data(), sizeof(float *) * ptrs.size(), hipMemcpyHostToDevice));
   hipEvent_t e0, e1;
   NNC_HIP(hipEventCreate(&e0));
   NNC_HIP(hipEventCreate(&e1));
   const int titers = std::max(1, std::min(iters, 10));
-  float best_ms = 1e30f;
-  int best_t = nncp_default_threads(pb, maxr);
-  for (int t : {256, 512, 1024}) {
-    if (nncp_lds_bytes(pb, maxr, t) > 150 * 1024) continue;
-    NNC_TRY(launch_fill_f32(fbase, off, 0.5f, s));
-    NNC_HIP(hipEventRecord(e0, s));
-    NNC_TRY(launch_nncp(core, pb, nbatch, (const int *)(base + w.oRank), maxr,
-                        (float *const *)(base + w.oTunePtr), nullptr, titers, 1e-12, nullptr,
-                        (unsigned long long *)(base + w.oClip), (float *)(base + w.oZ), t, s));
-    NNC_HIP(hipEventRecord(e1, s));
-    NNC_HIP(hipEventSynchronize(e1));
-    float ms = 0.f;
-    NNC_HIP(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best_ms) {
-      best_ms = ms;
-      best_t = t;
+  TuneChoice b;
+  b.ms = 1e30;
+  const bool lpt_matters = nbatch > device_cu_count();
+  nnc_status st = NNC_OK;
+  for (int lpt = 0; lpt <= (lpt_matters ? 1 : 0) && st == NNC_OK; ++lpt) {
+    // scratch factors (constant 0.5) and the rank / pointer tables in this order
+    const std::vector<int> ord = fit_order(nbatch, ranks, lpt != 0);
+    std::vector<int> rk(nbatch);
+    std::vector<float *> ptrs((size_t)nbatch * pb.d);
+    float *fbase = (float *)(base + w.oTune);
+    int64_t off = 0;
+    for (int i = 0; i < nbatch; ++i) {
+      rk[i] = ranks[ord[i]];
+      for (int k = 0; k < pb.d; ++k) {
+        ptrs[(size_t)i * pb.d + k] = fbase + off;
+        off += pb.dims[k] * rk[i];
+      }
+    }
+    NNC_HIP(hipMemcpy(base + w.oTunePtr, ptrs.data(), sizeof(float *) * ptrs.size(), hipMemcpyHostToDevice));
+    NNC_HIP(hipMemcpy(base + w.oTuneRank, rk.data(), sizeof(int) * nbatch, hipMemcpyHostToDevice));
+    for (int tg = 0; tg <= 1 && st == NNC_OK; ++tg) {
+      // reading the tensor from global memory is a distinct layout only when it fits in LDS
+      if (tg && nncp_lds_bytes(pb, maxr, 256, false, true) == nncp_lds_bytes(pb, maxr, 256, false, false)) continue;
+      for (int t : {256, 512, 1024}) {
+        if (nncp_lds_bytes(pb, maxr, t, false, tg != 0) > 150 * 1024) continue;
+        st = launch_fill_f32(fbase, off, 0.5f, s);
+        if (st != NNC_OK) break;
+        NNC_HIP(hipEventRecord(e0, s));
+        st = launch_nncp(core, pb, nbatch, (const int *)(base + w.oTuneRank), maxr,
+                         (float *const *)(base + w.oTunePtr), nullptr, titers, 1e-12, nullptr,
+                         (unsigned long long *)(base + w.oClip), (float *)(base + w.oZ), t, s, false, tg != 0);
+        if (st != NNC_OK) break;
+        NNC_HIP(hipEventRecord(e1, s));
+        NNC_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        NNC_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < b.ms) {
+          b.ms = ms;
+          b.threads = t;
+          b.t_global = tg;
+          b.lpt = lpt;
+        }
+      }
     }
   }
-  NNC_HIP(hipEventDestroy(e0));
-  NNC_HIP(hipEventDestroy(e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  NNC_TRY(st);
+  if (b.threads == 0) {
+    b.threads = nncp_default_threads(pb, maxr);
+    b.ms = 0.0;
+  }
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune_cache[key] = best_t;
-  *best = best_t;
+  g_tune_cache[key] = b;
+  tune_file_store();
+  *best = b;
+  note_tune(b, "measured");
   return NNC_OK;
 }
 
@@ -1888,13 +2023,25 @@ nnc_status nncp_fit_batched(const float *core, int ndim, const int64_t *core_dim
                 w.total);
   hipStream_t s = (hipStream_t)stream;
   char *base = (char *)workspace;
-  // The tables are copied synchronously: the host arrays need only live for the call.
   NNC_HIP(hipStreamSynchronize(s));
-  NNC_HIP(hipMemcpy(base + w.oRank, ranks, sizeof(int) * nbatch, hipMemcpyHostToDevice));
-  NNC_HIP(hipMemcpy(base + w.oPtr, cp_factors, sizeof(float *) * (size_t)nbatch * ndim,
-                    hipMemcpyHostToDevice));
-  int threads = threads_per_fit;
-  if (threads == 0) NNC_TRY(tune_threads(core, pb, nbatch, ranks, maxr, w, base, iters, s, &threads));
+  TuneChoice tc;
+  tc.threads = threads_per_fit;
+  if (tc.threads == 0)
+    NNC_TRY(tune_batched(core, pb, nbatch, ranks, maxr, w, base, iters, s, &tc));
+  else
+    note_tune(tc, "caller");
+  // The tables are copied synchronously (the host arrays need only live for the call), in
+  // the chosen order of the fits.
+  const std::vector<int> ord = fit_order(nbatch, ranks, tc.lpt != 0);
+  std::vector<int> rk(nbatch);
+  std::vector<float *> fp((size_t)nbatch * ndim);
+  for (int i = 0; i < nbatch; ++i) {
+    rk[i] = ranks[ord[i]];
+    for (int k = 0; k < ndim; ++k) fp[(size_t)i * ndim + k] = cp_factors[(size_t)ord[i] * ndim + k];
+  }
+  NNC_HIP(hipMemcpy(base + w.oRank, rk.data(), sizeof(int) * nbatch, hipMemcpyHostToDevice));
+  NNC_HIP(hipMemcpy(base + w.oPtr, fp.data(), sizeof(float *) * (size_t)nbatch * ndim, hipMemcpyHostToDevice));
+  const int threads = tc.threads;
   // One graph: clear the clip counter, then the single persistent launch of every fit.
   hipStream_t cs = s;
   if (!s) {
@@ -1909,7 +2056,8 @@ nnc_status nncp_fit_batched(const float *core, int ndim, const int64_t *core_dim
   if (st == NNC_OK)
     st = launch_nncp(core, pb, nbatch, (const int *)(base + w.oRank), maxr, (float *const *)(base + w.oPtr),
                      nullptr, iters, eps > 0 ? eps : 1e-12, (double *)(base + w.oRes),
-                     (unsigned long long *)(base + w.oClip), (float *)(base + w.oZ), threads, cs);
+                     (unsigned long long *)(base + w.oClip), (float *)(base + w.oZ), threads, cs, false,
+                     tc.t_global != 0);
   hipError_t ec = hipStreamEndCapture(cs, &g);
   if (st != NNC_OK) {
     if (g) (void)hipGraphDestroy(g);
@@ -1918,14 +2066,18 @@ nnc_status nncp_fit_batched(const float *core, int ndim, const int64_t *core_dim
   if (ec != hipSuccess) return fail(NNC_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
   NNC_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
   NNC_HIP(hipGraphLaunch(ge, cs));
-  NNC_HIP(hipMemcpyAsync(rel_residuals, base + w.oRes, sizeof(double) * nbatch, hipMemcpyDeviceToHost, cs));
+  std::vector<double> res(nbatch);
+  NNC_HIP(hipMemcpyAsync(res.data(), base + w.oRes, sizeof(double) * nbatch, hipMemcpyDeviceToHost, cs));
   NNC_HIP(hipStreamSynchronize(cs));
   NNC_HIP(hipGraphExecDestroy(ge));
   NNC_HIP(hipGraphDestroy(g));
+  for (int i = 0; i < nbatch; ++i) rel_residuals[ord[i]] = res[i];
   for (int j = 0; j < nbatch; ++j)
     if (!std::isfinite(rel_residuals[j])) return fail(NNC_ENUMERIC, "non-finite residual of fit %d", j);
   return NNC_OK;
 }
+
+const char *nnc_last_tune(void) { return g_last_tune.c_str(); }
 
 nnc_status nncandelinc_lift(int ndim, const int64_t *dims, const int64_t *multirank, int rank,
                             const float *const *tucker_factors, const float *const *cp_factors,

@@ -413,11 +413,12 @@ struct CpLayout {
 };
 
 // Keep T in LDS when possible (it is read every stage), then Z.
-static CpLayout cp_layout(const CpProblem &pb, int max_rank, int threads, bool als) {
+static CpLayout cp_layout(const CpProblem &pb, int max_rank, int threads, bool als, bool t_global = false) {
   CpLayout L;
   L.a = make_args(pb);
   const bool opts[4][2] = {{true, true}, {true, false}, {false, true}, {false, false}};
   for (const auto &o : opts) {
+    if (t_global && o[0]) continue;  // the tensor read from global memory (L2) on request
     const int64_t bytes = cp_lds_floats(L.a, max_rank, threads, o[0], o[1], als) * 4;
     if (bytes <= kCpLdsBudget || (!o[0] && !o[1])) {
       L.a.t_lds = o[0];
@@ -429,8 +430,8 @@ static CpLayout cp_layout(const CpProblem &pb, int max_rank, int threads, bool a
   return L;
 }
 
-int64_t nncp_lds_bytes(const CpProblem &pb, int max_rank, int threads, bool als) {
-  return cp_layout(pb, max_rank, threads, als).lds_bytes;
+int64_t nncp_lds_bytes(const CpProblem &pb, int max_rank, int threads, bool als, bool t_global) {
+  return cp_layout(pb, max_rank, threads, als, t_global).lds_bytes;
 }
 
 int64_t nncp_zscratch_floats(const CpProblem &pb, int max_rank) {
@@ -494,10 +495,12 @@ nnc_status nncp_check_shape(const CpProblem &pb, int max_rank, int threads, bool
 nnc_status launch_nncp(const float *T, const CpProblem &pb, int nbatch, const int *d_ranks,
                        int max_rank, float *const *d_factor_ptrs, float *const *single_ptrs,
                        int iters, double eps, double *d_resid, unsigned long long *clips,
-                       float *zscratch, int threads, hipStream_t s, bool als) {
+                       float *zscratch, int threads, hipStream_t s, bool als, bool t_global) {
   NNC_TRY(nncp_check_shape(pb, max_rank, threads, als));
   if (threads <= 0) threads = nncp_default_threads(pb, max_rank);
-  const CpLayout L = cp_layout(pb, max_rank, threads, als);
+  const CpLayout L = cp_layout(pb, max_rank, threads, als, t_global);
+  if (L.lds_bytes > kCpLdsBudget)
+    return fail(NNC_EUNSUPPORTED, "nnCP working set %lld bytes exceeds the LDS budget", (long long)L.lds_bytes);
   if (!L.a.z_lds && !zscratch) return fail(NNC_EWORKSPACE, "nnCP needs Z scratch in the workspace");
   CpPtrs p0;
   for (int k = 0; k < kMaxDim; ++k) p0.p[k] = (single_ptrs && k < pb.d) ? single_ptrs[k] : nullptr;

@@ -196,14 +196,17 @@ struct CpProblem {
 // d_resid (nullable) receives each fit's relative residual.  zscratch: nbatch *
 // nncp_zscratch_floats() floats, used when the contraction temporaries do not fit in LDS.
 // als: least-squares updates B_n <- M_n H_n^{-1} (real CP) instead of the multiplicative
-// ones; `clips` then counts pivots of H_n that were not positive.
+// ones; `clips` then counts pivots of H_n that were not positive.  t_global: the tensor is
+// read from global memory even when it would fit in LDS (a tuner choice).
 nnc_status launch_nncp(const float *T, const CpProblem &pb, int nbatch, const int *d_ranks,
                        int max_rank, float *const *d_factor_ptrs, float *const *single_ptrs,
                        int iters, double eps, double *d_resid, unsigned long long *clips,
-                       float *zscratch, int threads, hipStream_t s, bool als = false);
+                       float *zscratch, int threads, hipStream_t s, bool als = false,
+                       bool t_global = false);
 // Host-side check of a shape for launch_nncp (index ranges, rank, LDS); records the error.
 nnc_status nncp_check_shape(const CpProblem &pb, int max_rank, int threads, bool als = false);
-int64_t nncp_lds_bytes(const CpProblem &pb, int max_rank, int threads, bool als = false);
+int64_t nncp_lds_bytes(const CpProblem &pb, int max_rank, int threads, bool als = false,
+                       bool t_global = false);
 int64_t nncp_zscratch_floats(const CpProblem &pb, int max_rank);
 int nncp_default_threads(const CpProblem &pb, int max_rank);
 

@@ -5,6 +5,10 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# The batched-nnCP tuner keeps its choices in the process only, unless a test points it at a
+# file of its own.
+os.environ.setdefault("NNC_TUNE_CACHE", "off")
+
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an AMD Instinct GPU (gfx950) and the built HIP library")

@@ -373,10 +373,51 @@ def test_batched_nncp_uneven_ranks():
         assert abs(res[j] - oracle.cp_rel_residual(T.astype(np.float64), Bo)) <= 1e-4
         for b, bo in zip(facs[j], Bo):
             assert rel_fro(host(b), bo) <= 1e-3
-    # a batched fit equals the same fit launched alone
+    # a batched fit equals the same fit launched alone with the same threads per fit
+    threads = nnc.last_tune()["threads"]
     single = [dev(b) for b in inits[3]]
-    r1 = nnc.nncp_fit_batched(dev(T), [ranks[3]], 30, [single])
+    r1 = nnc.nncp_fit_batched(dev(T), [ranks[3]], 30, [single], threads_per_fit=threads)
     assert r1[0] == res[3] and all(np.array_equal(host(a), host(b)) for a, b in zip(single, facs[3]))
+
+
+def _device_tag():
+    p = torch.cuda.get_device_properties(0)
+    return "%s/%dcu" % (p.gcnArchName.split(":")[0], p.multi_processor_count)
+
+
+def test_batched_tuner_persists_and_reuses(tmp_path, monkeypatch):
+    """The tuner measures once per (device, core shape, rank multiset), writes its choice to
+    the cache file, reuses it (same results bit for bit), and takes a choice found in a file."""
+    nnc = need_gpu()
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("NNC_TUNE_CACHE", str(path))
+    rng = np.random.default_rng(161)
+    core_dims = (7, 9, 8)
+    T = dev((oracle.cp_full([rng.random((n, 4)) for n in core_dims]) + 1e-3 * rng.random(core_dims)).astype(np.float32))
+    ranks = [3, 5, 5, 9]
+    inits = [synth.init_cp_factors(161, core_dims, r, restart=j) for j, r in enumerate(ranks)]
+    f1 = [[dev(b) for b in B0] for B0 in inits]
+    r1 = nnc.nncp_fit_batched(T, ranks, 20, f1)
+    c1 = nnc.last_tune()
+    assert c1["source"] == "measured" and c1["threads"] in (256, 512, 1024), c1
+    key = "%s|7x9x8|3,5,5,9" % _device_tag()
+    lines = path.read_text().splitlines()
+    assert any(('"key": "%s"' % key) in l and ('"threads": %d' % c1["threads"]) in l for l in lines), lines
+    f2 = [[dev(b) for b in B0] for B0 in inits]
+    r2 = nnc.nncp_fit_batched(T, ranks[::-1], 20, f2[::-1])  # same multiset, other order
+    c2 = nnc.last_tune()
+    assert c2["source"] == "cache" and c2["threads"] == c1["threads"], c2
+    assert r2[::-1] == r1
+    assert all(np.array_equal(host(a), host(b)) for fa, fb in zip(f1, f2) for a, b in zip(fa, fb))
+    # a choice written to another file is picked up when the path changes
+    path2 = tmp_path / "other.json"
+    path2.write_text('{"key": "%s|6x6x6|2,4", "threads": 320, "t_global": 0, "lpt": 0, "ms": 1.0}\n' % _device_tag())
+    monkeypatch.setenv("NNC_TUNE_CACHE", str(path2))
+    T3 = dev(rng.random((6, 6, 6)).astype(np.float32))
+    f3 = [[dev(b) for b in synth.init_cp_factors(162, (6, 6, 6), r, restart=j)] for j, r in enumerate([4, 2])]
+    nnc.nncp_fit_batched(T3, [4, 2], 10, f3)
+    c3 = nnc.last_tune()
+    assert c3["source"] == "cache" and c3["threads"] == 320, c3
 
 
 # ------------------------------------------------------------------------------ adjoint
