@@ -275,7 +275,11 @@ static nnc_status core_chain(const TuckerBufs &b, const float *G, int skip, floa
   for (int k = 0; k < p.d; ++k) {
     if (k == skip) continue;
     float *out = (cnt == total - 1 && dst) ? dst : b.G(cnt % 2);
-    NNC_TRY(ttm_mode(in, NNC_F32, p.d, cur, k, b.S(k), p.R[k], out, s, false));
+    if (p.fast)
+      NNC_TRY(launch_ttm_small(in, prod(cur, 0, k), cur[k], prod(cur, k + 1, p.d), b.S(k), p.R[k], 1, p.R[k],
+                               out, s));
+    else
+      NNC_TRY(ttm_mode(in, NNC_F32, p.d, cur, k, b.S(k), p.R[k], out, s, false));
     in = out;
     ++cnt;
   }
@@ -290,9 +294,27 @@ static nnc_status factor_block(const TuckerBufs &b, int n, const float *Y, const
   const TuckerPlan &p = *b.p;
   const int64_t pre = prod(p.R, 0, n), post = prod(p.R, n + 1, p.d);
   NNC_TRY(launch_contract_except(Y, G, pre, p.N[n], p.R[n], post, b.num(), s));
-  const float *H = nullptr;
-  NNC_TRY(core_chain(b, G, n, nullptr, &H, s));
-  NNC_TRY(launch_contract_except(H, G, pre, p.R[n], p.R[n], post, b.M(), s));
+  if (p.fast && p.gsize <= 16384) {  // M_n by the core step of the fused sweep (every Gram is current)
+    CoreArgsHost h;
+    memset(&h, 0, sizeof h);
+    h.d = p.d;
+    for (int k = 0; k < p.d; ++k) {
+      h.R[k] = p.R[k];
+      h.N[k] = p.N[k];
+      h.S[k] = b.S(k);
+    }
+    h.G = const_cast<float *>(G);
+    h.M = b.M();
+    h.t0 = b.G(0);
+    h.t1 = b.G(1);
+    h.numG = b.G(2);
+    h.next = n;
+    NNC_TRY(launch_core_step(h, s));
+  } else {
+    const float *H = nullptr;
+    NNC_TRY(core_chain(b, G, n, nullptr, &H, s));
+    NNC_TRY(launch_contract_except(H, G, pre, p.R[n], p.R[n], post, b.M(), s));
+  }
   if (grad) {
     NNC_TRY(launch_matmul_small(A, b.M(), p.N[n], p.R[n], p.R[n], b.den(), s));
     NNC_TRY(launch_sub(b.den(), b.num(), grad, p.N[n] * p.R[n], s));
@@ -1334,7 +1356,10 @@ nnc_status nntucker_grad(const void *X, nnc_dtype xdt, int ndim, const int64_t *
     for (int k = 0; k < d - 1; ++k)
       if (k != n) modes[nm++] = k;
     const float *Y = nullptr;
-    NNC_TRY(chain(b.P(), d, cur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
+    if (p.fast)
+      NNC_TRY(chain_small(b.P(), d, cur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
+    else
+      NNC_TRY(chain(b.P(), d, cur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
     NNC_TRY(factor_block(b, n, Y, core, A[n], 0.0, grad_factors[n], s));
   }
   // factor d-1 and the core from T = X x_0 A_0^T
@@ -1344,9 +1369,15 @@ nnc_status nntucker_grad(const void *X, nnc_dtype xdt, int ndim, const int64_t *
   int modes[kMaxDim], nm = 0;
   for (int k = 1; k < d - 1; ++k) modes[nm++] = k;
   const float *Y = nullptr;
-  NNC_TRY(chain(b.T(), d, cur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
+  if (p.fast)
+    NNC_TRY(chain_small(b.T(), d, cur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
+  else
+    NNC_TRY(chain(b.T(), d, cur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
   NNC_TRY(factor_block(b, d - 1, Y, core, A[d - 1], 0.0, grad_factors[d - 1], s));
-  NNC_TRY(ttm_mode(Y, NNC_F32, d, cur, d - 1, A[d - 1], p.R[d - 1], b.G(2), s, false));
+  if (p.fast)
+    NNC_TRY(ttm_f32(Y, d, cur, d - 1, A[d - 1], p.R[d - 1], b.G(2), s));
+  else
+    NNC_TRY(ttm_mode(Y, NNC_F32, d, cur, d - 1, A[d - 1], p.R[d - 1], b.G(2), s, false));
   const float *den = nullptr;
   NNC_TRY(core_chain(b, core, -1, b.G(3), &den, s));
   NNC_TRY(launch_sub(den, b.G(2), grad_core, p.gsize, s));

@@ -130,54 +130,76 @@ __global__ void contract_except_k(const float *__restrict__ U, const float *__re
 
 // The same contraction for J <= JM (<= 32): one wave per output row i, its lanes striding
 // over the flattened summation index t = p * post + q (lane l takes t = l, l + 64, ...) with
-// JM partial sums each, then a butterfly over the wave.  V (pre x J x post) is staged in LDS
-// when it fits (vlds); U's loads are issued four steps ahead of their products.  Every sum
-// runs in a fixed order.
-constexpr int kCeVlds = 8192;  // floats of V staged in LDS (32 KB)
+// JM partial sums each, then a butterfly over the wave.  V (pre x J x post) passes through
+// LDS in chunks of the summation index that every wave of the block shares; U's loads are
+// issued four steps ahead of their products.  Every sum runs in a fixed order.
+constexpr int kCeVlds = 8192;  // floats of V staged in LDS per chunk (32 KB)
 
 template <int JM>
 __global__ __launch_bounds__(256) void contract_except_rows_k(const float *__restrict__ U,
                                                               const float *__restrict__ V, int pre,
-                                                              int64_t I, int J, int post, int vlds,
+                                                              int64_t I, int J, int post,
                                                               float *__restrict__ out) {
   __shared__ float Vs[kCeVlds];
-  const int nv = pre * J * post;
-  if (vlds) {
-    for (int e = threadIdx.x; e < nv; e += blockDim.x) Vs[e] = V[e];
-    __syncthreads();
-  }
-  const float *Vb = vlds ? Vs : V;
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (i >= I) return;
+  const bool active = i < I;  // every wave takes part in the staging barriers
+  const int total = pre * post;
+  const int tc = (kCeVlds / J) & ~63;  // chunk of the summation index, a multiple of 64
   float acc[JM];
 #pragma unroll
   for (int j = 0; j < JM; ++j) acc[j] = 0.f;
-  // (p, q) of t = lane, advanced by 64 per step without divisions
   const int dp = 64 / post, dq = 64 - (64 / post) * post;
-  int p = lane / post, q = lane - (lane / post) * post;
-  while (p < pre) {
-    float u[4];
-    int vo[4];
+  for (int t0 = 0; t0 < total; t0 += tc) {
+    const int tn = min(tc, total - t0);
+    __syncthreads();  // the previous chunk has been consumed
+    // eight loads in flight per thread before their LDS stores
+    for (int e0 = threadIdx.x; e0 < J * tn; e0 += 8 * blockDim.x) {
+      float v8[8];
+      int dst[8];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const bool ok = p < pre;
-      u[k] = ok ? U[((int64_t)p * I + i) * post + q] : 0.f;
-      vo[k] = ok ? (p * J) * post + q : 0;
-      p += dp;
-      q += dq;
-      if (q >= post) {
-        q -= post;
-        ++p;
+      for (int k = 0; k < 8; ++k) {
+        const int e = e0 + k * blockDim.x;
+        const int ee = e < J * tn ? e : 0;
+        const int j = ee / tn, tt = ee - (ee / tn) * tn;
+        const int t = t0 + tt;
+        const int p = t / post, q = t - (t / post) * post;
+        v8[k] = V[((int64_t)p * J + j) * post + q];
+        dst[k] = e < J * tn ? j * tc + tt : -1;
       }
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (dst[k] >= 0) Vs[dst[k]] = v8[k];
     }
+    __syncthreads();
+    if (!active) continue;
+    int tt = lane;
+    int p = (t0 + lane) / post, q = (t0 + lane) - ((t0 + lane) / post) * post;
+    while (tt < tn) {
+      float u[4];
+      int vo[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < 4; ++k) {
+        const bool ok = tt + 64 * k < tn;
+        u[k] = ok ? U[((int64_t)p * I + i) * post + q] : 0.f;
+        vo[k] = ok ? tt + 64 * k : 0;
+        p += dp;
+        q += dq;
+        if (q >= post) {
+          q -= post;
+          ++p;
+        }
+      }
 #pragma unroll
-      for (int j = 0; j < JM; ++j)
-        if (j < J) acc[j] = fmaf(u[k], Vb[vo[k] + j * post], acc[j]);
+      for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int j = 0; j < JM; ++j)
+          if (j < J) acc[j] = fmaf(u[k], Vs[j * tc + vo[k]], acc[j]);
+      }
+      tt += 256;
     }
   }
+  if (!active) return;
 #pragma unroll
   for (int j = 0; j < JM; ++j) {
 #pragma unroll
@@ -196,10 +218,9 @@ nnc_status launch_contract_except(const float *U, const float *V, int64_t pre, i
                                   int64_t post, float *out, hipStream_t s) {
   if (J <= 32 && pre * J * post < INT32_MAX && I < ((int64_t)1 << 31) / 64) {
     const int grid = (int)((I + 3) / 4);
-    const int vlds = pre * J * post <= kCeVlds ? 1 : 0;
 #define NNC_CE_ROWS(JM)                                                                              \
   hipLaunchKernelGGL(contract_except_rows_k<JM>, dim3(grid), dim3(256), 0, s, U, V, (int)pre, I, (int)J, \
-                     (int)post, vlds, out)
+                     (int)post, out)
     if (J <= 8)
       NNC_CE_ROWS(8);
     else if (J <= 16)
@@ -227,6 +248,7 @@ __global__ void gram_k(const float *__restrict__ A, int64_t N, int64_t R, float 
 }
 
 nnc_status launch_gram(const float *A, int64_t N, int64_t R, float *S, hipStream_t s) {
+  if (R <= 32) return launch_gram_block(A, N, (int)R, S, s);  // one workgroup, rows staged in LDS
   hipLaunchKernelGGL(gram_k, dim3(grid_for(R * R, 64, 1 << 30)), dim3(64), 0, s, A, N, R, S);
   NNC_HIP(hipGetLastError());
   return NNC_OK;
