@@ -133,7 +133,7 @@ __global__ void contract_except_k(const float *__restrict__ U, const float *__re
 // JM partial sums each, then a butterfly over the wave.  V (pre x J x post) passes through
 // LDS in chunks of the summation index that every wave of the block shares; U's loads are
 // issued four steps ahead of their products.  Every sum runs in a fixed order.
-constexpr int kCeVlds = 8192;  // floats of V staged in LDS per chunk (32 KB)
+constexpr int kCeVlds = 16384;  // floats of V staged in LDS per chunk (64 KB)
 
 template <int JM>
 __global__ __launch_bounds__(256) void contract_except_rows_k(const float *__restrict__ U,
@@ -153,23 +153,17 @@ __global__ __launch_bounds__(256) void contract_except_rows_k(const float *__res
   for (int t0 = 0; t0 < total; t0 += tc) {
     const int tn = min(tc, total - t0);
     __syncthreads();  // the previous chunk has been consumed
-    // eight loads in flight per thread before their LDS stores
-    for (int e0 = threadIdx.x; e0 < J * tn; e0 += 8 * blockDim.x) {
-      float v8[8];
-      int dst[8];
+    // thread per summation index tt: its J entries of V (stride post) loaded together
+    for (int tt = threadIdx.x; tt < tn; tt += blockDim.x) {
+      const int t = t0 + tt;
+      const int p = t / post, q = t - (t / post) * post;
+      const float *vb = V + (int64_t)p * J * post + q;
+      float v[JM];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int e = e0 + k * blockDim.x;
-        const int ee = e < J * tn ? e : 0;
-        const int j = ee / tn, tt = ee - (ee / tn) * tn;
-        const int t = t0 + tt;
-        const int p = t / post, q = t - (t / post) * post;
-        v8[k] = V[((int64_t)p * J + j) * post + q];
-        dst[k] = e < J * tn ? j * tc + tt : -1;
-      }
+      for (int j = 0; j < JM; ++j) v[j] = j < J ? vb[(int64_t)j * post] : 0.f;
 #pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (dst[k] >= 0) Vs[dst[k]] = v8[k];
+      for (int j = 0; j < JM; ++j)
+        if (j < J) Vs[j * tc + tt] = v[j];
     }
     __syncthreads();
     if (!active) continue;
