@@ -918,12 +918,68 @@ __global__ __launch_bounds__(kCoreThreads) void core_step_k(CoreArgs a) {
 
 nnc_status launch_slice_step(const CoreArgsHost &h, hipStream_t s);
 
+// The core step as a chain of grid-wide launches, for cores larger than one workgroup's LDS
+// (every rank <= 32): the Gram summed from its row-block partials in order, the core update
+// (den_G by small contractions with the Grams, the FP64 MU step) and M_next (the core with
+// every other mode multiplied by its Gram, contracted with the core over all modes but
+// next).  Each sum runs in a fixed order.
+static nnc_status core_step_multi(const CoreArgsHost &h, hipStream_t s) {
+  const int d = h.d;
+  int64_t gs = 1;
+  for (int k = 0; k < d; ++k) gs *= h.R[k];
+  auto pre = [&](int k) {
+    int64_t v = 1;
+    for (int j = 0; j < k; ++j) v *= h.R[j];
+    return v;
+  };
+  auto post = [&](int k) {
+    int64_t v = 1;
+    for (int j = k + 1; j < d; ++j) v *= h.R[j];
+    return v;
+  };
+  for (int k = h.gram_from; k < h.gram_to; ++k)
+    NNC_TRY(launch_sum_parts(h.gram, h.gram_parts, h.R[k] * h.R[k], h.S[k], s));
+  if (h.do_core) {
+    if (h.gpart && h.nparts > 0) NNC_TRY(launch_sum_parts(h.gpart, h.nparts, gs, h.numG, s));
+    const float *in = h.G;
+    for (int k = 0; k < d; ++k) {  // den_G = G x_0 S_0 ... x_{d-1} S_{d-1} (S_k symmetric)
+      float *o = (k % 2) ? h.t1 : h.t0;
+      NNC_TRY(launch_ttm_small(in, pre(k), h.R[k], post(k), h.S[k], h.R[k], 1, h.R[k], o, s));
+      in = o;
+    }
+    NNC_TRY(launch_mu_elem(h.G, h.numG, in, gs, h.eps, h.clips, s));
+  }
+  if (h.next >= 0) {
+    const float *in = h.G;
+    int cnt = 0;
+    for (int k = 0; k < d; ++k) {
+      if (k == h.next) continue;
+      float *o = (cnt % 2) ? h.t1 : h.t0;
+      NNC_TRY(launch_ttm_small(in, pre(k), h.R[k], post(k), h.S[k], h.R[k], 1, h.R[k], o, s));
+      in = o;
+      ++cnt;
+    }
+    NNC_TRY(launch_contract_except(in, h.G, pre(h.next), h.R[h.next], h.R[h.next], post(h.next), h.M, s));
+  }
+  return NNC_OK;
+}
+
 nnc_status launch_core_step(const CoreArgsHost &h, hipStream_t s) {
   // small cores: the work spread over one workgroup per slice (core_kernels.hip), the core
   // numerator summed from h.gpart there too
   {
     const nnc_status st = launch_slice_step(h, s);
     if (st != NNC_EUNSUPPORTED) return st;
+  }
+  {
+    int64_t gs = 1;
+    int maxr = 1;
+    for (int k = 0; k < h.d; ++k) {
+      gs *= h.R[k];
+      maxr = std::max(maxr, (int)h.R[k]);
+    }
+    // cores beyond one workgroup's LDS: grid-wide launches
+    if (gs > kCoreLdsMax && maxr <= 32 && h.gram_to - h.gram_from <= 1 && h.t0 && h.t1) return core_step_multi(h, s);
   }
   if (h.do_core && h.gpart && h.nparts > 0) {
     int64_t gs = 1;
