@@ -441,16 +441,18 @@ static nnc_status chain_small(const float *src, int d, int64_t *cur, const int *
 // The core step that closes a sweep: core numerator from the last mode's row-block
 // partials, Gram of the last factor and the core update.  (M_0 of the next sweep is formed
 // at that sweep's start, beside its first small contraction.)
-static nnc_status core_tail(const TuckerBufs &b, float *G, float *const *A, double eps, hipStream_t s) {
+static nnc_status core_tail(const TuckerBufs &b, float *G, float *const *A, double eps, hipStream_t s,
+                            bool from_parts = true) {
   const TuckerPlan &p = *b.p;
   const int d = p.d;
-  CoreArgsHost h = core_args(b, G, A, eps);  // core numerator summed from b.gpart() there
-  h.gram_from = d - 1;
+  CoreArgsHost h = core_args(b, G, A, eps);  // core numerator summed from b.gpart() there,
+  h.gram_from = d - 1;                       // or already in b.G(2) (from_parts false)
   h.gram_to = d;
   h.gram = b.gram();
   h.gram_parts = (int)mu_rows_blocks(p.N[d - 1]);
   h.do_core = 1;
-  h.nparts = (int)mu_rows_blocks(p.N[d - 1]);
+  h.nparts = from_parts ? (int)mu_rows_blocks(p.N[d - 1]) : 0;
+  if (!from_parts) h.gpart = nullptr;
   h.next = -1;
   return launch_core_step(h, s);
 }
@@ -535,9 +537,14 @@ static nnc_status fused_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, 
   for (int k = 1; k < d - 1; ++k) modes[nm++] = k;
   const float *Y = nullptr;
   NNC_TRY(chain_with_core(b, b.T(), d, cur, modes, nm, A, p.R, pending, &Y, s));
+  // the core numerator X x_k A_k^T: from the last mode's row-block partials, or, for cores
+  // beyond the slice kernels (where per-block partials of the whole core cost more than the
+  // contraction itself), by one small contraction with the new A_{d-1}
+  const bool big_core = p.gsize > 16384;
   NNC_TRY(launch_mu_rows(Y, G, A[d - 1], b.M(), prod(p.R, 0, d - 1), p.N[d - 1], 1, p.R[d - 1], eps,
-                         b.clips(), b.gram(), b.gpart(), nullptr, s));
-  return core_tail(b, G, A, eps, s);
+                         b.clips(), b.gram(), big_core ? nullptr : b.gpart(), nullptr, s));
+  if (big_core) NNC_TRY(ttm_f32(Y, d, cur, d - 1, A[d - 1], p.R[d - 1], b.G(2), s));
+  return core_tail(b, G, A, eps, s, !big_core);
 }
 
 // ------------------------------------------------------------------ fused three-way sweep

@@ -208,8 +208,80 @@ __global__ __launch_bounds__(256) void contract_except_rows_k(const float *__res
   }
 }
 
+// The same contraction for few output rows (I small, J <= JM <= 32): one block of kSplitWaves
+// waves per row i, wave w summing the contiguous range w of the flattened summation index
+// (lanes striding inside it), a butterfly per wave, then the waves' sums added in wave order
+// through LDS.
+constexpr int kSplitWaves = 16;
+
+template <int JM>
+__global__ __launch_bounds__(64 * kSplitWaves) void contract_except_split_k(const float *__restrict__ U,
+                                                                           const float *__restrict__ V,
+                                                                           int pre, int64_t I, int J,
+                                                                           int post,
+                                                                           float *__restrict__ out) {
+  __shared__ float ws[kSplitWaves][JM];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i = blockIdx.x;
+  const int total = pre * post;
+  const int per = (total + kSplitWaves - 1) / kSplitWaves;
+  const int tb = w * per, te = min(total, tb + per);
+  float acc[JM];
+#pragma unroll
+  for (int j = 0; j < JM; ++j) acc[j] = 0.f;
+  for (int t0 = tb + lane; t0 < te; t0 += 256) {
+    float u[4];
+    int vo[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int t = t0 + 64 * k;
+      const bool ok = t < te;
+      const int tt = ok ? t : tb;
+      const int p = tt / post, q = tt - (tt / post) * post;
+      u[k] = ok ? U[((int64_t)p * I + i) * post + q] : 0.f;
+      vo[k] = p * J * post + q;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+#pragma unroll
+      for (int j = 0; j < JM; ++j)
+        if (j < J) acc[j] = fmaf(u[k], V[vo[k] + j * post], acc[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < JM; ++j) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) acc[j] += __shfl_xor(acc[j], m, 64);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < JM; ++j) ws[w][j] = acc[j];
+  }
+  __syncthreads();
+  if (threadIdx.x < J) {
+    float sum = 0.f;
+    for (int ww = 0; ww < kSplitWaves; ++ww) sum += ws[ww][threadIdx.x];
+    out[i * J + threadIdx.x] = sum;
+  }
+}
+
 nnc_status launch_contract_except(const float *U, const float *V, int64_t pre, int64_t I, int64_t J,
                                   int64_t post, float *out, hipStream_t s) {
+  if (J <= 32 && I <= 64 && pre * post >= 64 * kSplitWaves && pre * J * post < INT32_MAX) {
+    // few rows and a long sum: every row's sum split over a block of waves
+#define NNC_CE_SPLIT(JM)                                                                        \
+  hipLaunchKernelGGL(contract_except_split_k<JM>, dim3((unsigned)I), dim3(64 * kSplitWaves), 0, s, U, V, \
+                     (int)pre, I, (int)J, (int)post, out)
+    if (J <= 8)
+      NNC_CE_SPLIT(8);
+    else if (J <= 16)
+      NNC_CE_SPLIT(16);
+    else
+      NNC_CE_SPLIT(32);
+#undef NNC_CE_SPLIT
+    NNC_HIP(hipGetLastError());
+    return NNC_OK;
+  }
   if (J <= 32 && pre * J * post < INT32_MAX && I < ((int64_t)1 << 31) / 64) {
     const int grid = (int)((I + 3) / 4);
 #define NNC_CE_ROWS(JM)                                                                              \
