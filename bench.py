@@ -45,8 +45,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-PASS_SOURCES = ["paper_1909_07570_amd/csrc/pass_kernels.hip", "paper_1909_07570_amd/csrc/kernels.hip",
-                "paper_1909_07570_amd/csrc/fused3_kernels.hip"]
+PASS_SOURCES = ["paper_1909_07570_amd/csrc/pass_kernels.hip", "paper_1909_07570_amd/csrc/fused3_kernels.hip"]
 COUNTERS = os.path.join(ROOT, "profiles", "pass_counters_512cubed.json")
 N_COPY = 128 << 20
 # The R = 20 (two 16-wide rank tiles) instantiations of the four pass kernels, X bytes per entry.
@@ -113,17 +112,17 @@ def summarize(args):
         raise SystemExit("--summarize takes PROF FETCH WRITE [MFMA_UTIL MFMA_FLOPS]")
     prof_dir, fetch_dir, write_dir = args.summarize[:3]
     dirs = " ".join(args.summarize)
-    lines = ["# Kernel time of one 512^3 bench step, both forms (rocprofv3 --kernel-trace --stats)", "",
+    lines = ["# Kernel time of the bench run, 512^3 step in both forms (rocprofv3 --kernel-trace --stats)", "",
              "Command (repo root):", "",
              "    rocprofv3 --kernel-trace --stats --output-format csv -d %s -o run -- "
              "python -u bench.py --steps 1 --warmup 0 --no-cpu" % prof_dir, "",
-             "The step runs 500 nnTucker sweeps per form (BF16 form: 480 on BF16 X + 20 on FP32 X),",
-             "nnCP rank 10 x 300 sweeps, lift and residuals; then Algorithm 2 twice per form (nnCP of",
-             "X rank 10 x 500 sweeps with the R = 10 pass instantiations, NMF of each factor, lift), the",
-             "Section 4.2 study (tiny_candelinc_k: 8 launches of 1000 starts x 5000 + 5000 sweeps, plus",
-             "8 warm-up launches) and the Section 4.3 sample (8 generated 40^3 tensors, both",
-             "algorithms, 5000 sweeps per sub-fit: the 40^3 instantiations below); bench.py then",
-             "times each X-streaming pass kernel over 23 launches and runs a 20-sweep eager fit.",
+             "The step runs 500 nnTucker sweeps per form (BF16 form: 480 sweeps of the fused three-way",
+             "schedule -- pass1y_k, mu_rows_k<0>, pass2y_k, mu_rows_k<0>, small_mrows_k, mu_rows_k<1>,",
+             "coreL_k -- on BF16 X + 20 general sweeps on FP32 X), nnCP rank 10 x 300 sweeps, lift and",
+             "residuals.  Then Algorithm 2 twice per form, the Section 4.2 study (tiny_candelinc_k), the",
+             "Section 4.3 sample, the other configurations (128^4 BF16, the 256^3 adjoint, 64^5 with",
+             "64 batched restarts, long-mode passes, real-valued CANDELINC at 512^3), the plain pass",
+             "kernels timed through nnc_ttm and five eager 20-sweep BF16 fits with per-pass events.",
              "Every kernel of the run is listed.", "",
              "| kernel | calls | total ms | avg us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
     with open(_find(prof_dir, "kernel_stats.csv")) as f:
@@ -204,7 +203,8 @@ def summarize(args):
 
 
 PASS_KEYS = (("ttm_last_lds_k<true, 2", "bf16"), ("ttm_mid_lds_k<2>", "bf16"),
-             ("ttm_last_lds_k<false, 2", "f32"), ("ttm_mid_lds_f32_k<2", "f32"))
+             ("ttm_last_lds_k<false, 2", "f32"), ("ttm_mid_lds_f32_k<2", "f32"),
+             ("pass1y_k", "bf16"), ("pass2y_k", "bf16"))
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}
 
 
