@@ -294,7 +294,7 @@ static nnc_status factor_block(const TuckerBufs &b, int n, const float *Y, const
   const TuckerPlan &p = *b.p;
   const int64_t pre = prod(p.R, 0, n), post = prod(p.R, n + 1, p.d);
   NNC_TRY(launch_contract_except(Y, G, pre, p.N[n], p.R[n], post, b.num(), s));
-  if (p.fast && p.gsize <= 16384) {  // M_n by the core step of the fused sweep (every Gram is current)
+  if (p.fast) {  // M_n by the core step of the fused sweep (every Gram is current)
     CoreArgsHost h;
     memset(&h, 0, sizeof h);
     h.d = p.d;

@@ -322,6 +322,76 @@ __global__ __launch_bounds__(kSliceThreads) void mrows_k(SliceArgs a) {
   mrows_body<RM, BIG>(a, blockIdx.x);
 }
 
+// Rows of M_n for cores larger than the whole-core kernels above take (slices of up to
+// kSliceMax entries): block (a, g) stages the slice G_a and the slices G_b of its group,
+// b in [g nb, g nb + nb), in LDS with one round of loads beside the Grams', forms
+// H_a = G_a x_{k != n} S_k there, and writes M_n[a][b] = <H_a, G_b>.  Every group of row a
+// forms H_a again (a few hundred multiply-adds per thread), which costs far less than the
+// launches of a grid-wide chain.  Each dot product is split over Tb = kSliceThreads / nbp
+// threads (nbp = nb rounded up to a power of two; thread j adds c = j, j + Tb, ... in
+// order), reduced by a fixed butterfly within each wave (or half wave) and the partial sums
+// added in thread order.
+template <int RM>
+__global__ __launch_bounds__(kSliceThreads) void mrows_big_k(SliceArgs a, int nb, int ngrp) {
+  extern __shared__ __attribute__((aligned(16))) float lds[];
+  const int d = a.d, tid = threadIdx.x, n = a.n;
+  const int ia = blockIdx.x / ngrp, g = blockIdx.x - ia * ngrp;
+  const int Rn = a.R[n];
+  const int slice = a.gsize / Rn;
+  const int b0 = g * nb, nbl = min(nb, Rn - b0);
+  float *Sl = lds;
+  float *red = Sl + d * RM * RM;
+  float *H0 = red + SliceLds<RM>::kRed, *H1 = H0 + slice;  // the slices G_b follow H1
+  int post = 1;
+  for (int k = n + 1; k < d; ++k) post *= a.R[k];
+  // staged entry e = s * slice + c (s = 0: G_a, s >= 1: G_{b0 + s - 1}; c = pc * post + qc)
+  // holds G[(pc * Rn + row) * post + qc] and goes to H0[e] (s = 0) or H0[e + slice]
+  const int total = (1 + nbl) * slice;  // < 2^22 (see big_slice_fits)
+  const float inv_slice = 1.0f / (float)slice, inv_post = 1.0f / (float)post;
+  GramStage<RM> gs;
+  gs.issue(a);
+  constexpr int kU = 16;  // staged values per thread and round
+  for (int e0 = 0; e0 < total; e0 += kU * kSliceThreads) {
+    float v[kU];
+    int dst[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int e = min(e0 + tid + u * kSliceThreads, total - 1);  // past the end: the last again
+      const int sx = qdiv(e, inv_slice), c = e - sx * slice;
+      const int pc = qdiv(c, inv_post), qc = c - pc * post;
+      const int row = sx == 0 ? ia : b0 + sx - 1;
+      v[u] = a.G[((int64_t)pc * Rn + row) * post + qc];
+      dst[u] = sx == 0 ? e : e + slice;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) H0[dst[u]] = v[u];
+  }
+  gs.finish(a, Sl, red);
+  __syncthreads();
+  const float *H = contract_slice<RM>(a, n, Sl, H0, H1);  // ends with a barrier
+  const float *Gb = H1 + slice;
+  int nbp = 1;
+  while (nbp < nb) nbp <<= 1;
+  const int Tb = kSliceThreads / nbp;  // >= 32 (nb <= 32)
+  const int W = Tb < 64 ? Tb : 64;
+  const int bi = tid / Tb, j = tid - bi * Tb;
+  float acc = 0.f;
+  if (bi < nbl) {
+    const float *gp = Gb + bi * slice;
+#pragma unroll 4
+    for (int c = j; c < slice; c += Tb) acc = fmaf(H[c], gp[c], acc);
+  }
+  for (int off = W >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, W);
+  if ((tid & (W - 1)) == 0) red[tid / W] = acc;
+  __syncthreads();
+  if (tid < nbl) {
+    const int per = Tb / W;
+    float m = 0.f;
+    for (int w = 0; w < per; ++w) m += red[tid * per + w];
+    a.M[(int64_t)ia * Rn + b0 + tid] = m;
+  }
+}
+
 // T_i = G[i, ..] x_1 S_1 ... x_{d-1} S_{d-1} for slice i (and the new Gram of a.gram).
 template <int RM, bool BIG>
 static __device__ void denA_body(const SliceArgs &a, int i) {
@@ -720,10 +790,94 @@ static bool slice_fits(const CoreArgsHost &h, int *RMo, bool *bigo) {
   return true;
 }
 
+// Cores beyond kSliceMax entries whose mode slices the slice kernels can hold: the core
+// update by denA_k / denB_k (which keep one slice, not the core, in LDS) and the rows of
+// M_next by mrows_big_k.  LDS: the Grams, the reduction space and at least three slices.
+constexpr int kBigSliceB = 4;  // slices G_b per mrows_big_k block at most
+
+static bool big_slice_fits(const CoreArgsHost &h, int *RMo) {
+  int64_t gsize = 1;
+  int maxr = 1;
+  for (int k = 0; k < h.d; ++k) {
+    gsize *= h.R[k];
+    maxr = std::max(maxr, (int)h.R[k]);
+  }
+  if (gsize <= kSliceMax || maxr > 32 || h.gram_to - h.gram_from > 1) return false;
+  // a Gram alone (no core update, no M_next) is left to the grid-wide steps
+  if (!h.do_core && h.next < 0) return false;
+  for (int64_t k = 1, off = h.R[0] * h.R[0]; k < h.d; off += h.R[k] * h.R[k], ++k)
+    if (h.S[k] != h.S[0] + off) return false;
+  const int RM = maxr <= 8 ? 8 : (maxr <= 16 ? 16 : (maxr <= 24 ? 24 : 32));
+  int64_t worst = 0;
+  for (int k = 0; k < h.d; ++k) worst = std::max(worst, gsize / h.R[k]);
+  // staged entries of mrows_big_k ((1 + nb) slices) stay below 2^22 for the float-reciprocal
+  // index divisions
+  if (worst > kSliceMax || (1 + kBigSliceB) * worst >= ((int64_t)1 << 22)) return false;
+  if (4 * ((int64_t)h.d * RM * RM + SliceLds<8>::kRed + 3 * worst) > 160 * 1024) return false;
+  *RMo = RM;
+  return true;
+}
+
+template <int RM>
+static nnc_status big_slice_step(const CoreArgsHost &h, hipStream_t s) {
+  SliceArgs a = slice_args(h);
+  if (h.do_core) {
+    a.T = h.t0;
+    a.n = -1;
+    const int slice0 = a.gsize / a.R[0];
+    const size_t la = SliceLds<RM>::bytes(a.d, a.gsize, slice0, false);
+    const bool bigs = slice0 > kSliceMax / 2;
+    if (h.gpart && h.nparts > 0) {
+      const int nsum = (a.gsize + kSliceThreads - 1) / kSliceThreads;
+      if (bigs) {
+        NNC_TRY(allow_slice_lds(reinterpret_cast<const void *>(denA_sum_k<RM, true>), la));
+        hipLaunchKernelGGL((denA_sum_k<RM, true>), dim3(a.R[0] + nsum), dim3(kSliceThreads), la, s, a,
+                           h.gpart, h.nparts, h.numG, a.R[0]);
+      } else {
+        NNC_TRY(allow_slice_lds(reinterpret_cast<const void *>(denA_sum_k<RM, false>), la));
+        hipLaunchKernelGGL((denA_sum_k<RM, false>), dim3(a.R[0] + nsum), dim3(kSliceThreads), la, s, a,
+                           h.gpart, h.nparts, h.numG, a.R[0]);
+      }
+    } else if (bigs) {
+      NNC_TRY(allow_slice_lds(reinterpret_cast<const void *>(denA_k<RM, true>), la));
+      hipLaunchKernelGGL((denA_k<RM, true>), dim3(a.R[0]), dim3(kSliceThreads), la, s, a);
+    } else {
+      NNC_TRY(allow_slice_lds(reinterpret_cast<const void *>(denA_k<RM, false>), la));
+      hipLaunchKernelGGL((denA_k<RM, false>), dim3(a.R[0]), dim3(kSliceThreads), la, s, a);
+    }
+    SliceArgs b = a;
+    b.gram = -1;
+    b.numG = h.numG;
+    b.Gout = h.G;
+    hipLaunchKernelGGL(denB_k, dim3(a.R[0]), dim3(kSliceThreads), 0, s, b);
+    a.gram = -1;  // its Gram is stored now
+  }
+  if (h.next >= 0) {
+    a.n = h.next;
+    a.M = h.M;
+    const int Rn = a.R[h.next];
+    const int slice = a.gsize / Rn;
+    const int64_t room = (160 * 1024 / 4 - (int64_t)a.d * RM * RM - SliceLds<RM>::kRed) / slice - 2;
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kBigSliceB, room, (int64_t)Rn}));
+    const int ngrp = (Rn + nb - 1) / nb;
+    const size_t lm = sizeof(float) * ((size_t)a.d * RM * RM + SliceLds<RM>::kRed + (size_t)(2 + nb) * slice);
+    NNC_TRY(allow_slice_lds(reinterpret_cast<const void *>(mrows_big_k<RM>), lm));
+    hipLaunchKernelGGL((mrows_big_k<RM>), dim3(Rn * ngrp), dim3(kSliceThreads), lm, s, a, nb, ngrp);
+  }
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
 nnc_status launch_slice_step(const CoreArgsHost &h, hipStream_t s) {
   int RM;
   bool big;
-  if (!slice_fits(h, &RM, &big)) return NNC_EUNSUPPORTED;
+  if (!slice_fits(h, &RM, &big)) {
+    if (getenv("NNC_NO_BIG_SLICES") || !big_slice_fits(h, &RM)) return NNC_EUNSUPPORTED;
+    if (RM == 8) return big_slice_step<8>(h, s);
+    if (RM == 16) return big_slice_step<16>(h, s);
+    if (RM == 24) return big_slice_step<24>(h, s);
+    return big_slice_step<32>(h, s);
+  }
 #define NNC_SLICE(RMV) return big ? slice_step<RMV, true>(h, s) : slice_step<RMV, false>(h, s)
   if (RM == 8) NNC_SLICE(8);
   if (RM == 16) NNC_SLICE(16);

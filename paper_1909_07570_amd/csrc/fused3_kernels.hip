@@ -667,7 +667,8 @@ __global__ __launch_bounds__(kYThreads) void pass2y_k(const uint16_t *__restrict
       }
     }
     __builtin_amdgcn_wave_barrier();  // the A2 rows are read before the T tile overwrites them
-    // T tile: through the wave's LDS region, whole rows per store instruction, non-temporal
+    // T tile: through the wave's LDS region, whole rows per store instruction (ordinary
+    // stores: the launch after this one reads T back)
 #pragma unroll
     for (int nt = 0; nt < RT; ++nt) {
       const int r = nt * 16 + li;
@@ -687,8 +688,7 @@ __global__ __launch_bounds__(kYThreads) void pass2y_k(const uint16_t *__restrict
       const int r = rr + (lane >> 5);
       const int qq = (lane & 31) * 4;
       if (r < R)
-        __builtin_nontemporal_store(*reinterpret_cast<const f4 *>(stg + r * 128 + qq),
-                                    reinterpret_cast<f4 *>(out + (int64_t)r * Q + q0 + qq));
+        *reinterpret_cast<f4 *>(out + (int64_t)r * Q + q0 + qq) = *reinterpret_cast<const f4 *>(stg + r * 128 + qq);
     }
     __builtin_amdgcn_wave_barrier();
     // unit end: partial sums of each group (waves g Tg .. g Tg + Tg - 1, in order) into

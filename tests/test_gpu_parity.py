@@ -5,6 +5,7 @@ the factor as a hi+lo bf16 pair, so in practice only X's rounding matters and th
 error is far below that bar); final relative residual within 1e-3 of the oracle after equal
 sweeps; integer work (conversion, exact examples, fixed points) bit-exact.
 """
+import os
 import zlib
 
 import numpy as np
@@ -156,7 +157,11 @@ def _fit_gpu(nnc, X, G0, A0, iters, dt="f32", **kw):
                                         # small contractions split over blocks along the
                                         # contracted mode (ragged splits, two rounds each)
                                         ((300, 40, 260), (4, 5, 6)),
-                                        ((45, 1100, 37), (3, 7, 2))])
+                                        ((45, 1100, 37), (3, 7, 2)),
+                                        # cores beyond the whole-core kernels: mode slices in
+                                        # LDS, each row of M over several blocks
+                                        ((20, 18, 17, 19), (16, 16, 16, 16)),
+                                        ((10, 9, 8, 9, 10), (8, 8, 8, 8, 8))])
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_nntucker_few_sweeps_match_oracle(dims, ranks, use_graph):
     nnc = need_gpu()
@@ -170,6 +175,29 @@ def test_nntucker_few_sweeps_match_oracle(dims, ranks, use_graph):
     ref = oracle.tucker_rel_residual(X.astype(np.float64), Go, Ao)
     assert abs(rep.rel_residual - ref) <= 1e-5
     assert rep.eps_clips == 0
+
+
+@pytest.mark.parametrize("dims,ranks", [((20, 18, 17, 19), (16, 16, 16, 16)), ((40, 36, 34), (32, 32, 32)),
+                                        ((10, 9, 8, 9, 10), (8, 8, 8, 8, 8)), ((24, 20, 22, 18), (16, 16, 16, 8))])
+def test_big_core_slice_steps_match_grid_wide_steps(dims, ranks):
+    """Cores beyond the whole-core kernels: the core-space steps on mode slices (rows of M
+    over several blocks, the core update slice by slice) against the grid-wide chain of
+    small contractions (NNC_NO_BIG_SLICES), the same sweeps in other summation orders."""
+    nnc = need_gpu()
+    X, _, G0, A0 = problem(38, dims, 3, ranks)
+    print("case", dims, ranks, flush=True)
+    G, A, rep = _fit_gpu(nnc, X, G0, A0, 3)
+    os.environ["NNC_NO_BIG_SLICES"] = "1"
+    try:
+        Gg, Ag, repg = _fit_gpu(nnc, X, G0, A0, 3)
+    finally:
+        del os.environ["NNC_NO_BIG_SLICES"]
+    assert rel_fro(G, Gg) <= 1e-5
+    for a, ag in zip(A, Ag):
+        assert rel_fro(a, ag) <= 1e-5
+    assert rep.eps_clips == repg.eps_clips == 0
+    Go, Ao, _, _ = oracle.nntucker(X.astype(np.float64), G0, A0, 3)
+    assert rel_fro(oracle.tucker_full(G, A), oracle.tucker_full(Go, Ao)) <= 1e-4
 
 
 def _offset_view(a):
