@@ -200,7 +200,8 @@ struct GramStage {
 // out[p][r][q] = sum_l S[l][r] in[p][l][q] on an LDS tensor whose mode of size Rk has pre
 // entries before it and post after it; one output per thread and step.  The RM inputs of an
 // output are loaded before the multiply-adds (rows l >= Rk read row Rk - 1, which the zero
-// rows of S cancel), so each output costs one LDS round trip.
+// rows of S cancel), so each output costs one LDS round trip.  Kernels that keep many values
+// in registers around it (coreL_k, small_mrows_k) use this form.
 template <int RM>
 static __device__ void slice_ttm(const float *in, float *out, int pre, int Rk, int post,
                                  const float *S) {
@@ -226,6 +227,56 @@ static __device__ void slice_ttm(const float *in, float *out, int pre, int Rk, i
   }
 }
 
+// The same product with four outputs per thread, for RM <= 16 (at RM 24 and 32 the kernels
+// that use it ran out of registers): a thread takes the four outputs r = 4g .. 4g + 3 of
+// one (p, q): each input x[l] is read once for the four, and S[l][4g .. 4g + 3] is one
+// 16-byte read (S rows are RM floats, zero past Rk).  The inputs are read in batches
+// before their multiply-adds (rows l >= Rk read row Rk - 1, which the zero rows of S
+// cancel); every output still takes its RM terms in l order.
+template <int RM>
+static __device__ void slice_ttm4(const float *in, float *out, int pre, int Rk, int post,
+                                 const float *S) {
+  const int RG = (Rk + 3) >> 2;
+  const int total = pre * RG * post;
+  int off[RM];  // the same for every output; opaque so that it is not folded into multiplies
+#pragma unroll
+  for (int l = 0; l < RM; ++l) off[l] = __builtin_amdgcn_readfirstlane((l < Rk ? l : Rk - 1) * post);
+  const float inv_post = 1.0f / post, inv_rg = 1.0f / RG;
+  for (int o = threadIdx.x; o < total; o += kSliceThreads) {  // total <= kSliceMax < 2^22
+    const int pr = qdiv(o, inv_post), q = o - pr * post;
+    const int p = qdiv(pr, inv_rg), g = pr - p * RG;
+    const float *src = in + p * Rk * post + q;
+    const float *sg = S + 4 * g;
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    constexpr int LB = RM < 16 ? RM : 16;
+#pragma unroll
+    for (int l0 = 0; l0 < RM; l0 += LB) {
+      float x[LB];
+      float4 sv[LB];
+#pragma unroll
+      for (int l = 0; l < LB; ++l) {
+        if (l0 + l < RM) {
+          x[l] = src[off[l0 + l]];
+          sv[l] = *reinterpret_cast<const float4 *>(sg + (l0 + l) * RM);
+        }
+      }
+#pragma unroll
+      for (int l = 0; l < LB; ++l) {
+        if (l0 + l < RM) {
+          acc[0] = fmaf(sv[l].x, x[l], acc[0]);
+          acc[1] = fmaf(sv[l].y, x[l], acc[1]);
+          acc[2] = fmaf(sv[l].z, x[l], acc[2]);
+          acc[3] = fmaf(sv[l].w, x[l], acc[3]);
+        }
+      }
+    }
+    float *dst = out + (p * Rk + 4 * g) * post + q;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (4 * g + j < Rk) dst[j * post] = acc[j];
+  }
+}
+
 // Contract the slice (modes of the core except `skip`, kept in order) with the Grams of its
 // modes; returns the LDS buffer holding the result (H0 or H1).
 template <int RM>
@@ -241,7 +292,10 @@ static __device__ float *contract_slice(const SliceArgs &a, int skip, const floa
     int pre = 1, post = 1;
     for (int t = 0; t < j; ++t) pre *= dims[t];
     for (int t = j + 1; t < nd; ++t) post *= dims[t];
-    slice_ttm<RM>(cur, nxt, pre, dims[j], post, Sl + k * RM * RM);
+    if constexpr (RM <= 16)
+      slice_ttm4<RM>(cur, nxt, pre, dims[j], post, Sl + k * RM * RM);
+    else
+      slice_ttm<RM>(cur, nxt, pre, dims[j], post, Sl + k * RM * RM);
     __syncthreads();
     float *t2 = cur;
     cur = nxt;
@@ -793,7 +847,9 @@ static bool slice_fits(const CoreArgsHost &h, int *RMo, bool *bigo) {
 // Cores beyond kSliceMax entries whose mode slices the slice kernels can hold: the core
 // update by denA_k / denB_k (which keep one slice, not the core, in LDS) and the rows of
 // M_next by mrows_big_k.  LDS: the Grams, the reduction space and at least three slices.
-constexpr int kBigSliceB = 4;  // slices G_b per mrows_big_k block at most
+// slices G_b per mrows_big_k block at most: two measured faster than four at 16^4 (more
+// blocks, one round of loads) and the same as one
+constexpr int kBigSliceB = 2;
 
 static bool big_slice_fits(const CoreArgsHost &h, int *RMo) {
   int64_t gsize = 1;
@@ -955,7 +1011,7 @@ __global__ __launch_bounds__(kSliceThreads) void coreL_k(SliceArgs a, const floa
   const int slice = a.gsize / a.R[0];
   float *H0 = red + SliceLds<RM>::kRed, *H1 = H0 + slice;
   constexpr int SPT = (BIG ? kSliceMax : kSliceMax / 2) / kSliceThreads;  // slice values per thread
-  constexpr int kNB = 64;                                                  // partials in flight
+  constexpr int kNB = BIG ? 32 : 64;  // partials in flight (fewer beside a larger slice)
   float uv[SPT];
 #pragma unroll
   for (int u = 0; u < SPT; ++u) {

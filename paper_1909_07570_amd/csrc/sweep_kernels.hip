@@ -21,7 +21,10 @@ namespace nnc {
 // =====================================================================================
 constexpr int kRB = 8;
 constexpr int kRowThreads = 512;
-constexpr int kRowLdsFloats = 14 * 1024;  // dynamic LDS budget of one block (floats)
+// dynamic LDS budget of one block (floats); with the static arrays below one block takes
+// most of a CU's LDS when the core is large (fewer chunks of G: 128^4 at rank 16 ran 2.5 %
+// faster than with a 56 KB budget), while small problems use only what their chunk needs
+constexpr int kRowLdsFloats = 32 * 1024;
 constexpr int kRowRed = 4096;             // partial sums of the contraction (floats)
 
 // Contraction paths (chosen per launch from the shape):
@@ -102,7 +105,7 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
     for (int q0 = 0; q0 < post; q0 += QC) {
       const int qn = (post - q0) < QC ? (post - q0) : QC;
       const bool whole = qn == post;  // whole slices: G and Y chunk offsets are linear
-      const int ng = pn * R * qn, ny = pn * nr * qn;  // both below 2^14 (the LDS budget)
+      const int ng = pn * R * qn, ny = pn * nr * qn;  // both at most 2^15 (the LDS budget)
       const int nrq = nr * qn;
       const int qs = PATH == kPathQ4 && ((qn >> 2) & 1) == 0 ? qn + 4 : qn;
       float *Gs = dynr, *Ys = dynr + pn * R * qs;
@@ -522,6 +525,16 @@ nnc_status launch_mu_rows(const float *Y, const float *G, float *A, const float 
   }
   const size_t lds = (size_t)(PC * (R + kRB) * (QC + pad)) * sizeof(float);
   const int64_t blocks = (Nn + kRB - 1) / kRB;
+  if (lds > 64 * 1024) {
+    static bool attr[3] = {false, false, false};
+    if (!attr[path]) {
+      const void *k = path == kPathQ4 ? reinterpret_cast<const void *>(mu_rows_k<kPathQ4>)
+                      : path == kPathP ? reinterpret_cast<const void *>(mu_rows_k<kPathP>)
+                                       : reinterpret_cast<const void *>(mu_rows_k<kPathS>);
+      NNC_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kRowLdsFloats * (int)sizeof(float)));
+      attr[path] = true;
+    }
+  }
 #define NNC_MU(PV)                                                                                \
   hipLaunchKernelGGL(mu_rows_k<PV>, dim3((unsigned)blocks), dim3(kRowThreads), lds, s, Y, G, A, M, \
                      (int)pre, (int)Nn, (int)post, (int)R, (int)PC, (int)QC, eps, clips, gram,    \

@@ -161,7 +161,10 @@ def _fit_gpu(nnc, X, G0, A0, iters, dt="f32", **kw):
                                         # cores beyond the whole-core kernels: mode slices in
                                         # LDS, each row of M over several blocks
                                         ((20, 18, 17, 19), (16, 16, 16, 16)),
-                                        ((10, 9, 8, 9, 10), (8, 8, 8, 8, 8))])
+                                        ((10, 9, 8, 9, 10), (8, 8, 8, 8, 8)),
+                                        # uneven slices; mode 0's row update in the scalar
+                                        # path over several chunks (a ragged last one)
+                                        ((9, 8, 34, 35), (5, 5, 30, 31))])
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_nntucker_few_sweeps_match_oracle(dims, ranks, use_graph):
     nnc = need_gpu()
