@@ -111,9 +111,9 @@ struct TuckerPlan {
   int d = 0;
   int64_t N[kMaxDim], R[kMaxDim];
   int64_t size = 0, gsize = 0;
-  int64_t nP = 0, nT = 0, nU = 0, nC = 0, nY = 0, nNum = 0, nS = 0, nM = 0, nGp = 0, nGr = 0;
+  int64_t nP = 0, nT = 0, nU = 0, nC = 0, nY = 0, nNum = 0, nS = 0, nM = 0, nGp = 0, nGr = 0, nNp = 0;
   bool fast = false;  // every multirank <= 32: fused small-step kernels
-  size_t oP, oT, oU0, oU1, oC0, oC1, oY, oNum, oDen, oS, oM, oG0, oG1, oG2, oG3, oGp, oGr, oClip,
+  size_t oP, oT, oU0, oU1, oC0, oC1, oY, oNum, oDen, oS, oM, oG0, oG1, oG2, oG3, oGp, oGr, oNp, oClip,
       oFlag, oRed, oPart, oLsT, oLsL, oLsS, total;
 };
 
@@ -157,6 +157,7 @@ static TuckerPlan plan_tucker(int d, const int64_t *dims, const int64_t *rk) {
   for (int n = 0; n < d; ++n) {
     grow(p.nY, p.gsize / p.R[n] * p.N[n]);
     grow(p.nNum, p.N[n] * p.R[n]);
+    grow(p.nNp, mu_rows_split_floats(p.N[n], p.R[n]));
     grow(p.nM, p.R[n] * p.R[n]);
     p.nS += p.R[n] * p.R[n];
   }
@@ -184,6 +185,7 @@ static TuckerPlan plan_tucker(int d, const int64_t *dims, const int64_t *rk) {
   p.oG3 = L.take(sizeof(float) * p.gsize);
   p.oGp = L.take(sizeof(float) * p.nGp);
   p.oGr = L.take(sizeof(float) * p.nGr);
+  p.oNp = L.take(sizeof(float) * p.nNp);
   p.oClip = L.take(sizeof(unsigned long long));
   p.oFlag = L.take(sizeof(unsigned int));
   p.oRed = L.take(2 * sizeof(double));
@@ -205,6 +207,7 @@ struct TuckerBufs {
   float *C(int i) const { return f(i ? p->oC1 : p->oC0); }
   float *Y() const { return f(p->oY); }
   float *num() const { return f(p->oNum); }
+  float *npart() const { return f(p->oNp); }
   float *den() const { return f(p->oDen); }
   float *S(int k) const {
     size_t o = p->oS;
@@ -511,7 +514,7 @@ static nnc_status fused_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, 
     else
       NNC_TRY(chain_small(U, d, ycur, modes, nm, A, p.R, b.C(0), b.C(1), b.Y(), &Y, s));
     NNC_TRY(launch_mu_rows(Y, G, A[n], b.M(), prod(p.R, 0, n), p.N[n], prod(p.R, n + 1, d), p.R[n],
-                           eps, b.clips(), b.gram(), nullptr, nullptr, s));
+                           eps, b.clips(), b.gram(), nullptr, nullptr, s, b.npart()));
     // core step n: Gram of the new A_n and M_{n+1}
     CoreArgsHost h = core_args(b, G, A, eps);
     h.gram_from = n;
@@ -542,7 +545,7 @@ static nnc_status fused_sweep(const TuckerBufs &b, const void *X, nnc_dtype dt, 
   // contraction itself), by one small contraction with the new A_{d-1}
   const bool big_core = p.gsize > 16384;
   NNC_TRY(launch_mu_rows(Y, G, A[d - 1], b.M(), prod(p.R, 0, d - 1), p.N[d - 1], 1, p.R[d - 1], eps,
-                         b.clips(), b.gram(), big_core ? nullptr : b.gpart(), nullptr, s));
+                         b.clips(), b.gram(), big_core ? nullptr : b.gpart(), nullptr, s, b.npart()));
   if (big_core) NNC_TRY(ttm_f32(Y, d, cur, d - 1, A[d - 1], p.R[d - 1], b.G(2), s));
   return core_tail(b, G, A, eps, s, !big_core);
 }

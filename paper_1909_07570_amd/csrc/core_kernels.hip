@@ -724,8 +724,18 @@ static bool small_args(const float *in, int64_t P, int64_t N, int64_t Q, const f
   return true;
 }
 
+// Partial tensors of at least this many floats (64 MiB) go to the X-streaming pass kernels
+// when they take the shape (FP32 matrix cores, the factor in LDS, the tensor read once at
+// near-HBM rate): 64^5 at multirank 8 ran 2.7 % faster, 128^4 at 16 0.8 %; below it this
+// kernel's shorter launches win.
+constexpr int64_t kStreamFloats = (int64_t)16 << 20;
+
 nnc_status launch_ttm_small(const float *in, int64_t P, int64_t N, int64_t Q, const float *F,
                             int64_t ldl, int64_t ldr, int64_t R, float *out, hipStream_t s) {
+  if (P * N * Q >= kStreamFloats) {
+    const nnc_status st = launch_pass(in, NNC_F32, P, N, Q, F, ldl, ldr, R, out, s, nullptr, 0);
+    if (st != NNC_EUNSUPPORTED) return st;
+  }
   SmallArgs a;
   int RM;
   int64_t tiles;

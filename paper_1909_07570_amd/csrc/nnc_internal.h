@@ -219,9 +219,12 @@ nnc_status launch_ttm_small(const float *in, int64_t P, int64_t N, int64_t Q, co
                             int64_t ldl, int64_t ldr, int64_t R, float *out, hipStream_t s);
 
 // Fused num/den/update of factor rows (R <= 32); see sweep_kernels.hip.
+// npart (nullable; mu_rows_split_floats(Nn, R) floats): scratch that lets a long contracted
+// index be split over blocks when the factor has few row blocks.
 nnc_status launch_mu_rows(const float *Y, const float *G, float *A, const float *M, int64_t pre,
                           int64_t Nn, int64_t post, int64_t R, double eps, unsigned long long *clips,
-                          float *gram, float *gpart, float *grad, hipStream_t s);
+                          float *gram, float *gpart, float *grad, hipStream_t s, float *npart = nullptr);
+int64_t mu_rows_split_floats(int64_t Nn, int64_t R);
 int64_t mu_rows_blocks(int64_t Nn);
 // Per-block Gram partials of a factor, as mu_rows_k leaves them.
 nnc_status launch_gram_parts(const float *A, int64_t Nn, int64_t R, float *gram, hipStream_t s);

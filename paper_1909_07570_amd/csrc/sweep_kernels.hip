@@ -48,8 +48,9 @@ enum { kPathQ4 = 0, kPathP = 1, kPathS = 2 };
 // end of a slice.  The contraction issues the reads of kUn steps before their products, so
 // one LDS latency covers kUn steps; each accumulator still takes its terms in c order.
 constexpr int kUn = 4;
+constexpr int kMuSplitMax = 16;  // parts of a split numerator at most (mu_fin_k takes up to 16 at once)
 
-template <int PATH>
+template <int PATH, bool SPLIT>
 __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict__ Y,
                                                          const float *__restrict__ G,
                                                          float *__restrict__ A,
@@ -58,7 +59,8 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
                                                          double eps, unsigned long long *clips,
                                                          float *__restrict__ gram,
                                                          float *__restrict__ gpart,
-                                                         float *__restrict__ grad) {
+                                                         float *__restrict__ grad,
+                                                         int ksplit, float *__restrict__ npart) {
   extern __shared__ __attribute__((aligned(16))) float dynr[];
   // the block's rows of A_n and M_n transposed, zero past nr / R, rows of 36 floats (an odd
   // number of 16-byte quads) for the 16-byte reads of the denominator
@@ -100,10 +102,25 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
   const float mv1 = M[mok1 ? ms0 * R + mr1 : 0];
   constexpr int kSG = 16, kSY = 8;  // staged values per thread and round
   bool first = true;
-  for (int p0 = 0; p0 < pre; p0 += PC) {
-    const int pn = (pre - p0) < PC ? (pre - p0) : PC;
-    for (int q0 = 0; q0 < post; q0 += QC) {
-      const int qn = (post - q0) < QC ? (post - q0) : QC;
+  // SPLIT: block (b, ks) takes part ks of the contracted index (a range of p, or with
+  // pre < ksplit a quad-aligned range of q in slices of one p, PC == 1) and leaves its
+  // partial numerator in npart[ks]; mu_fin_k adds the parts in order and updates the rows
+  int pb = 0, pe = pre, qb = 0, qe = post;
+  if (SPLIT) {
+    const int ks = blockIdx.y;
+    if (pre >= ksplit) {
+      pb = (int)((int64_t)pre * ks / ksplit);
+      pe = (int)((int64_t)pre * (ks + 1) / ksplit);
+    } else {
+      const int nq4 = (post + 3) >> 2;
+      qb = 4 * (int)((int64_t)nq4 * ks / ksplit);
+      qe = min(post, 4 * (int)((int64_t)nq4 * (ks + 1) / ksplit));
+    }
+  }
+  for (int p0 = pb; p0 < pe; p0 += PC) {
+    const int pn = (pe - p0) < PC ? (pe - p0) : PC;
+    for (int q0 = qb; q0 < qe; q0 += QC) {
+      const int qn = (qe - q0) < QC ? (qe - q0) : QC;
       const bool whole = qn == post;  // whole slices: G and Y chunk offsets are linear
       const int ng = pn * R * qn, ny = pn * nr * qn;  // both at most 2^15 (the LDS budget)
       const int nrq = nr * qn;
@@ -363,6 +380,15 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
   __syncthreads();
   const bool own = tid < NRR;  // thread tid owns output (tid / R, tid % R) from here
   const int oi = qdiv(tid, inv_R), orr = tid - oi * R;
+  if (SPLIT) {
+    if (own) {
+      float num = 0.f;
+#pragma unroll 8
+      for (int k = 0; k < SPL; ++k) num += red[k * NRR + tid];
+      npart[((int64_t)blockIdx.y * Nn + i0) * R + tid] = num;
+    }
+    return;
+  }
   float nv = 0.f;
   if (own) {
     float num = 0.f;
@@ -502,9 +528,101 @@ __global__ __launch_bounds__(kRowThreads) void mu_rows_k(const float *__restrict
   }
 }
 
+// The row update after a split numerator (mu_rows_k<PATH, true>): rows [i0, i0 + kRB) of
+// A_n, num = the ksplit parts added in order, den = A M (s in order, as in mu_rows_k), the
+// multiplicative step with the FP64 division (or grad = den - num), the clip count and the
+// Gram partial of the new rows.
+constexpr int kFinThreads = kRB * 32;
+__global__ __launch_bounds__(kFinThreads) void mu_fin_k(const float *__restrict__ npart, int ksplit,
+                                                       float *__restrict__ A, const float *__restrict__ M,
+                                                       int Nn, int R, double eps, unsigned long long *clips,
+                                                       float *__restrict__ gram, float *__restrict__ grad) {
+  __shared__ __attribute__((aligned(16))) float As[kRB][36];
+  __shared__ __attribute__((aligned(16))) float MsT[32][36];
+  __shared__ unsigned int nclip;
+  const int tid = threadIdx.x;
+  const int i0 = blockIdx.x * kRB;
+  const int nr = (Nn - i0) < kRB ? (Nn - i0) : kRB;
+  const int NRR = nr * R;
+  const bool own = tid < NRR;
+  const float inv_R = 1.0f / (float)R;
+  const int oi = qdiv(tid, inv_R), orr = tid - oi * R;
+  // the parts of the thread's output, all loads issued together
+  constexpr int kFP = 16;
+  float pv[kFP];
+#pragma unroll
+  for (int k = 0; k < kFP; ++k) {
+    const int kk = k < ksplit ? k : ksplit - 1;
+    pv[k] = own ? npart[((int64_t)kk * Nn + i0) * R + tid] : 0.f;
+  }
+  {
+    const int ai = tid >> 5, ac = tid & 31;  // kFinThreads == kRB * 32
+    As[ai][ac] = (ai < nr && ac < R) ? A[(int64_t)(i0 + ai) * R + ac] : 0.f;
+    for (int e = tid; e < 32 * 32; e += kFinThreads) {
+      const int r = e >> 5, s2 = e & 31;
+      MsT[r][s2] = (r < R && s2 < R) ? M[s2 * R + r] : 0.f;
+    }
+  }
+  if (tid == 0) nclip = 0;
+  __syncthreads();
+  float nv = 0.f;
+  if (own) {
+    float num = 0.f;
+#pragma unroll
+    for (int k = 0; k < kFP; ++k)
+      if (k < ksplit) num += pv[k];
+    for (int k = kFP; k < ksplit; ++k) num += npart[((int64_t)k * Nn + i0) * R + tid];
+    const float4 *arow = reinterpret_cast<const float4 *>(As[oi]);
+    const float4 *mrow = reinterpret_cast<const float4 *>(MsT[orr]);
+    float den = 0.f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const float4 a = arow[q], m = mrow[q];
+      den = fmaf(a.x, m.x, den);
+      den = fmaf(a.y, m.y, den);
+      den = fmaf(a.z, m.z, den);
+      den = fmaf(a.w, m.w, den);
+    }
+    if (grad) {
+      nv = den - num;
+    } else {
+      double dd = (double)den;
+      if (dd < eps) {
+        dd = eps;
+        atomicAdd(&nclip, 1u);
+      }
+      nv = (float)(((double)As[oi][orr] * (double)num) / dd);
+    }
+  }
+  __syncthreads();
+  if (own) {
+    if (grad) {
+      grad[(int64_t)i0 * R + tid] = nv;
+    } else {
+      A[(int64_t)i0 * R + tid] = nv;
+      As[oi][orr] = nv;
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && nclip) atomicAdd(clips, (unsigned long long)nclip);
+  if (grad || !gram) return;
+  float *gb = gram + (int64_t)blockIdx.x * R * R;  // the arithmetic of mu_rows_k's partials
+  for (int idx = tid; idx < R * R; idx += kFinThreads) {
+    const int x = qdiv(idx, inv_R), y = idx - x * R;
+    float s2 = 0.f;
+#pragma unroll
+    for (int i = 0; i < kRB; ++i) {
+      const int ic = i < nr ? i : nr - 1;
+      const float t = fmaf(As[ic][x], As[ic][y], s2);
+      s2 = i < nr ? t : s2;
+    }
+    gb[idx] = s2;
+  }
+}
+
 nnc_status launch_mu_rows(const float *Y, const float *G, float *A, const float *M, int64_t pre,
                           int64_t Nn, int64_t post, int64_t R, double eps, unsigned long long *clips,
-                          float *gram, float *gpart, float *grad, hipStream_t s) {
+                          float *gram, float *gpart, float *grad, hipStream_t s, float *npart) {
   if (R > 32) return fail(NNC_EUNSUPPORTED, "mu_rows: R %lld above 32", (long long)R);
   if (pre * post > (int64_t)1 << 30 || Nn > (int64_t)1 << 30)
     return fail(NNC_EUNSUPPORTED, "mu_rows: sizes above 2^30");
@@ -523,25 +641,55 @@ nnc_status launch_mu_rows(const float *Y, const float *G, float *A, const float 
     PC = 1;
     QC = (kRowLdsFloats / (R + kRB) - pad) / 4 * 4;
   }
-  const size_t lds = (size_t)(PC * (R + kRB) * (QC + pad)) * sizeof(float);
   const int64_t blocks = (Nn + kRB - 1) / kRB;
+  // few row blocks over a long contracted index (the factors of large cores): the index is
+  // split over blocks and the parts added in order by mu_fin_k
+  const int64_t K = pre * post;
+  int ksplit = 1;
+  if (npart && !gpart && blocks < 64 && K >= 2048) {
+    ksplit = (int)std::min<int64_t>(std::min<int64_t>(kMuSplitMax, 256 / blocks), K / 512);
+    if (ksplit < 2) ksplit = 1;
+  }
+  if (ksplit > 1 && pre < ksplit) {  // q ranges of one slice at a time
+    const int64_t qr = ((post + ksplit - 1) / ksplit + 3) / 4 * 4;
+    PC = 1;
+    if (QC > qr) QC = qr;
+  } else if (ksplit > 1 && PC > (pre + ksplit - 1) / ksplit) {
+    PC = (pre + ksplit - 1) / ksplit;  // no chunk longer than one part's range of p
+  }
+  const size_t lds = (size_t)(PC * (R + kRB) * (QC + pad)) * sizeof(float);
   if (lds > 64 * 1024) {
-    static bool attr[3] = {false, false, false};
-    if (!attr[path]) {
-      const void *k = path == kPathQ4 ? reinterpret_cast<const void *>(mu_rows_k<kPathQ4>)
-                      : path == kPathP ? reinterpret_cast<const void *>(mu_rows_k<kPathP>)
-                                       : reinterpret_cast<const void *>(mu_rows_k<kPathS>);
+    static bool attr[6] = {false, false, false, false, false, false};
+    const int ai = path + 3 * (ksplit > 1);
+    if (!attr[ai]) {
+      const void *k = nullptr;
+      if (ksplit > 1)
+        k = path == kPathQ4 ? reinterpret_cast<const void *>(mu_rows_k<kPathQ4, true>)
+            : path == kPathP ? reinterpret_cast<const void *>(mu_rows_k<kPathP, true>)
+                             : reinterpret_cast<const void *>(mu_rows_k<kPathS, true>);
+      else
+        k = path == kPathQ4 ? reinterpret_cast<const void *>(mu_rows_k<kPathQ4, false>)
+            : path == kPathP ? reinterpret_cast<const void *>(mu_rows_k<kPathP, false>)
+                             : reinterpret_cast<const void *>(mu_rows_k<kPathS, false>);
       NNC_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kRowLdsFloats * (int)sizeof(float)));
-      attr[path] = true;
+      attr[ai] = true;
     }
   }
-#define NNC_MU(PV)                                                                                \
-  hipLaunchKernelGGL(mu_rows_k<PV>, dim3((unsigned)blocks), dim3(kRowThreads), lds, s, Y, G, A, M, \
-                     (int)pre, (int)Nn, (int)post, (int)R, (int)PC, (int)QC, eps, clips, gram,    \
-                     gpart, grad)
-  if (path == kPathQ4) NNC_MU(kPathQ4);
-  else if (path == kPathP) NNC_MU(kPathP);
-  else NNC_MU(kPathS);
+#define NNC_MU(PV, SV)                                                                                 \
+  hipLaunchKernelGGL((mu_rows_k<PV, SV>), dim3((unsigned)blocks, (unsigned)ksplit), dim3(kRowThreads), \
+                     lds, s, Y, G, A, M, (int)pre, (int)Nn, (int)post, (int)R, (int)PC, (int)QC, eps,   \
+                     clips, gram, gpart, grad, ksplit, npart)
+  if (ksplit > 1) {
+    if (path == kPathQ4) NNC_MU(kPathQ4, true);
+    else if (path == kPathP) NNC_MU(kPathP, true);
+    else NNC_MU(kPathS, true);
+    hipLaunchKernelGGL(mu_fin_k, dim3((unsigned)blocks), dim3(kFinThreads), 0, s, npart, ksplit, A, M, (int)Nn,
+                       (int)R, eps, clips, gram, grad);
+  } else {
+    if (path == kPathQ4) NNC_MU(kPathQ4, false);
+    else if (path == kPathP) NNC_MU(kPathP, false);
+    else NNC_MU(kPathS, false);
+  }
 #undef NNC_MU
   NNC_HIP(hipGetLastError());
   return NNC_OK;
@@ -569,6 +717,7 @@ nnc_status launch_gram_parts(const float *A, int64_t Nn, int64_t R, float *gram,
 }
 
 int64_t mu_rows_blocks(int64_t Nn) { return (Nn + kRB - 1) / kRB; }
+int64_t mu_rows_split_floats(int64_t Nn, int64_t R) { return kMuSplitMax * Nn * R; }
 
 // out[e] = sum_{b < nparts} part[b][e], blocks added in order (loads issued 8 at a time).
 __global__ __launch_bounds__(256) void sum_parts_k(const float *__restrict__ part, int nparts,
