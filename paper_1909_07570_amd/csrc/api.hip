@@ -296,7 +296,7 @@ static nnc_status factor_block(const TuckerBufs &b, int n, const float *Y, const
                                float *A, double eps, float *grad, hipStream_t s) {
   const TuckerPlan &p = *b.p;
   const int64_t pre = prod(p.R, 0, n), post = prod(p.R, n + 1, p.d);
-  NNC_TRY(launch_contract_except(Y, G, pre, p.N[n], p.R[n], post, b.num(), s));
+  if (!p.fast || !grad) NNC_TRY(launch_contract_except(Y, G, pre, p.N[n], p.R[n], post, b.num(), s));
   if (p.fast) {  // M_n by the core step of the fused sweep (every Gram is current)
     CoreArgsHost h;
     memset(&h, 0, sizeof h);
@@ -318,6 +318,9 @@ static nnc_status factor_block(const TuckerBufs &b, int n, const float *Y, const
     NNC_TRY(core_chain(b, G, n, nullptr, &H, s));
     NNC_TRY(launch_contract_except(H, G, pre, p.R[n], p.R[n], post, b.M(), s));
   }
+  if (grad && p.fast)  // grad = A_n M_n - num_n by the row kernel (num formed there)
+    return launch_mu_rows(Y, G, A, b.M(), pre, p.N[n], post, p.R[n], 0.0, b.clips(), nullptr, nullptr, grad, s,
+                          b.npart());
   if (grad) {
     NNC_TRY(launch_matmul_small(A, b.M(), p.N[n], p.R[n], p.R[n], b.den(), s));
     NNC_TRY(launch_sub(b.den(), b.num(), grad, p.N[n] * p.R[n], s));
@@ -1355,7 +1358,13 @@ nnc_status nntucker_grad(const void *X, nnc_dtype xdt, int ndim, const int64_t *
   TuckerBufs b{(char *)workspace, &p};
   const int d = ndim;
   float *const *A = const_cast<float *const *>(factors);
-  for (int k = 0; k < d; ++k) NNC_TRY(launch_gram(A[k], p.N[k], p.R[k], b.S(k), s));
+  if (p.fast) {
+    float *Sk[kMaxDim];
+    for (int k = 0; k < d; ++k) Sk[k] = b.S(k);
+    NNC_TRY(launch_gram_set(d, A, p.N, p.R, Sk, s));
+  } else {
+    for (int k = 0; k < d; ++k) NNC_TRY(launch_gram(A[k], p.N[k], p.R[k], b.S(k), s));
+  }
   // factors 0..d-2 from P = X x_{d-1} A_{d-1}^T (all factors held fixed)
   NNC_TRY(launch_ttm(X, xdt, p.size / p.N[d - 1], p.N[d - 1], 1, A[d - 1], p.R[d - 1], 1, p.R[d - 1],
                      b.P(), s, true));
@@ -1388,9 +1397,17 @@ nnc_status nntucker_grad(const void *X, nnc_dtype xdt, int ndim, const int64_t *
     NNC_TRY(ttm_f32(Y, d, cur, d - 1, A[d - 1], p.R[d - 1], b.G(2), s));
   else
     NNC_TRY(ttm_mode(Y, NNC_F32, d, cur, d - 1, A[d - 1], p.R[d - 1], b.G(2), s, false));
-  const float *den = nullptr;
-  NNC_TRY(core_chain(b, core, -1, b.G(3), &den, s));
-  NNC_TRY(launch_sub(den, b.G(2), grad_core, p.gsize, s));
+  nnc_status cst = NNC_EUNSUPPORTED;
+  if (p.fast) {  // den_G - num_G slice by slice
+    CoreArgsHost h = core_args(b, const_cast<float *>(core), A, 0.0);
+    cst = launch_core_grad(h, grad_core, s);
+    if (cst != NNC_EUNSUPPORTED) NNC_TRY(cst);
+  }
+  if (cst == NNC_EUNSUPPORTED) {
+    const float *den = nullptr;
+    NNC_TRY(core_chain(b, core, -1, b.G(3), &den, s));
+    NNC_TRY(launch_sub(den, b.G(2), grad_core, p.gsize, s));
+  }
   if (loss) {
     NNC_TRY(tucker_resid(b, X, xdt, core, factors, s));
     double red[2];

@@ -41,6 +41,7 @@ struct SliceArgs {
   float *M;            // mrows_k output (R_n x R_n)
   float *T;            // denA_k output / denB_k input (gsize floats)
   const float *numG;   // denB_k: core numerator
+  float *gradG;        // denB_k: when set, gradG = den - numG instead of the update of G
   double eps;
   unsigned long long *clips;
 };
@@ -539,6 +540,10 @@ __global__ __launch_bounds__(kSliceThreads) void denB_k(SliceArgs a) {
   __syncthreads();
   unsigned int mine = 0;
   auto update = [&](int c, float den, float g, float num) {
+    if (a.gradG) {  // the gradient of the loss with respect to G (reading R1): den - num
+      a.gradG[(int64_t)i * slice + c] = den - num;
+      return;
+    }
     double dd = (double)den;
     if (dd < a.eps) {
       dd = a.eps;
@@ -857,9 +862,10 @@ static bool slice_fits(const CoreArgsHost &h, int *RMo, bool *bigo) {
 // Cores beyond kSliceMax entries whose mode slices the slice kernels can hold: the core
 // update by denA_k / denB_k (which keep one slice, not the core, in LDS) and the rows of
 // M_next by mrows_big_k.  LDS: the Grams, the reduction space and at least three slices.
-// slices G_b per mrows_big_k block at most: two measured faster than four at 16^4 (more
-// blocks, one round of loads) and the same as one
-constexpr int kBigSliceB = 2;
+// slices G_b per mrows_big_k block: enough that the R_n x ceil(R_n / nb) blocks fit the CUs
+// in one round (R_n = 32: four), at least two (at 16^4 two measured faster than four, with
+// more blocks and one round of loads, and the same as one), at most kBigSliceB
+constexpr int kBigSliceB = 8;
 
 static bool big_slice_fits(const CoreArgsHost &h, int *RMo) {
   int64_t gsize = 1;
@@ -924,7 +930,8 @@ static nnc_status big_slice_step(const CoreArgsHost &h, hipStream_t s) {
     const int Rn = a.R[h.next];
     const int slice = a.gsize / Rn;
     const int64_t room = (160 * 1024 / 4 - (int64_t)a.d * RM * RM - SliceLds<RM>::kRed) / slice - 2;
-    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kBigSliceB, room, (int64_t)Rn}));
+    const int64_t want = std::max<int64_t>(2, ((int64_t)Rn * Rn + device_cu_count() - 1) / device_cu_count());
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>({want, (int64_t)kBigSliceB, room, (int64_t)Rn}));
     const int ngrp = (Rn + nb - 1) / nb;
     const size_t lm = sizeof(float) * ((size_t)a.d * RM * RM + SliceLds<RM>::kRed + (size_t)(2 + nb) * slice);
     NNC_TRY(allow_slice_lds(reinterpret_cast<const void *>(mrows_big_k<RM>), lm));
@@ -932,6 +939,48 @@ static nnc_status big_slice_step(const CoreArgsHost &h, hipStream_t s) {
   }
   NNC_HIP(hipGetLastError());
   return NNC_OK;
+}
+
+// dL/dG = den_G - num_G (h.numG, the core numerator) with den_G = G x_k S_k, by the slice
+// kernels (denA_k, then denB_k in its gradient form); G is left as it is.  NNC_EUNSUPPORTED
+// (no error recorded) when they do not take the core.
+template <int RM>
+static nnc_status core_grad_step(const CoreArgsHost &h, float *grad_out, hipStream_t s) {
+  SliceArgs a = slice_args(h);
+  a.gram = -1;
+  a.T = h.t0;
+  a.n = -1;
+  const int slice0 = a.gsize / a.R[0];
+  const size_t la = SliceLds<RM>::bytes(a.d, a.gsize, slice0, false);
+  if (slice0 > kSliceMax / 2) {
+    NNC_TRY(allow_slice_lds(reinterpret_cast<const void *>(denA_k<RM, true>), la));
+    hipLaunchKernelGGL((denA_k<RM, true>), dim3(a.R[0]), dim3(kSliceThreads), la, s, a);
+  } else {
+    NNC_TRY(allow_slice_lds(reinterpret_cast<const void *>(denA_k<RM, false>), la));
+    hipLaunchKernelGGL((denA_k<RM, false>), dim3(a.R[0]), dim3(kSliceThreads), la, s, a);
+  }
+  SliceArgs b = a;
+  b.numG = h.numG;
+  b.Gout = h.G;
+  b.gradG = grad_out;
+  hipLaunchKernelGGL(denB_k, dim3(a.R[0]), dim3(kSliceThreads), 0, s, b);
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+nnc_status launch_core_grad(const CoreArgsHost &h0, float *grad_out, hipStream_t s) {
+  CoreArgsHost h = h0;
+  h.gram_from = h.gram_to = 0;
+  h.do_core = 1;
+  h.next = -1;
+  int RM;
+  bool big;
+  if (!grad_out || !h.numG || !h.t0) return NNC_EUNSUPPORTED;
+  if (!slice_fits(h, &RM, &big) && !big_slice_fits(h, &RM)) return NNC_EUNSUPPORTED;
+  if (RM == 8) return core_grad_step<8>(h, grad_out, s);
+  if (RM == 16) return core_grad_step<16>(h, grad_out, s);
+  if (RM == 24) return core_grad_step<24>(h, grad_out, s);
+  return core_grad_step<32>(h, grad_out, s);
 }
 
 nnc_status launch_slice_step(const CoreArgsHost &h, hipStream_t s) {

@@ -265,8 +265,7 @@ nnc_status launch_cp_mu(float *B, const float *M, const float *S, int d, int n, 
 // round of coalesced loads: read from global memory, the sum waited on one load latency per
 // few rows.
 constexpr int kGramLds = 8192;  // floats of A staged per chunk
-__global__ __launch_bounds__(1024) void gram_block_k(const float *__restrict__ A, int64_t N, int r,
-                                                     float *__restrict__ S) {
+static __device__ void gram_block_body(const float *__restrict__ A, int64_t N, int r, float *__restrict__ S) {
   __shared__ float part[1024];
   __shared__ float As[kGramLds];
   const int tid = threadIdx.x;
@@ -307,9 +306,54 @@ __global__ __launch_bounds__(1024) void gram_block_k(const float *__restrict__ A
   }
 }
 
+__global__ __launch_bounds__(1024) void gram_block_k(const float *__restrict__ A, int64_t N, int r,
+                                                     float *__restrict__ S) {
+  gram_block_body(A, N, r, S);
+}
+
+// The Grams of several factors at once, block k taking factor k.
+struct GramSet {
+  const float *A[kMaxDim];
+  float *S[kMaxDim];
+  int64_t N[kMaxDim];
+  int r[kMaxDim];
+};
+__global__ __launch_bounds__(1024) void gram_set_k(GramSet g) {
+  const int k = blockIdx.x;
+  const float *A = nullptr;
+  float *S = nullptr;
+  int64_t N = 0;
+  int r = 1;
+#pragma unroll
+  for (int j = 0; j < kMaxDim; ++j)  // selects by unrolled compares: no dynamic argument indexing
+    if (j == k) {
+      A = g.A[j];
+      S = g.S[j];
+      N = g.N[j];
+      r = g.r[j];
+    }
+  gram_block_body(A, N, r, S);
+}
+
 nnc_status launch_gram_block(const float *A, int64_t N, int r, float *S, hipStream_t s) {
   if (r < 1 || r > 32) return fail(NNC_EUNSUPPORTED, "rank %d outside [1, 32]", r);
   hipLaunchKernelGGL(gram_block_k, dim3(1), dim3(1024), 0, s, A, N, r, S);
+  NNC_HIP(hipGetLastError());
+  return NNC_OK;
+}
+
+nnc_status launch_gram_set(int d, const float *const *A, const int64_t *N, const int64_t *R, float *const *S,
+                           hipStream_t s) {
+  GramSet g;
+  memset(&g, 0, sizeof g);
+  for (int k = 0; k < d; ++k) {
+    if (R[k] < 1 || R[k] > 32) return NNC_EUNSUPPORTED;
+    g.A[k] = A[k];
+    g.S[k] = S[k];
+    g.N[k] = N[k];
+    g.r[k] = (int)R[k];
+  }
+  hipLaunchKernelGGL(gram_set_k, dim3(d), dim3(1024), 0, s, g);
   NNC_HIP(hipGetLastError());
   return NNC_OK;
 }

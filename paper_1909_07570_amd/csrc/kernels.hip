@@ -464,10 +464,11 @@ int resid_stream_max_blocks() { return kResidMaxBlocks; }
 // kResidRows rows: the tile's W rows go to LDS, each thread keeps the factor rows of its
 // columns k = t + 256 j (j < kResidCols) in registers and reads X along rows (coalesced).
 // Each difference is formed and squared in FP64; sums are FP64 per thread, then per block.
+// Rows past M are read clamped and left out of the sums by a predicate (not a loop exit), so
+// the products of the tile's rows can interleave.
 constexpr int kResidRows = 16;
-constexpr int kResidCols = 2;  // columns per thread per chunk (chunk = 512 columns)
 
-template <typename XT, int RB>
+template <typename XT, int RB, int kResidCols>  // columns per thread per chunk (1 when K <= 256)
 __global__ __launch_bounds__(kResidThreads) void resid_stream_k(const XT *__restrict__ X, int64_t M,
                                                                 int64_t K, const float *__restrict__ W,
                                                                 const float *__restrict__ Ad,
@@ -509,7 +510,7 @@ __global__ __launch_bounds__(kResidThreads) void resid_stream_k(const XT *__rest
       __syncthreads();
 #pragma unroll
       for (int row = 0; row < kResidRows; ++row) {
-        if (m0 + row >= M) break;
+        const bool rv = m0 + row < M;
         const float4 *w4 = reinterpret_cast<const float4 *>(&Ws[row][0]);
         float xh[kResidCols];
 #pragma unroll
@@ -527,7 +528,7 @@ __global__ __launch_bounds__(kResidThreads) void resid_stream_k(const XT *__rest
         }
 #pragma unroll
         for (int j = 0; j < kResidCols; ++j) {
-          if (!kv[j]) continue;
+          if (!kv[j] || !rv) continue;
           const double df = (double)xv[row][j] - (double)xh[j];
           sr += df * df;
           sx += (double)xv[row][j] * (double)xv[row][j];
@@ -606,9 +607,15 @@ nnc_status launch_resid_stream(const void *X, nnc_dtype xdt, int64_t M, int64_t 
   }
   const int64_t ntile = (M + kResidRows - 1) / kResidRows;
   const int grid = (int)std::min<int64_t>(std::max<int64_t>(ntile, 1), kResidMaxBlocks);
-#define NNC_RES(XT, RBV)                                                                          \
-  hipLaunchKernelGGL((resid_stream_k<XT, RBV>), dim3(grid), dim3(kResidThreads), 0, s,           \
-                     (const XT *)X, M, K, W, Ad, (int)R, part)
+#define NNC_RES(XT, RBV)                                                                              \
+  do {                                                                                                \
+    if (K <= kResidThreads)                                                                           \
+      hipLaunchKernelGGL((resid_stream_k<XT, RBV, 1>), dim3(grid), dim3(kResidThreads), 0, s,         \
+                         (const XT *)X, M, K, W, Ad, (int)R, part);                                   \
+    else                                                                                              \
+      hipLaunchKernelGGL((resid_stream_k<XT, RBV, 2>), dim3(grid), dim3(kResidThreads), 0, s,         \
+                         (const XT *)X, M, K, W, Ad, (int)R, part);                                   \
+  } while (0)
 #define NNC_RES2(XT)                    \
   do {                                  \
     if (R <= 8) NNC_RES(XT, 8);         \

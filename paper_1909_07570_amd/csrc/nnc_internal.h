@@ -249,6 +249,9 @@ struct CoreArgsHost {
   float *u_out;  // launch_small_with_core: also U = G x_0 S_0 ... x_{d-2} S_{d-2} here (R_0 blocks)
 };
 nnc_status launch_core_step(const CoreArgsHost &h, hipStream_t s);
+// dL/dG = G x_k S_k - h.numG into grad_out by the slice kernels (G unchanged); NNC_EUNSUPPORTED
+// (no error recorded) for cores they do not take.
+nnc_status launch_core_grad(const CoreArgsHost &h, float *grad_out, hipStream_t s);
 // The core update in one launch (numerator from h.gpart, Gram of the last factor from its
 // partials, den_G = U x_{d-1} S_{d-1} with U in h.t0, formed by launch_small_with_core).
 nnc_status launch_core_last(const CoreArgsHost &h, hipStream_t s);
@@ -265,6 +268,9 @@ int64_t diag_part_floats(int64_t A, int64_t Nt, int64_t C, int r);
 nnc_status launch_cp_mu(float *B, const float *M, const float *S, int d, int n, int64_t N, int r,
                         double eps, unsigned long long *clips, hipStream_t s);
 nnc_status launch_gram_block(const float *A, int64_t N, int r, float *S, hipStream_t s);
+// S[k] = A[k]^T A[k] for k < d in one launch (one workgroup per factor, R[k] <= 32).
+nnc_status launch_gram_set(int d, const float *const *A, const int64_t *N, const int64_t *R, float *const *S,
+                           hipStream_t s);
 bool nmf_block_fits(int rows, int cols, int m);
 nnc_status launch_nmf_block(int n, const float *const *A, const int *rows, int cols, const int *m,
                             int iters, float *const *W, float *const *H, double eps,

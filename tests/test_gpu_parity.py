@@ -452,9 +452,16 @@ def test_batched_tuner_persists_and_reuses(tmp_path, monkeypatch):
 
 
 # ------------------------------------------------------------------------------ adjoint
-def test_gradient_matches_oracle():
+@pytest.mark.parametrize("dims,ranks", [((24, 20, 18), (4, 5, 3)),
+                                        # cores beyond the whole-core kernels; factor rows
+                                        # with the contracted index split over blocks
+                                        ((20, 18, 17, 19), (16, 16, 16, 16)),
+                                        ((10, 9, 8, 9, 10), (8, 8, 8, 8, 8)),
+                                        ((40, 36, 34), (32, 32, 32))])
+def test_gradient_matches_oracle(dims, ranks):
     nnc = need_gpu()
-    X, _, G0, A0 = problem(17, (24, 20, 18), 3, (4, 5, 3))
+    print("case", dims, ranks, flush=True)
+    X, _, G0, A0 = problem(17, dims, 3, ranks)
     L, gG, gA = nnc.nntucker_grad(dev(X), dev(G0), [dev(a) for a in A0])
     Lo, gGo, gAo = oracle.tucker_grad(X.astype(np.float64), G0, A0)
     assert abs(L - Lo) <= 1e-6 * Lo
