@@ -987,6 +987,8 @@ nnc_status launch_slice_step(const CoreArgsHost &h, hipStream_t s) {
   int RM;
   bool big;
   if (!slice_fits(h, &RM, &big)) {
+    // NNC_NO_BIG_SLICES in the environment leaves large cores to the grid-wide steps (for
+    // comparisons: the tests check that both give the same sweeps)
     if (getenv("NNC_NO_BIG_SLICES") || !big_slice_fits(h, &RM)) return NNC_EUNSUPPORTED;
     if (RM == 8) return big_slice_step<8>(h, s);
     if (RM == 16) return big_slice_step<16>(h, s);
