@@ -50,7 +50,7 @@ COUNTERS = os.path.join(ROOT, "profiles", "pass_counters_512cubed.json")
 N_COPY = 128 << 20
 # The R = 20 (two 16-wide rank tiles) instantiations of the four pass kernels, X bytes per entry.
 PASS_BYTES = (("ttm_last_lds_k<true, 2", 512 ** 3 * 2 + 512 * 512 * 20 * 4),
-              ("ttm_mid_lds_k<2>", 512 ** 3 * 2 + 512 * 512 * 20 * 4),
+              ("ttm_mid_lds_k<2, false>", 512 ** 3 * 2 + 512 * 512 * 20 * 4),
               ("ttm_last_lds_k<false, 2", 512 ** 3 * 4 + 512 * 512 * 20 * 4),
               ("ttm_mid_lds_f32_k<2", 512 ** 3 * 4 + 512 * 512 * 20 * 4),
               # fused three-way passes of the BF16 fit: X once, plus Y_0 (pass 1) or T and Y_1 (pass 2)
@@ -202,7 +202,7 @@ def summarize(args):
     print(json.dumps(res, indent=1))
 
 
-PASS_KEYS = (("ttm_last_lds_k<true, 2", "bf16"), ("ttm_mid_lds_k<2>", "bf16"),
+PASS_KEYS = (("ttm_last_lds_k<true, 2", "bf16"), ("ttm_mid_lds_k<2, false>", "bf16"),
              ("ttm_last_lds_k<false, 2", "f32"), ("ttm_mid_lds_f32_k<2", "f32"),
              ("pass1y_k", "bf16"), ("pass2y_k", "bf16"))
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}

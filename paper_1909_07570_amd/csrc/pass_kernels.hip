@@ -188,7 +188,7 @@ constexpr int kMidWaves = 8;
 constexpr int kMidDepth = 1;
 constexpr int kMidDepthF32 = 1;  // steps in flight per wave, FP32 X (one measured fastest, as for bf16)
 
-template <int RT>
+template <int RT, bool HS>
 __global__ __launch_bounds__(64 * kMidWaves) void ttm_mid_lds_k(const uint16_t *__restrict__ X,
                                                                int64_t P, int N, int64_t Q,
                                                                const float *__restrict__ F,
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(64 * kMidWaves) void ttm_mid_lds_k(const uint16_t *
   const int64_t qt = (Q + 127) >> 7;
   const int64_t ntile = P * qt;
   const int nsteps = Np >> 5;
-  float *stg = reinterpret_cast<float *>(lds_b + 2 * RP * NS * 2) + wave * (R * 128);
+  float *stg = reinterpret_cast<float *>(lds_b + 2 * RP * NS * 2) + wave * (R * (HS ? 64 : 128));
   u4 v[kMidDepth][8];
   const uint16_t *xp = X;  // lane's column of the current tile
   int nlim = 0;            // last row a load may touch (0: one line, for loads past the work)
@@ -309,36 +309,77 @@ __global__ __launch_bounds__(64 * kMidWaves) void ttm_mid_lds_k(const uint16_t *
 #pragma unroll
     for (int b = 0; b < kMidDepth; ++b) load(v[b], b);
     __builtin_amdgcn_sched_barrier(0);
+    if (!HS) {
 #pragma unroll
-    for (int nt = 0; nt < RT; ++nt) {
-      const int r = nt * 16 + li;
-      if (r < R) {
+      for (int nt = 0; nt < RT; ++nt) {
+        const int r = nt * 16 + li;
+        if (r < R) {
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          const int qq = 32 * lg + 8 * jj;
-          *reinterpret_cast<f4 *>(stg + r * 128 + qq) =
-              f4{acc[0][nt][jj], acc[1][nt][jj], acc[2][nt][jj], acc[3][nt][jj]};
-          *reinterpret_cast<f4 *>(stg + r * 128 + qq + 4) =
-              f4{acc[4][nt][jj], acc[5][nt][jj], acc[6][nt][jj], acc[7][nt][jj]};
+          for (int jj = 0; jj < 4; ++jj) {
+            const int qq = 32 * lg + 8 * jj;
+            *reinterpret_cast<f4 *>(stg + r * 128 + qq) =
+                f4{acc[0][nt][jj], acc[1][nt][jj], acc[2][nt][jj], acc[3][nt][jj]};
+            *reinterpret_cast<f4 *>(stg + r * 128 + qq + 4) =
+                f4{acc[4][nt][jj], acc[5][nt][jj], acc[6][nt][jj], acc[7][nt][jj]};
+          }
         }
       }
-    }
-    __builtin_amdgcn_wave_barrier();  // the wave reads back only what it wrote
-    for (int rr = 0; rr < R; rr += 2) {
-      const int r = rr + (lane >> 5);
-      const int qq = (lane & 31) * 4;
-      if (r < R && q0 + qq < Q) {
-        f4 *o = reinterpret_cast<f4 *>(out + (p * R + r) * Q + q0 + qq);
-        f4 val = *reinterpret_cast<const f4 *>(stg + r * 128 + qq);
-        if (acc_out) {
-          val += *o;  // a later chunk of the contracted index: added in chunk order
-          *o = val;
-        } else {
-          __builtin_nontemporal_store(val, o);
+      __builtin_amdgcn_wave_barrier();  // the wave reads back only what it wrote
+      for (int rr = 0; rr < R; rr += 2) {
+        const int r = rr + (lane >> 5);
+        const int qq = (lane & 31) * 4;
+        if (r < R && q0 + qq < Q) {
+          f4 *o = reinterpret_cast<f4 *>(out + (p * R + r) * Q + q0 + qq);
+          f4 val = *reinterpret_cast<const f4 *>(stg + r * 128 + qq);
+          if (acc_out) {
+            val += *o;  // a later chunk of the contracted index: added in chunk order
+            *o = val;
+          } else {
+            __builtin_nontemporal_store(val, o);
+          }
         }
       }
+      __builtin_amdgcn_wave_barrier();
+    } else {
+      // half staging (large R): columns 64 h .. 64 h + 63 of the tile in turn; lanes with
+      // lg >> 1 == h hold them (column 32 (lg & 1) + 8 jj + c of the half)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if ((lg >> 1) == h) {
+#pragma unroll
+          for (int nt = 0; nt < RT; ++nt) {
+            const int r = nt * 16 + li;
+            if (r < R) {
+#pragma unroll
+              for (int jj = 0; jj < 4; ++jj) {
+                const int qq = 32 * (lg & 1) + 8 * jj;
+                *reinterpret_cast<f4 *>(stg + r * 64 + qq) =
+                    f4{acc[0][nt][jj], acc[1][nt][jj], acc[2][nt][jj], acc[3][nt][jj]};
+                *reinterpret_cast<f4 *>(stg + r * 64 + qq + 4) =
+                    f4{acc[4][nt][jj], acc[5][nt][jj], acc[6][nt][jj], acc[7][nt][jj]};
+              }
+            }
+          }
+        }
+        __builtin_amdgcn_wave_barrier();  // the wave reads back only what it wrote
+        for (int rr = 0; rr < R; rr += 4) {
+          const int r = rr + (lane >> 4);
+          const int qq = (lane & 15) * 4;
+          const int64_t qc = q0 + 64 * h + qq;
+          if (r < R && qc < Q) {
+            f4 *o = reinterpret_cast<f4 *>(out + (p * R + r) * Q + qc);
+            f4 val = *reinterpret_cast<const f4 *>(stg + r * 64 + qq);
+            if (acc_out) {
+              val += *o;
+              *o = val;
+            } else {
+              __builtin_nontemporal_store(val, o);
+            }
+          }
+        }
+        __builtin_amdgcn_wave_barrier();  // the half is read before the next one overwrites it
+      }
     }
-    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -723,9 +764,9 @@ size_t pass_last_lds(bool bf, int RT, int64_t K) {
 
 // Earlier-mode kernels: the factor (bf16 hi / lo rows, or FP32 rows) plus each wave's
 // output staging.
-size_t pass_mid_lds(bool bf, int RT, int64_t N, int64_t R) {
+size_t pass_mid_lds(bool bf, int RT, int64_t N, int64_t R, bool hs) {
   const int64_t Np = (N + 31) / 32 * 32;
-  if (bf) return (size_t)(2 * 16 * RT * (Np + 8) * 2 + (int64_t)kMidWaves * R * 128 * 4);
+  if (bf) return (size_t)(2 * 16 * RT * (Np + 8) * 2 + (int64_t)kMidWaves * R * (hs ? 64 : 128) * 4);
   return (size_t)(Np * (16 * RT + 2) * 4 + (int64_t)kMidWaves * R * 64 * 4);
 }
 
@@ -860,16 +901,19 @@ nnc_status launch_pass(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64
     // earlier mode: ttm_mid_lds_k (bf16 X) / ttm_mid_lds_f32_k (FP32 X)
     if (Q % (bf ? 8 : 4)) return NNC_EUNSUPPORTED;
     if (N > (1 << 20) || N * ldl + R * ldr >= ((int64_t)1 << 31)) return NNC_EUNSUPPORTED;  // 32-bit factor indexing
-    // rows of the factor per launch: all of them, or chunks of a multiple of 32
+    // bf16 output staging by halves of the tile when the whole tile's does not fit beside the
+    // factor (R above 20 at N = 512); rows of the factor per launch: all of them, or chunks of
+    // a multiple of 32
+    const bool hs = bf && pass_mid_lds(bf, RT, N, R, false) > kCuLdsBytes;
     int64_t Nc = N;
-    if (pass_mid_lds(bf, RT, N, R) > kCuLdsBytes) {
+    if (pass_mid_lds(bf, RT, N, R, hs) > kCuLdsBytes) {
       int64_t Nmax = 0;
-      while (pass_mid_lds(bf, RT, Nmax + 32, R) <= kCuLdsBytes) Nmax += 32;
+      while (pass_mid_lds(bf, RT, Nmax + 32, R, hs) <= kCuLdsBytes) Nmax += 32;
       if (Nmax == 0) return NNC_EUNSUPPORTED;
       const int64_t nch = (N + Nmax - 1) / Nmax;
       Nc = ((N + nch - 1) / nch + 31) / 32 * 32;
     }
-    const size_t lds = pass_mid_lds(bf, RT, Nc, R);
+    const size_t lds = pass_mid_lds(bf, RT, Nc, R, hs);
     const int64_t tiles = P * ((Q + (bf ? 127 : 63)) / (bf ? 128 : 64));
     int grid = (int)std::min<int64_t>((tiles + kMidWaves - 1) / kMidWaves, device_cu_count());
     if (grid < 1) grid = 1;
@@ -886,8 +930,10 @@ nnc_status launch_pass(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64
   } while (0)
       if (bf) {
 #define XARG (const uint16_t *)Xc
-        if (RT == 1) NNC_MID(ttm_mid_lds_k<1>);
-        else NNC_MID(ttm_mid_lds_k<2>);
+        if (RT == 1 && !hs) NNC_MID((ttm_mid_lds_k<1, false>));
+        else if (RT == 1) NNC_MID((ttm_mid_lds_k<1, true>));
+        else if (!hs) NNC_MID((ttm_mid_lds_k<2, false>));
+        else NNC_MID((ttm_mid_lds_k<2, true>));
 #undef XARG
       } else {
 #define XARG (const float *)Xc

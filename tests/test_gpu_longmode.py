@@ -25,7 +25,9 @@ def _fibre_err(out, ref, n):
 
 
 CASES = [((1024, 512, 512), 0, 20), ((512, 512, 1024), 2, 20), ((64, 1024, 256), 1, 20),
-         ((256, 256, 256), 0, 32), ((256, 256, 256), 2, 32), ((800, 64, 800), 0, 20), ((800, 64, 800), 2, 20)]
+         ((256, 256, 256), 0, 32), ((256, 256, 256), 2, 32), ((800, 64, 800), 0, 20), ((800, 64, 800), 2, 20),
+         # earlier-mode bf16 pass with its output staged by halves of the tile (R above 20)
+         ((512, 512, 512), 0, 24), ((512, 384, 512), 1, 32)]
 
 
 @pytest.mark.parametrize("shape,mode,R", CASES)
@@ -60,6 +62,9 @@ def test_chunked_passes_report_chunks():
     nnc.nnc_ttm(Xb, 2, dev(np.ones((1024, 20), dtype=np.float32)))
     assert nnc.last_ttm_kernel() == "ttm_last_lds_bf16 (chunked)"
     nnc.nnc_ttm(Xb, 0, dev(np.ones((512, 20), dtype=np.float32)))
+    assert nnc.last_ttm_kernel() == "ttm_mid_bf16"
+    # R = 32 at N = 512: the tile's output staged by halves, one launch (no chunks)
+    nnc.nnc_ttm(Xb, 0, dev(np.ones((512, 32), dtype=np.float32)))
     assert nnc.last_ttm_kernel() == "ttm_mid_bf16"
 
 
