@@ -68,7 +68,7 @@ static int64_t cp_lds_floats(const CpArgs &a, int r, int threads, bool t_lds, bo
 // Every per-mode array below is indexed only by loop counters of fully unrolled loops over
 // kMaxDim, so it lives in registers (no scratch memory); factor blocks are addressed by
 // offsets kept in LDS.
-template <int RM, bool ALS>
+template <int RM, bool ALS, int DC>
 __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpArgs a, int rank0,
                                                CpPtrs ptr0, const int *__restrict__ ranks,
                                                float *const *__restrict__ fptrs, int iters,
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
   const int b = blockIdx.x;
   const int r = ranks ? ranks[b] : rank0;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int d = a.d;
+  const int d = DC > 0 ? DC : a.d;  // DC > 0: the order fixed at compile time
   float *p = sm;
   const float *T = Tg;
   if (a.t_lds) {
@@ -505,11 +505,24 @@ nnc_status launch_nncp(const float *T, const CpProblem &pb, int nbatch, const in
   CpPtrs p0;
   for (int k = 0; k < kMaxDim; ++k) p0.p[k] = (single_ptrs && k < pb.d) ? single_ptrs[k] : nullptr;
   const size_t lds = (size_t)L.lds_bytes;
-#define NNC_CP_LAUNCH(RM, ALSV)                                                                   \
-  do {                                                                                            \
-    NNC_TRY(allow_lds(reinterpret_cast<const void *>(nncp_k<RM, ALSV>), L.lds_bytes));            \
-    hipLaunchKernelGGL((nncp_k<RM, ALSV>), dim3(nbatch), dim3(threads), lds, s, T, L.a, max_rank, \
-                       p0, d_ranks, d_factor_ptrs, iters, eps, d_resid, clips, zscratch);         \
+  // Orders 2 to 5 have kernels of their own: with the order a constant, the loops over modes
+  // unroll and their index bookkeeping folds away (300 sweeps of a 20^3 core at rank 10:
+  // 4.3 -> 3.3 ms).
+#define NNC_CP_LAUNCH3(RM, ALSV, DCV)                                                                  \
+  do {                                                                                                 \
+    NNC_TRY(allow_lds(reinterpret_cast<const void *>(nncp_k<RM, ALSV, DCV>), L.lds_bytes));            \
+    hipLaunchKernelGGL((nncp_k<RM, ALSV, DCV>), dim3(nbatch), dim3(threads), lds, s, T, L.a, max_rank, \
+                       p0, d_ranks, d_factor_ptrs, iters, eps, d_resid, clips, zscratch);              \
+  } while (0)
+#define NNC_CP_LAUNCH(RM, ALSV)                  \
+  do {                                           \
+    switch (pb.d) {                              \
+      case 2: NNC_CP_LAUNCH3(RM, ALSV, 2); break; \
+      case 3: NNC_CP_LAUNCH3(RM, ALSV, 3); break; \
+      case 4: NNC_CP_LAUNCH3(RM, ALSV, 4); break; \
+      case 5: NNC_CP_LAUNCH3(RM, ALSV, 5); break; \
+      default: NNC_CP_LAUNCH3(RM, ALSV, 0);      \
+    }                                            \
   } while (0)
   if (als) {
     if (max_rank <= 8)
@@ -527,6 +540,7 @@ nnc_status launch_nncp(const float *T, const CpProblem &pb, int nbatch, const in
       NNC_CP_LAUNCH(32, false);
   }
 #undef NNC_CP_LAUNCH
+#undef NNC_CP_LAUNCH3
   NNC_HIP(hipGetLastError());
   return NNC_OK;
 }
