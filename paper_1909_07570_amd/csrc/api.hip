@@ -114,7 +114,7 @@ struct TuckerPlan {
   int64_t nP = 0, nT = 0, nU = 0, nC = 0, nY = 0, nNum = 0, nS = 0, nM = 0, nGp = 0, nGr = 0, nNp = 0;
   bool fast = false;  // every multirank <= 32: fused small-step kernels
   size_t oP, oT, oU0, oU1, oC0, oC1, oY, oNum, oDen, oS, oM, oG0, oG1, oG2, oG3, oGp, oGr, oNp, oClip,
-      oFlag, oRed, oPart, oLsT, oLsL, oLsS, total;
+      oFlag, oTicket, oRed, oPart, oLsT, oLsL, oLsS, total;
 };
 
 static void grow(int64_t &v, int64_t x) {
@@ -188,6 +188,7 @@ static TuckerPlan plan_tucker(int d, const int64_t *dims, const int64_t *rk) {
   p.oNp = L.take(sizeof(float) * p.nNp);
   p.oClip = L.take(sizeof(unsigned long long));
   p.oFlag = L.take(sizeof(unsigned int));
+  p.oTicket = L.take(sizeof(unsigned int));
   p.oRed = L.take(2 * sizeof(double));
   p.oPart = L.take(2 * sizeof(double) * resid_stream_max_blocks());
   p.oLsT = L.take(sizeof(double) * 32 * 32);         // the real-valued fit's R x R transform,
@@ -223,6 +224,7 @@ struct TuckerBufs {
   float *gram() const { return f(p->oGr); }
   unsigned long long *clips() const { return reinterpret_cast<unsigned long long *>(base + p->oClip); }
   unsigned int *flag() const { return reinterpret_cast<unsigned int *>(base + p->oFlag); }
+  unsigned int *ticket() const { return reinterpret_cast<unsigned int *>(base + p->oTicket); }
   double *red() const { return reinterpret_cast<double *>(base + p->oRed); }
   double *part() const { return reinterpret_cast<double *>(base + p->oPart); }
   double *lsT() const { return reinterpret_cast<double *>(base + p->oLsT); }
@@ -585,6 +587,7 @@ static Side3 side3(const TuckerBufs &b, const float *G, int n) {
   sd.G = G;
   sd.M = b.M();
   sd.gmode = -1;
+  sd.ticket = b.ticket();
   return sd;
 }
 
@@ -1102,6 +1105,7 @@ static nnc_status tucker_fit_impl(bool ls, const void *X, nnc_dtype xdt, int ndi
   TuckerBufs b{(char *)o.workspace, &p};
   NNC_HIP(hipMemsetAsync(b.clips(), 0, sizeof(unsigned long long), s));
   NNC_HIP(hipMemsetAsync(b.flag(), 0, sizeof(unsigned int), s));
+  NNC_HIP(hipMemsetAsync(b.ticket(), 0, sizeof(unsigned int), s));
   if (ls)  // orthonormal initial factors (A_n = Q R, G <- G x_n R: the same initial model)
     for (int k = 0; k < ndim; ++k)
       NNC_TRY(ls_orthonormalize(b, k, core, factors[k], s));

@@ -15,10 +15,10 @@
 //              FP32 MFMA over the tile's columns; the waves holding the tiles of one i1 row
 //              add their partial sums in wave order through LDS.
 //
-// Each pass also runs a side job in its first blocks, beside the stream: row blockIdx.x of
-// the next mode's R x R matrix M_n = unfold_n(G x_{k!=n} S_k) unfold_n(G)^T (and, for pass 2,
-// the new Gram S_0 summed from the row-block partials of the mode-0 update), so that the
-// update of mode n needs no launch of its own for it.
+// Each pass also runs a side job in the first blocks to finish their share of the stream:
+// one row each of the next mode's R x R matrix M_n = unfold_n(G x_{k!=n} S_k) unfold_n(G)^T
+// (and, for pass 2, the new Gram S_0 summed from the row-block partials of the mode-0
+// update), so that the update of mode n needs no launch of its own for it.
 //
 // X is bfloat16 (v_mfma_f32_16x16x32_bf16 with FP32 accumulation, the factor applied as a
 // bf16 hi + lo pair); FP32 X takes the general schedule, whose FP32 passes measured faster
@@ -66,13 +66,13 @@ constexpr int kYS = 33;                   // row stride of a wave's 32 x 32 part
 constexpr int kYPartBytes = 32 * kYS * 4;  // bytes of one such partial
 
 // ------------------------------------------------------------------------------ side job
-// Row a = blockIdx.x of M_n for a three-way core G (R0 x R1 x R2): with p < q the two other
+// Row a of M_n for a three-way core G (R0 x R1 x R2): with p < q the two other
 // modes and G_a the R_p x R_q slice of G at i_n = a,
 //   H_a = S_p G_a S_q,   M_n[a][b] = sum_{u,v} H_a[u][v] G_b[u][v]
 // (the Grams are symmetric, so this is G x_p S_p x_q S_q restricted to the slice).  With
-// SUMMED, the Gram of mode gmode is first summed from its row-block partials and block 0
-// stores it.  issue() starts every global read the job needs, as wide coalesced loads (the
-// pass calls it right after its first X loads); finish() consumes them:
+// SUMMED, the Gram of mode gmode is first summed from its row-block partials and the job of
+// row 0 stores it.  issue() starts every global read the job needs, as wide coalesced loads;
+// finish() consumes them:
 //   - G goes to LDS in the mode-n unfolding Gn[b][u * R_q + v];
 //   - the partials: entry groups of 4 (or single entries), each group's partials split into
 //     nch contiguous chunks added in order, then the chunks added in order;
@@ -91,11 +91,12 @@ struct SideJob {
   float4 pv[SUMMED ? kSidePB : 1];
   float4 gq[kSideG4];
   float sv[2][2];
-  int p, q, Rp, Rq, Rn, RPQ, gsize, RR, Rg, W, ngrp, nch, ch, grp, b0, b1;
+  int p, q, Rp, Rq, Rn, RPQ, gsize, RR, Rg, W, ngrp, nch, ch, grp, b0, b1, row;
   bool vec, pact;
 
-  __device__ void issue(const Side3 &a) {
+  __device__ void issue(const Side3 &a, int ia) {
     const int tid = threadIdx.x;
+    row = ia;
     const int n = a.n;
     p = n == 0 ? 1 : 0;
     q = n == 2 ? 1 : 2;
@@ -219,7 +220,7 @@ struct SideJob {
         if (e < Rk * Rk) dst[(e / Rk) * kYS + e % Rk] = sv[which][u];
       }
     }
-    const int ia = blockIdx.x;
+    const int ia = row;
     for (int e = tid; e < RPQ; e += kYThreads) Ga[(e / Rq) * kYS + e % Rq] = Gn[ia * RPQ + e];
     __syncthreads();
     if (SUMMED) {  // chunks in order, into the LDS Gram of mode gmode
@@ -237,7 +238,7 @@ struct SideJob {
         for (int w = 0; w < W; ++w) {
           const int e = g * W + w;
           dst[(e / Rg) * kYS + e % Rg] = tv[w];
-          if (blockIdx.x == 0) a.S_store[e] = tv[w];
+          if (row == 0) a.S_store[e] = tv[w];
         }
       }
       __syncthreads();
@@ -280,6 +281,27 @@ struct SideJob {
     __syncthreads();
   }
 };
+
+// The side job runs after the block's share of the stream, in the first side.nrows blocks to
+// finish it (a ticket counter): the blocks end their shares a few microseconds apart, and the
+// side rows fill that spread instead of delaying the shares of fixed blocks.  Which block
+// forms a row depends on timing, the row does not.  The block that takes the last ticket
+// sets the counter back to zero.  Every wave calls it; the stream's LDS is free.
+template <bool SUMMED>
+static __device__ void side_after_stream(const Side3 &side, unsigned char *lds_b, int fbytes) {
+  unsigned int *tk = reinterpret_cast<unsigned int *>(lds_b);
+  if (threadIdx.x == 0) {
+    const unsigned int t = atomicAdd(side.ticket, 1u);
+    if (t == gridDim.x - 1) atomicExch(side.ticket, 0u);
+    *tk = t;
+  }
+  __syncthreads();
+  const int t = (int)*tk;
+  if (t >= side.nrows) return;
+  SideJob<SUMMED> sj;
+  sj.issue(side, t);
+  sj.finish(side, reinterpret_cast<float *>(lds_b + fbytes));
+}
 
 // ------------------------------------------------------------------------------ pass 1
 // Rows m = i0 * N1 + i1 of X (K = N2 contiguous bf16 values each).  A tile is 16 rows (so
@@ -439,10 +461,6 @@ __global__ __launch_bounds__(kYThreads) void pass1y_k(const uint16_t *__restrict
   load_a1(a1n, 0);
   load_piece(bb, 0);
   __builtin_amdgcn_sched_barrier(0);
-  const bool has_side = (int)blockIdx.x < side.nrows;
-  SideJob<false> sj;
-  if (has_side) sj.issue(side);
-  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int u = 0; u < kFB; ++u) fac_store(fk + u * KSTR, fv[u]);
   for (int k0 = kFB * KSTR; k0 < Kp; k0 += kFB * KSTR) {
@@ -452,7 +470,6 @@ __global__ __launch_bounds__(kYThreads) void pass1y_k(const uint16_t *__restrict
     for (int u = 0; u < kFB; ++u) fac_store(k0 + fk + u * KSTR, fv[u]);
   }
   __syncthreads();
-  if (has_side) sj.finish(side, reinterpret_cast<float *>(lds_b + fbytes));
   int i = 0;
   for (int j = 0; j < nsl; ++j) {
     for (int r = 0; r < pps; ++r, ++i) {
@@ -471,6 +488,8 @@ __global__ __launch_bounds__(kYThreads) void pass1y_k(const uint16_t *__restrict
     }
     slab_end(j);
   }
+  __syncthreads();
+  side_after_stream<false>(side, lds_b, fbytes);
 }
 
 // ------------------------------------------------------------------------------ pass 2
@@ -524,10 +543,6 @@ __global__ __launch_bounds__(kYThreads) void pass2y_k(const uint16_t *__restrict
   if (nub > 0) tile_base(tile_of(0));
   load(0);
   __builtin_amdgcn_sched_barrier(0);  // the X loads go out before the factor is staged
-  const bool has_side = (int)blockIdx.x < side.nrows;
-  SideJob<true> sj;
-  if (has_side) sj.issue(side);
-  __builtin_amdgcn_sched_barrier(0);
   {
     const int total = RP * Np;
     constexpr int kB = 8;
@@ -555,7 +570,6 @@ __global__ __launch_bounds__(kYThreads) void pass2y_k(const uint16_t *__restrict
     }
   }
   __syncthreads();
-  if (has_side) sj.finish(side, reinterpret_cast<float *>(lds_b + fbytes));
   const int cc0 = li < R2 ? li : 0, cc1 = 16 + li < R2 ? 16 + li : 0;
   const float m0 = li < R2 ? 1.f : 0.f, m1 = 16 + li < R2 ? 1.f : 0.f;
   for (int64_t j = 0; j < nub; ++j) {
@@ -713,6 +727,8 @@ __global__ __launch_bounds__(kYThreads) void pass2y_k(const uint16_t *__restrict
     }
     __syncthreads();
   }
+  __syncthreads();
+  side_after_stream<true>(side, lds_b, fbytes);
 }
 
 // ------------------------------------------------------------------------------ launchers
@@ -773,6 +789,7 @@ nnc_status launch_pass1y(const void *X, nnc_dtype dt, int64_t N0, int64_t N1, in
       (reinterpret_cast<uintptr_t>(X) & 15u) || (side.nrows > 0 && (reinterpret_cast<uintptr_t>(side.G) & 15u)))
     return fail(NNC_EUNSUPPORTED, "pass1y: unsupported shape");
   if (side.nrows > 0 && side.gram_part) return fail(NNC_EINVAL, "pass1y: its side job sums no partials");
+  if (side.nrows > 0 && !side.ticket) return fail(NNC_EINVAL, "pass1y: the side job needs its ticket counter");
   const int RT = R2 <= 16 ? 1 : 2;
   const int CPR = pass1y_cpr(N2);
   const size_t lds = pass1y_lds(RT, CPR, N2, (int64_t)side.R[0] * R1 * R2);
@@ -811,6 +828,7 @@ nnc_status launch_pass2y(const void *X, nnc_dtype dt, int64_t N0, int64_t N1, in
       (reinterpret_cast<uintptr_t>(A2) & 15u) || (side.nrows > 0 && (reinterpret_cast<uintptr_t>(side.G) & 15u)))
     return fail(NNC_EUNSUPPORTED, "pass2y: unsupported shape");
   if (side.nrows > 0 && !side.gram_part) return fail(NNC_EINVAL, "pass2y: its side job sums partials");
+  if (side.nrows > 0 && !side.ticket) return fail(NNC_EINVAL, "pass2y: the side job needs its ticket counter");
   const int RT = R0 <= 16 ? 1 : 2;
   const size_t lds = pass2y_lds(RT, N0, R0, R2, (int64_t)R0 * side.R[1] * R2);
   const int64_t units = N1 / (8 / (N2 / 128));

@@ -172,6 +172,7 @@ struct Side3 {
   int gmode, gram_parts;
   float *S_store;
   float *M;
+  unsigned int *ticket;  // zero before a launch, left zero (the side rows go to the first blocks done)
 };
 // Y0 = X x_2 A2^T x_1 A1^T (N0 x R1 x R2) without storing X x_2 A2^T.
 bool pass1y_ok(nnc_dtype dt, int64_t N0, int64_t N1, int64_t N2, int64_t R0, int64_t R1, int64_t R2);
