@@ -1,7 +1,8 @@
 """The fused three-way sweep (both X passes carrying the next small contraction, the R x R
-matrices of modes 0 and 1 formed by side blocks of the passes; bf16 X) against the FP64
+matrices of modes 0 and 1 formed by side jobs of the passes, in the first blocks to finish
+their share of the stream; bf16 X) against the FP64
 oracle and against the general fused schedule (selected by NNC_NO_FUSED3), on shapes that
-span the pass kernels' cases: several slabs per block and fewer slabs than side blocks,
+span the pass kernels' cases: several slabs per block and fewer slabs than side rows,
 ragged and padded multiranks, multiranks above the dimensions, one or two 16-column tiles,
 pass-2 units of one tile per wave and of several.  FP32 X takes the general schedule; the
 same cases run in that form too."""
@@ -19,7 +20,7 @@ pytestmark = pytest.mark.gpu
 SHAPES = [((48, 32, 256), (5, 7, 9)),
           ((40, 48, 512), (20, 20, 20)),
           ((24, 32, 128), (3, 32, 8)),       # pass 2: one tile per i1 row, 8 groups per unit
-          ((8, 32, 256), (20, 4, 20)),       # fewer slabs and units than side blocks
+          ((8, 32, 256), (20, 4, 20)),       # fewer slabs and units than side rows
           ((16, 16, 256), (20, 20, 20)),     # multirank above the first two dimensions
           ((300, 64, 256), (17, 1, 32)),     # several slabs per block, rank 1
           ((1, 16, 256), (1, 1, 1))]
