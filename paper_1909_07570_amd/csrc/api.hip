@@ -468,6 +468,15 @@ static nnc_status core_tail(const TuckerBufs &b, float *G, float *const *A, doub
 // Sweeps captured in one graph when no objective is recorded in between.
 constexpr int kSweepsPerGraph = 8;
 
+// Sweeps per graph for a run of n: a divisor of n between kSweepsPerGraph / 2 and
+// kSweepsPerGraph when there is one, so the run needs one capture instead of two (capture and
+// instantiation cost more than the extra graph launches), else kSweepsPerGraph (n at most).
+static int sweeps_per_graph(int n) {
+  for (int d = kSweepsPerGraph; d >= kSweepsPerGraph / 2; --d)
+    if (n >= d && n % d == 0) return d;
+  return std::min(n, kSweepsPerGraph);
+}
+
 // Chain of small contractions (chain_small) whose first launch also carries the core step
 // `h` (independent of the chain); without contractions the core step runs alone.
 static nnc_status chain_with_core(const TuckerBufs &b, const float *src, int d, int64_t *cur,
@@ -821,7 +830,7 @@ static hipStream_t capture_stream() {
   return st;
 }
 
-// Run `n` sweeps, each enqueued by `sweep(stream)`, captured kSweepsPerGraph at a time into
+// Run `n` sweeps, each enqueued by `sweep(stream)`, captured sweeps_per_graph(n) at a time into
 // HIP graphs when `graphs` is set (a library stream stands in for the default stream, which
 // cannot be captured).  Returns after the sweeps are enqueued on `s` (synchronised once).
 static nnc_status run_sweeps(hipStream_t s, bool graphs, int n,
@@ -857,7 +866,7 @@ static nnc_status run_sweeps(hipStream_t s, bool graphs, int n,
     if (ei != hipSuccess) return fail(NNC_EHIP, "graph instantiation failed: %s", hipGetErrorString(ei));
     return NNC_OK;
   };
-  const int per = std::min(n, kSweepsPerGraph);
+  const int per = sweeps_per_graph(n);
   hipGraphExec_t gb = nullptr, gr = nullptr;
   nnc_status st = capture(&gb, per);
   if (st == NNC_OK && n % per) st = capture(&gr, n % per);
@@ -1173,11 +1182,11 @@ static nnc_status tucker_fit_impl(bool ls, const void *X, nnc_dtype xdt, int ndi
     };
     if (!every && tb - ta > 1) {
       // several sweeps per graph: the turnaround between two graph launches (several
-      // microseconds) is paid once per kSweepsPerGraph sweeps.  An executable graph is
+      // microseconds) is paid once per sweeps_per_graph(n) sweeps.  An executable graph is
       // destroyed only after its launches have finished: its resources must not be
       // released (and reused by the next instantiation) while queued launches read them.
       const int n = tb - ta;
-      const int per = std::min(n, kSweepsPerGraph);
+      const int per = sweeps_per_graph(n);
       hipGraphExec_t gb = nullptr, gr = nullptr;
       nnc_status st = capture(&gb, per);
       if (st == NNC_OK && n % per) st = capture(&gr, n % per);
