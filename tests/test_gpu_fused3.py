@@ -90,6 +90,25 @@ def test_fused3_many_sweeps_deterministic_and_resumable(use_graph):
     assert abs(r1.rel_residual - oracle.tucker_rel_residual(X.astype(np.float64), Go, Ao)) <= 1e-4
 
 
+def test_fused3_graph_replays_match_eager_sweeps():
+    """Sweeps replayed from captured graphs (several sweeps per graph, a remainder graph) give
+    the eager sweeps' results bit for bit, with the workspace reused across the fits."""
+    nnc = need_gpu()
+    import synth
+    X, _, G0, A0 = problem(67, (40, 48, 512), 4, (20, 20, 20))
+    Xd = bf16_dev(synth.round_bf16(X.astype(np.float64)))
+    dims, ranks = X.shape, G0.shape
+    ws = torch.empty(nnc.nntucker_workspace_bytes(dims, ranks), dtype=torch.uint8, device="cuda")
+    out = []
+    for use_graph in (False, True, True):
+        G = dev(G0)
+        A = [dev(a) for a in A0]
+        nnc.nntucker_fit(Xd, ranks, 19, G, A, use_graph=use_graph, workspace=ws, report=False)
+        out.append((host(G), [host(a) for a in A]))
+    for G, A in out[1:]:
+        assert np.array_equal(G, out[0][0]) and all(np.array_equal(a, b) for a, b in zip(A, out[0][1]))
+
+
 def test_fused3_objective_history_monotone():
     nnc = need_gpu()
     X, _, G0, A0 = problem(63, (32, 32, 512), 4, (4, 4, 4))
