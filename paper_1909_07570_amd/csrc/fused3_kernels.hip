@@ -313,7 +313,7 @@ static __device__ void side_after_stream(const Side3 &side, unsigned char *lds_b
 // previous one is multiplied; A1 entries of a tile are loaded when the tile's first piece
 // is, one tile ahead of their use (double buffer a1n -> a1c).
 template <int RT, int CPR>
-__global__ __launch_bounds__(kYThreads) void pass1y_k(const uint16_t *__restrict__ X, int N0, int N1, int K,
+__global__ __launch_bounds__(kYThreads) __attribute__((amdgpu_waves_per_eu(CPR <= 16 ? 4 : 1))) void pass1y_k(const uint16_t *__restrict__ X, int N0, int N1, int K,
                                                       const float *__restrict__ F, int R2,
                                                       const float *__restrict__ A1, int R1,
                                                       float *__restrict__ Y0, Side3 side) {
@@ -327,9 +327,12 @@ __global__ __launch_bounds__(kYThreads) void pass1y_k(const uint16_t *__restrict
   constexpr int WSB = 16 * SS > kYPartBytes ? 16 * SS : kYPartBytes;
   const int Kp = (K + KC - 1) / KC * KC;
   const int KS = Kp + 8;
+  // factor rows in LDS: the R2 columns of A2 and one zero row that the MFMA tiles' rows past
+  // R2 read (RP rows when R2 fills the tiles)
+  const int FR = RP < R2 + 1 ? RP : R2 + 1;
   uint16_t *hi = reinterpret_cast<uint16_t *>(lds_b);
-  uint16_t *lo = hi + RP * KS;
-  const int fbytes = 2 * RP * KS * 2;
+  uint16_t *lo = hi + FR * KS;
+  const int fbytes = 2 * FR * KS * 2;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lg = lane >> 4;
@@ -395,7 +398,7 @@ __global__ __launch_bounds__(kYThreads) void pass1y_k(const uint16_t *__restrict
       const int kk = h * KC + st * 32;
 #pragma unroll
       for (int nt = 0; nt < RT; ++nt) {
-        const int off = (nt * 16 + li) * KS + kk + 8 * lg;
+        const int off = min(nt * 16 + li, FR - 1) * KS + kk + 8 * lg;
         acc[nt] = y_mfma_bf16(av, *reinterpret_cast<const u4 *>(hi + off), acc[nt]);
         acc[nt] = y_mfma_bf16(av, *reinterpret_cast<const u4 *>(lo + off), acc[nt]);
       }
@@ -440,8 +443,8 @@ __global__ __launch_bounds__(kYThreads) void pass1y_k(const uint16_t *__restrict
     __syncthreads();
   };
 
-  // ---- prologue: a first batch of factor loads, the first piece of X and its A1 rows, the
-  // side job's reads, then the factor's conversion into LDS
+  // ---- prologue: a first batch of factor loads, the first piece of X and its A1 rows, then
+  // the factor's conversion into LDS
   constexpr int KSTR = kYThreads / RP;
   const int fr = threadIdx.x % RP, fk = threadIdx.x / RP;
   const int frc = fr < R2 ? fr : R2 - 1;
@@ -450,8 +453,10 @@ __global__ __launch_bounds__(kYThreads) void pass1y_k(const uint16_t *__restrict
     const float a = (k < K && fr < R2) ? x : 0.f;
     const int kk = k < Kp ? k : Kp;
     const uint16_t h = y_f2bf(a);
-    hi[fr * KS + kk] = h;
-    lo[fr * KS + kk] = y_f2bf(a - y_bf2f(h));
+    if (fr < FR) {
+      hi[fr * KS + kk] = h;
+      lo[fr * KS + kk] = y_f2bf(a - y_bf2f(h));
+    }
   };
   float fv[kFB];
 #pragma unroll
@@ -489,7 +494,7 @@ __global__ __launch_bounds__(kYThreads) void pass1y_k(const uint16_t *__restrict
     slab_end(j);
   }
   __syncthreads();
-  side_after_stream<false>(side, lds_b, fbytes);
+  side_after_stream<false>(side, lds_b, 16);  // the stream's LDS, factor included, is free
 }
 
 // ------------------------------------------------------------------------------ pass 2
@@ -748,12 +753,26 @@ constexpr size_t kYCuLds = 160 * 1024;
 
 static int pass1y_cpr(int64_t K) { return K >= 256 ? 32 : (K >= 128 ? 16 : 8); }
 
-static size_t pass1y_lds(int RT, int CPR, int64_t K, int64_t gsize) {
+static size_t pass1y_lds(int RT, int CPR, int64_t K, int64_t R2, int64_t gsize) {
   const int64_t KC = CPR * 8;
   const int64_t Kp = (K + KC - 1) / KC * KC;
-  const int64_t fbytes = 2 * 16 * RT * (Kp + 8) * 2;
+  const int64_t FR = std::min<int64_t>(16 * RT, R2 + 1);
+  const int64_t fbytes = 2 * FR * (Kp + 8) * 2;
   const int64_t wsb = std::max<int64_t>(16 * (CPR * 16 + 16), kYPartBytes);
-  return (size_t)(fbytes + std::max<int64_t>(kYWaves * wsb, 4 * (int64_t)side_lds_floats((int)gsize)));
+  // the side job runs after the stream, over the stream's LDS (from byte 16)
+  return (size_t)std::max<int64_t>(fbytes + kYWaves * wsb, 16 + 4 * (int64_t)side_lds_floats((int)gsize));
+}
+
+// Pass 1's piece width and blocks per CU: pieces of 16 chunks (127 VGPRs) and two blocks per
+// CU when two blocks' LDS fits a CU, else pieces by K and one block per CU.
+static void pass1y_config(int RT, int64_t K, int64_t R2, int64_t gsize, int *cpr, int *per_cu) {
+  if (K >= 128 && 2 * pass1y_lds(RT, 16, K, R2, gsize) <= kYCuLds) {
+    *cpr = 16;
+    *per_cu = 2;
+  } else {
+    *cpr = pass1y_cpr(K);
+    *per_cu = 1;
+  }
 }
 
 static size_t pass2y_lds(int RT, int64_t N, int64_t R, int64_t R2, int64_t gsize) {
@@ -769,7 +788,9 @@ bool pass1y_ok(nnc_dtype dt, int64_t N0, int64_t N1, int64_t N2, int64_t R0, int
   if (R0 * R1 * R2 > kSideG4 * kYThreads * 4) return false;
   if (N1 % 16 || N2 % 8 || N2 < 64 || N2 > (1 << 20)) return false;
   if (N0 * N1 >= ((int64_t)1 << 31) || N0 * R1 * R2 >= ((int64_t)1 << 31)) return false;
-  return pass1y_lds(R2 <= 16 ? 1 : 2, pass1y_cpr(N2), N2, R0 * R1 * R2) <= kYCuLds;
+  int cpr, per_cu;
+  pass1y_config(R2 <= 16 ? 1 : 2, N2, R2, R0 * R1 * R2, &cpr, &per_cu);
+  return pass1y_lds(R2 <= 16 ? 1 : 2, cpr, N2, R2, R0 * R1 * R2) <= kYCuLds;
 }
 
 bool pass2y_ok(nnc_dtype dt, int64_t N0, int64_t N1, int64_t N2, int64_t R0, int64_t R1, int64_t R2) {
@@ -791,9 +812,10 @@ nnc_status launch_pass1y(const void *X, nnc_dtype dt, int64_t N0, int64_t N1, in
   if (side.nrows > 0 && side.gram_part) return fail(NNC_EINVAL, "pass1y: its side job sums no partials");
   if (side.nrows > 0 && !side.ticket) return fail(NNC_EINVAL, "pass1y: the side job needs its ticket counter");
   const int RT = R2 <= 16 ? 1 : 2;
-  const int CPR = pass1y_cpr(N2);
-  const size_t lds = pass1y_lds(RT, CPR, N2, (int64_t)side.R[0] * R1 * R2);
-  const int grid = (int)std::max<int64_t>(std::min<int64_t>(N0, device_cu_count()), side.nrows);
+  int CPR, per_cu;
+  pass1y_config(RT, N2, R2, (int64_t)side.R[0] * R1 * R2, &CPR, &per_cu);
+  const size_t lds = pass1y_lds(RT, CPR, N2, R2, (int64_t)side.R[0] * R1 * R2);
+  const int grid = (int)std::max<int64_t>(std::min<int64_t>(N0, (int64_t)per_cu * device_cu_count()), side.nrows);
   const uint16_t *Xb = (const uint16_t *)X;
 #define NNC_P1(RTV, CPRV)                                                                         \
   do {                                                                                            \
