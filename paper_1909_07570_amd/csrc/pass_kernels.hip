@@ -546,7 +546,7 @@ constexpr int kLdsThreads = 512;
 constexpr int kLdsWaves = kLdsThreads / 64;
 
 template <bool BF, int RT, int CPR, int NB>
-__global__ __launch_bounds__(kLdsThreads) void ttm_last_lds_k(const void *__restrict__ Xv, int64_t M,
+__global__ __launch_bounds__(kLdsThreads) __attribute__((amdgpu_waves_per_eu(CPR <= 16 ? 4 : 1))) void ttm_last_lds_k(const void *__restrict__ Xv, int64_t M,
                                                               int K, const float *__restrict__ F,
                                                               int64_t ldl, int64_t ldr, int R,
                                                               float *__restrict__ out, int64_t ldx,
@@ -563,10 +563,13 @@ __global__ __launch_bounds__(kLdsThreads) void ttm_last_lds_k(const void *__rest
   constexpr int kFB = 32;            // factor loads in flight per thread while staging
   const int Kp = (K + KC - 1) / KC * KC;
   const int KS = Kp + (BF ? 8 : 4);  // factor row stride (elements)
+  // factor rows in LDS: the R columns of the factor and one zero row that the MFMA tiles'
+  // rows past R read (RP rows when R fills the tiles)
+  const int FR = RP < R + 1 ? RP : R + 1;
   uint16_t *hi = reinterpret_cast<uint16_t *>(lds_b);
-  uint16_t *lo = hi + RP * KS;
+  uint16_t *lo = hi + FR * KS;
   float *fl = reinterpret_cast<float *>(lds_b);
-  const int fbytes = BF ? 2 * RP * KS * 2 : RP * KS * 4;  // a multiple of 16
+  const int fbytes = BF ? 2 * FR * KS * 2 : FR * KS * 4;  // a multiple of 16
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int li = lane & 15, lg = lane >> 4;
@@ -612,7 +615,7 @@ __global__ __launch_bounds__(kLdsThreads) void ttm_last_lds_k(const void *__rest
       if (BF) {
 #pragma unroll
         for (int nt = 0; nt < RT; ++nt) {
-          const int off = (nt * 16 + li) * KS + kk + 8 * lg;
+          const int off = min(nt * 16 + li, FR - 1) * KS + kk + 8 * lg;
           acc[nt] = p_mfma_bf16(a, *reinterpret_cast<const u4 *>(hi + off), acc[nt]);
           acc[nt] = p_mfma_bf16(a, *reinterpret_cast<const u4 *>(lo + off), acc[nt]);
         }
@@ -620,7 +623,7 @@ __global__ __launch_bounds__(kLdsThreads) void ttm_last_lds_k(const void *__rest
         const f4 xv = __builtin_bit_cast(f4, a);
 #pragma unroll
         for (int nt = 0; nt < RT; ++nt) {
-          const f4 bv = *reinterpret_cast<const f4 *>(fl + (nt * 16 + li) * KS + kk + 4 * lg);
+          const f4 bv = *reinterpret_cast<const f4 *>(fl + min(nt * 16 + li, FR - 1) * KS + kk + 4 * lg);
 #pragma unroll
           for (int e = 0; e < 4; ++e) acc[nt] = p_mfma_f32(xv[e], bv[e], acc[nt]);
         }
@@ -681,17 +684,19 @@ __global__ __launch_bounds__(kLdsThreads) void ttm_last_lds_k(const void *__rest
   const int fr = threadIdx.x % RP, fk = threadIdx.x / RP;
   const int frc = fr < R ? fr : R - 1;
   auto fac_load = [&](int k) { return F[(int64_t)(k < K ? k : K - 1) * ldl + (int64_t)frc * ldr]; };
-  // Rows k >= Kp go to the padding column Kp, which no MFMA reads: the store is then
-  // unconditional, so every factor load is consumed on every path.
+  // Rows k >= Kp go to the padding column Kp, which no MFMA reads, and columns past the
+  // zero row write their zeros into it: the store is then unconditional, so every factor
+  // load is consumed on every path.
+  const int frs = fr < FR ? fr : FR - 1;
   auto fac_store = [&](int k, float x) {
     const float a = (k < K && fr < R) ? x : 0.f;
     const int kk = k < Kp ? k : Kp;
     if (BF) {
       const uint16_t h = p_f2bf(a);
-      hi[fr * KS + kk] = h;
-      lo[fr * KS + kk] = p_f2bf(a - p_bf2f(h));
+      hi[frs * KS + kk] = h;
+      lo[frs * KS + kk] = p_f2bf(a - p_bf2f(h));
     } else {
-      fl[fr * KS + kk] = a;
+      fl[frs * KS + kk] = a;
     }
   };
   float fv[kFB];
@@ -787,11 +792,12 @@ int device_cu_count() {
   return n;
 }
 
-size_t last_lds_bytes(bool bf, int RT, int CPR, int64_t K) {
+size_t last_lds_bytes(bool bf, int RT, int CPR, int64_t K, int64_t R) {
   const int64_t EPC = bf ? 8 : 4, KC = CPR * EPC;
   const int64_t Kp = (K + KC - 1) / KC * KC;
   const int64_t KS = Kp + (bf ? 8 : 4);
-  const int64_t fbytes = bf ? 2 * 16 * RT * KS * 2 : 16 * RT * KS * 4;
+  const int64_t FR = std::min<int64_t>(16 * RT, R + 1);
+  const int64_t fbytes = bf ? 2 * FR * KS * 2 : FR * KS * 4;
   return (size_t)(fbytes + (int64_t)kLdsWaves * 16 * (CPR * 16 + 16));
 }
 
@@ -800,13 +806,20 @@ static nnc_status launch_last_lds(const void *X, bool bf, int64_t M, int64_t K, 
                                   const char **kernel_name, int reserve, int64_t ldx, int acc_out) {
   const int EPC = bf ? 8 : 4;
   if (K % EPC || K > (1 << 20) || K < 8 * EPC) return NNC_EUNSUPPORTED;
-  const int CPR = K >= 32 * EPC ? 32 : (K >= 16 * EPC ? 16 : 8);
   const int RT = R <= 16 ? 1 : 2;
-  const size_t lds = last_lds_bytes(bf, RT, CPR, K);
+  // pieces of 16 chunks and two blocks per CU when two blocks' LDS fits a CU (every variant
+  // of 16 chunks stays within 128 VGPRs, four waves per SIMD), else the widest pieces that fit
+  int CPR = K >= 32 * EPC ? 32 : (K >= 16 * EPC ? 16 : 8), per_cu = 1;
+  if (K >= 16 * EPC && 2 * last_lds_bytes(bf, RT, 16, K, R) <= kCuLdsBytes) {
+    CPR = 16;
+    per_cu = 2;
+  }
+  const size_t lds = last_lds_bytes(bf, RT, CPR, K, R);
   if (lds > kCuLdsBytes) return NNC_EUNSUPPORTED;
   const int64_t tiles = (M + 15) / 16;
   const int grid = (int)std::max<int64_t>(
-      1, std::min<int64_t>((tiles + kLdsWaves - 1) / kLdsWaves, device_cu_count() - std::max(reserve, 0)));
+      1, std::min<int64_t>((tiles + kLdsWaves - 1) / kLdsWaves,
+                           (int64_t)per_cu * (device_cu_count() - std::max(reserve, 0))));
   // one piece in flight per wave (measured fastest at 512^3 with random data, 51.5-52 us
   // against 53.5-54 with two and 54-55 with three for bf16 X: with the HBM saturated, more
   // outstanding loads only queue)
@@ -860,11 +873,11 @@ nnc_status launch_pass(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64
     nnc_status st = launch_last_lds(X, bf, P, N, F, ldl, ldr, R, out, s, kernel_name, reserve_cus, N, 0);
     if (st != NNC_EUNSUPPORTED) return st;
     const int EPC = bf ? 8 : 4, KC = 32 * EPC;
-    if (N % EPC == 0 && N >= 8 * EPC && last_lds_bytes(bf, RT, 32, KC) <= kCuLdsBytes) {
+    if (N % EPC == 0 && N >= 8 * EPC && last_lds_bytes(bf, RT, 32, KC, R) <= kCuLdsBytes) {
       // chunks of Kc (a multiple of the 32-chunk piece width, so every slab starts 16-byte
       // aligned), the last one long enough for the kernel's pieces
       int64_t Kmax = KC;
-      while (last_lds_bytes(bf, RT, 32, Kmax + KC) <= kCuLdsBytes) Kmax += KC;
+      while (last_lds_bytes(bf, RT, 32, Kmax + KC, R) <= kCuLdsBytes) Kmax += KC;
       int64_t Kc = Kmax, nch = 1;
       for (; Kc >= KC; Kc -= KC) {
         nch = (N + Kc - 1) / Kc;

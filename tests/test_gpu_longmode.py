@@ -59,7 +59,10 @@ def test_chunked_passes_report_chunks():
     nnc.nnc_ttm(X, 1, dev(np.ones((1024, 20), dtype=np.float32)))
     assert nnc.last_ttm_kernel() == "ttm_mid_f32 (chunked)"
     Xb = bf16_dev(np.ones((512, 512, 1024)))
+    # the last-mode pass holds R + 1 factor rows: N_d = 1024 fits at R = 20, not at R = 32
     nnc.nnc_ttm(Xb, 2, dev(np.ones((1024, 20), dtype=np.float32)))
+    assert nnc.last_ttm_kernel() == "ttm_last_lds_bf16"
+    nnc.nnc_ttm(Xb, 2, dev(np.ones((1024, 32), dtype=np.float32)))
     assert nnc.last_ttm_kernel() == "ttm_last_lds_bf16 (chunked)"
     nnc.nnc_ttm(Xb, 0, dev(np.ones((512, 20), dtype=np.float32)))
     assert nnc.last_ttm_kernel() == "ttm_mid_bf16"
