@@ -189,7 +189,7 @@ constexpr int kMidDepth = 1;
 constexpr int kMidDepthF32 = 1;  // steps in flight per wave, FP32 X (one measured fastest, as for bf16)
 
 template <int RT, bool HS>
-__global__ __launch_bounds__(64 * kMidWaves) void ttm_mid_lds_k(const uint16_t *__restrict__ X,
+__global__ __launch_bounds__(64 * kMidWaves) __attribute__((amdgpu_waves_per_eu(RT == 1 ? 4 : 1))) void ttm_mid_lds_k(const uint16_t *__restrict__ X,
                                                                int64_t P, int N, int64_t Q,
                                                                const float *__restrict__ F,
                                                                int64_t ldl, int64_t ldr, int R,
@@ -393,7 +393,7 @@ __global__ __launch_bounds__(64 * kMidWaves) void ttm_mid_lds_k(const uint16_t *
 // adjacent columns q0 + 16 lg + 4 i + (0..3) of each accumulator set c.
 // =====================================================================================
 template <int RT, int DEPTH>
-__global__ __launch_bounds__(64 * kMidWaves) void ttm_mid_lds_f32_k(const float *__restrict__ X,
+__global__ __launch_bounds__(64 * kMidWaves) __attribute__((amdgpu_waves_per_eu(4))) void ttm_mid_lds_f32_k(const float *__restrict__ X,
                                                                    int64_t P, int N, int64_t Q,
                                                                    const float *__restrict__ F,
                                                                    int64_t ldl, int64_t ldr, int R,
@@ -928,7 +928,10 @@ nnc_status launch_pass(const void *X, nnc_dtype xdt, int64_t P, int64_t N, int64
     }
     const size_t lds = pass_mid_lds(bf, RT, Nc, R, hs);
     const int64_t tiles = P * ((Q + (bf ? 127 : 63)) / (bf ? 128 : 64));
-    int grid = (int)std::min<int64_t>((tiles + kMidWaves - 1) / kMidWaves, device_cu_count());
+    // two blocks per CU when their LDS fits and the variant stays within 128 VGPRs (four
+    // waves per SIMD: the FP32 kernels and the bf16 ones of one rank tile)
+    const int per_cu = ((!bf || RT == 1) && 2 * lds <= kCuLdsBytes) ? 2 : 1;
+    int grid = (int)std::min<int64_t>((tiles + kMidWaves - 1) / kMidWaves, (int64_t)per_cu * device_cu_count());
     if (grid < 1) grid = 1;
     for (int64_t n0 = 0; n0 < N; n0 += Nc) {
       const int64_t nc = std::min(Nc, N - n0);
