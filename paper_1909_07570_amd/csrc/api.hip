@@ -830,6 +830,31 @@ static hipStream_t capture_stream() {
   return st;
 }
 
+// Executable sweep graphs of the fits, kept across calls of one host thread: a later fit
+// whose key matches (every pointer, size and setting its launches take, and the schedule
+// switches read from the environment) replays them instead of capturing and instantiating
+// again.  The graphs capture pointers, not data, so new values in the same buffers are read
+// by the replay.  Each fit synchronises before it returns, so no cached graph is in flight
+// when another call evicts it.
+struct SweepGraphKey {
+  const void *X, *ws, *core, *A[kMaxDim];
+  int64_t N[kMaxDim], R[kMaxDim];
+  double eps;
+  hipStream_t stream;
+  int dt, d, count, device, ls, no_fused3, no_big_slices, pad;  // pad: no trailing padding bytes
+};
+static_assert(sizeof(SweepGraphKey) % 8 == 0 && offsetof(SweepGraphKey, pad) + sizeof(int) == sizeof(SweepGraphKey),
+              "the key is compared bytewise and must have no padding");
+struct SweepGraphKeyLess {
+  bool operator()(const SweepGraphKey &a, const SweepGraphKey &b) const { return memcmp(&a, &b, sizeof a) < 0; }
+};
+constexpr size_t kSweepGraphCacheMax = 16;  // executable graphs per host thread
+static std::map<SweepGraphKey, hipGraphExec_t, SweepGraphKeyLess> &sweep_graph_cache() {
+  // never destroyed: graphs are not torn down after the runtime at process exit
+  static thread_local auto *c = new std::map<SweepGraphKey, hipGraphExec_t, SweepGraphKeyLess>();
+  return *c;
+}
+
 // Run `n` sweeps, each enqueued by `sweep(stream)`, captured sweeps_per_graph(n) at a time into
 // HIP graphs when `graphs` is set (a library stream stands in for the default stream, which
 // cannot be captured).  Returns after the sweeps are enqueued on `s` (synchronised once).
@@ -1182,22 +1207,74 @@ static nnc_status tucker_fit_impl(bool ls, const void *X, nnc_dtype xdt, int ndi
     };
     if (!every && tb - ta > 1) {
       // several sweeps per graph: the turnaround between two graph launches (several
-      // microseconds) is paid once per sweeps_per_graph(n) sweeps.  An executable graph is
-      // destroyed only after its launches have finished: its resources must not be
-      // released (and reused by the next instantiation) while queued launches read them.
+      // microseconds) is paid once per sweeps_per_graph(n) sweeps.  The executable graphs
+      // are cached (see sweep_graph_cache) and destroyed only after their launches have
+      // finished: their resources must not be released (and reused by the next
+      // instantiation) while queued launches read them.
       const int n = tb - ta;
       const int per = sweeps_per_graph(n);
+      // the cache key of `count` sweeps on (Xs, dts)
+      auto key_of = [&](int count, SweepGraphKey *k) -> nnc_status {
+        memset(k, 0, sizeof *k);
+        k->X = Xs;
+        k->ws = o.workspace;
+        k->core = core;
+        for (int j = 0; j < ndim; ++j) {
+          k->A[j] = factors[j];
+          k->N[j] = p.N[j];
+          k->R[j] = p.R[j];
+        }
+        k->eps = eps;
+        k->stream = cs;
+        k->dt = (int)dts;
+        k->d = ndim;
+        k->count = count;
+        NNC_HIP(hipGetDevice(&k->device));
+        k->ls = ls ? 1 : 0;
+        k->no_fused3 = getenv("NNC_NO_FUSED3") ? 1 : 0;
+        k->no_big_slices = getenv("NNC_NO_BIG_SLICES") ? 1 : 0;
+        return NNC_OK;
+      };
+      const int rem = n % per;
+      SweepGraphKey kb, kr;
+      NNC_TRY(key_of(per, &kb));
+      NNC_TRY(key_of(rem, &kr));
+      auto &c = sweep_graph_cache();
+      auto ib = c.find(kb);
+      auto ir = rem ? c.find(kr) : c.end();
+      const size_t misses = (ib == c.end() ? 1 : 0) + (rem && ir == c.end() ? 1 : 0);
+      if (misses && c.size() + misses > kSweepGraphCacheMax) {
+        // make room, keeping the graphs this range replays (every fit has synchronized its
+        // launches before returning, so none of the others is in flight)
+        for (auto it = c.begin(); it != c.end();) {
+          if (it == ib || it == ir) {
+            ++it;
+            continue;
+          }
+          (void)hipGraphExecDestroy(it->second);
+          it = c.erase(it);
+        }
+      }
       hipGraphExec_t gb = nullptr, gr = nullptr;
-      nnc_status st = capture(&gb, per);
-      if (st == NNC_OK && n % per) st = capture(&gr, n % per);
+      nnc_status st = NNC_OK;
+      if (ib != c.end()) {
+        gb = ib->second;
+      } else if ((st = capture(&gb, per)) == NNC_OK) {
+        c.emplace(kb, gb);
+      }
+      if (st == NNC_OK && rem) {
+        if (ir != c.end()) {
+          gr = ir->second;
+        } else if ((st = capture(&gr, rem)) == NNC_OK) {
+          c.emplace(kr, gr);
+        }
+      }
       for (int t = 0; st == NNC_OK && t + per <= n; t += per)
         if (hipGraphLaunch(gb, cs) != hipSuccess) st = fail(NNC_EHIP, "graph launch failed");
       if (st == NNC_OK && gr && hipGraphLaunch(gr, cs) != hipSuccess) st = fail(NNC_EHIP, "graph launch failed");
       if (hipStreamSynchronize(cs) != hipSuccess && st == NNC_OK)
         st = fail(NNC_EHIP, "stream synchronization after the sweeps failed");
-      for (hipGraphExec_t e : {gb, gr})
-        if (e) (void)hipGraphExecDestroy(e);
-      NNC_TRY(st);
+      NNC_TRY(st);  // the graphs stay in the cache
     } else {
       hipGraphExec_t ge = nullptr;
       NNC_TRY(capture(&ge, 1));

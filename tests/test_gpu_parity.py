@@ -328,6 +328,41 @@ def test_graph_replays_match_eager_sweeps(dims, ranks):
     assert re_.rel_residual == rg.rel_residual
 
 
+def test_cached_sweep_graphs_follow_buffers_and_settings():
+    """Graph fits that repeat an earlier fit's buffers and sizes replay its cached graphs: new
+    contents written into the same buffers are read, a least-squares fit on the same buffers
+    and another eps take graphs of their own, and more configurations than the cache keeps
+    (20 X buffers, several sweep counts) still give the eager sweeps' results bit for bit."""
+    nnc = need_gpu()
+    dims, ranks = (30, 20, 26), (3, 4, 3)
+    size = int(np.prod(dims))
+    ws = torch.empty(nnc.nntucker_workspace_bytes(dims, ranks), dtype=torch.uint8, device="cuda")
+    xbuf = torch.empty(20 * size, device="cuda")
+    G = torch.empty(ranks, device="cuda")
+    A = [torch.empty(n, r, device="cuda") for n, r in zip(dims, ranks)]
+
+    def run(fit, slot, X, G0, A0, iters, use_graph, **kw):
+        Xd = xbuf[slot * size:(slot + 1) * size].view(dims)
+        Xd.copy_(torch.from_numpy(X))
+        G.copy_(torch.from_numpy(G0))
+        for a, a0 in zip(A, A0):
+            a.copy_(torch.from_numpy(a0))
+        fit(Xd, ranks, iters, G, A, use_graph=use_graph, workspace=ws, report=False, **kw)
+        return host(G), [host(a) for a in A]
+
+    cases = [(nnc.nntucker_fit, 0, 31, 11, {}), (nnc.nntucker_fit, 0, 32, 11, {}),
+             (nnc.tucker_ls_fit, 0, 32, 11, {}), (nnc.nntucker_fit, 0, 32, 11, {"eps": 1e-3}),
+             (nnc.nntucker_fit, 0, 33, 11, {})]
+    cases += [(nnc.nntucker_fit, slot, 40 + slot, 5 + slot % 7, {}) for slot in range(20)]
+    cases += [(nnc.nntucker_fit, 3, 70, 13, {}), (nnc.tucker_ls_fit, 3, 71, 9, {})]
+    for fit, slot, seed, iters, kw in cases:
+        X, _, G0, A0 = problem(seed, dims, 2, ranks)
+        Ge, Ae = run(fit, slot, X, G0, A0, iters, False, **kw)
+        Gg, Ag = run(fit, slot, X, G0, A0, iters, True, **kw)
+        assert np.array_equal(Ge, Gg) and all(np.array_equal(a, b) for a, b in zip(Ae, Ag)), \
+            (fit.__name__, slot, seed, iters, kw)
+
+
 def test_nan_in_x_is_reported():
     nnc = need_gpu()
     X, _, G0, A0 = problem(11, (16, 16, 16), 2, (2, 2, 2))
