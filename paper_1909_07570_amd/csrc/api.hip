@@ -466,7 +466,7 @@ static nnc_status core_tail(const TuckerBufs &b, float *G, float *const *A, doub
 }
 
 // Sweeps captured in one graph when no objective is recorded in between.
-constexpr int kSweepsPerGraph = 8;
+constexpr int kSweepsPerGraph = 16;
 
 // Sweeps per graph for a run of n: a divisor of n between kSweepsPerGraph / 2 and
 // kSweepsPerGraph when there is one, so the run needs one capture instead of two (capture and

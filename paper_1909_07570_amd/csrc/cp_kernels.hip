@@ -154,7 +154,10 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
       // index divisions through float reciprocals (qdiv; nncp_check_shape keeps every
       // index here below 2^22)
       const float inv_nq = 1.0f / (float)nq, inv_postL = 1.0f / (float)postL;
-      for (int w = tid; w < nq * zrows; w += nt) {
+      // modes 1 .. d-2 contract the same mode L = d-1 as mode 0, whose factor has not changed
+      // since mode 0's stage 1 in this sweep: Z is already there
+      const bool z_current = n >= 1 && n <= d - 2;
+      for (int w = z_current ? nq * zrows : tid; w < nq * zrows; w += nt) {
         const int o = qdiv(w, inv_nq), c4 = (w - o * nq) * 4;
         const int pre = qdiv(o, inv_postL), q = o - pre * postL;
         const float *t = T + pre * mL * postL + q;
