@@ -48,7 +48,8 @@ static __device__ inline float mu_cp(float x, float num, float den, double eps, 
 
 // LDS floats of one fit of rank r with `threads` threads:
 //   [T if t_lds] B_k (dims[k] x r) | Gram_k (r x r) | H (r x r)
-//   | part (max(threads, maxdim * r)) | red (2 * threads doubles) | [2 r x r doubles if ALS]
+//   | part (max(threads, maxdim * r)) | new factor values (maxdim x RM)
+//   | red (2 * threads doubles) | [2 r x r doubles if ALS]
 //   | [Z (zmax x r) if z_lds]
 static int64_t cp_lds_floats(const CpArgs &a, int r, int threads, bool t_lds, bool z_lds, bool als) {
   int64_t s = t_lds ? a.size : 0;
@@ -57,6 +58,8 @@ static int64_t cp_lds_floats(const CpArgs &a, int r, int threads, bool t_lds, bo
   for (int k = 0; k < a.d; ++k) s += (int64_t)a.dims[k] * RM;
   s += (int64_t)(a.d + 1) * r * r;
   s += std::max<int64_t>(threads, (int64_t)a.maxdim * r);
+  s = (s + 3) & ~(int64_t)3;
+  s += (int64_t)a.maxdim * RM;  // new values of the last updated factor
   s += (s & 1);               // keep the doubles 8-byte aligned
   s += 4 * (int64_t)threads;  // 2 * threads doubles
   if (als) s += 4 * (int64_t)r * r;  // two r x r double buffers for the inverse of H
@@ -101,6 +104,9 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
   p += r * r;
   float *part = p;
   p += (nt > a.maxdim * r ? nt : a.maxdim * r);
+  p += (4 - ((p - sm) & 3)) & 3;  // fnew rows are read as float4
+  float *fnew = p;  // the new values of the factor just updated (rows padded to RM, zeros past r)
+  p += a.maxdim * RM;
   p += ((p - sm) & 1);
   double *red = reinterpret_cast<double *>(p);
   p += 4 * nt;
@@ -108,6 +114,7 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
   if (ALS) p += 4 * r * r;
   p += (4 - ((p - sm) & 3)) & 3;
   float *Z = a.z_lds ? p : zg + (int64_t)b * a.zmax * RM;
+  for (int e = tid; e < a.maxdim * RM; e += nt) fnew[e] = 0.f;
   if (tid == 0) {
     nclip = 0;
     int o = 0;
@@ -139,6 +146,12 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
   }
   __syncthreads();
 
+  // Multiplicative updates leave the new values of B_n in fnew; the phase that starts the next
+  // mode copies them into place and forms their Gram (`pending`, mode `np`), so a mode takes
+  // three barriers.  A stage-1 contraction over that same factor reads fnew directly.
+  bool pending = false;
+  int np = 0;
+  const float inv_r = 1.0f / (float)r;
   for (int it = 0; it < iters; ++it) {
     for (int n = 0; n < d; ++n) {
       const int L = (n == d - 1) ? d - 2 : d - 1;
@@ -146,7 +159,7 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
       int postL = 1;
       for (int k = L + 1; k < d; ++k) postL *= a.dims[k];
       const int zrows = a.size / mL;
-      const float *BL = sB + boff[L];
+      const float *BL = (pending && L == np) ? fnew : sB + boff[L];
       // ---- stage 1: Z[o][rho] = sum_l T[(pre*mL + l)*postL + q] B_L[l][rho], o = pre*postL + q;
       // one thread per (row, quad of columns), quads past the rank left out.  H_n (Hadamard
       // product of the other Grams, final since the last update) in the same phase.
@@ -173,14 +186,28 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
         }
         *reinterpret_cast<float4 *>(Z + o * RM + c4) = acc;
       }
+      if (pending) {
+        float *Bp = sB + boff[np];
+        const int Ip = a.dims[np];
+        for (int e = tid; e < Ip * RM; e += nt) Bp[e] = fnew[e];
+        for (int e = tid; e < r * r; e += nt) {
+          const int x = qdiv(e, inv_r), y = e - x * r;
+          float acc = 0.f;
+#pragma unroll 4
+          for (int i = 0; i < Ip; ++i) acc = fmaf(fnew[i * RM + x], fnew[i * RM + y], acc);
+          sW[np * r * r + e] = acc;
+        }
+        pending = false;
+      }
+      if (!a.z_lds) __threadfence_block();
+      __syncthreads();
+      // H_n: Hadamard product of the other Grams (all final since the phase above)
       for (int e = tid; e < r * r; e += nt) {
         float h = 1.f;
         for (int k = 0; k < d; ++k)
           if (k != n) h *= sW[k * r * r + e];
         H[e] = h;
       }
-      if (!a.z_lds) __threadfence_block();
-      __syncthreads();
       // ---- stage 2: M[i][rho] = sum over Z rows with i_n = i of Z[o][rho] prod_{k!=n,L} B_k[i_k][rho]
       // Z's modes are T's modes without L (row-major).  With one mode j besides n and L
       // (d = 3), Z is 2-D and the sum runs over j's index directly (split s taking the
@@ -191,7 +218,7 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
       const int npairs = In * r;
       const int other = zrows / In;
       const int S = npairs >= nt ? 1 : nt / npairs;
-      const float inv_npairs = 1.0f / (float)npairs, inv_r = 1.0f / (float)r;
+      const float inv_npairs = 1.0f / (float)npairs;
       if (d <= 3) {
         // position of n among Z's modes and the other mode (if any)
         int jo = -1;
@@ -317,7 +344,8 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
         __syncthreads();
         continue;
       }
-      // ---- B_n <- B_n * M / max(B_n H, eps): new values go to `part` first
+      // ---- B_n <- B_n * M / max(B_n H, eps): new values go to fnew (moved into place, and
+      // their Gram formed, by the first phase of the next mode or after the last sweep)
       for (int e = tid; e < npairs; e += nt) {
         const int i = qdiv(e, inv_r), c = e - i * r;
         float m = 0.f;  // the S partial sums of pair e, in split order
@@ -326,23 +354,17 @@ __global__ __launch_bounds__(1024) void nncp_k(const float *__restrict__ Tg, CpA
         float den = 0.f;
 #pragma unroll 4
         for (int s2 = 0; s2 < r; ++s2) den = fmaf(Bn[i * RM + s2], H[s2 * r + c], den);
-        part[e] = mu_cp(Bn[i * RM + c], m, den, eps, &nclip);
+        fnew[i * RM + c] = mu_cp(Bn[i * RM + c], m, den, eps, &nclip);
       }
-      __syncthreads();
-      for (int e = tid; e < npairs; e += nt) {
-        const int i = qdiv(e, inv_r);
-        Bn[i * RM + (e - i * r)] = part[e];
-      }
-      __syncthreads();
-      for (int e = tid; e < r * r; e += nt) {
-        const int x = qdiv(e, inv_r), y = e - x * r;
-        float acc = 0.f;
-#pragma unroll 4
-        for (int i = 0; i < In; ++i) acc = fmaf(Bn[i * RM + x], Bn[i * RM + y], acc);
-        sW[n * r * r + e] = acc;
-      }
+      pending = true;
+      np = n;
       __syncthreads();
     }
+  }
+  if (pending) {
+    float *Bp = sB + boff[np];
+    for (int e = tid; e < a.dims[np] * RM; e += nt) Bp[e] = fnew[e];
+    __syncthreads();
   }
 #pragma unroll
   for (int k = 0; k < kMaxDim; ++k) {
