@@ -1274,7 +1274,16 @@ static nnc_status tucker_fit_impl(bool ls, const void *X, nnc_dtype xdt, int ndi
       if (st == NNC_OK && gr && hipGraphLaunch(gr, cs) != hipSuccess) st = fail(NNC_EHIP, "graph launch failed");
       if (hipStreamSynchronize(cs) != hipSuccess && st == NNC_OK)
         st = fail(NNC_EHIP, "stream synchronization after the sweeps failed");
-      NNC_TRY(st);  // the graphs stay in the cache
+      if (st != NNC_OK) {  // a failed range leaves no graph in the cache
+        for (const SweepGraphKey *kk : {&kb, &kr}) {
+          const auto it = c.find(*kk);
+          if (it != c.end()) {
+            (void)hipGraphExecDestroy(it->second);
+            c.erase(it);
+          }
+        }
+        return st;
+      }  // else the graphs stay in the cache
     } else {
       hipGraphExec_t ge = nullptr;
       NNC_TRY(capture(&ge, 1));
