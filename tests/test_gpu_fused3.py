@@ -92,7 +92,8 @@ def test_fused3_many_sweeps_deterministic_and_resumable(use_graph):
 
 def test_fused3_graph_replays_match_eager_sweeps():
     """Sweeps replayed from captured graphs (several sweeps per graph, a remainder graph) give
-    the eager sweeps' results bit for bit, with the workspace reused across the fits."""
+    the eager sweeps' results bit for bit, with the workspace reused across the fits, also
+    after new contents are written into the same X buffer (the cached graphs read them)."""
     nnc = need_gpu()
     import synth
     X, _, G0, A0 = problem(67, (40, 48, 512), 4, (20, 20, 20))
@@ -107,6 +108,17 @@ def test_fused3_graph_replays_match_eager_sweeps():
         out.append((host(G), [host(a) for a in A]))
     for G, A in out[1:]:
         assert np.array_equal(G, out[0][0]) and all(np.array_equal(a, b) for a, b in zip(A, out[0][1]))
+    # new contents in the same X buffer: the replayed graphs read them
+    X2, _, _, _ = problem(68, (40, 48, 512), 4, (20, 20, 20))
+    Xd.copy_(bf16_dev(synth.round_bf16(X2.astype(np.float64))))
+    out2 = []
+    for use_graph in (True, False):
+        G = dev(G0)
+        A = [dev(a) for a in A0]
+        nnc.nntucker_fit(Xd, ranks, 19, G, A, use_graph=use_graph, workspace=ws, report=False)
+        out2.append((host(G), [host(a) for a in A]))
+    assert np.array_equal(out2[0][0], out2[1][0]) and all(np.array_equal(a, b) for a, b in zip(out2[0][1], out2[1][1]))
+    assert not np.array_equal(out2[0][0], out[0][0])
 
 
 def test_fused3_objective_history_monotone():
