@@ -274,3 +274,19 @@ def test_real_valued_fits_validate():
     assert g(FAKE, 3, D(5, 5, 5), 33, 10, _ptrs(3), ctypes.byref(opt), None, None) == nnc.NNC_EUNSUPPORTED
     assert g(FAKE, 3, D(5, 5, 5), 3, 10, _ptrs(3, 0), ctypes.byref(opt), None, None) == nnc.NNC_EINVAL
     assert g(FAKE, 3, D(5, 5, 5), 3, 10, _ptrs(3), None, None, None) == nnc.NNC_EWORKSPACE
+
+
+def test_bench_refuses_more_than_one_gpu_and_needs_the_gpu():
+    """bench.py measures one GPU: --gpus 2 exits with status 2 and says so; without a GPU it
+    exits with status 1 and names what it needs (no CPU stand-in is timed)."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr, (r.returncode, r.stderr)
+    import torch
+    if not torch.cuda.is_available():
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "1", "--warmup", "0"],
+                           capture_output=True, text=True, timeout=120)
+        assert r.returncode == 1 and "needs an MI355X" in (r.stderr + r.stdout), (r.returncode, r.stderr)
+        assert not r.stdout.lstrip().startswith("{")
